@@ -1,0 +1,272 @@
+"""CPU oracle for the voxel-map plane-segmentation path.
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by the smoke check and by
+the benchmark's CPU-baseline leg, never by the library.  It shares no code
+with the HIP path; both only take their inputs from ``scenes``.
+
+The arithmetic lives in ``vm_oracle.c`` (plain C, fp64 where the method is
+floating point).  This wrapper adds the steps whose definition is a library
+primitive: grouping voxels by label is a stable sort (Sec. III-C,
+"Clustering of steppable points", last sentence).
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+import subprocess
+from typing import List, Optional, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "vm_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+NO_KEY = 0xFFFFFFFF
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (no contraction, no fast-math)."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fno-fast-math",
+                               "-fPIC", "-shared", "-Wall", "-Wextra", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+            build()
+        L = ctypes.CDLL(_LIB_PATH)
+        P = ctypes.c_void_p
+        i64, u32, u64, f32, f64 = ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_float, ctypes.c_double
+        L.vo_philox4x64_10.argtypes = [P, P, P]
+        L.vo_philox4x64_10.restype = None
+        L.vo_draw3.argtypes = [u64, u64, u64, u64, u64, P]
+        L.vo_draw3.restype = None
+        L.vo_voxelize.argtypes = [P, i64, P, P, P, f64, P, P, P]
+        L.vo_voxelize.restype = i64
+        L.vo_map_accumulate.argtypes = [P, P, P, i64, P, P, i64, P, P, P, i64]
+        L.vo_map_accumulate.restype = i64
+        L.vo_voxel_mean.argtypes = [P, P, P, i64, P, f64, P, P]
+        L.vo_voxel_mean.restype = None
+        L.vo_ccl26.argtypes = [P, i64, P, P]
+        L.vo_ccl26.restype = i64
+        L.vo_ransac.argtypes = [P, P, P, i64, u32, f32, u64, u64, u64, P, P, P, P, P]
+        L.vo_ransac.restype = ctypes.c_int32
+        L.vo_hull.argtypes = [P, P, P, i64, P, P, P, P]
+        L.vo_hull.restype = i64
+        L.vo_hull_project.argtypes = [P, P, P, i64, P, P, P]
+        L.vo_hull_project.restype = None
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray) -> int:
+    assert a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data
+
+
+def _c(a, dtype) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=dtype))
+
+
+# --------------------------------------------------------------------------
+# primitives
+# --------------------------------------------------------------------------
+def philox4x64_10(ctr, key) -> np.ndarray:
+    c, k, out = _c(ctr, np.uint64), _c(key, np.uint64), np.zeros(4, np.uint64)
+    lib().vo_philox4x64_10(_p(c), _p(k), _p(out))
+    return out
+
+
+def draw3(seed: int, tag: int, frame: int, h: int, n: int) -> Tuple[int, int, int]:
+    out = np.zeros(3, np.uint64)
+    lib().vo_draw3(seed & (2**64 - 1), tag & (2**64 - 1), frame & (2**64 - 1), h, n, _p(out))
+    return int(out[0]), int(out[1]), int(out[2])
+
+
+def voxelize(xyz: np.ndarray, R, t, origin, voxel_size: float, dims) -> Tuple[np.ndarray, np.ndarray, int]:
+    xyz = _c(xyz, np.float32).reshape(-1, 3)
+    n = len(xyz)
+    key = np.empty(n, np.uint32)
+    frac = np.empty((n, 3), np.uint64)
+    kept = lib().vo_voxelize(_p(xyz), n, _p(_c(R, np.float64)), _p(_c(t, np.float64)),
+                             _p(_c(origin, np.float64)), float(voxel_size), _p(_c(dims, np.int32)),
+                             _p(key), _p(frac))
+    return key, frac, int(kept)
+
+
+def voxel_mean(key, cnt, sums, origin, voxel_size, dims) -> np.ndarray:
+    key, cnt, sums = _c(key, np.uint32), _c(cnt, np.uint32), _c(sums, np.uint64).reshape(-1, 3)
+    mu = np.empty((len(key), 3), np.float32)
+    lib().vo_voxel_mean(_p(key), _p(cnt), _p(sums), len(key), _p(_c(origin, np.float64)),
+                        float(voxel_size), _p(_c(dims, np.int32)), _p(mu))
+    return mu
+
+
+def ccl26(keys: np.ndarray, dims) -> Tuple[np.ndarray, int]:
+    keys = _c(keys, np.uint32)
+    if len(keys) > 1 and not np.all(keys[1:] > keys[:-1]):
+        raise ValueError("keys must be strictly ascending")
+    lab = np.empty(len(keys), np.uint32)
+    nc = lib().vo_ccl26(_p(keys), len(keys), _p(_c(dims, np.int32)), _p(lab))
+    if nc < 0:
+        raise MemoryError("oracle CCL allocation failed")
+    return lab, int(nc)
+
+
+@dataclasses.dataclass
+class RansacResult:
+    best_h: int
+    plane: np.ndarray          # float32[4]
+    counts: np.ndarray         # int32[H]
+    hyp: np.ndarray            # float32[H, 4]
+    inliers: np.ndarray        # uint32[m], cluster-local ascending
+
+
+def ransac(x, y, z, n_hyp: int, eps: float, seed: int, tag: int, frame: int) -> RansacResult:
+    x, y, z = _c(x, np.float32), _c(y, np.float32), _c(z, np.float32)
+    n = len(x)
+    counts = np.empty(n_hyp, np.int32)
+    hyp = np.empty((n_hyp, 4), np.float32)
+    best = np.empty(4, np.float32)
+    inl = np.empty(max(n, 1), np.uint32)
+    nin = np.zeros(1, np.int64)
+    h = lib().vo_ransac(_p(x), _p(y), _p(z), n, n_hyp, ctypes.c_float(eps), seed & (2**64 - 1),
+                        tag & (2**64 - 1), frame & (2**64 - 1), _p(counts), _p(hyp), _p(best),
+                        _p(inl), _p(nin))
+    return RansacResult(int(h), best, counts, hyp, inl[: int(nin[0])].copy())
+
+
+@dataclasses.dataclass
+class HullResult:
+    idx: np.ndarray            # uint32[h], indices into the hull's input points
+    xyz: np.ndarray            # float32[h, 3]
+    area: float
+
+
+def hull(x, y, z, plane) -> HullResult:
+    x, y, z = _c(x, np.float32), _c(y, np.float32), _c(z, np.float32)
+    m = len(x)
+    idx = np.empty(max(m, 1), np.uint32)
+    xyz = np.empty((max(m, 1), 3), np.float32)
+    area = np.zeros(1, np.float64)
+    h = lib().vo_hull(_p(x), _p(y), _p(z), m, _p(_c(plane, np.float32)), _p(idx), _p(xyz), _p(area))
+    if h < 0:
+        raise MemoryError("oracle hull allocation failed")
+    return HullResult(idx[:h].copy(), xyz[:h].copy(), float(area[0]))
+
+
+def hull_project(x, y, z, plane) -> Tuple[np.ndarray, np.ndarray]:
+    x, y, z = _c(x, np.float32), _c(y, np.float32), _c(z, np.float32)
+    u = np.empty(len(x), np.float64)
+    v = np.empty(len(x), np.float64)
+    lib().vo_hull_project(_p(x), _p(y), _p(z), len(x), _p(_c(plane, np.float32)), _p(u), _p(v))
+    return u, v
+
+
+# --------------------------------------------------------------------------
+# the map and the per-frame path
+# --------------------------------------------------------------------------
+class OracleMap:
+    """Sparse voxel map as arrays sorted by key (Sec. III-B): per occupied
+    voxel its point count and the integer sums of its fixed-point offsets."""
+
+    def __init__(self, origin, voxel_size: float, dims):
+        self.origin = np.asarray(origin, np.float64)
+        self.voxel_size = float(voxel_size)
+        self.dims = np.asarray(dims, np.int32)
+        self.key = np.zeros(0, np.uint32)
+        self.cnt = np.zeros(0, np.uint32)
+        self.sums = np.zeros((0, 3), np.uint64)
+        self.points_in = 0
+        self.points_dropped = 0
+
+    def insert(self, xyz: np.ndarray, R=None, t=None) -> None:
+        R = np.eye(3) if R is None else R
+        t = np.zeros(3) if t is None else t
+        pk, pf, kept = voxelize(xyz, R, t, self.origin, self.voxel_size, self.dims)
+        cap = len(self.key) + kept
+        ok = np.empty(max(cap, 1), np.uint32)
+        oc = np.empty(max(cap, 1), np.uint32)
+        osum = np.empty((max(cap, 1), 3), np.uint64)
+        n = lib().vo_map_accumulate(_p(self.key), _p(self.cnt), _p(self.sums), len(self.key),
+                                    _p(pk), _p(pf), len(pk), _p(ok), _p(oc), _p(osum), cap)
+        if n < 0:
+            raise MemoryError("oracle map accumulate failed")
+        self.key, self.cnt, self.sums = ok[:n].copy(), oc[:n].copy(), osum[:n].copy()
+        self.points_in += kept
+        self.points_dropped += len(pk) - kept
+
+    def means(self) -> np.ndarray:
+        return voxel_mean(self.key, self.cnt, self.sums, self.origin, self.voxel_size, self.dims)
+
+
+@dataclasses.dataclass
+class Clusters:
+    off: np.ndarray            # uint32[K+1]
+    key: np.ndarray            # uint32[sum]: voxel keys, ascending inside a cluster
+    xyz: np.ndarray            # float32[sum, 3]: voxel means
+    tag: np.ndarray            # uint32[K]: cluster label = smallest key
+
+
+def group(keys: np.ndarray, labels: np.ndarray, mu: np.ndarray, min_cluster: int) -> Clusters:
+    """Voxels sharing a label form a cluster (Sec. III-C, clustering); clusters
+    below ``min_cluster`` voxels are dropped; clusters are ordered by label and
+    the voxels of a cluster by key (both inputs are in ascending key order)."""
+    uniq, inv, counts = np.unique(labels, return_inverse=True, return_counts=True)
+    keep = counts[inv] >= min_cluster
+    sel = np.nonzero(keep)[0]
+    order = sel[np.argsort(labels[sel], kind="stable")]
+    kept_labels = uniq[counts >= min_cluster]
+    sizes = counts[counts >= min_cluster]
+    off = np.zeros(len(kept_labels) + 1, np.uint32)
+    off[1:] = np.cumsum(sizes)
+    return Clusters(off, keys[order].astype(np.uint32), mu[order].astype(np.float32),
+                    kept_labels.astype(np.uint32))
+
+
+@dataclasses.dataclass
+class ClusterResult:
+    tag: int
+    ransac: RansacResult
+    hull: Optional[HullResult]          # hull vertices indexed cluster-locally
+    hull_local: Optional[np.ndarray]    # uint32 cluster-local point indices of the vertices
+
+
+def plane_and_hull(x, y, z, n_hyp: int, eps: float, seed: int, tag: int, frame: int) -> ClusterResult:
+    r = ransac(x, y, z, n_hyp, eps, seed, tag, frame)
+    if r.best_h < 0:
+        return ClusterResult(tag, r, None, None)
+    inl = r.inliers
+    hres = hull(np.asarray(x)[inl], np.asarray(y)[inl], np.asarray(z)[inl], r.plane)
+    return ClusterResult(tag, r, hres, inl[hres.idx].astype(np.uint32))
+
+
+@dataclasses.dataclass
+class FrameResult:
+    labels: np.ndarray
+    clusters: Clusters
+    results: List[ClusterResult]
+
+
+def segment(m: OracleMap, min_cluster: int, n_hyp: int, eps: float, seed: int, frame: int,
+            cluster_subset: Optional[List[int]] = None) -> FrameResult:
+    """Sec. III-C on the whole accumulated map: label, group, then one plane
+    and one hull per kept cluster (optionally only for ``cluster_subset``)."""
+    labels, _ = ccl26(m.key, m.dims)
+    cl = group(m.key, labels, m.means(), min_cluster)
+    res = []
+    ks = range(len(cl.tag)) if cluster_subset is None else cluster_subset
+    for k in ks:
+        a, b = int(cl.off[k]), int(cl.off[k + 1])
+        p = cl.xyz[a:b]
+        res.append(plane_and_hull(p[:, 0], p[:, 1], p[:, 2], n_hyp, eps, seed, int(cl.tag[k]), frame))
+    return FrameResult(labels, cl, res)

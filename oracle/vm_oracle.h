@@ -1,0 +1,88 @@
+/*
+ * vm_oracle.h -- slow, plain CPU reference of the voxel-map plane-segmentation
+ * path.  TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the
+ * benchmark's CPU-baseline leg call it; the product path never does.
+ *
+ * It shares no code, header, table or constant generator with the HIP
+ * library.  Every function computes the plain definition of its step
+ * (arithmetic mean, connected components, argmax of inlier counts, convex
+ * hull) or, for the randomised RANSAC step, the algorithm's own steps in the
+ * paper's order.  Numeric conventions: IEEE binary32/binary64 with
+ * round-to-nearest-even, no contraction (built with -ffp-contract=off), every
+ * fused multiply-add written out as fma()/fmaf().
+ */
+#ifndef VM_ORACLE_H
+#define VM_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VO_NO_KEY 0xFFFFFFFFu
+
+/* Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): one block. */
+void vo_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);
+
+/* Sec. III-C (a): the three distinct point indices in [0, n) that hypothesis
+ * h of cluster `tag` in frame `frame` samples (n >= 3). */
+void vo_draw3(uint64_t seed, uint64_t tag, uint64_t frame, uint64_t h, uint64_t n, uint64_t out[3]);
+
+/* Sec. III-B "Voxel information update", first step: transform each sensor
+ * point by map_from_sensor (R row-major, t) and voxelise it.  Per point i:
+ *   key[i]  = x + NX*(y + NY*z) of the voxel, or VO_NO_KEY if the point is
+ *             non-finite or outside the grid;
+ *   frac[3i..3i+2] = offset inside the voxel in units of s/2^20.
+ * Returns the number of kept points. */
+int64_t vo_voxelize(const float* xyz, int64_t n, const double R[9], const double t[3],
+                    const double origin[3], double voxel_size, const int32_t dims[3],
+                    uint32_t* key, uint64_t* frac);
+
+/* Eq. (1): accumulate voxelised points into a map held as arrays sorted by
+ * key (count and integer offset sums per voxel).  The input map arrays
+ * (n_in entries) and the output arrays (capacity out_cap) must not alias.
+ * Returns the new number of occupied voxels, or -1 if out_cap is too small. */
+int64_t vo_map_accumulate(const uint32_t* in_key, const uint32_t* in_cnt, const uint64_t* in_sum,
+                          int64_t n_in, const uint32_t* pt_key, const uint64_t* pt_frac,
+                          int64_t n_pts, uint32_t* out_key, uint32_t* out_cnt, uint64_t* out_sum,
+                          int64_t out_cap);
+
+/* Eq. (1) closed form: the voxel's mean position, one float32 xyz per voxel. */
+void vo_voxel_mean(const uint32_t* key, const uint32_t* cnt, const uint64_t* sum, int64_t n,
+                   const double origin[3], double voxel_size, const int32_t dims[3], float* mu);
+
+/* Alg. 1 fixed point: label[i] = smallest key in the 26-connected component of
+ * occupied voxel i.  keys must be strictly ascending.  Breadth-first search
+ * from each unvisited voxel in ascending key order.  Returns the number of
+ * components, or -1 on allocation failure. */
+int64_t vo_ccl26(const uint32_t* keys, int64_t n, const int32_t dims[3], uint32_t* label);
+
+/* Sec. III-C "Multi-plane estimation" (a)-(c) for one cluster of n points in
+ * canonical order.  counts[h] = inliers of hypothesis h (-1: degenerate),
+ * hyp[4h..4h+3] = its float32 plane (nx,ny,nz,d).  best = [nx,ny,nz,d] of the
+ * winning hypothesis; inlier_idx lists its inliers (ascending local indices).
+ * Returns the best hypothesis index, or -1 if every hypothesis is degenerate
+ * (or n < 3). *n_inliers receives the inlier count (0 if none). */
+int32_t vo_ransac(const float* x, const float* y, const float* z, int64_t n,
+                  uint32_t n_hyp, float eps, uint64_t seed, uint64_t tag, uint64_t frame,
+                  int32_t* counts, float* hyp, float best[4], uint32_t* inlier_idx,
+                  int64_t* n_inliers);
+
+/* Sec. III-C "Boundary polygon generation": 2D convex hull of m points lying
+ * near the plane (nx,ny,nz,d).  hull_idx receives indices into the m points,
+ * counter-clockwise from the lexicographically smallest (u,v); hull_xyz the
+ * vertices projected onto the plane; *area the polygon area (m^2, 0 when the
+ * hull has fewer than 3 vertices).  Returns the vertex count, or -1 on
+ * allocation failure.  Buffers must hold m entries. */
+int64_t vo_hull(const float* x, const float* y, const float* z, int64_t m, const float plane[4],
+                uint32_t* hull_idx, float* hull_xyz, double* area);
+
+/* The in-plane 2D coordinates used by vo_hull (exposed for tests). */
+void vo_hull_project(const float* x, const float* y, const float* z, int64_t m,
+                     const float plane[4], double* u_out, double* v_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

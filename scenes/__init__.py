@@ -1,0 +1,336 @@
+"""Seeded synthetic inputs shaped like the paper's workloads.
+
+This module only *draws inputs*: planar surfaces sampled uniformly by area,
+Gaussian noise along each surface normal, uniform outliers, sensor poses.
+It holds none of the segmentation method's arithmetic (no voxelisation, no
+clustering, no plane fitting, no hulls), so both the HIP path and the CPU
+oracle may take their inputs from here.
+
+The paper evaluates on simulated MuJoCo scenes seen through simulated
+D435 / Livox / RoboSense sensors (Sec. IV-A); those are not available, so the
+scenes below stand in for them with the same structure: a floor, an
+open-tread staircase, a tabletop and tilted planar patches inside a
+robot-centric box at 0.01 m voxels (Sec. IV-A), plus the cluster-parallel
+ablation shape (Sec. IV-C) scaled up to thousands of clusters.
+
+All randomness comes from ``numpy.random.default_rng(seed)``; every array
+returned is a fresh float32/float64 numpy array.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+__all__ = [
+    "Rect", "Scene", "MapGeom",
+    "scene_tiny", "scene_tiny_exact", "scene_full_map", "scene_stress",
+    "frame_points", "identity_pose", "pose_inverse_apply",
+    "random_walk_poses", "batched_clusters",
+]
+
+
+@dataclasses.dataclass(frozen=True)
+class MapGeom:
+    """Voxel grid geometry: lower corner, voxel edge, cell counts."""
+    origin: Tuple[float, float, float]
+    voxel_size: float
+    dims: Tuple[int, int, int]
+
+    @property
+    def hi(self) -> np.ndarray:
+        return np.asarray(self.origin) + self.voxel_size * np.asarray(self.dims, dtype=np.float64)
+
+
+@dataclasses.dataclass(frozen=True)
+class Rect:
+    """Planar rectangle: centre, two orthonormal in-plane axes, half-sizes."""
+    centre: Tuple[float, float, float]
+    axis_a: Tuple[float, float, float]
+    axis_b: Tuple[float, float, float]
+    half_a: float
+    half_b: float
+
+    @property
+    def normal(self) -> np.ndarray:
+        n = np.cross(np.asarray(self.axis_a), np.asarray(self.axis_b))
+        return n / np.linalg.norm(n)
+
+    @property
+    def area(self) -> float:
+        return 4.0 * self.half_a * self.half_b
+
+    def sample(self, rng: np.random.Generator, n: int, sigma: float) -> np.ndarray:
+        s = rng.uniform(-1.0, 1.0, size=(n, 2))
+        p = (np.asarray(self.centre)[None, :]
+             + (s[:, :1] * self.half_a) * np.asarray(self.axis_a)[None, :]
+             + (s[:, 1:] * self.half_b) * np.asarray(self.axis_b)[None, :])
+        if sigma > 0:
+            p = p + rng.normal(0.0, sigma, size=(n, 1)) * self.normal[None, :]
+        return p
+
+    def corners(self) -> np.ndarray:
+        c = np.asarray(self.centre)
+        a = np.asarray(self.axis_a) * self.half_a
+        b = np.asarray(self.axis_b) * self.half_b
+        return np.stack([c - a - b, c + a - b, c + a + b, c - a + b])
+
+
+def _hrect(x0: float, x1: float, y0: float, y1: float, z: float) -> Rect:
+    """Horizontal rectangle [x0,x1) x [y0,y1) at height z (normal +z)."""
+    return Rect(((x0 + x1) / 2, (y0 + y1) / 2, z), (1.0, 0.0, 0.0), (0.0, 1.0, 0.0),
+                (x1 - x0) / 2, (y1 - y0) / 2)
+
+
+@dataclasses.dataclass
+class Scene:
+    """A static scene plus the per-frame sampling recipe."""
+    name: str
+    geom: MapGeom
+    rects: List[Rect]
+    n_points: int
+    sigma: float
+    outlier_frac: float
+    n_hyp: int
+    eps: float = 0.01
+    min_cluster: int = 30
+    seed: int = 0
+    extra_points: Optional[np.ndarray] = None  # injected exact points (float64)
+
+
+def scene_tiny(seed: int = 0) -> Scene:
+    """1.28 m cube at 0.01 m (128^3): floor z=0 and two 0.30x0.60 m stair
+    treads at z=0.18 and z=0.36; 50k points, N(0, 2 mm), 2 % outliers."""
+    geom = MapGeom((0.0, 0.0, -0.64), 0.01, (128, 128, 128))
+    rects = [
+        _hrect(0.0, 1.28, 0.0, 1.28, 0.0),
+        _hrect(0.40, 0.70, 0.34, 0.94, 0.18),
+        _hrect(0.70, 1.00, 0.34, 0.94, 0.36),
+    ]
+    return Scene("tiny", geom, rects, 50_000, 0.002, 0.02, n_hyp=256, seed=seed)
+
+
+def scene_tiny_exact(seed: int = 0) -> Scene:
+    """Noise-free, outlier-free variant of :func:`scene_tiny` with each
+    rectangle's four corners injected (for exact-recovery checks)."""
+    sc = scene_tiny(seed)
+    corners = np.concatenate([r.corners() for r in sc.rects[1:]], axis=0)
+    # keep the injected corners strictly inside the grid's half-open range
+    corners = np.minimum(corners, np.nextafter(sc.geom.hi, -np.inf) - 1e-9)
+    return dataclasses.replace(sc, name="tiny_exact", sigma=0.0, outlier_frac=0.0,
+                               extra_points=corners)
+
+
+def _rot_xy(alpha: float, beta: float) -> np.ndarray:
+    ca, sa, cb, sb = math.cos(alpha), math.sin(alpha), math.cos(beta), math.sin(beta)
+    rx = np.array([[1, 0, 0], [0, ca, -sa], [0, sa, ca]])
+    ry = np.array([[cb, 0, sb], [0, 1, 0], [-sb, 0, cb]])
+    return rx @ ry
+
+
+def _rect_grid(r: Rect, spacing: float) -> np.ndarray:
+    na = max(2, int(2 * r.half_a / spacing) + 1)
+    nb = max(2, int(2 * r.half_b / spacing) + 1)
+    sa, sb = np.meshgrid(np.linspace(-1, 1, na), np.linspace(-1, 1, nb), indexing="ij")
+    return (np.asarray(r.centre)[None, :]
+            + (sa.reshape(-1, 1) * r.half_a) * np.asarray(r.axis_a)[None, :]
+            + (sb.reshape(-1, 1) * r.half_b) * np.asarray(r.axis_b)[None, :])
+
+
+def _staircase(n_steps: int, x0: float, y0: float, y1: float, run: float, rise: float) -> List[Rect]:
+    return [_hrect(x0 + run * i, x0 + run * (i + 1), y0, y1, rise * (i + 1)) for i in range(n_steps)]
+
+
+def _place_patches(rng: np.random.Generator, fixed: List[Rect], n: int, side: Tuple[float, float],
+                   centre_lo: Sequence[float], centre_hi: Sequence[float], tilt_deg: float,
+                   clearance: float, z_range: Tuple[float, float]) -> List[Rect]:
+    """Rejection-sample ``n`` tilted square-ish patches keeping ``clearance``
+    metres from every other surface (so each stays its own component)."""
+    from scipy.spatial import cKDTree
+    spacing = 0.02
+    placed: List[Rect] = []
+    cloud = [_rect_grid(r, spacing) for r in fixed]
+    tries = 0
+    while len(placed) < n:
+        tries += 1
+        if tries > 200_000:
+            raise RuntimeError("patch placement did not converge")
+        ha, hb = rng.uniform(side[0], side[1], size=2) / 2
+        c = rng.uniform(centre_lo, centre_hi)
+        alpha, beta = np.deg2rad(rng.uniform(-tilt_deg, tilt_deg, size=2))
+        rot = _rot_xy(alpha, beta)
+        r = Rect(tuple(c), tuple(rot[:, 0]), tuple(rot[:, 1]), float(ha), float(hb))
+        g = _rect_grid(r, spacing)
+        if g[:, 2].min() < z_range[0] or g[:, 2].max() > z_range[1]:
+            continue
+        tree = cKDTree(np.concatenate(cloud, axis=0))
+        d, _ = tree.query(g, k=1)
+        if d.min() < clearance + spacing:
+            continue
+        placed.append(r)
+        cloud.append(g)
+    return placed
+
+
+def scene_full_map(seed: int = 1) -> Scene:
+    """4x4x2 m local map at 0.01 m (400x400x200 cells): floor, 12-step
+    open-tread staircase (0.18 m rise, 0.28 m run; treads above the map top
+    fall outside the grid), a 1.2x0.8 m tabletop at 0.72 m and 20 tilted
+    (up to +-30 deg) planar patches with sides 0.2-0.6 m; 1M points per frame,
+    N(0, 3 mm), 5 % outliers, 512 hypotheses."""
+    geom = MapGeom((-2.0, -2.0, -0.1), 0.01, (400, 400, 200))
+    rng = np.random.default_rng(seed)
+    fixed = [_hrect(-2.0, 2.0, -2.0, 2.0, 0.0)]
+    fixed += _staircase(12, -1.5, -1.9, -0.9, 0.28, 0.18)
+    fixed += [_hrect(0.3, 1.5, 0.5, 1.3, 0.72)]
+    patches = _place_patches(rng, fixed, 20, (0.2, 0.6), (-1.8, -1.8, 0.1), (1.8, 1.8, 1.6),
+                             30.0, 0.05, (0.05, 1.85))
+    return Scene("full_map", geom, fixed + patches, 1_000_000, 0.003, 0.05, n_hyp=512, seed=seed)
+
+
+def scene_stress(seed: int = 5, n_boxes: int = 500) -> Scene:
+    """4x4x2 m at 0.005 m (800x800x400 cells): floor, staircase, two tables
+    and ``n_boxes`` floating yawed boxes (sides 0.05-0.4 m, all 6 faces);
+    8M points per frame, N(0, 1.5 mm), 5 % outliers, 1024 hypotheses."""
+    from scipy.spatial import cKDTree
+    geom = MapGeom((-2.0, -2.0, -0.1), 0.005, (800, 800, 400))
+    rng = np.random.default_rng(seed)
+    fixed = [_hrect(-2.0, 2.0, -2.0, 2.0, 0.0)]
+    fixed += _staircase(12, -1.5, -1.9, -0.9, 0.28, 0.18)
+    fixed += [_hrect(0.3, 1.5, 0.5, 1.3, 0.72), _hrect(-1.2, -0.4, 0.6, 1.4, 0.76)]
+    cloud = [_rect_grid(r, 0.02) for r in fixed]
+    tree = cKDTree(np.concatenate(cloud))
+    boxes: List[Rect] = []
+    placed_pts = []
+    tries = 0
+    while len(boxes) < 6 * n_boxes:
+        tries += 1
+        if tries > 500_000:
+            raise RuntimeError("box placement did not converge")
+        sx, sy, sz = rng.uniform(0.05, 0.4, size=3)
+        c = rng.uniform((-1.8, -1.8, 0.1), (1.8, 1.8, 1.7))
+        yaw = rng.uniform(0, 2 * math.pi)
+        ex = np.array([math.cos(yaw), math.sin(yaw), 0.0])
+        ey = np.array([-math.sin(yaw), math.cos(yaw), 0.0])
+        ez = np.array([0.0, 0.0, 1.0])
+        faces = []
+        for ax, (u, v), h, (hu, hv) in ((ez, (ex, ey), sz / 2, (sx / 2, sy / 2)),
+                                        (ex, (ey, ez), sx / 2, (sy / 2, sz / 2)),
+                                        (ey, (ez, ex), sy / 2, (sz / 2, sx / 2))):
+            for sgn in (1.0, -1.0):
+                fc = c + sgn * h * ax
+                uu, vv = (u, v) if sgn > 0 else (v, u)
+                hu_, hv_ = (hu, hv) if sgn > 0 else (hv, hu)
+                faces.append(Rect(tuple(fc), tuple(uu), tuple(vv), float(hu_), float(hv_)))
+        g = np.concatenate([_rect_grid(f, 0.02) for f in faces])
+        if g[:, 2].min() < 0.03 or g[:, 2].max() > 1.85:
+            continue
+        if tree.query(g, k=1)[0].min() < 0.04:
+            continue
+        if placed_pts:
+            t2 = cKDTree(np.concatenate(placed_pts))
+            if t2.query(g, k=1)[0].min() < 0.04:
+                continue
+        boxes += faces
+        placed_pts.append(g)
+    return Scene("stress", geom, fixed + boxes, 8_000_000, 0.0015, 0.05, n_hyp=1024, seed=seed)
+
+
+def identity_pose() -> Tuple[np.ndarray, np.ndarray]:
+    return np.eye(3), np.zeros(3)
+
+
+def pose_inverse_apply(R: np.ndarray, t: np.ndarray, pw: np.ndarray) -> np.ndarray:
+    """Express map-frame points in the sensor frame of map_from_sensor (R, t)."""
+    return (pw - t[None, :]) @ R
+
+
+def frame_points(scene: Scene, frame_seed: int, n: Optional[int] = None,
+                 pose: Optional[Tuple[np.ndarray, np.ndarray]] = None) -> np.ndarray:
+    """One sensor frame: ``n`` float32 xyz points (default ``scene.n_points``).
+
+    A fraction ``outlier_frac`` is uniform in the map box; the rest is spread
+    over the scene's rectangles proportionally to area with Gaussian noise of
+    ``sigma`` along each normal. With ``pose`` = map_from_sensor (R, t), the
+    points are returned in the sensor frame (map points pushed through the
+    inverse pose, then rounded to float32)."""
+    n = scene.n_points if n is None else int(n)
+    rng = np.random.default_rng(frame_seed)
+    n_out = int(round(n * scene.outlier_frac))
+    extra = scene.extra_points if scene.extra_points is not None else np.zeros((0, 3))
+    n_surf = n - n_out - len(extra)
+    areas = np.array([r.area for r in scene.rects])
+    per = rng.multinomial(n_surf, areas / areas.sum())
+    parts = [r.sample(rng, int(k), scene.sigma) for r, k in zip(scene.rects, per) if k > 0]
+    lo = np.asarray(scene.geom.origin, dtype=np.float64)
+    hi = scene.geom.hi
+    parts.append(rng.uniform(lo, hi, size=(n_out, 3)))
+    parts.append(np.asarray(extra, dtype=np.float64))
+    pw = np.concatenate(parts, axis=0)
+    pw = pw[rng.permutation(len(pw))]
+    if pose is not None:
+        pw = pose_inverse_apply(np.asarray(pose[0]), np.asarray(pose[1]), pw)
+    return np.ascontiguousarray(pw.astype(np.float32))
+
+
+def _so3_exp(w: np.ndarray) -> np.ndarray:
+    th = float(np.linalg.norm(w))
+    k = np.array([[0, -w[2], w[1]], [w[2], 0, -w[0]], [-w[1], w[0], 0]])
+    if th < 1e-12:
+        return np.eye(3) + k
+    return np.eye(3) + math.sin(th) / th * k + (1 - math.cos(th)) / th ** 2 * (k @ k)
+
+
+def random_walk_poses(seed: int, n_frames: int, sigma_t: float = 0.01,
+                      sigma_rot_deg: float = 0.5) -> List[Tuple[np.ndarray, np.ndarray]]:
+    """6-DoF random walk from the identity: per frame dt ~ N(0, sigma_t)^3 and
+    a rotation increment exp(N(0, sigma_rot)^3), composed in float64."""
+    rng = np.random.default_rng(seed)
+    R, t = np.eye(3), np.zeros(3)
+    out = []
+    for _ in range(n_frames):
+        out.append((R.copy(), t.copy()))
+        dR = _so3_exp(np.deg2rad(rng.normal(0.0, sigma_rot_deg, size=3)))
+        R = R @ dR
+        t = t + rng.normal(0.0, sigma_t, size=3)
+    return out
+
+
+def batched_clusters(seed: int = 3, n_clusters: int = 2000, n_min: int = 50, n_max: int = 200_000,
+                     sigma: float = 0.002, outlier_frac: float = 0.10,
+                     cap_deg: float = 40.0) -> Tuple[np.ndarray, np.ndarray]:
+    """Thousands of noisy plane patches of log-uniform size, as a CSR.
+
+    Cluster k holds n_k = floor(exp(U(ln n_min, ln n_max))) points: a square of
+    side 0.01*sqrt(n_k) m (one point per cm^2, like 0.01 m voxel means) with
+    normal uniform on the ``cap_deg`` cap around +z and centre uniform in
+    [-2,2]^2 x [0,2]; (1-outlier_frac) of the points lie on it with N(0, sigma)
+    along the normal, the rest are uniform in the square x [-0.1, 0.1] m
+    along the normal. Returns (off uint32[K+1], xyz float32[sum n_k, 3])."""
+    rng = np.random.default_rng(seed)
+    sizes = np.floor(np.exp(rng.uniform(math.log(n_min), math.log(n_max), size=n_clusters))).astype(np.int64)
+    off = np.zeros(n_clusters + 1, dtype=np.int64)
+    off[1:] = np.cumsum(sizes)
+    xyz = np.empty((int(off[-1]), 3), dtype=np.float32)
+    cos_cap = math.cos(math.radians(cap_deg))
+    for k in range(n_clusters):
+        n = int(sizes[k])
+        ct = rng.uniform(cos_cap, 1.0)
+        st = math.sqrt(max(0.0, 1 - ct * ct))
+        ph = rng.uniform(0, 2 * math.pi)
+        nrm = np.array([st * math.cos(ph), st * math.sin(ph), ct])
+        a = np.cross(nrm, [1.0, 0.0, 0.0])
+        a /= np.linalg.norm(a)
+        b = np.cross(nrm, a)
+        c = rng.uniform((-2, -2, 0), (2, 2, 2))
+        half = 0.005 * math.sqrt(n)
+        n_out = int(round(n * outlier_frac))
+        n_in = n - n_out
+        s = rng.uniform(-half, half, size=(n, 2))
+        h = np.concatenate([rng.normal(0.0, sigma, size=n_in), rng.uniform(-0.1, 0.1, size=n_out)])
+        p = c[None, :] + s[:, :1] * a[None, :] + s[:, 1:] * b[None, :] + h[:, None] * nrm[None, :]
+        p = p[rng.permutation(n)]
+        xyz[off[k]:off[k + 1]] = p.astype(np.float32)
+    return off.astype(np.uint32), xyz
