@@ -1,0 +1,268 @@
+/*
+ * vm.h -- C ABI of the MI355X (gfx950) voxel-map plane-segmentation library.
+ *
+ * The library implements the data-parallel path of Niijima et al., "Real-time
+ * Multi-Plane Segmentation Based on GPU Accelerated High-Resolution 3D Voxel
+ * Mapping for Legged Robot Locomotion" (arXiv 2510.01592):
+ *   vm_insert        Sec. III-B, Eq. (1)    points + pose -> sparse voxel map
+ *   vm_ccl           Sec. III-C, Alg. 1     occupied voxels -> component labels,
+ *                                           clusters (grouping)
+ *   vm_ransac_planes Sec. III-C (a)-(c)     one plane + inlier set per cluster
+ *   vm_hulls         Sec. III-C, boundary   one convex polygon per plane
+ *   vm_segment_frame Sec. III-A overview    all of the above for one frame
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Pointers named d_* are device (HBM) pointers on the current HIP device;
+ *   everything else is host memory read during the call only.
+ * - `stream` is a hipStream_t (passed as void*; NULL = the null stream).  All
+ *   device work is enqueued on it and the call returns without waiting,
+ *   except where a call says it synchronises.  Device buffers handed to a
+ *   call must stay alive until the stream has passed that call.
+ * - Argument errors are detected on the host before anything is enqueued and
+ *   return VM_E_ARG; nothing is written then.  Conditions only the device can
+ *   see (hash table full, output capacity exceeded) never write out of
+ *   bounds: the overflowing items are dropped and a VM_FLAG_* bit is OR-ed
+ *   into a device status word (the map's, readable with vm_map_stats, or the
+ *   caller's d_status).  No C++ exception crosses this ABI.
+ * - Calls on one map, and calls sharing one workspace, must be serialised by
+ *   the caller (one stream at a time); different maps and workspaces are
+ *   independent.
+ * - Numeric conventions: IEEE binary32/binary64, round-to-nearest-even, no
+ *   contraction; every fused multiply-add is an explicit fma.  The results
+ *   are deterministic: they do not depend on launch shapes, scheduling or
+ *   stream interleaving.
+ */
+#ifndef VM_H
+#define VM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes (return values) ------------------------------------- */
+typedef int32_t vm_status;
+#define VM_OK            0
+#define VM_E_ARG        -1   /* invalid argument (null pointer, bad size, bad geometry) */
+#define VM_E_OOM        -2   /* device allocation failed */
+#define VM_E_CAPACITY   -3   /* a host-known size exceeds a capacity */
+#define VM_E_DEVICE     -4   /* a HIP runtime call failed */
+#define VM_E_STATE      -5   /* call out of order (e.g. no clusters computed yet) */
+
+/* ---- device status flags (OR-ed into a device uint32 word) ------------ */
+#define VM_FLAG_HASH_FULL      0x1u  /* a new voxel found no free hash slot; its points were dropped */
+#define VM_FLAG_CLUSTERS_CAP   0x2u  /* more clusters than the output's k_cap; the rest were skipped */
+#define VM_FLAG_INLIERS_CAP    0x4u  /* inlier index output full; later inliers not listed */
+#define VM_FLAG_HULL_CAP       0x8u  /* hull vertex output full; later polygons truncated */
+#define VM_FLAG_BAD_CLUSTERS   0x10u /* cluster offsets not ascending from 0 or beyond n_cap; nothing processed */
+
+/* Human-readable text for a status code (static storage). */
+const char* vm_status_string(vm_status s);
+
+/* Library version, major*10000 + minor*100 + patch. */
+int32_t vm_version(void);
+
+/* ---- the voxel map (Sec. III-B) ---------------------------------------- */
+typedef struct vm_map_s* vm_map;
+
+/* Grid geometry and storage of a map.  Voxel (x, y, z) covers
+ * [origin + s*(x,y,z), origin + s*(x+1,y+1,z+1)) (half-open cells) and has
+ * key x + NX*(y + NY*z); NX*NY*NZ must be below 2^32.  Occupied voxels live in
+ * an open-addressing hash of 2^hash_capacity_log2 slots (at most half of them
+ * should be used); the map also holds a 1-bit-per-cell occupancy index
+ * (NX*NY*NZ/8 bytes) and the per-frame segmentation buffers, all allocated
+ * once by vm_map_create. */
+typedef struct {
+    double   origin[3];           /* metres, map frame */
+    double   voxel_size;          /* s, metres, > 0 */
+    int32_t  dims[3];             /* NX, NY, NZ, each >= 1 */
+    uint32_t hash_capacity_log2;  /* 10..30 */
+} vm_map_desc;
+
+/* Rigid transform map_from_sensor: p_map = R p_sensor + t (R row-major). */
+typedef struct {
+    double R[9];
+    double t[3];
+} vm_pose;
+
+typedef struct {
+    uint64_t occupied;        /* occupied voxels */
+    uint64_t points_in;       /* points accumulated since create/clear */
+    uint64_t points_dropped;  /* non-finite or outside the grid */
+    uint64_t points_lost;     /* inside the grid but dropped because the hash was full */
+    uint32_t status_flags;    /* VM_FLAG_* seen since create/clear */
+    uint32_t hash_capacity_log2;
+} vm_map_stats_t;
+
+/* Allocate a map on the current device (hipMalloc; the map owns the memory
+ * until vm_map_destroy) and clear it (synchronously).  VM_E_ARG for bad
+ * geometry, VM_E_OOM if the device allocation fails. */
+vm_status vm_map_create(const vm_map_desc* desc, vm_map* out);
+vm_status vm_map_destroy(vm_map map);
+/* Empty the map (asynchronous on `stream`). */
+vm_status vm_map_clear(vm_map map, void* stream);
+/* Synchronises `stream`, then reports the map's counters. */
+vm_status vm_map_stats(vm_map map, void* stream, vm_map_stats_t* out);
+
+/* Sec. III-B "Voxel information update", Eq. (1).  Transforms the n float32
+ * xyz points at d_xyz (AoS, 12 bytes each, caller-owned device memory) by
+ * `pose` in fp64 (x' = fma(R02, z, fma(R01, y, fma(R00, x, t0))), likewise for
+ * y', z'), voxelises them, and accumulates each into its voxel: count += 1 and
+ * the 2^-20-voxel fixed-point offset added to the voxel's integer sums, so
+ * the stored mean is the arithmetic mean that Eq. (1)'s recurrence computes,
+ * independent of arrival order.  Non-finite points and points outside the
+ * grid are counted and dropped.  n = 0 is a no-op; n < 0 is VM_E_ARG. */
+vm_status vm_insert(vm_map map, const float* d_xyz, int64_t n, const vm_pose* pose, void* stream);
+
+/* Export the occupied voxels in ascending key order (e.g. for checkpoints
+ * and checks).  Synchronises `stream`.  Writes min(occupied, cap) entries:
+ * d_key[i], d_count[i], d_sum[3i..3i+2] (integer offset sums, units of
+ * s*2^-20), d_mean[3i..3i+2] (float32 voxel mean; may be NULL).  *n_out
+ * receives the occupied count; VM_E_CAPACITY if cap is too small (the first
+ * cap entries are still written). */
+vm_status vm_map_export(vm_map map, uint32_t* d_key, uint32_t* d_count, uint64_t* d_sum,
+                        float* d_mean, uint64_t cap, uint64_t* n_out, void* stream);
+
+/* Replace the map's content with n voxels (keys strictly ascending and
+ * inside the grid, counts >= 1); the inverse of vm_map_export.
+ * Asynchronous. */
+vm_status vm_map_import(vm_map map, const uint32_t* d_key, const uint32_t* d_count,
+                        const uint64_t* d_sum, uint64_t n, void* stream);
+
+/* ---- clusters (Sec. III-C, Alg. 1 and grouping) ----------------------- */
+
+/* A set of point clusters in CSR form.  Cluster k owns points
+ * [d_off[k], d_off[k+1]) of the structure-of-arrays d_x/d_y/d_z; its RANSAC
+ * stream is selected by d_tag[k].  The number of clusters and of points can
+ * live on the device (d_meta[0] = K, d_meta[1] = total points), so a
+ * pipeline never has to wait for the host; k_cap and n_cap bound them and size
+ * every grid.  Views returned by vm_ccl point into the map and stay valid
+ * until the next vm_ccl / vm_segment_frame / vm_map_destroy on that map. */
+typedef struct {
+    uint32_t        k_cap;   /* host: upper bound on K (d_off has k_cap+1 entries, d_tag k_cap) */
+    uint32_t        n_cap;   /* host: upper bound on the total point count */
+    const uint32_t* d_meta;  /* device: [0] = K, [1] = total points */
+    const uint32_t* d_off;
+    const float*    d_x;
+    const float*    d_y;
+    const float*    d_z;
+    const uint32_t* d_key;   /* device, optional (NULL): voxel key of each point */
+    const uint32_t* d_tag;   /* device: per-cluster RNG tag (for map clusters: the label) */
+} vm_clusters;
+
+/* Alg. 1's fixed point over all occupied voxels of `map`: every voxel gets
+ * the smallest key of its 26-connected component (exact integer result).
+ * Then the grouping step: components of at least min_cluster voxels become
+ * clusters, ordered by label, with their voxels in ascending key order and
+ * each point the voxel's Eq. (1) mean; tag = label.
+ * d_labels (optional, NULL to skip): receives one label per occupied voxel
+ * in ascending key order (the caller sizes it by vm_map_stats().occupied).
+ * `out` receives a device-resident view (see vm_clusters).  Asynchronous. */
+vm_status vm_ccl(vm_map map, uint32_t min_cluster, uint32_t* d_labels, vm_clusters* out,
+                 void* stream);
+
+/* ---- planes (Sec. III-C "Multi-plane estimation") --------------------- */
+typedef struct {
+    uint32_t n_hyp;      /* hypotheses per cluster, 1..65536 */
+    float    eps;        /* inlier threshold, metres (the paper uses 0.01) */
+    uint64_t seed;       /* Philox4x64-10 key word 0 */
+    uint32_t frame;      /* counter word 2 (per-map frame number) */
+    uint32_t reserved;   /* must be 0 */
+} vm_ransac_params;
+
+/* Per-cluster RANSAC outputs (caller-owned device buffers).  For cluster k:
+ * hypothesis h draws three distinct point indices from Philox4x64-10 with key
+ * (seed, 0) and counter (h, tag[k], frame, 0), fits the plane through them in
+ * fp64 (unit normal oriented to +z, ties to +y then +x; rounded to float32),
+ * and counts the points with |fmaf(nz,z,fmaf(ny,y,fmaf(nx,x,d)))| < eps.  The
+ * first hypothesis with the largest count wins (degenerate triples count
+ * -1).  Clusters with no valid hypothesis get best_h = -1, n_inliers = 0 and
+ * a zero plane. */
+typedef struct {
+    uint32_t  k_cap;       /* capacity of the per-cluster arrays */
+    uint32_t  in_cap;      /* capacity of d_in_idx */
+    float*    d_plane;     /* [k_cap][4] nx, ny, nz, d of the winner */
+    int32_t*  d_best_h;    /* [k_cap] */
+    int32_t*  d_n_inliers; /* [k_cap] */
+    uint32_t* d_in_off;    /* [k_cap+1] inlier CSR: cluster k's inliers at [in_off[k], in_off[k+1]) */
+    uint32_t* d_in_idx;    /* [in_cap] cluster-local point indices, ascending */
+    int32_t*  d_counts;    /* optional [k_cap][n_hyp]: every hypothesis' count (NULL to skip) */
+    float*    d_hyp;       /* optional [k_cap][n_hyp][4]: every hypothesis' plane (NULL to skip) */
+    uint32_t* d_status;    /* [1] device word, VM_FLAG_* OR-ed in (never cleared by the library) */
+} vm_planes;
+
+/* Device scratch for vm_ransac_planes / vm_hulls, in bytes, for clusters
+ * bounded by (k_cap, n_cap) and n_hyp hypotheses. */
+size_t vm_workspace_bytes(uint32_t k_cap, uint32_t n_cap, uint32_t n_hyp);
+
+/* Sec. III-C (a)-(c) on every cluster of `cl`, all clusters in one pass.
+ * d_work: caller-owned device scratch of at least
+ * vm_workspace_bytes(cl->k_cap, cl->n_cap, params->n_hyp) bytes.
+ * Asynchronous. */
+vm_status vm_ransac_planes(const vm_clusters* cl, const vm_ransac_params* params, vm_planes* out,
+                           void* d_work, size_t work_bytes, void* stream);
+
+/* ---- polygons (Sec. III-C "Boundary polygon generation") -------------- */
+
+/* For cluster k with a plane: the 2D convex hull of its inliers in the
+ * plane.  In-plane basis (fp64): u = normalize(a x n) with a = e_x if
+ * |nx| < 0.9 else e_y, v = n x u; origin = the first inlier.  Vertices are
+ * listed counter-clockwise from the lexicographically smallest (u, v),
+ * without collinear or repeated points.  d_v_idx holds cluster-local point
+ * indices, d_v_xyz the vertices projected onto the plane (fp64 -> float32),
+ * d_area the shoelace area in fp64 (0 if fewer than 3 vertices or no plane). */
+typedef struct {
+    uint32_t  k_cap;
+    uint32_t  v_cap;     /* capacity of d_v_idx / d_v_xyz */
+    uint32_t* d_v_off;   /* [k_cap+1] */
+    uint32_t* d_v_idx;   /* [v_cap] */
+    float*    d_v_xyz;   /* [v_cap][3] */
+    double*   d_area;    /* [k_cap] */
+    uint32_t* d_status;  /* [1] device word, VM_FLAG_* OR-ed in */
+} vm_hulls_out;
+
+/* Asynchronous; d_work as for vm_ransac_planes (the same buffer may be
+ * reused: the calls are ordered on the stream). */
+vm_status vm_hulls(const vm_clusters* cl, const vm_planes* planes, vm_hulls_out* out,
+                   void* d_work, size_t work_bytes, void* stream);
+
+/* ---- one frame (Sec. III-A overview) ------------------------------------ */
+typedef struct {
+    uint32_t         min_cluster;   /* clusters below this many voxels are dropped (30) */
+    uint32_t         reserved;      /* must be 0 */
+    vm_ransac_params ransac;
+} vm_seg_params;
+
+/* vm_insert of the frame, then vm_ccl, vm_ransac_planes and vm_hulls over the
+ * whole accumulated map, using the map's own workspace.  Outputs as for the
+ * individual calls; d_labels and clusters_out may be NULL.  Asynchronous:
+ * nothing waits for the host. */
+vm_status vm_segment_frame(vm_map map, const float* d_xyz, int64_t n, const vm_pose* pose,
+                           const vm_seg_params* params, vm_planes* planes, vm_hulls_out* hulls,
+                           uint32_t* d_labels, vm_clusters* clusters_out, void* stream);
+
+/* ---- per-stage timing ---------------------------------------------------- */
+/* When enabled, every stage kernel of the library is bracketed by HIP events
+ * recorded on the stream it runs on; vm_stage_times synchronises each
+ * recorded event and returns accumulated milliseconds and launch counts per
+ * stage (index = VM_STAGE_*), then resets them.  Costs an event pair per
+ * launch, so leave it off outside measurements. */
+#define VM_STAGE_INSERT      0
+#define VM_STAGE_RANK        1
+#define VM_STAGE_CCL         2
+#define VM_STAGE_GROUP       3
+#define VM_STAGE_HYPOTHESES  4
+#define VM_STAGE_COUNT       5
+#define VM_STAGE_SELECT      6
+#define VM_STAGE_HULL        7
+#define VM_STAGE_N           8
+vm_status vm_set_stage_timing(int32_t enable);
+vm_status vm_stage_times(double* ms_out, uint64_t* launches_out, int32_t n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VM_H */

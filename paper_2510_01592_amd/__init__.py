@@ -1,0 +1,389 @@
+"""Python binding of ``libvm.so`` (include/vm.h): argument marshalling only.
+
+Every step of the path runs in the library's HIP kernels; this module only
+turns torch tensors into device pointers and the current HIP stream, and
+mirrors the C structs with ctypes.  Importing it loads the library and fails
+loudly if it has not been built (``python -m paper_2510_01592_amd.build``).
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libvm.so")
+
+VM_OK, VM_E_ARG, VM_E_OOM, VM_E_CAPACITY, VM_E_DEVICE, VM_E_STATE = 0, -1, -2, -3, -4, -5
+FLAG_HASH_FULL, FLAG_CLUSTERS_CAP, FLAG_INLIERS_CAP, FLAG_HULL_CAP = 0x1, 0x2, 0x4, 0x8
+STAGES = ["insert", "rank", "ccl", "group", "hypotheses", "count", "select", "hull"]
+
+EXPORTED = [
+    "vm_status_string", "vm_version", "vm_map_create", "vm_map_destroy", "vm_map_clear", "vm_map_stats",
+    "vm_insert", "vm_map_export", "vm_map_import", "vm_ccl", "vm_workspace_bytes", "vm_ransac_planes",
+    "vm_hulls", "vm_segment_frame", "vm_set_stage_timing", "vm_stage_times",
+]
+
+_P = ctypes.c_void_p
+
+
+class MapDesc(ctypes.Structure):
+    _fields_ = [("origin", ctypes.c_double * 3), ("voxel_size", ctypes.c_double),
+                ("dims", ctypes.c_int32 * 3), ("hash_capacity_log2", ctypes.c_uint32)]
+
+
+class Pose(ctypes.Structure):
+    _fields_ = [("R", ctypes.c_double * 9), ("t", ctypes.c_double * 3)]
+
+
+class MapStats(ctypes.Structure):
+    _fields_ = [("occupied", ctypes.c_uint64), ("points_in", ctypes.c_uint64),
+                ("points_dropped", ctypes.c_uint64), ("points_lost", ctypes.c_uint64),
+                ("status_flags", ctypes.c_uint32), ("hash_capacity_log2", ctypes.c_uint32)]
+
+
+class Clusters(ctypes.Structure):
+    _fields_ = [("k_cap", ctypes.c_uint32), ("n_cap", ctypes.c_uint32), ("d_meta", _P), ("d_off", _P),
+                ("d_x", _P), ("d_y", _P), ("d_z", _P), ("d_key", _P), ("d_tag", _P)]
+
+
+class RansacParams(ctypes.Structure):
+    _fields_ = [("n_hyp", ctypes.c_uint32), ("eps", ctypes.c_float), ("seed", ctypes.c_uint64),
+                ("frame", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class Planes(ctypes.Structure):
+    _fields_ = [("k_cap", ctypes.c_uint32), ("in_cap", ctypes.c_uint32), ("d_plane", _P), ("d_best_h", _P),
+                ("d_n_inliers", _P), ("d_in_off", _P), ("d_in_idx", _P), ("d_counts", _P), ("d_hyp", _P),
+                ("d_status", _P)]
+
+
+class HullsOut(ctypes.Structure):
+    _fields_ = [("k_cap", ctypes.c_uint32), ("v_cap", ctypes.c_uint32), ("d_v_off", _P), ("d_v_idx", _P),
+                ("d_v_xyz", _P), ("d_area", _P), ("d_status", _P)]
+
+
+class SegParams(ctypes.Structure):
+    _fields_ = [("min_cluster", ctypes.c_uint32), ("reserved", ctypes.c_uint32), ("ransac", RansacParams)]
+
+
+class VMError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {status_string(status)} ({status})")
+        self.status = status
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libvm.so; raises if it is missing (there is no fallback path)."""
+    global _lib
+    if _lib is None:
+        # torch first: the library then binds to the HIP runtime torch already
+        # loaded (same SONAME), so both share one runtime and one device context
+        import torch  # noqa: F401
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2510_01592_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        i32, u32, u64, i64, sz = ctypes.c_int32, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int64, ctypes.c_size_t
+        sig = {
+            "vm_status_string": ([i32], ctypes.c_char_p),
+            "vm_version": ([], i32),
+            "vm_map_create": ([ctypes.POINTER(MapDesc), ctypes.POINTER(_P)], i32),
+            "vm_map_destroy": ([_P], i32),
+            "vm_map_clear": ([_P, _P], i32),
+            "vm_map_stats": ([_P, _P, ctypes.POINTER(MapStats)], i32),
+            "vm_insert": ([_P, _P, i64, ctypes.POINTER(Pose), _P], i32),
+            "vm_map_export": ([_P, _P, _P, _P, _P, u64, ctypes.POINTER(u64), _P], i32),
+            "vm_map_import": ([_P, _P, _P, _P, u64, _P], i32),
+            "vm_ccl": ([_P, u32, _P, ctypes.POINTER(Clusters), _P], i32),
+            "vm_workspace_bytes": ([u32, u32, u32], sz),
+            "vm_ransac_planes": ([ctypes.POINTER(Clusters), ctypes.POINTER(RansacParams), ctypes.POINTER(Planes),
+                                  _P, sz, _P], i32),
+            "vm_hulls": ([ctypes.POINTER(Clusters), ctypes.POINTER(Planes), ctypes.POINTER(HullsOut), _P, sz, _P],
+                         i32),
+            "vm_segment_frame": ([_P, _P, i64, ctypes.POINTER(Pose), ctypes.POINTER(SegParams),
+                                  ctypes.POINTER(Planes), ctypes.POINTER(HullsOut), _P, ctypes.POINTER(Clusters), _P],
+                                 i32),
+            "vm_set_stage_timing": ([i32], i32),
+            "vm_stage_times": ([ctypes.POINTER(ctypes.c_double), ctypes.POINTER(u64), i32], i32),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def status_string(s: int) -> str:
+    return lib().vm_status_string(s).decode()
+
+
+def _check(st: int, what: str) -> None:
+    if st != VM_OK:
+        raise VMError(st, what)
+
+
+def _stream(stream=None) -> int:
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return s.cuda_stream
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("device tensor expected")
+    if not t.is_contiguous():
+        raise ValueError("contiguous tensor expected")
+    return t.data_ptr()
+
+
+def make_pose(R=None, t=None) -> Pose:
+    p = Pose()
+    R = np.eye(3) if R is None else np.asarray(R, np.float64).reshape(3, 3)
+    t = np.zeros(3) if t is None else np.asarray(t, np.float64).reshape(3)
+    for i in range(9):
+        p.R[i] = float(R.reshape(-1)[i])
+    for i in range(3):
+        p.t[i] = float(t[i])
+    return p
+
+
+def version() -> int:
+    return int(lib().vm_version())
+
+
+# --------------------------------------------------------------------------
+# outputs
+# --------------------------------------------------------------------------
+@dataclasses.dataclass
+class PlaneBuffers:
+    """Device buffers of vm_planes (allocated with torch)."""
+    k_cap: int
+    in_cap: int
+    n_hyp: int
+    plane: "torch.Tensor"
+    best_h: "torch.Tensor"
+    n_inliers: "torch.Tensor"
+    in_off: "torch.Tensor"
+    in_idx: "torch.Tensor"
+    status: "torch.Tensor"
+    counts: Optional["torch.Tensor"] = None
+    hyp: Optional["torch.Tensor"] = None
+
+    @staticmethod
+    def alloc(k_cap: int, in_cap: int, n_hyp: int, with_all: bool = False, device="cuda") -> "PlaneBuffers":
+        import torch
+        z = dict(device=device)
+        return PlaneBuffers(
+            k_cap, in_cap, n_hyp,
+            torch.zeros((k_cap, 4), dtype=torch.float32, **z),
+            torch.zeros(k_cap, dtype=torch.int32, **z),
+            torch.zeros(k_cap, dtype=torch.int32, **z),
+            torch.zeros(k_cap + 1, dtype=torch.int32, **z),
+            torch.zeros(max(in_cap, 1), dtype=torch.int32, **z),
+            torch.zeros(1, dtype=torch.int32, **z),
+            torch.zeros((k_cap, n_hyp), dtype=torch.int32, **z) if with_all else None,
+            torch.zeros((k_cap, n_hyp, 4), dtype=torch.float32, **z) if with_all else None,
+        )
+
+    def c(self) -> Planes:
+        return Planes(self.k_cap, self.in_cap, _ptr(self.plane), _ptr(self.best_h), _ptr(self.n_inliers),
+                      _ptr(self.in_off), _ptr(self.in_idx), _ptr(self.counts), _ptr(self.hyp), _ptr(self.status))
+
+
+@dataclasses.dataclass
+class HullBuffers:
+    k_cap: int
+    v_cap: int
+    v_off: "torch.Tensor"
+    v_idx: "torch.Tensor"
+    v_xyz: "torch.Tensor"
+    area: "torch.Tensor"
+    status: "torch.Tensor"
+
+    @staticmethod
+    def alloc(k_cap: int, v_cap: int, device="cuda") -> "HullBuffers":
+        import torch
+        z = dict(device=device)
+        return HullBuffers(k_cap, v_cap, torch.zeros(k_cap + 1, dtype=torch.int32, **z),
+                           torch.zeros(max(v_cap, 1), dtype=torch.int32, **z),
+                           torch.zeros((max(v_cap, 1), 3), dtype=torch.float32, **z),
+                           torch.zeros(k_cap, dtype=torch.float64, **z), torch.zeros(1, dtype=torch.int32, **z))
+
+    def c(self) -> HullsOut:
+        return HullsOut(self.k_cap, self.v_cap, _ptr(self.v_off), _ptr(self.v_idx), _ptr(self.v_xyz),
+                        _ptr(self.area), _ptr(self.status))
+
+
+def ransac_params(n_hyp: int, eps: float = 0.01, seed: int = 0x5EED, frame: int = 0) -> RansacParams:
+    return RansacParams(int(n_hyp), float(eps), int(seed) & (2 ** 64 - 1), int(frame) & 0xFFFFFFFF, 0)
+
+
+# --------------------------------------------------------------------------
+# the map
+# --------------------------------------------------------------------------
+class Map:
+    """A device-resident sparse voxel map (vm_map)."""
+
+    def __init__(self, origin: Sequence[float], voxel_size: float, dims: Sequence[int], hash_capacity_log2: int):
+        d = MapDesc()
+        for i in range(3):
+            d.origin[i] = float(origin[i])
+            d.dims[i] = int(dims[i])
+        d.voxel_size = float(voxel_size)
+        d.hash_capacity_log2 = int(hash_capacity_log2)
+        h = _P()
+        _check(lib().vm_map_create(ctypes.byref(d), ctypes.byref(h)), "vm_map_create")
+        self._h = h
+        self.origin = tuple(float(v) for v in origin)
+        self.voxel_size = float(voxel_size)
+        self.dims = tuple(int(v) for v in dims)
+
+    @property
+    def handle(self) -> int:
+        return self._h.value
+
+    def close(self) -> None:
+        if self._h is not None and self._h.value:
+            lib().vm_map_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def clear(self, stream=None) -> None:
+        _check(lib().vm_map_clear(self._h, _stream(stream)), "vm_map_clear")
+
+    def stats(self, stream=None) -> MapStats:
+        s = MapStats()
+        _check(lib().vm_map_stats(self._h, _stream(stream), ctypes.byref(s)), "vm_map_stats")
+        return s
+
+    def insert(self, xyz, R=None, t=None, stream=None) -> None:
+        if xyz.dtype.__str__() != "torch.float32" or xyz.dim() != 2 or xyz.shape[1] != 3:
+            raise ValueError("float32 [N, 3] tensor expected")
+        pose = make_pose(R, t)
+        _check(lib().vm_insert(self._h, _ptr(xyz), int(xyz.shape[0]), ctypes.byref(pose), _stream(stream)),
+               "vm_insert")
+
+    def export(self, cap: Optional[int] = None, stream=None):
+        """(key, count, sums, mean) of every occupied voxel, ascending keys (torch, device)."""
+        import torch
+        if cap is None:
+            cap = int(self.stats(stream).occupied)
+        cap = max(int(cap), 1)
+        key = torch.empty(cap, dtype=torch.int32, device="cuda")
+        cnt = torch.empty(cap, dtype=torch.int32, device="cuda")
+        sums = torch.empty((cap, 3), dtype=torch.int64, device="cuda")
+        mean = torch.empty((cap, 3), dtype=torch.float32, device="cuda")
+        n = ctypes.c_uint64()
+        st = lib().vm_map_export(self._h, _ptr(key), _ptr(cnt), _ptr(sums), _ptr(mean), cap, ctypes.byref(n),
+                                 _stream(stream))
+        _check(st, "vm_map_export")
+        m = int(n.value)
+        return key[:m], cnt[:m], sums[:m], mean[:m]
+
+    def import_(self, key, cnt, sums, stream=None) -> None:
+        _check(lib().vm_map_import(self._h, _ptr(key), _ptr(cnt), _ptr(sums), int(key.shape[0]), _stream(stream)),
+               "vm_map_import")
+
+    def ccl(self, min_cluster: int = 30, labels=None, stream=None) -> Clusters:
+        cl = Clusters()
+        _check(lib().vm_ccl(self._h, int(min_cluster), _ptr(labels), ctypes.byref(cl), _stream(stream)), "vm_ccl")
+        return cl
+
+    def segment_frame(self, xyz, planes: PlaneBuffers, hulls: HullBuffers, R=None, t=None, min_cluster: int = 30,
+                      n_hyp: int = 256, eps: float = 0.01, seed: int = 0x5EED, frame: int = 0, labels=None,
+                      stream=None) -> Clusters:
+        pose = make_pose(R, t)
+        sp = SegParams(int(min_cluster), 0, ransac_params(n_hyp, eps, seed, frame))
+        cl = Clusters()
+        pc, hc = planes.c(), hulls.c()
+        n = 0 if xyz is None else int(xyz.shape[0])
+        st = lib().vm_segment_frame(self._h, _ptr(xyz) if n else None, n, ctypes.byref(pose), ctypes.byref(sp),
+                                    ctypes.byref(pc), ctypes.byref(hc), _ptr(labels), ctypes.byref(cl),
+                                    _stream(stream))
+        _check(st, "vm_segment_frame")
+        return cl
+
+
+def cluster_view(off, x, y, z, tag, meta, key=None) -> Clusters:
+    """vm_clusters over caller-owned device tensors (off int32[K+1], x/y/z
+    float32[N], tag int32[K], meta int32[2] = (K, N))."""
+    K = int(tag.shape[0])
+    N = int(x.shape[0])
+    return Clusters(K, N, _ptr(meta), _ptr(off), _ptr(x), _ptr(y), _ptr(z), _ptr(key), _ptr(tag))
+
+
+def workspace_bytes(k_cap: int, n_cap: int, n_hyp: int) -> int:
+    return int(lib().vm_workspace_bytes(int(k_cap), int(n_cap), int(n_hyp)))
+
+
+def ransac_planes(cl: Clusters, params: RansacParams, out: PlaneBuffers, work, stream=None) -> None:
+    pc = out.c()
+    _check(lib().vm_ransac_planes(ctypes.byref(cl), ctypes.byref(params), ctypes.byref(pc), _ptr(work),
+                                  int(work.numel() * work.element_size()), _stream(stream)), "vm_ransac_planes")
+
+
+def hulls(cl: Clusters, planes: PlaneBuffers, out: HullBuffers, work, stream=None) -> None:
+    pc, hc = planes.c(), out.c()
+    _check(lib().vm_hulls(ctypes.byref(cl), ctypes.byref(pc), ctypes.byref(hc), _ptr(work),
+                          int(work.numel() * work.element_size()), _stream(stream)), "vm_hulls")
+
+
+def set_stage_timing(enable: bool) -> None:
+    _check(lib().vm_set_stage_timing(1 if enable else 0), "vm_set_stage_timing")
+
+
+def stage_times() -> Tuple[np.ndarray, np.ndarray]:
+    """(milliseconds, launches) per stage since the last call (synchronises)."""
+    ms = (ctypes.c_double * len(STAGES))()
+    n = (ctypes.c_uint64 * len(STAGES))()
+    _check(lib().vm_stage_times(ms, n, len(STAGES)), "vm_stage_times")
+    return np.array(ms[:]), np.array(n[:], dtype=np.int64)
+
+
+class _DevArray:
+    """Zero-copy view of library-owned device memory for torch."""
+
+    def __init__(self, ptr: int, n: int, typestr: str):
+        self.__cuda_array_interface__ = {"shape": (n,), "typestr": typestr, "data": (ptr, True), "version": 2}
+
+
+def device_view(ptr: int, n: int, dtype):
+    """torch tensor aliasing n elements at a device pointer owned by the library."""
+    import torch
+    ts = {np.uint32: "<u4", np.int32: "<i4", np.float32: "<f4"}[dtype]
+    if n == 0 or not ptr:
+        return torch.zeros(0, dtype={np.uint32: torch.int32, np.int32: torch.int32, np.float32: torch.float32}[dtype],
+                           device="cuda")
+    return torch.as_tensor(_DevArray(ptr, n, ts), device="cuda")
+
+
+def read_clusters(cl: Clusters):
+    """Copy a device cluster view to host numpy arrays (synchronises)."""
+    import torch
+    torch.cuda.synchronize()
+
+    def dev(ptr, n, dtype):
+        return device_view(ptr, n, dtype).cpu().numpy().view(dtype).copy()
+
+    meta = dev(cl.d_meta, 2, np.uint32)
+    K, N = int(meta[0]), int(meta[1])
+    return dict(K=K, N=N, off=dev(cl.d_off, K + 1, np.uint32), tag=dev(cl.d_tag, K, np.uint32),
+                x=dev(cl.d_x, N, np.float32), y=dev(cl.d_y, N, np.float32), z=dev(cl.d_z, N, np.float32),
+                key=dev(cl.d_key, N, np.uint32) if cl.d_key else None)
+
+
+lib()

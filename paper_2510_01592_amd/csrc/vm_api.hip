@@ -1,0 +1,451 @@
+// vm_api.hip -- the C ABI (include/vm.h): argument checks, map ownership,
+// per-stage timing, and the order in which the stages are enqueued.
+#include <algorithm>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "vm_common.h"
+
+using namespace vm;
+
+struct vm_map_s {
+    int device = 0;
+    Geom g{};
+    Hash h{};
+    uint32_t cap = 0;
+    uint32_t* bits = nullptr;
+    DevCounters* ctr = nullptr;
+    SegBuffers b{};
+    std::vector<void*> allocs;
+    // workspace for the map's own RANSAC/hull pass (grown on demand)
+    void* work = nullptr;
+    size_t work_bytes = 0;
+    uint32_t work_k = 0, work_hyp = 0;
+    bool have_clusters = false;
+    uint32_t last_min_cluster = 1;
+};
+
+namespace vm {
+
+// ---- stage timing ---------------------------------------------------------------
+namespace {
+struct TimingState {
+    std::mutex mu;
+    bool enabled = false;
+    std::vector<hipEvent_t> pool;
+    struct Rec {
+        int stage;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> recs;
+};
+TimingState& timing()
+{
+    static TimingState* t = new TimingState();
+    return *t;
+}
+hipEvent_t take_event(TimingState& t)
+{
+    if (!t.pool.empty()) {
+        hipEvent_t e = t.pool.back();
+        t.pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+}  // namespace
+
+StageScope::StageScope(int stage, hipStream_t s) : stage_(stage), s_(s), ev0_(nullptr)
+{
+    TimingState& t = timing();
+    std::lock_guard<std::mutex> lk(t.mu);
+    if (!t.enabled) return;
+    hipEvent_t e = take_event(t);
+    if (e && hipEventRecord(e, s) == hipSuccess) ev0_ = e;
+}
+
+StageScope::~StageScope()
+{
+    if (!ev0_) return;
+    TimingState& t = timing();
+    std::lock_guard<std::mutex> lk(t.mu);
+    hipEvent_t e = take_event(t);
+    if (e && hipEventRecord(e, s_) == hipSuccess) t.recs.push_back({stage_, (hipEvent_t)ev0_, e});
+}
+
+}  // namespace vm
+
+namespace {
+
+bool bad_ptr(const void* p) { return p == nullptr; }
+
+vm_status map_alloc(vm_map m, void** p, size_t bytes)
+{
+    if (hipMalloc(p, bytes ? bytes : 4) != hipSuccess) {
+        (void)hipGetLastError();
+        return VM_E_OOM;
+    }
+    m->allocs.push_back(*p);
+    return VM_OK;
+}
+
+void map_free_all(vm_map m)
+{
+    for (void* p : m->allocs) (void)hipFree(p);
+    m->allocs.clear();
+    if (m->work) (void)hipFree(m->work);
+    m->work = nullptr;
+}
+
+Pose pose_of(const vm_pose* p)
+{
+    Pose q{};
+    if (!p) {
+        q.R[0] = q.R[4] = q.R[8] = 1.0;
+        return q;
+    }
+    for (int i = 0; i < 9; ++i) q.R[i] = p->R[i];
+    for (int i = 0; i < 3; ++i) q.t[i] = p->t[i];
+    return q;
+}
+
+bool finite_pose(const vm_pose* p)
+{
+    if (!p) return true;
+    for (int i = 0; i < 9; ++i)
+        if (!(p->R[i] == p->R[i]) || p->R[i] > 1e300 || p->R[i] < -1e300) return false;
+    for (int i = 0; i < 3; ++i)
+        if (!(p->t[i] == p->t[i]) || p->t[i] > 1e300 || p->t[i] < -1e300) return false;
+    return true;
+}
+
+uint32_t map_k_bound(vm_map m, uint32_t min_cluster)
+{
+    if (min_cluster < 1) min_cluster = 1;
+    return m->cap / min_cluster + 1;
+}
+
+void fill_cluster_view(vm_map m, uint32_t min_cluster, vm_clusters* out)
+{
+    out->k_cap = map_k_bound(m, min_cluster);
+    out->n_cap = m->cap;
+    out->d_meta = m->ctr->meta;
+    out->d_off = m->b.cl_off;
+    out->d_x = m->b.cl_x;
+    out->d_y = m->b.cl_y;
+    out->d_z = m->b.cl_z;
+    out->d_key = m->b.cl_key;
+    out->d_tag = m->b.cl_tag;
+}
+
+vm_status check_planes(const vm_planes* p, uint32_t n_hyp)
+{
+    if (!p || bad_ptr(p->d_plane) || bad_ptr(p->d_best_h) || bad_ptr(p->d_n_inliers) || bad_ptr(p->d_in_off) ||
+        bad_ptr(p->d_status) || (p->in_cap > 0 && bad_ptr(p->d_in_idx)))
+        return VM_E_ARG;
+    (void)n_hyp;
+    return VM_OK;
+}
+
+vm_status check_hulls(const vm_hulls_out* o)
+{
+    if (!o || bad_ptr(o->d_v_off) || bad_ptr(o->d_area) || bad_ptr(o->d_status) ||
+        (o->v_cap > 0 && (bad_ptr(o->d_v_idx) || bad_ptr(o->d_v_xyz))))
+        return VM_E_ARG;
+    return VM_OK;
+}
+
+vm_status check_params(const vm_ransac_params* p)
+{
+    if (!p || p->n_hyp < 1 || p->n_hyp > 65536 || !(p->eps > 0.0f) || p->reserved != 0) return VM_E_ARG;
+    return VM_OK;
+}
+
+vm_status check_clusters(const vm_clusters* c)
+{
+    if (!c || bad_ptr(c->d_meta) || bad_ptr(c->d_off) || bad_ptr(c->d_x) || bad_ptr(c->d_y) || bad_ptr(c->d_z) ||
+        bad_ptr(c->d_tag))
+        return VM_E_ARG;
+    return VM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* vm_status_string(vm_status s)
+{
+    switch (s) {
+        case VM_OK: return "ok";
+        case VM_E_ARG: return "invalid argument";
+        case VM_E_OOM: return "device allocation failed";
+        case VM_E_CAPACITY: return "capacity exceeded";
+        case VM_E_DEVICE: return "HIP runtime error";
+        case VM_E_STATE: return "call out of order";
+        default: return "unknown status";
+    }
+}
+
+int32_t vm_version(void) { return 100; }
+
+vm_status vm_map_create(const vm_map_desc* d, vm_map* out)
+{
+    if (!d || !out) return VM_E_ARG;
+    *out = nullptr;
+    if (!(d->voxel_size > 0.0) || d->voxel_size > 1e6) return VM_E_ARG;
+    for (int a = 0; a < 3; ++a) {
+        if (d->dims[a] < 1) return VM_E_ARG;
+        if (!(d->origin[a] == d->origin[a]) || d->origin[a] > 1e12 || d->origin[a] < -1e12) return VM_E_ARG;
+    }
+    const uint64_t ncell = (uint64_t)d->dims[0] * (uint64_t)d->dims[1] * (uint64_t)d->dims[2];
+    if (ncell >= (1ull << 32) || ncell == 0) return VM_E_ARG;
+    if (d->hash_capacity_log2 < 10 || d->hash_capacity_log2 > 30) return VM_E_ARG;
+
+    vm_map m = new (std::nothrow) vm_map_s();
+    if (!m) return VM_E_OOM;
+    if (hipGetDevice(&m->device) != hipSuccess) {
+        delete m;
+        return VM_E_DEVICE;
+    }
+    m->cap = 1u << d->hash_capacity_log2;
+    for (int a = 0; a < 3; ++a) {
+        m->g.origin[a] = d->origin[a];
+        m->g.dims[a] = d->dims[a];
+    }
+    m->g.voxel_size = d->voxel_size;
+    m->g.inv_q = 1048576.0 / d->voxel_size;
+    m->g.nwords = (uint32_t)((ncell + 31) / 32);
+
+    const size_t cap = m->cap;
+    vm_status st = VM_OK;
+    auto A = [&](void** p, size_t bytes) {
+        if (st == VM_OK) st = map_alloc(m, p, bytes);
+    };
+    A((void**)&m->h.key, cap * 4);
+    A((void**)&m->h.cnt, cap * 4);
+    A((void**)&m->h.sum, cap * 3 * 8);
+    m->h.log2cap = d->hash_capacity_log2;
+    m->h.mask = m->cap - 1;
+    A((void**)&m->bits, (size_t)m->g.nwords * 4);
+    A((void**)&m->ctr, sizeof(DevCounters));
+    SegBuffers& b = m->b;
+    A((void**)&b.occ_key, cap * 4);
+    A((void**)&b.parent, cap * 4);
+    A((void**)&b.csize, cap * 4);
+    A((void**)&b.scan_a, cap * 4);
+    A((void**)&b.scan_b, cap * 4);
+    for (int i = 0; i < 2; ++i) {
+        A((void**)&b.sort_k[i], cap * 4);
+        A((void**)&b.sort_v[i], cap * 4);
+    }
+    A((void**)&b.cl_off, (cap + 2) * 4);
+    A((void**)&b.cl_tag, cap * 4);
+    A((void**)&b.cl_key, cap * 4);
+    A((void**)&b.cl_x, cap * 4);
+    A((void**)&b.cl_y, cap * 4);
+    A((void**)&b.cl_z, cap * 4);
+    A((void**)&b.wrank, ((size_t)m->g.nwords + 1) * 4);
+    const uint64_t scan_n = std::max<uint64_t>(std::max<uint64_t>(cap, m->g.nwords), radix_hist_words(cap));
+    A((void**)&b.blk, scan_blk_words(scan_n) * 4);
+    A((void**)&b.hist, radix_hist_words(cap) * 4);
+    if (st != VM_OK) {
+        map_free_all(m);
+        delete m;
+        return st;
+    }
+    if (launch_clear(m->g, m->h, m->bits, m->ctr, nullptr) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+        map_free_all(m);
+        delete m;
+        return VM_E_DEVICE;
+    }
+    *out = m;
+    return VM_OK;
+}
+
+vm_status vm_map_destroy(vm_map m)
+{
+    if (!m) return VM_E_ARG;
+    (void)hipDeviceSynchronize();
+    map_free_all(m);
+    delete m;
+    return VM_OK;
+}
+
+vm_status vm_map_clear(vm_map m, void* stream)
+{
+    if (!m) return VM_E_ARG;
+    VM_HIP(launch_clear(m->g, m->h, m->bits, m->ctr, (hipStream_t)stream));
+    m->have_clusters = false;
+    return VM_OK;
+}
+
+vm_status vm_map_stats(vm_map m, void* stream, vm_map_stats_t* out)
+{
+    if (!m || !out) return VM_E_ARG;
+    VM_HIP(hipStreamSynchronize((hipStream_t)stream));
+    DevCounters c;
+    VM_HIP(hipMemcpy(&c, m->ctr, sizeof c, hipMemcpyDeviceToHost));
+    out->occupied = c.occupied;
+    out->points_in = c.points_in;
+    out->points_dropped = c.points_dropped;
+    out->points_lost = c.points_lost;
+    out->status_flags = c.flags;
+    out->hash_capacity_log2 = m->h.log2cap;
+    return VM_OK;
+}
+
+vm_status vm_insert(vm_map m, const float* d_xyz, int64_t n, const vm_pose* pose, void* stream)
+{
+    if (!m || n < 0 || (n > 0 && !d_xyz) || !finite_pose(pose)) return VM_E_ARG;
+    if (n == 0) return VM_OK;
+    StageScope t(VM_STAGE_INSERT, (hipStream_t)stream);
+    VM_HIP(launch_insert(d_xyz, n, pose_of(pose), m->g, m->h, m->bits, m->ctr, (hipStream_t)stream));
+    return VM_OK;
+}
+
+vm_status vm_map_export(vm_map m, uint32_t* d_key, uint32_t* d_count, uint64_t* d_sum, float* d_mean, uint64_t cap,
+                        uint64_t* n_out, void* stream)
+{
+    if (!m || !n_out) return VM_E_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    VM_HIP(launch_rank(m->g, m->bits, m->b, m->cap, m->ctr, s));
+    VM_HIP(launch_export(m->g, m->h, m->b, m->ctr, d_key, d_count, (unsigned long long*)d_sum, d_mean, cap, s));
+    VM_HIP(hipStreamSynchronize(s));
+    DevCounters c;
+    VM_HIP(hipMemcpy(&c, m->ctr, sizeof c, hipMemcpyDeviceToHost));
+    *n_out = c.n_occ;
+    return c.n_occ > cap ? VM_E_CAPACITY : VM_OK;
+}
+
+vm_status vm_map_import(vm_map m, const uint32_t* d_key, const uint32_t* d_count, const uint64_t* d_sum, uint64_t n,
+                        void* stream)
+{
+    if (!m || (n > 0 && (!d_key || !d_count || !d_sum))) return VM_E_ARG;
+    if (n > m->cap / 2 + m->cap / 4) return VM_E_CAPACITY;
+    VM_HIP(launch_import(m->g, m->h, m->bits, m->ctr, d_key, d_count, (const unsigned long long*)d_sum, n,
+                         (hipStream_t)stream));
+    m->have_clusters = false;
+    return VM_OK;
+}
+
+vm_status vm_ccl(vm_map m, uint32_t min_cluster, uint32_t* d_labels, vm_clusters* out, void* stream)
+{
+    if (!m) return VM_E_ARG;
+    if (min_cluster < 1) min_cluster = 1;
+    hipStream_t s = (hipStream_t)stream;
+    {
+        StageScope t(VM_STAGE_RANK, s);
+        VM_HIP(launch_rank(m->g, m->bits, m->b, m->cap, m->ctr, s));
+    }
+    VM_HIP(launch_ccl(m->g, m->bits, m->b, m->cap, m->ctr, s));
+    VM_HIP(launch_group(m->g, m->h, m->b, m->cap, min_cluster, d_labels, m->ctr, s));
+    m->have_clusters = true;
+    m->last_min_cluster = min_cluster;
+    if (out) fill_cluster_view(m, min_cluster, out);
+    return VM_OK;
+}
+
+size_t vm_workspace_bytes(uint32_t k_cap, uint32_t n_cap, uint32_t n_hyp)
+{
+    return work_layout(nullptr, k_cap, n_cap, n_hyp).bytes;
+}
+
+vm_status vm_ransac_planes(const vm_clusters* cl, const vm_ransac_params* params, vm_planes* out, void* d_work,
+                           size_t work_bytes, void* stream)
+{
+    if (check_clusters(cl) != VM_OK || check_params(params) != VM_OK || check_planes(out, params ? params->n_hyp : 0) != VM_OK ||
+        !d_work)
+        return VM_E_ARG;
+    const WorkLayout w = work_layout(d_work, cl->k_cap, cl->n_cap, params->n_hyp);
+    if (work_bytes < w.bytes) return VM_E_CAPACITY;
+    return ransac_planes(*cl, *params, *out, w, (hipStream_t)stream);
+}
+
+vm_status vm_hulls(const vm_clusters* cl, const vm_planes* planes, vm_hulls_out* out, void* d_work, size_t work_bytes,
+                   void* stream)
+{
+    if (check_clusters(cl) != VM_OK || check_planes(planes, 1) != VM_OK || check_hulls(out) != VM_OK || !d_work)
+        return VM_E_ARG;
+    // the hull pass uses only the hypothesis-independent part of the layout
+    const WorkLayout w = work_layout(d_work, cl->k_cap, cl->n_cap, 1);
+    const WorkLayout wz = work_layout(nullptr, cl->k_cap, cl->n_cap, 1);
+    if (work_bytes < wz.bytes) return VM_E_CAPACITY;
+    return hulls(*cl, *planes, *out, w, (hipStream_t)stream);
+}
+
+vm_status vm_segment_frame(vm_map m, const float* d_xyz, int64_t n, const vm_pose* pose, const vm_seg_params* params,
+                           vm_planes* planes, vm_hulls_out* hulls_out, uint32_t* d_labels, vm_clusters* clusters_out,
+                           void* stream)
+{
+    if (!m || !params || params->reserved != 0 || check_params(&params->ransac) != VM_OK) return VM_E_ARG;
+    if (check_planes(planes, params->ransac.n_hyp) != VM_OK || check_hulls(hulls_out) != VM_OK) return VM_E_ARG;
+    if (n < 0 || (n > 0 && !d_xyz) || !finite_pose(pose)) return VM_E_ARG;
+    const uint32_t minc = params->min_cluster < 1 ? 1 : params->min_cluster;
+    const uint32_t kb = map_k_bound(m, minc);
+    // the map's own workspace: allocated once per (cluster bound, hypotheses)
+    if (!m->work || m->work_k < kb || m->work_hyp < params->ransac.n_hyp) {
+        const uint32_t k = std::max(kb, m->work_k);
+        const uint32_t hh = std::max(params->ransac.n_hyp, m->work_hyp);
+        const size_t bytes = vm_workspace_bytes(k, m->cap, hh);
+        VM_HIP(hipStreamSynchronize((hipStream_t)stream));
+        if (m->work) (void)hipFree(m->work);
+        m->work = nullptr;
+        if (hipMalloc(&m->work, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            m->work_bytes = 0;
+            return VM_E_OOM;
+        }
+        m->work_bytes = bytes;
+        m->work_k = k;
+        m->work_hyp = hh;
+    }
+    vm_status st = vm_insert(m, d_xyz, n, pose, stream);
+    if (st != VM_OK) return st;
+    vm_clusters cl;
+    st = vm_ccl(m, minc, d_labels, &cl, stream);
+    if (st != VM_OK) return st;
+    if (clusters_out) *clusters_out = cl;
+    const WorkLayout w = work_layout(m->work, cl.k_cap, cl.n_cap, params->ransac.n_hyp);
+    if (w.bytes > m->work_bytes) return VM_E_STATE;
+    st = ransac_planes(cl, params->ransac, *planes, w, (hipStream_t)stream);
+    if (st != VM_OK) return st;
+    const WorkLayout wh = work_layout(m->work, cl.k_cap, cl.n_cap, params->ransac.n_hyp);
+    return hulls(cl, *planes, *hulls_out, wh, (hipStream_t)stream);
+}
+
+vm_status vm_set_stage_timing(int32_t enable)
+{
+    TimingState& t = timing();
+    std::lock_guard<std::mutex> lk(t.mu);
+    t.enabled = enable != 0;
+    return VM_OK;
+}
+
+vm_status vm_stage_times(double* ms_out, uint64_t* launches_out, int32_t n)
+{
+    if (n < 0 || (n > 0 && (!ms_out || !launches_out))) return VM_E_ARG;
+    TimingState& t = timing();
+    std::lock_guard<std::mutex> lk(t.mu);
+    for (int i = 0; i < n; ++i) {
+        ms_out[i] = 0.0;
+        launches_out[i] = 0;
+    }
+    vm_status st = VM_OK;
+    for (auto& r : t.recs) {
+        float ms = 0.0f;
+        if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) st = VM_E_DEVICE;
+        if (r.stage >= 0 && r.stage < n) {
+            ms_out[r.stage] += ms;
+            launches_out[r.stage] += 1;
+        }
+        t.pool.push_back(r.a);
+        t.pool.push_back(r.b);
+    }
+    t.recs.clear();
+    return st;
+}
+
+}  // extern "C"

@@ -1,0 +1,337 @@
+// vm_ccl.hip -- connected-component labelling of the occupied voxels and the
+// grouping of voxels into clusters (Sec. III-C, "Clustering", Alg. 1).
+//
+// Alg. 1 propagates the smaller label over every adjacency until nothing
+// changes; from L_i = i its fixed point is the smallest index of each
+// connected component.  That fixed point is reached here with a lock-free
+// union-find over the occupied ranks (rank order == key order, so the
+// smallest rank of a component is its smallest key):
+//   * init:    every voxel points at the start of its run along x (runs of
+//              consecutive occupied cells share a component trivially);
+//   * merge:   runs in the four neighbouring rows with smaller keys
+//              (dz = -1, any dy; dz = 0, dy = -1) are hooked together; a
+//              voxel only hooks where an overlap between its run and a run of
+//              the other row begins, plus the diagonal end cells, so each
+//              pair of touching runs is hooked about once;
+//   * flatten: every voxel takes its root.
+// Hooks always put the larger root under the smaller one with a CAS on the
+// root, so every root ends as the minimum of its tree and the labels are
+// exact whatever the interleaving.  Path halving keeps trees shallow.  The
+// 26-neighbourhood never needs the hash: occupancy and ranks come from the
+// 1-bit-per-cell index.
+#include "vm_common.h"
+
+namespace vm {
+namespace {
+
+__device__ __forceinline__ uint32_t ld_agent(const uint32_t* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void st_agent(uint32_t* p, uint32_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ bool occ(const uint32_t* __restrict__ bits, uint32_t key)
+{
+    return (bits[key >> 5] >> (key & 31)) & 1u;
+}
+
+__device__ __forceinline__ uint32_t rank_of(const uint32_t* __restrict__ bits, const uint32_t* __restrict__ wrank,
+                                            uint32_t key)
+{
+    const uint32_t b = key & 31;
+    return wrank[key >> 5] + __popc(bits[key >> 5] & ((1u << b) - 1u));
+}
+
+// Root of x with path halving (each visited node is re-pointed at its
+// grandparent; concurrent writes only ever store an ancestor).
+__device__ __forceinline__ uint32_t uf_find(uint32_t* parent, uint32_t x)
+{
+    uint32_t p = ld_agent(&parent[x]);
+    while (p != x) {
+        const uint32_t g = ld_agent(&parent[p]);
+        if (g == p) return p;
+        st_agent(&parent[x], g);
+        x = g;
+        p = ld_agent(&parent[x]);
+    }
+    return x;
+}
+
+__device__ __forceinline__ void uf_unite(uint32_t* parent, uint32_t a, uint32_t b)
+{
+    a = uf_find(parent, a);
+    b = uf_find(parent, b);
+    while (a != b) {
+        if (a < b) { const uint32_t t = a; a = b; b = t; }
+        const uint32_t old = atomicCAS(&parent[a], a, b);   // hook root a under b
+        if (old == a) return;
+        a = uf_find(parent, old);
+        b = uf_find(parent, b);
+    }
+}
+
+struct Dims {
+    uint32_t nx, ny, nz, nxy;
+};
+
+__global__ void __launch_bounds__(kBlock) k_ccl_init(const uint32_t* __restrict__ bits,
+                                                     const uint32_t* __restrict__ occ_key,
+                                                     const DevCounters* __restrict__ ctr, Dims d,
+                                                     uint32_t* __restrict__ parent)
+{
+    const uint32_t V = ctr->n_occ;
+    for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < V; r += gridDim.x * blockDim.x) {
+        const uint32_t key = occ_key[r];
+        const uint32_t x = key % d.nx;
+        const uint32_t rowstart = key - x;
+        // smallest key of the run of occupied cells ending at `key`
+        const uint32_t w = key >> 5, b = key & 31;
+        uint32_t start;
+        const uint32_t zeros = (~bits[w]) & ((1u << b) - 1u);
+        if (zeros) {
+            start = (w << 5) + 32u - __clz(zeros);
+        } else {
+            start = w << 5;
+            uint32_t ww = w;
+            while (start > rowstart && ww > 0) {
+                --ww;
+                const uint32_t z = ~bits[ww];
+                if (z) { start = (ww << 5) + 32u - __clz(z); break; }
+                start = ww << 5;
+            }
+        }
+        if (start < rowstart) start = rowstart;
+        parent[r] = r - (key - start);
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_ccl_merge(const uint32_t* __restrict__ bits,
+                                                      const uint32_t* __restrict__ wrank,
+                                                      const uint32_t* __restrict__ occ_key,
+                                                      const DevCounters* __restrict__ ctr, Dims d,
+                                                      uint32_t* parent)
+{
+    const uint32_t V = ctr->n_occ;
+    for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < V; r += gridDim.x * blockDim.x) {
+        const uint32_t key = occ_key[r];
+        const uint32_t x = key % d.nx;
+        const uint32_t y = (key / d.nx) % d.ny;
+        const uint32_t z = key / d.nxy;
+        const bool run_start = (x == 0) || !occ(bits, key - 1);
+        const bool run_end = (x + 1 == d.nx) || !occ(bits, key + 1);
+        // the four rows with smaller keys: (dy, dz) = (-1,0), (-1,-1), (0,-1), (+1,-1)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int dy = (j == 0) ? -1 : (j - 2);
+            const int dz = (j == 0) ? 0 : -1;
+            if ((dz < 0 && z == 0) || (dy < 0 && y == 0) || (dy > 0 && y + 1 == d.ny)) continue;
+            const uint32_t nk = (uint32_t)((int64_t)key + (int64_t)dy * d.nx + (int64_t)dz * d.nxy);
+            if (occ(bits, nk) && (run_start || !occ(bits, nk - 1)))
+                uf_unite(parent, r, rank_of(bits, wrank, nk));
+            if (run_start && x > 0 && occ(bits, nk - 1))
+                uf_unite(parent, r, rank_of(bits, wrank, nk - 1));
+            if (run_end && x + 1 < d.nx && occ(bits, nk + 1))
+                uf_unite(parent, r, rank_of(bits, wrank, nk + 1));
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_ccl_flatten(const DevCounters* __restrict__ ctr, uint32_t* parent)
+{
+    const uint32_t V = ctr->n_occ;
+    for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < V; r += gridDim.x * blockDim.x)
+        parent[r] = uf_find(parent, r);
+}
+
+// Component sizes at the roots.  Consecutive ranks mostly share a root, so a
+// wave adds one count per run of equal roots.
+__global__ void __launch_bounds__(kBlock) k_ccl_sizes(const DevCounters* __restrict__ ctr,
+                                                      const uint32_t* __restrict__ parent, uint32_t* csize)
+{
+    const uint32_t V = ctr->n_occ;
+    const int lane = threadIdx.x & (kWave - 1);
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t r0 = blockIdx.x * blockDim.x; r0 < V; r0 += stride) {
+        const uint32_t r = r0 + threadIdx.x;
+        const bool valid = r < V;
+        const uint32_t root = valid ? parent[r] : 0xFFFFFFFFu;
+        const uint32_t prev = __shfl_up(root, 1, kWave);
+        const bool head = valid && (lane == 0 || prev != root);
+        const uint64_t heads = __ballot(head);
+        const uint64_t vmask = __ballot(valid);
+        if (head) {
+            const uint64_t after = (lane == 63) ? 0ull : (heads & (~0ull << (lane + 1)));
+            const uint32_t end = after ? (uint32_t)(__ffsll((long long)after) - 1) : (uint32_t)(64 - __clzll((long long)vmask));
+            atomicAdd(&csize[root], end - (uint32_t)lane);
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_zero(uint32_t* p, const DevCounters* __restrict__ ctr)
+{
+    const uint32_t V = ctr->n_occ;
+    for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < V; r += gridDim.x * blockDim.x) p[r] = 0;
+}
+
+// ---- grouping -------------------------------------------------------------------
+// flags for the two scans: kept root -> 1 (cluster id), and its size (offset)
+__global__ void __launch_bounds__(kBlock) k_group_flags(const DevCounters* __restrict__ ctr,
+                                                        const uint32_t* __restrict__ parent,
+                                                        const uint32_t* __restrict__ csize, uint32_t min_cluster,
+                                                        uint32_t* __restrict__ is_root, uint32_t* __restrict__ root_size,
+                                                        uint32_t* __restrict__ keep)
+{
+    const uint32_t V = ctr->n_occ;
+    for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < V; r += gridDim.x * blockDim.x) {
+        const uint32_t root = parent[r];
+        const uint32_t sz = csize[root];
+        const bool kept = sz >= min_cluster;
+        const bool rt = kept && root == r;
+        is_root[r] = rt ? 1u : 0u;
+        root_size[r] = rt ? sz : 0u;
+        keep[r] = kept ? 1u : 0u;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_group_clusters(DevCounters* __restrict__ ctr,
+                                                           const uint32_t* __restrict__ parent,
+                                                           const uint32_t* __restrict__ csize, uint32_t min_cluster,
+                                                           const uint32_t* __restrict__ occ_key,
+                                                           const uint32_t* __restrict__ cid_scan,
+                                                           const uint32_t* __restrict__ off_scan,
+                                                           uint32_t* __restrict__ cl_off, uint32_t* __restrict__ cl_tag)
+{
+    const uint32_t V = ctr->n_occ;
+    for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < V; r += gridDim.x * blockDim.x) {
+        if (parent[r] == r && csize[r] >= min_cluster) {
+            const uint32_t c = cid_scan[r];
+            cl_off[c] = off_scan[r];
+            cl_tag[c] = occ_key[r];
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const uint32_t K = ctr->meta[0];
+        cl_off[K] = ctr->meta[1];
+        ctr->kmax = K ? K - 1 : 0;
+    }
+}
+
+// (cluster id, rank) pairs of the kept voxels, in rank order
+__global__ void __launch_bounds__(kBlock) k_group_pairs(const DevCounters* __restrict__ ctr,
+                                                        const uint32_t* __restrict__ parent,
+                                                        const uint32_t* __restrict__ csize, uint32_t min_cluster,
+                                                        const uint32_t* __restrict__ cid_scan,
+                                                        const uint32_t* __restrict__ pos_scan,
+                                                        uint32_t* __restrict__ out_cid, uint32_t* __restrict__ out_rank)
+{
+    const uint32_t V = ctr->n_occ;
+    for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < V; r += gridDim.x * blockDim.x) {
+        const uint32_t root = parent[r];
+        if (csize[root] >= min_cluster) {
+            const uint32_t p = pos_scan[r];
+            out_cid[p] = cid_scan[root];
+            out_rank[p] = r;
+        }
+    }
+}
+
+// CSR points: key and Eq. (1) mean of each kept voxel, cluster-major
+__global__ void __launch_bounds__(kBlock) k_group_gather(Geom g, Hash h, const DevCounters* __restrict__ ctr,
+                                                         const uint32_t* __restrict__ sorted_rank,
+                                                         const uint32_t* __restrict__ occ_key,
+                                                         uint32_t* __restrict__ cl_key, float* __restrict__ cl_x,
+                                                         float* __restrict__ cl_y, float* __restrict__ cl_z)
+{
+    const uint32_t n = ctr->meta[1];
+    const uint32_t hc = h.mask + 1;
+    const uint32_t nx = (uint32_t)g.dims[0], ny = (uint32_t)g.dims[1];
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const uint32_t k = occ_key[sorted_rank[i]];
+        const uint32_t s = hash_find(h, k);
+        float mx = 0.0f, my = 0.0f, mz = 0.0f;
+        if (s != kEmpty) {
+            const uint32_t c = h.cnt[s];
+            mx = voxel_mean_axis(k % nx, h.sum[s], c, g.voxel_size, g.origin[0]);
+            my = voxel_mean_axis((k / nx) % ny, h.sum[hc + s], c, g.voxel_size, g.origin[1]);
+            mz = voxel_mean_axis(k / (nx * ny), h.sum[2 * (size_t)hc + s], c, g.voxel_size, g.origin[2]);
+        }
+        cl_key[i] = k;
+        cl_x[i] = mx;
+        cl_y[i] = my;
+        cl_z[i] = mz;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_labels(const DevCounters* __restrict__ ctr,
+                                                   const uint32_t* __restrict__ parent,
+                                                   const uint32_t* __restrict__ occ_key, uint32_t* __restrict__ labels)
+{
+    const uint32_t V = ctr->n_occ;
+    for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < V; r += gridDim.x * blockDim.x)
+        labels[r] = occ_key[parent[r]];
+}
+
+Dims dims_of(const Geom& g)
+{
+    Dims d;
+    d.nx = (uint32_t)g.dims[0];
+    d.ny = (uint32_t)g.dims[1];
+    d.nz = (uint32_t)g.dims[2];
+    d.nxy = d.nx * d.ny;
+    return d;
+}
+
+}  // namespace
+
+hipError_t launch_ccl(const Geom& g, const uint32_t* bits, SegBuffers& b, uint32_t cap, DevCounters* ctr,
+                      hipStream_t s)
+{
+    const Dims d = dims_of(g);
+    const int grid = grid_for(cap);
+    {
+        StageScope t(VM_STAGE_CCL, s);
+        k_ccl_init<<<grid, kBlock, 0, s>>>(bits, b.occ_key, ctr, d, b.parent);
+        k_ccl_merge<<<grid, kBlock, 0, s>>>(bits, b.wrank, b.occ_key, ctr, d, b.parent);
+        k_ccl_flatten<<<grid, kBlock, 0, s>>>(ctr, b.parent);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_group(const Geom& g, const Hash& h, SegBuffers& b, uint32_t cap, uint32_t min_cluster,
+                        uint32_t* d_labels, DevCounters* ctr, hipStream_t s)
+{
+    StageScope t(VM_STAGE_GROUP, s);
+    const int grid = grid_for(cap);
+    if (min_cluster < 1) min_cluster = 1;
+    k_zero<<<grid, kBlock, 0, s>>>(b.csize, ctr);
+    k_ccl_sizes<<<grid, kBlock, 0, s>>>(ctr, b.parent, b.csize);
+    uint32_t* is_root = b.scan_a;
+    uint32_t* root_size = b.scan_b;
+    uint32_t* keep = b.sort_k[1];
+    k_group_flags<<<grid, kBlock, 0, s>>>(ctr, b.parent, b.csize, min_cluster, is_root, root_size, keep);
+    hipError_t e;
+    if ((e = scan_exclusive_dev(is_root, is_root, &ctr->n_occ, cap, &ctr->meta[0], b.blk, s)) != hipSuccess) return e;
+    if ((e = scan_exclusive_dev(root_size, root_size, &ctr->n_occ, cap, &ctr->meta[1], b.blk, s)) != hipSuccess)
+        return e;
+    if ((e = scan_exclusive_dev(keep, keep, &ctr->n_occ, cap, nullptr, b.blk, s)) != hipSuccess) return e;
+    k_group_clusters<<<grid, kBlock, 0, s>>>(ctr, b.parent, b.csize, min_cluster, b.occ_key, is_root, root_size,
+                                             b.cl_off, b.cl_tag);
+    k_group_pairs<<<grid, kBlock, 0, s>>>(ctr, b.parent, b.csize, min_cluster, is_root, keep, b.sort_k[0],
+                                          b.sort_v[0]);
+    // stable sort by cluster id keeps ascending keys inside each cluster
+    const uint32_t kbound = cap / min_cluster + 1;
+    const int bits_needed = 32 - __builtin_clz(kbound | 1u);
+    int res = 0;
+    if ((e = radix_sort_pairs_dev(b.sort_k, b.sort_v, &ctr->meta[1], cap, bits_needed, &ctr->kmax, b.hist, b.blk,
+                                  &res, s)) != hipSuccess)
+        return e;
+    k_group_gather<<<grid, kBlock, 0, s>>>(g, h, ctr, b.sort_v[res], b.occ_key, b.cl_key, b.cl_x, b.cl_y, b.cl_z);
+    if (d_labels) k_labels<<<grid, kBlock, 0, s>>>(ctr, b.parent, b.occ_key, d_labels);
+    return hipGetLastError();
+}
+
+}  // namespace vm

@@ -1,0 +1,206 @@
+// vm_common.h -- internal declarations shared by the library's HIP translation
+// units (gfx950 only).  Not part of the ABI; the ABI is include/vm.h.
+#pragma once
+#pragma clang fp contract(off)
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/vm.h"
+
+namespace vm {
+
+constexpr uint32_t kEmpty = 0xFFFFFFFFu;   // empty hash slot / "no key"
+constexpr int kBlock = 256;                 // default workgroup: 4 wave64
+constexpr int kWave = 64;
+constexpr uint32_t kMaxProbe = 8192;        // linear-probe limit of the voxel hash
+
+// Device-side counters of one map (one 128-byte line).
+struct DevCounters {
+    unsigned long long points_in;
+    unsigned long long points_dropped;
+    unsigned long long points_lost;
+    unsigned long long occupied;      // voxels in the hash
+    uint32_t flags;                   // VM_FLAG_*
+    uint32_t n_occ;                   // occupied voxels ranked by the last rank pass
+    uint32_t meta[2];                 // clusters view: [0] K, [1] total points
+    uint32_t kmax;                    // largest cluster id (K - 1, or 0)
+    uint32_t pad[15];
+};
+
+struct Geom {
+    double origin[3];
+    double voxel_size;
+    double inv_q;          // 2^20 / voxel_size
+    int32_t dims[3];
+    uint32_t nwords;       // occupancy words (32 cells each)
+};
+
+struct Pose {
+    double R[9];
+    double t[3];
+};
+
+// Open-addressing hash over voxel keys with linear probing.  Keys and the
+// payload are separate arrays: probes touch only the dense key array.
+struct Hash {
+    uint32_t* key;            // [cap]
+    uint32_t* cnt;            // [cap]
+    unsigned long long* sum;  // [3][cap] (x sums, then y, then z)
+    uint32_t log2cap;
+    uint32_t mask;
+};
+
+__device__ __forceinline__ uint32_t hash_slot(uint32_t key, uint32_t log2cap)
+{
+    // Fibonacci hashing: spreads neighbouring voxel keys over the table.
+    return (uint32_t)((key * 2654435769u) >> (32 - log2cap));
+}
+
+// Slot holding `key`, or kEmpty if absent.
+__device__ __forceinline__ uint32_t hash_find(const Hash& h, uint32_t key)
+{
+    uint32_t s = hash_slot(key, h.log2cap);
+    for (uint32_t p = 0; p < kMaxProbe && p <= h.mask; ++p) {
+        const uint32_t k = h.key[s];
+        if (k == key) return s;
+        if (k == kEmpty) return kEmpty;
+        s = (s + 1) & h.mask;
+    }
+    return kEmpty;
+}
+
+// Eq. (1) closed form for one axis: the voxel's mean position from its
+// integer offset sum (units of s*2^-20) and point count.
+__device__ __forceinline__ float voxel_mean_axis(uint32_t idx, unsigned long long sum, uint32_t cnt, double s,
+                                                 double o)
+{
+    const unsigned long long mq = sum / (unsigned long long)cnt;
+    const double cell = (double)idx + (double)mq * 0x1p-20;
+    return (float)fma(cell, s, o);
+}
+
+// Per-map workspace for the segmentation buffers (indexed by occupied rank
+// or by cluster-CSR position; all sized by the hash capacity).
+struct SegBuffers {
+    uint32_t* occ_key;     // [cap] occupied keys, ascending
+    uint32_t* parent;      // [cap] union-find parent (rank indices)
+    uint32_t* csize;       // [cap] component size at its root
+    uint32_t* scan_a;      // [cap] scan scratch
+    uint32_t* scan_b;      // [cap]
+    uint32_t* sort_k[2];   // [cap] radix keys (cluster id), ping-pong
+    uint32_t* sort_v[2];   // [cap] radix values (rank), ping-pong
+    uint32_t* cl_off;      // [cap+1]
+    uint32_t* cl_tag;      // [cap]
+    uint32_t* cl_key;      // [cap]
+    float* cl_x;           // [cap]
+    float* cl_y;
+    float* cl_z;
+    uint32_t* wrank;       // [nwords+1] exclusive popcount prefix of the occupancy words
+    uint32_t* blk;         // block partials for scans (sized generously)
+    uint32_t* hist;        // radix histograms
+};
+
+// Number of clusters a pass may process: min(meta[0], k_cap) if the offsets
+// are a valid CSR (off[0] = 0, non-decreasing, off[K] = meta[1] <= n_cap),
+// else 0 with VM_FLAG_BAD_CLUSTERS raised.  Run by one workgroup.
+__device__ __forceinline__ uint32_t validate_clusters(const uint32_t* meta, const uint32_t* off, uint32_t k_cap,
+                                                      uint32_t n_cap, uint32_t* status, int* bad_lds)
+{
+    const uint32_t K = min(meta[0], k_cap);
+    if (threadIdx.x == 0) *bad_lds = (off[0] != 0u) || (off[K] > n_cap) || (meta[0] <= k_cap && off[K] != meta[1]);
+    __syncthreads();
+    for (uint32_t k = threadIdx.x; k < K; k += blockDim.x)
+        if (off[k] > off[k + 1]) *bad_lds = 1;
+    __syncthreads();
+    const bool bad = *bad_lds != 0;
+    if (bad && threadIdx.x == 0) atomicOr(status, (uint32_t)VM_FLAG_BAD_CLUSTERS);
+    return bad ? 0u : K;
+}
+
+// ---- host-side error plumbing ------------------------------------------
+#define VM_HIP(call)                                                    \
+    do {                                                                \
+        hipError_t e_ = (call);                                         \
+        if (e_ != hipSuccess) return VM_E_DEVICE;                       \
+    } while (0)
+
+// ---- stage timing (vm_timing.cpp) --------------------------------------
+struct StageScope {
+    StageScope(int stage, hipStream_t s);
+    ~StageScope();
+    int stage_;
+    hipStream_t s_;
+    void* ev0_;
+};
+
+// ---- launch helpers ----------------------------------------------------
+inline int grid_for(uint64_t n, int block = kBlock, int max_grid = 8192)
+{
+    uint64_t g = (n + block - 1) / block;
+    if (g < 1) g = 1;
+    if (g > (uint64_t)max_grid) g = max_grid;
+    return (int)g;
+}
+
+// ---- scans and sorts (vm_scan.hip) ----------------------------------------
+// Exclusive prefix sum of n u32 values (n read from *d_n on the device, at
+// most n_cap; or n = n_cap when d_n is null), in place allowed (in == out).  Writes the total to *d_total if
+// non-null.  `blk` needs scan_blk_words(n_cap) words.
+size_t scan_blk_words(uint64_t n_cap);
+hipError_t scan_exclusive_dev(const uint32_t* in, uint32_t* out, const uint32_t* d_n, uint32_t n_cap,
+                              uint32_t* d_total, uint32_t* blk, hipStream_t s);
+
+// Stable LSD radix sort of (key, value) pairs by the low `bits` bits of key;
+// n from *d_n (<= n_cap).  Passes whose digit is zero for every key (key <=
+// *d_max_key) reduce to copies.  The result lands in keys[r]/vals[r] with
+// r = *result_buf (host-known).  `hist` needs radix_hist_words(n_cap) words,
+// `blk` as for the scan.
+size_t radix_hist_words(uint64_t n_cap);
+hipError_t radix_sort_pairs_dev(uint32_t* keys[2], uint32_t* vals[2], const uint32_t* d_n, uint32_t n_cap,
+                                int bits, const uint32_t* d_max_key, uint32_t* hist, uint32_t* blk,
+                                int* result_buf, hipStream_t s);
+
+// ---- map stages (vm_map.hip) ------------------------------------------------
+hipError_t launch_insert(const float* xyz, int64_t n, const Pose& pose, const Geom& g, const Hash& h,
+                         uint32_t* bits, DevCounters* ctr, hipStream_t s);
+hipError_t launch_rank(const Geom& g, const uint32_t* bits, SegBuffers& b, uint32_t cap,
+                       DevCounters* ctr, hipStream_t s);
+hipError_t launch_clear(const Geom& g, const Hash& h, uint32_t* bits, DevCounters* ctr, hipStream_t s);
+hipError_t launch_export(const Geom& g, const Hash& h, const SegBuffers& b, const DevCounters* ctr,
+                         uint32_t* key, uint32_t* cnt, unsigned long long* sum, float* mean, uint64_t cap,
+                         hipStream_t s);
+hipError_t launch_import(const Geom& g, const Hash& h, uint32_t* bits, DevCounters* ctr, const uint32_t* key,
+                         const uint32_t* cnt, const unsigned long long* sum, uint64_t n, hipStream_t s);
+
+// ---- CCL and grouping (vm_ccl.hip) --------------------------------------------
+hipError_t launch_ccl(const Geom& g, const uint32_t* bits, SegBuffers& b, uint32_t cap, DevCounters* ctr,
+                      hipStream_t s);
+hipError_t launch_group(const Geom& g, const Hash& h, SegBuffers& b, uint32_t cap, uint32_t min_cluster,
+                        uint32_t* d_labels, DevCounters* ctr, hipStream_t s);
+
+// ---- RANSAC and hulls (vm_ransac.hip, vm_hull.hip) --------------------------
+struct WorkLayout {
+    int32_t* counts;        // [k_cap * H]
+    float4* hyp;            // [k_cap * H]
+    uint32_t* tile_off;     // [k_cap + 1]
+    uint32_t* flags;        // [n_cap]
+    uint32_t* blk;          // scan partials
+    uint32_t* hull_cnt;     // [k_cap + 2]
+    uint32_t* hull_off;     // [k_cap + 2]
+    uint32_t* hull_tmp;     // [n_cap + k_cap + 2]
+    double* hull_u;         // [n_cap]
+    double* hull_v;         // [n_cap]
+    uint32_t* hull_i;       // [n_cap]
+    uint32_t* small;        // [64] misc device scalars
+    size_t bytes;
+};
+WorkLayout work_layout(void* base, uint32_t k_cap, uint32_t n_cap, uint32_t n_hyp);
+
+vm_status ransac_planes(const vm_clusters& cl, const vm_ransac_params& p, const vm_planes& out,
+                        const WorkLayout& w, hipStream_t s);
+vm_status hulls(const vm_clusters& cl, const vm_planes& planes, const vm_hulls_out& out, const WorkLayout& w,
+                hipStream_t s);
+
+}  // namespace vm

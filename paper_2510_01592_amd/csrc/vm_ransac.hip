@@ -1,0 +1,385 @@
+// vm_ransac.hip -- cluster-parallel RANSAC (Sec. III-C, "Multi-plane
+// estimation"): (a) hypotheses from three sampled points, (b) inlier
+// counting, (c) selection of the best hypothesis and extraction of its inliers.
+//
+// All clusters are processed together.  Work is cut into tiles of a fixed
+// number of points inside one cluster (the tile list is built on the device
+// from the cluster offsets), so thousands of clusters of very different sizes
+// load-balance across the 256 CUs without the host knowing any size.
+//
+// Inlier counting is the arithmetic hot spot (sum over clusters of n_k x H
+// point-plane tests).  Each lane keeps P points of its tile in registers; the
+// plane of the current hypothesis is wave-uniform (scalar loads), so one test
+// is three v_fma_f32 and one v_cmp with the |.| modifier, and the count of a
+// whole wave is a ballot and one scalar popcount.  Counts are integers added
+// with atomics, hence independent of the order of tiles.
+#include "vm_common.h"
+
+#include <math.h>
+
+namespace vm {
+namespace {
+
+constexpr int kCountBlock = 256;
+constexpr int kPtsPerLane = 4;
+constexpr int kTile = kCountBlock * kPtsPerLane;   // points per tile (1024)
+constexpr int kMaxHypChunk = 4096;                 // hypotheses staged per item (LDS counters)
+
+__device__ __forceinline__ void philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3, uint64_t k0,
+                                              uint64_t k1, uint64_t out[4])
+{
+    const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t hi0 = __umul64hi(M0, c0), lo0 = M0 * c0;
+        const uint64_t hi1 = __umul64hi(M1, c2), lo1 = M1 * c2;
+        const uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+        k0 += W0;
+        k1 += W1;
+    }
+    out[0] = c0;
+    out[1] = c1;
+    out[2] = c2;
+    out[3] = c3;
+}
+
+// (a) hypothesis (k, h): three distinct points -> unit normal (+z first) and
+// offset in fp64, rounded to float32.  Degenerate triples get a NaN plane.
+__global__ void __launch_bounds__(kBlock) k_hypotheses(const uint32_t* __restrict__ small,
+                                                       const uint32_t* __restrict__ off,
+                                                       const uint32_t* __restrict__ tag, const float* __restrict__ X,
+                                                       const float* __restrict__ Y, const float* __restrict__ Z,
+                                                       uint32_t H, uint64_t seed, uint32_t frame,
+                                                       int32_t* __restrict__ counts, float4* __restrict__ hyp)
+{
+    const uint32_t K = small[0];
+    const uint64_t total = (uint64_t)K * H;
+    for (uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t k = (uint32_t)(idx / H), h = (uint32_t)(idx % H);
+        const uint32_t base = off[k];
+        const uint64_t n = (uint64_t)(off[k + 1] - base);
+        const float qnan = __builtin_nanf("");
+        float4 pl = make_float4(qnan, qnan, qnan, qnan);
+        if (n >= 3) {
+            uint64_t r[4];
+            philox4x64_10(h, tag[k], frame, 0, seed, 0, r);
+            const uint64_t u0 = r[0] >> 32, u1 = r[1] >> 32, u2 = r[2] >> 32;
+            const uint64_t ia = (u0 * n) >> 32;
+            uint64_t ib = (u1 * (n - 1)) >> 32;
+            if (ib >= ia) ib += 1;
+            uint64_t ic = (u2 * (n - 2)) >> 32;
+            const uint64_t lo = ia < ib ? ia : ib, hi = ia < ib ? ib : ia;
+            if (ic >= lo) ic += 1;
+            if (ic >= hi) ic += 1;
+            const double ax = X[base + ia], ay = Y[base + ia], az = Z[base + ia];
+            const double e1x = (double)X[base + ib] - ax, e1y = (double)Y[base + ib] - ay,
+                         e1z = (double)Z[base + ib] - az;
+            const double e2x = (double)X[base + ic] - ax, e2y = (double)Y[base + ic] - ay,
+                         e2z = (double)Z[base + ic] - az;
+            double nx = e1y * e2z - e1z * e2y;
+            double ny = e1z * e2x - e1x * e2z;
+            double nz = e1x * e2y - e1y * e2x;
+            const double nn = nx * nx + ny * ny + nz * nz;
+            if (nn >= 1e-24) {
+                const double inv = 1.0 / sqrt(nn);
+                nx = nx * inv;
+                ny = ny * inv;
+                nz = nz * inv;
+                if (nz < 0.0 || (nz == 0.0 && (ny < 0.0 || (ny == 0.0 && nx < 0.0)))) {
+                    nx = -nx;
+                    ny = -ny;
+                    nz = -nz;
+                }
+                const double d = -(nx * ax + ny * ay + nz * az);
+                pl = make_float4((float)nx, (float)ny, (float)nz, (float)d);
+            }
+        }
+        counts[idx] = 0;
+        hyp[idx] = pl;
+    }
+}
+
+// the clusters this pass processes (small[0] = K, 0 if the CSR is invalid)
+__global__ void __launch_bounds__(kBlock) k_validate(const uint32_t* __restrict__ meta, uint32_t k_cap,
+                                                     uint32_t out_k_cap, uint32_t n_cap,
+                                                     const uint32_t* __restrict__ off, uint32_t* __restrict__ small,
+                                                     uint32_t* __restrict__ status)
+{
+    __shared__ int bad;
+    const uint32_t K = validate_clusters(meta, off, k_cap, n_cap, status, &bad);
+    if (threadIdx.x == 0) {
+        small[0] = K;
+        if (meta[0] > out_k_cap) atomicOr(status, (uint32_t)VM_FLAG_CLUSTERS_CAP);
+    }
+}
+
+// tiles per cluster (for the device-built tile list)
+__global__ void __launch_bounds__(kBlock) k_tiles(const uint32_t* __restrict__ small,
+                                                  const uint32_t* __restrict__ off, uint32_t* __restrict__ ntiles)
+{
+    const uint32_t K = small[0];
+    for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < K; k += gridDim.x * blockDim.x)
+        ntiles[k] = (off[k + 1] - off[k] + kTile - 1) / kTile;
+}
+
+__device__ __forceinline__ uint32_t cluster_of_tile(const uint32_t* __restrict__ tile_off, uint32_t K, uint32_t t)
+{
+    // largest k with tile_off[k] <= t (tile_off is the exclusive scan, K entries)
+    uint32_t lo = 0, hi = K;   // answer in [lo, hi)
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (tile_off[mid] <= t) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// (b) inlier counting over (tile, hypothesis-chunk) items
+__global__ void __launch_bounds__(kCountBlock) k_count(const uint32_t* __restrict__ small,
+                                                       const uint32_t* __restrict__ tile_off,
+                                                       const uint32_t* __restrict__ off, const float* __restrict__ X,
+                                                       const float* __restrict__ Y, const float* __restrict__ Z,
+                                                       uint32_t H, uint32_t hyp_chunk, float eps,
+                                                       const float4* __restrict__ hyp, int32_t* __restrict__ counts)
+{
+    __shared__ uint32_t lcnt[kMaxHypChunk];
+    const uint32_t K = small[0];
+    const uint32_t T = small[1];
+    const uint32_t HC = (H + hyp_chunk - 1) / hyp_chunk;
+    const uint64_t items = (uint64_t)T * HC;
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    for (uint64_t item = blockIdx.x; item < items; item += gridDim.x) {
+        const uint32_t t = (uint32_t)(item / HC), hc = (uint32_t)(item % HC);
+        const uint32_t k = cluster_of_tile(tile_off, K, t);
+        const uint32_t p0 = off[k] + (t - tile_off[k]) * kTile;
+        const uint32_t pend = off[k + 1];
+        const uint32_t h0 = hc * hyp_chunk, h1 = min(H, h0 + hyp_chunk);
+        float px[kPtsPerLane], py[kPtsPerLane], pz[kPtsPerLane];
+        const float qnan = __builtin_nanf("");
+#pragma unroll
+        for (int j = 0; j < kPtsPerLane; ++j) {
+            const uint32_t i = p0 + (uint32_t)(wave * kWave * kPtsPerLane + j * kWave + lane);
+            const bool v = i < pend;
+            px[j] = v ? X[i] : qnan;   // NaN never passes |d| < eps
+            py[j] = v ? Y[i] : qnan;
+            pz[j] = v ? Z[i] : qnan;
+        }
+        for (uint32_t h = h0 + threadIdx.x; h < h1; h += kCountBlock) lcnt[h - h0] = 0;
+        __syncthreads();
+        const float4* hk = hyp + (size_t)k * H;
+        for (uint32_t h = h0; h < h1; ++h) {
+            const float4 pl = hk[h];
+            if (pl.x != pl.x) continue;   // degenerate hypothesis
+            uint32_t acc = 0;
+#pragma unroll
+            for (int j = 0; j < kPtsPerLane; ++j) {
+                const float dd = fmaf(pl.z, pz[j], fmaf(pl.y, py[j], fmaf(pl.x, px[j], pl.w)));
+                acc += (uint32_t)__popcll(__ballot(fabsf(dd) < eps));
+            }
+            if (lane == 0 && acc) atomicAdd(&lcnt[h - h0], acc);
+        }
+        __syncthreads();
+        int32_t* ck = counts + (size_t)k * H;
+        for (uint32_t h = h0 + threadIdx.x; h < h1; h += kCountBlock) {
+            const uint32_t c = lcnt[h - h0];
+            if (c) atomicAdd(&ck[h], (int32_t)c);
+        }
+        __syncthreads();
+    }
+}
+
+// (c) best hypothesis per cluster: largest count, first index on ties
+__global__ void __launch_bounds__(kBlock) k_select(const uint32_t* __restrict__ small, uint32_t H,
+                                                   const int32_t* __restrict__ counts, const float4* __restrict__ hyp,
+                                                   float4* __restrict__ plane_out, int32_t* __restrict__ best_out,
+                                                   int32_t* __restrict__ nin_out, int32_t* __restrict__ counts_out,
+                                                   float4* __restrict__ hyp_out)
+{
+    const uint32_t K = small[0];
+    const int lane = threadIdx.x & (kWave - 1);
+    const uint32_t waves = gridDim.x * (blockDim.x / kWave);
+    for (uint32_t k = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; k < K; k += waves) {
+        int32_t bc = -1;
+        uint32_t bh = 0xFFFFFFFFu;
+        for (uint32_t h = lane; h < H; h += kWave) {
+            const float4 pl = hyp[(size_t)k * H + h];
+            const bool degen = pl.x != pl.x;
+            const int32_t c = degen ? -1 : counts[(size_t)k * H + h];
+            if (c > bc) { bc = c; bh = h; }
+            if (counts_out) counts_out[(size_t)k * H + h] = c;
+            if (hyp_out) hyp_out[(size_t)k * H + h] = degen ? make_float4(0.f, 0.f, 0.f, 0.f) : pl;
+        }
+#pragma unroll
+        for (int d = kWave / 2; d >= 1; d >>= 1) {
+            const int32_t oc = __shfl_xor(bc, d, kWave);
+            const uint32_t oh = __shfl_xor(bh, d, kWave);
+            if (oc > bc || (oc == bc && oh < bh)) { bc = oc; bh = oh; }
+        }
+        if (lane == 0) {
+            if (bc < 0) {
+                best_out[k] = -1;
+                nin_out[k] = 0;
+                plane_out[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+            } else {
+                best_out[k] = (int32_t)bh;
+                nin_out[k] = bc;
+                plane_out[k] = hyp[(size_t)k * H + bh];
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ bool inlier_test(const float4 pl, float x, float y, float z, float eps)
+{
+    return fabsf(fmaf(pl.z, z, fmaf(pl.y, y, fmaf(pl.x, x, pl.w)))) < eps;
+}
+
+// inlier flags of the winning plane, over the same tiles
+__global__ void __launch_bounds__(kCountBlock) k_inlier_flags(const uint32_t* __restrict__ small,
+                                                              const uint32_t* __restrict__ tile_off,
+                                                              const uint32_t* __restrict__ off,
+                                                              const float* __restrict__ X, const float* __restrict__ Y,
+                                                              const float* __restrict__ Z, float eps,
+                                                              const int32_t* __restrict__ best,
+                                                              const float4* __restrict__ plane,
+                                                              uint32_t* __restrict__ flags)
+{
+    const uint32_t K = small[0];
+    const uint32_t T = small[1];
+    for (uint32_t t = blockIdx.x; t < T; t += gridDim.x) {
+        const uint32_t k = cluster_of_tile(tile_off, K, t);
+        const uint32_t p0 = off[k] + (t - tile_off[k]) * kTile;
+        const uint32_t pend = min(p0 + kTile, off[k + 1]);
+        const bool has = best[k] >= 0;
+        const float4 pl = plane[k];
+        for (uint32_t i = p0 + threadIdx.x; i < pend; i += kCountBlock)
+            flags[i] = (has && inlier_test(pl, X[i], Y[i], Z[i], eps)) ? 1u : 0u;
+    }
+}
+
+__global__ void __launch_bounds__(kCountBlock) k_inlier_write(const uint32_t* __restrict__ small,
+                                                              const uint32_t* __restrict__ tile_off,
+                                                              const uint32_t* __restrict__ off,
+                                                              const float* __restrict__ X, const float* __restrict__ Y,
+                                                              const float* __restrict__ Z, float eps,
+                                                              const int32_t* __restrict__ best,
+                                                              const float4* __restrict__ plane,
+                                                              const uint32_t* __restrict__ pos, uint32_t in_cap,
+                                                              uint32_t* __restrict__ in_idx, uint32_t* __restrict__ status)
+{
+    const uint32_t K = small[0];
+    const uint32_t T = small[1];
+    bool over = false;
+    for (uint32_t t = blockIdx.x; t < T; t += gridDim.x) {
+        const uint32_t k = cluster_of_tile(tile_off, K, t);
+        const uint32_t base = off[k];
+        const uint32_t p0 = base + (t - tile_off[k]) * kTile;
+        const uint32_t pend = min(p0 + kTile, off[k + 1]);
+        if (best[k] < 0) continue;
+        const float4 pl = plane[k];
+        for (uint32_t i = p0 + threadIdx.x; i < pend; i += kCountBlock) {
+            if (inlier_test(pl, X[i], Y[i], Z[i], eps)) {
+                const uint32_t p = pos[i];
+                if (p < in_cap) in_idx[p] = i - base;
+                else over = true;
+            }
+        }
+    }
+    if (over) atomicOr(status, (uint32_t)VM_FLAG_INLIERS_CAP);
+}
+
+__global__ void __launch_bounds__(kBlock) k_inlier_off(const uint32_t* __restrict__ small,
+                                                       const uint32_t* __restrict__ off,
+                                                       const uint32_t* __restrict__ pos,
+                                                       const uint32_t* __restrict__ meta, uint32_t* __restrict__ in_off)
+{
+    const uint32_t K = small[0];
+    const uint32_t n = meta[1];
+    const uint32_t total = small[2];
+    for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k <= K; k += gridDim.x * blockDim.x) {
+        const uint32_t o = off[k];
+        in_off[k] = o < n ? pos[o] : total;
+    }
+}
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+
+WorkLayout work_layout(void* base, uint32_t k_cap, uint32_t n_cap, uint32_t n_hyp)
+{
+    WorkLayout w{};
+    char* p = (char*)base;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        char* r = p ? p + o : nullptr;
+        o += align256(bytes);
+        return r;
+    };
+    const size_t kh = (size_t)k_cap * (size_t)n_hyp;
+    w.counts = (int32_t*)take(kh * sizeof(int32_t));
+    w.hyp = (float4*)take(kh * sizeof(float4));
+    w.tile_off = (uint32_t*)take(((size_t)k_cap + 2) * sizeof(uint32_t));
+    w.flags = (uint32_t*)take(((size_t)n_cap + 1) * sizeof(uint32_t));
+    const size_t blk_words = scan_blk_words((uint64_t)n_cap + k_cap + 2) + 64;
+    w.blk = (uint32_t*)take(blk_words * sizeof(uint32_t));
+    w.hull_cnt = (uint32_t*)take(((size_t)k_cap + 2) * sizeof(uint32_t));
+    w.hull_off = (uint32_t*)take(((size_t)k_cap + 2) * sizeof(uint32_t));
+    w.hull_tmp = (uint32_t*)take(((size_t)n_cap + k_cap + 2) * sizeof(uint32_t));
+    w.hull_u = (double*)take(((size_t)n_cap + 1) * sizeof(double));
+    w.hull_v = (double*)take(((size_t)n_cap + 1) * sizeof(double));
+    w.hull_i = (uint32_t*)take(((size_t)n_cap + 1) * sizeof(uint32_t));
+    w.small = (uint32_t*)take(64 * sizeof(uint32_t));
+    w.bytes = o;
+    return w;
+}
+
+vm_status ransac_planes(const vm_clusters& cl, const vm_ransac_params& p, const vm_planes& out,
+                        const WorkLayout& w, hipStream_t s)
+{
+    const uint32_t kc = cl.k_cap < out.k_cap ? cl.k_cap : out.k_cap;
+    const uint32_t H = p.n_hyp;
+    // small[0] = K (clamped), small[1] = tiles, small[2] = inliers
+    {
+        StageScope t(VM_STAGE_HYPOTHESES, s);
+        k_validate<<<1, kBlock, 0, s>>>(cl.d_meta, kc, out.k_cap, cl.n_cap, cl.d_off, w.small, out.d_status);
+        k_tiles<<<grid_for(kc), kBlock, 0, s>>>(w.small, cl.d_off, w.tile_off);
+        VM_HIP(scan_exclusive_dev(w.tile_off, w.tile_off, w.small, kc, w.small + 1, w.blk, s));
+        const uint64_t kh = (uint64_t)kc * H;
+        k_hypotheses<<<grid_for(kh, kBlock, 16384), kBlock, 0, s>>>(w.small, cl.d_off, cl.d_tag, cl.d_x, cl.d_y,
+                                                                    cl.d_z, H, p.seed, p.frame, w.counts, w.hyp);
+        VM_HIP(hipGetLastError());
+    }
+    {
+        StageScope t(VM_STAGE_COUNT, s);
+        const uint32_t chunk = H < (uint32_t)kMaxHypChunk ? H : (uint32_t)kMaxHypChunk;
+        k_count<<<4096, kCountBlock, 0, s>>>(w.small, w.tile_off, cl.d_off, cl.d_x, cl.d_y, cl.d_z, H, chunk, p.eps,
+                                             w.hyp, w.counts);
+        VM_HIP(hipGetLastError());
+    }
+    {
+        StageScope t(VM_STAGE_SELECT, s);
+        k_select<<<grid_for((uint64_t)kc * kWave), kBlock, 0, s>>>(w.small, H, w.counts, w.hyp, (float4*)out.d_plane,
+                                                                   out.d_best_h, out.d_n_inliers, out.d_counts,
+                                                                   (float4*)out.d_hyp);
+        const int tgrid = grid_for((uint64_t)cl.n_cap / kTile + kc + 1, 1, 8192);
+        k_inlier_flags<<<tgrid, kCountBlock, 0, s>>>(w.small, w.tile_off, cl.d_off, cl.d_x, cl.d_y, cl.d_z, p.eps,
+                                                     out.d_best_h, (const float4*)out.d_plane, w.flags);
+        VM_HIP(scan_exclusive_dev(w.flags, w.flags, cl.d_meta + 1, cl.n_cap, w.small + 2, w.blk, s));
+        k_inlier_write<<<tgrid, kCountBlock, 0, s>>>(w.small, w.tile_off, cl.d_off, cl.d_x, cl.d_y, cl.d_z, p.eps,
+                                                     out.d_best_h, (const float4*)out.d_plane, w.flags, out.in_cap,
+                                                     out.d_in_idx, out.d_status);
+        k_inlier_off<<<grid_for((uint64_t)kc + 1), kBlock, 0, s>>>(w.small, cl.d_off, w.flags, cl.d_meta,
+                                                                    out.d_in_off);
+        VM_HIP(hipGetLastError());
+    }
+    return VM_OK;
+}
+
+}  // namespace vm

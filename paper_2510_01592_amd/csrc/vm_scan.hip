@@ -1,0 +1,252 @@
+// vm_scan.hip -- device-wide exclusive scan and stable LSD radix sort of
+// (key, value) pairs, with element counts read on the device so that no
+// stage of a frame waits for the host.
+#include "vm_common.h"
+
+namespace vm {
+namespace {
+
+constexpr int kScanItems = 16;                      // per thread
+constexpr int kScanTile = kBlock * kScanItems;      // 4096 values per block
+
+constexpr int kRadixBits = 8;
+constexpr int kRadixBins = 1 << kRadixBits;
+constexpr int kRadixIters = 8;
+constexpr int kRadixTile = kBlock * kRadixIters;    // 2048 pairs per block
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, int lane)
+{
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint32_t o = __shfl_up(v, d, kWave);
+        if (lane >= d) v += o;
+    }
+    return v;
+}
+
+// Block-wide exclusive scan of one value per thread; returns the prefix and
+// writes the block total to *total.
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* lds4, uint32_t* total)
+{
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const uint32_t inc = wave_incl_scan(v, lane);
+    if (lane == kWave - 1) lds4[wave] = inc;
+    __syncthreads();
+    uint32_t off = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < kBlock / kWave; ++w) {
+        const uint32_t t = lds4[w];
+        off += (w < wave) ? t : 0u;
+        tot += t;
+    }
+    __syncthreads();
+    *total = tot;
+    return off + inc - v;
+}
+
+__global__ void __launch_bounds__(kBlock) k_scan_reduce(const uint32_t* __restrict__ in, const uint32_t* d_n,
+                                                        uint32_t n_fixed, uint32_t* __restrict__ blk)
+{
+    __shared__ uint32_t lds[kBlock / kWave];
+    const uint32_t n = d_n ? min(*d_n, n_fixed) : n_fixed;
+    const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
+    if (base >= n) {
+        if (threadIdx.x == 0) blk[blockIdx.x] = 0;
+        return;
+    }
+    uint32_t s = 0;
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        const uint64_t i = base + (uint64_t)j * kBlock + threadIdx.x;
+        if (i < n) s += in[i];
+    }
+    uint32_t tot;
+    block_excl_scan(s, lds, &tot);
+    if (threadIdx.x == 0) blk[blockIdx.x] = tot;
+}
+
+// One block scans the per-block totals (any count) in place.
+__global__ void __launch_bounds__(1024) k_scan_blocks(uint32_t* blk, uint32_t nblk, uint32_t* d_total)
+{
+    __shared__ uint32_t lds[1024 / kWave];
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    uint32_t carry = 0;
+    for (uint32_t base = 0; base < nblk; base += 1024) {
+        const uint32_t i = base + threadIdx.x;
+        const uint32_t v = i < nblk ? blk[i] : 0u;
+        const uint32_t inc = wave_incl_scan(v, lane);
+        if (lane == kWave - 1) lds[wave] = inc;
+        __syncthreads();
+        uint32_t off = 0, tot = 0;
+        for (int w = 0; w < 1024 / kWave; ++w) {
+            const uint32_t t = lds[w];
+            off += (w < wave) ? t : 0u;
+            tot += t;
+        }
+        __syncthreads();
+        if (i < nblk) blk[i] = carry + off + inc - v;
+        carry += tot;
+    }
+    if (threadIdx.x == 0 && d_total) *d_total = carry;
+}
+
+__global__ void __launch_bounds__(kBlock) k_scan_down(const uint32_t* __restrict__ in, uint32_t* __restrict__ out,
+                                                      const uint32_t* d_n, uint32_t n_fixed,
+                                                      const uint32_t* __restrict__ blk)
+{
+    __shared__ uint32_t lds[kBlock / kWave];
+    const uint32_t n = d_n ? min(*d_n, n_fixed) : n_fixed;
+    const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
+    if (base >= n) return;
+    // blocked arrangement: thread t owns values [t*I, t*I + I) of the tile
+    uint32_t v[kScanItems];
+    uint32_t s = 0;
+    const uint64_t mine = base + (uint64_t)threadIdx.x * kScanItems;
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        const uint64_t i = mine + j;
+        v[j] = i < n ? in[i] : 0u;
+        s += v[j];
+    }
+    uint32_t tot;
+    uint32_t run = block_excl_scan(s, lds, &tot) + blk[blockIdx.x];
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        const uint64_t i = mine + j;
+        if (i < n) out[i] = run;
+        run += v[j];
+    }
+}
+
+// ---- radix sort ---------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock) k_radix_hist(const uint32_t* __restrict__ keys, const uint32_t* d_n,
+                                                       int shift, const uint32_t* d_max_key, uint32_t nblk,
+                                                       uint32_t* __restrict__ hist)
+{
+    __shared__ uint32_t cnt[kRadixBins];
+    const uint32_t n = *d_n;
+    cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const bool identity = ((*d_max_key) >> shift) == 0u;
+    const uint64_t base = (uint64_t)blockIdx.x * kRadixTile;
+    if (!identity) {
+        for (int j = 0; j < kRadixIters; ++j) {
+            const uint64_t i = base + (uint64_t)j * kBlock + threadIdx.x;
+            if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & (kRadixBins - 1)], 1u);
+        }
+    }
+    __syncthreads();
+    hist[(uint64_t)threadIdx.x * nblk + blockIdx.x] = cnt[threadIdx.x];
+}
+
+__global__ void __launch_bounds__(kBlock) k_radix_scatter(const uint32_t* __restrict__ kin,
+                                                          const uint32_t* __restrict__ vin,
+                                                          uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
+                                                          const uint32_t* d_n, int shift, const uint32_t* d_max_key,
+                                                          uint32_t nblk, const uint32_t* __restrict__ hist)
+{
+    __shared__ uint32_t base[kRadixBins];
+    __shared__ uint32_t wcnt[kBlock / kWave][kRadixBins];
+    const uint32_t n = *d_n;
+    const uint64_t tile = (uint64_t)blockIdx.x * kRadixTile;
+    if (tile >= n) return;
+    if (((*d_max_key) >> shift) == 0u) {
+        // every digit is zero: the stable pass is the identity permutation
+        for (int j = 0; j < kRadixIters; ++j) {
+            const uint64_t i = tile + (uint64_t)j * kBlock + threadIdx.x;
+            if (i < n) { kout[i] = kin[i]; vout[i] = vin[i]; }
+        }
+        return;
+    }
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    base[threadIdx.x] = hist[(uint64_t)threadIdx.x * nblk + blockIdx.x];
+#pragma unroll
+    for (int w = 0; w < kBlock / kWave; ++w) wcnt[w][threadIdx.x] = 0;
+    __syncthreads();
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int j = 0; j < kRadixIters; ++j) {
+        const uint64_t i = tile + (uint64_t)j * kBlock + threadIdx.x;
+        const bool valid = i < n;
+        const uint32_t k = valid ? kin[i] : 0u;
+        const uint32_t v = valid ? vin[i] : 0u;
+        const uint32_t dig = (k >> shift) & (kRadixBins - 1);
+        // lanes of this wave holding the same digit
+        uint64_t m = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < kRadixBits; ++b) {
+            const bool bit = (dig >> b) & 1u;
+            const uint64_t bb = __ballot(valid && bit);
+            m &= bit ? bb : ~bb;
+        }
+        const uint32_t r = (uint32_t)__popcll(m & lt);
+        if (valid && r == 0) wcnt[wave][dig] = (uint32_t)__popcll(m);
+        __syncthreads();
+        if (valid) {
+            uint32_t pos = base[dig] + r;
+            for (int w = 0; w < wave; ++w) pos += wcnt[w][dig];
+            kout[pos] = k;
+            vout[pos] = v;
+        }
+        __syncthreads();
+        {
+            const int d = threadIdx.x;
+            uint32_t add = 0;
+#pragma unroll
+            for (int w = 0; w < kBlock / kWave; ++w) { add += wcnt[w][d]; wcnt[w][d] = 0; }
+            base[d] += add;
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+size_t scan_blk_words(uint64_t n_cap)
+{
+    return (size_t)((n_cap + kScanTile - 1) / kScanTile) + 64;
+}
+
+hipError_t scan_exclusive_dev(const uint32_t* in, uint32_t* out, const uint32_t* d_n, uint32_t n_cap,
+                              uint32_t* d_total, uint32_t* blk, hipStream_t s)
+{
+    const uint32_t nblk = (uint32_t)((uint64_t(n_cap) + kScanTile - 1) / kScanTile);
+    if (nblk == 0) {
+        k_scan_blocks<<<1, 1024, 0, s>>>(blk, 0, d_total);
+        return hipGetLastError();
+    }
+    k_scan_reduce<<<nblk, kBlock, 0, s>>>(in, d_n, n_cap, blk);
+    k_scan_blocks<<<1, 1024, 0, s>>>(blk, nblk, d_total);
+    k_scan_down<<<nblk, kBlock, 0, s>>>(in, out, d_n, n_cap, blk);
+    return hipGetLastError();
+}
+
+size_t radix_hist_words(uint64_t n_cap)
+{
+    return (size_t)kRadixBins * ((n_cap + kRadixTile - 1) / kRadixTile + 1) + 64;
+}
+
+hipError_t radix_sort_pairs_dev(uint32_t* keys[2], uint32_t* vals[2], const uint32_t* d_n, uint32_t n_cap,
+                                int bits, const uint32_t* d_max_key, uint32_t* hist, uint32_t* blk,
+                                int* result_buf, hipStream_t s)
+{
+    const uint32_t nblk = (uint32_t)((uint64_t(n_cap) + kRadixTile - 1) / kRadixTile);
+    const int passes = (bits + kRadixBits - 1) / kRadixBits;
+    *result_buf = 0;
+    if (nblk == 0 || passes == 0) return hipSuccess;
+    const uint32_t hn = (uint32_t)kRadixBins * nblk;
+    hipError_t e = hipSuccess;
+    int src = 0;
+    for (int p = 0; p < passes; ++p) {
+        const int shift = p * kRadixBits;
+        k_radix_hist<<<nblk, kBlock, 0, s>>>(keys[src], d_n, shift, d_max_key, nblk, hist);
+        e = scan_exclusive_dev(hist, hist, nullptr, hn, nullptr, blk, s);
+        if (e != hipSuccess) return e;
+        k_radix_scatter<<<nblk, kBlock, 0, s>>>(keys[src], vals[src], keys[src ^ 1], vals[src ^ 1], d_n, shift,
+                                                 d_max_key, nblk, hist);
+        src ^= 1;
+    }
+    *result_buf = src;
+    return hipGetLastError();
+}
+
+}  // namespace vm

@@ -1,0 +1,99 @@
+"""The C ABI: the library loads and exports every function include/vm.h
+declares; host-side argument checks reject bad input before any device work
+(no GPU needed for these)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "vm.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s+(vm_[a-z_0-9]+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_parses():
+    names = _declared()
+    for n in ("vm_insert", "vm_ccl", "vm_ransac_planes", "vm_hulls", "vm_segment_frame", "vm_map_create"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2510_01592_amd as vm
+    L = vm.lib()
+    for n in _declared():
+        assert hasattr(L, n), n
+    assert sorted(vm.EXPORTED) == _declared()
+
+
+def test_status_strings_and_version():
+    import paper_2510_01592_amd as vm
+    assert vm.version() >= 100
+    assert vm.status_string(0) == "ok"
+    assert vm.status_string(-1) == "invalid argument"
+    assert "unknown" in vm.status_string(-99)
+
+
+def test_workspace_bytes_monotone():
+    import paper_2510_01592_amd as vm
+    a = vm.workspace_bytes(10, 1000, 64)
+    assert a > 0
+    assert vm.workspace_bytes(20, 1000, 64) > a
+    assert vm.workspace_bytes(10, 2000, 64) > a
+    assert vm.workspace_bytes(10, 1000, 128) > a
+
+
+def test_argument_errors_without_device_work():
+    import paper_2510_01592_amd as vm
+    L = vm.lib()
+    h = ctypes.c_void_p()
+    # null descriptor / out pointer
+    assert L.vm_map_create(None, ctypes.byref(h)) == vm.VM_E_ARG
+    d = vm.MapDesc()
+    d.voxel_size = 0.0
+    assert L.vm_map_create(ctypes.byref(d), ctypes.byref(h)) == vm.VM_E_ARG
+    d.voxel_size = 0.01
+    for i in range(3):
+        d.dims[i] = 4096
+    d.hash_capacity_log2 = 12
+    assert L.vm_map_create(ctypes.byref(d), ctypes.byref(h)) == vm.VM_E_ARG     # 2^36 cells
+    for i in range(3):
+        d.dims[i] = 8
+    d.hash_capacity_log2 = 40
+    assert L.vm_map_create(ctypes.byref(d), ctypes.byref(h)) == vm.VM_E_ARG
+    # null map handles
+    assert L.vm_insert(None, None, 0, None, None) == vm.VM_E_ARG
+    assert L.vm_map_destroy(None) == vm.VM_E_ARG
+    assert L.vm_ccl(None, 30, None, None, None) == vm.VM_E_ARG
+    # bad RANSAC parameters are rejected before any device pointer is touched
+    cl = vm.Clusters(1, 1, 8, 8, 8, 8, 8, None, 8)
+    pl = vm.Planes(1, 1, 8, 8, 8, 8, 8, None, None, 8)
+    bad = vm.RansacParams(0, 0.01, 1, 0, 0)
+    assert L.vm_ransac_planes(ctypes.byref(cl), ctypes.byref(bad), ctypes.byref(pl), 8, 1 << 20, None) == vm.VM_E_ARG
+    bad = vm.RansacParams(16, -1.0, 1, 0, 0)
+    assert L.vm_ransac_planes(ctypes.byref(cl), ctypes.byref(bad), ctypes.byref(pl), 8, 1 << 20, None) == vm.VM_E_ARG
+    bad = vm.RansacParams(16, 0.01, 1, 0, 7)
+    assert L.vm_ransac_planes(ctypes.byref(cl), ctypes.byref(bad), ctypes.byref(pl), 8, 1 << 20, None) == vm.VM_E_ARG
+    ok = vm.RansacParams(16, 0.01, 1, 0, 0)
+    assert L.vm_ransac_planes(ctypes.byref(cl), ctypes.byref(ok), ctypes.byref(pl), 8, 16, None) == vm.VM_E_CAPACITY
+    ms = (ctypes.c_double * 8)()
+    n = (ctypes.c_uint64 * 8)()
+    assert L.vm_stage_times(ms, n, -1) == vm.VM_E_ARG
+
+
+def test_struct_layouts_match_header_sizes():
+    import paper_2510_01592_amd as vm
+    # natural C alignment on x86-64 / amdgcn host ABI
+    assert ctypes.sizeof(vm.MapDesc) == 3 * 8 + 8 + 3 * 4 + 4
+    assert ctypes.sizeof(vm.Pose) == 12 * 8
+    assert ctypes.sizeof(vm.RansacParams) == 24
+    assert ctypes.sizeof(vm.SegParams) == 32
+    assert ctypes.sizeof(vm.Clusters) == 8 + 7 * 8
+    assert ctypes.sizeof(vm.Planes) == 8 + 8 * 8
+    assert ctypes.sizeof(vm.HullsOut) == 8 + 5 * 8
