@@ -107,6 +107,11 @@ vm_status vm_map_clear(vm_map map, void* stream);
 /* Synchronises `stream`, then reports the map's counters. */
 vm_status vm_map_stats(vm_map map, void* stream, vm_map_stats_t* out);
 
+/* Enqueue a copy of the map's counters (as vm_map_stats would report them
+ * once `stream` reaches this point) into caller-owned device memory d_out;
+ * nothing waits for the host. */
+vm_status vm_map_stats_async(vm_map map, vm_map_stats_t* d_out, void* stream);
+
 /* Sec. III-B "Voxel information update", Eq. (1).  Transforms the n float32
  * xyz points at d_xyz (AoS, 12 bytes each, caller-owned device memory) by
  * `pose` in fp64 (x' = fma(R02, z, fma(R01, y, fma(R00, x, t0))), likewise for
@@ -194,8 +199,10 @@ typedef struct {
     uint32_t* d_status;    /* [1] device word, VM_FLAG_* OR-ed in (never cleared by the library) */
 } vm_planes;
 
-/* Device scratch for vm_ransac_planes / vm_hulls, in bytes, for clusters
- * bounded by (k_cap, n_cap) and n_hyp hypotheses. */
+/* Device scratch for vm_ransac_planes / vm_hulls, in bytes: k_cap is the
+ * number of clusters a call may process, min(clusters.k_cap, outputs'
+ * k_cap); n_cap the clusters' point bound; n_hyp the hypotheses per cluster
+ * (1 for a buffer that only serves vm_hulls). */
 size_t vm_workspace_bytes(uint32_t k_cap, uint32_t n_cap, uint32_t n_hyp);
 
 /* Sec. III-C (a)-(c) on every cluster of `cl`, all clusters in one pass.

@@ -23,6 +23,7 @@ STAGES = ["insert", "rank", "ccl", "group", "hypotheses", "count", "select", "hu
 
 EXPORTED = [
     "vm_status_string", "vm_version", "vm_map_create", "vm_map_destroy", "vm_map_clear", "vm_map_stats",
+    "vm_map_stats_async",
     "vm_insert", "vm_map_export", "vm_map_import", "vm_ccl", "vm_workspace_bytes", "vm_ransac_planes",
     "vm_hulls", "vm_segment_frame", "vm_set_stage_timing", "vm_stage_times",
 ]
@@ -97,6 +98,7 @@ def lib() -> ctypes.CDLL:
             "vm_map_destroy": ([_P], i32),
             "vm_map_clear": ([_P, _P], i32),
             "vm_map_stats": ([_P, _P, ctypes.POINTER(MapStats)], i32),
+            "vm_map_stats_async": ([_P, _P, _P], i32),
             "vm_insert": ([_P, _P, i64, ctypes.POINTER(Pose), _P], i32),
             "vm_map_export": ([_P, _P, _P, _P, _P, u64, ctypes.POINTER(u64), _P], i32),
             "vm_map_import": ([_P, _P, _P, _P, u64, _P], i32),
@@ -270,6 +272,12 @@ class Map:
         _check(lib().vm_map_stats(self._h, _stream(stream), ctypes.byref(s)), "vm_map_stats")
         return s
 
+    def stats_async(self, out, stream=None) -> None:
+        """Enqueue the counters into ``out`` (device int64 tensor of >= 5 entries)."""
+        if out.numel() * out.element_size() < ctypes.sizeof(MapStats):
+            raise ValueError("stats buffer too small")
+        _check(lib().vm_map_stats_async(self._h, _ptr(out), _stream(stream)), "vm_map_stats_async")
+
     def insert(self, xyz, R=None, t=None, stream=None) -> None:
         if xyz.dtype.__str__() != "torch.float32" or xyz.dim() != 2 or xyz.shape[1] != 3:
             raise ValueError("float32 [N, 3] tensor expected")
@@ -358,13 +366,13 @@ class _DevArray:
     """Zero-copy view of library-owned device memory for torch."""
 
     def __init__(self, ptr: int, n: int, typestr: str):
-        self.__cuda_array_interface__ = {"shape": (n,), "typestr": typestr, "data": (ptr, True), "version": 2}
+        self.__cuda_array_interface__ = {"shape": (n,), "typestr": typestr, "data": (ptr, False), "version": 2}
 
 
 def device_view(ptr: int, n: int, dtype):
     """torch tensor aliasing n elements at a device pointer owned by the library."""
     import torch
-    ts = {np.uint32: "<u4", np.int32: "<i4", np.float32: "<f4"}[dtype]
+    ts = {np.uint32: "<i4", np.int32: "<i4", np.float32: "<f4"}[dtype]   # uint32 travels as int32 bits
     if n == 0 or not ptr:
         return torch.zeros(0, dtype={np.uint32: torch.int32, np.int32: torch.int32, np.float32: torch.float32}[dtype],
                            device="cuda")

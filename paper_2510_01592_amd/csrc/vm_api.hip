@@ -297,6 +297,13 @@ vm_status vm_map_stats(vm_map m, void* stream, vm_map_stats_t* out)
     return VM_OK;
 }
 
+vm_status vm_map_stats_async(vm_map m, vm_map_stats_t* d_out, void* stream)
+{
+    if (!m || !d_out) return VM_E_ARG;
+    VM_HIP(launch_stats(m->ctr, m->h.log2cap, d_out, (hipStream_t)stream));
+    return VM_OK;
+}
+
 vm_status vm_insert(vm_map m, const float* d_xyz, int64_t n, const vm_pose* pose, void* stream)
 {
     if (!m || n < 0 || (n > 0 && !d_xyz) || !finite_pose(pose)) return VM_E_ARG;
@@ -359,7 +366,8 @@ vm_status vm_ransac_planes(const vm_clusters* cl, const vm_ransac_params* params
     if (check_clusters(cl) != VM_OK || check_params(params) != VM_OK || check_planes(out, params ? params->n_hyp : 0) != VM_OK ||
         !d_work)
         return VM_E_ARG;
-    const WorkLayout w = work_layout(d_work, cl->k_cap, cl->n_cap, params->n_hyp);
+    const uint32_t kc = std::min(cl->k_cap, out->k_cap);
+    const WorkLayout w = work_layout(d_work, kc, cl->n_cap, params->n_hyp);
     if (work_bytes < w.bytes) return VM_E_CAPACITY;
     return ransac_planes(*cl, *params, *out, w, (hipStream_t)stream);
 }
@@ -369,10 +377,10 @@ vm_status vm_hulls(const vm_clusters* cl, const vm_planes* planes, vm_hulls_out*
 {
     if (check_clusters(cl) != VM_OK || check_planes(planes, 1) != VM_OK || check_hulls(out) != VM_OK || !d_work)
         return VM_E_ARG;
-    // the hull pass uses only the hypothesis-independent part of the layout
-    const WorkLayout w = work_layout(d_work, cl->k_cap, cl->n_cap, 1);
-    const WorkLayout wz = work_layout(nullptr, cl->k_cap, cl->n_cap, 1);
-    if (work_bytes < wz.bytes) return VM_E_CAPACITY;
+    // the hull pass needs no per-hypothesis storage
+    const uint32_t kc = std::min(std::min(cl->k_cap, planes->k_cap), out->k_cap);
+    const WorkLayout w = work_layout(d_work, kc, cl->n_cap, 1);
+    if (work_bytes < w.bytes) return VM_E_CAPACITY;
     return hulls(*cl, *planes, *out, w, (hipStream_t)stream);
 }
 
@@ -384,7 +392,7 @@ vm_status vm_segment_frame(vm_map m, const float* d_xyz, int64_t n, const vm_pos
     if (check_planes(planes, params->ransac.n_hyp) != VM_OK || check_hulls(hulls_out) != VM_OK) return VM_E_ARG;
     if (n < 0 || (n > 0 && !d_xyz) || !finite_pose(pose)) return VM_E_ARG;
     const uint32_t minc = params->min_cluster < 1 ? 1 : params->min_cluster;
-    const uint32_t kb = map_k_bound(m, minc);
+    const uint32_t kb = std::min(map_k_bound(m, minc), std::min(planes->k_cap, hulls_out->k_cap));
     // the map's own workspace: allocated once per (cluster bound, hypotheses)
     if (!m->work || m->work_k < kb || m->work_hyp < params->ransac.n_hyp) {
         const uint32_t k = std::max(kb, m->work_k);
@@ -408,12 +416,11 @@ vm_status vm_segment_frame(vm_map m, const float* d_xyz, int64_t n, const vm_pos
     st = vm_ccl(m, minc, d_labels, &cl, stream);
     if (st != VM_OK) return st;
     if (clusters_out) *clusters_out = cl;
-    const WorkLayout w = work_layout(m->work, cl.k_cap, cl.n_cap, params->ransac.n_hyp);
+    const WorkLayout w = work_layout(m->work, kb, cl.n_cap, params->ransac.n_hyp);
     if (w.bytes > m->work_bytes) return VM_E_STATE;
     st = ransac_planes(cl, params->ransac, *planes, w, (hipStream_t)stream);
     if (st != VM_OK) return st;
-    const WorkLayout wh = work_layout(m->work, cl.k_cap, cl.n_cap, params->ransac.n_hyp);
-    return hulls(cl, *planes, *hulls_out, wh, (hipStream_t)stream);
+    return hulls(cl, *planes, *hulls_out, w, (hipStream_t)stream);
 }
 
 vm_status vm_set_stage_timing(int32_t enable)

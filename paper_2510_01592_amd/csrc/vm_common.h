@@ -165,6 +165,7 @@ hipError_t radix_sort_pairs_dev(uint32_t* keys[2], uint32_t* vals[2], const uint
 // ---- map stages (vm_map.hip) ------------------------------------------------
 hipError_t launch_insert(const float* xyz, int64_t n, const Pose& pose, const Geom& g, const Hash& h,
                          uint32_t* bits, DevCounters* ctr, hipStream_t s);
+hipError_t launch_stats(const DevCounters* ctr, uint32_t log2cap, vm_map_stats_t* out, hipStream_t s);
 hipError_t launch_rank(const Geom& g, const uint32_t* bits, SegBuffers& b, uint32_t cap,
                        DevCounters* ctr, hipStream_t s);
 hipError_t launch_clear(const Geom& g, const Hash& h, uint32_t* bits, DevCounters* ctr, hipStream_t s);

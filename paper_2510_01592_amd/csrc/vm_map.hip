@@ -175,7 +175,25 @@ __global__ void __launch_bounds__(kBlock) k_import(Geom g, Hash h, uint32_t* __r
     if (__ballot(n_lost != 0) && (threadIdx.x & (kWave - 1)) == 0) atomicOr(&ctr->flags, (uint32_t)VM_FLAG_HASH_FULL);
 }
 
+__global__ void k_stats(const DevCounters* __restrict__ c, uint32_t log2cap, vm_map_stats_t* out)
+{
+    if (threadIdx.x == 0) {
+        out->occupied = c->occupied;
+        out->points_in = c->points_in;
+        out->points_dropped = c->points_dropped;
+        out->points_lost = c->points_lost;
+        out->status_flags = c->flags;
+        out->hash_capacity_log2 = log2cap;
+    }
+}
+
 }  // namespace
+
+hipError_t launch_stats(const DevCounters* ctr, uint32_t log2cap, vm_map_stats_t* out, hipStream_t s)
+{
+    k_stats<<<1, 64, 0, s>>>(ctr, log2cap, out);
+    return hipGetLastError();
+}
 
 hipError_t launch_insert(const float* xyz, int64_t n, const Pose& pose, const Geom& g, const Hash& h,
                          uint32_t* bits, DevCounters* ctr, hipStream_t s)

@@ -343,6 +343,7 @@ WorkLayout work_layout(void* base, uint32_t k_cap, uint32_t n_cap, uint32_t n_hy
 vm_status ransac_planes(const vm_clusters& cl, const vm_ransac_params& p, const vm_planes& out,
                         const WorkLayout& w, hipStream_t s)
 {
+    // the workspace is laid out for kc = min(cl.k_cap, out.k_cap) clusters
     const uint32_t kc = cl.k_cap < out.k_cap ? cl.k_cap : out.k_cap;
     const uint32_t H = p.n_hyp;
     // small[0] = K (clamped), small[1] = tiles, small[2] = inliers

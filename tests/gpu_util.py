@@ -51,7 +51,7 @@ def cluster_tensors(off: np.ndarray, xyz: np.ndarray, tag: np.ndarray):
 
 def run_planes_and_hulls(vm, cl, k_cap, n_cap, n_hyp, eps, seed, frame, with_all=True):
     import torch
-    work = torch.empty(vm.workspace_bytes(k_cap, n_cap, n_hyp), dtype=torch.uint8, device="cuda")
+    work = torch.empty(vm.workspace_bytes(min(k_cap, cl.k_cap), cl.n_cap, n_hyp), dtype=torch.uint8, device="cuda")
     pb = vm.PlaneBuffers.alloc(k_cap, n_cap, n_hyp, with_all=with_all)
     hb = vm.HullBuffers.alloc(k_cap, n_cap)
     vm.ransac_planes(cl, vm.ransac_params(n_hyp, eps, seed, frame), pb, work)

@@ -219,7 +219,7 @@ def test_empty_and_small(vm):
     got = vm.read_clusters(cl)
     assert got["K"] == 0 and got["N"] == 0
     # a handful of points: clusters below the minimum size are dropped
-    pts = np.array([[0.1, 0.1, 0.1], [0.11, 0.1, 0.1], [0.5, 0.5, 0.5]], np.float32)
+    pts = np.array([[0.105, 0.105, 0.105], [0.115, 0.105, 0.105], [0.505, 0.505, 0.505]], np.float32)
     note("tiny frame")
     cl = m.segment_frame(_t(pts), pb, hb, min_cluster=2, n_hyp=16)
     got = vm.read_clusters(cl)
@@ -244,7 +244,7 @@ def test_overflow_flags(vm):
     pb, hb = run_planes_and_hulls(vm, cl, 64, 1 << 17, 32, 0.01, SEED, 0, with_all=False)
     full = planes_np(pb)
     # only two of the three clusters fit; few hull slots
-    work = torch.empty(vm.workspace_bytes(cl.k_cap, cl.n_cap, 32), dtype=torch.uint8, device="cuda")
+    work = torch.empty(vm.workspace_bytes(4, cl.n_cap, 32), dtype=torch.uint8, device="cuda")
     small = vm.PlaneBuffers.alloc(2, 30000, 32)
     hsmall = vm.HullBuffers.alloc(2, 10)
     vm.ransac_planes(cl, vm.ransac_params(32, 0.01, SEED, 0), small, work)
