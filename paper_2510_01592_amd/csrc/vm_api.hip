@@ -58,22 +58,36 @@ hipEvent_t take_event(TimingState& t)
 }
 }  // namespace
 
-StageScope::StageScope(int stage, hipStream_t s) : stage_(stage), s_(s), ev0_(nullptr)
+// Both events of a scope are taken from the pool before the first one is
+// recorded, so nothing slow (an event creation) sits between a stage's
+// kernels and its closing event.
+StageScope::StageScope(int stage, hipStream_t s) : stage_(stage), s_(s), ev0_(nullptr), ev1_(nullptr)
 {
     TimingState& t = timing();
     std::lock_guard<std::mutex> lk(t.mu);
     if (!t.enabled) return;
-    hipEvent_t e = take_event(t);
-    if (e && hipEventRecord(e, s) == hipSuccess) ev0_ = e;
+    hipEvent_t a = take_event(t), b = take_event(t);
+    if (!a || !b || hipEventRecord(a, s) != hipSuccess) {
+        if (a) t.pool.push_back(a);
+        if (b) t.pool.push_back(b);
+        return;
+    }
+    ev0_ = a;
+    ev1_ = b;
 }
 
 StageScope::~StageScope()
 {
     if (!ev0_) return;
+    hipEvent_t b = (hipEvent_t)ev1_;
+    const bool ok = hipEventRecord(b, s_) == hipSuccess;
     TimingState& t = timing();
     std::lock_guard<std::mutex> lk(t.mu);
-    hipEvent_t e = take_event(t);
-    if (e && hipEventRecord(e, s_) == hipSuccess) t.recs.push_back({stage_, (hipEvent_t)ev0_, e});
+    if (ok) t.recs.push_back({stage_, (hipEvent_t)ev0_, b});
+    else {
+        t.pool.push_back((hipEvent_t)ev0_);
+        t.pool.push_back(b);
+    }
 }
 
 }  // namespace vm
@@ -224,9 +238,7 @@ vm_status vm_map_create(const vm_map_desc* d, vm_map* out)
     auto A = [&](void** p, size_t bytes) {
         if (st == VM_OK) st = map_alloc(m, p, bytes);
     };
-    A((void**)&m->h.key, cap * 4);
-    A((void**)&m->h.cnt, cap * 4);
-    A((void**)&m->h.sum, cap * 3 * 8);
+    A((void**)&m->h.slot, cap * sizeof(Slot));
     m->h.log2cap = d->hash_capacity_log2;
     m->h.mask = m->cap - 1;
     A((void**)&m->bits, (size_t)m->g.nwords * 4);
@@ -392,7 +404,7 @@ vm_status vm_segment_frame(vm_map m, const float* d_xyz, int64_t n, const vm_pos
     if (check_planes(planes, params->ransac.n_hyp) != VM_OK || check_hulls(hulls_out) != VM_OK) return VM_E_ARG;
     if (n < 0 || (n > 0 && !d_xyz) || !finite_pose(pose)) return VM_E_ARG;
     const uint32_t minc = params->min_cluster < 1 ? 1 : params->min_cluster;
-    const uint32_t kb = std::min(map_k_bound(m, minc), std::min(planes->k_cap, hulls_out->k_cap));
+    const uint32_t kb = std::min(map_k_bound(m, minc), planes->k_cap);
     // the map's own workspace: allocated once per (cluster bound, hypotheses)
     if (!m->work || m->work_k < kb || m->work_hyp < params->ransac.n_hyp) {
         const uint32_t k = std::max(kb, m->work_k);
@@ -428,6 +440,12 @@ vm_status vm_set_stage_timing(int32_t enable)
     TimingState& t = timing();
     std::lock_guard<std::mutex> lk(t.mu);
     t.enabled = enable != 0;
+    // events are created here, outside any timed span
+    while (t.enabled && t.pool.size() < 1024) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return VM_E_DEVICE;
+        t.pool.push_back(e);
+    }
     return VM_OK;
 }
 

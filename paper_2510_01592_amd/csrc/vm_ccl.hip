@@ -24,14 +24,19 @@
 namespace vm {
 namespace {
 
-__device__ __forceinline__ uint32_t ld_agent(const uint32_t* p)
+// Parent pointers are read and path-halved through the ordinary caches.  A
+// stale value is still an ancestor (parents only ever move to smaller ranks
+// of the same component), so finds stay correct; only the hook itself needs a
+// device-coherent CAS.  Relaxed atomics keep the compiler from caching or
+// tearing the accesses.
+__device__ __forceinline__ uint32_t ld_parent(const uint32_t* p)
 {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
 }
 
-__device__ __forceinline__ void st_agent(uint32_t* p, uint32_t v)
+__device__ __forceinline__ void st_parent(uint32_t* p, uint32_t v)
 {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
 }
 
 __device__ __forceinline__ bool occ(const uint32_t* __restrict__ bits, uint32_t key)
@@ -50,13 +55,13 @@ __device__ __forceinline__ uint32_t rank_of(const uint32_t* __restrict__ bits, c
 // grandparent; concurrent writes only ever store an ancestor).
 __device__ __forceinline__ uint32_t uf_find(uint32_t* parent, uint32_t x)
 {
-    uint32_t p = ld_agent(&parent[x]);
+    uint32_t p = ld_parent(&parent[x]);
     while (p != x) {
-        const uint32_t g = ld_agent(&parent[p]);
+        const uint32_t g = ld_parent(&parent[p]);
         if (g == p) return p;
-        st_agent(&parent[x], g);
+        st_parent(&parent[x], g);
         x = g;
-        p = ld_agent(&parent[x]);
+        p = ld_parent(&parent[x]);
     }
     return x;
 }
@@ -140,11 +145,21 @@ __global__ void __launch_bounds__(kBlock) k_ccl_merge(const uint32_t* __restrict
     }
 }
 
+// After the merge every tree is final.  Each voxel walks to its root without
+// writing anything on the way (a path-halving store here could overwrite the
+// root another thread has just stored for that node) and stores only its own
+// entry; every value a walk can read is an ancestor, so walks stay correct.
 __global__ void __launch_bounds__(kBlock) k_ccl_flatten(const DevCounters* __restrict__ ctr, uint32_t* parent)
 {
     const uint32_t V = ctr->n_occ;
-    for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < V; r += gridDim.x * blockDim.x)
-        parent[r] = uf_find(parent, r);
+    for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < V; r += gridDim.x * blockDim.x) {
+        uint32_t x = r, p = ld_parent(&parent[r]);
+        while (p != x) {
+            x = p;
+            p = ld_parent(&parent[x]);
+        }
+        st_parent(&parent[r], x);
+    }
 }
 
 // Component sizes at the roots.  Consecutive ranks mostly share a root, so a
@@ -247,17 +262,16 @@ __global__ void __launch_bounds__(kBlock) k_group_gather(Geom g, Hash h, const D
                                                          float* __restrict__ cl_y, float* __restrict__ cl_z)
 {
     const uint32_t n = ctr->meta[1];
-    const uint32_t hc = h.mask + 1;
     const uint32_t nx = (uint32_t)g.dims[0], ny = (uint32_t)g.dims[1];
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         const uint32_t k = occ_key[sorted_rank[i]];
         const uint32_t s = hash_find(h, k);
         float mx = 0.0f, my = 0.0f, mz = 0.0f;
         if (s != kEmpty) {
-            const uint32_t c = h.cnt[s];
-            mx = voxel_mean_axis(k % nx, h.sum[s], c, g.voxel_size, g.origin[0]);
-            my = voxel_mean_axis((k / nx) % ny, h.sum[hc + s], c, g.voxel_size, g.origin[1]);
-            mz = voxel_mean_axis(k / (nx * ny), h.sum[2 * (size_t)hc + s], c, g.voxel_size, g.origin[2]);
+            const Slot sl = h.slot[s];
+            mx = voxel_mean_axis(k % nx, sl.sum[0], sl.cnt, g.voxel_size, g.origin[0]);
+            my = voxel_mean_axis((k / nx) % ny, sl.sum[1], sl.cnt, g.voxel_size, g.origin[1]);
+            mz = voxel_mean_axis(k / (nx * ny), sl.sum[2], sl.cnt, g.voxel_size, g.origin[2]);
         }
         cl_key[i] = k;
         cl_x[i] = mx;

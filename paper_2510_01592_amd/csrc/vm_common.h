@@ -42,12 +42,18 @@ struct Pose {
     double t[3];
 };
 
-// Open-addressing hash over voxel keys with linear probing.  Keys and the
-// payload are separate arrays: probes touch only the dense key array.
+// One voxel of the hash: key, point count and the three fixed-point offset
+// sums in one 32-byte slot, so a point's probe and its four atomics hit one
+// memory sector.
+struct __align__(32) Slot {
+    uint32_t key;
+    uint32_t cnt;
+    unsigned long long sum[3];
+};
+
+// Open-addressing hash over voxel keys with linear probing.
 struct Hash {
-    uint32_t* key;            // [cap]
-    uint32_t* cnt;            // [cap]
-    unsigned long long* sum;  // [3][cap] (x sums, then y, then z)
+    Slot* slot;               // [cap]
     uint32_t log2cap;
     uint32_t mask;
 };
@@ -63,7 +69,7 @@ __device__ __forceinline__ uint32_t hash_find(const Hash& h, uint32_t key)
 {
     uint32_t s = hash_slot(key, h.log2cap);
     for (uint32_t p = 0; p < kMaxProbe && p <= h.mask; ++p) {
-        const uint32_t k = h.key[s];
+        const uint32_t k = h.slot[s].key;
         if (k == key) return s;
         if (k == kEmpty) return kEmpty;
         s = (s + 1) & h.mask;
@@ -133,6 +139,7 @@ struct StageScope {
     int stage_;
     hipStream_t s_;
     void* ev0_;
+    void* ev1_;
 };
 
 // ---- launch helpers ----------------------------------------------------
@@ -183,6 +190,7 @@ hipError_t launch_group(const Geom& g, const Hash& h, SegBuffers& b, uint32_t ca
 
 // ---- RANSAC and hulls (vm_ransac.hip, vm_hull.hip) --------------------------
 struct WorkLayout {
+    uint32_t k_cap;         // clusters the layout was made for
     int32_t* counts;        // [k_cap * H]
     float4* hyp;            // [k_cap * H]
     uint32_t* tile_off;     // [k_cap + 1]
@@ -194,10 +202,16 @@ struct WorkLayout {
     double* hull_u;         // [n_cap]
     double* hull_v;         // [n_cap]
     uint32_t* hull_i;       // [n_cap]
-    uint32_t* small;        // [64] misc device scalars
+    uint32_t* hull_tile_off;  // [k_cap + 2]
+    double* ext_v;          // [hull tiles * 8]
+    uint32_t* ext_i;        // [hull tiles * 8]
+    double* poly;           // [k_cap * 18]
+    uint32_t* surv_cnt;     // [k_cap]
+    uint32_t* small;        // [64] device scalars: K, tiles, inliers, -, K (hull), vertices, hull tiles
     size_t bytes;
 };
 WorkLayout work_layout(void* base, uint32_t k_cap, uint32_t n_cap, uint32_t n_hyp);
+uint64_t hull_tiles_bound(uint32_t k_cap, uint32_t n_cap);
 
 vm_status ransac_planes(const vm_clusters& cl, const vm_ransac_params& p, const vm_planes& out,
                         const WorkLayout& w, hipStream_t s);

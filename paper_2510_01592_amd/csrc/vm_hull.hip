@@ -1,20 +1,25 @@
 // vm_hull.hip -- boundary polygons (Sec. III-C, "Boundary polygon
 // generation"): the convex hull of each plane's inliers, in the plane.
 //
-// The paper filters most points on the GPU and finishes the hull on the CPU
-// from the few candidates left.  Here the whole hull stays on the device, one
-// workgroup per cluster:
-//   1. project the inliers onto an orthonormal in-plane basis (fp64);
-//   2. find the extreme inlier in each of 8 directions (every 45 degrees);
-//      these are hull points, and the convex polygon through them lies inside
-//      the hull, so any point strictly inside it (by a margin far above the
-//      fp64 rounding of the test) cannot be a hull vertex and is dropped;
-//   3. sort the survivors by (u, v, inlier index) -- bitonic in LDS, or in
-//      global memory for very large survivor sets;
-//   4. Andrew's monotone chain over the survivors, popping on every non-left
-//      turn (strictly convex output, counter-clockwise from the smallest point).
-// A second pass packs the polygons into the caller's CSR and projects each
-// vertex onto the plane.
+// The paper filters most points on the GPU and finishes each hull on the CPU
+// from the few candidates left.  Here the whole hull stays on the device and
+// every pass over the inliers is tile-parallel, so one huge cluster (a floor)
+// spreads over the whole chip instead of one workgroup:
+//   B. per tile of inliers: project onto the in-plane basis (fp64) and find
+//      the extreme inlier in each of 8 directions (every 45 degrees);
+//   C. per cluster: combine the tiles' extremes; the convex polygon through
+//      them lies inside the hull, so a point strictly inside it (by a margin
+//      far above the fp64 rounding of the test) cannot be a hull vertex;
+//   D. per tile: keep only the points not strictly inside that polygon
+//      (block-aggregated compaction into the cluster's own region);
+//   E. per cluster: sort the survivors by (u, v, inlier index) -- bitonic in
+//      LDS, or in global memory for very large survivor sets -- and run
+//      Andrew's monotone chain, popping on every non-left turn (strictly
+//      convex, counter-clockwise from the smallest point).  In LDS the lower
+//      and the upper chain run on two lanes at once; joined at their shared
+//      end points they give exactly the single-stack chain's output;
+//   F. scan the vertex counts and pack the polygons, each vertex projected
+//      onto the plane.
 #include "vm_common.h"
 
 #include <math.h>
@@ -22,13 +27,11 @@
 namespace vm {
 namespace {
 
-constexpr int kHullBlock = 512;
-constexpr int kLdsCap = 2048;   // survivors sorted in LDS; more go through global memory
-
-struct P2 {
-    double u, v;
-    uint32_t i;
-};
+constexpr int kTileThreads = 256;
+constexpr int kTileItems = 4;
+constexpr int kHullTile = kTileThreads * kTileItems;   // inliers per tile
+constexpr int kChainBlock = 256;
+constexpr int kLdsCap = 2048;                           // survivors sorted in LDS
 
 __device__ __forceinline__ bool p2_less(double au, double av, uint32_t ai, double bu, double bv, uint32_t bi)
 {
@@ -43,28 +46,26 @@ __device__ __forceinline__ double cross3(double ou, double ov, double au, double
 }
 
 struct Basis {
-    double u[3], v[3], n[3];
+    double u[3], v[3];
 };
 
 __device__ __forceinline__ Basis plane_basis(float4 pl)
 {
     Basis b;
-    b.n[0] = pl.x;
-    b.n[1] = pl.y;
-    b.n[2] = pl.z;
+    const double n0 = pl.x, n1 = pl.y, n2 = pl.z;
     double a[3] = {0.0, 0.0, 0.0};
-    if (fabs(b.n[0]) < 0.9) a[0] = 1.0;
+    if (fabs(n0) < 0.9) a[0] = 1.0;
     else a[1] = 1.0;
-    const double c0 = a[1] * b.n[2] - a[2] * b.n[1];
-    const double c1 = a[2] * b.n[0] - a[0] * b.n[2];
-    const double c2 = a[0] * b.n[1] - a[1] * b.n[0];
+    const double c0 = a[1] * n2 - a[2] * n1;
+    const double c1 = a[2] * n0 - a[0] * n2;
+    const double c2 = a[0] * n1 - a[1] * n0;
     const double inv = 1.0 / sqrt(c0 * c0 + c1 * c1 + c2 * c2);
     b.u[0] = c0 * inv;
     b.u[1] = c1 * inv;
     b.u[2] = c2 * inv;
-    b.v[0] = b.n[1] * b.u[2] - b.n[2] * b.u[1];
-    b.v[1] = b.n[2] * b.u[0] - b.n[0] * b.u[2];
-    b.v[2] = b.n[0] * b.u[1] - b.n[1] * b.u[0];
+    b.v[0] = n1 * b.u[2] - n2 * b.u[1];
+    b.v[1] = n2 * b.u[0] - n0 * b.u[2];
+    b.v[2] = n0 * b.u[1] - n1 * b.u[0];
     return b;
 }
 
@@ -83,80 +84,120 @@ __device__ __forceinline__ double dir_val(int d, double u, double v)
     }
 }
 
-__global__ void __launch_bounds__(kBlock) k_hull_k(const uint32_t* __restrict__ meta, uint32_t kc, uint32_t n_cap,
-                                                   const uint32_t* __restrict__ off, uint32_t* small,
-                                                   uint32_t* status)
+// per-cluster constants of the passes over inliers
+struct ClusterFrame {
+    uint32_t ib, m, pb, nk;   // inlier offset/count, point offset/count
+    Basis B;
+    double ox, oy, oz;        // origin = first inlier
+};
+
+// Whether cluster k gets a polygon: it has a plane, its inlier list fits the
+// output and indexes its own points.
+__device__ __forceinline__ bool cluster_ok(uint32_t k, const uint32_t* off, const int32_t* best,
+                                           const uint32_t* in_off, const uint32_t* in_idx, uint32_t in_cap)
+{
+    const uint32_t ib = in_off[k], ie = in_off[k + 1];
+    if (best[k] < 0 || ie <= ib || ie > in_cap) return false;
+    return in_idx[ib] < off[k + 1] - off[k];
+}
+
+__device__ __forceinline__ ClusterFrame cluster_frame(uint32_t k, const uint32_t* off, const float* X, const float* Y,
+                                                      const float* Z, const float4* plane, const uint32_t* in_off,
+                                                      const uint32_t* in_idx)
+{
+    ClusterFrame f;
+    f.ib = in_off[k];
+    f.m = in_off[k + 1] - f.ib;
+    f.pb = off[k];
+    f.nk = off[k + 1] - f.pb;
+    f.B = plane_basis(plane[k]);
+    const uint32_t i0 = f.pb + in_idx[f.ib];
+    f.ox = X[i0];
+    f.oy = Y[i0];
+    f.oz = Z[i0];
+    return f;
+}
+
+__device__ __forceinline__ void project(const ClusterFrame& f, float x, float y, float z, double* pu, double* pv)
+{
+    const double dx = (double)x - f.ox, dy = (double)y - f.oy, dz = (double)z - f.oz;
+    *pu = f.B.u[0] * dx + f.B.u[1] * dy + f.B.u[2] * dz;
+    *pv = f.B.v[0] * dx + f.B.v[1] * dy + f.B.v[2] * dz;
+}
+
+// largest k with tile_off[k] <= t (tile_off is an exclusive scan of K entries)
+__device__ __forceinline__ uint32_t cluster_of_tile(const uint32_t* __restrict__ tile_off, uint32_t K, uint32_t t)
+{
+    uint32_t lo = 0, hi = K;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (tile_off[mid] <= t) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// tiles of cluster k: [tile_off[k], end)
+__device__ __forceinline__ uint32_t tiles_end(const uint32_t* tile_off, uint32_t k, uint32_t K, uint32_t total)
+{
+    return k + 1 < K ? tile_off[k + 1] : total;
+}
+
+// ---- A: validate, tiles per cluster ------------------------------------------
+__global__ void __launch_bounds__(kBlock) k_hull_validate(const uint32_t* __restrict__ meta, uint32_t kc,
+                                                          uint32_t n_cap, const uint32_t* __restrict__ off,
+                                                          uint32_t* small, uint32_t* status)
 {
     __shared__ int bad;
     const uint32_t K = validate_clusters(meta, off, kc, n_cap, status, &bad);
     if (threadIdx.x == 0) small[4] = K;
 }
 
-__global__ void __launch_bounds__(kHullBlock) k_hull(const uint32_t* __restrict__ small,
-                                                     const uint32_t* __restrict__ off, const float* __restrict__ X,
-                                                     const float* __restrict__ Y, const float* __restrict__ Z,
-                                                     const int32_t* __restrict__ best, const float4* __restrict__ plane,
-                                                     const uint32_t* __restrict__ in_off,
-                                                     const uint32_t* __restrict__ in_idx, uint32_t in_cap,
-                                                     uint32_t* __restrict__ hull_cnt, uint32_t* __restrict__ hull_tmp,
-                                                     double* __restrict__ gu, double* __restrict__ gv,
-                                                     uint32_t* __restrict__ gi, double* __restrict__ area_out,
-                                                     uint32_t* __restrict__ status)
+__global__ void __launch_bounds__(kBlock) k_hull_tiles(const uint32_t* __restrict__ small,
+                                                       const uint32_t* __restrict__ off,
+                                                       const int32_t* __restrict__ best,
+                                                       const uint32_t* __restrict__ in_off,
+                                                       const uint32_t* __restrict__ in_idx, uint32_t in_cap,
+                                                       uint32_t* __restrict__ ntiles, uint32_t* __restrict__ status)
 {
-    __shared__ double su[kLdsCap];
-    __shared__ double sv[kLdsCap];
-    __shared__ uint32_t si[kLdsCap];
-    __shared__ uint16_t stk[kLdsCap + 2];
-    __shared__ double red_val[kHullBlock / kWave][8];
-    __shared__ uint32_t red_idx[kHullBlock / kWave][8];
-    __shared__ double poly_u[8], poly_v[8];
-    __shared__ int npoly;
-    __shared__ uint32_t nsurv;
-    __shared__ double margin;
-
     const uint32_t K = small[4];
+    for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < K; k += gridDim.x * blockDim.x) {
+        const bool ok = cluster_ok(k, off, best, in_off, in_idx, in_cap);
+        ntiles[k] = ok ? (in_off[k + 1] - in_off[k] + kHullTile - 1) / kHullTile : 0u;
+        if (best[k] >= 0 && in_off[k + 1] > in_cap) atomicOr(status, (uint32_t)VM_FLAG_INLIERS_CAP);
+    }
+}
+
+// ---- B: projection + 8 directional extremes per tile ------------------------------
+__global__ void __launch_bounds__(kTileThreads) k_hull_extremes(
+    const uint32_t* __restrict__ small, const uint32_t* __restrict__ tile_off, const uint32_t* __restrict__ off,
+    const float* __restrict__ X, const float* __restrict__ Y, const float* __restrict__ Z,
+    const float4* __restrict__ plane, const uint32_t* __restrict__ in_off, const uint32_t* __restrict__ in_idx,
+    double* __restrict__ ext_v, uint32_t* __restrict__ ext_i)
+{
+    __shared__ double rv[kTileThreads / kWave][8];
+    __shared__ uint32_t ri[kTileThreads / kWave][8];
+    const uint32_t K = small[4];
+    const uint32_t T = small[6];
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-
-    for (uint32_t k = blockIdx.x; k < K; k += gridDim.x) {
-        const uint32_t ib = in_off[k], ie = in_off[k + 1];
-        if (best[k] < 0 || ie <= ib || ie > in_cap) {
-            if (threadIdx.x == 0) {
-                hull_cnt[k] = 0;
-                area_out[k] = 0.0;
-                if (best[k] >= 0 && ie > in_cap) atomicOr(status, (uint32_t)VM_FLAG_INLIERS_CAP);
-            }
-            continue;
-        }
-        const uint32_t m = ie - ib;
-        const uint32_t pb = off[k];
-        const uint32_t nk = off[k + 1] - pb;
-        if (in_idx[ib] >= nk) {   // inlier lists must index the cluster's own points
-            if (threadIdx.x == 0) {
-                hull_cnt[k] = 0;
-                area_out[k] = 0.0;
-            }
-            continue;
-        }
-        const Basis B = plane_basis(plane[k]);
-        const uint32_t i0 = pb + in_idx[ib];
-        const double ox = X[i0], oy = Y[i0], oz = Z[i0];
-
-        // ---- 1+2a: extreme points in 8 directions --------------------------------
+    for (uint32_t t = blockIdx.x; t < T; t += gridDim.x) {
+        const uint32_t k = cluster_of_tile(tile_off, K, t);
+        const ClusterFrame f = cluster_frame(k, off, X, Y, Z, plane, in_off, in_idx);
+        const uint32_t j0 = (t - tile_off[k]) * kHullTile, j1 = min(j0 + kHullTile, f.m);
         double bv[8];
         uint32_t bi[8];
 #pragma unroll
         for (int d = 0; d < 8; ++d) { bv[d] = -INFINITY; bi[d] = 0xFFFFFFFFu; }
-        for (uint32_t j = threadIdx.x; j < m; j += kHullBlock) {
-            const uint32_t li = in_idx[ib + j];
-            if (li >= nk) continue;
-            const uint32_t i = pb + li;
-            const double dx = (double)X[i] - ox, dy = (double)Y[i] - oy, dz = (double)Z[i] - oz;
-            const double pu = B.u[0] * dx + B.u[1] * dy + B.u[2] * dz;
-            const double pv = B.v[0] * dx + B.v[1] * dy + B.v[2] * dz;
+        for (uint32_t j = j0 + threadIdx.x; j < j1; j += kTileThreads) {
+            const uint32_t li = in_idx[f.ib + j];
+            if (li >= f.nk) continue;
+            const uint32_t i = f.pb + li;
+            double pu, pv;
+            project(f, X[i], Y[i], Z[i], &pu, &pv);
 #pragma unroll
             for (int d = 0; d < 8; ++d) {
-                const double f = dir_val(d, pu, pv);
-                if (f > bv[d] || (f == bv[d] && j < bi[d])) { bv[d] = f; bi[d] = j; }
+                const double v = dir_val(d, pu, pv);
+                if (v > bv[d]) { bv[d] = v; bi[d] = j; }   // j ascends per thread: first maximum kept
             }
         }
 #pragma unroll
@@ -166,194 +207,318 @@ __global__ void __launch_bounds__(kHullBlock) k_hull(const uint32_t* __restrict_
                 const uint32_t oi = __shfl_xor(bi[d], s, kWave);
                 if (ov > bv[d] || (ov == bv[d] && oi < bi[d])) { bv[d] = ov; bi[d] = oi; }
             }
-            if (lane == 0) { red_val[wave][d] = bv[d]; red_idx[wave][d] = bi[d]; }
+            if (lane == 0) { rv[wave][d] = bv[d]; ri[wave][d] = bi[d]; }
         }
         __syncthreads();
-        if (threadIdx.x == 0) {
-            uint32_t e[8];
-            for (int d = 0; d < 8; ++d) {
-                double v = red_val[0][d];
-                uint32_t ix = red_idx[0][d];
-                for (int w = 1; w < kHullBlock / kWave; ++w)
-                    if (red_val[w][d] > v || (red_val[w][d] == v && red_idx[w][d] < ix)) { v = red_val[w][d]; ix = red_idx[w][d]; }
-                e[d] = ix;
+        if (threadIdx.x < 8) {
+            const int d = threadIdx.x;
+            double v = rv[0][d];
+            uint32_t ix = ri[0][d];
+            for (int w = 1; w < kTileThreads / kWave; ++w)
+                if (rv[w][d] > v || (rv[w][d] == v && ri[w][d] < ix)) { v = rv[w][d]; ix = ri[w][d]; }
+            ext_v[8 * (size_t)t + d] = v;
+            ext_i[8 * (size_t)t + d] = ix;
+        }
+        __syncthreads();
+    }
+}
+
+// ---- C: per-cluster extreme polygon -----------------------------------------------
+// poly layout per cluster (18 doubles): u[8], v[8], margin, vertex count
+// (-1: no polygon for the cluster, 0: no filtering)
+__global__ void __launch_bounds__(kWave) k_hull_poly(const uint32_t* __restrict__ small,
+                                                     const uint32_t* __restrict__ tile_off,
+                                                     const uint32_t* __restrict__ off, const float* __restrict__ X,
+                                                     const float* __restrict__ Y, const float* __restrict__ Z,
+                                                     const float4* __restrict__ plane,
+                                                     const uint32_t* __restrict__ in_off,
+                                                     const uint32_t* __restrict__ in_idx,
+                                                     const double* __restrict__ ext_v,
+                                                     const uint32_t* __restrict__ ext_i, double* __restrict__ poly,
+                                                     uint32_t* __restrict__ surv_cnt)
+{
+    const uint32_t K = small[4];
+    const uint32_t T = small[6];
+    const int lane = threadIdx.x;
+    for (uint32_t k = blockIdx.x; k < K; k += gridDim.x) {
+        const uint32_t t0 = tile_off[k], t1 = tiles_end(tile_off, k, K, T);
+        if (lane == 0) surv_cnt[k] = 0;
+        double* P = poly + 18 * (size_t)k;
+        if (t0 == t1) {
+            if (lane == 0) P[17] = -1.0;
+            continue;
+        }
+        // lane d < 8 reduces direction d over the cluster's tiles
+        double v = -INFINITY;
+        uint32_t ix = 0xFFFFFFFFu;
+        if (lane < 8) {
+            for (uint32_t t = t0; t < t1; ++t) {
+                const double tv = ext_v[8 * (size_t)t + lane];
+                const uint32_t ti = ext_i[8 * (size_t)t + lane];
+                if (tv > v || (tv == v && ti < ix)) { v = tv; ix = ti; }
             }
-            // distinct extreme points in CCW order
+        }
+        uint32_t e[8];
+#pragma unroll
+        for (int d = 0; d < 8; ++d) e[d] = __shfl(ix, d, kWave);
+        if (lane == 0) {
+            const ClusterFrame f = cluster_frame(k, off, X, Y, Z, plane, in_off, in_idx);
             int np = 0;
             uint32_t q[8];
             bool found = true;
-            for (int d = 0; d < 8; ++d) found = found && e[d] < m;
+            for (int d = 0; d < 8; ++d) found = found && e[d] < f.m;
             for (int d = 0; found && d < 8; ++d)
                 if (np == 0 || q[np - 1] != e[d]) q[np++] = e[d];
             while (np > 1 && q[np - 1] == q[0]) --np;
+            double pu[8], pv[8];
             double umin = INFINITY, umax = -INFINITY, vmin = INFINITY, vmax = -INFINITY;
             for (int a = 0; a < np; ++a) {
-                const uint32_t i = pb + in_idx[ib + q[a]];
-                const double dx = (double)X[i] - ox, dy = (double)Y[i] - oy, dz = (double)Z[i] - oz;
-                poly_u[a] = B.u[0] * dx + B.u[1] * dy + B.u[2] * dz;
-                poly_v[a] = B.v[0] * dx + B.v[1] * dy + B.v[2] * dz;
-                umin = fmin(umin, poly_u[a]); umax = fmax(umax, poly_u[a]);
-                vmin = fmin(vmin, poly_v[a]); vmax = fmax(vmax, poly_v[a]);
+                const uint32_t i = f.pb + in_idx[f.ib + q[a]];
+                project(f, X[i], Y[i], Z[i], &pu[a], &pv[a]);
+                umin = fmin(umin, pu[a]);
+                umax = fmax(umax, pu[a]);
+                vmin = fmin(vmin, pv[a]);
+                vmax = fmax(vmax, pv[a]);
             }
-            const double span = fmax(umax - umin, vmax - vmin);
-            // margin: far above fp64 rounding of a cross product at this scale
-            margin = 1e-9 * span * span + 1e-300;
+            const double span = np > 0 ? fmax(umax - umin, vmax - vmin) : 0.0;
+            // far above the fp64 rounding of a cross product at this scale
+            const double margin = 1e-9 * span * span + 1e-300;
             bool convex = np >= 3;
             for (int a = 0; convex && a < np; ++a) {
-                const int b2 = (a + 1) % np, c2 = (a + 2) % np;
-                if (cross3(poly_u[a], poly_v[a], poly_u[b2], poly_v[b2], poly_u[c2], poly_v[c2]) <= margin) convex = false;
+                const int b = (a + 1) % np, c = (a + 2) % np;
+                if (cross3(pu[a], pv[a], pu[b], pv[b], pu[c], pv[c]) <= margin) convex = false;
             }
-            npoly = convex ? np : 0;
-            nsurv = 0;
+            for (int a = 0; a < 8; ++a) {
+                P[a] = a < np ? pu[a] : 0.0;
+                P[8 + a] = a < np ? pv[a] : 0.0;
+            }
+            P[16] = margin;
+            P[17] = convex ? (double)np : 0.0;
         }
-        __syncthreads();
+    }
+}
 
-        // ---- 2b: survivors (not strictly inside the extreme polygon) ------------------
-        const int np = npoly;
-        const double mg = margin;
-        for (uint32_t j = threadIdx.x; j < m; j += kHullBlock) {
-            const uint32_t li = in_idx[ib + j];
-            if (li >= nk) continue;
-            const uint32_t i = pb + li;
-            const double dx = (double)X[i] - ox, dy = (double)Y[i] - oy, dz = (double)Z[i] - oz;
-            const double pu = B.u[0] * dx + B.u[1] * dy + B.u[2] * dz;
-            const double pv = B.v[0] * dx + B.v[1] * dy + B.v[2] * dz;
+// ---- D: survivors of the polygon test, compacted per cluster ---------------------
+__global__ void __launch_bounds__(kTileThreads) k_hull_filter(
+    const uint32_t* __restrict__ small, const uint32_t* __restrict__ tile_off, const uint32_t* __restrict__ off,
+    const float* __restrict__ X, const float* __restrict__ Y, const float* __restrict__ Z,
+    const float4* __restrict__ plane, const uint32_t* __restrict__ in_off, const uint32_t* __restrict__ in_idx,
+    const double* __restrict__ poly, uint32_t* __restrict__ surv_cnt, double* __restrict__ gu,
+    double* __restrict__ gv, uint32_t* __restrict__ gi)
+{
+    __shared__ double P[18];
+    __shared__ uint32_t lcount, lbase;
+    const uint32_t K = small[4];
+    const uint32_t T = small[6];
+    for (uint32_t t = blockIdx.x; t < T; t += gridDim.x) {
+        const uint32_t k = cluster_of_tile(tile_off, K, t);
+        if (threadIdx.x < 18) P[threadIdx.x] = poly[18 * (size_t)k + threadIdx.x];
+        if (threadIdx.x == 0) lcount = 0;
+        __syncthreads();
+        const ClusterFrame f = cluster_frame(k, off, X, Y, Z, plane, in_off, in_idx);
+        const uint32_t j0 = (t - tile_off[k]) * kHullTile;
+        const int np = (int)P[17];
+        const double mg = P[16];
+        double su[kTileItems], sv[kTileItems];
+        uint32_t sj[kTileItems], slot[kTileItems];
+        int ns = 0;
+#pragma unroll
+        for (int it = 0; it < kTileItems; ++it) {
+            const uint32_t j = j0 + it * kTileThreads + threadIdx.x;
+            if (j >= f.m) continue;
+            const uint32_t li = in_idx[f.ib + j];
+            if (li >= f.nk) continue;
+            const uint32_t i = f.pb + li;
+            double pu, pv;
+            project(f, X[i], Y[i], Z[i], &pu, &pv);
             bool inside = np >= 3;
             for (int a = 0; inside && a < np; ++a) {
-                const int b2 = (a + 1 == np) ? 0 : a + 1;
-                inside = cross3(poly_u[a], poly_v[a], poly_u[b2], poly_v[b2], pu, pv) > mg;
+                const int b = (a + 1 == np) ? 0 : a + 1;
+                inside = cross3(P[a], P[8 + a], P[b], P[8 + b], pu, pv) > mg;
             }
             if (!inside) {
-                const uint32_t slot = atomicAdd(&nsurv, 1u);
-                gu[ib + slot] = pu;
-                gv[ib + slot] = pv;
-                gi[ib + slot] = j;
+                su[ns] = pu;
+                sv[ns] = pv;
+                sj[ns] = j;
+                slot[ns] = atomicAdd(&lcount, 1u);
+                ++ns;
             }
         }
         __syncthreads();
-        const uint32_t ns = nsurv;
+        if (threadIdx.x == 0) lbase = lcount ? atomicAdd(&surv_cnt[k], lcount) : 0u;
+        __syncthreads();
+        for (int a = 0; a < ns; ++a) {
+            const uint32_t dst = f.ib + lbase + slot[a];
+            gu[dst] = su[a];
+            gv[dst] = sv[a];
+            gi[dst] = sj[a];
+        }
+        __syncthreads();
+    }
+}
 
-        // ---- 3: sort survivors by (u, v, index) -------------------------------------------
-        double* Su;
-        double* Sv;
-        uint32_t* Si;
+// ---- E: sort + monotone chain per cluster ------------------------------------------
+__device__ __forceinline__ void swap3(double* U, double* V, uint32_t* I, uint32_t a, uint32_t b)
+{
+    const double tu = U[a], tv = V[a];
+    const uint32_t ti = I[a];
+    U[a] = U[b];
+    V[a] = V[b];
+    I[a] = I[b];
+    U[b] = tu;
+    V[b] = tv;
+    I[b] = ti;
+}
+
+// one monotone chain over n sorted points (forward: lower chain, backward:
+// upper chain) into stack st; returns its length
+template <typename S>
+__device__ __forceinline__ uint32_t chain(const double* U, const double* V, uint32_t n, bool forward, S* st)
+{
+    uint32_t h = 0;
+    for (uint32_t s = 0; s < n; ++s) {
+        const uint32_t i = forward ? s : n - 1 - s;
+        while (h >= 2) {
+            const uint32_t a = st[h - 2], b = st[h - 1];
+            if (cross3(U[a], V[a], U[b], V[b], U[i], V[i]) <= 0.0) --h;
+            else break;
+        }
+        st[h++] = (S)i;
+    }
+    return h;
+}
+
+__global__ void __launch_bounds__(kChainBlock) k_hull_chain(
+    const uint32_t* __restrict__ small, const uint32_t* __restrict__ tile_off, const uint32_t* __restrict__ in_off,
+    const uint32_t* __restrict__ in_idx, const uint32_t* __restrict__ surv_cnt, double* __restrict__ gu,
+    double* __restrict__ gv, uint32_t* __restrict__ gi, uint32_t* __restrict__ hull_cnt,
+    uint32_t* __restrict__ hull_tmp, double* __restrict__ area_out)
+{
+    __shared__ double su[kLdsCap];
+    __shared__ double sv[kLdsCap];
+    __shared__ uint32_t si[kLdsCap];
+    __shared__ uint16_t st_lo[2 * kLdsCap];
+    __shared__ uint16_t st_up[kLdsCap + 1];
+    __shared__ uint32_t hlo, hup;
+    const uint32_t K = small[4];
+    const uint32_t T = small[6];
+    for (uint32_t k = blockIdx.x; k < K; k += gridDim.x) {
+        if (tile_off[k] == tiles_end(tile_off, k, K, T)) {   // no polygon
+            if (threadIdx.x == 0) {
+                hull_cnt[k] = 0;
+                area_out[k] = 0.0;
+            }
+            continue;
+        }
+        const uint32_t ib = in_off[k];
+        const uint32_t ns = surv_cnt[k];
         if (ns <= (uint32_t)kLdsCap) {
             uint32_t N = 1;
             while (N < ns) N <<= 1;
-            for (uint32_t t = threadIdx.x; t < N; t += kHullBlock) {
-                if (t < ns) { su[t] = gu[ib + t]; sv[t] = gv[ib + t]; si[t] = gi[ib + t]; }
-                else { su[t] = INFINITY; sv[t] = INFINITY; si[t] = 0xFFFFFFFFu; }
+            for (uint32_t t = threadIdx.x; t < N; t += kChainBlock) {
+                if (t < ns) {
+                    su[t] = gu[ib + t];
+                    sv[t] = gv[ib + t];
+                    si[t] = gi[ib + t];
+                } else {
+                    su[t] = INFINITY;
+                    sv[t] = INFINITY;
+                    si[t] = 0xFFFFFFFFu;
+                }
             }
             __syncthreads();
             for (uint32_t size = 2; size <= N; size <<= 1) {
                 for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
-                    for (uint32_t t = threadIdx.x; t < N / 2; t += kHullBlock) {
-                        const uint32_t a = 2 * t - (t & (stride - 1));
-                        const uint32_t b2 = a + stride;
-                        const bool up = (a & size) == 0;
-                        const bool lt = p2_less(su[b2], sv[b2], si[b2], su[a], sv[a], si[a]);
-                        if (lt == up) {
-                            const double tu = su[a], tv = sv[a];
-                            const uint32_t ti = si[a];
-                            su[a] = su[b2]; sv[a] = sv[b2]; si[a] = si[b2];
-                            su[b2] = tu; sv[b2] = tv; si[b2] = ti;
-                        }
+                    for (uint32_t t = threadIdx.x; t < N / 2; t += kChainBlock) {
+                        const uint32_t a = 2 * t - (t & (stride - 1)), b = a + stride;
+                        const bool upw = (a & size) == 0;
+                        if (p2_less(su[b], sv[b], si[b], su[a], sv[a], si[a]) == upw) swap3(su, sv, si, a, b);
                     }
                     __syncthreads();
                 }
             }
-            Su = su; Sv = sv; Si = si;
+            if (threadIdx.x == 0) hlo = chain(su, sv, ns, true, st_lo);
+            if (threadIdx.x == kWave) hup = chain(su, sv, ns, false, st_up);
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                // hull = lower chain, then the upper chain without its end points
+                // (they are the lower chain's last and first points)
+                uint32_t h = hlo;
+                for (uint32_t q = 1; q + 1 < hup; ++q) st_lo[h++] = st_up[q];
+                double s = 0.0;
+                if (h >= 3) {
+                    for (uint32_t q = 0; q < h; ++q) {
+                        const uint32_t p0 = st_lo[q], p1 = st_lo[q + 1 == h ? 0 : q + 1];
+                        s = s + (su[p0] * sv[p1] - su[p1] * sv[p0]);
+                    }
+                }
+                area_out[k] = h >= 3 ? 0.5 * s : 0.0;
+                for (uint32_t q = 0; q < h; ++q) hull_tmp[ib + k + q] = in_idx[ib + si[st_lo[q]]];
+                hull_cnt[k] = h;
+            }
         } else {
-            // bitonic network on the survivors in global memory; partners beyond
-            // ns are +infinity and never move
+            // bitonic network in global memory; partners beyond ns are +infinity
             uint32_t N = 1;
             while (N < ns) N <<= 1;
             double* U = gu + ib;
             double* Vv = gv + ib;
             uint32_t* I = gi + ib;
             for (uint32_t size = 2; size <= N; size <<= 1) {
-                for (uint32_t t = threadIdx.x; t < N / 2; t += kHullBlock) {
+                for (uint32_t t = threadIdx.x; t < N / 2; t += kChainBlock) {
                     const uint32_t blk = t / (size >> 1), r = t % (size >> 1);
-                    const uint32_t a = blk * size + r, b2 = blk * size + size - 1 - r;
-                    if (b2 < ns && p2_less(U[b2], Vv[b2], I[b2], U[a], Vv[a], I[a])) {
-                        const double tu = U[a], tv = Vv[a];
-                        const uint32_t ti = I[a];
-                        U[a] = U[b2]; Vv[a] = Vv[b2]; I[a] = I[b2];
-                        U[b2] = tu; Vv[b2] = tv; I[b2] = ti;
-                    }
+                    const uint32_t a = blk * size + r, b = blk * size + size - 1 - r;
+                    if (b < ns && p2_less(U[b], Vv[b], I[b], U[a], Vv[a], I[a])) swap3(U, Vv, I, a, b);
                 }
                 __syncthreads();
                 for (uint32_t stride = size >> 2; stride > 0; stride >>= 1) {
-                    for (uint32_t t = threadIdx.x; t < N / 2; t += kHullBlock) {
-                        const uint32_t a = 2 * t - (t & (stride - 1));
-                        const uint32_t b2 = a + stride;
-                        if (b2 < ns && p2_less(U[b2], Vv[b2], I[b2], U[a], Vv[a], I[a])) {
-                            const double tu = U[a], tv = Vv[a];
-                            const uint32_t ti = I[a];
-                            U[a] = U[b2]; Vv[a] = Vv[b2]; I[a] = I[b2];
-                            U[b2] = tu; Vv[b2] = tv; I[b2] = ti;
-                        }
+                    for (uint32_t t = threadIdx.x; t < N / 2; t += kChainBlock) {
+                        const uint32_t a = 2 * t - (t & (stride - 1)), b = a + stride;
+                        if (b < ns && p2_less(U[b], Vv[b], I[b], U[a], Vv[a], I[a])) swap3(U, Vv, I, a, b);
                     }
                     __syncthreads();
                 }
             }
-            Su = U; Sv = Vv; Si = I;
-        }
-
-        // ---- 4: monotone chain (one lane) ------------------------------------------------
-        if (threadIdx.x == 0) {
-            const bool lds_stack = ns <= (uint32_t)kLdsCap;
-            // cluster k owns hull_tmp[ib + k, ib + k + m + 1): the chain's stack never
-            // holds more than (survivors + 1) <= m + 1 entries
-            uint32_t* gst = hull_tmp + ib + k;
-            auto st_get = [&](uint32_t q) -> uint32_t { return lds_stack ? (uint32_t)stk[q] : gst[q]; };
-            auto st_set = [&](uint32_t q, uint32_t v) {
-                if (lds_stack) stk[q] = (uint16_t)v;
-                else gst[q] = v;
-            };
-            uint32_t h = 0;
-            if (ns == 1) {
-                st_set(h++, 0);
-            } else {
+            if (threadIdx.x == 0) {
+                // single-stack chain; cluster k's stack is hull_tmp[ib + k, ib + k + m + 1)
+                // and never holds more than ns + 1 <= m + 1 entries
+                uint32_t* st = hull_tmp + ib + k;
+                uint32_t h = 0;
                 for (uint32_t i = 0; i < ns; ++i) {
                     while (h >= 2) {
-                        const uint32_t a = st_get(h - 2), b2 = st_get(h - 1);
-                        if (cross3(Su[a], Sv[a], Su[b2], Sv[b2], Su[i], Sv[i]) <= 0.0) --h;
+                        const uint32_t a = st[h - 2], b = st[h - 1];
+                        if (cross3(U[a], Vv[a], U[b], Vv[b], U[i], Vv[i]) <= 0.0) --h;
                         else break;
                     }
-                    st_set(h++, i);
+                    st[h++] = i;
                 }
                 const uint32_t lower = h + 1;
                 for (int32_t i = (int32_t)ns - 2; i >= 0; --i) {
                     while (h >= lower) {
-                        const uint32_t a = st_get(h - 2), b2 = st_get(h - 1);
-                        if (cross3(Su[a], Sv[a], Su[b2], Sv[b2], Su[i], Sv[i]) <= 0.0) --h;
+                        const uint32_t a = st[h - 2], b = st[h - 1];
+                        if (cross3(U[a], Vv[a], U[b], Vv[b], U[i], Vv[i]) <= 0.0) --h;
                         else break;
                     }
-                    st_set(h++, (uint32_t)i);
+                    st[h++] = (uint32_t)i;
                 }
-                --h;
-            }
-            double s = 0.0;
-            if (h >= 3) {
-                for (uint32_t q = 0; q < h; ++q) {
-                    const uint32_t a = st_get(q), b2 = st_get(q + 1 == h ? 0 : q + 1);
-                    s = s + (Su[a] * Sv[b2] - Su[b2] * Sv[a]);
+                --h;   // the last point repeats the first
+                double s = 0.0;
+                if (h >= 3) {
+                    for (uint32_t q = 0; q < h; ++q) {
+                        const uint32_t p0 = st[q], p1 = st[q + 1 == h ? 0 : q + 1];
+                        s = s + (U[p0] * Vv[p1] - U[p1] * Vv[p0]);
+                    }
                 }
+                area_out[k] = h >= 3 ? 0.5 * s : 0.0;
+                // entry q of the stack is read before slot q is overwritten
+                for (uint32_t q = 0; q < h; ++q) hull_tmp[ib + k + q] = in_idx[ib + I[st[q]]];
+                hull_cnt[k] = h;
             }
-            area_out[k] = h >= 3 ? 0.5 * s : 0.0;
-            // vertex list: cluster-local point indices (the stack is read before
-            // hull_tmp is overwritten, entry by entry in increasing order)
-            for (uint32_t q = 0; q < h; ++q) {
-                const uint32_t j = Si[st_get(q)];
-                hull_tmp[ib + k + q] = in_idx[ib + j];
-            }
-            hull_cnt[k] = h;
         }
         __syncthreads();
     }
 }
 
+// ---- F: pack --------------------------------------------------------------------------
 __global__ void __launch_bounds__(kBlock) k_hull_pack(const uint32_t* __restrict__ small,
                                                       const uint32_t* __restrict__ off, const float* __restrict__ X,
                                                       const float* __restrict__ Y, const float* __restrict__ Z,
@@ -377,7 +542,10 @@ __global__ void __launch_bounds__(kBlock) k_hull_pack(const uint32_t* __restrict
         const uint32_t ib = in_off[k], pb = off[k];
         for (uint32_t q = threadIdx.x; q < h; q += blockDim.x) {
             const uint32_t pos = base + q;
-            if (pos >= v_cap) { over = true; continue; }
+            if (pos >= v_cap) {
+                over = true;
+                continue;
+            }
             const uint32_t j = hull_tmp[ib + k + q];
             const double px = X[pb + j], py = Y[pb + j], pz = Z[pb + j];
             const double dist = nx * px + ny * py + nz * pz + d;
@@ -393,23 +561,41 @@ __global__ void __launch_bounds__(kBlock) k_hull_pack(const uint32_t* __restrict
 
 }  // namespace
 
+uint64_t hull_tiles_bound(uint32_t k_cap, uint32_t n_cap)
+{
+    return (uint64_t)n_cap / kHullTile + (uint64_t)k_cap + 2;
+}
+
 vm_status hulls(const vm_clusters& cl, const vm_planes& planes, const vm_hulls_out& out, const WorkLayout& w,
                 hipStream_t s)
 {
     uint32_t kc = cl.k_cap;
     if (planes.k_cap < kc) kc = planes.k_cap;
     if (out.k_cap < kc) kc = out.k_cap;
+    if (kc > w.k_cap) return VM_E_STATE;
     StageScope t(VM_STAGE_HULL, s);
-    k_hull_k<<<1, kBlock, 0, s>>>(cl.d_meta, kc, cl.n_cap, cl.d_off, w.small, out.d_status);
-    const int grid = kc < 4096 ? (int)(kc ? kc : 1) : 4096;
-    k_hull<<<grid, kHullBlock, 0, s>>>(w.small, cl.d_off, cl.d_x, cl.d_y, cl.d_z, planes.d_best_h,
-                                       (const float4*)planes.d_plane, planes.d_in_off, planes.d_in_idx, planes.in_cap,
-                                       w.hull_cnt, w.hull_tmp, w.hull_u, w.hull_v, w.hull_i, out.d_area, out.d_status);
+    const float4* pl = (const float4*)planes.d_plane;
+    k_hull_validate<<<1, kBlock, 0, s>>>(cl.d_meta, kc, cl.n_cap, cl.d_off, w.small, out.d_status);
+    k_hull_tiles<<<grid_for(kc), kBlock, 0, s>>>(w.small, cl.d_off, planes.d_best_h, planes.d_in_off,
+                                                 planes.d_in_idx, planes.in_cap, w.hull_tile_off, out.d_status);
+    VM_HIP(scan_exclusive_dev(w.hull_tile_off, w.hull_tile_off, w.small + 4, kc, w.small + 6, w.blk, s));
+    const int tgrid = grid_for(hull_tiles_bound(kc, cl.n_cap), 1, 4096);
+    k_hull_extremes<<<tgrid, kTileThreads, 0, s>>>(w.small, w.hull_tile_off, cl.d_off, cl.d_x, cl.d_y, cl.d_z, pl,
+                                                   planes.d_in_off, planes.d_in_idx, w.ext_v, w.ext_i);
+    const int kgrid = kc < 4096 ? (int)(kc ? kc : 1) : 4096;
+    k_hull_poly<<<kgrid, kWave, 0, s>>>(w.small, w.hull_tile_off, cl.d_off, cl.d_x, cl.d_y, cl.d_z, pl,
+                                        planes.d_in_off, planes.d_in_idx, w.ext_v, w.ext_i, w.poly, w.surv_cnt);
+    k_hull_filter<<<tgrid, kTileThreads, 0, s>>>(w.small, w.hull_tile_off, cl.d_off, cl.d_x, cl.d_y, cl.d_z, pl,
+                                                 planes.d_in_off, planes.d_in_idx, w.poly, w.surv_cnt, w.hull_u,
+                                                 w.hull_v, w.hull_i);
+    k_hull_chain<<<kgrid, kChainBlock, 0, s>>>(w.small, w.hull_tile_off, planes.d_in_off, planes.d_in_idx,
+                                               w.surv_cnt, w.hull_u, w.hull_v, w.hull_i, w.hull_cnt, w.hull_tmp,
+                                               out.d_area);
     VM_HIP(hipGetLastError());
     VM_HIP(scan_exclusive_dev(w.hull_cnt, w.hull_off, w.small + 4, kc, w.small + 5, w.blk, s));
-    k_hull_pack<<<grid, kBlock, 0, s>>>(w.small, cl.d_off, cl.d_x, cl.d_y, cl.d_z, (const float4*)planes.d_plane,
-                                         planes.d_in_off, w.hull_cnt, w.hull_tmp, w.hull_off, out.v_cap, out.d_v_off,
-                                         out.d_v_idx, out.d_v_xyz, out.d_status);
+    k_hull_pack<<<kgrid, kBlock, 0, s>>>(w.small, cl.d_off, cl.d_x, cl.d_y, cl.d_z, pl, planes.d_in_off, w.hull_cnt,
+                                         w.hull_tmp, w.hull_off, out.v_cap, out.d_v_off, out.d_v_idx, out.d_v_xyz,
+                                         out.d_status);
     VM_HIP(hipGetLastError());
     return VM_OK;
 }

@@ -32,7 +32,6 @@ __global__ void __launch_bounds__(kBlock) k_insert(const float* __restrict__ xyz
     const double lim0 = (double)g.dims[0] * 1048576.0;
     const double lim1 = (double)g.dims[1] * 1048576.0;
     const double lim2 = (double)g.dims[2] * 1048576.0;
-    const uint32_t cap = h.mask + 1;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         const double px = (double)xyz[3 * i + 0];
         const double py = (double)xyz[3 * i + 1];
@@ -56,10 +55,10 @@ __global__ void __launch_bounds__(kBlock) k_insert(const float* __restrict__ xyz
         uint32_t s = hash_slot(key, h.log2cap);
         bool ok = false;
         for (uint32_t p = 0; p < kMaxProbe && p <= h.mask; ++p) {
-            const uint32_t k = h.key[s];
+            const uint32_t k = h.slot[s].key;
             if (k == key) { ok = true; break; }
             if (k == kEmpty) {
-                const uint32_t old = atomicCAS(&h.key[s], kEmpty, key);
+                const uint32_t old = atomicCAS(&h.slot[s].key, kEmpty, key);
                 if (old == kEmpty) {
                     atomicOr(&bits[key >> 5], 1u << (key & 31));
                     ++n_new;
@@ -74,10 +73,11 @@ __global__ void __launch_bounds__(kBlock) k_insert(const float* __restrict__ xyz
             ++n_lost;
             continue;
         }
-        atomicAdd(&h.cnt[s], 1u);
-        atomicAdd(&h.sum[s], (unsigned long long)(qx & 0xFFFFF));
-        atomicAdd(&h.sum[(size_t)cap + s], (unsigned long long)(qy & 0xFFFFF));
-        atomicAdd(&h.sum[2 * (size_t)cap + s], (unsigned long long)(qz & 0xFFFFF));
+        Slot* sl = &h.slot[s];
+        atomicAdd(&sl->cnt, 1u);
+        atomicAdd(&sl->sum[0], (unsigned long long)(qx & 0xFFFFF));
+        atomicAdd(&sl->sum[1], (unsigned long long)(qy & 0xFFFFF));
+        atomicAdd(&sl->sum[2], (unsigned long long)(qz & 0xFFFFF));
         ++n_in;
     }
     wave_add_u64(&ctr->points_in, n_in);
@@ -116,17 +116,16 @@ __global__ void __launch_bounds__(kBlock) k_export(Geom g, Hash h, const uint32_
                                                    uint64_t cap)
 {
     const uint64_t n = ctr->n_occ < cap ? ctr->n_occ : cap;
-    const uint32_t hc = h.mask + 1;
     for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (uint64_t)gridDim.x * blockDim.x) {
         const uint32_t k = occ_key[r];
         const uint32_t s = hash_find(h, k);
         uint32_t c = 0;
         unsigned long long sx = 0, sy = 0, sz = 0;
         if (s != kEmpty) {
-            c = h.cnt[s];
-            sx = h.sum[s];
-            sy = h.sum[hc + s];
-            sz = h.sum[2 * (size_t)hc + s];
+            c = h.slot[s].cnt;
+            sx = h.slot[s].sum[0];
+            sy = h.slot[s].sum[1];
+            sz = h.slot[s].sum[2];
         }
         if (key_out) key_out[r] = k;
         if (cnt_out) cnt_out[r] = c;
@@ -151,7 +150,6 @@ __global__ void __launch_bounds__(kBlock) k_import(Geom g, Hash h, uint32_t* __r
                                                    const unsigned long long* __restrict__ sum, uint64_t n)
 {
     uint32_t n_new = 0, n_lost = 0;
-    const uint32_t hc = h.mask + 1;
     const uint64_t ncell = (uint64_t)g.dims[0] * (uint64_t)g.dims[1] * (uint64_t)g.dims[2];
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
         const uint32_t k = key[i];
@@ -159,20 +157,31 @@ __global__ void __launch_bounds__(kBlock) k_import(Geom g, Hash h, uint32_t* __r
         uint32_t s = hash_slot(k, h.log2cap);
         bool ok = false;
         for (uint32_t p = 0; p < kMaxProbe && p <= h.mask; ++p) {
-            const uint32_t old = atomicCAS(&h.key[s], kEmpty, k);
+            const uint32_t old = atomicCAS(&h.slot[s].key, kEmpty, k);
             if (old == kEmpty || old == k) { ok = true; break; }
             s = (s + 1) & h.mask;
         }
         if (!ok) { ++n_lost; continue; }
-        h.cnt[s] = cnt[i];
-        h.sum[s] = sum[3 * i + 0];
-        h.sum[hc + s] = sum[3 * i + 1];
-        h.sum[2 * (size_t)hc + s] = sum[3 * i + 2];
+        h.slot[s].cnt = cnt[i];
+        h.slot[s].sum[0] = sum[3 * i + 0];
+        h.slot[s].sum[1] = sum[3 * i + 1];
+        h.slot[s].sum[2] = sum[3 * i + 2];
         atomicOr(&bits[k >> 5], 1u << (k & 31));
         ++n_new;
     }
     wave_add_u64(&ctr->occupied, n_new);
     if (__ballot(n_lost != 0) && (threadIdx.x & (kWave - 1)) == 0) atomicOr(&ctr->flags, (uint32_t)VM_FLAG_HASH_FULL);
+}
+
+__global__ void __launch_bounds__(kBlock) k_clear_slots(Slot* __restrict__ slot, uint32_t cap)
+{
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < cap; i += gridDim.x * blockDim.x) {
+        Slot z;
+        z.key = kEmpty;
+        z.cnt = 0;
+        z.sum[0] = z.sum[1] = z.sum[2] = 0;
+        slot[i] = z;
+    }
 }
 
 __global__ void k_stats(const DevCounters* __restrict__ c, uint32_t log2cap, vm_map_stats_t* out)
@@ -215,11 +224,10 @@ hipError_t launch_rank(const Geom& g, const uint32_t* bits, SegBuffers& b, uint3
 
 hipError_t launch_clear(const Geom& g, const Hash& h, uint32_t* bits, DevCounters* ctr, hipStream_t s)
 {
-    const size_t cap = (size_t)h.mask + 1;
+    const uint32_t cap = h.mask + 1;
     hipError_t e;
-    if ((e = hipMemsetAsync(h.key, 0xFF, cap * sizeof(uint32_t), s)) != hipSuccess) return e;
-    if ((e = hipMemsetAsync(h.cnt, 0, cap * sizeof(uint32_t), s)) != hipSuccess) return e;
-    if ((e = hipMemsetAsync(h.sum, 0, 3 * cap * sizeof(unsigned long long), s)) != hipSuccess) return e;
+    k_clear_slots<<<grid_for(cap, kBlock, 16384), kBlock, 0, s>>>(h.slot, cap);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = hipMemsetAsync(bits, 0, (size_t)g.nwords * sizeof(uint32_t), s)) != hipSuccess) return e;
     return hipMemsetAsync(ctr, 0, sizeof(DevCounters), s);
 }

@@ -315,6 +315,7 @@ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 WorkLayout work_layout(void* base, uint32_t k_cap, uint32_t n_cap, uint32_t n_hyp)
 {
     WorkLayout w{};
+    w.k_cap = k_cap;
     char* p = (char*)base;
     size_t o = 0;
     auto take = [&](size_t bytes) {
@@ -335,6 +336,12 @@ WorkLayout work_layout(void* base, uint32_t k_cap, uint32_t n_cap, uint32_t n_hy
     w.hull_u = (double*)take(((size_t)n_cap + 1) * sizeof(double));
     w.hull_v = (double*)take(((size_t)n_cap + 1) * sizeof(double));
     w.hull_i = (uint32_t*)take(((size_t)n_cap + 1) * sizeof(uint32_t));
+    w.hull_tile_off = (uint32_t*)take(((size_t)k_cap + 2) * sizeof(uint32_t));
+    const size_t ht = hull_tiles_bound(k_cap, n_cap);
+    w.ext_v = (double*)take(ht * 8 * sizeof(double));
+    w.ext_i = (uint32_t*)take(ht * 8 * sizeof(uint32_t));
+    w.poly = (double*)take((size_t)k_cap * 18 * sizeof(double) + 8);
+    w.surv_cnt = (uint32_t*)take(((size_t)k_cap + 1) * sizeof(uint32_t));
     w.small = (uint32_t*)take(64 * sizeof(uint32_t));
     w.bytes = o;
     return w;
@@ -345,6 +352,7 @@ vm_status ransac_planes(const vm_clusters& cl, const vm_ransac_params& p, const 
 {
     // the workspace is laid out for kc = min(cl.k_cap, out.k_cap) clusters
     const uint32_t kc = cl.k_cap < out.k_cap ? cl.k_cap : out.k_cap;
+    if (kc > w.k_cap) return VM_E_STATE;
     const uint32_t H = p.n_hyp;
     // small[0] = K (clamped), small[1] = tiles, small[2] = inliers
     {
