@@ -80,6 +80,9 @@ typedef struct {
     double   voxel_size;          /* s, metres, > 0 */
     int32_t  dims[3];             /* NX, NY, NZ, each >= 1 */
     uint32_t hash_capacity_log2;  /* 10..30 */
+    uint32_t insert_batch_log2;   /* largest point batch one sorted insert pass takes
+                                     (0: 2^22); larger calls are split. 16..26 */
+    uint32_t reserved;            /* must be 0 */
 } vm_map_desc;
 
 /* Rigid transform map_from_sensor: p_map = R p_sensor + t (R row-major). */
@@ -95,6 +98,8 @@ typedef struct {
     uint64_t points_lost;     /* inside the grid but dropped because the hash was full */
     uint32_t status_flags;    /* VM_FLAG_* seen since create/clear */
     uint32_t hash_capacity_log2;
+    uint64_t last_touched;    /* distinct voxels the last vm_insert call updated
+                                 (counted on its sorted path; 0 for small calls) */
 } vm_map_stats_t;
 
 /* Allocate a map on the current device (hipMalloc; the map owns the memory
@@ -119,7 +124,10 @@ vm_status vm_map_stats_async(vm_map map, vm_map_stats_t* d_out, void* stream);
  * the 2^-20-voxel fixed-point offset added to the voxel's integer sums, so
  * the stored mean is the arithmetic mean that Eq. (1)'s recurrence computes,
  * independent of arrival order.  Non-finite points and points outside the
- * grid are counted and dropped.  n = 0 is a no-op; n < 0 is VM_E_ARG. */
+ * grid are counted and dropped.  Large calls sort the points by voxel first
+ * and update each touched voxel once; small ones update per point with
+ * integer atomics; both give the same map.  n = 0 is a no-op; n < 0 is
+ * VM_E_ARG. */
 vm_status vm_insert(vm_map map, const float* d_xyz, int64_t n, const vm_pose* pose, void* stream);
 
 /* Export the occupied voxels in ascending key order (e.g. for checkpoints

@@ -33,7 +33,8 @@ _P = ctypes.c_void_p
 
 class MapDesc(ctypes.Structure):
     _fields_ = [("origin", ctypes.c_double * 3), ("voxel_size", ctypes.c_double),
-                ("dims", ctypes.c_int32 * 3), ("hash_capacity_log2", ctypes.c_uint32)]
+                ("dims", ctypes.c_int32 * 3), ("hash_capacity_log2", ctypes.c_uint32),
+                ("insert_batch_log2", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 class Pose(ctypes.Structure):
@@ -43,7 +44,8 @@ class Pose(ctypes.Structure):
 class MapStats(ctypes.Structure):
     _fields_ = [("occupied", ctypes.c_uint64), ("points_in", ctypes.c_uint64),
                 ("points_dropped", ctypes.c_uint64), ("points_lost", ctypes.c_uint64),
-                ("status_flags", ctypes.c_uint32), ("hash_capacity_log2", ctypes.c_uint32)]
+                ("status_flags", ctypes.c_uint32), ("hash_capacity_log2", ctypes.c_uint32),
+                ("last_touched", ctypes.c_uint64)]
 
 
 class Clusters(ctypes.Structure):
@@ -235,8 +237,10 @@ def ransac_params(n_hyp: int, eps: float = 0.01, seed: int = 0x5EED, frame: int 
 class Map:
     """A device-resident sparse voxel map (vm_map)."""
 
-    def __init__(self, origin: Sequence[float], voxel_size: float, dims: Sequence[int], hash_capacity_log2: int):
+    def __init__(self, origin: Sequence[float], voxel_size: float, dims: Sequence[int], hash_capacity_log2: int,
+                 insert_batch_log2: int = 0):
         d = MapDesc()
+        d.insert_batch_log2 = int(insert_batch_log2)
         for i in range(3):
             d.origin[i] = float(origin[i])
             d.dims[i] = int(dims[i])

@@ -17,6 +17,7 @@ struct vm_map_s {
     uint32_t* bits = nullptr;
     DevCounters* ctr = nullptr;
     SegBuffers b{};
+    InsertScratch ins{};
     std::vector<void*> allocs;
     // workspace for the map's own RANSAC/hull pass (grown on demand)
     void* work = nullptr;
@@ -217,6 +218,8 @@ vm_status vm_map_create(const vm_map_desc* d, vm_map* out)
     const uint64_t ncell = (uint64_t)d->dims[0] * (uint64_t)d->dims[1] * (uint64_t)d->dims[2];
     if (ncell >= (1ull << 32) || ncell == 0) return VM_E_ARG;
     if (d->hash_capacity_log2 < 10 || d->hash_capacity_log2 > 30) return VM_E_ARG;
+    if (d->reserved != 0 || (d->insert_batch_log2 != 0 && (d->insert_batch_log2 < 16 || d->insert_batch_log2 > 26)))
+        return VM_E_ARG;
 
     vm_map m = new (std::nothrow) vm_map_s();
     if (!m) return VM_E_OOM;
@@ -260,9 +263,20 @@ vm_status vm_map_create(const vm_map_desc* d, vm_map* out)
     A((void**)&b.cl_y, cap * 4);
     A((void**)&b.cl_z, cap * 4);
     A((void**)&b.wrank, ((size_t)m->g.nwords + 1) * 4);
-    const uint64_t scan_n = std::max<uint64_t>(std::max<uint64_t>(cap, m->g.nwords), radix_hist_words(cap));
+    const uint32_t batch = 1u << (d->insert_batch_log2 ? d->insert_batch_log2 : 22);
+    const uint64_t scan_n = std::max<uint64_t>(std::max<uint64_t>(cap, m->g.nwords),
+                                               std::max<uint64_t>(radix_hist_words(cap), radix_hist_words(batch)));
     A((void**)&b.blk, scan_blk_words(scan_n) * 4);
     A((void**)&b.hist, radix_hist_words(cap) * 4);
+    InsertScratch& ins = m->ins;
+    ins.cap = batch;
+    for (int i = 0; i < 2; ++i) {
+        A((void**)&ins.key[i], (size_t)batch * 4);
+        A((void**)&ins.val[i], (size_t)batch * 4);
+    }
+    A((void**)&ins.packed, (size_t)batch * 8);
+    A((void**)&ins.hist, radix_hist_words(batch) * 4);
+    ins.blk = b.blk;
     if (st != VM_OK) {
         map_free_all(m);
         delete m;
@@ -306,6 +320,7 @@ vm_status vm_map_stats(vm_map m, void* stream, vm_map_stats_t* out)
     out->points_lost = c.points_lost;
     out->status_flags = c.flags;
     out->hash_capacity_log2 = m->h.log2cap;
+    out->last_touched = c.touched;
     return VM_OK;
 }
 
@@ -321,7 +336,7 @@ vm_status vm_insert(vm_map m, const float* d_xyz, int64_t n, const vm_pose* pose
     if (!m || n < 0 || (n > 0 && !d_xyz) || !finite_pose(pose)) return VM_E_ARG;
     if (n == 0) return VM_OK;
     StageScope t(VM_STAGE_INSERT, (hipStream_t)stream);
-    VM_HIP(launch_insert(d_xyz, n, pose_of(pose), m->g, m->h, m->bits, m->ctr, (hipStream_t)stream));
+    VM_HIP(launch_insert(d_xyz, n, pose_of(pose), m->g, m->h, m->bits, m->ctr, m->ins, (hipStream_t)stream));
     return VM_OK;
 }
 

@@ -26,7 +26,10 @@ struct DevCounters {
     uint32_t n_occ;                   // occupied voxels ranked by the last rank pass
     uint32_t meta[2];                 // clusters view: [0] K, [1] total points
     uint32_t kmax;                    // largest cluster id (K - 1, or 0)
-    uint32_t pad[15];
+    uint32_t sort_n;                  // points in the current sorted insert batch
+    uint32_t sort_max;                // largest sort key of that batch (2^bits - 1)
+    unsigned long long touched;       // distinct voxels updated by the last insert call
+    uint32_t pad[11];
 };
 
 struct Geom {
@@ -169,9 +172,20 @@ hipError_t radix_sort_pairs_dev(uint32_t* keys[2], uint32_t* vals[2], const uint
                                 int bits, const uint32_t* d_max_key, uint32_t* hist, uint32_t* blk,
                                 int* result_buf, hipStream_t s);
 
+// Scratch of the sorted insert path (sized for `cap` points per batch).
+struct InsertScratch {
+    uint32_t* key[2];
+    uint32_t* val[2];
+    unsigned long long* packed;   // fixed-point offsets of each point, 20 bits per axis
+    uint32_t* hist;
+    uint32_t* blk;
+    uint32_t cap;
+};
+
 // ---- map stages (vm_map.hip) ------------------------------------------------
+constexpr int64_t kSortedInsertMin = 1 << 17;   // smaller calls use per-point atomics
 hipError_t launch_insert(const float* xyz, int64_t n, const Pose& pose, const Geom& g, const Hash& h,
-                         uint32_t* bits, DevCounters* ctr, hipStream_t s);
+                         uint32_t* bits, DevCounters* ctr, const InsertScratch& sc, hipStream_t s);
 hipError_t launch_stats(const DevCounters* ctr, uint32_t log2cap, vm_map_stats_t* out, hipStream_t s);
 hipError_t launch_rank(const Geom& g, const uint32_t* bits, SegBuffers& b, uint32_t cap,
                        DevCounters* ctr, hipStream_t s);

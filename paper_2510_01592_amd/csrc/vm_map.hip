@@ -87,6 +87,117 @@ __global__ void __launch_bounds__(kBlock) k_insert(const float* __restrict__ xyz
     if (__ballot(n_lost != 0) && (threadIdx.x & (kWave - 1)) == 0) atomicOr(&ctr->flags, (uint32_t)VM_FLAG_HASH_FULL);
 }
 
+// ---- sorted insert path -------------------------------------------------------
+// 1. voxelise every point: (key, point index) pairs plus its packed offsets;
+//    points outside the grid get a key above every valid one.
+__global__ void __launch_bounds__(kBlock) k_voxelize(const float* __restrict__ xyz, uint32_t n, Pose pose, Geom g,
+                                                     uint32_t invalid_key, bool first_batch,
+                                                     uint32_t* __restrict__ key_out, uint32_t* __restrict__ val_out,
+                                                     unsigned long long* __restrict__ packed,
+                                                     DevCounters* __restrict__ ctr)
+{
+    uint32_t n_in = 0, n_drop = 0;
+    const double lim0 = (double)g.dims[0] * 1048576.0;
+    const double lim1 = (double)g.dims[1] * 1048576.0;
+    const double lim2 = (double)g.dims[2] * 1048576.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        ctr->sort_n = n;
+        ctr->sort_max = invalid_key;
+        if (first_batch) ctr->touched = 0;
+    }
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const double px = (double)xyz[3 * (size_t)i + 0];
+        const double py = (double)xyz[3 * (size_t)i + 1];
+        const double pz = (double)xyz[3 * (size_t)i + 2];
+        const double wx = fma(pose.R[2], pz, fma(pose.R[1], py, fma(pose.R[0], px, pose.t[0])));
+        const double wy = fma(pose.R[5], pz, fma(pose.R[4], py, fma(pose.R[3], px, pose.t[1])));
+        const double wz = fma(pose.R[8], pz, fma(pose.R[7], py, fma(pose.R[6], px, pose.t[2])));
+        const double fx = floor((wx - g.origin[0]) * g.inv_q);
+        const double fy = floor((wy - g.origin[1]) * g.inv_q);
+        const double fz = floor((wz - g.origin[2]) * g.inv_q);
+        uint32_t key = invalid_key;
+        unsigned long long pk = 0;
+        if (fx >= 0.0 && fx < lim0 && fy >= 0.0 && fy < lim1 && fz >= 0.0 && fz < lim2) {
+            const int64_t qx = (int64_t)fx, qy = (int64_t)fy, qz = (int64_t)fz;
+            key = (uint32_t)((uint64_t)(qx >> 20) +
+                             (uint64_t)g.dims[0] * ((uint64_t)(qy >> 20) + (uint64_t)g.dims[1] * (uint64_t)(qz >> 20)));
+            pk = (unsigned long long)(qx & 0xFFFFF) | ((unsigned long long)(qy & 0xFFFFF) << 20) |
+                 ((unsigned long long)(qz & 0xFFFFF) << 40);
+            ++n_in;
+        } else {
+            ++n_drop;
+        }
+        key_out[i] = key;
+        val_out[i] = i;
+        packed[i] = pk;
+    }
+    wave_add_u64(&ctr->points_in, n_in);
+    wave_add_u64(&ctr->points_dropped, n_drop);
+}
+
+// 3. after the sort by key: one lane per run of equal keys sums the run and
+//    updates the voxel's slot once.  Every key occurs in one run only, so no
+//    other lane touches that slot in this pass: the payload is a plain
+//    read-modify-write; only claiming an empty slot needs a CAS.
+__global__ void __launch_bounds__(kBlock) k_insert_runs(const uint32_t* __restrict__ key,
+                                                        const uint32_t* __restrict__ val,
+                                                        const unsigned long long* __restrict__ packed, Hash h,
+                                                        uint32_t* __restrict__ bits, DevCounters* __restrict__ ctr)
+{
+    const uint32_t n = ctr->sort_n;
+    const uint32_t invalid_key = ctr->sort_max;
+    uint32_t n_lost = 0, n_new = 0, n_runs = 0;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const uint32_t k = key[i];
+        if (k == invalid_key) continue;
+        if (i > 0 && key[i - 1] == k) continue;   // not the start of a run
+        uint32_t c = 0;
+        unsigned long long sx = 0, sy = 0, sz = 0;
+        for (uint32_t j = i; j < n && key[j] == k; ++j) {
+            const unsigned long long pk = packed[val[j]];
+            ++c;
+            sx += pk & 0xFFFFF;
+            sy += (pk >> 20) & 0xFFFFF;
+            sz += (pk >> 40) & 0xFFFFF;
+        }
+        ++n_runs;
+        uint32_t s = hash_slot(k, h.log2cap);
+        bool ok = false;
+        for (uint32_t p = 0; p < kMaxProbe && p <= h.mask; ++p) {
+            const uint32_t kk = h.slot[s].key;
+            if (kk == k) { ok = true; break; }
+            if (kk == kEmpty) {
+                const uint32_t old = atomicCAS(&h.slot[s].key, kEmpty, k);
+                if (old == kEmpty) {
+                    atomicOr(&bits[k >> 5], 1u << (k & 31));
+                    ++n_new;
+                    ok = true;
+                    break;
+                }
+                if (old == k) { ok = true; break; }
+            }
+            s = (s + 1) & h.mask;
+        }
+        if (!ok) {
+            n_lost += c;
+            continue;
+        }
+        Slot* sl = &h.slot[s];
+        sl->cnt += c;
+        sl->sum[0] += sx;
+        sl->sum[1] += sy;
+        sl->sum[2] += sz;
+    }
+    wave_add_u64(&ctr->points_lost, n_lost);
+    wave_add_u64(&ctr->occupied, n_new);
+    wave_add_u64(&ctr->touched, n_runs);
+    if (n_lost) {
+        // points lost here were counted as inserted by the voxelise pass
+        atomicAdd(&ctr->points_in, 0ull - (unsigned long long)n_lost);
+    }
+    if (__ballot(n_lost != 0) && (threadIdx.x & (kWave - 1)) == 0) atomicOr(&ctr->flags, (uint32_t)VM_FLAG_HASH_FULL);
+}
+
 __global__ void __launch_bounds__(kBlock) k_popc(const uint32_t* __restrict__ bits, uint32_t nwords,
                                                  uint32_t* __restrict__ out)
 {
@@ -187,6 +298,7 @@ __global__ void __launch_bounds__(kBlock) k_clear_slots(Slot* __restrict__ slot,
 __global__ void k_stats(const DevCounters* __restrict__ c, uint32_t log2cap, vm_map_stats_t* out)
 {
     if (threadIdx.x == 0) {
+        out->last_touched = c->touched;
         out->occupied = c->occupied;
         out->points_in = c->points_in;
         out->points_dropped = c->points_dropped;
@@ -205,11 +317,33 @@ hipError_t launch_stats(const DevCounters* ctr, uint32_t log2cap, vm_map_stats_t
 }
 
 hipError_t launch_insert(const float* xyz, int64_t n, const Pose& pose, const Geom& g, const Hash& h,
-                         uint32_t* bits, DevCounters* ctr, hipStream_t s)
+                         uint32_t* bits, DevCounters* ctr, const InsertScratch& sc, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    k_insert<<<grid_for((uint64_t)n, kBlock, 16384), kBlock, 0, s>>>(xyz, n, pose, g, h, bits, ctr);
-    return hipGetLastError();
+    if (n < kSortedInsertMin || sc.cap == 0) {
+        k_insert<<<grid_for((uint64_t)n, kBlock, 16384), kBlock, 0, s>>>(xyz, n, pose, g, h, bits, ctr);
+        return hipGetLastError();
+    }
+    // keys below ncell; the sort covers bit_width(ncell) bits and dropped
+    // points carry the all-ones key of that width, after every valid key
+    const uint64_t ncell = (uint64_t)g.dims[0] * (uint64_t)g.dims[1] * (uint64_t)g.dims[2];
+    int bits_needed = 0;
+    while (bits_needed < 32 && (1ull << bits_needed) <= ncell) ++bits_needed;
+    const uint32_t invalid_key = bits_needed >= 32 ? 0xFFFFFFFFu : (uint32_t)((1ull << bits_needed) - 1);
+    uint32_t* keys[2] = {sc.key[0], sc.key[1]};
+    uint32_t* vals[2] = {sc.val[0], sc.val[1]};
+    for (int64_t done = 0; done < n; done += sc.cap) {
+        const uint32_t m = (uint32_t)((n - done) < (int64_t)sc.cap ? (n - done) : (int64_t)sc.cap);
+        k_voxelize<<<grid_for(m, kBlock, 16384), kBlock, 0, s>>>(xyz + 3 * done, m, pose, g, invalid_key, done == 0,
+                                                                  keys[0], vals[0], sc.packed, ctr);
+        int res = 0;
+        hipError_t e = radix_sort_pairs_dev(keys, vals, &ctr->sort_n, sc.cap, bits_needed, &ctr->sort_max, sc.hist,
+                                            sc.blk, &res, s);
+        if (e != hipSuccess) return e;
+        k_insert_runs<<<grid_for(m, kBlock, 16384), kBlock, 0, s>>>(keys[res], vals[res], sc.packed, h, bits, ctr);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_rank(const Geom& g, const uint32_t* bits, SegBuffers& b, uint32_t /*cap*/, DevCounters* ctr,

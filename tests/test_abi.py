@@ -90,7 +90,8 @@ def test_argument_errors_without_device_work():
 def test_struct_layouts_match_header_sizes():
     import paper_2510_01592_amd as vm
     # natural C alignment on x86-64 / amdgcn host ABI
-    assert ctypes.sizeof(vm.MapDesc) == 3 * 8 + 8 + 3 * 4 + 4
+    assert ctypes.sizeof(vm.MapDesc) == 3 * 8 + 8 + 3 * 4 + 4 + 4 + 4
+    assert ctypes.sizeof(vm.MapStats) == 4 * 8 + 2 * 4 + 8
     assert ctypes.sizeof(vm.Pose) == 12 * 8
     assert ctypes.sizeof(vm.RansacParams) == 24
     assert ctypes.sizeof(vm.SegParams) == 32

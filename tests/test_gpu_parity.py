@@ -61,6 +61,30 @@ def test_insert_posed_frames(vm):
     assert st.points_dropped == om.points_dropped and st.points_in == om.points_in
 
 
+@pytest.mark.parametrize("batch_log2", [0, 16])
+def test_insert_sorted_and_atomic_paths_agree(vm, batch_log2):
+    # one large call (sorted path, split into batches of 2^16 when batch_log2=16)
+    # against many small calls (per-point atomics) and against the oracle
+    sc = scenes.scene_full_map(1)
+    g = sc.geom
+    pts = scenes.frame_points(sc, 77, n=400_000)
+    note(f"insert sorted vs atomic, batch_log2={batch_log2}")
+    a = vm.Map(g.origin, g.voxel_size, g.dims, 21, insert_batch_log2=batch_log2)
+    a.insert(_t(pts))
+    b = vm.Map(g.origin, g.voxel_size, g.dims, 21)
+    for c in range(0, len(pts), 50_000):
+        b.insert(_t(pts[c:c + 50_000]))
+    om = oracle.OracleMap(g.origin, g.voxel_size, g.dims)
+    om.insert(pts)
+    assert_map_equal(a, om)
+    assert_map_equal(b, om)
+    sa, sb = a.stats(), b.stats()
+    assert sa.points_in == sb.points_in == om.points_in
+    assert sa.points_dropped == sb.points_dropped == om.points_dropped
+    key, _, _ = oracle.voxelize(pts, np.eye(3), np.zeros(3), g.origin, g.voxel_size, g.dims)
+    assert sa.last_touched == len(np.unique(key[key != oracle.NO_KEY]))
+
+
 def test_insert_drops_and_bounds(vm):
     g = scenes.MapGeom((0.0, 0.0, 0.0), 0.25, (8, 8, 8))
     pts = np.array([[np.nan, 0.1, 0.1], [0.1, np.inf, 0.1], [0.1, 0.1, -np.inf], [2.0, 0.1, 0.1],
