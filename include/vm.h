@@ -98,8 +98,9 @@ typedef struct {
     uint64_t points_lost;     /* inside the grid but dropped because the hash was full */
     uint32_t status_flags;    /* VM_FLAG_* seen since create/clear */
     uint32_t hash_capacity_log2;
-    uint64_t last_touched;    /* distinct voxels the last vm_insert call updated
-                                 (counted on its sorted path; 0 for small calls) */
+    uint64_t last_touched;    /* voxel slot updates of the last vm_insert call on its
+                                 sorted path: one per distinct voxel of each sorted
+                                 batch (0 for calls small enough for per-point atomics) */
 } vm_map_stats_t;
 
 /* Allocate a map on the current device (hipMalloc; the map owns the memory

@@ -86,7 +86,7 @@ struct Dims {
 __global__ void __launch_bounds__(kBlock) k_ccl_init(const uint32_t* __restrict__ bits,
                                                      const uint32_t* __restrict__ occ_key,
                                                      const DevCounters* __restrict__ ctr, Dims d,
-                                                     uint32_t* __restrict__ parent)
+                                                     uint32_t* __restrict__ parent, uint32_t* __restrict__ linked)
 {
     const uint32_t V = ctr->n_occ;
     for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < V; r += gridDim.x * blockDim.x) {
@@ -111,14 +111,26 @@ __global__ void __launch_bounds__(kBlock) k_ccl_init(const uint32_t* __restrict_
         }
         if (start < rowstart) start = rowstart;
         parent[r] = r - (key - start);
+        // part of a run of two or more voxels along x?
+        const bool next = (x + 1 < d.nx) && occ(bits, key + 1);
+        linked[r] = (start < key || next) ? 1u : 0u;
     }
+}
+
+// a voxel joined to another across rows: both ends are marked (stores of 1
+// only, so concurrent marks cannot conflict)
+__device__ __forceinline__ void link(uint32_t* parent, uint32_t* linked, uint32_t a, uint32_t b)
+{
+    linked[a] = 1u;
+    linked[b] = 1u;
+    uf_unite(parent, a, b);
 }
 
 __global__ void __launch_bounds__(kBlock) k_ccl_merge(const uint32_t* __restrict__ bits,
                                                       const uint32_t* __restrict__ wrank,
                                                       const uint32_t* __restrict__ occ_key,
                                                       const DevCounters* __restrict__ ctr, Dims d,
-                                                      uint32_t* parent)
+                                                      uint32_t* parent, uint32_t* linked)
 {
     const uint32_t V = ctr->n_occ;
     for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < V; r += gridDim.x * blockDim.x) {
@@ -136,11 +148,11 @@ __global__ void __launch_bounds__(kBlock) k_ccl_merge(const uint32_t* __restrict
             if ((dz < 0 && z == 0) || (dy < 0 && y == 0) || (dy > 0 && y + 1 == d.ny)) continue;
             const uint32_t nk = (uint32_t)((int64_t)key + (int64_t)dy * d.nx + (int64_t)dz * d.nxy);
             if (occ(bits, nk) && (run_start || !occ(bits, nk - 1)))
-                uf_unite(parent, r, rank_of(bits, wrank, nk));
+                link(parent, linked, r, rank_of(bits, wrank, nk));
             if (run_start && x > 0 && occ(bits, nk - 1))
-                uf_unite(parent, r, rank_of(bits, wrank, nk - 1));
+                link(parent, linked, r, rank_of(bits, wrank, nk - 1));
             if (run_end && x + 1 < d.nx && occ(bits, nk + 1))
-                uf_unite(parent, r, rank_of(bits, wrank, nk + 1));
+                link(parent, linked, r, rank_of(bits, wrank, nk + 1));
         }
     }
 }
@@ -162,27 +174,62 @@ __global__ void __launch_bounds__(kBlock) k_ccl_flatten(const DevCounters* __res
     }
 }
 
-// Component sizes at the roots.  Consecutive ranks mostly share a root, so a
-// wave adds one count per run of equal roots.
+// Component sizes at the roots.  A voxel never linked to another is a
+// component of its own: size 1, a plain store.  For the rest, consecutive
+// ranks mostly share a root: a wave first sums each run of equal roots, then
+// the block merges its runs in an LDS table and adds one count per distinct
+// root (a large component's root would otherwise take an atomic from every
+// wave that holds part of it).
+constexpr int kSizeItems = 8;
+constexpr int kSizeSpan = kBlock * kSizeItems;   // ranks per block pass
+constexpr int kSizeTab = kSizeSpan;              // one slot per possible root
+static_assert(kSizeTab == 1 << 11, "the table hash below indexes 2^11 slots");
+
 __global__ void __launch_bounds__(kBlock) k_ccl_sizes(const DevCounters* __restrict__ ctr,
-                                                      const uint32_t* __restrict__ parent, uint32_t* csize)
+                                                      const uint32_t* __restrict__ parent,
+                                                      const uint32_t* __restrict__ linked, uint32_t* csize)
 {
+    __shared__ uint32_t tkey[kSizeTab];
+    __shared__ uint32_t tcnt[kSizeTab];
     const uint32_t V = ctr->n_occ;
     const int lane = threadIdx.x & (kWave - 1);
-    const uint32_t stride = gridDim.x * blockDim.x;
-    for (uint32_t r0 = blockIdx.x * blockDim.x; r0 < V; r0 += stride) {
-        const uint32_t r = r0 + threadIdx.x;
-        const bool valid = r < V;
-        const uint32_t root = valid ? parent[r] : 0xFFFFFFFFu;
-        const uint32_t prev = __shfl_up(root, 1, kWave);
-        const bool head = valid && (lane == 0 || prev != root);
-        const uint64_t heads = __ballot(head);
-        const uint64_t vmask = __ballot(valid);
-        if (head) {
-            const uint64_t after = (lane == 63) ? 0ull : (heads & (~0ull << (lane + 1)));
-            const uint32_t end = after ? (uint32_t)(__ffsll((long long)after) - 1) : (uint32_t)(64 - __clzll((long long)vmask));
-            atomicAdd(&csize[root], end - (uint32_t)lane);
+    for (uint32_t base = blockIdx.x * kSizeSpan; base < V; base += gridDim.x * kSizeSpan) {
+        for (int i = threadIdx.x; i < kSizeTab; i += kBlock) {
+            tkey[i] = kEmpty;
+            tcnt[i] = 0;
         }
+        __syncthreads();
+        for (int it = 0; it < kSizeItems; ++it) {
+            const uint32_t r = base + it * kBlock + threadIdx.x;
+            const bool in = r < V;
+            const bool alone = in && linked[r] == 0u;
+            if (alone) csize[r] = 1u;
+            const bool valid = in && !alone;
+            const uint32_t root = valid ? parent[r] : 0xFFFFFFFFu;
+            const uint32_t prev = __shfl_up(root, 1, kWave);
+            const uint64_t vmask = __ballot(valid);
+            const bool prev_valid = lane > 0 && ((vmask >> (lane - 1)) & 1ull);
+            const bool head = valid && (!prev_valid || prev != root);
+            // a run ends before the next head or the next lane that is not valid
+            const uint64_t stops = __ballot(head) | ~vmask;
+            if (head) {
+                const uint64_t after = (lane == 63) ? 0ull : (stops & (~0ull << (lane + 1)));
+                const uint32_t len = (after ? (uint32_t)(__ffsll((long long)after) - 1) : 64u) - (uint32_t)lane;
+                uint32_t h = (root * 2654435769u) >> (32 - 11);   // kSizeTab = 2^11 slots
+                for (;;) {
+                    const uint32_t old = atomicCAS(&tkey[h], kEmpty, root);
+                    if (old == kEmpty || old == root) {
+                        atomicAdd(&tcnt[h], len);
+                        break;
+                    }
+                    h = (h + 1) & (kSizeTab - 1);
+                }
+            }
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < kSizeTab; i += kBlock)
+            if (tkey[i] != kEmpty) atomicAdd(&csize[tkey[i]], tcnt[i]);
+        __syncthreads();
     }
 }
 
@@ -308,8 +355,8 @@ hipError_t launch_ccl(const Geom& g, const uint32_t* bits, SegBuffers& b, uint32
     const int grid = grid_for(cap);
     {
         StageScope t(VM_STAGE_CCL, s);
-        k_ccl_init<<<grid, kBlock, 0, s>>>(bits, b.occ_key, ctr, d, b.parent);
-        k_ccl_merge<<<grid, kBlock, 0, s>>>(bits, b.wrank, b.occ_key, ctr, d, b.parent);
+        k_ccl_init<<<grid, kBlock, 0, s>>>(bits, b.occ_key, ctr, d, b.parent, b.scan_a);
+        k_ccl_merge<<<grid, kBlock, 0, s>>>(bits, b.wrank, b.occ_key, ctr, d, b.parent, b.scan_a);
         k_ccl_flatten<<<grid, kBlock, 0, s>>>(ctr, b.parent);
     }
     return hipGetLastError();
@@ -322,7 +369,8 @@ hipError_t launch_group(const Geom& g, const Hash& h, SegBuffers& b, uint32_t ca
     const int grid = grid_for(cap);
     if (min_cluster < 1) min_cluster = 1;
     k_zero<<<grid, kBlock, 0, s>>>(b.csize, ctr);
-    k_ccl_sizes<<<grid, kBlock, 0, s>>>(ctr, b.parent, b.csize);
+    // scan_a: linked flags from the CCL
+    k_ccl_sizes<<<grid_for(cap, kSizeSpan, 1024), kBlock, 0, s>>>(ctr, b.parent, b.scan_a, b.csize);
     uint32_t* is_root = b.scan_a;
     uint32_t* root_size = b.scan_b;
     uint32_t* keep = b.sort_k[1];

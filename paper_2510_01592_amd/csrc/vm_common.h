@@ -128,6 +128,28 @@ __device__ __forceinline__ uint32_t validate_clusters(const uint32_t* meta, cons
     return bad ? 0u : K;
 }
 
+// Add per-thread counts into global 64-bit counters with one atomic per block
+// and counter (zero totals skipped).  Every thread of the block must call it.
+template <int N>
+__device__ __forceinline__ void block_add_counters(unsigned long long* const (&dst)[N], const uint32_t (&v)[N])
+{
+    __shared__ unsigned long long part[N][kBlock / kWave];
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+#pragma unroll
+    for (int c = 0; c < N; ++c) {
+        unsigned long long s = v[c];
+#pragma unroll
+        for (int d = kWave / 2; d >= 1; d >>= 1) s += __shfl_xor(s, d, kWave);
+        if (lane == 0) part[c][wave] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < N) {
+        unsigned long long t = 0;
+        for (int w = 0; w < (int)(blockDim.x / kWave); ++w) t += part[threadIdx.x][w];
+        if (t) atomicAdd(dst[threadIdx.x], t);
+    }
+}
+
 // ---- host-side error plumbing ------------------------------------------
 #define VM_HIP(call)                                                    \
     do {                                                                \

@@ -14,14 +14,10 @@
 namespace vm {
 namespace {
 
-__device__ __forceinline__ void wave_add_u64(unsigned long long* dst, uint32_t v)
-{
-    // one atomic per wave: sum over lanes via popcount-free shuffle tree
-    unsigned long long s = v;
-#pragma unroll
-    for (int d = kWave / 2; d >= 1; d >>= 1) s += __shfl_xor(s, d, kWave);
-    if ((threadIdx.x & (kWave - 1)) == 0 && s) atomicAdd(dst, s);
-}
+// Counters are reduced per block before one atomic each (same-address device
+// atomics from every wave would serialise).  Grids stay at most kMapGrid
+// blocks; threads stride over the points.
+constexpr int kMapGrid = 1024;
 
 __global__ void __launch_bounds__(kBlock) k_insert(const float* __restrict__ xyz, int64_t n, Pose pose, Geom g,
                                                    Hash h, uint32_t* __restrict__ bits,
@@ -80,11 +76,12 @@ __global__ void __launch_bounds__(kBlock) k_insert(const float* __restrict__ xyz
         atomicAdd(&sl->sum[2], (unsigned long long)(qz & 0xFFFFF));
         ++n_in;
     }
-    wave_add_u64(&ctr->points_in, n_in);
-    wave_add_u64(&ctr->points_dropped, n_drop);
-    wave_add_u64(&ctr->points_lost, n_lost);
-    wave_add_u64(&ctr->occupied, n_new);
-    if (__ballot(n_lost != 0) && (threadIdx.x & (kWave - 1)) == 0) atomicOr(&ctr->flags, (uint32_t)VM_FLAG_HASH_FULL);
+    {
+        unsigned long long* const dst[4] = {&ctr->points_in, &ctr->points_dropped, &ctr->points_lost, &ctr->occupied};
+        const uint32_t v[4] = {n_in, n_drop, n_lost, n_new};
+        block_add_counters<4>(dst, v);
+    }
+    if (n_lost) atomicOr(&ctr->flags, (uint32_t)VM_FLAG_HASH_FULL);
 }
 
 // ---- sorted insert path -------------------------------------------------------
@@ -131,8 +128,9 @@ __global__ void __launch_bounds__(kBlock) k_voxelize(const float* __restrict__ x
         val_out[i] = i;
         packed[i] = pk;
     }
-    wave_add_u64(&ctr->points_in, n_in);
-    wave_add_u64(&ctr->points_dropped, n_drop);
+    unsigned long long* const dst[2] = {&ctr->points_in, &ctr->points_dropped};
+    const uint32_t v[2] = {n_in, n_drop};
+    block_add_counters<2>(dst, v);
 }
 
 // 3. after the sort by key: one lane per run of equal keys sums the run and
@@ -188,14 +186,16 @@ __global__ void __launch_bounds__(kBlock) k_insert_runs(const uint32_t* __restri
         sl->sum[1] += sy;
         sl->sum[2] += sz;
     }
-    wave_add_u64(&ctr->points_lost, n_lost);
-    wave_add_u64(&ctr->occupied, n_new);
-    wave_add_u64(&ctr->touched, n_runs);
+    {
+        unsigned long long* const dst[3] = {&ctr->points_lost, &ctr->occupied, &ctr->touched};
+        const uint32_t v[3] = {n_lost, n_new, n_runs};
+        block_add_counters<3>(dst, v);
+    }
     if (n_lost) {
         // points lost here were counted as inserted by the voxelise pass
         atomicAdd(&ctr->points_in, 0ull - (unsigned long long)n_lost);
+        atomicOr(&ctr->flags, (uint32_t)VM_FLAG_HASH_FULL);
     }
-    if (__ballot(n_lost != 0) && (threadIdx.x & (kWave - 1)) == 0) atomicOr(&ctr->flags, (uint32_t)VM_FLAG_HASH_FULL);
 }
 
 __global__ void __launch_bounds__(kBlock) k_popc(const uint32_t* __restrict__ bits, uint32_t nwords,
@@ -280,8 +280,12 @@ __global__ void __launch_bounds__(kBlock) k_import(Geom g, Hash h, uint32_t* __r
         atomicOr(&bits[k >> 5], 1u << (k & 31));
         ++n_new;
     }
-    wave_add_u64(&ctr->occupied, n_new);
-    if (__ballot(n_lost != 0) && (threadIdx.x & (kWave - 1)) == 0) atomicOr(&ctr->flags, (uint32_t)VM_FLAG_HASH_FULL);
+    {
+        unsigned long long* const dst[1] = {&ctr->occupied};
+        const uint32_t v[1] = {n_new};
+        block_add_counters<1>(dst, v);
+    }
+    if (n_lost) atomicOr(&ctr->flags, (uint32_t)VM_FLAG_HASH_FULL);
 }
 
 __global__ void __launch_bounds__(kBlock) k_clear_slots(Slot* __restrict__ slot, uint32_t cap)
@@ -321,7 +325,7 @@ hipError_t launch_insert(const float* xyz, int64_t n, const Pose& pose, const Ge
 {
     if (n <= 0) return hipSuccess;
     if (n < kSortedInsertMin || sc.cap == 0) {
-        k_insert<<<grid_for((uint64_t)n, kBlock, 16384), kBlock, 0, s>>>(xyz, n, pose, g, h, bits, ctr);
+        k_insert<<<grid_for((uint64_t)n, kBlock, kMapGrid), kBlock, 0, s>>>(xyz, n, pose, g, h, bits, ctr);
         return hipGetLastError();
     }
     // keys below ncell; the sort covers bit_width(ncell) bits and dropped
@@ -334,13 +338,14 @@ hipError_t launch_insert(const float* xyz, int64_t n, const Pose& pose, const Ge
     uint32_t* vals[2] = {sc.val[0], sc.val[1]};
     for (int64_t done = 0; done < n; done += sc.cap) {
         const uint32_t m = (uint32_t)((n - done) < (int64_t)sc.cap ? (n - done) : (int64_t)sc.cap);
-        k_voxelize<<<grid_for(m, kBlock, 16384), kBlock, 0, s>>>(xyz + 3 * done, m, pose, g, invalid_key, done == 0,
-                                                                  keys[0], vals[0], sc.packed, ctr);
+        k_voxelize<<<grid_for(m, kBlock, kMapGrid), kBlock, 0, s>>>(xyz + 3 * done, m, pose, g, invalid_key, done == 0,
+                                                                     keys[0], vals[0], sc.packed, ctr);
         int res = 0;
-        hipError_t e = radix_sort_pairs_dev(keys, vals, &ctr->sort_n, sc.cap, bits_needed, &ctr->sort_max, sc.hist,
+        // the batch size is known here, so the sort's grids are sized by it
+        hipError_t e = radix_sort_pairs_dev(keys, vals, &ctr->sort_n, m, bits_needed, &ctr->sort_max, sc.hist,
                                             sc.blk, &res, s);
         if (e != hipSuccess) return e;
-        k_insert_runs<<<grid_for(m, kBlock, 16384), kBlock, 0, s>>>(keys[res], vals[res], sc.packed, h, bits, ctr);
+        k_insert_runs<<<grid_for(m, kBlock, kMapGrid), kBlock, 0, s>>>(keys[res], vals[res], sc.packed, h, bits, ctr);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     return hipSuccess;
@@ -378,7 +383,7 @@ hipError_t launch_import(const Geom& g, const Hash& h, uint32_t* bits, DevCounte
 {
     hipError_t e = launch_clear(g, h, bits, ctr, s);
     if (e != hipSuccess || n == 0) return e;
-    k_import<<<grid_for(n), kBlock, 0, s>>>(g, h, bits, ctr, key, cnt, sum, n);
+    k_import<<<grid_for(n, kBlock, kMapGrid), kBlock, 0, s>>>(g, h, bits, ctr, key, cnt, sum, n);
     return hipGetLastError();
 }
 

@@ -21,9 +21,10 @@ namespace vm {
 namespace {
 
 constexpr int kCountBlock = 256;
-constexpr int kPtsPerLane = 4;
-constexpr int kTile = kCountBlock * kPtsPerLane;   // points per tile (1024)
-constexpr int kMaxHypChunk = 4096;                 // hypotheses staged per item (LDS counters)
+constexpr int kPtsPerLane = 8;
+constexpr int kTile = kCountBlock * kPtsPerLane;   // points per tile (2048)
+constexpr int kMaxHypChunk = 4096;                 // hypotheses per work item (LDS counters)
+constexpr int kHypBatch = 4;                       // planes loaded together
 
 __device__ __forceinline__ void philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3, uint64_t k0,
                                               uint64_t k1, uint64_t out[4])
@@ -140,18 +141,41 @@ __device__ __forceinline__ uint32_t cluster_of_tile(const uint32_t* __restrict__
     return lo;
 }
 
-// (b) inlier counting over (tile, hypothesis-chunk) items
+// (b) inlier counting over (tile, hypothesis-chunk) items.  The number of
+// hypothesis chunks is chosen on the device from the tile count so that small
+// frames still cover every CU; each item keeps its points in registers and
+// sweeps its chunk of planes, kHypBatch planes per scalar-load batch.
+__device__ __forceinline__ uint32_t count_one(const float4 pl, const float* px, const float* py, const float* pz,
+                                              float eps)
+{
+    uint32_t acc = 0;
+#pragma unroll
+    for (int j = 0; j < kPtsPerLane; ++j) {
+        const float dd = fmaf(pl.z, pz[j], fmaf(pl.y, py[j], fmaf(pl.x, px[j], pl.w)));
+        acc += (uint32_t)__popcll(__ballot(fabsf(dd) < eps));
+    }
+    return acc;
+}
+
 __global__ void __launch_bounds__(kCountBlock) k_count(const uint32_t* __restrict__ small,
                                                        const uint32_t* __restrict__ tile_off,
                                                        const uint32_t* __restrict__ off, const float* __restrict__ X,
                                                        const float* __restrict__ Y, const float* __restrict__ Z,
-                                                       uint32_t H, uint32_t hyp_chunk, float eps,
-                                                       const float4* __restrict__ hyp, int32_t* __restrict__ counts)
+                                                       uint32_t H, float eps, const float4* __restrict__ hyp,
+                                                       int32_t* __restrict__ counts)
 {
     __shared__ uint32_t lcnt[kMaxHypChunk];
     const uint32_t K = small[0];
     const uint32_t T = small[1];
-    const uint32_t HC = (H + hyp_chunk - 1) / hyp_chunk;
+    if (T == 0) return;
+    // chunks per tile: enough items for two per block of the grid, chunks of
+    // at least 32 hypotheses, at most kMaxHypChunk
+    uint32_t HC = (2u * gridDim.x + T - 1) / T;
+    const uint32_t hc_max = (H + 31) / 32;
+    if (HC > hc_max) HC = hc_max;
+    if (HC < (H + kMaxHypChunk - 1) / kMaxHypChunk) HC = (H + kMaxHypChunk - 1) / kMaxHypChunk;
+    if (HC < 1) HC = 1;
+    const uint32_t chunk = (H + HC - 1) / HC;
     const uint64_t items = (uint64_t)T * HC;
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     for (uint64_t item = blockIdx.x; item < items; item += gridDim.x) {
@@ -159,7 +183,7 @@ __global__ void __launch_bounds__(kCountBlock) k_count(const uint32_t* __restric
         const uint32_t k = cluster_of_tile(tile_off, K, t);
         const uint32_t p0 = off[k] + (t - tile_off[k]) * kTile;
         const uint32_t pend = off[k + 1];
-        const uint32_t h0 = hc * hyp_chunk, h1 = min(H, h0 + hyp_chunk);
+        const uint32_t h0 = hc * chunk, h1 = min(H, h0 + chunk);
         float px[kPtsPerLane], py[kPtsPerLane], pz[kPtsPerLane];
         const float qnan = __builtin_nanf("");
 #pragma unroll
@@ -173,22 +197,29 @@ __global__ void __launch_bounds__(kCountBlock) k_count(const uint32_t* __restric
         for (uint32_t h = h0 + threadIdx.x; h < h1; h += kCountBlock) lcnt[h - h0] = 0;
         __syncthreads();
         const float4* hk = hyp + (size_t)k * H;
-        for (uint32_t h = h0; h < h1; ++h) {
-            const float4 pl = hk[h];
-            if (pl.x != pl.x) continue;   // degenerate hypothesis
-            uint32_t acc = 0;
+        uint32_t h = h0;
+        for (; h + kHypBatch <= h1; h += kHypBatch) {
+            float4 pl[kHypBatch];
 #pragma unroll
-            for (int j = 0; j < kPtsPerLane; ++j) {
-                const float dd = fmaf(pl.z, pz[j], fmaf(pl.y, py[j], fmaf(pl.x, px[j], pl.w)));
-                acc += (uint32_t)__popcll(__ballot(fabsf(dd) < eps));
+            for (int b = 0; b < kHypBatch; ++b) pl[b] = hk[h + b];
+#pragma unroll
+            for (int b = 0; b < kHypBatch; ++b) {
+                if (pl[b].x != pl[b].x) continue;   // degenerate hypothesis
+                const uint32_t acc = count_one(pl[b], px, py, pz, eps);
+                if (lane == 0 && acc) atomicAdd(&lcnt[h + b - h0], acc);
             }
+        }
+        for (; h < h1; ++h) {
+            const float4 pl = hk[h];
+            if (pl.x != pl.x) continue;
+            const uint32_t acc = count_one(pl, px, py, pz, eps);
             if (lane == 0 && acc) atomicAdd(&lcnt[h - h0], acc);
         }
         __syncthreads();
         int32_t* ck = counts + (size_t)k * H;
-        for (uint32_t h = h0 + threadIdx.x; h < h1; h += kCountBlock) {
-            const uint32_t c = lcnt[h - h0];
-            if (c) atomicAdd(&ck[h], (int32_t)c);
+        for (uint32_t hh = h0 + threadIdx.x; hh < h1; hh += kCountBlock) {
+            const uint32_t c = lcnt[hh - h0];
+            if (c) atomicAdd(&ck[hh], (int32_t)c);
         }
         __syncthreads();
     }
@@ -367,9 +398,8 @@ vm_status ransac_planes(const vm_clusters& cl, const vm_ransac_params& p, const 
     }
     {
         StageScope t(VM_STAGE_COUNT, s);
-        const uint32_t chunk = H < (uint32_t)kMaxHypChunk ? H : (uint32_t)kMaxHypChunk;
-        k_count<<<4096, kCountBlock, 0, s>>>(w.small, w.tile_off, cl.d_off, cl.d_x, cl.d_y, cl.d_z, H, chunk, p.eps,
-                                             w.hyp, w.counts);
+        k_count<<<2048, kCountBlock, 0, s>>>(w.small, w.tile_off, cl.d_off, cl.d_x, cl.d_y, cl.d_z, H, p.eps, w.hyp,
+                                             w.counts);
         VM_HIP(hipGetLastError());
     }
     {

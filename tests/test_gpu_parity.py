@@ -82,7 +82,12 @@ def test_insert_sorted_and_atomic_paths_agree(vm, batch_log2):
     assert sa.points_in == sb.points_in == om.points_in
     assert sa.points_dropped == sb.points_dropped == om.points_dropped
     key, _, _ = oracle.voxelize(pts, np.eye(3), np.zeros(3), g.origin, g.voxel_size, g.dims)
-    assert sa.last_touched == len(np.unique(key[key != oracle.NO_KEY]))
+    if batch_log2 == 0:      # one sorted batch: one update per distinct voxel
+        assert sa.last_touched == len(np.unique(key[key != oracle.NO_KEY]))
+    else:                    # one update per distinct voxel of each 2^16-point batch
+        B = 1 << batch_log2
+        expect = sum(len(np.unique(kb[kb != oracle.NO_KEY])) for kb in (key[i:i + B] for i in range(0, len(key), B)))
+        assert sa.last_touched == expect
 
 
 def test_insert_drops_and_bounds(vm):
