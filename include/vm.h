@@ -185,6 +185,9 @@ typedef struct {
     uint64_t seed;       /* Philox4x64-10 key word 0 */
     uint32_t frame;      /* counter word 2 (per-map frame number) */
     uint32_t reserved;   /* must be 0 */
+    const uint32_t* d_frame;  /* optional device word: when non-NULL the frame number is
+                                 read from it when the work executes (graph replays
+                                 advance it between launches); `frame` is then unused */
 } vm_ransac_params;
 
 /* Per-cluster RANSAC outputs (caller-owned device buffers).  For cluster k:
@@ -259,6 +262,23 @@ typedef struct {
 vm_status vm_segment_frame(vm_map map, const float* d_xyz, int64_t n, const vm_pose* pose,
                            const vm_seg_params* params, vm_planes* planes, vm_hulls_out* hulls,
                            uint32_t* d_labels, vm_clusters* clusters_out, void* stream);
+
+/* ---- graph capture and replay ------------------------------------------- */
+/* Record the library calls enqueued on `stream` between vm_capture_begin and
+ * vm_capture_end into an executable HIP graph instead of running them
+ * (hipStreamBeginCapture / hipGraphInstantiate).  Every argument of the
+ * captured calls is frozen (pointers, sizes, poses, parameters); only the
+ * contents of device buffers may change between replays (new points in the
+ * same buffer, a device frame counter via vm_ransac_params.d_frame).  Calls
+ * that would have to allocate or synchronise (a first vm_segment_frame on a
+ * map, vm_map_stats, vm_map_export) return VM_E_STATE while capturing; stage
+ * timing is skipped inside captures.  vm_graph_launch enqueues one replay on
+ * `stream`; replays of one graph must not overlap. */
+typedef struct vm_graph_s* vm_graph;
+vm_status vm_capture_begin(void* stream);
+vm_status vm_capture_end(void* stream, vm_graph* out);
+vm_status vm_graph_launch(vm_graph graph, void* stream);
+vm_status vm_graph_destroy(vm_graph graph);
 
 /* ---- per-stage timing ---------------------------------------------------- */
 /* When enabled, every stage kernel of the library is bracketed by HIP events

@@ -26,6 +26,7 @@ EXPORTED = [
     "vm_map_stats_async",
     "vm_insert", "vm_map_export", "vm_map_import", "vm_ccl", "vm_workspace_bytes", "vm_ransac_planes",
     "vm_hulls", "vm_segment_frame", "vm_set_stage_timing", "vm_stage_times",
+    "vm_capture_begin", "vm_capture_end", "vm_graph_launch", "vm_graph_destroy",
 ]
 
 _P = ctypes.c_void_p
@@ -55,7 +56,7 @@ class Clusters(ctypes.Structure):
 
 class RansacParams(ctypes.Structure):
     _fields_ = [("n_hyp", ctypes.c_uint32), ("eps", ctypes.c_float), ("seed", ctypes.c_uint64),
-                ("frame", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("frame", ctypes.c_uint32), ("reserved", ctypes.c_uint32), ("d_frame", _P)]
 
 
 class Planes(ctypes.Structure):
@@ -113,6 +114,10 @@ def lib() -> ctypes.CDLL:
             "vm_segment_frame": ([_P, _P, i64, ctypes.POINTER(Pose), ctypes.POINTER(SegParams),
                                   ctypes.POINTER(Planes), ctypes.POINTER(HullsOut), _P, ctypes.POINTER(Clusters), _P],
                                  i32),
+            "vm_capture_begin": ([_P], i32),
+            "vm_capture_end": ([_P, ctypes.POINTER(_P)], i32),
+            "vm_graph_launch": ([_P, _P], i32),
+            "vm_graph_destroy": ([_P], i32),
             "vm_set_stage_timing": ([i32], i32),
             "vm_stage_times": ([ctypes.POINTER(ctypes.c_double), ctypes.POINTER(u64), i32], i32),
         }
@@ -227,8 +232,10 @@ class HullBuffers:
                         _ptr(self.area), _ptr(self.status))
 
 
-def ransac_params(n_hyp: int, eps: float = 0.01, seed: int = 0x5EED, frame: int = 0) -> RansacParams:
-    return RansacParams(int(n_hyp), float(eps), int(seed) & (2 ** 64 - 1), int(frame) & 0xFFFFFFFF, 0)
+def ransac_params(n_hyp: int, eps: float = 0.01, seed: int = 0x5EED, frame: int = 0, d_frame=None) -> RansacParams:
+    """``d_frame``: optional int32 device tensor holding the frame number (read when the work runs)."""
+    return RansacParams(int(n_hyp), float(eps), int(seed) & (2 ** 64 - 1), int(frame) & 0xFFFFFFFF, 0,
+                        _ptr(d_frame))
 
 
 # --------------------------------------------------------------------------
@@ -317,9 +324,9 @@ class Map:
 
     def segment_frame(self, xyz, planes: PlaneBuffers, hulls: HullBuffers, R=None, t=None, min_cluster: int = 30,
                       n_hyp: int = 256, eps: float = 0.01, seed: int = 0x5EED, frame: int = 0, labels=None,
-                      stream=None) -> Clusters:
+                      stream=None, d_frame=None) -> Clusters:
         pose = make_pose(R, t)
-        sp = SegParams(int(min_cluster), 0, ransac_params(n_hyp, eps, seed, frame))
+        sp = SegParams(int(min_cluster), 0, ransac_params(n_hyp, eps, seed, frame, d_frame))
         cl = Clusters()
         pc, hc = planes.c(), hulls.c()
         n = 0 if xyz is None else int(xyz.shape[0])
@@ -352,6 +359,50 @@ def hulls(cl: Clusters, planes: PlaneBuffers, out: HullBuffers, work, stream=Non
     pc, hc = planes.c(), out.c()
     _check(lib().vm_hulls(ctypes.byref(cl), ctypes.byref(pc), ctypes.byref(hc), _ptr(work),
                           int(work.numel() * work.element_size()), _stream(stream)), "vm_hulls")
+
+
+class Graph:
+    """A captured sequence of library calls (vm_capture_begin/end), replayed with launch()."""
+
+    def __init__(self, handle):
+        self._h = handle
+
+    def launch(self, stream=None) -> None:
+        _check(lib().vm_graph_launch(self._h, _stream(stream)), "vm_graph_launch")
+
+    def close(self) -> None:
+        if self._h is not None and self._h.value:
+            lib().vm_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class capture:
+    """``with vm.capture(stream) as cap: ...library calls...`` then ``cap.graph.launch()``.
+    The stream must not be the null stream (use a torch.cuda.Stream)."""
+
+    def __init__(self, stream):
+        self.stream = stream
+        self.graph = None
+
+    def __enter__(self):
+        _check(lib().vm_capture_begin(_stream(self.stream)), "vm_capture_begin")
+        return self
+
+    def __exit__(self, exc_type, exc, tb):
+        h = _P()
+        st = lib().vm_capture_end(_stream(self.stream), ctypes.byref(h))
+        if exc_type is None:
+            _check(st, "vm_capture_end")
+            self.graph = Graph(h)
+        elif h.value:
+            lib().vm_graph_destroy(h)
+        return False
 
 
 def set_stage_timing(enable: bool) -> None:

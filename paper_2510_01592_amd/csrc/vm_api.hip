@@ -9,6 +9,11 @@
 
 using namespace vm;
 
+struct vm_graph_s {
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
 struct vm_map_s {
     int device = 0;
     Geom g{};
@@ -67,6 +72,8 @@ StageScope::StageScope(int stage, hipStream_t s) : stage_(stage), s_(s), ev0_(nu
     TimingState& t = timing();
     std::lock_guard<std::mutex> lk(t.mu);
     if (!t.enabled) return;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
     hipEvent_t a = take_event(t), b = take_event(t);
     if (!a || !b || hipEventRecord(a, s) != hipSuccess) {
         if (a) t.pool.push_back(a);
@@ -96,6 +103,13 @@ StageScope::~StageScope()
 namespace {
 
 bool bad_ptr(const void* p) { return p == nullptr; }
+
+bool capturing(hipStream_t s)
+{
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &st) != hipSuccess) return false;
+    return st == hipStreamCaptureStatusActive;
+}
 
 vm_status map_alloc(vm_map m, void** p, size_t bytes)
 {
@@ -303,6 +317,7 @@ vm_status vm_map_destroy(vm_map m)
 vm_status vm_map_clear(vm_map m, void* stream)
 {
     if (!m) return VM_E_ARG;
+    if (capturing((hipStream_t)stream)) return VM_E_STATE;   // clears with memset nodes
     VM_HIP(launch_clear(m->g, m->h, m->bits, m->ctr, (hipStream_t)stream));
     m->have_clusters = false;
     return VM_OK;
@@ -311,6 +326,7 @@ vm_status vm_map_clear(vm_map m, void* stream)
 vm_status vm_map_stats(vm_map m, void* stream, vm_map_stats_t* out)
 {
     if (!m || !out) return VM_E_ARG;
+    if (capturing((hipStream_t)stream)) return VM_E_STATE;
     VM_HIP(hipStreamSynchronize((hipStream_t)stream));
     DevCounters c;
     VM_HIP(hipMemcpy(&c, m->ctr, sizeof c, hipMemcpyDeviceToHost));
@@ -344,6 +360,7 @@ vm_status vm_map_export(vm_map m, uint32_t* d_key, uint32_t* d_count, uint64_t* 
                         uint64_t* n_out, void* stream)
 {
     if (!m || !n_out) return VM_E_ARG;
+    if (capturing((hipStream_t)stream)) return VM_E_STATE;
     hipStream_t s = (hipStream_t)stream;
     VM_HIP(launch_rank(m->g, m->bits, m->b, m->cap, m->ctr, s));
     VM_HIP(launch_export(m->g, m->h, m->b, m->ctr, d_key, d_count, (unsigned long long*)d_sum, d_mean, cap, s));
@@ -358,6 +375,7 @@ vm_status vm_map_import(vm_map m, const uint32_t* d_key, const uint32_t* d_count
                         void* stream)
 {
     if (!m || (n > 0 && (!d_key || !d_count || !d_sum))) return VM_E_ARG;
+    if (capturing((hipStream_t)stream)) return VM_E_STATE;
     if (n > m->cap / 2 + m->cap / 4) return VM_E_CAPACITY;
     VM_HIP(launch_import(m->g, m->h, m->bits, m->ctr, d_key, d_count, (const unsigned long long*)d_sum, n,
                          (hipStream_t)stream));
@@ -422,6 +440,7 @@ vm_status vm_segment_frame(vm_map m, const float* d_xyz, int64_t n, const vm_pos
     const uint32_t kb = std::min(map_k_bound(m, minc), planes->k_cap);
     // the map's own workspace: allocated once per (cluster bound, hypotheses)
     if (!m->work || m->work_k < kb || m->work_hyp < params->ransac.n_hyp) {
+        if (capturing((hipStream_t)stream)) return VM_E_STATE;   // no allocation inside a capture
         const uint32_t k = std::max(kb, m->work_k);
         const uint32_t hh = std::max(params->ransac.n_hyp, m->work_hyp);
         const size_t bytes = vm_workspace_bytes(k, m->cap, hh);
@@ -448,6 +467,54 @@ vm_status vm_segment_frame(vm_map m, const float* d_xyz, int64_t n, const vm_pos
     st = ransac_planes(cl, params->ransac, *planes, w, (hipStream_t)stream);
     if (st != VM_OK) return st;
     return hulls(cl, *planes, *hulls_out, w, (hipStream_t)stream);
+}
+
+vm_status vm_capture_begin(void* stream)
+{
+    hipStream_t s = (hipStream_t)stream;
+    if (!s) return VM_E_ARG;   // the null stream cannot be captured
+    if (capturing(s)) return VM_E_STATE;
+    VM_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+    return VM_OK;
+}
+
+vm_status vm_capture_end(void* stream, vm_graph* out)
+{
+    hipStream_t s = (hipStream_t)stream;
+    if (!s || !out) return VM_E_ARG;
+    *out = nullptr;
+    if (!capturing(s)) return VM_E_STATE;
+    hipGraph_t g = nullptr;
+    VM_HIP(hipStreamEndCapture(s, &g));
+    hipGraphExec_t e = nullptr;
+    if (hipGraphInstantiate(&e, g, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return VM_E_DEVICE;
+    }
+    vm_graph r = new (std::nothrow) vm_graph_s{g, e};
+    if (!r) {
+        (void)hipGraphExecDestroy(e);
+        (void)hipGraphDestroy(g);
+        return VM_E_OOM;
+    }
+    *out = r;
+    return VM_OK;
+}
+
+vm_status vm_graph_launch(vm_graph g, void* stream)
+{
+    if (!g) return VM_E_ARG;
+    VM_HIP(hipGraphLaunch(g->exec, (hipStream_t)stream));
+    return VM_OK;
+}
+
+vm_status vm_graph_destroy(vm_graph g)
+{
+    if (!g) return VM_E_ARG;
+    (void)hipGraphExecDestroy(g->exec);
+    (void)hipGraphDestroy(g->graph);
+    delete g;
+    return VM_OK;
 }
 
 vm_status vm_set_stage_timing(int32_t enable)

@@ -55,9 +55,11 @@ __global__ void __launch_bounds__(kBlock) k_hypotheses(const uint32_t* __restric
                                                        const uint32_t* __restrict__ off,
                                                        const uint32_t* __restrict__ tag, const float* __restrict__ X,
                                                        const float* __restrict__ Y, const float* __restrict__ Z,
-                                                       uint32_t H, uint64_t seed, uint32_t frame,
+                                                       uint32_t H, uint64_t seed, uint32_t frame_arg,
+                                                       const uint32_t* __restrict__ d_frame,
                                                        int32_t* __restrict__ counts, float4* __restrict__ hyp)
 {
+    const uint32_t frame = d_frame ? *d_frame : frame_arg;
     const uint32_t K = small[0];
     const uint64_t total = (uint64_t)K * H;
     for (uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
@@ -393,7 +395,8 @@ vm_status ransac_planes(const vm_clusters& cl, const vm_ransac_params& p, const 
         VM_HIP(scan_exclusive_dev(w.tile_off, w.tile_off, w.small, kc, w.small + 1, w.blk, s));
         const uint64_t kh = (uint64_t)kc * H;
         k_hypotheses<<<grid_for(kh, kBlock, 16384), kBlock, 0, s>>>(w.small, cl.d_off, cl.d_tag, cl.d_x, cl.d_y,
-                                                                    cl.d_z, H, p.seed, p.frame, w.counts, w.hyp);
+                                                                    cl.d_z, H, p.seed, p.frame, p.d_frame, w.counts,
+                                                                    w.hyp);
         VM_HIP(hipGetLastError());
     }
     {

@@ -74,9 +74,12 @@ def test_argument_errors_without_device_work():
     # bad RANSAC parameters are rejected before any device pointer is touched
     cl = vm.Clusters(1, 1, 8, 8, 8, 8, 8, None, 8)
     pl = vm.Planes(1, 1, 8, 8, 8, 8, 8, None, None, 8)
+    assert L.vm_capture_begin(None) == vm.VM_E_ARG
+    assert L.vm_graph_launch(None, None) == vm.VM_E_ARG
+    assert L.vm_graph_destroy(None) == vm.VM_E_ARG
     bad = vm.RansacParams(0, 0.01, 1, 0, 0)
     assert L.vm_ransac_planes(ctypes.byref(cl), ctypes.byref(bad), ctypes.byref(pl), 8, 1 << 20, None) == vm.VM_E_ARG
-    bad = vm.RansacParams(16, -1.0, 1, 0, 0)
+    bad = vm.RansacParams(16, -1.0, 1, 0, 0, None)
     assert L.vm_ransac_planes(ctypes.byref(cl), ctypes.byref(bad), ctypes.byref(pl), 8, 1 << 20, None) == vm.VM_E_ARG
     bad = vm.RansacParams(16, 0.01, 1, 0, 7)
     assert L.vm_ransac_planes(ctypes.byref(cl), ctypes.byref(bad), ctypes.byref(pl), 8, 1 << 20, None) == vm.VM_E_ARG
@@ -93,8 +96,8 @@ def test_struct_layouts_match_header_sizes():
     assert ctypes.sizeof(vm.MapDesc) == 3 * 8 + 8 + 3 * 4 + 4 + 4 + 4
     assert ctypes.sizeof(vm.MapStats) == 4 * 8 + 2 * 4 + 8
     assert ctypes.sizeof(vm.Pose) == 12 * 8
-    assert ctypes.sizeof(vm.RansacParams) == 24
-    assert ctypes.sizeof(vm.SegParams) == 32
+    assert ctypes.sizeof(vm.RansacParams) == 32
+    assert ctypes.sizeof(vm.SegParams) == 40
     assert ctypes.sizeof(vm.Clusters) == 8 + 7 * 8
     assert ctypes.sizeof(vm.Planes) == 8 + 8 * 8
     assert ctypes.sizeof(vm.HullsOut) == 8 + 5 * 8
