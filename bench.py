@@ -1,22 +1,27 @@
 #!/usr/bin/env python3
-"""Benchmark: occupied voxels segmented per second, and frame latency, on the
+"""Benchmark: occupied voxels segmented per second and frame latency on the
 full local map workload (4x4x2 m at 0.01 m = 400x400x200 cells, 1M float32
 points per frame with N(0, 3 mm) noise and 5 % outliers, 512 RANSAC
 hypotheses, clusters below 30 voxels dropped), on one MI355X.
 
-A step is one frame of the whole path (vm_segment_frame): insert the frame
-into the resident map, label all occupied voxels, group them, fit one plane
-per cluster and outline it.  The map is first warmed with 30 frames (about
-2M occupied voxels) and keeps growing by the outliers of each new frame, as
-an accumulating map does; the metric sums the occupied voxels each step
-segmented.  Frames are resident in HBM before the timed region starts.
+A step is one frame of the whole path: insert the frame into the resident
+map, label all occupied voxels, group them, fit one plane per cluster and
+outline it.  The map is warmed with 30 frames (about 1.95M occupied voxels)
+and keeps growing by each frame's outliers, as an accumulating map does; the
+metric sums the occupied voxels each step segmented.  Frames are resident in
+HBM before a timed region starts.  Two forms run on the same starting map
+(snapshot/restore) and the same frames:
+  plain  -- one vm_segment_frame call per frame;
+  graph  -- the frame captured once as a HIP graph and replayed (the frame's
+            points copied into the captured input buffer, the RANSAC frame
+            number advanced in device memory).
+`value` is the graph form's throughput; the plain form is reported beside it.
 
-Prints one JSON line (see the keys below)."""
+Prints one JSON line."""
 from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -29,6 +34,10 @@ if ROOT not in sys.path:
 
 METRIC = "occupied voxels segmented/s and p50/p99 frame latency, plain vs batched/served @0.01 m"
 HBM_PEAK_GBS = 8000.0
+# vector ALU: 256 CUs x 64 lanes x 2.4 GHz lane-instructions/s; one inlier
+# test is 3 v_fma_f32 + 1 v_cmp (packed fp32 off), so 4 lane-instructions
+VALU_LANE_OPS = 256 * 64 * 2.4e9
+COUNT_PEAK_GEVAL = VALU_LANE_OPS / 4 / 1e9
 
 
 def _log(msg: str) -> None:
@@ -44,6 +53,7 @@ def main() -> int:
     ap.add_argument("--latency-frames", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-frames", type=int, default=1)
+    ap.add_argument("--no-batched", action="store_true", help="skip the 2000-cluster batched measurement")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -60,19 +70,27 @@ def main() -> int:
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    stream = torch.cuda.Stream()
 
     sc = scenes.scene_full_map(1)
     g = sc.geom
     H, eps, minc, seed = sc.n_hyp, sc.eps, sc.min_cluster, 0x5EED
     m = vm.Map(g.origin, g.voxel_size, g.dims, 23)
 
-    # ---- pre-warm the map (not timed) -------------------------------------
+    # ---- pre-warm the map and keep a snapshot (not timed) -------------------
     t0 = time.perf_counter()
-    for f in range(args.prewarm):
-        m.insert(torch.from_numpy(scenes.frame_points(sc, 2 + f)).to(dev))
-    torch.cuda.synchronize()
-    v_prewarm = int(m.stats().occupied)
+    with torch.cuda.stream(stream):
+        for f in range(args.prewarm):
+            m.insert(torch.from_numpy(scenes.frame_points(sc, 2 + f)).to(dev), stream=stream)
+    stream.synchronize()
+    snap = m.export(stream=stream)
+    v_prewarm = int(snap[0].shape[0])
     _log(f"prewarm {args.prewarm} frames -> {v_prewarm} occupied voxels ({time.perf_counter() - t0:.1f}s)")
+
+    def restore():
+        with torch.cuda.stream(stream):
+            m.import_(snap[0], snap[1], snap[2], stream=stream)
+        stream.synchronize()
 
     n_frames = args.warmup + args.steps
     frames = [torch.from_numpy(scenes.frame_points(sc, 1000 + i)).to(dev) for i in range(n_frames)]
@@ -80,97 +98,137 @@ def main() -> int:
     planes = vm.PlaneBuffers.alloc(k_cap, 1 << 23, H)
     hulls = vm.HullBuffers.alloc(k_cap, 1 << 22)
     stats_dev = torch.zeros((n_frames + 1, 6), dtype=torch.int64, device=dev)
-
+    stage = torch.empty((sc.n_points, 3), dtype=torch.float32, device=dev)
+    frame_t = torch.zeros(1, dtype=torch.int32, device=dev)
+    kw = dict(min_cluster=minc, n_hyp=H, eps=eps, seed=seed)
     last = {}
 
-    def step(i: int) -> None:
-        last["cl"] = m.segment_frame(frames[i], planes, hulls, min_cluster=minc, n_hyp=H, eps=eps, seed=seed,
-                                     frame=i)
-        m.stats_async(stats_dev[i])
+    # ---- plain form ------------------------------------------------------------
+    def plain_step(i: int) -> None:
+        last["cl"] = m.segment_frame(frames[i], planes, hulls, frame=i, stream=stream, **kw)
+        m.stats_async(stats_dev[i], stream=stream)
 
-    for i in range(args.warmup):
-        step(i)
-    torch.cuda.synchronize()
-    _log(f"warmup {args.warmup} steps done")
-
-    # ---- timed region: K steps back to back on one stream -------------------
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for i in range(args.warmup, n_frames):
-        step(i)
-    torch.cuda.synchronize()
-    t_total = time.perf_counter() - t_start
-    st = stats_dev.cpu().numpy()
-    occ = st[args.warmup:n_frames, 0].astype(np.int64)       # occupied voxels segmented by each step
-    voxels = int(occ.sum())
-    value = voxels / t_total
-    ms_per_step = 1e3 * t_total / args.steps
-    _log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step, {value / 1e6:.1f} M voxels/s, "
+    restore()
+    with torch.cuda.stream(stream):
+        for i in range(args.warmup):
+            plain_step(i)
+        stream.synchronize()
+        t_s = time.perf_counter()
+        for i in range(args.warmup, n_frames):
+            plain_step(i)
+        stream.synchronize()
+        t_plain = time.perf_counter() - t_s
+    occ = stats_dev.cpu().numpy()[args.warmup:n_frames, 0].astype(np.int64)
+    plain_value = float(occ.sum()) / t_plain
+    _log(f"plain: {1e3 * t_plain / args.steps:.3f} ms/step, {plain_value / 1e6:.1f} M voxels/s, "
          f"occupied {occ[0]}..{occ[-1]}")
 
-    # ---- per-stage device time (HIP events on the stream the kernels run on) --
-    vm.set_stage_timing(True)
-    n_stage = min(5, args.steps)
-    for i in range(n_stage):
-        step(args.warmup + i)
-    torch.cuda.synchronize()
-    ms, launches = vm.stage_times()
-    vm.set_stage_timing(False)
-    stage_ms = {name: float(ms[j]) / n_stage for j, name in enumerate(vm.STAGES)}
-    _log("stage ms/frame: " + ", ".join(f"{k}={v:.3f}" for k, v in stage_ms.items()))
+    # ---- graph form: the frame captured once, replayed per frame ---------------
+    restore()
+    stats_slot = torch.zeros(6, dtype=torch.int64, device=dev)
+    with torch.cuda.stream(stream):
+        with vm.capture(stream) as cap:
+            last["cl"] = m.segment_frame(stage, planes, hulls, d_frame=frame_t, stream=stream, **kw)
+            m.stats_async(stats_slot, stream=stream)
+    graph = cap.graph
+    stats_dev.zero_()
 
-    # ---- frame latency: pinned host frame -> results in host memory ----------
-    lat = []
-    host_frames = [torch.from_numpy(scenes.frame_points(sc, 5000 + i)).pin_memory()
-                   for i in range(min(args.latency_frames, 8))]
+    def graph_step(i: int) -> None:
+        stage.copy_(frames[i])
+        frame_t.fill_(i)
+        graph.launch(stream)
+        stats_dev[i].copy_(stats_slot)
+
+    with torch.cuda.stream(stream):
+        for i in range(args.warmup):
+            graph_step(i)
+        stream.synchronize()
+        t_s = time.perf_counter()
+        for i in range(args.warmup, n_frames):
+            graph_step(i)
+        stream.synchronize()
+        t_graph = time.perf_counter() - t_s
+    occ_g = stats_dev.cpu().numpy()[args.warmup:n_frames, 0].astype(np.int64)
+    assert np.array_equal(occ_g, occ), "graph replays must see the same maps as direct calls"
+    value = float(occ_g.sum()) / t_graph
+    ms_per_step = 1e3 * t_graph / args.steps
+    _log(f"graph: {ms_per_step:.3f} ms/step, {value / 1e6:.1f} M voxels/s")
+
+    # ---- frame latency: pinned host frame -> results in host memory -------------
+    host_frames = [torch.from_numpy(scenes.frame_points(sc, 5000 + i)).pin_memory() for i in range(4)]
     res_plane = torch.empty((k_cap, 4), dtype=torch.float32).pin_memory()
     res_area = torch.empty(k_cap, dtype=torch.float64).pin_memory()
     res_voff = torch.empty(k_cap + 1, dtype=torch.int32).pin_memory()
     res_stat = torch.empty(2, dtype=torch.int32).pin_memory()
-    dframe = torch.empty((sc.n_points, 3), dtype=torch.float32, device=dev)
-    for i in range(args.latency_frames):
-        hf = host_frames[i % len(host_frames)]
-        torch.cuda.synchronize()
-        ta = time.perf_counter()
-        dframe.copy_(hf, non_blocking=True)
-        last["cl"] = m.segment_frame(dframe, planes, hulls, min_cluster=minc, n_hyp=H, eps=eps, seed=seed,
-                                     frame=10000 + i)
+
+    def fetch():
         res_plane.copy_(planes.plane, non_blocking=True)
         res_area.copy_(hulls.area, non_blocking=True)
         res_voff.copy_(hulls.v_off, non_blocking=True)
         res_stat[0:1].copy_(planes.status, non_blocking=True)
         res_stat[1:2].copy_(hulls.status, non_blocking=True)
-        torch.cuda.synchronize()
-        lat.append(1e3 * (time.perf_counter() - ta))
-    lat = np.array(lat)
-    p50, p99 = float(np.percentile(lat, 50)), float(np.percentile(lat, 99))
-    _log(f"latency p50 {p50:.2f} ms p99 {p99:.2f} ms over {len(lat)} frames")
 
-    # ---- roofline of the dominant kernel --------------------------------------
-    # inlier counting: 3 fma + 1 abs-compare per point x hypothesis, all lanes
-    # (vector ALU bound); its work per launch is sum_k n_k * H evaluations.
+    lat = {"plain": [], "graph": []}
+    with torch.cuda.stream(stream):
+        for i in range(args.latency_frames):
+            hf = host_frames[i % len(host_frames)]
+            for form in ("graph", "plain"):
+                stream.synchronize()
+                ta = time.perf_counter()
+                stage.copy_(hf, non_blocking=True)
+                if form == "graph":
+                    frame_t.fill_(20000 + i)
+                    graph.launch(stream)
+                else:
+                    m.segment_frame(stage, planes, hulls, frame=20000 + i, stream=stream, **kw)
+                fetch()
+                stream.synchronize()
+                lat[form].append(1e3 * (time.perf_counter() - ta))
+    lat_out = {}
+    for form, v in lat.items():
+        a = np.array(v)
+        lat_out[form] = {"p50": float(np.percentile(a, 50)), "p99": float(np.percentile(a, 99)), "frames": len(a)}
+    _log(f"latency graph p50 {lat_out['graph']['p50']:.2f} p99 {lat_out['graph']['p99']:.2f} ms; "
+         f"plain p50 {lat_out['plain']['p50']:.2f} p99 {lat_out['plain']['p99']:.2f} ms")
+
+    # ---- per-stage device time (HIP events on the library's stream) -------------
+    restore()
+    vm.set_stage_timing(True)
+    n_stage = min(5, args.steps)
+    with torch.cuda.stream(stream):
+        for i in range(n_stage):
+            last["cl"] = m.segment_frame(frames[args.warmup + i], planes, hulls, frame=args.warmup + i,
+                                         stream=stream, **kw)
+        stream.synchronize()
+    ms, _ = vm.stage_times()
+    stage_ms = {name: float(ms[j]) / n_stage for j, name in enumerate(vm.STAGES)}
+    # inlier counting timed alone (standalone calls keep the GPU busy, so the
+    # events bracket the kernel itself); the last frame's clusters, all of them
+    work = torch.empty(vm.workspace_bytes(k_cap, last["cl"].n_cap, H), dtype=torch.uint8, device=dev)
+    reps = 10
+    with torch.cuda.stream(stream):
+        for r in range(reps):
+            vm.ransac_planes(last["cl"], vm.ransac_params(H, eps, seed, r), planes, work, stream=stream)
+        stream.synchronize()
+    ms2, n2 = vm.stage_times()
+    vm.set_stage_timing(False)
+    count_ms = float(ms2[vm.STAGES.index("count")]) / reps
     cl_meta = vm.read_clusters(last["cl"])
     n_pts = cl_meta["N"]
     evals = float(n_pts) * H
-    stage_name = max(stage_ms, key=stage_ms.get)
-    roof = None
-    insert_bytes = 12.0 * sc.n_points
-    if stage_name == "count":
-        # peak: 256 CUs x 64 lanes x 2.4 GHz = 39.3 T lane-ops/s; 4 ops per evaluation
-        peak_geval = 256 * 64 * 2.4e9 / 4 / 1e9
-        ach = evals / (stage_ms["count"] * 1e-3) / 1e9
-        roof = {"bound": "alu", "achieved": ach, "peak": peak_geval, "unit": "Geval/s", "frac": ach / peak_geval,
-                "traffic": None, "kernel": "k_count"}
-    else:
-        per = {"insert": insert_bytes}
-        algo = per.get(stage_name)
-        if algo is not None:
-            ach = algo / (stage_ms[stage_name] * 1e-3) / 1e9
-            roof = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
-                    "traffic": None, "kernel": stage_name}
-        else:
-            roof = {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": None,
-                    "traffic": None, "kernel": stage_name}
+    _log("stage ms/frame: " + ", ".join(f"{k}={v:.3f}" for k, v in stage_ms.items()) +
+         f"; k_count alone {count_ms:.3f} ms for {evals / 1e6:.0f}M evaluations")
+    ach = evals / (count_ms * 1e-3) / 1e9
+    roof = {"bound": "alu", "achieved": ach, "peak": COUNT_PEAK_GEVAL, "unit": "Geval/s",
+            "frac": ach / COUNT_PEAK_GEVAL, "traffic": None, "kernel": "k_count",
+            "work_per_launch": f"{n_pts} points x {H} hypotheses",
+            "peak_derivation": "256 CU x 64 lanes x 2.4 GHz / 4 VALU instructions per point-plane test"}
+
+    # ---- batched clusters: 2000 log-uniform clusters, one pass, graph replays ------
+    batched = None
+    if not args.no_batched:
+        batched = _batched(vm, torch, dev, stream)
+        _log(f"batched: {batched}")
 
     # ---- the oracle on the host, bounded sample ---------------------------------
     cpu = None
@@ -178,6 +236,7 @@ def main() -> int:
         cpu = _cpu_baseline(sc, args.prewarm, args.cpu_frames, H, eps, minc, seed)
         _log(f"cpu baseline: {cpu}")
 
+    graph.close()
     out = {
         "metric": METRIC,
         "value": value,
@@ -195,22 +254,84 @@ def main() -> int:
             "workload": "full local map: 4x4x2 m at 0.01 m (400x400x200 cells), floor + 12-step open-tread "
                         "staircase + tabletop + 20 tilted patches, 1M float32 points/frame, N(0,3 mm), 5% outliers, "
                         "512 hypotheses, eps 0.01 m, min cluster 30",
-            "form": "plain",
+            "form": "graph (captured frame replayed)",
             "prewarm_frames": args.prewarm,
             "occupied_first_step": int(occ[0]),
             "occupied_last_step": int(occ[-1]),
             "points_per_frame": sc.n_points,
             "n_hyp": H,
         },
-        "latency_ms": {"p50": p50, "p99": p99, "frames": len(lat),
-                       "includes": "H2D of the frame from pinned host memory, vm_segment_frame, D2H of planes, "
-                                   "areas, polygon offsets and status words"},
+        "forms": {
+            "plain": {"value": plain_value, "ms_per_step": 1e3 * t_plain / args.steps},
+            "graph": {"value": value, "ms_per_step": ms_per_step},
+        },
+        "latency_ms": dict(lat_out, includes="H2D of the frame from pinned host memory, the frame, D2H of planes, "
+                                             "areas, polygon offsets and status words"),
         "stage_ms_per_frame": stage_ms,
         "roofline": roof,
+        "batched": batched,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
     return 0
+
+
+def _batched(vm, torch, dev, stream, replays: int = 100):
+    """2000 clusters of log-uniform size (50..200k points, about 48.5M in all),
+    1024 hypotheses: planes and hulls of all clusters in one pass, captured as
+    a graph and replayed `replays` times with the frame number advanced in
+    device memory (the data stays resident)."""
+    import scenes
+    t0 = time.perf_counter()
+    off, xyz = scenes.batched_clusters(seed=3)
+    K, N, H = len(off) - 1, len(xyz), 1024
+    cl, keep = vm.clusters_from_host(off, xyz, np.arange(K, dtype=np.uint32))
+    gen_s = time.perf_counter() - t0
+    work = torch.empty(vm.workspace_bytes(K, N, H), dtype=torch.uint8, device=dev)
+    planes = vm.PlaneBuffers.alloc(K, N, H)
+    hulls = vm.HullBuffers.alloc(K, N)
+    frame_t = torch.zeros(1, dtype=torch.int32, device=dev)
+    with torch.cuda.stream(stream):
+        vm.ransac_planes(cl, vm.ransac_params(H, 0.01, 0x5EED, 0), planes, work, stream=stream)
+        vm.hulls(cl, planes, hulls, work, stream=stream)
+        stream.synchronize()
+        t_s = time.perf_counter()
+        for f in range(3):
+            vm.ransac_planes(cl, vm.ransac_params(H, 0.01, 0x5EED, f), planes, work, stream=stream)
+            vm.hulls(cl, planes, hulls, work, stream=stream)
+        stream.synchronize()
+        plain_ms = 1e3 * (time.perf_counter() - t_s) / 3
+        with vm.capture(stream) as cap:
+            vm.ransac_planes(cl, vm.ransac_params(H, 0.01, 0x5EED, d_frame=frame_t), planes, work, stream=stream)
+            vm.hulls(cl, planes, hulls, work, stream=stream)
+        cap.graph.launch(stream)
+        stream.synchronize()
+        t_s = time.perf_counter()
+        for f in range(replays):
+            frame_t.fill_(f)
+            cap.graph.launch(stream)
+        stream.synchronize()
+        graph_ms = 1e3 * (time.perf_counter() - t_s) / replays
+        vm.set_stage_timing(True)
+        for f in range(3):
+            vm.ransac_planes(cl, vm.ransac_params(H, 0.01, 0x5EED, f), planes, work, stream=stream)
+        stream.synchronize()
+        ms, _ = vm.stage_times()
+        vm.set_stage_timing(False)
+    cap.graph.close()
+    count_ms = float(ms[vm.STAGES.index("count")]) / 3
+    evals = float(N) * H
+    ach = evals / (count_ms * 1e-3) / 1e9
+    st = int(planes.status.cpu()[0]) | int(hulls.status.cpu()[0])
+    del keep
+    return {"workload": f"{K} clusters, log-uniform 50..200k points ({N} in all), {H} hypotheses, "
+                        "planes + hulls of all clusters per frame",
+            "ms_per_frame_graph": graph_ms, "ms_per_frame_plain": plain_ms, "replays": replays,
+            "points_per_s_graph": N / (graph_ms * 1e-3), "evaluations_per_s_graph": evals / (graph_ms * 1e-3),
+            "k_count_ms": count_ms,
+            "roofline_k_count": {"bound": "alu", "achieved": ach, "peak": COUNT_PEAK_GEVAL, "unit": "Geval/s",
+                                 "frac": ach / COUNT_PEAK_GEVAL},
+            "status_flags": st, "generation_s": gen_s}
 
 
 def _cpu_baseline(sc, prewarm, n_frames, H, eps, minc, seed):

@@ -286,15 +286,16 @@ vm_status vm_graph_destroy(vm_graph graph);
  * recorded event and returns accumulated milliseconds and launch counts per
  * stage (index = VM_STAGE_*), then resets them.  Costs an event pair per
  * launch, so leave it off outside measurements. */
-#define VM_STAGE_INSERT      0
-#define VM_STAGE_RANK        1
-#define VM_STAGE_CCL         2
-#define VM_STAGE_GROUP       3
-#define VM_STAGE_HYPOTHESES  4
-#define VM_STAGE_COUNT       5
-#define VM_STAGE_SELECT      6
-#define VM_STAGE_HULL        7
-#define VM_STAGE_N           8
+#define VM_STAGE_INSERT      0   /* voxelise + sort + slot updates (or per-point atomics) */
+#define VM_STAGE_RANK        1   /* occupancy ranks and the sorted occupied keys */
+#define VM_STAGE_CCL         2   /* in-tile labelling (one kernel) */
+#define VM_STAGE_CCL_LINK    3   /* cross-tile hooks + flatten */
+#define VM_STAGE_GROUP       4   /* sizes, cluster ids, sort, CSR gather */
+#define VM_STAGE_HYPOTHESES  5   /* validation, tile list, hypotheses */
+#define VM_STAGE_COUNT       6   /* inlier counting (one kernel) */
+#define VM_STAGE_SELECT      7   /* best hypothesis, inlier CSR */
+#define VM_STAGE_HULL        8   /* polygons */
+#define VM_STAGE_N           9
 vm_status vm_set_stage_timing(int32_t enable);
 vm_status vm_stage_times(double* ms_out, uint64_t* launches_out, int32_t n);
 

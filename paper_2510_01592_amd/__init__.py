@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libvm.so")
 
 VM_OK, VM_E_ARG, VM_E_OOM, VM_E_CAPACITY, VM_E_DEVICE, VM_E_STATE = 0, -1, -2, -3, -4, -5
 FLAG_HASH_FULL, FLAG_CLUSTERS_CAP, FLAG_INLIERS_CAP, FLAG_HULL_CAP = 0x1, 0x2, 0x4, 0x8
-STAGES = ["insert", "rank", "ccl", "group", "hypotheses", "count", "select", "hull"]
+STAGES = ["insert", "rank", "ccl", "ccl_link", "group", "hypotheses", "count", "select", "hull"]
 
 EXPORTED = [
     "vm_status_string", "vm_version", "vm_map_create", "vm_map_destroy", "vm_map_clear", "vm_map_stats",
@@ -343,6 +343,23 @@ def cluster_view(off, x, y, z, tag, meta, key=None) -> Clusters:
     K = int(tag.shape[0])
     N = int(x.shape[0])
     return Clusters(K, N, _ptr(meta), _ptr(off), _ptr(x), _ptr(y), _ptr(z), _ptr(key), _ptr(tag))
+
+
+def clusters_from_host(off, xyz, tag):
+    """Upload a host CSR (off uint32[K+1], xyz float32[N,3], tag uint32[K]) to
+    device tensors and return (vm_clusters view, dict of the owning tensors;
+    keep it alive while the view is used)."""
+    import torch
+    off = np.ascontiguousarray(np.asarray(off, np.uint32))
+    xyz = np.asarray(xyz, np.float32).reshape(-1, 3)
+    tag = np.ascontiguousarray(np.asarray(tag, np.uint32))
+    t = dict(off=torch.from_numpy(off.view(np.int32)).cuda(),
+             x=torch.from_numpy(np.ascontiguousarray(xyz[:, 0])).cuda(),
+             y=torch.from_numpy(np.ascontiguousarray(xyz[:, 1])).cuda(),
+             z=torch.from_numpy(np.ascontiguousarray(xyz[:, 2])).cuda(),
+             tag=torch.from_numpy(tag.view(np.int32)).cuda(),
+             meta=torch.tensor([len(tag), len(xyz)], dtype=torch.int32).cuda())
+    return cluster_view(t["off"], t["x"], t["y"], t["z"], t["tag"], t["meta"]), t
 
 
 def workspace_bytes(k_cap: int, n_cap: int, n_hyp: int) -> int:

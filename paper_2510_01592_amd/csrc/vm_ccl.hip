@@ -83,40 +83,6 @@ struct Dims {
     uint32_t nx, ny, nz, nxy;
 };
 
-__global__ void __launch_bounds__(kBlock) k_ccl_init(const uint32_t* __restrict__ bits,
-                                                     const uint32_t* __restrict__ occ_key,
-                                                     const DevCounters* __restrict__ ctr, Dims d,
-                                                     uint32_t* __restrict__ parent, uint32_t* __restrict__ linked)
-{
-    const uint32_t V = ctr->n_occ;
-    for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < V; r += gridDim.x * blockDim.x) {
-        const uint32_t key = occ_key[r];
-        const uint32_t x = key % d.nx;
-        const uint32_t rowstart = key - x;
-        // smallest key of the run of occupied cells ending at `key`
-        const uint32_t w = key >> 5, b = key & 31;
-        uint32_t start;
-        const uint32_t zeros = (~bits[w]) & ((1u << b) - 1u);
-        if (zeros) {
-            start = (w << 5) + 32u - __clz(zeros);
-        } else {
-            start = w << 5;
-            uint32_t ww = w;
-            while (start > rowstart && ww > 0) {
-                --ww;
-                const uint32_t z = ~bits[ww];
-                if (z) { start = (ww << 5) + 32u - __clz(z); break; }
-                start = ww << 5;
-            }
-        }
-        if (start < rowstart) start = rowstart;
-        parent[r] = r - (key - start);
-        // part of a run of two or more voxels along x?
-        const bool next = (x + 1 < d.nx) && occ(bits, key + 1);
-        linked[r] = (start < key || next) ? 1u : 0u;
-    }
-}
-
 // a voxel joined to another across rows: both ends are marked (stores of 1
 // only, so concurrent marks cannot conflict)
 __device__ __forceinline__ void link(uint32_t* parent, uint32_t* linked, uint32_t a, uint32_t b)
@@ -126,33 +92,180 @@ __device__ __forceinline__ void link(uint32_t* parent, uint32_t* linked, uint32_
     uf_unite(parent, a, b);
 }
 
-__global__ void __launch_bounds__(kBlock) k_ccl_merge(const uint32_t* __restrict__ bits,
-                                                      const uint32_t* __restrict__ wrank,
-                                                      const uint32_t* __restrict__ occ_key,
-                                                      const DevCounters* __restrict__ ctr, Dims d,
-                                                      uint32_t* parent, uint32_t* linked)
+// ---- tiled labelling ------------------------------------------------------------
+// The grid is cut into 32 x 16 x 16-cell tiles, one workgroup each.  Thread
+// j of the workgroup owns local row j (y = j % 16, z = j / 16), 32 cells along
+// x as one 32-bit occupancy word.  Inside a tile the components are found with
+// a union-find in LDS (parents are local cell indices, hooked with LDS CAS);
+// local cell order is the same as key order, so every local root is the
+// smallest key of its local component.  Each occupied voxel then stores, as
+// its global parent, the rank of its local root.  Adjacencies that cross a
+// tile face are hooked afterwards by k_ccl_boundary with the global
+// union-find; only those need device-wide atomics.
+constexpr int kTX = 32, kTY = 16, kTZ = 16;
+constexpr int kTileCells = kTX * kTY * kTZ;   // 8192
+constexpr int kTileRows = kTY * kTZ;          // 256 = threads per workgroup
+static_assert(kTileRows == kBlock, "one thread per tile row");
+
+struct TileGrid {
+    uint32_t ntx, nty, ntz;
+};
+
+// 32 occupancy bits of grid row (y, z) starting at x0 (bits beyond NX cleared)
+__device__ __forceinline__ uint32_t row_bits(const uint32_t* __restrict__ bits, uint32_t nwords, const Dims& d,
+                                             uint32_t x0, uint32_t y, uint32_t z, uint32_t* key0_out)
 {
-    const uint32_t V = ctr->n_occ;
-    for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < V; r += gridDim.x * blockDim.x) {
-        const uint32_t key = occ_key[r];
-        const uint32_t x = key % d.nx;
-        const uint32_t y = (key / d.nx) % d.ny;
-        const uint32_t z = key / d.nxy;
-        const bool run_start = (x == 0) || !occ(bits, key - 1);
-        const bool run_end = (x + 1 == d.nx) || !occ(bits, key + 1);
-        // the four rows with smaller keys: (dy, dz) = (-1,0), (-1,-1), (0,-1), (+1,-1)
+    if (y >= d.ny || z >= d.nz) {
+        *key0_out = 0;
+        return 0u;
+    }
+    const uint32_t key0 = x0 + d.nx * (y + d.ny * z);
+    *key0_out = key0;
+    const uint32_t w = key0 >> 5, sh = key0 & 31;
+    uint32_t v = bits[w] >> sh;
+    if (sh && w + 1 < nwords) v |= bits[w + 1] << (32 - sh);
+    const uint32_t xcount = d.nx - x0 < 32u ? d.nx - x0 : 32u;
+    if (xcount < 32u) v &= (1u << xcount) - 1u;
+    return v;
+}
+
+__device__ __forceinline__ bool bit_at(uint32_t w, int x) { return x >= 0 && x < 32 && ((w >> x) & 1u); }
+
+__device__ __forceinline__ uint32_t lds_find(const uint32_t* par, uint32_t x)
+{
+    uint32_t p = par[x];
+    while (p != x) {
+        x = p;
+        p = par[x];
+    }
+    return x;
+}
+
+__device__ __forceinline__ void lds_unite(uint32_t* par, uint32_t a, uint32_t b)
+{
+    a = lds_find(par, a);
+    b = lds_find(par, b);
+    while (a != b) {
+        if (a < b) { const uint32_t t = a; a = b; b = t; }
+        const uint32_t old = atomicCAS(&par[a], a, b);
+        if (old == a) return;
+        a = lds_find(par, old);
+        b = lds_find(par, b);
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_ccl_tile(const uint32_t* __restrict__ bits, uint32_t nwords,
+                                                     const uint32_t* __restrict__ wrank, Dims d, TileGrid tg,
+                                                     uint32_t* __restrict__ parent, uint32_t* __restrict__ linked)
+{
+    __shared__ uint32_t rowv[kTileRows];
+    __shared__ uint32_t rowrank[kTileRows];
+    __shared__ uint32_t members[kTileCells / 32];
+    __shared__ uint32_t par[kTileCells];
+    __shared__ uint16_t root[kTileCells];
+    const uint32_t ntiles = tg.ntx * tg.nty * tg.ntz;
+    const uint32_t j = threadIdx.x;
+    const int yl = (int)(j % kTY), zl = (int)(j / kTY);
+    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const uint32_t tx = t % tg.ntx, ty = (t / tg.ntx) % tg.nty, tz = t / (tg.ntx * tg.nty);
+        const uint32_t x0 = tx * kTX, y = ty * kTY + yl, z = tz * kTZ + zl;
+        uint32_t key0;
+        const uint32_t v = row_bits(bits, nwords, d, x0, y, z, &key0);
+        rowv[j] = v;
+        members[j] = 0;
+        // rank of the row's first cell (occupied cells before it)
+        rowrank[j] = v ? wrank[key0 >> 5] + __popc(bits[key0 >> 5] & ((1u << (key0 & 31)) - 1u)) : 0u;
+        // local parents: the start of each cell's run along x inside the row
+        for (uint32_t m = v; m; m &= m - 1) {
+            const int xl = __ffs(m) - 1;
+            const uint32_t zeros = ~v & ((1u << xl) - 1u);
+            const int start = zeros ? 32 - __clz(zeros) : 0;
+            par[j * kTX + xl] = j * kTX + (uint32_t)start;
+        }
+        // barrier + vote: a tile without occupied cells is skipped by all threads
+        if (!__syncthreads_or(v != 0u)) continue;
+        // hook runs of the four neighbouring rows with smaller keys (in the tile)
+        for (uint32_t m = v; m; m &= m - 1) {
+            const int xl = __ffs(m) - 1;
+            const bool run_start = xl == 0 || !bit_at(v, xl - 1);
+            const bool run_end = xl == 31 || !bit_at(v, xl + 1);
+            const uint32_t c = j * kTX + xl;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int dy = (j == 0) ? -1 : (j - 2);
-            const int dz = (j == 0) ? 0 : -1;
-            if ((dz < 0 && z == 0) || (dy < 0 && y == 0) || (dy > 0 && y + 1 == d.ny)) continue;
-            const uint32_t nk = (uint32_t)((int64_t)key + (int64_t)dy * d.nx + (int64_t)dz * d.nxy);
-            if (occ(bits, nk) && (run_start || !occ(bits, nk - 1)))
-                link(parent, linked, r, rank_of(bits, wrank, nk));
-            if (run_start && x > 0 && occ(bits, nk - 1))
-                link(parent, linked, r, rank_of(bits, wrank, nk - 1));
-            if (run_end && x + 1 < d.nx && occ(bits, nk + 1))
-                link(parent, linked, r, rank_of(bits, wrank, nk + 1));
+            for (int q = 0; q < 4; ++q) {
+                const int dy = (q == 0) ? -1 : (q - 2);
+                const int dz = (q == 0) ? 0 : -1;
+                const int ny2 = yl + dy, nz2 = zl + dz;
+                if (ny2 < 0 || ny2 >= kTY || nz2 < 0) continue;
+                const uint32_t nr = (uint32_t)(ny2 + kTY * nz2);
+                const uint32_t w = rowv[nr];
+                if (bit_at(w, xl) && (run_start || !bit_at(w, xl - 1))) lds_unite(par, c, nr * kTX + xl);
+                if (run_start && bit_at(w, xl - 1)) lds_unite(par, c, nr * kTX + xl - 1);
+                if (run_end && bit_at(w, xl + 1)) lds_unite(par, c, nr * kTX + xl + 1);
+            }
+        }
+        __syncthreads();
+        // roots by read-only walks into a separate array (nobody writes par now)
+        for (uint32_t m = v; m; m &= m - 1) {
+            const int xl = __ffs(m) - 1;
+            const uint32_t rt = lds_find(par, j * kTX + xl);
+            root[j * kTX + xl] = (uint16_t)rt;
+            if (rt != j * kTX + xl) atomicOr(&members[rt >> 5], 1u << (rt & 31));
+        }
+        __syncthreads();
+        // global parents: the rank of the local root; a voxel is linked if its
+        // local component has another member
+        for (uint32_t m = v; m; m &= m - 1) {
+            const int xl = __ffs(m) - 1;
+            const uint32_t c = j * kTX + xl, rt = root[c];
+            const uint32_t r = rowrank[j] + __popc(v & ((1u << xl) - 1u));
+            const uint32_t rrow = rt / kTX, rx = rt % kTX;
+            const uint32_t rr = rowrank[rrow] + __popc(rowv[rrow] & ((1u << rx) - 1u));
+            parent[r] = rr;
+            linked[r] = (rt != c || ((members[c >> 5] >> (c & 31)) & 1u)) ? 1u : 0u;
+        }
+        __syncthreads();   // LDS is reused by the next tile
+    }
+}
+
+__device__ __forceinline__ bool occ_cell(const uint32_t* __restrict__ bits, const Dims& d, int x, int y, int z)
+{
+    if (x < 0 || y < 0 || z < 0 || x >= (int)d.nx || y >= (int)d.ny || z >= (int)d.nz) return false;
+    return occ(bits, (uint32_t)x + d.nx * ((uint32_t)y + d.ny * (uint32_t)z));
+}
+
+// Cross-tile adjacencies: every occupied cell on a tile face hooks its
+// occupied neighbours with smaller keys that lie in another tile.
+__global__ void __launch_bounds__(kBlock) k_ccl_boundary(const uint32_t* __restrict__ bits, uint32_t nwords,
+                                                         const uint32_t* __restrict__ wrank, Dims d, TileGrid tg,
+                                                         uint32_t* parent, uint32_t* linked)
+{
+    const uint32_t ntiles = tg.ntx * tg.nty * tg.ntz;
+    const uint32_t j = threadIdx.x;
+    const int yl = (int)(j % kTY), zl = (int)(j / kTY);
+    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const uint32_t tx = t % tg.ntx, ty = (t / tg.ntx) % tg.nty, tz = t / (tg.ntx * tg.nty);
+        const uint32_t x0 = tx * kTX;
+        const int y = (int)(ty * kTY) + yl, z = (int)(tz * kTZ) + zl;
+        uint32_t key0;
+        uint32_t v = row_bits(bits, nwords, d, x0, (uint32_t)y, (uint32_t)z, &key0);
+        const bool yface = yl == 0 || yl == kTY - 1, zface = zl == 0;
+        if (!yface && !zface) v &= (1u << 0) | (1u << 31);   // interior rows: only the x faces
+        for (uint32_t m = v; m; m &= m - 1) {
+            const int xl = __ffs(m) - 1;
+            const int x = (int)x0 + xl;
+            uint32_t r = kEmpty;
+            for (int dz = -1; dz <= 0; ++dz)
+                for (int dy = -1; dy <= 1; ++dy)
+                    for (int dx = -1; dx <= 1; ++dx) {
+                        // the 13 neighbours with smaller keys
+                        if (dz == 0 && (dy > 0 || (dy == 0 && dx >= 0))) continue;
+                        const int lx = xl + dx, ly = yl + dy, lz = zl + dz;
+                        if (lx >= 0 && lx < kTX && ly >= 0 && ly < kTY && lz >= 0) continue;   // same tile
+                        if (!occ_cell(bits, d, x + dx, y + dy, z + dz)) continue;
+                        if (r == kEmpty) r = rank_of(bits, wrank, key0 + (uint32_t)xl);
+                        const uint32_t nk = (uint32_t)(x + dx) + d.nx * ((uint32_t)(y + dy) + d.ny * (uint32_t)(z + dz));
+                        link(parent, linked, r, rank_of(bits, wrank, nk));
+                    }
         }
     }
 }
@@ -353,10 +466,19 @@ hipError_t launch_ccl(const Geom& g, const uint32_t* bits, SegBuffers& b, uint32
 {
     const Dims d = dims_of(g);
     const int grid = grid_for(cap);
+    TileGrid tg;
+    tg.ntx = (d.nx + kTX - 1) / kTX;
+    tg.nty = (d.ny + kTY - 1) / kTY;
+    tg.ntz = (d.nz + kTZ - 1) / kTZ;
+    const uint64_t ntiles = (uint64_t)tg.ntx * tg.nty * tg.ntz;
+    const int tgrid = (int)(ntiles < 16384 ? ntiles : 16384);
     {
         StageScope t(VM_STAGE_CCL, s);
-        k_ccl_init<<<grid, kBlock, 0, s>>>(bits, b.occ_key, ctr, d, b.parent, b.scan_a);
-        k_ccl_merge<<<grid, kBlock, 0, s>>>(bits, b.wrank, b.occ_key, ctr, d, b.parent, b.scan_a);
+        k_ccl_tile<<<tgrid, kBlock, 0, s>>>(bits, g.nwords, b.wrank, d, tg, b.parent, b.scan_a);
+    }
+    {
+        StageScope t(VM_STAGE_CCL_LINK, s);
+        k_ccl_boundary<<<tgrid, kBlock, 0, s>>>(bits, g.nwords, b.wrank, d, tg, b.parent, b.scan_a);
         k_ccl_flatten<<<grid, kBlock, 0, s>>>(ctr, b.parent);
     }
     return hipGetLastError();

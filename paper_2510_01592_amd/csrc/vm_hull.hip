@@ -248,19 +248,29 @@ __global__ void __launch_bounds__(kWave) k_hull_poly(const uint32_t* __restrict_
             if (lane == 0) P[17] = -1.0;
             continue;
         }
-        // lane d < 8 reduces direction d over the cluster's tiles
-        double v = -INFINITY;
-        uint32_t ix = 0xFFFFFFFFu;
-        if (lane < 8) {
-            for (uint32_t t = t0; t < t1; ++t) {
-                const double tv = ext_v[8 * (size_t)t + lane];
-                const uint32_t ti = ext_i[8 * (size_t)t + lane];
-                if (tv > v || (tv == v && ti < ix)) { v = tv; ix = ti; }
+        // the wave strides over the cluster's tiles, then reduces each direction
+        double bv[8];
+        uint32_t bi[8];
+#pragma unroll
+        for (int d = 0; d < 8; ++d) { bv[d] = -INFINITY; bi[d] = 0xFFFFFFFFu; }
+        for (uint32_t t = t0 + lane; t < t1; t += kWave) {
+#pragma unroll
+            for (int d = 0; d < 8; ++d) {
+                const double tv = ext_v[8 * (size_t)t + d];
+                const uint32_t ti = ext_i[8 * (size_t)t + d];
+                if (tv > bv[d] || (tv == bv[d] && ti < bi[d])) { bv[d] = tv; bi[d] = ti; }
             }
         }
         uint32_t e[8];
 #pragma unroll
-        for (int d = 0; d < 8; ++d) e[d] = __shfl(ix, d, kWave);
+        for (int d = 0; d < 8; ++d) {
+            for (int sft = kWave / 2; sft >= 1; sft >>= 1) {
+                const double ov = __shfl_xor(bv[d], sft, kWave);
+                const uint32_t oi = __shfl_xor(bi[d], sft, kWave);
+                if (ov > bv[d] || (ov == bv[d] && oi < bi[d])) { bv[d] = ov; bi[d] = oi; }
+            }
+            e[d] = bi[d];
+        }
         if (lane == 0) {
             const ClusterFrame f = cluster_frame(k, off, X, Y, Z, plane, in_off, in_idx);
             int np = 0;
