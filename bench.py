@@ -54,6 +54,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-frames", type=int, default=1)
     ap.add_argument("--no-batched", action="store_true", help="skip the 2000-cluster batched measurement")
+    ap.add_argument("--no-served", action="store_true", help="skip the multi-robot served measurement")
+    ap.add_argument("--served-seconds", type=float, default=3.0, help="span of the served arrival process")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -230,6 +232,12 @@ def main() -> int:
         batched = _batched(vm, torch, dev, stream)
         _log(f"batched: {batched}")
 
+    # ---- served: 8 robots, Poisson arrivals, continuous admission ---------------
+    served = None
+    if not args.no_served:
+        served = _served(vm, torch, args.served_seconds)
+        _log(f"served: {served}")
+
     # ---- the oracle on the host, bounded sample ---------------------------------
     cpu = None
     if not args.no_cpu_baseline:
@@ -270,6 +278,7 @@ def main() -> int:
         "stage_ms_per_frame": stage_ms,
         "roofline": roof,
         "batched": batched,
+        "served": served,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
@@ -332,6 +341,57 @@ def _batched(vm, torch, dev, stream, replays: int = 100):
             "roofline_k_count": {"bound": "alu", "achieved": ach, "peak": COUNT_PEAK_GEVAL, "unit": "Geval/s",
                                  "frac": ach / COUNT_PEAK_GEVAL},
             "status_flags": st, "generation_s": gen_s}
+
+
+def _served(vm, torch, seconds: float, n_robots: int = 8, rate_hz: float = 30.0, pool: int = 3):
+    """Several robots, each with its own map of the full-map workload (scene
+    seed = robot), send frames as Poisson processes at `rate_hz`; a frame has
+    U(200k, 2M) points (a prefix of one of the robot's `pool` shuffled
+    pre-generated frames, each taken at its own pose of a random walk).  The
+    scheduler admits frames as they arrive, subject to per-robot order, result
+    slots and an HBM budget for in-flight frames; latency is arrival ->
+    results in pinned host memory."""
+    import scenes
+    from paper_2510_01592_amd.serve import GpuBackend, Request, Scheduler, latency_summary, poisson_arrivals
+    t0 = time.perf_counter()
+    maps, host = [], []
+    n_max = 2_000_000
+    for r in range(n_robots):
+        sc = scenes.scene_full_map(1 + r)
+        g = sc.geom
+        maps.append(vm.Map(g.origin, g.voxel_size, g.dims, 23))
+        poses = scenes.random_walk_poses(100 + r, pool, sigma_t=0.01, sigma_rot_deg=0.5)
+        host.append([(torch.from_numpy(scenes.frame_points(sc, 7000 + 10 * r + k, n=n_max, pose=poses[k])).pin_memory(),
+                      poses[k][0], poses[k][1]) for k in range(pool)])
+    gen_s = time.perf_counter() - t0
+    n_slots, budget = 16, 256 << 20
+    be = GpuBackend(maps, n_slots=n_slots, n_hyp=512)
+    rng = np.random.default_rng(12345)
+    reqs = []
+    # one untimed warm-up frame per robot (allocates each map's workspace)
+    warm = [Request(r, 0, 0.0, 1_000_000, (host[r][0][0][:1_000_000], host[r][0][1], host[r][0][2]))
+            for r in range(n_robots)]
+    Scheduler(be, n_robots, n_slots, budget).run(warm)
+    for r in range(n_robots):
+        for k, ta in enumerate(poisson_arrivals(rate_hz, seconds, 500 + r)):
+            n = int(rng.integers(200_000, n_max + 1))
+            src = host[r][k % pool]
+            reqs.append(Request(r, k + 1, float(ta), n, (src[0][:n], src[1], src[2])))
+    sch = Scheduler(be, n_robots, n_slots, budget)
+    torch.cuda.synchronize()
+    t_s = time.perf_counter()
+    done = sch.run(reqs, t0=t_s)
+    t_span = time.perf_counter() - t_s
+    summ = latency_summary(done, t_span)
+    vox = sum(c.result["occupied"] for c in done)
+    bad = sum(1 for c in done if c.result["status"].any())
+    for m in maps:
+        m.close()
+    return dict(summ, robots=n_robots, rate_hz_per_robot=rate_hz, arrival_span_s=seconds, wall_s=t_span,
+                points_per_frame="U(200k, 2M)", n_hyp=512, slots=n_slots, budget_mib=budget >> 20,
+                peak_inflight=sch.peak_inflight, rejected=len(sch.rejected), frames_with_status_flags=bad,
+                voxels_per_s=vox / t_span, points_per_s=sum(c.request.n_points for c in done) / t_span,
+                generation_s=gen_s)
 
 
 def _cpu_baseline(sc, prewarm, n_frames, H, eps, minc, seed):

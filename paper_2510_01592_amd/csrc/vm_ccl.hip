@@ -131,12 +131,60 @@ __device__ __forceinline__ uint32_t row_bits(const uint32_t* __restrict__ bits, 
 
 __device__ __forceinline__ bool bit_at(uint32_t w, int x) { return x >= 0 && x < 32 && ((w >> x) & 1u); }
 
-__device__ __forceinline__ uint32_t lds_find(const uint32_t* par, uint32_t x)
+// first cells of the runs of w, and last cells
+__device__ __forceinline__ uint32_t run_starts(uint32_t w) { return w & ~(w << 1); }
+__device__ __forceinline__ uint32_t run_ends(uint32_t w) { return w & ~(w >> 1); }
+
+// rank of the first cell of a row segment (occupied cells with smaller keys)
+__device__ __forceinline__ uint32_t seg_rank0(const uint32_t* __restrict__ bits, const uint32_t* __restrict__ wrank,
+                                              uint32_t key0)
 {
-    uint32_t p = par[x];
+    return wrank[key0 >> 5] + __popc(bits[key0 >> 5] & ((1u << (key0 & 31)) - 1u));
+}
+
+// Hooks between the runs of row segment v and those of an adjacent row
+// segment w (same x range): f(xa, xb) is called for a cell xa of v and an
+// adjacent occupied cell xb of w so that every pair of 26-adjacent runs gets
+// at least one call.  Two runs touch iff their x ranges, one widened by a
+// cell on each side, overlap: an overlap begins where the run of v or the
+// run of w starts (first test); a purely diagonal touch is the start of one
+// run against the end of the other (second and third tests).  Only run
+// starts and ends of v and run starts of w can fire.
+template <class F>
+__device__ __forceinline__ void hook_segments(uint32_t v, uint32_t w, F&& f)
+{
+    const uint32_t sv = run_starts(v), ev = run_ends(v);
+    for (uint32_t m = v & (sv | ev | run_starts(w)); m; m &= m - 1) {
+        const int xl = __ffs(m) - 1;
+        const bool st = (sv >> xl) & 1u, en = (ev >> xl) & 1u;
+        if (bit_at(w, xl) && (st || !bit_at(w, xl - 1))) f(xl, xl);
+        if (st && bit_at(w, xl - 1)) f(xl, xl - 1);
+        if (en && bit_at(w, xl + 1)) f(xl, xl + 1);
+    }
+}
+
+// LDS union-find.  Finds halve the path (a node is re-pointed at its
+// grandparent: a store of an ancestor, harmless to concurrent finds), hooks
+// put the larger root under the smaller one with a CAS on the root.
+__device__ __forceinline__ uint32_t lds_ld(const uint32_t* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ __forceinline__ void lds_st(uint32_t* p, uint32_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ __forceinline__ uint32_t lds_find(uint32_t* par, uint32_t x)
+{
+    uint32_t p = lds_ld(&par[x]);
     while (p != x) {
-        x = p;
-        p = par[x];
+        const uint32_t g = lds_ld(&par[p]);
+        if (g == p) return p;
+        lds_st(&par[x], g);
+        x = g;
+        p = lds_ld(&par[x]);
     }
     return x;
 }
@@ -162,7 +210,6 @@ __global__ void __launch_bounds__(kBlock) k_ccl_tile(const uint32_t* __restrict_
     __shared__ uint32_t rowrank[kTileRows];
     __shared__ uint32_t members[kTileCells / 32];
     __shared__ uint32_t par[kTileCells];
-    __shared__ uint16_t root[kTileCells];
     const uint32_t ntiles = tg.ntx * tg.nty * tg.ntz;
     const uint32_t j = threadIdx.x;
     const int yl = (int)(j % kTY), zl = (int)(j / kTY);
@@ -171,25 +218,20 @@ __global__ void __launch_bounds__(kBlock) k_ccl_tile(const uint32_t* __restrict_
         const uint32_t x0 = tx * kTX, y = ty * kTY + yl, z = tz * kTZ + zl;
         uint32_t key0;
         const uint32_t v = row_bits(bits, nwords, d, x0, y, z, &key0);
+        const uint32_t sv = run_starts(v), ev = run_ends(v);
         rowv[j] = v;
         members[j] = 0;
-        // rank of the row's first cell (occupied cells before it)
-        rowrank[j] = v ? wrank[key0 >> 5] + __popc(bits[key0 >> 5] & ((1u << (key0 & 31)) - 1u)) : 0u;
-        // local parents: the start of each cell's run along x inside the row
-        for (uint32_t m = v; m; m &= m - 1) {
-            const int xl = __ffs(m) - 1;
-            const uint32_t zeros = ~v & ((1u << xl) - 1u);
-            const int start = zeros ? 32 - __clz(zeros) : 0;
-            par[j * kTX + xl] = j * kTX + (uint32_t)start;
+        rowrank[j] = v ? seg_rank0(bits, wrank, key0) : 0u;
+        // local parents: every cell points at the start of its run along x
+        for (uint32_t m = sv; m; m &= m - 1) {
+            const int s0 = __ffs(m) - 1;
+            const int e0 = __ffs(ev & ~((1u << s0) - 1u)) - 1;
+            for (int xl = s0; xl <= e0; ++xl) par[j * kTX + xl] = j * kTX + (uint32_t)s0;
         }
         // barrier + vote: a tile without occupied cells is skipped by all threads
         if (!__syncthreads_or(v != 0u)) continue;
-        // hook runs of the four neighbouring rows with smaller keys (in the tile)
-        for (uint32_t m = v; m; m &= m - 1) {
-            const int xl = __ffs(m) - 1;
-            const bool run_start = xl == 0 || !bit_at(v, xl - 1);
-            const bool run_end = xl == 31 || !bit_at(v, xl + 1);
-            const uint32_t c = j * kTX + xl;
+        // hook the runs of the (up to) four neighbouring rows with smaller keys
+        if (v) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int dy = (q == 0) ? -1 : (q - 2);
@@ -197,31 +239,39 @@ __global__ void __launch_bounds__(kBlock) k_ccl_tile(const uint32_t* __restrict_
                 const int ny2 = yl + dy, nz2 = zl + dz;
                 if (ny2 < 0 || ny2 >= kTY || nz2 < 0) continue;
                 const uint32_t nr = (uint32_t)(ny2 + kTY * nz2);
-                const uint32_t w = rowv[nr];
-                if (bit_at(w, xl) && (run_start || !bit_at(w, xl - 1))) lds_unite(par, c, nr * kTX + xl);
-                if (run_start && bit_at(w, xl - 1)) lds_unite(par, c, nr * kTX + xl - 1);
-                if (run_end && bit_at(w, xl + 1)) lds_unite(par, c, nr * kTX + xl + 1);
+                hook_segments(v, rowv[nr], [&](int xa, int xb) {
+                    lds_unite(par, j * kTX + (uint32_t)xa, nr * kTX + (uint32_t)xb);
+                });
             }
         }
         __syncthreads();
-        // roots by read-only walks into a separate array (nobody writes par now)
-        for (uint32_t m = v; m; m &= m - 1) {
-            const int xl = __ffs(m) - 1;
-            const uint32_t rt = lds_find(par, j * kTX + xl);
-            root[j * kTX + xl] = (uint16_t)rt;
-            if (rt != j * kTX + xl) atomicOr(&members[rt >> 5], 1u << (rt & 31));
+        // roots of the run starts (a start's entry then holds its root); a
+        // root with another member is marked
+        for (uint32_t m = sv; m; m &= m - 1) {
+            const int s0 = __ffs(m) - 1;
+            const int e0 = __ffs(ev & ~((1u << s0) - 1u)) - 1;
+            const uint32_t c = j * kTX + (uint32_t)s0;
+            const uint32_t rt = lds_find(par, c);
+            lds_st(&par[c], rt);
+            if (rt != c || e0 > s0) atomicOr(&members[rt >> 5], 1u << (rt & 31));
         }
         __syncthreads();
-        // global parents: the rank of the local root; a voxel is linked if its
-        // local component has another member
-        for (uint32_t m = v; m; m &= m - 1) {
-            const int xl = __ffs(m) - 1;
-            const uint32_t c = j * kTX + xl, rt = root[c];
-            const uint32_t r = rowrank[j] + __popc(v & ((1u << xl) - 1u));
+        // global parents: the rank of the local root, for a whole run at once
+        // (consecutive cells of a run have consecutive ranks); a voxel is
+        // linked if its local component has another member
+        for (uint32_t m = sv; m; m &= m - 1) {
+            const int s0 = __ffs(m) - 1;
+            const int e0 = __ffs(ev & ~((1u << s0) - 1u)) - 1;
+            const uint32_t c = j * kTX + (uint32_t)s0;
+            const uint32_t rt = par[c];
             const uint32_t rrow = rt / kTX, rx = rt % kTX;
             const uint32_t rr = rowrank[rrow] + __popc(rowv[rrow] & ((1u << rx) - 1u));
-            parent[r] = rr;
-            linked[r] = (rt != c || ((members[c >> 5] >> (c & 31)) & 1u)) ? 1u : 0u;
+            const uint32_t lk = (e0 > s0 || rt != c || ((members[c >> 5] >> (c & 31)) & 1u)) ? 1u : 0u;
+            const uint32_t r = rowrank[j] + __popc(v & ((1u << s0) - 1u));
+            for (int i = 0; i <= e0 - s0; ++i) {
+                parent[r + i] = rr;
+                linked[r + i] = lk;
+            }
         }
         __syncthreads();   // LDS is reused by the next tile
     }
@@ -233,8 +283,14 @@ __device__ __forceinline__ bool occ_cell(const uint32_t* __restrict__ bits, cons
     return occ(bits, (uint32_t)x + d.nx * ((uint32_t)y + d.ny * (uint32_t)z));
 }
 
-// Cross-tile adjacencies: every occupied cell on a tile face hooks its
-// occupied neighbours with smaller keys that lie in another tile.
+// Cross-tile adjacencies, from the cell with the larger key.
+//  * y/z faces: a row segment whose neighbouring row (dz = -1 any dy, or
+//    dz = 0 and dy = -1) lies in another tile with the same x range hooks the
+//    runs of the two segments with the run rule above (runs cut at the tile's
+//    x edges are joined inside their tiles).
+//  * x faces: the first cell of a segment links each occupied neighbour with
+//    a smaller key at x - 1 (five of them), the last cell each one at x + 1
+//    (four); these pairs lie in tiles of another x range.
 __global__ void __launch_bounds__(kBlock) k_ccl_boundary(const uint32_t* __restrict__ bits, uint32_t nwords,
                                                          const uint32_t* __restrict__ wrank, Dims d, TileGrid tg,
                                                          uint32_t* parent, uint32_t* linked)
@@ -247,25 +303,45 @@ __global__ void __launch_bounds__(kBlock) k_ccl_boundary(const uint32_t* __restr
         const uint32_t x0 = tx * kTX;
         const int y = (int)(ty * kTY) + yl, z = (int)(tz * kTZ) + zl;
         uint32_t key0;
-        uint32_t v = row_bits(bits, nwords, d, x0, (uint32_t)y, (uint32_t)z, &key0);
-        const bool yface = yl == 0 || yl == kTY - 1, zface = zl == 0;
-        if (!yface && !zface) v &= (1u << 0) | (1u << 31);   // interior rows: only the x faces
-        for (uint32_t m = v; m; m &= m - 1) {
-            const int xl = __ffs(m) - 1;
-            const int x = (int)x0 + xl;
-            uint32_t r = kEmpty;
-            for (int dz = -1; dz <= 0; ++dz)
-                for (int dy = -1; dy <= 1; ++dy)
-                    for (int dx = -1; dx <= 1; ++dx) {
-                        // the 13 neighbours with smaller keys
-                        if (dz == 0 && (dy > 0 || (dy == 0 && dx >= 0))) continue;
-                        const int lx = xl + dx, ly = yl + dy, lz = zl + dz;
-                        if (lx >= 0 && lx < kTX && ly >= 0 && ly < kTY && lz >= 0) continue;   // same tile
-                        if (!occ_cell(bits, d, x + dx, y + dy, z + dz)) continue;
-                        if (r == kEmpty) r = rank_of(bits, wrank, key0 + (uint32_t)xl);
-                        const uint32_t nk = (uint32_t)(x + dx) + d.nx * ((uint32_t)(y + dy) + d.ny * (uint32_t)(z + dz));
-                        link(parent, linked, r, rank_of(bits, wrank, nk));
-                    }
+        const uint32_t v = row_bits(bits, nwords, d, x0, (uint32_t)y, (uint32_t)z, &key0);
+        if (!v) continue;
+        const uint32_t r0 = seg_rank0(bits, wrank, key0);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int dy = (q == 0) ? -1 : (q - 2);
+            const int dz = (q == 0) ? 0 : -1;
+            const int ly = yl + dy, lz = zl + dz;
+            if (ly >= 0 && ly < kTY && lz >= 0) continue;   // same tile
+            uint32_t nkey0;
+            const uint32_t w = row_bits(bits, nwords, d, x0, (uint32_t)(y + dy), (uint32_t)(z + dz), &nkey0);
+            if (!w) continue;
+            const uint32_t n0 = seg_rank0(bits, wrank, nkey0);
+            hook_segments(v, w, [&](int xa, int xb) {
+                link(parent, linked, r0 + __popc(v & ((1u << xa) - 1u)), n0 + __popc(w & ((1u << xb) - 1u)));
+            });
+        }
+        if ((v & 1u) && x0 > 0) {
+            const int x = (int)x0;
+#pragma unroll
+            for (int q = 0; q < 5; ++q) {
+                const int dy = (q < 3) ? q - 1 : (q == 3 ? -1 : 0);
+                const int dz = (q < 3) ? -1 : 0;
+                if (!occ_cell(bits, d, x - 1, y + dy, z + dz)) continue;
+                const uint32_t nk = (uint32_t)(x - 1) + d.nx * ((uint32_t)(y + dy) + d.ny * (uint32_t)(z + dz));
+                link(parent, linked, r0, rank_of(bits, wrank, nk));
+            }
+        }
+        if ((v >> 31) & 1u) {
+            const int x = (int)x0 + 31;
+            const uint32_t r = r0 + (uint32_t)__popc(v) - 1u;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int dy = (q < 3) ? q - 1 : -1;
+                const int dz = (q < 3) ? -1 : 0;
+                if (!occ_cell(bits, d, x + 1, y + dy, z + dz)) continue;
+                const uint32_t nk = (uint32_t)(x + 1) + d.nx * ((uint32_t)(y + dy) + d.ny * (uint32_t)(z + dz));
+                link(parent, linked, r, rank_of(bits, wrank, nk));
+            }
         }
     }
 }

@@ -146,17 +146,46 @@ __device__ __forceinline__ uint32_t cluster_of_tile(const uint32_t* __restrict__
 // (b) inlier counting over (tile, hypothesis-chunk) items.  The number of
 // hypothesis chunks is chosen on the device from the tile count so that small
 // frames still cover every CU; each item keeps its points in registers and
-// sweeps its chunk of planes, kHypBatch planes per scalar-load batch.
-__device__ __forceinline__ uint32_t count_one(const float4 pl, const float* px, const float* py, const float* pz,
-                                              float eps)
+// sweeps its chunk of planes, kHypBatch planes per scalar-load batch.  A wave
+// evaluates only the rows of 64 points that hold points of the tile's
+// cluster: the last tile of a cluster is usually short, and most clusters
+// are smaller than one tile.
+template <int R>
+__device__ __forceinline__ uint32_t count_rows(const float4 pl, const float* px, const float* py, const float* pz,
+                                               float eps)
 {
     uint32_t acc = 0;
 #pragma unroll
-    for (int j = 0; j < kPtsPerLane; ++j) {
+    for (int j = 0; j < R; ++j) {
         const float dd = fmaf(pl.z, pz[j], fmaf(pl.y, py[j], fmaf(pl.x, px[j], pl.w)));
         acc += (uint32_t)__popcll(__ballot(fabsf(dd) < eps));
     }
     return acc;
+}
+
+template <int R>
+__device__ __forceinline__ void count_planes(const float4* __restrict__ hk, uint32_t h0, uint32_t h1,
+                                             const float* px, const float* py, const float* pz, float eps,
+                                             uint32_t* lcnt, int lane)
+{
+    uint32_t h = h0;
+    for (; h + kHypBatch <= h1; h += kHypBatch) {
+        float4 pl[kHypBatch];
+#pragma unroll
+        for (int b = 0; b < kHypBatch; ++b) pl[b] = hk[h + b];
+#pragma unroll
+        for (int b = 0; b < kHypBatch; ++b) {
+            if (pl[b].x != pl[b].x) continue;   // degenerate hypothesis
+            const uint32_t acc = count_rows<R>(pl[b], px, py, pz, eps);
+            if (lane == 0 && acc) atomicAdd(&lcnt[h + b - h0], acc);
+        }
+    }
+    for (; h < h1; ++h) {
+        const float4 pl = hk[h];
+        if (pl.x != pl.x) continue;
+        const uint32_t acc = count_rows<R>(pl, px, py, pz, eps);
+        if (lane == 0 && acc) atomicAdd(&lcnt[h - h0], acc);
+    }
 }
 
 __global__ void __launch_bounds__(kCountBlock) k_count(const uint32_t* __restrict__ small,
@@ -186,11 +215,13 @@ __global__ void __launch_bounds__(kCountBlock) k_count(const uint32_t* __restric
         const uint32_t p0 = off[k] + (t - tile_off[k]) * kTile;
         const uint32_t pend = off[k + 1];
         const uint32_t h0 = hc * chunk, h1 = min(H, h0 + chunk);
+        const uint32_t wbase = p0 + (uint32_t)(wave * kWave * kPtsPerLane);
+        const int rows = pend > wbase ? (int)min((uint32_t)kPtsPerLane, (pend - wbase + kWave - 1) / kWave) : 0;
         float px[kPtsPerLane], py[kPtsPerLane], pz[kPtsPerLane];
         const float qnan = __builtin_nanf("");
 #pragma unroll
         for (int j = 0; j < kPtsPerLane; ++j) {
-            const uint32_t i = p0 + (uint32_t)(wave * kWave * kPtsPerLane + j * kWave + lane);
+            const uint32_t i = wbase + (uint32_t)(j * kWave + lane);
             const bool v = i < pend;
             px[j] = v ? X[i] : qnan;   // NaN never passes |d| < eps
             py[j] = v ? Y[i] : qnan;
@@ -199,24 +230,12 @@ __global__ void __launch_bounds__(kCountBlock) k_count(const uint32_t* __restric
         for (uint32_t h = h0 + threadIdx.x; h < h1; h += kCountBlock) lcnt[h - h0] = 0;
         __syncthreads();
         const float4* hk = hyp + (size_t)k * H;
-        uint32_t h = h0;
-        for (; h + kHypBatch <= h1; h += kHypBatch) {
-            float4 pl[kHypBatch];
-#pragma unroll
-            for (int b = 0; b < kHypBatch; ++b) pl[b] = hk[h + b];
-#pragma unroll
-            for (int b = 0; b < kHypBatch; ++b) {
-                if (pl[b].x != pl[b].x) continue;   // degenerate hypothesis
-                const uint32_t acc = count_one(pl[b], px, py, pz, eps);
-                if (lane == 0 && acc) atomicAdd(&lcnt[h + b - h0], acc);
-            }
-        }
-        for (; h < h1; ++h) {
-            const float4 pl = hk[h];
-            if (pl.x != pl.x) continue;
-            const uint32_t acc = count_one(pl, px, py, pz, eps);
-            if (lane == 0 && acc) atomicAdd(&lcnt[h - h0], acc);
-        }
+        // rows is wave-uniform; rows past the cluster's end hold NaN points
+        if (rows == kPtsPerLane) count_planes<kPtsPerLane>(hk, h0, h1, px, py, pz, eps, lcnt, lane);
+        else if (rows > 4) count_planes<kPtsPerLane>(hk, h0, h1, px, py, pz, eps, lcnt, lane);
+        else if (rows > 2) count_planes<4>(hk, h0, h1, px, py, pz, eps, lcnt, lane);
+        else if (rows > 1) count_planes<2>(hk, h0, h1, px, py, pz, eps, lcnt, lane);
+        else if (rows == 1) count_planes<1>(hk, h0, h1, px, py, pz, eps, lcnt, lane);
         __syncthreads();
         int32_t* ck = counts + (size_t)k * H;
         for (uint32_t hh = h0 + threadIdx.x; hh < h1; hh += kCountBlock) {
