@@ -282,6 +282,8 @@ vm_status vm_map_create(const vm_map_desc* d, vm_map* out)
                                                std::max<uint64_t>(radix_hist_words(cap), radix_hist_words(batch)));
     A((void**)&b.blk, scan_blk_words(scan_n) * 4);
     A((void**)&b.hist, radix_hist_words(cap) * 4);
+    A((void**)&b.pairs, ccl_tiles(m->g) * kCclTilePairs * 8);
+    A((void**)&b.npair, ccl_tiles(m->g) * 4);
     InsertScratch& ins = m->ins;
     ins.cap = batch;
     for (int i = 0; i < 2; ++i) {

@@ -202,6 +202,14 @@ __device__ __forceinline__ void lds_unite(uint32_t* par, uint32_t a, uint32_t b)
     }
 }
 
+// first cell of the run of w that contains cell x (x must be occupied)
+__device__ __forceinline__ uint32_t run_start_of(uint32_t starts, int x)
+{
+    return 31u - __clz(starts & ((2u << x) - 1u));   // x = 31: (2u << 31) - 1 wraps to all ones
+}
+
+constexpr uint32_t kPairCap = 2048;   // hook pairs buffered per tile (more are united at once)
+
 __global__ void __launch_bounds__(kBlock) k_ccl_tile(const uint32_t* __restrict__ bits, uint32_t nwords,
                                                      const uint32_t* __restrict__ wrank, Dims d, TileGrid tg,
                                                      uint32_t* __restrict__ parent, uint32_t* __restrict__ linked)
@@ -210,6 +218,8 @@ __global__ void __launch_bounds__(kBlock) k_ccl_tile(const uint32_t* __restrict_
     __shared__ uint32_t rowrank[kTileRows];
     __shared__ uint32_t members[kTileCells / 32];
     __shared__ uint32_t par[kTileCells];
+    __shared__ uint32_t pairs[kPairCap];
+    __shared__ uint32_t npairs;
     const uint32_t ntiles = tg.ntx * tg.nty * tg.ntz;
     const uint32_t j = threadIdx.x;
     const int yl = (int)(j % kTY), zl = (int)(j / kTY);
@@ -222,15 +232,17 @@ __global__ void __launch_bounds__(kBlock) k_ccl_tile(const uint32_t* __restrict_
         rowv[j] = v;
         members[j] = 0;
         rowrank[j] = v ? seg_rank0(bits, wrank, key0) : 0u;
-        // local parents: every cell points at the start of its run along x
+        if (j == 0) npairs = 0;
+        // the union-find runs over run starts (cells of a run share its start)
         for (uint32_t m = sv; m; m &= m - 1) {
-            const int s0 = __ffs(m) - 1;
-            const int e0 = __ffs(ev & ~((1u << s0) - 1u)) - 1;
-            for (int xl = s0; xl <= e0; ++xl) par[j * kTX + xl] = j * kTX + (uint32_t)s0;
+            const uint32_t c = j * kTX + (uint32_t)(__ffs(m) - 1);
+            par[c] = c;
         }
         // barrier + vote: a tile without occupied cells is skipped by all threads
         if (!__syncthreads_or(v != 0u)) continue;
-        // hook the runs of the (up to) four neighbouring rows with smaller keys
+        // hooks between the runs of the (up to) four neighbouring rows with
+        // smaller keys; the pairs are collected first and then united by all
+        // threads, so that rows with many hooks do not hold up their wave
         if (v) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
@@ -239,9 +251,21 @@ __global__ void __launch_bounds__(kBlock) k_ccl_tile(const uint32_t* __restrict_
                 const int ny2 = yl + dy, nz2 = zl + dz;
                 if (ny2 < 0 || ny2 >= kTY || nz2 < 0) continue;
                 const uint32_t nr = (uint32_t)(ny2 + kTY * nz2);
-                hook_segments(v, rowv[nr], [&](int xa, int xb) {
-                    lds_unite(par, j * kTX + (uint32_t)xa, nr * kTX + (uint32_t)xb);
+                const uint32_t w = rowv[nr], sw = run_starts(w);
+                hook_segments(v, w, [&](int xa, int xb) {
+                    const uint32_t a = j * kTX + run_start_of(sv, xa), b = nr * kTX + run_start_of(sw, xb);
+                    const uint32_t i = atomicAdd(&npairs, 1u);
+                    if (i < kPairCap) pairs[i] = (a << 16) | b;
+                    else lds_unite(par, a, b);
                 });
+            }
+        }
+        __syncthreads();
+        {
+            const uint32_t np = min(npairs, kPairCap);
+            for (uint32_t i = j; i < np; i += kBlock) {
+                const uint32_t pr = pairs[i];
+                lds_unite(par, pr >> 16, pr & 0xFFFFu);
             }
         }
         __syncthreads();
@@ -291,57 +315,112 @@ __device__ __forceinline__ bool occ_cell(const uint32_t* __restrict__ bits, cons
 //  * x faces: the first cell of a segment links each occupied neighbour with
 //    a smaller key at x - 1 (five of them), the last cell each one at x + 1
 //    (four); these pairs lie in tiles of another x range.
+// Each pair is replaced by the local roots of its two voxels (the labelling
+// pass left every voxel pointing at its tile-local root), both voxels are
+// marked linked, and a tile keeps one copy of each distinct root pair (an
+// LDS hash set): along a dense surface many cells link the same two local
+// components.  The distinct pairs go to the tile's slice of a pair buffer; a
+// second kernel unites all pairs of the grid at once.  A tile with more
+// distinct pairs than its slice unites the excess itself.
+constexpr uint32_t kPairHash = 1024;   // LDS hash set of root pairs per tile
+
 __global__ void __launch_bounds__(kBlock) k_ccl_boundary(const uint32_t* __restrict__ bits, uint32_t nwords,
                                                          const uint32_t* __restrict__ wrank, Dims d, TileGrid tg,
-                                                         uint32_t* parent, uint32_t* linked)
+                                                         uint32_t* parent, uint32_t* linked,
+                                                         uint64_t* __restrict__ pairs, uint32_t* __restrict__ npair)
 {
+    __shared__ uint64_t buf[kCclTilePairs];
+    __shared__ unsigned long long hset[kPairHash];
+    __shared__ uint32_t nbuf;
     const uint32_t ntiles = tg.ntx * tg.nty * tg.ntz;
     const uint32_t j = threadIdx.x;
     const int yl = (int)(j % kTY), zl = (int)(j / kTY);
     for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        if (j == 0) nbuf = 0;
+        for (uint32_t i = j; i < kPairHash; i += kBlock) hset[i] = ~0ull;
+        __syncthreads();
         const uint32_t tx = t % tg.ntx, ty = (t / tg.ntx) % tg.nty, tz = t / (tg.ntx * tg.nty);
         const uint32_t x0 = tx * kTX;
         const int y = (int)(ty * kTY) + yl, z = (int)(tz * kTZ) + zl;
         uint32_t key0;
         const uint32_t v = row_bits(bits, nwords, d, x0, (uint32_t)y, (uint32_t)z, &key0);
-        if (!v) continue;
-        const uint32_t r0 = seg_rank0(bits, wrank, key0);
+        auto emit = [&](uint32_t a, uint32_t b) {
+            linked[a] = 1u;
+            linked[b] = 1u;
+            const uint32_t ra = ld_parent(&parent[a]), rb = ld_parent(&parent[b]);
+            const unsigned long long key = ((unsigned long long)ra << 32) | rb;
+            uint32_t h = (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> 54);   // kPairHash = 2^10 slots
+            for (uint32_t probe = 0; probe < kPairHash; ++probe) {
+                const unsigned long long old = atomicCAS(&hset[h], ~0ull, key);
+                if (old == key) return;          // this root pair is already listed
+                if (old == ~0ull) break;         // first time
+                h = (h + 1) & (kPairHash - 1);
+            }
+            const uint32_t i = atomicAdd(&nbuf, 1u);
+            if (i < kCclTilePairs) buf[i] = key;
+            else uf_unite(parent, ra, rb);
+        };
+        const bool face = yl == 0 || yl == kTY - 1 || zl == 0;
+        const bool first = (v & 1u) && x0 > 0, last = (v >> 31) & 1u;
+        if (v && (face || first || last)) {
+            const uint32_t r0 = seg_rank0(bits, wrank, key0);
+            if (face) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int dy = (q == 0) ? -1 : (q - 2);
-            const int dz = (q == 0) ? 0 : -1;
-            const int ly = yl + dy, lz = zl + dz;
-            if (ly >= 0 && ly < kTY && lz >= 0) continue;   // same tile
-            uint32_t nkey0;
-            const uint32_t w = row_bits(bits, nwords, d, x0, (uint32_t)(y + dy), (uint32_t)(z + dz), &nkey0);
-            if (!w) continue;
-            const uint32_t n0 = seg_rank0(bits, wrank, nkey0);
-            hook_segments(v, w, [&](int xa, int xb) {
-                link(parent, linked, r0 + __popc(v & ((1u << xa) - 1u)), n0 + __popc(w & ((1u << xb) - 1u)));
-            });
-        }
-        if ((v & 1u) && x0 > 0) {
-            const int x = (int)x0;
+                for (int q = 0; q < 4; ++q) {
+                    const int dy = (q == 0) ? -1 : (q - 2);
+                    const int dz = (q == 0) ? 0 : -1;
+                    const int ly = yl + dy, lz = zl + dz;
+                    if (ly >= 0 && ly < kTY && lz >= 0) continue;   // same tile
+                    uint32_t nkey0;
+                    const uint32_t w = row_bits(bits, nwords, d, x0, (uint32_t)(y + dy), (uint32_t)(z + dz), &nkey0);
+                    if (!w) continue;
+                    const uint32_t n0 = seg_rank0(bits, wrank, nkey0);
+                    hook_segments(v, w, [&](int xa, int xb) {
+                        emit(r0 + __popc(v & ((1u << xa) - 1u)), n0 + __popc(w & ((1u << xb) - 1u)));
+                    });
+                }
+            }
+            if (first) {
+                const int x = (int)x0;
 #pragma unroll
-            for (int q = 0; q < 5; ++q) {
-                const int dy = (q < 3) ? q - 1 : (q == 3 ? -1 : 0);
-                const int dz = (q < 3) ? -1 : 0;
-                if (!occ_cell(bits, d, x - 1, y + dy, z + dz)) continue;
-                const uint32_t nk = (uint32_t)(x - 1) + d.nx * ((uint32_t)(y + dy) + d.ny * (uint32_t)(z + dz));
-                link(parent, linked, r0, rank_of(bits, wrank, nk));
+                for (int q = 0; q < 5; ++q) {
+                    const int dy = (q < 3) ? q - 1 : (q == 3 ? -1 : 0);
+                    const int dz = (q < 3) ? -1 : 0;
+                    if (!occ_cell(bits, d, x - 1, y + dy, z + dz)) continue;
+                    const uint32_t nk = (uint32_t)(x - 1) + d.nx * ((uint32_t)(y + dy) + d.ny * (uint32_t)(z + dz));
+                    emit(r0, rank_of(bits, wrank, nk));
+                }
+            }
+            if (last) {
+                const int x = (int)x0 + 31;
+                const uint32_t r = r0 + (uint32_t)__popc(v) - 1u;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int dy = (q < 3) ? q - 1 : -1;
+                    const int dz = (q < 3) ? -1 : 0;
+                    if (!occ_cell(bits, d, x + 1, y + dy, z + dz)) continue;
+                    const uint32_t nk = (uint32_t)(x + 1) + d.nx * ((uint32_t)(y + dy) + d.ny * (uint32_t)(z + dz));
+                    emit(r, rank_of(bits, wrank, nk));
+                }
             }
         }
-        if ((v >> 31) & 1u) {
-            const int x = (int)x0 + 31;
-            const uint32_t r = r0 + (uint32_t)__popc(v) - 1u;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int dy = (q < 3) ? q - 1 : -1;
-                const int dz = (q < 3) ? -1 : 0;
-                if (!occ_cell(bits, d, x + 1, y + dy, z + dz)) continue;
-                const uint32_t nk = (uint32_t)(x + 1) + d.nx * ((uint32_t)(y + dy) + d.ny * (uint32_t)(z + dz));
-                link(parent, linked, r, rank_of(bits, wrank, nk));
-            }
+        __syncthreads();
+        const uint32_t np = min(nbuf, kCclTilePairs);
+        for (uint32_t i = j; i < np; i += kBlock) pairs[(uint64_t)t * kCclTilePairs + i] = buf[i];
+        if (j == 0) npair[t] = np;
+        __syncthreads();   // LDS is reused by the next tile
+    }
+}
+
+// Unions of the buffered cross-tile pairs, one pair per thread.
+__global__ void __launch_bounds__(kBlock) k_ccl_pairs(uint32_t ntiles, const uint64_t* __restrict__ pairs,
+                                                      const uint32_t* __restrict__ npair, uint32_t* parent)
+{
+    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const uint32_t np = npair[t];
+        for (uint32_t i = threadIdx.x; i < np; i += blockDim.x) {
+            const uint64_t pr = pairs[(uint64_t)t * kCclTilePairs + i];
+            uf_unite(parent, (uint32_t)(pr >> 32), (uint32_t)pr);
         }
     }
 }
@@ -492,11 +571,13 @@ __global__ void __launch_bounds__(kBlock) k_group_pairs(const DevCounters* __res
 
 // CSR points: key and Eq. (1) mean of each kept voxel, cluster-major
 __global__ void __launch_bounds__(kBlock) k_group_gather(Geom g, Hash h, const DevCounters* __restrict__ ctr,
-                                                         const uint32_t* __restrict__ sorted_rank,
+                                                         const uint32_t* __restrict__ sorted_rank0,
+                                                         const uint32_t* __restrict__ sorted_rank1,
                                                          const uint32_t* __restrict__ occ_key,
                                                          uint32_t* __restrict__ cl_key, float* __restrict__ cl_x,
                                                          float* __restrict__ cl_y, float* __restrict__ cl_z)
 {
+    const uint32_t* __restrict__ sorted_rank = ctr->group_sel ? sorted_rank1 : sorted_rank0;
     const uint32_t n = ctr->meta[1];
     const uint32_t nx = (uint32_t)g.dims[0], ny = (uint32_t)g.dims[1];
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
@@ -537,6 +618,12 @@ Dims dims_of(const Geom& g)
 
 }  // namespace
 
+uint64_t ccl_tiles(const Geom& g)
+{
+    const Dims d = dims_of(g);
+    return (uint64_t)((d.nx + kTX - 1) / kTX) * ((d.ny + kTY - 1) / kTY) * ((d.nz + kTZ - 1) / kTZ);
+}
+
 hipError_t launch_ccl(const Geom& g, const uint32_t* bits, SegBuffers& b, uint32_t cap, DevCounters* ctr,
                       hipStream_t s)
 {
@@ -554,7 +641,9 @@ hipError_t launch_ccl(const Geom& g, const uint32_t* bits, SegBuffers& b, uint32
     }
     {
         StageScope t(VM_STAGE_CCL_LINK, s);
-        k_ccl_boundary<<<tgrid, kBlock, 0, s>>>(bits, g.nwords, b.wrank, d, tg, b.parent, b.scan_a);
+        k_ccl_boundary<<<tgrid, kBlock, 0, s>>>(bits, g.nwords, b.wrank, d, tg, b.parent, b.scan_a, b.pairs,
+                                                b.npair);
+        k_ccl_pairs<<<tgrid, kBlock, 0, s>>>((uint32_t)ntiles, b.pairs, b.npair, b.parent);
         k_ccl_flatten<<<grid, kBlock, 0, s>>>(ctr, b.parent);
     }
     return hipGetLastError();
@@ -585,11 +674,11 @@ hipError_t launch_group(const Geom& g, const Hash& h, SegBuffers& b, uint32_t ca
     // stable sort by cluster id keeps ascending keys inside each cluster
     const uint32_t kbound = cap / min_cluster + 1;
     const int bits_needed = 32 - __builtin_clz(kbound | 1u);
-    int res = 0;
     if ((e = radix_sort_pairs_dev(b.sort_k, b.sort_v, &ctr->meta[1], cap, bits_needed, &ctr->kmax, b.hist, b.blk,
-                                  &res, s)) != hipSuccess)
+                                  &ctr->group_sel, s)) != hipSuccess)
         return e;
-    k_group_gather<<<grid, kBlock, 0, s>>>(g, h, ctr, b.sort_v[res], b.occ_key, b.cl_key, b.cl_x, b.cl_y, b.cl_z);
+    k_group_gather<<<grid, kBlock, 0, s>>>(g, h, ctr, b.sort_v[0], b.sort_v[1], b.occ_key, b.cl_key, b.cl_x, b.cl_y,
+                                           b.cl_z);
     if (d_labels) k_labels<<<grid, kBlock, 0, s>>>(ctr, b.parent, b.occ_key, d_labels);
     return hipGetLastError();
 }

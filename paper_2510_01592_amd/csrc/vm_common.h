@@ -29,7 +29,9 @@ struct DevCounters {
     uint32_t sort_n;                  // points in the current sorted insert batch
     uint32_t sort_max;                // largest sort key of that batch (2^bits - 1)
     unsigned long long touched;       // distinct voxels updated by the last insert call
-    uint32_t pad[11];
+    uint32_t sort_sel;                // buffer (0/1) holding the sorted insert batch
+    uint32_t group_sel;               // buffer (0/1) holding the voxels sorted by cluster
+    uint32_t pad[9];
 };
 
 struct Geom {
@@ -109,7 +111,12 @@ struct SegBuffers {
     uint32_t* wrank;       // [nwords+1] exclusive popcount prefix of the occupancy words
     uint32_t* blk;         // block partials for scans (sized generously)
     uint32_t* hist;        // radix histograms
+    uint64_t* pairs;       // [ccl_tiles * kCclTilePairs] cross-tile hook pairs, per tile
+    uint32_t* npair;       // [ccl_tiles] pairs stored per tile
 };
+
+constexpr uint32_t kCclTilePairs = 256;   // cross-tile hook pairs buffered per labelling tile
+uint64_t ccl_tiles(const Geom& g);        // labelling tiles covering the grid
 
 // Number of clusters a pass may process: min(meta[0], k_cap) if the offsets
 // are a valid CSR (off[0] = 0, non-decreasing, off[K] = meta[1] <= n_cap),
@@ -185,14 +192,15 @@ hipError_t scan_exclusive_dev(const uint32_t* in, uint32_t* out, const uint32_t*
                               uint32_t* d_total, uint32_t* blk, hipStream_t s);
 
 // Stable LSD radix sort of (key, value) pairs by the low `bits` bits of key;
-// n from *d_n (<= n_cap).  Passes whose digit is zero for every key (key <=
-// *d_max_key) reduce to copies.  The result lands in keys[r]/vals[r] with
-// r = *result_buf (host-known).  `hist` needs radix_hist_words(n_cap) words,
-// `blk` as for the scan.
+// n from *d_n (<= n_cap).  Every key is at most *d_max_key; a pass whose
+// digit and all higher digits of that bound are zero does nothing (the
+// passes that run are the first ones).  The result lands in keys[r]/vals[r] with r = *d_sel, written on
+// the device.  `hist` needs radix_hist_words(n_cap) words, `blk` as for the
+// scan.
 size_t radix_hist_words(uint64_t n_cap);
 hipError_t radix_sort_pairs_dev(uint32_t* keys[2], uint32_t* vals[2], const uint32_t* d_n, uint32_t n_cap,
                                 int bits, const uint32_t* d_max_key, uint32_t* hist, uint32_t* blk,
-                                int* result_buf, hipStream_t s);
+                                uint32_t* d_sel, hipStream_t s);
 
 // Scratch of the sorted insert path (sized for `cap` points per batch).
 struct InsertScratch {
@@ -230,6 +238,7 @@ struct WorkLayout {
     int32_t* counts;        // [k_cap * H]
     float4* hyp;            // [k_cap * H]
     uint32_t* tile_off;     // [k_cap + 1]
+    uint32_t* tile_k;       // [n_cap / tile + k_cap + 1] cluster of each point tile
     uint32_t* flags;        // [n_cap]
     uint32_t* blk;          // scan partials
     uint32_t* hull_cnt;     // [k_cap + 2]

@@ -380,20 +380,54 @@ __device__ __forceinline__ void swap3(double* U, double* V, uint32_t* I, uint32_
     I[b] = ti;
 }
 
-// one monotone chain over n sorted points (forward: lower chain, backward:
-// upper chain) into stack st; returns its length
+// One monotone chain over n sorted points (forward: lower chain, backward:
+// upper chain), computed by one wave.  Lane l first chains its contiguous
+// chunk of the sequence into tmp, dropping only points that lie strictly on
+// the inner side of a segment between two other points (such a point is no
+// vertex of the hull of any set holding those three; collinear and
+// coincident points are kept, so the choice among them is left to the full
+// rule); lane 0 then runs the
+// chain (dropping collinear and coincident points as well) over the
+// concatenated chunk results, which gives the output of the plain chain over
+// all n points.  All lanes of the wave call chain_chunks; lens has kWave
+// entries.
 template <typename S>
-__device__ __forceinline__ uint32_t chain(const double* U, const double* V, uint32_t n, bool forward, S* st)
+__device__ __forceinline__ void chain_chunks(const double* U, const double* V, uint32_t n, bool forward, S* tmp,
+                                             uint32_t* lens)
 {
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint32_t c = (n + kWave - 1) / kWave;
+    const uint32_t s0 = lane * c < n ? lane * c : n;
+    const uint32_t s1 = s0 + c < n ? s0 + c : n;
     uint32_t h = 0;
-    for (uint32_t s = 0; s < n; ++s) {
+    for (uint32_t s = s0; s < s1; ++s) {
         const uint32_t i = forward ? s : n - 1 - s;
         while (h >= 2) {
-            const uint32_t a = st[h - 2], b = st[h - 1];
-            if (cross3(U[a], V[a], U[b], V[b], U[i], V[i]) <= 0.0) --h;
+            const uint32_t a = tmp[s0 + h - 2], b = tmp[s0 + h - 1];
+            if (cross3(U[a], V[a], U[b], V[b], U[i], V[i]) < 0.0) --h;
             else break;
         }
-        st[h++] = (S)i;
+        tmp[s0 + h++] = (S)i;
+    }
+    lens[lane] = h;
+}
+
+template <typename S>
+__device__ __forceinline__ uint32_t chain_merge(const double* U, const double* V, uint32_t n, const S* tmp,
+                                                const uint32_t* lens, S* st)
+{
+    const uint32_t c = (n + kWave - 1) / kWave;
+    uint32_t h = 0;
+    for (uint32_t l = 0; l < (uint32_t)kWave; ++l) {
+        for (uint32_t q = 0; q < lens[l]; ++q) {
+            const uint32_t i = tmp[l * c + q];
+            while (h >= 2) {
+                const uint32_t a = st[h - 2], b = st[h - 1];
+                if (cross3(U[a], V[a], U[b], V[b], U[i], V[i]) <= 0.0) --h;
+                else break;
+            }
+            st[h++] = (S)i;
+        }
     }
     return h;
 }
@@ -409,6 +443,9 @@ __global__ void __launch_bounds__(kChainBlock) k_hull_chain(
     __shared__ uint32_t si[kLdsCap];
     __shared__ uint16_t st_lo[2 * kLdsCap];
     __shared__ uint16_t st_up[kLdsCap + 1];
+    __shared__ uint16_t tmp_lo[kLdsCap];
+    __shared__ uint16_t tmp_up[kLdsCap];
+    __shared__ uint32_t len_lo[kWave], len_up[kWave];
     __shared__ uint32_t hlo, hup;
     const uint32_t K = small[4];
     const uint32_t T = small[6];
@@ -447,8 +484,12 @@ __global__ void __launch_bounds__(kChainBlock) k_hull_chain(
                     __syncthreads();
                 }
             }
-            if (threadIdx.x == 0) hlo = chain(su, sv, ns, true, st_lo);
-            if (threadIdx.x == kWave) hup = chain(su, sv, ns, false, st_up);
+            // lower chain on wave 0, upper chain on wave 1, each split in chunks
+            if (threadIdx.x < kWave) chain_chunks(su, sv, ns, true, tmp_lo, len_lo);
+            else if (threadIdx.x < 2 * kWave) chain_chunks(su, sv, ns, false, tmp_up, len_up);
+            __syncthreads();
+            if (threadIdx.x == 0) hlo = chain_merge(su, sv, ns, tmp_lo, len_lo, st_lo);
+            if (threadIdx.x == kWave) hup = chain_merge(su, sv, ns, tmp_up, len_up, st_up);
             __syncthreads();
             if (threadIdx.x == 0) {
                 // hull = lower chain, then the upper chain without its end points

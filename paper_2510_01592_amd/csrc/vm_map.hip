@@ -137,11 +137,16 @@ __global__ void __launch_bounds__(kBlock) k_voxelize(const float* __restrict__ x
 //    updates the voxel's slot once.  Every key occurs in one run only, so no
 //    other lane touches that slot in this pass: the payload is a plain
 //    read-modify-write; only claiming an empty slot needs a CAS.
-__global__ void __launch_bounds__(kBlock) k_insert_runs(const uint32_t* __restrict__ key,
-                                                        const uint32_t* __restrict__ val,
+__global__ void __launch_bounds__(kBlock) k_insert_runs(const uint32_t* __restrict__ key0,
+                                                        const uint32_t* __restrict__ key1,
+                                                        const uint32_t* __restrict__ val0,
+                                                        const uint32_t* __restrict__ val1,
                                                         const unsigned long long* __restrict__ packed, Hash h,
                                                         uint32_t* __restrict__ bits, DevCounters* __restrict__ ctr)
 {
+    // the sort left the batch in buffer ctr->sort_sel
+    const uint32_t* __restrict__ key = ctr->sort_sel ? key1 : key0;
+    const uint32_t* __restrict__ val = ctr->sort_sel ? val1 : val0;
     const uint32_t n = ctr->sort_n;
     const uint32_t invalid_key = ctr->sort_max;
     uint32_t n_lost = 0, n_new = 0, n_runs = 0;
@@ -340,12 +345,12 @@ hipError_t launch_insert(const float* xyz, int64_t n, const Pose& pose, const Ge
         const uint32_t m = (uint32_t)((n - done) < (int64_t)sc.cap ? (n - done) : (int64_t)sc.cap);
         k_voxelize<<<grid_for(m, kBlock, kMapGrid), kBlock, 0, s>>>(xyz + 3 * done, m, pose, g, invalid_key, done == 0,
                                                                      keys[0], vals[0], sc.packed, ctr);
-        int res = 0;
         // the batch size is known here, so the sort's grids are sized by it
         hipError_t e = radix_sort_pairs_dev(keys, vals, &ctr->sort_n, m, bits_needed, &ctr->sort_max, sc.hist,
-                                            sc.blk, &res, s);
+                                            sc.blk, &ctr->sort_sel, s);
         if (e != hipSuccess) return e;
-        k_insert_runs<<<grid_for(m, kBlock, kMapGrid), kBlock, 0, s>>>(keys[res], vals[res], sc.packed, h, bits, ctr);
+        k_insert_runs<<<grid_for(m, kBlock, kMapGrid), kBlock, 0, s>>>(keys[0], keys[1], vals[0], vals[1], sc.packed,
+                                                                       h, bits, ctr);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     return hipSuccess;

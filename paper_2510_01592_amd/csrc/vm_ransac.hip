@@ -57,6 +57,8 @@ __global__ void __launch_bounds__(kBlock) k_hypotheses(const uint32_t* __restric
                                                        const float* __restrict__ Y, const float* __restrict__ Z,
                                                        uint32_t H, uint64_t seed, uint32_t frame_arg,
                                                        const uint32_t* __restrict__ d_frame,
+                                                       const uint32_t* __restrict__ tile_off,
+                                                       uint32_t* __restrict__ tile_k,
                                                        int32_t* __restrict__ counts, float4* __restrict__ hyp)
 {
     const uint32_t frame = d_frame ? *d_frame : frame_arg;
@@ -67,6 +69,9 @@ __global__ void __launch_bounds__(kBlock) k_hypotheses(const uint32_t* __restric
         const uint32_t k = (uint32_t)(idx / H), h = (uint32_t)(idx % H);
         const uint32_t base = off[k];
         const uint64_t n = (uint64_t)(off[k + 1] - base);
+        // the cluster of each of its point tiles, for the counting and inlier kernels
+        const uint32_t nt = (uint32_t)((n + kTile - 1) / kTile);
+        for (uint32_t q = h; q < nt; q += H) tile_k[tile_off[k] + q] = k;
         const float qnan = __builtin_nanf("");
         float4 pl = make_float4(qnan, qnan, qnan, qnan);
         if (n >= 3) {
@@ -131,18 +136,6 @@ __global__ void __launch_bounds__(kBlock) k_tiles(const uint32_t* __restrict__ s
         ntiles[k] = (off[k + 1] - off[k] + kTile - 1) / kTile;
 }
 
-__device__ __forceinline__ uint32_t cluster_of_tile(const uint32_t* __restrict__ tile_off, uint32_t K, uint32_t t)
-{
-    // largest k with tile_off[k] <= t (tile_off is the exclusive scan, K entries)
-    uint32_t lo = 0, hi = K;   // answer in [lo, hi)
-    while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (tile_off[mid] <= t) lo = mid;
-        else hi = mid;
-    }
-    return lo;
-}
-
 // (b) inlier counting over (tile, hypothesis-chunk) items.  The number of
 // hypothesis chunks is chosen on the device from the tile count so that small
 // frames still cover every CU; each item keeps its points in registers and
@@ -189,7 +182,7 @@ __device__ __forceinline__ void count_planes(const float4* __restrict__ hk, uint
 }
 
 __global__ void __launch_bounds__(kCountBlock) k_count(const uint32_t* __restrict__ small,
-                                                       const uint32_t* __restrict__ tile_off,
+                                                       const uint32_t* __restrict__ tile_off, const uint32_t* __restrict__ tile_k,
                                                        const uint32_t* __restrict__ off, const float* __restrict__ X,
                                                        const float* __restrict__ Y, const float* __restrict__ Z,
                                                        uint32_t H, float eps, const float4* __restrict__ hyp,
@@ -211,7 +204,7 @@ __global__ void __launch_bounds__(kCountBlock) k_count(const uint32_t* __restric
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     for (uint64_t item = blockIdx.x; item < items; item += gridDim.x) {
         const uint32_t t = (uint32_t)(item / HC), hc = (uint32_t)(item % HC);
-        const uint32_t k = cluster_of_tile(tile_off, K, t);
+        const uint32_t k = tile_k[t];
         const uint32_t p0 = off[k] + (t - tile_off[k]) * kTile;
         const uint32_t pend = off[k + 1];
         const uint32_t h0 = hc * chunk, h1 = min(H, h0 + chunk);
@@ -294,7 +287,7 @@ __device__ __forceinline__ bool inlier_test(const float4 pl, float x, float y, f
 
 // inlier flags of the winning plane, over the same tiles
 __global__ void __launch_bounds__(kCountBlock) k_inlier_flags(const uint32_t* __restrict__ small,
-                                                              const uint32_t* __restrict__ tile_off,
+                                                              const uint32_t* __restrict__ tile_off, const uint32_t* __restrict__ tile_k,
                                                               const uint32_t* __restrict__ off,
                                                               const float* __restrict__ X, const float* __restrict__ Y,
                                                               const float* __restrict__ Z, float eps,
@@ -305,7 +298,7 @@ __global__ void __launch_bounds__(kCountBlock) k_inlier_flags(const uint32_t* __
     const uint32_t K = small[0];
     const uint32_t T = small[1];
     for (uint32_t t = blockIdx.x; t < T; t += gridDim.x) {
-        const uint32_t k = cluster_of_tile(tile_off, K, t);
+        const uint32_t k = tile_k[t];
         const uint32_t p0 = off[k] + (t - tile_off[k]) * kTile;
         const uint32_t pend = min(p0 + kTile, off[k + 1]);
         const bool has = best[k] >= 0;
@@ -316,7 +309,7 @@ __global__ void __launch_bounds__(kCountBlock) k_inlier_flags(const uint32_t* __
 }
 
 __global__ void __launch_bounds__(kCountBlock) k_inlier_write(const uint32_t* __restrict__ small,
-                                                              const uint32_t* __restrict__ tile_off,
+                                                              const uint32_t* __restrict__ tile_off, const uint32_t* __restrict__ tile_k,
                                                               const uint32_t* __restrict__ off,
                                                               const float* __restrict__ X, const float* __restrict__ Y,
                                                               const float* __restrict__ Z, float eps,
@@ -329,7 +322,7 @@ __global__ void __launch_bounds__(kCountBlock) k_inlier_write(const uint32_t* __
     const uint32_t T = small[1];
     bool over = false;
     for (uint32_t t = blockIdx.x; t < T; t += gridDim.x) {
-        const uint32_t k = cluster_of_tile(tile_off, K, t);
+        const uint32_t k = tile_k[t];
         const uint32_t base = off[k];
         const uint32_t p0 = base + (t - tile_off[k]) * kTile;
         const uint32_t pend = min(p0 + kTile, off[k + 1]);
@@ -379,6 +372,7 @@ WorkLayout work_layout(void* base, uint32_t k_cap, uint32_t n_cap, uint32_t n_hy
     w.counts = (int32_t*)take(kh * sizeof(int32_t));
     w.hyp = (float4*)take(kh * sizeof(float4));
     w.tile_off = (uint32_t*)take(((size_t)k_cap + 2) * sizeof(uint32_t));
+    w.tile_k = (uint32_t*)take(((size_t)n_cap / kTile + k_cap + 2) * sizeof(uint32_t));
     w.flags = (uint32_t*)take(((size_t)n_cap + 1) * sizeof(uint32_t));
     const size_t blk_words = scan_blk_words((uint64_t)n_cap + k_cap + 2) + 64;
     w.blk = (uint32_t*)take(blk_words * sizeof(uint32_t));
@@ -414,13 +408,13 @@ vm_status ransac_planes(const vm_clusters& cl, const vm_ransac_params& p, const 
         VM_HIP(scan_exclusive_dev(w.tile_off, w.tile_off, w.small, kc, w.small + 1, w.blk, s));
         const uint64_t kh = (uint64_t)kc * H;
         k_hypotheses<<<grid_for(kh, kBlock, 16384), kBlock, 0, s>>>(w.small, cl.d_off, cl.d_tag, cl.d_x, cl.d_y,
-                                                                    cl.d_z, H, p.seed, p.frame, p.d_frame, w.counts,
-                                                                    w.hyp);
+                                                                    cl.d_z, H, p.seed, p.frame, p.d_frame,
+                                                                    w.tile_off, w.tile_k, w.counts, w.hyp);
         VM_HIP(hipGetLastError());
     }
     {
         StageScope t(VM_STAGE_COUNT, s);
-        k_count<<<2048, kCountBlock, 0, s>>>(w.small, w.tile_off, cl.d_off, cl.d_x, cl.d_y, cl.d_z, H, p.eps, w.hyp,
+        k_count<<<2048, kCountBlock, 0, s>>>(w.small, w.tile_off, w.tile_k, cl.d_off, cl.d_x, cl.d_y, cl.d_z, H, p.eps, w.hyp,
                                              w.counts);
         VM_HIP(hipGetLastError());
     }
@@ -430,10 +424,10 @@ vm_status ransac_planes(const vm_clusters& cl, const vm_ransac_params& p, const 
                                                                    out.d_best_h, out.d_n_inliers, out.d_counts,
                                                                    (float4*)out.d_hyp);
         const int tgrid = grid_for((uint64_t)cl.n_cap / kTile + kc + 1, 1, 8192);
-        k_inlier_flags<<<tgrid, kCountBlock, 0, s>>>(w.small, w.tile_off, cl.d_off, cl.d_x, cl.d_y, cl.d_z, p.eps,
+        k_inlier_flags<<<tgrid, kCountBlock, 0, s>>>(w.small, w.tile_off, w.tile_k, cl.d_off, cl.d_x, cl.d_y, cl.d_z, p.eps,
                                                      out.d_best_h, (const float4*)out.d_plane, w.flags);
         VM_HIP(scan_exclusive_dev(w.flags, w.flags, cl.d_meta + 1, cl.n_cap, w.small + 2, w.blk, s));
-        k_inlier_write<<<tgrid, kCountBlock, 0, s>>>(w.small, w.tile_off, cl.d_off, cl.d_x, cl.d_y, cl.d_z, p.eps,
+        k_inlier_write<<<tgrid, kCountBlock, 0, s>>>(w.small, w.tile_off, w.tile_k, cl.d_off, cl.d_x, cl.d_y, cl.d_z, p.eps,
                                                      out.d_best_h, (const float4*)out.d_plane, w.flags, out.in_cap,
                                                      out.d_in_idx, out.d_status);
         k_inlier_off<<<grid_for((uint64_t)kc + 1), kBlock, 0, s>>>(w.small, cl.d_off, w.flags, cl.d_meta,

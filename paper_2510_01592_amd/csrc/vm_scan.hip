@@ -65,39 +65,22 @@ __global__ void __launch_bounds__(kBlock) k_scan_reduce(const uint32_t* __restri
     if (threadIdx.x == 0) blk[blockIdx.x] = tot;
 }
 
-// One block scans the per-block totals (any count) in place.
-__global__ void __launch_bounds__(1024) k_scan_blocks(uint32_t* blk, uint32_t nblk, uint32_t* d_total)
-{
-    __shared__ uint32_t lds[1024 / kWave];
-    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-    uint32_t carry = 0;
-    for (uint32_t base = 0; base < nblk; base += 1024) {
-        const uint32_t i = base + threadIdx.x;
-        const uint32_t v = i < nblk ? blk[i] : 0u;
-        const uint32_t inc = wave_incl_scan(v, lane);
-        if (lane == kWave - 1) lds[wave] = inc;
-        __syncthreads();
-        uint32_t off = 0, tot = 0;
-        for (int w = 0; w < 1024 / kWave; ++w) {
-            const uint32_t t = lds[w];
-            off += (w < wave) ? t : 0u;
-            tot += t;
-        }
-        __syncthreads();
-        if (i < nblk) blk[i] = carry + off + inc - v;
-        carry += tot;
-    }
-    if (threadIdx.x == 0 && d_total) *d_total = carry;
-}
-
-__global__ void __launch_bounds__(kBlock) k_scan_down(const uint32_t* __restrict__ in, uint32_t* __restrict__ out,
-                                                      const uint32_t* d_n, uint32_t n_fixed,
-                                                      const uint32_t* __restrict__ blk)
+// Down-sweep: each tile adds up the totals of the tiles before it (a block-
+// wide sum over at most a few thousand words, read from L2), so the scan
+// needs no pass over the totals of its own and no workgroup waits on another.
+__global__ void __launch_bounds__(kBlock) k_scan_down(const uint32_t* in, uint32_t* out, const uint32_t* d_n,
+                                                      uint32_t n_fixed, const uint32_t* __restrict__ blk,
+                                                      uint32_t* d_total)
 {
     __shared__ uint32_t lds[kBlock / kWave];
     const uint32_t n = d_n ? min(*d_n, n_fixed) : n_fixed;
     const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
-    if (base >= n) return;
+    if (base >= n) {
+        if (blockIdx.x == 0 && threadIdx.x == 0 && d_total) *d_total = 0;   // n == 0
+        return;
+    }
+    uint32_t pre = 0;
+    for (uint32_t i = threadIdx.x; i < blockIdx.x; i += kBlock) pre += blk[i];
     // blocked arrangement: thread t owns values [t*I, t*I + I) of the tile
     uint32_t v[kScanItems];
     uint32_t s = 0;
@@ -108,32 +91,51 @@ __global__ void __launch_bounds__(kBlock) k_scan_down(const uint32_t* __restrict
         v[j] = i < n ? in[i] : 0u;
         s += v[j];
     }
+    uint32_t prefix;
+    block_excl_scan(pre, lds, &prefix);   // block total of the partial sums = prefix of this tile
     uint32_t tot;
-    uint32_t run = block_excl_scan(s, lds, &tot) + blk[blockIdx.x];
+    uint32_t run = block_excl_scan(s, lds, &tot) + prefix;
 #pragma unroll
     for (int j = 0; j < kScanItems; ++j) {
         const uint64_t i = mine + j;
         if (i < n) out[i] = run;
         run += v[j];
     }
+    if (d_total && threadIdx.x == 0 && base + kScanTile >= n) *d_total = prefix + tot;
 }
 
 // ---- radix sort ---------------------------------------------------------------
+// A pass runs if it is the first or the bound's digits from `shift` up are
+// not all zero (keys are at most the bound).
+__device__ __forceinline__ bool radix_pass_runs(const uint32_t* d_max_key, int shift)
+{
+    return shift == 0 || ((*d_max_key) >> shift) != 0u;
+}
+
 __global__ void __launch_bounds__(kBlock) k_radix_hist(const uint32_t* __restrict__ keys, const uint32_t* d_n,
-                                                       int shift, const uint32_t* d_max_key, uint32_t nblk,
-                                                       uint32_t* __restrict__ hist)
+                                                       int shift, int passes, const uint32_t* d_max_key, uint32_t nblk,
+                                                       uint32_t* __restrict__ hist, uint32_t* __restrict__ scan_n,
+                                                       uint32_t* __restrict__ d_sel)
 {
     __shared__ uint32_t cnt[kRadixBins];
+    const bool runs = radix_pass_runs(d_max_key, shift);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        // the scan of this pass's histograms covers nothing if the pass is skipped
+        *scan_n = runs ? (uint32_t)kRadixBins * nblk : 0u;
+        if (shift == 0) {
+            int ran = 1;
+            for (int p = 1; p < passes; ++p) ran += radix_pass_runs(d_max_key, p * kRadixBits) ? 1 : 0;
+            *d_sel = (uint32_t)(ran & 1);
+        }
+    }
+    if (!runs) return;
     const uint32_t n = *d_n;
     cnt[threadIdx.x] = 0;
     __syncthreads();
-    const bool identity = ((*d_max_key) >> shift) == 0u;
     const uint64_t base = (uint64_t)blockIdx.x * kRadixTile;
-    if (!identity) {
-        for (int j = 0; j < kRadixIters; ++j) {
-            const uint64_t i = base + (uint64_t)j * kBlock + threadIdx.x;
-            if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & (kRadixBins - 1)], 1u);
-        }
+    for (int j = 0; j < kRadixIters; ++j) {
+        const uint64_t i = base + (uint64_t)j * kBlock + threadIdx.x;
+        if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & (kRadixBins - 1)], 1u);
     }
     __syncthreads();
     hist[(uint64_t)threadIdx.x * nblk + blockIdx.x] = cnt[threadIdx.x];
@@ -147,17 +149,10 @@ __global__ void __launch_bounds__(kBlock) k_radix_scatter(const uint32_t* __rest
 {
     __shared__ uint32_t base[kRadixBins];
     __shared__ uint32_t wcnt[kBlock / kWave][kRadixBins];
+    if (!radix_pass_runs(d_max_key, shift)) return;
     const uint32_t n = *d_n;
     const uint64_t tile = (uint64_t)blockIdx.x * kRadixTile;
     if (tile >= n) return;
-    if (((*d_max_key) >> shift) == 0u) {
-        // every digit is zero: the stable pass is the identity permutation
-        for (int j = 0; j < kRadixIters; ++j) {
-            const uint64_t i = tile + (uint64_t)j * kBlock + threadIdx.x;
-            if (i < n) { kout[i] = kin[i]; vout[i] = vin[i]; }
-        }
-        return;
-    }
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     base[threadIdx.x] = hist[(uint64_t)threadIdx.x * nblk + blockIdx.x];
 #pragma unroll
@@ -209,14 +204,10 @@ size_t scan_blk_words(uint64_t n_cap)
 hipError_t scan_exclusive_dev(const uint32_t* in, uint32_t* out, const uint32_t* d_n, uint32_t n_cap,
                               uint32_t* d_total, uint32_t* blk, hipStream_t s)
 {
-    const uint32_t nblk = (uint32_t)((uint64_t(n_cap) + kScanTile - 1) / kScanTile);
-    if (nblk == 0) {
-        k_scan_blocks<<<1, 1024, 0, s>>>(blk, 0, d_total);
-        return hipGetLastError();
-    }
+    uint32_t nblk = (uint32_t)((uint64_t(n_cap) + kScanTile - 1) / kScanTile);
+    if (nblk == 0) nblk = 1;   // still writes the total (0)
     k_scan_reduce<<<nblk, kBlock, 0, s>>>(in, d_n, n_cap, blk);
-    k_scan_blocks<<<1, 1024, 0, s>>>(blk, nblk, d_total);
-    k_scan_down<<<nblk, kBlock, 0, s>>>(in, out, d_n, n_cap, blk);
+    k_scan_down<<<nblk, kBlock, 0, s>>>(in, out, d_n, n_cap, blk, d_total);
     return hipGetLastError();
 }
 
@@ -227,25 +218,25 @@ size_t radix_hist_words(uint64_t n_cap)
 
 hipError_t radix_sort_pairs_dev(uint32_t* keys[2], uint32_t* vals[2], const uint32_t* d_n, uint32_t n_cap,
                                 int bits, const uint32_t* d_max_key, uint32_t* hist, uint32_t* blk,
-                                int* result_buf, hipStream_t s)
+                                uint32_t* d_sel, hipStream_t s)
 {
-    const uint32_t nblk = (uint32_t)((uint64_t(n_cap) + kRadixTile - 1) / kRadixTile);
-    const int passes = (bits + kRadixBits - 1) / kRadixBits;
-    *result_buf = 0;
-    if (nblk == 0 || passes == 0) return hipSuccess;
+    uint32_t nblk = (uint32_t)((uint64_t(n_cap) + kRadixTile - 1) / kRadixTile);
+    if (nblk == 0) nblk = 1;   // still writes *d_sel
+    int passes = (bits + kRadixBits - 1) / kRadixBits;
+    if (passes < 1) passes = 1;
     const uint32_t hn = (uint32_t)kRadixBins * nblk;
+    // per-pass scan lengths live past the histograms (radix_hist_words leaves room)
+    uint32_t* scan_n = hist + hn + 8;
     hipError_t e = hipSuccess;
-    int src = 0;
     for (int p = 0; p < passes; ++p) {
         const int shift = p * kRadixBits;
-        k_radix_hist<<<nblk, kBlock, 0, s>>>(keys[src], d_n, shift, d_max_key, nblk, hist);
-        e = scan_exclusive_dev(hist, hist, nullptr, hn, nullptr, blk, s);
+        const int src = p & 1;
+        k_radix_hist<<<nblk, kBlock, 0, s>>>(keys[src], d_n, shift, passes, d_max_key, nblk, hist, scan_n + p, d_sel);
+        e = scan_exclusive_dev(hist, hist, scan_n + p, hn, nullptr, blk, s);
         if (e != hipSuccess) return e;
         k_radix_scatter<<<nblk, kBlock, 0, s>>>(keys[src], vals[src], keys[src ^ 1], vals[src ^ 1], d_n, shift,
                                                  d_max_key, nblk, hist);
-        src ^= 1;
     }
-    *result_buf = src;
     return hipGetLastError();
 }
 
