@@ -83,14 +83,6 @@ struct Dims {
     uint32_t nx, ny, nz, nxy;
 };
 
-// a voxel joined to another across rows: both ends are marked (stores of 1
-// only, so concurrent marks cannot conflict)
-__device__ __forceinline__ void link(uint32_t* parent, uint32_t* linked, uint32_t a, uint32_t b)
-{
-    linked[a] = 1u;
-    linked[b] = 1u;
-    uf_unite(parent, a, b);
-}
 
 // ---- tiled labelling ------------------------------------------------------------
 // The grid is cut into 32 x 16 x 16-cell tiles, one workgroup each.  Thread
@@ -212,7 +204,7 @@ constexpr uint32_t kPairCap = 2048;   // hook pairs buffered per tile (more are 
 
 __global__ void __launch_bounds__(kBlock) k_ccl_tile(const uint32_t* __restrict__ bits, uint32_t nwords,
                                                      const uint32_t* __restrict__ wrank, Dims d, TileGrid tg,
-                                                     uint32_t* __restrict__ parent, uint32_t* __restrict__ linked)
+                                                     uint32_t* __restrict__ parent, uint32_t* __restrict__ csize)
 {
     __shared__ uint32_t rowv[kTileRows];
     __shared__ uint32_t rowrank[kTileRows];
@@ -270,7 +262,7 @@ __global__ void __launch_bounds__(kBlock) k_ccl_tile(const uint32_t* __restrict_
         }
         __syncthreads();
         // roots of the run starts (a start's entry then holds its root); a
-        // root with another member is marked
+        // root with another run or another cell is marked
         for (uint32_t m = sv; m; m &= m - 1) {
             const int s0 = __ffs(m) - 1;
             const int e0 = __ffs(ev & ~((1u << s0) - 1u)) - 1;
@@ -281,8 +273,9 @@ __global__ void __launch_bounds__(kBlock) k_ccl_tile(const uint32_t* __restrict_
         }
         __syncthreads();
         // global parents: the rank of the local root, for a whole run at once
-        // (consecutive cells of a run have consecutive ranks); a voxel is
-        // linked if its local component has another member
+        // (consecutive cells of a run have consecutive ranks); the local
+        // root's rank counts its component's voxels in the tile (a lone voxel
+        // stores its 1, other runs add their lengths)
         for (uint32_t m = sv; m; m &= m - 1) {
             const int s0 = __ffs(m) - 1;
             const int e0 = __ffs(ev & ~((1u << s0) - 1u)) - 1;
@@ -290,12 +283,10 @@ __global__ void __launch_bounds__(kBlock) k_ccl_tile(const uint32_t* __restrict_
             const uint32_t rt = par[c];
             const uint32_t rrow = rt / kTX, rx = rt % kTX;
             const uint32_t rr = rowrank[rrow] + __popc(rowv[rrow] & ((1u << rx) - 1u));
-            const uint32_t lk = (e0 > s0 || rt != c || ((members[c >> 5] >> (c & 31)) & 1u)) ? 1u : 0u;
             const uint32_t r = rowrank[j] + __popc(v & ((1u << s0) - 1u));
-            for (int i = 0; i <= e0 - s0; ++i) {
-                parent[r + i] = rr;
-                linked[r + i] = lk;
-            }
+            for (int i = 0; i <= e0 - s0; ++i) parent[r + i] = rr;
+            if (e0 == s0 && rt == c && !((members[c >> 5] >> (c & 31)) & 1u)) csize[r] = 1u;
+            else atomicAdd(&csize[rr], (uint32_t)(e0 - s0 + 1));
         }
         __syncthreads();   // LDS is reused by the next tile
     }
@@ -316,8 +307,8 @@ __device__ __forceinline__ bool occ_cell(const uint32_t* __restrict__ bits, cons
 //    a smaller key at x - 1 (five of them), the last cell each one at x + 1
 //    (four); these pairs lie in tiles of another x range.
 // Each pair is replaced by the local roots of its two voxels (the labelling
-// pass left every voxel pointing at its tile-local root), both voxels are
-// marked linked, and a tile keeps one copy of each distinct root pair (an
+// pass left every voxel pointing at its tile-local root), and a tile keeps
+// one copy of each distinct root pair (an
 // LDS hash set): along a dense surface many cells link the same two local
 // components.  The distinct pairs go to the tile's slice of a pair buffer; a
 // second kernel unites all pairs of the grid at once.  A tile with more
@@ -326,8 +317,8 @@ constexpr uint32_t kPairHash = 1024;   // LDS hash set of root pairs per tile
 
 __global__ void __launch_bounds__(kBlock) k_ccl_boundary(const uint32_t* __restrict__ bits, uint32_t nwords,
                                                          const uint32_t* __restrict__ wrank, Dims d, TileGrid tg,
-                                                         uint32_t* parent, uint32_t* linked,
-                                                         uint64_t* __restrict__ pairs, uint32_t* __restrict__ npair)
+                                                         uint32_t* parent, uint64_t* __restrict__ pairs,
+                                                         uint32_t* __restrict__ npair)
 {
     __shared__ uint64_t buf[kCclTilePairs];
     __shared__ unsigned long long hset[kPairHash];
@@ -345,8 +336,6 @@ __global__ void __launch_bounds__(kBlock) k_ccl_boundary(const uint32_t* __restr
         uint32_t key0;
         const uint32_t v = row_bits(bits, nwords, d, x0, (uint32_t)y, (uint32_t)z, &key0);
         auto emit = [&](uint32_t a, uint32_t b) {
-            linked[a] = 1u;
-            linked[b] = 1u;
             const uint32_t ra = ld_parent(&parent[a]), rb = ld_parent(&parent[b]);
             const unsigned long long key = ((unsigned long long)ra << 32) | rb;
             uint32_t h = (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> 54);   // kPairHash = 2^10 slots
@@ -429,7 +418,8 @@ __global__ void __launch_bounds__(kBlock) k_ccl_pairs(uint32_t ntiles, const uin
 // writing anything on the way (a path-halving store here could overwrite the
 // root another thread has just stored for that node) and stores only its own
 // entry; every value a walk can read is an ancestor, so walks stay correct.
-__global__ void __launch_bounds__(kBlock) k_ccl_flatten(const DevCounters* __restrict__ ctr, uint32_t* parent)
+__global__ void __launch_bounds__(kBlock) k_ccl_flatten(const DevCounters* __restrict__ ctr, uint32_t* parent,
+                                                        uint32_t* csize)
 {
     const uint32_t V = ctr->n_occ;
     for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < V; r += gridDim.x * blockDim.x) {
@@ -439,72 +429,14 @@ __global__ void __launch_bounds__(kBlock) k_ccl_flatten(const DevCounters* __res
             p = ld_parent(&parent[x]);
         }
         st_parent(&parent[r], x);
-    }
-}
-
-// Component sizes at the roots.  A voxel never linked to another is a
-// component of its own: size 1, a plain store.  For the rest, consecutive
-// ranks mostly share a root: a wave first sums each run of equal roots, then
-// the block merges its runs in an LDS table and adds one count per distinct
-// root (a large component's root would otherwise take an atomic from every
-// wave that holds part of it).
-constexpr int kSizeItems = 8;
-constexpr int kSizeSpan = kBlock * kSizeItems;   // ranks per block pass
-constexpr int kSizeTab = kSizeSpan;              // one slot per possible root
-static_assert(kSizeTab == 1 << 11, "the table hash below indexes 2^11 slots");
-
-__global__ void __launch_bounds__(kBlock) k_ccl_sizes(const DevCounters* __restrict__ ctr,
-                                                      const uint32_t* __restrict__ parent,
-                                                      const uint32_t* __restrict__ linked, uint32_t* csize)
-{
-    __shared__ uint32_t tkey[kSizeTab];
-    __shared__ uint32_t tcnt[kSizeTab];
-    const uint32_t V = ctr->n_occ;
-    const int lane = threadIdx.x & (kWave - 1);
-    for (uint32_t base = blockIdx.x * kSizeSpan; base < V; base += gridDim.x * kSizeSpan) {
-        for (int i = threadIdx.x; i < kSizeTab; i += kBlock) {
-            tkey[i] = kEmpty;
-            tcnt[i] = 0;
+        // a tile-local root joined to another tile's component hands its
+        // count to the component's root (only roots receive counts, so the
+        // count read here is final)
+        if (x != r) {
+            const uint32_t cs = csize[r];
+            if (cs) atomicAdd(&csize[x], cs);
         }
-        __syncthreads();
-        for (int it = 0; it < kSizeItems; ++it) {
-            const uint32_t r = base + it * kBlock + threadIdx.x;
-            const bool in = r < V;
-            const bool alone = in && linked[r] == 0u;
-            if (alone) csize[r] = 1u;
-            const bool valid = in && !alone;
-            const uint32_t root = valid ? parent[r] : 0xFFFFFFFFu;
-            const uint32_t prev = __shfl_up(root, 1, kWave);
-            const uint64_t vmask = __ballot(valid);
-            const bool prev_valid = lane > 0 && ((vmask >> (lane - 1)) & 1ull);
-            const bool head = valid && (!prev_valid || prev != root);
-            // a run ends before the next head or the next lane that is not valid
-            const uint64_t stops = __ballot(head) | ~vmask;
-            if (head) {
-                const uint64_t after = (lane == 63) ? 0ull : (stops & (~0ull << (lane + 1)));
-                const uint32_t len = (after ? (uint32_t)(__ffsll((long long)after) - 1) : 64u) - (uint32_t)lane;
-                uint32_t h = (root * 2654435769u) >> (32 - 11);   // kSizeTab = 2^11 slots
-                for (;;) {
-                    const uint32_t old = atomicCAS(&tkey[h], kEmpty, root);
-                    if (old == kEmpty || old == root) {
-                        atomicAdd(&tcnt[h], len);
-                        break;
-                    }
-                    h = (h + 1) & (kSizeTab - 1);
-                }
-            }
-        }
-        __syncthreads();
-        for (int i = threadIdx.x; i < kSizeTab; i += kBlock)
-            if (tkey[i] != kEmpty) atomicAdd(&csize[tkey[i]], tcnt[i]);
-        __syncthreads();
     }
-}
-
-__global__ void __launch_bounds__(kBlock) k_zero(uint32_t* p, const DevCounters* __restrict__ ctr)
-{
-    const uint32_t V = ctr->n_occ;
-    for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < V; r += gridDim.x * blockDim.x) p[r] = 0;
 }
 
 // ---- grouping -------------------------------------------------------------------
@@ -637,14 +569,13 @@ hipError_t launch_ccl(const Geom& g, const uint32_t* bits, SegBuffers& b, uint32
     const int tgrid = (int)(ntiles < 16384 ? ntiles : 16384);
     {
         StageScope t(VM_STAGE_CCL, s);
-        k_ccl_tile<<<tgrid, kBlock, 0, s>>>(bits, g.nwords, b.wrank, d, tg, b.parent, b.scan_a);
+        k_ccl_tile<<<tgrid, kBlock, 0, s>>>(bits, g.nwords, b.wrank, d, tg, b.parent, b.csize);
     }
     {
         StageScope t(VM_STAGE_CCL_LINK, s);
-        k_ccl_boundary<<<tgrid, kBlock, 0, s>>>(bits, g.nwords, b.wrank, d, tg, b.parent, b.scan_a, b.pairs,
-                                                b.npair);
+        k_ccl_boundary<<<tgrid, kBlock, 0, s>>>(bits, g.nwords, b.wrank, d, tg, b.parent, b.pairs, b.npair);
         k_ccl_pairs<<<tgrid, kBlock, 0, s>>>((uint32_t)ntiles, b.pairs, b.npair, b.parent);
-        k_ccl_flatten<<<grid, kBlock, 0, s>>>(ctr, b.parent);
+        k_ccl_flatten<<<grid, kBlock, 0, s>>>(ctr, b.parent, b.csize);
     }
     return hipGetLastError();
 }
@@ -655,9 +586,6 @@ hipError_t launch_group(const Geom& g, const Hash& h, SegBuffers& b, uint32_t ca
     StageScope t(VM_STAGE_GROUP, s);
     const int grid = grid_for(cap);
     if (min_cluster < 1) min_cluster = 1;
-    k_zero<<<grid, kBlock, 0, s>>>(b.csize, ctr);
-    // scan_a: linked flags from the CCL
-    k_ccl_sizes<<<grid_for(cap, kSizeSpan, 1024), kBlock, 0, s>>>(ctr, b.parent, b.scan_a, b.csize);
     uint32_t* is_root = b.scan_a;
     uint32_t* root_size = b.scan_b;
     uint32_t* keep = b.sort_k[1];

@@ -211,15 +211,18 @@ __global__ void __launch_bounds__(kBlock) k_popc(const uint32_t* __restrict__ bi
 }
 
 // Occupied keys in ascending order: word w's set bits go to ranks wrank[w]...
+// Occupied keys in rank order; the component-size counters of the ranks are
+// cleared on the way (the labelling accumulates into them).
 __global__ void __launch_bounds__(kBlock) k_compact(const uint32_t* __restrict__ bits, uint32_t nwords,
                                                     const uint32_t* __restrict__ wrank,
-                                                    uint32_t* __restrict__ occ_key)
+                                                    uint32_t* __restrict__ occ_key, uint32_t* __restrict__ csize)
 {
     for (uint32_t w = blockIdx.x * blockDim.x + threadIdx.x; w < nwords; w += gridDim.x * blockDim.x) {
         uint32_t b = bits[w];
         uint32_t r = wrank[w];
         while (b) {
             const uint32_t j = __ffs(b) - 1;
+            csize[r] = 0u;
             occ_key[r++] = (w << 5) | j;
             b &= b - 1;
         }
@@ -362,7 +365,7 @@ hipError_t launch_rank(const Geom& g, const uint32_t* bits, SegBuffers& b, uint3
     k_popc<<<grid_for(g.nwords), kBlock, 0, s>>>(bits, g.nwords, b.wrank);
     hipError_t e = scan_exclusive_dev(b.wrank, b.wrank, nullptr, g.nwords, &ctr->n_occ, b.blk, s);
     if (e != hipSuccess) return e;
-    k_compact<<<grid_for(g.nwords), kBlock, 0, s>>>(bits, g.nwords, b.wrank, b.occ_key);
+    k_compact<<<grid_for(g.nwords), kBlock, 0, s>>>(bits, g.nwords, b.wrank, b.occ_key, b.csize);
     return hipGetLastError();
 }
 

@@ -21,8 +21,8 @@ namespace vm {
 namespace {
 
 constexpr int kCountBlock = 256;
-constexpr int kPtsPerLane = 8;
-constexpr int kTile = kCountBlock * kPtsPerLane;   // points per tile (2048)
+constexpr int kPtsPerLane = 16;
+constexpr int kTile = kCountBlock * kPtsPerLane;   // points per tile (4096)
 constexpr int kMaxHypChunk = 4096;                 // hypotheses per work item (LDS counters)
 constexpr int kHypBatch = 4;                       // planes loaded together
 
@@ -156,28 +156,37 @@ __device__ __forceinline__ uint32_t count_rows(const float4 pl, const float* px,
     return acc;
 }
 
+// Planes h0..h1 against the wave's points.  A wave's count for a plane is
+// uniform; the counts of up to 64 consecutive planes are gathered in one
+// register (lane q keeps plane hb + q) and added to the block's LDS counters
+// with one vector LDS add per 64 planes.
 template <int R>
 __device__ __forceinline__ void count_planes(const float4* __restrict__ hk, uint32_t h0, uint32_t h1,
                                              const float* px, const float* py, const float* pz, float eps,
                                              uint32_t* lcnt, int lane)
 {
-    uint32_t h = h0;
-    for (; h + kHypBatch <= h1; h += kHypBatch) {
-        float4 pl[kHypBatch];
+    for (uint32_t hb = h0; hb < h1; hb += kWave) {
+        const uint32_t he = min(h1, hb + (uint32_t)kWave);
+        int cv = 0;
+        uint32_t h = hb;
+        for (; h + kHypBatch <= he; h += kHypBatch) {
+            float4 pl[kHypBatch];
 #pragma unroll
-        for (int b = 0; b < kHypBatch; ++b) pl[b] = hk[h + b];
+            for (int b = 0; b < kHypBatch; ++b) pl[b] = hk[h + b];
 #pragma unroll
-        for (int b = 0; b < kHypBatch; ++b) {
-            if (pl[b].x != pl[b].x) continue;   // degenerate hypothesis
-            const uint32_t acc = count_rows<R>(pl[b], px, py, pz, eps);
-            if (lane == 0 && acc) atomicAdd(&lcnt[h + b - h0], acc);
+            for (int b = 0; b < kHypBatch; ++b) {
+                if (pl[b].x != pl[b].x) continue;   // degenerate hypothesis
+                const uint32_t acc = count_rows<R>(pl[b], px, py, pz, eps);
+                cv = (lane == (int)(h + b - hb)) ? (int)acc : cv;
+            }
         }
-    }
-    for (; h < h1; ++h) {
-        const float4 pl = hk[h];
-        if (pl.x != pl.x) continue;
-        const uint32_t acc = count_rows<R>(pl, px, py, pz, eps);
-        if (lane == 0 && acc) atomicAdd(&lcnt[h - h0], acc);
+        for (; h < he; ++h) {
+            const float4 pl = hk[h];
+            if (pl.x != pl.x) continue;
+            const uint32_t acc = count_rows<R>(pl, px, py, pz, eps);
+            cv = (lane == (int)(h - hb)) ? (int)acc : cv;
+        }
+        if ((uint32_t)lane < he - hb && cv) atomicAdd(&lcnt[hb - h0 + (uint32_t)lane], (uint32_t)cv);
     }
 }
 
@@ -189,7 +198,6 @@ __global__ void __launch_bounds__(kCountBlock) k_count(const uint32_t* __restric
                                                        int32_t* __restrict__ counts)
 {
     __shared__ uint32_t lcnt[kMaxHypChunk];
-    const uint32_t K = small[0];
     const uint32_t T = small[1];
     if (T == 0) return;
     // chunks per tile: enough items for two per block of the grid, chunks of
@@ -224,8 +232,9 @@ __global__ void __launch_bounds__(kCountBlock) k_count(const uint32_t* __restric
         __syncthreads();
         const float4* hk = hyp + (size_t)k * H;
         // rows is wave-uniform; rows past the cluster's end hold NaN points
-        if (rows == kPtsPerLane) count_planes<kPtsPerLane>(hk, h0, h1, px, py, pz, eps, lcnt, lane);
-        else if (rows > 4) count_planes<kPtsPerLane>(hk, h0, h1, px, py, pz, eps, lcnt, lane);
+        static_assert(kPtsPerLane == 16, "the row dispatch below assumes 16 rows per lane");
+        if (rows > 8) count_planes<16>(hk, h0, h1, px, py, pz, eps, lcnt, lane);
+        else if (rows > 4) count_planes<8>(hk, h0, h1, px, py, pz, eps, lcnt, lane);
         else if (rows > 2) count_planes<4>(hk, h0, h1, px, py, pz, eps, lcnt, lane);
         else if (rows > 1) count_planes<2>(hk, h0, h1, px, py, pz, eps, lcnt, lane);
         else if (rows == 1) count_planes<1>(hk, h0, h1, px, py, pz, eps, lcnt, lane);
@@ -295,7 +304,6 @@ __global__ void __launch_bounds__(kCountBlock) k_inlier_flags(const uint32_t* __
                                                               const float4* __restrict__ plane,
                                                               uint32_t* __restrict__ flags)
 {
-    const uint32_t K = small[0];
     const uint32_t T = small[1];
     for (uint32_t t = blockIdx.x; t < T; t += gridDim.x) {
         const uint32_t k = tile_k[t];
@@ -318,7 +326,6 @@ __global__ void __launch_bounds__(kCountBlock) k_inlier_write(const uint32_t* __
                                                               const uint32_t* __restrict__ pos, uint32_t in_cap,
                                                               uint32_t* __restrict__ in_idx, uint32_t* __restrict__ status)
 {
-    const uint32_t K = small[0];
     const uint32_t T = small[1];
     bool over = false;
     for (uint32_t t = blockIdx.x; t < T; t += gridDim.x) {
@@ -414,7 +421,7 @@ vm_status ransac_planes(const vm_clusters& cl, const vm_ransac_params& p, const 
     }
     {
         StageScope t(VM_STAGE_COUNT, s);
-        k_count<<<2048, kCountBlock, 0, s>>>(w.small, w.tile_off, w.tile_k, cl.d_off, cl.d_x, cl.d_y, cl.d_z, H, p.eps, w.hyp,
+        k_count<<<4096, kCountBlock, 0, s>>>(w.small, w.tile_off, w.tile_k, cl.d_off, cl.d_x, cl.d_y, cl.d_z, H, p.eps, w.hyp,
                                              w.counts);
         VM_HIP(hipGetLastError());
     }
