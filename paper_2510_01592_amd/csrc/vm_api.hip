@@ -6,6 +6,7 @@
 #include <vector>
 
 #include "vm_common.h"
+#include "vm_tilescan.h"
 
 using namespace vm;
 
@@ -280,7 +281,8 @@ vm_status vm_map_create(const vm_map_desc* d, vm_map* out)
     const uint32_t batch = 1u << (d->insert_batch_log2 ? d->insert_batch_log2 : 22);
     const uint64_t scan_n = std::max<uint64_t>(std::max<uint64_t>(cap, m->g.nwords),
                                                std::max<uint64_t>(radix_hist_words(cap), radix_hist_words(batch)));
-    A((void**)&b.blk, scan_blk_words(scan_n) * 4);
+    // scan partials; also the fused scans' per-tile totals (3 words per 1024 items)
+    A((void**)&b.blk, std::max<size_t>(scan_blk_words(scan_n), 3 * (size_t)ts_tiles(scan_n)) * 4);
     A((void**)&b.hist, radix_hist_words(cap) * 4);
     A((void**)&b.pairs, ccl_tiles(m->g) * kCclTilePairs * 8);
     A((void**)&b.npair, ccl_tiles(m->g) * 4);

@@ -20,6 +20,7 @@
 // 26-neighbourhood never needs the hash: occupancy and ranks come from the
 // 1-bit-per-cell index.
 #include "vm_common.h"
+#include "vm_tilescan.h"
 
 namespace vm {
 namespace {
@@ -440,49 +441,53 @@ __global__ void __launch_bounds__(kBlock) k_ccl_flatten(const DevCounters* __res
 }
 
 // ---- grouping -------------------------------------------------------------------
-// flags for the two scans: kept root -> 1 (cluster id), and its size (offset)
-__global__ void __launch_bounds__(kBlock) k_group_flags(const DevCounters* __restrict__ ctr,
-                                                        const uint32_t* __restrict__ parent,
-                                                        const uint32_t* __restrict__ csize, uint32_t min_cluster,
-                                                        uint32_t* __restrict__ is_root, uint32_t* __restrict__ root_size,
-                                                        uint32_t* __restrict__ keep)
-{
-    const uint32_t V = ctr->n_occ;
-    for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < V; r += gridDim.x * blockDim.x) {
+// One fused scan over the ranks gives, in rank order: the cluster id of each
+// kept root (roots of components with at least min_cluster voxels), the
+// cluster offsets (running sum of the kept roots' sizes, i.e. clusters in
+// label order), and each kept voxel's position among the kept voxels.
+struct GroupF {
+    const uint32_t* parent;
+    const uint32_t* csize;
+    uint32_t min_cluster;
+    __device__ Vec<3> operator()(uint32_t r) const
+    {
         const uint32_t root = parent[r];
         const uint32_t sz = csize[root];
         const bool kept = sz >= min_cluster;
         const bool rt = kept && root == r;
-        is_root[r] = rt ? 1u : 0u;
-        root_size[r] = rt ? sz : 0u;
-        keep[r] = kept ? 1u : 0u;
+        Vec<3> x;
+        x.v[0] = rt ? 1u : 0u;
+        x.v[1] = rt ? sz : 0u;
+        x.v[2] = kept ? 1u : 0u;
+        return x;
     }
-}
+};
 
-__global__ void __launch_bounds__(kBlock) k_group_clusters(DevCounters* __restrict__ ctr,
-                                                           const uint32_t* __restrict__ parent,
-                                                           const uint32_t* __restrict__ csize, uint32_t min_cluster,
-                                                           const uint32_t* __restrict__ occ_key,
-                                                           const uint32_t* __restrict__ cid_scan,
-                                                           const uint32_t* __restrict__ off_scan,
-                                                           uint32_t* __restrict__ cl_off, uint32_t* __restrict__ cl_tag)
-{
-    const uint32_t V = ctr->n_occ;
-    for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < V; r += gridDim.x * blockDim.x) {
-        if (parent[r] == r && csize[r] >= min_cluster) {
-            const uint32_t c = cid_scan[r];
-            cl_off[c] = off_scan[r];
-            cl_tag[c] = occ_key[r];
+struct GroupG {
+    uint32_t* cid;        // cluster id, at kept roots
+    uint32_t* kpos;       // position among kept voxels, at kept voxels
+    uint32_t* cl_off;
+    uint32_t* cl_tag;
+    const uint32_t* occ_key;
+    DevCounters* ctr;
+    __device__ void operator()(uint32_t r, const Vec<3>& x, const Vec<3>& pre) const
+    {
+        if (x.v[2]) kpos[r] = pre.v[2];
+        if (x.v[0]) {
+            cid[r] = pre.v[0];
+            cl_off[pre.v[0]] = pre.v[1];
+            cl_tag[pre.v[0]] = occ_key[r];
         }
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        const uint32_t K = ctr->meta[0];
-        cl_off[K] = ctr->meta[1];
-        ctr->kmax = K ? K - 1 : 0;
+    __device__ void total(const Vec<3>& t) const
+    {
+        ctr->meta[0] = t.v[0];
+        ctr->meta[1] = t.v[1];
+        cl_off[t.v[0]] = t.v[1];
+        ctr->kmax = t.v[0] ? t.v[0] - 1 : 0;
     }
-}
+};
 
-// (cluster id, rank) pairs of the kept voxels, in rank order
 __global__ void __launch_bounds__(kBlock) k_group_pairs(const DevCounters* __restrict__ ctr,
                                                         const uint32_t* __restrict__ parent,
                                                         const uint32_t* __restrict__ csize, uint32_t min_cluster,
@@ -586,18 +591,14 @@ hipError_t launch_group(const Geom& g, const Hash& h, SegBuffers& b, uint32_t ca
     StageScope t(VM_STAGE_GROUP, s);
     const int grid = grid_for(cap);
     if (min_cluster < 1) min_cluster = 1;
-    uint32_t* is_root = b.scan_a;
-    uint32_t* root_size = b.scan_b;
+    uint32_t* cid = b.scan_a;
     uint32_t* keep = b.sort_k[1];
-    k_group_flags<<<grid, kBlock, 0, s>>>(ctr, b.parent, b.csize, min_cluster, is_root, root_size, keep);
+    const GroupF f{b.parent, b.csize, min_cluster};
+    const GroupG gg{cid, keep, b.cl_off, b.cl_tag, b.occ_key, ctr};
+    Vec<3>* tiles = reinterpret_cast<Vec<3>*>(b.blk);
+    tile_scan<3>(f, gg, &ctr->n_occ, cap, tiles, s);
     hipError_t e;
-    if ((e = scan_exclusive_dev(is_root, is_root, &ctr->n_occ, cap, &ctr->meta[0], b.blk, s)) != hipSuccess) return e;
-    if ((e = scan_exclusive_dev(root_size, root_size, &ctr->n_occ, cap, &ctr->meta[1], b.blk, s)) != hipSuccess)
-        return e;
-    if ((e = scan_exclusive_dev(keep, keep, &ctr->n_occ, cap, nullptr, b.blk, s)) != hipSuccess) return e;
-    k_group_clusters<<<grid, kBlock, 0, s>>>(ctr, b.parent, b.csize, min_cluster, b.occ_key, is_root, root_size,
-                                             b.cl_off, b.cl_tag);
-    k_group_pairs<<<grid, kBlock, 0, s>>>(ctr, b.parent, b.csize, min_cluster, is_root, keep, b.sort_k[0],
+    k_group_pairs<<<grid, kBlock, 0, s>>>(ctr, b.parent, b.csize, min_cluster, cid, keep, b.sort_k[0],
                                           b.sort_v[0]);
     // stable sort by cluster id keeps ascending keys inside each cluster
     const uint32_t kbound = cap / min_cluster + 1;

@@ -386,14 +386,13 @@ __device__ __forceinline__ void swap3(double* U, double* V, uint32_t* I, uint32_
 // the inner side of a segment between two other points (such a point is no
 // vertex of the hull of any set holding those three; collinear and
 // coincident points are kept, so the choice among them is left to the full
-// rule); lane 0 then runs the
-// chain (dropping collinear and coincident points as well) over the
-// concatenated chunk results, which gives the output of the plain chain over
-// all n points.  All lanes of the wave call chain_chunks; lens has kWave
-// entries.
+// rule); the chunk results are concatenated into seq, and one thread then
+// runs the chain (dropping collinear and coincident points as well) over
+// them, which gives the output of the plain chain over all n points.  All
+// lanes of the wave call chain_chunks.
 template <typename S>
 __device__ __forceinline__ void chain_chunks(const double* U, const double* V, uint32_t n, bool forward, S* tmp,
-                                             uint32_t* lens)
+                                             S* seq, uint32_t* seq_len)
 {
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint32_t c = (n + kWave - 1) / kWave;
@@ -409,25 +408,54 @@ __device__ __forceinline__ void chain_chunks(const double* U, const double* V, u
         }
         tmp[s0 + h++] = (S)i;
     }
-    lens[lane] = h;
+    // concatenate the chunk results into seq (wave prefix sum of the lengths)
+    uint32_t inc = h;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint32_t t = __shfl_up(inc, d, kWave);
+        if ((int)lane >= d) inc += t;
+    }
+    const uint32_t off = inc - h;
+    for (uint32_t q = 0; q < h; ++q) seq[off + q] = tmp[s0 + q];
+    if (lane == kWave - 1) *seq_len = inc;
 }
 
+// The plain chain over seq[0, m), run by one thread.  The coordinates of the
+// two top stack entries stay in registers and the next point is fetched one
+// step ahead, so a step waits on LDS only when it pops.
 template <typename S>
-__device__ __forceinline__ uint32_t chain_merge(const double* U, const double* V, uint32_t n, const S* tmp,
-                                                const uint32_t* lens, S* st)
+__device__ __forceinline__ uint32_t chain_merge(const double* U, const double* V, const S* seq, uint32_t m, S* st)
 {
-    const uint32_t c = (n + kWave - 1) / kWave;
     uint32_t h = 0;
-    for (uint32_t l = 0; l < (uint32_t)kWave; ++l) {
-        for (uint32_t q = 0; q < lens[l]; ++q) {
-            const uint32_t i = tmp[l * c + q];
-            while (h >= 2) {
-                const uint32_t a = st[h - 2], b = st[h - 1];
-                if (cross3(U[a], V[a], U[b], V[b], U[i], V[i]) <= 0.0) --h;
-                else break;
-            }
-            st[h++] = (S)i;
+    double au = 0.0, av = 0.0, bu = 0.0, bv = 0.0;   // st[h - 2], st[h - 1]
+    uint32_t inext = m ? (uint32_t)seq[0] : 0u;
+    double nu = m ? U[inext] : 0.0, nv = m ? V[inext] : 0.0;
+    for (uint32_t j = 0; j < m; ++j) {
+        const uint32_t i = inext;
+        const double iu = nu, iv = nv;
+        if (j + 1 < m) {
+            inext = seq[j + 1];
+            nu = U[inext];
+            nv = V[inext];
         }
+        while (h >= 2 && cross3(au, av, bu, bv, iu, iv) <= 0.0) {
+            --h;
+            bu = au;
+            bv = av;
+            if (h >= 2) {
+                const uint32_t a = st[h - 2];
+                au = U[a];
+                av = V[a];
+            }
+        }
+        st[h] = (S)i;
+        if (h >= 1) {
+            au = bu;
+            av = bv;
+        }
+        bu = iu;
+        bv = iv;
+        ++h;
     }
     return h;
 }
@@ -445,7 +473,9 @@ __global__ void __launch_bounds__(kChainBlock) k_hull_chain(
     __shared__ uint16_t st_up[kLdsCap + 1];
     __shared__ uint16_t tmp_lo[kLdsCap];
     __shared__ uint16_t tmp_up[kLdsCap];
-    __shared__ uint32_t len_lo[kWave], len_up[kWave];
+    __shared__ uint16_t seq_lo[kLdsCap];
+    __shared__ uint16_t seq_up[kLdsCap];
+    __shared__ uint32_t m_lo, m_up;
     __shared__ uint32_t hlo, hup;
     const uint32_t K = small[4];
     const uint32_t T = small[6];
@@ -485,11 +515,11 @@ __global__ void __launch_bounds__(kChainBlock) k_hull_chain(
                 }
             }
             // lower chain on wave 0, upper chain on wave 1, each split in chunks
-            if (threadIdx.x < kWave) chain_chunks(su, sv, ns, true, tmp_lo, len_lo);
-            else if (threadIdx.x < 2 * kWave) chain_chunks(su, sv, ns, false, tmp_up, len_up);
+            if (threadIdx.x < kWave) chain_chunks(su, sv, ns, true, tmp_lo, seq_lo, &m_lo);
+            else if (threadIdx.x < 2 * kWave) chain_chunks(su, sv, ns, false, tmp_up, seq_up, &m_up);
             __syncthreads();
-            if (threadIdx.x == 0) hlo = chain_merge(su, sv, ns, tmp_lo, len_lo, st_lo);
-            if (threadIdx.x == kWave) hup = chain_merge(su, sv, ns, tmp_up, len_up, st_up);
+            if (threadIdx.x == 0) hlo = chain_merge(su, sv, seq_lo, m_lo, st_lo);
+            if (threadIdx.x == kWave) hup = chain_merge(su, sv, seq_up, m_up, st_up);
             __syncthreads();
             if (threadIdx.x == 0) {
                 // hull = lower chain, then the upper chain without its end points
