@@ -381,18 +381,23 @@ __device__ __forceinline__ void swap3(double* U, double* V, uint32_t* I, uint32_
 }
 
 // One monotone chain over n sorted points (forward: lower chain, backward:
-// upper chain), computed by one wave.  Lane l first chains its contiguous
-// chunk of the sequence into tmp, dropping only points that lie strictly on
-// the inner side of a segment between two other points (such a point is no
-// vertex of the hull of any set holding those three; collinear and
-// coincident points are kept, so the choice among them is left to the full
-// rule); the chunk results are concatenated into seq, and one thread then
-// runs the chain (dropping collinear and coincident points as well) over
-// them, which gives the output of the plain chain over all n points.  All
-// lanes of the wave call chain_chunks.
+// upper chain), computed by one wave in three levels.  The first two levels
+// drop only points that lie strictly on the inner side of a segment between
+// two other points (such a point is no vertex of the hull of any set holding
+// those three; collinear and coincident points are kept, so the choice among
+// them is left to the full rule):
+//   level 1: lane l chains its contiguous chunk of the n points into tmp,
+//            and the chunk results are concatenated into seq;
+//   level 2: lane w < 8 chains the concatenated results of chunks 8w..8w+7
+//            in place;
+//   level 3: one thread runs the full chain (dropping collinear and
+//            coincident points as well) over the level-2 results in order,
+//            which gives the output of the plain chain over all n points.
+constexpr int kChainL2 = 8;   // level-2 windows (of kWave / kChainL2 chunks each)
+
 template <typename S>
-__device__ __forceinline__ void chain_chunks(const double* U, const double* V, uint32_t n, bool forward, S* tmp,
-                                             S* seq, uint32_t* seq_len)
+__device__ __forceinline__ void chain_level1(const double* U, const double* V, uint32_t n, bool forward, S* tmp,
+                                             S* seq, uint32_t* offs)
 {
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint32_t c = (n + kWave - 1) / kWave;
@@ -417,45 +422,69 @@ __device__ __forceinline__ void chain_chunks(const double* U, const double* V, u
     }
     const uint32_t off = inc - h;
     for (uint32_t q = 0; q < h; ++q) seq[off + q] = tmp[s0 + q];
-    if (lane == kWave - 1) *seq_len = inc;
+    offs[lane] = off;
+    if (lane == kWave - 1) offs[kWave] = inc;
 }
 
-// The plain chain over seq[0, m), run by one thread.  The coordinates of the
-// two top stack entries stay in registers and the next point is fetched one
-// step ahead, so a step waits on LDS only when it pops.
+// level 2 for window w (called by one lane per window); returns its length
 template <typename S>
-__device__ __forceinline__ uint32_t chain_merge(const double* U, const double* V, const S* seq, uint32_t m, S* st)
+__device__ __forceinline__ uint32_t chain_level2(const double* U, const double* V, S* seq, const uint32_t* offs,
+                                                 uint32_t w)
+{
+    const uint32_t a0 = offs[w * (kWave / kChainL2)], a1 = offs[(w + 1) * (kWave / kChainL2)];
+    uint32_t h = 0;
+    for (uint32_t j = a0; j < a1; ++j) {
+        const uint32_t i = seq[j];
+        while (h >= 2) {
+            const uint32_t a = seq[a0 + h - 2], b = seq[a0 + h - 1];
+            if (cross3(U[a], V[a], U[b], V[b], U[i], V[i]) < 0.0) --h;
+            else break;
+        }
+        seq[a0 + h++] = (S)i;   // the stack never runs ahead of the read position
+    }
+    return h;
+}
+
+// level 3 by one thread.  The coordinates of the two top stack entries stay
+// in registers and the next point is fetched one step ahead, so a step waits
+// on LDS only when it pops.
+template <typename S>
+__device__ __forceinline__ uint32_t chain_level3(const double* U, const double* V, const S* seq,
+                                                 const uint32_t* offs, const uint32_t* len2, S* st)
 {
     uint32_t h = 0;
     double au = 0.0, av = 0.0, bu = 0.0, bv = 0.0;   // st[h - 2], st[h - 1]
-    uint32_t inext = m ? (uint32_t)seq[0] : 0u;
-    double nu = m ? U[inext] : 0.0, nv = m ? V[inext] : 0.0;
-    for (uint32_t j = 0; j < m; ++j) {
-        const uint32_t i = inext;
-        const double iu = nu, iv = nv;
-        if (j + 1 < m) {
-            inext = seq[j + 1];
-            nu = U[inext];
-            nv = V[inext];
-        }
-        while (h >= 2 && cross3(au, av, bu, bv, iu, iv) <= 0.0) {
-            --h;
-            bu = au;
-            bv = av;
-            if (h >= 2) {
-                const uint32_t a = st[h - 2];
-                au = U[a];
-                av = V[a];
+    for (uint32_t w = 0; w < (uint32_t)kChainL2; ++w) {
+        const uint32_t a0 = offs[w * (kWave / kChainL2)], m = len2[w];
+        uint32_t inext = m ? (uint32_t)seq[a0] : 0u;
+        double nu = m ? U[inext] : 0.0, nv = m ? V[inext] : 0.0;
+        for (uint32_t j = 0; j < m; ++j) {
+            const uint32_t i = inext;
+            const double iu = nu, iv = nv;
+            if (j + 1 < m) {
+                inext = seq[a0 + j + 1];
+                nu = U[inext];
+                nv = V[inext];
             }
+            while (h >= 2 && cross3(au, av, bu, bv, iu, iv) <= 0.0) {
+                --h;
+                bu = au;
+                bv = av;
+                if (h >= 2) {
+                    const uint32_t a = st[h - 2];
+                    au = U[a];
+                    av = V[a];
+                }
+            }
+            st[h] = (S)i;
+            if (h >= 1) {
+                au = bu;
+                av = bv;
+            }
+            bu = iu;
+            bv = iv;
+            ++h;
         }
-        st[h] = (S)i;
-        if (h >= 1) {
-            au = bu;
-            av = bv;
-        }
-        bu = iu;
-        bv = iv;
-        ++h;
     }
     return h;
 }
@@ -475,7 +504,8 @@ __global__ void __launch_bounds__(kChainBlock) k_hull_chain(
     __shared__ uint16_t tmp_up[kLdsCap];
     __shared__ uint16_t seq_lo[kLdsCap];
     __shared__ uint16_t seq_up[kLdsCap];
-    __shared__ uint32_t m_lo, m_up;
+    __shared__ uint32_t offs_lo[kWave + 1], offs_up[kWave + 1];
+    __shared__ uint32_t len2_lo[kChainL2], len2_up[kChainL2];
     __shared__ uint32_t hlo, hup;
     const uint32_t K = small[4];
     const uint32_t T = small[6];
@@ -514,12 +544,16 @@ __global__ void __launch_bounds__(kChainBlock) k_hull_chain(
                     __syncthreads();
                 }
             }
-            // lower chain on wave 0, upper chain on wave 1, each split in chunks
-            if (threadIdx.x < kWave) chain_chunks(su, sv, ns, true, tmp_lo, seq_lo, &m_lo);
-            else if (threadIdx.x < 2 * kWave) chain_chunks(su, sv, ns, false, tmp_up, seq_up, &m_up);
+            // lower chain on wave 0, upper chain on wave 1
+            if (threadIdx.x < kWave) chain_level1(su, sv, ns, true, tmp_lo, seq_lo, offs_lo);
+            else if (threadIdx.x < 2 * kWave) chain_level1(su, sv, ns, false, tmp_up, seq_up, offs_up);
             __syncthreads();
-            if (threadIdx.x == 0) hlo = chain_merge(su, sv, seq_lo, m_lo, st_lo);
-            if (threadIdx.x == kWave) hup = chain_merge(su, sv, seq_up, m_up, st_up);
+            if (threadIdx.x < kChainL2) len2_lo[threadIdx.x] = chain_level2(su, sv, seq_lo, offs_lo, threadIdx.x);
+            else if (threadIdx.x >= kWave && threadIdx.x < kWave + kChainL2)
+                len2_up[threadIdx.x - kWave] = chain_level2(su, sv, seq_up, offs_up, threadIdx.x - kWave);
+            __syncthreads();
+            if (threadIdx.x == 0) hlo = chain_level3(su, sv, seq_lo, offs_lo, len2_lo, st_lo);
+            if (threadIdx.x == kWave) hup = chain_level3(su, sv, seq_up, offs_up, len2_up, st_up);
             __syncthreads();
             if (threadIdx.x == 0) {
                 // hull = lower chain, then the upper chain without its end points
@@ -534,9 +568,12 @@ __global__ void __launch_bounds__(kChainBlock) k_hull_chain(
                     }
                 }
                 area_out[k] = h >= 3 ? 0.5 * s : 0.0;
-                for (uint32_t q = 0; q < h; ++q) hull_tmp[ib + k + q] = in_idx[ib + si[st_lo[q]]];
                 hull_cnt[k] = h;
+                hlo = h;
             }
+            __syncthreads();
+            // vertex indices, one per thread (each needs a load of its own)
+            for (uint32_t q = threadIdx.x; q < hlo; q += kChainBlock) hull_tmp[ib + k + q] = in_idx[ib + si[st_lo[q]]];
         } else {
             // bitonic network in global memory; partners beyond ns are +infinity
             uint32_t N = 1;
@@ -660,16 +697,19 @@ vm_status hulls(const vm_clusters& cl, const vm_planes& planes, const vm_hulls_o
     k_hull_tiles<<<grid_for(kc), kBlock, 0, s>>>(w.small, cl.d_off, planes.d_best_h, planes.d_in_off,
                                                  planes.d_in_idx, planes.in_cap, w.hull_tile_off, out.d_status);
     VM_HIP(scan_exclusive_dev(w.hull_tile_off, w.hull_tile_off, w.small + 4, kc, w.small + 6, w.blk, s));
-    const int tgrid = grid_for(hull_tiles_bound(kc, cl.n_cap), 1, 4096);
+    // grids sized for a few workgroups per CU; the kernels stride over the
+    // device-side counts, so empty workgroups are not launched by the thousand
+    const int tgrid = grid_for(hull_tiles_bound(kc, cl.n_cap), 1, 2048);
     k_hull_extremes<<<tgrid, kTileThreads, 0, s>>>(w.small, w.hull_tile_off, cl.d_off, cl.d_x, cl.d_y, cl.d_z, pl,
                                                    planes.d_in_off, planes.d_in_idx, w.ext_v, w.ext_i);
-    const int kgrid = kc < 4096 ? (int)(kc ? kc : 1) : 4096;
+    const int kgrid = kc < 1024 ? (int)(kc ? kc : 1) : 1024;
+    const int cgrid = kc < 512 ? (int)(kc ? kc : 1) : 512;   // the chain kernel holds ~70 KB of LDS
     k_hull_poly<<<kgrid, kWave, 0, s>>>(w.small, w.hull_tile_off, cl.d_off, cl.d_x, cl.d_y, cl.d_z, pl,
                                         planes.d_in_off, planes.d_in_idx, w.ext_v, w.ext_i, w.poly, w.surv_cnt);
     k_hull_filter<<<tgrid, kTileThreads, 0, s>>>(w.small, w.hull_tile_off, cl.d_off, cl.d_x, cl.d_y, cl.d_z, pl,
                                                  planes.d_in_off, planes.d_in_idx, w.poly, w.surv_cnt, w.hull_u,
                                                  w.hull_v, w.hull_i);
-    k_hull_chain<<<kgrid, kChainBlock, 0, s>>>(w.small, w.hull_tile_off, planes.d_in_off, planes.d_in_idx,
+    k_hull_chain<<<cgrid, kChainBlock, 0, s>>>(w.small, w.hull_tile_off, planes.d_in_off, planes.d_in_idx,
                                                w.surv_cnt, w.hull_u, w.hull_v, w.hull_i, w.hull_cnt, w.hull_tmp,
                                                out.d_area);
     VM_HIP(hipGetLastError());

@@ -10,7 +10,6 @@
 // dense rank in ascending key order, which the clustering stages use as their
 // index space (4 MB of bits for a 400x400x200 grid).
 #include "vm_common.h"
-#include "vm_tilescan.h"
 
 namespace vm {
 namespace {
@@ -204,31 +203,22 @@ __global__ void __launch_bounds__(kBlock) k_insert_runs(const uint32_t* __restri
     }
 }
 
-// Ranks of the occupied voxels: the exclusive popcount prefix of the
-// occupancy words (wrank), and the occupied keys in ascending order (rank r
-// holds the r-th smallest key).  The component-size counters of the ranks
-// are cleared on the way (the labelling accumulates into them).
-struct RankF {
-    const uint32_t* bits;
-    __device__ Vec<1> operator()(uint32_t w) const
-    {
-        Vec<1> x;
-        x.v[0] = (uint32_t)__popc(bits[w]);
-        return x;
-    }
-};
+__global__ void __launch_bounds__(kBlock) k_popc(const uint32_t* __restrict__ bits, uint32_t nwords,
+                                                 uint32_t* __restrict__ out)
+{
+    for (uint32_t w = blockIdx.x * blockDim.x + threadIdx.x; w < nwords; w += gridDim.x * blockDim.x)
+        out[w] = __popc(bits[w]);
+}
 
-struct RankG {
-    const uint32_t* bits;
-    uint32_t* wrank;
-    uint32_t* occ_key;
-    uint32_t* csize;
-    DevCounters* ctr;
-    __device__ void operator()(uint32_t w, const Vec<1>& x, const Vec<1>& pre) const
-    {
-        wrank[w] = pre.v[0];
-        uint32_t b = x.v[0] ? bits[w] : 0u;
-        uint32_t r = pre.v[0];
+// Occupied keys in rank order; the component-size counters of the ranks are
+// cleared on the way (the labelling accumulates into them).
+__global__ void __launch_bounds__(kBlock) k_compact(const uint32_t* __restrict__ bits, uint32_t nwords,
+                                                    const uint32_t* __restrict__ wrank,
+                                                    uint32_t* __restrict__ occ_key, uint32_t* __restrict__ csize)
+{
+    for (uint32_t w = blockIdx.x * blockDim.x + threadIdx.x; w < nwords; w += gridDim.x * blockDim.x) {
+        uint32_t b = bits[w];
+        uint32_t r = wrank[w];
         while (b) {
             const uint32_t j = __ffs(b) - 1;
             csize[r] = 0u;
@@ -236,8 +226,7 @@ struct RankG {
             b &= b - 1;
         }
     }
-    __device__ void total(const Vec<1>& t) const { ctr->n_occ = t.v[0]; }
-};
+}
 
 __global__ void __launch_bounds__(kBlock) k_export(Geom g, Hash h, const uint32_t* __restrict__ occ_key,
                                                    const DevCounters* __restrict__ ctr, uint32_t* key_out,
@@ -372,10 +361,10 @@ hipError_t launch_insert(const float* xyz, int64_t n, const Pose& pose, const Ge
 hipError_t launch_rank(const Geom& g, const uint32_t* bits, SegBuffers& b, uint32_t /*cap*/, DevCounters* ctr,
                        hipStream_t s)
 {
-    const RankF f{bits};
-    const RankG gg{bits, b.wrank, b.occ_key, b.csize, ctr};
-    Vec<1>* tiles = reinterpret_cast<Vec<1>*>(b.blk);
-    tile_scan<1>(f, gg, nullptr, g.nwords, tiles, s);
+    k_popc<<<grid_for(g.nwords), kBlock, 0, s>>>(bits, g.nwords, b.wrank);
+    hipError_t e = scan_exclusive_dev(b.wrank, b.wrank, nullptr, g.nwords, &ctr->n_occ, b.blk, s);
+    if (e != hipSuccess) return e;
+    k_compact<<<grid_for(g.nwords), kBlock, 0, s>>>(bits, g.nwords, b.wrank, b.occ_key, b.csize);
     return hipGetLastError();
 }
 

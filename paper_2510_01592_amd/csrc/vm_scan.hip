@@ -112,6 +112,15 @@ __device__ __forceinline__ bool radix_pass_runs(const uint32_t* d_max_key, int s
     return shift == 0 || ((*d_max_key) >> shift) != 0u;
 }
 
+// Tiles holding keys: the histograms are laid out digit-major over these
+// only, so a sort sized for a large capacity scans and scatters only what
+// the device-side count holds.
+__device__ __forceinline__ uint32_t radix_tiles(uint32_t n, uint32_t nblk)
+{
+    const uint32_t t = (uint32_t)(((uint64_t)n + kRadixTile - 1) / kRadixTile);
+    return t < nblk ? t : nblk;
+}
+
 __global__ void __launch_bounds__(kBlock) k_radix_hist(const uint32_t* __restrict__ keys, const uint32_t* d_n,
                                                        int shift, int passes, const uint32_t* d_max_key, uint32_t nblk,
                                                        uint32_t* __restrict__ hist, uint32_t* __restrict__ scan_n,
@@ -119,17 +128,18 @@ __global__ void __launch_bounds__(kBlock) k_radix_hist(const uint32_t* __restric
 {
     __shared__ uint32_t cnt[kRadixBins];
     const bool runs = radix_pass_runs(d_max_key, shift);
+    const uint32_t n = *d_n;
+    const uint32_t nt = radix_tiles(n, nblk);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         // the scan of this pass's histograms covers nothing if the pass is skipped
-        *scan_n = runs ? (uint32_t)kRadixBins * nblk : 0u;
+        *scan_n = runs ? (uint32_t)kRadixBins * nt : 0u;
         if (shift == 0) {
             int ran = 1;
             for (int p = 1; p < passes; ++p) ran += radix_pass_runs(d_max_key, p * kRadixBits) ? 1 : 0;
             *d_sel = (uint32_t)(ran & 1);
         }
     }
-    if (!runs) return;
-    const uint32_t n = *d_n;
+    if (!runs || blockIdx.x >= nt) return;
     cnt[threadIdx.x] = 0;
     __syncthreads();
     const uint64_t base = (uint64_t)blockIdx.x * kRadixTile;
@@ -138,7 +148,7 @@ __global__ void __launch_bounds__(kBlock) k_radix_hist(const uint32_t* __restric
         if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & (kRadixBins - 1)], 1u);
     }
     __syncthreads();
-    hist[(uint64_t)threadIdx.x * nblk + blockIdx.x] = cnt[threadIdx.x];
+    hist[(uint64_t)threadIdx.x * nt + blockIdx.x] = cnt[threadIdx.x];
 }
 
 __global__ void __launch_bounds__(kBlock) k_radix_scatter(const uint32_t* __restrict__ kin,
@@ -151,10 +161,11 @@ __global__ void __launch_bounds__(kBlock) k_radix_scatter(const uint32_t* __rest
     __shared__ uint32_t wcnt[kBlock / kWave][kRadixBins];
     if (!radix_pass_runs(d_max_key, shift)) return;
     const uint32_t n = *d_n;
+    const uint32_t nt = radix_tiles(n, nblk);
     const uint64_t tile = (uint64_t)blockIdx.x * kRadixTile;
-    if (tile >= n) return;
+    if (blockIdx.x >= nt) return;
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-    base[threadIdx.x] = hist[(uint64_t)threadIdx.x * nblk + blockIdx.x];
+    base[threadIdx.x] = hist[(uint64_t)threadIdx.x * nt + blockIdx.x];
 #pragma unroll
     for (int w = 0; w < kBlock / kWave; ++w) wcnt[w][threadIdx.x] = 0;
     __syncthreads();
