@@ -201,7 +201,7 @@ __device__ __forceinline__ uint32_t run_start_of(uint32_t starts, int x)
     return 31u - __clz(starts & ((2u << x) - 1u));   // x = 31: (2u << 31) - 1 wraps to all ones
 }
 
-constexpr uint32_t kPairCap = 2048;   // hook pairs buffered per tile (more are united at once)
+constexpr uint32_t kPairCap = 1024;   // hook pairs buffered per tile (more are united at once)
 
 __global__ void __launch_bounds__(kBlock) k_ccl_tile(const uint32_t* __restrict__ bits, uint32_t nwords,
                                                      const uint32_t* __restrict__ wrank, Dims d, TileGrid tg,
@@ -315,20 +315,39 @@ __device__ __forceinline__ bool occ_cell(const uint32_t* __restrict__ bits, cons
 // second kernel unites all pairs of the grid at once.  A tile with more
 // distinct pairs than its slice unites the excess itself.
 constexpr uint32_t kPairHash = 1024;   // LDS hash set of root pairs per tile
+constexpr uint32_t kRawPairs = 1024;   // voxel pairs gathered per tile before the root lookups
 
 __global__ void __launch_bounds__(kBlock) k_ccl_boundary(const uint32_t* __restrict__ bits, uint32_t nwords,
                                                          const uint32_t* __restrict__ wrank, Dims d, TileGrid tg,
                                                          uint32_t* parent, uint64_t* __restrict__ pairs,
                                                          uint32_t* __restrict__ npair)
 {
+    __shared__ uint64_t raw[kRawPairs];
     __shared__ uint64_t buf[kCclTilePairs];
     __shared__ unsigned long long hset[kPairHash];
-    __shared__ uint32_t nbuf;
+    __shared__ uint32_t nraw, nbuf;
     const uint32_t ntiles = tg.ntx * tg.nty * tg.ntz;
     const uint32_t j = threadIdx.x;
     const int yl = (int)(j % kTY), zl = (int)(j / kTY);
+    // a distinct root pair goes to the tile's list (united in place if full)
+    auto add_roots = [&](uint32_t ra, uint32_t rb) {
+        const unsigned long long key = ((unsigned long long)ra << 32) | rb;
+        uint32_t h = (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> 54);   // kPairHash = 2^10 slots
+        for (uint32_t probe = 0; probe < kPairHash; ++probe) {
+            const unsigned long long old = atomicCAS(&hset[h], ~0ull, key);
+            if (old == key) return;          // this root pair is already listed
+            if (old == ~0ull) break;         // first time
+            h = (h + 1) & (kPairHash - 1);
+        }
+        const uint32_t i = atomicAdd(&nbuf, 1u);
+        if (i < kCclTilePairs) buf[i] = key;
+        else uf_unite(parent, ra, rb);
+    };
     for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        if (j == 0) nbuf = 0;
+        if (j == 0) {
+            nraw = 0;
+            nbuf = 0;
+        }
         for (uint32_t i = j; i < kPairHash; i += kBlock) hset[i] = ~0ull;
         __syncthreads();
         const uint32_t tx = t % tg.ntx, ty = (t / tg.ntx) % tg.nty, tz = t / (tg.ntx * tg.nty);
@@ -336,19 +355,11 @@ __global__ void __launch_bounds__(kBlock) k_ccl_boundary(const uint32_t* __restr
         const int y = (int)(ty * kTY) + yl, z = (int)(tz * kTZ) + zl;
         uint32_t key0;
         const uint32_t v = row_bits(bits, nwords, d, x0, (uint32_t)y, (uint32_t)z, &key0);
+        // first the voxel pairs (no loads of parents yet), ...
         auto emit = [&](uint32_t a, uint32_t b) {
-            const uint32_t ra = ld_parent(&parent[a]), rb = ld_parent(&parent[b]);
-            const unsigned long long key = ((unsigned long long)ra << 32) | rb;
-            uint32_t h = (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> 54);   // kPairHash = 2^10 slots
-            for (uint32_t probe = 0; probe < kPairHash; ++probe) {
-                const unsigned long long old = atomicCAS(&hset[h], ~0ull, key);
-                if (old == key) return;          // this root pair is already listed
-                if (old == ~0ull) break;         // first time
-                h = (h + 1) & (kPairHash - 1);
-            }
-            const uint32_t i = atomicAdd(&nbuf, 1u);
-            if (i < kCclTilePairs) buf[i] = key;
-            else uf_unite(parent, ra, rb);
+            const uint32_t i = atomicAdd(&nraw, 1u);
+            if (i < kRawPairs) raw[i] = ((uint64_t)a << 32) | b;
+            else add_roots(ld_parent(&parent[a]), ld_parent(&parent[b]));
         };
         const bool face = yl == 0 || yl == kTY - 1 || zl == 0;
         const bool first = (v & 1u) && x0 > 0, last = (v >> 31) & 1u;
@@ -393,6 +404,13 @@ __global__ void __launch_bounds__(kBlock) k_ccl_boundary(const uint32_t* __restr
                     emit(r, rank_of(bits, wrank, nk));
                 }
             }
+        }
+        __syncthreads();
+        // ... then the local roots of all of them at once, deduplicated
+        const uint32_t nr = min(nraw, kRawPairs);
+        for (uint32_t i = j; i < nr; i += kBlock) {
+            const uint64_t pr = raw[i];
+            add_roots(ld_parent(&parent[(uint32_t)(pr >> 32)]), ld_parent(&parent[(uint32_t)pr]));
         }
         __syncthreads();
         const uint32_t np = min(nbuf, kCclTilePairs);
