@@ -56,7 +56,13 @@ def main() -> int:
     ap.add_argument("--no-batched", action="store_true", help="skip the 2000-cluster batched measurement")
     ap.add_argument("--no-served", action="store_true", help="skip the multi-robot served measurement")
     ap.add_argument("--served-seconds", type=float, default=3.0, help="span of the served arrival process")
+    ap.add_argument("--counters", action="store_true",
+                    help="run only the inlier-counting launches of the roofline and a 256 MiB copy (for rocprofv3 --pmc)")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="turn two rocprofv3 --pmc counter files of a --counters run into profiles/k_count_traffic.json")
     args = ap.parse_args()
+    if args.traffic_from:
+        return _traffic_from(*args.traffic_from)
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -104,6 +110,9 @@ def main() -> int:
     frame_t = torch.zeros(1, dtype=torch.int32, device=dev)
     kw = dict(min_cluster=minc, n_hyp=H, eps=eps, seed=seed)
     last = {}
+    if args.counters:
+        return _counters_run(vm, torch, m, frames, planes, hulls, k_cap, H, eps, seed, kw, stream, dev, restore,
+                             args.warmup, min(5, args.steps))
 
     # ---- plain form ------------------------------------------------------------
     def plain_step(i: int) -> None:
@@ -222,7 +231,7 @@ def main() -> int:
          f"; k_count alone {count_ms:.3f} ms for {evals / 1e6:.0f}M evaluations")
     ach = evals / (count_ms * 1e-3) / 1e9
     roof = {"bound": "alu", "achieved": ach, "peak": COUNT_PEAK_GEVAL, "unit": "Geval/s",
-            "frac": ach / COUNT_PEAK_GEVAL, "traffic": None, "kernel": "k_count",
+            "frac": ach / COUNT_PEAK_GEVAL, "traffic": _traffic(), "kernel": "k_count",
             "work_per_launch": f"{n_pts} points x {H} hypotheses",
             "peak_derivation": "256 CU x 64 lanes x 2.4 GHz / 4 VALU instructions per point-plane test"}
 
@@ -392,6 +401,83 @@ def _served(vm, torch, seconds: float, n_robots: int = 8, rate_hz: float = 30.0,
                 peak_inflight=sch.peak_inflight, rejected=len(sch.rejected), frames_with_status_flags=bad,
                 voxels_per_s=vox / t_span, points_per_s=sum(c.request.n_points for c in done) / t_span,
                 generation_s=gen_s)
+
+
+COPY_BYTES = 256 << 20
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "k_count_traffic.json")
+COUNT_SRC = os.path.join(ROOT, "paper_2510_01592_amd", "csrc", "vm_ransac.hip")
+
+
+def _sha256(path: str) -> str:
+    import hashlib
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def _counters_run(vm, torch, m, frames, planes, hulls, k_cap, H, eps, seed, kw, stream, dev, restore, first, n):
+    """The launches the roofline is measured on -- n frames, then 10
+    standalone inlier-counting passes over the last frame's clusters -- and a
+    256 MiB device copy whose counters scale FETCH_SIZE/WRITE_SIZE to bytes."""
+    restore()
+    with torch.cuda.stream(stream):
+        cl = None
+        for i in range(n):
+            cl = m.segment_frame(frames[first + i], planes, hulls, frame=first + i, stream=stream, **kw)
+        work = torch.empty(vm.workspace_bytes(k_cap, cl.n_cap, H), dtype=torch.uint8, device=dev)
+        for r in range(10):
+            vm.ransac_planes(cl, vm.ransac_params(H, eps, seed, r), planes, work, stream=stream)
+        src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        stream.synchronize()
+    meta = vm.read_clusters(cl)
+    print(json.dumps({"counters_run": True, "k_count_launches": 10, "points": int(meta["N"]),
+                      "clusters": int(meta["K"]), "n_hyp": H, "copy_bytes": COPY_BYTES}), flush=True)
+    return 0
+
+
+def _pmc_rows(path: str):
+    import csv
+    with open(path) as f:
+        return list(csv.DictReader(f))
+
+
+def _traffic_from(fetch_csv: str, write_csv: str) -> int:
+    """Per-launch HBM bytes of the last 10 k_count dispatches: FETCH_SIZE and
+    WRITE_SIZE (KiB per dispatch) each scaled by what the same counter reads
+    for the 256 MiB copy of the --counters run."""
+    out = {"kernel": "k_count", "source": os.path.relpath(COUNT_SRC, ROOT), "source_sha256": _sha256(COUNT_SRC)}
+    for name, path in (("fetch", fetch_csv), ("write", write_csv)):
+        rows = _pmc_rows(path)
+        cnt = "FETCH_SIZE" if name == "fetch" else "WRITE_SIZE"
+        rows = [r for r in rows if r["Counter_Name"] == cnt]
+        kc = [float(r["Counter_Value"]) for r in rows if "k_count" in r["Kernel_Name"]][-10:]
+        cp = max(float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"]
+                 or "elementwise" in r["Kernel_Name"])
+        scale = COPY_BYTES / (cp * 1024.0)
+        out[f"{name}_kib_per_launch_raw"] = sum(kc) / len(kc)
+        out[f"{name}_copy_kib_raw"] = cp
+        out[f"{name}_scale"] = scale
+        out[f"{name}_bytes_per_launch"] = sum(kc) / len(kc) * 1024.0 * scale
+    out["traffic_bytes_per_launch"] = out["fetch_bytes_per_launch"] + out["write_bytes_per_launch"]
+    os.makedirs(os.path.dirname(TRAFFIC_JSON), exist_ok=True)
+    with open(TRAFFIC_JSON, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def _traffic():
+    """Measured HBM bytes per k_count launch, if the counters were taken on the
+    kernel source as it is now; else None."""
+    try:
+        with open(TRAFFIC_JSON) as f:
+            t = json.load(f)
+        if t.get("source_sha256") != _sha256(COUNT_SRC):
+            return None
+        return float(t["traffic_bytes_per_launch"])
+    except (OSError, ValueError, KeyError):
+        return None
 
 
 def _cpu_baseline(sc, prewarm, n_frames, H, eps, minc, seed):

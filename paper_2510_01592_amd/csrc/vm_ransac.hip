@@ -25,6 +25,8 @@ constexpr int kPtsPerLane = 16;
 constexpr int kTile = kCountBlock * kPtsPerLane;   // points per tile (4096)
 constexpr int kMaxHypChunk = 4096;                 // hypotheses per work item (LDS counters)
 constexpr int kHypBatch = 4;                       // planes loaded together
+constexpr uint32_t kXcds = 8;                      // accelerator complex dies (separate L2s)
+constexpr int kCountGrid = 4096;                   // a multiple of kXcds
 
 __device__ __forceinline__ void philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3, uint64_t k0,
                                               uint64_t k1, uint64_t out[4])
@@ -208,10 +210,15 @@ __global__ void __launch_bounds__(kCountBlock) k_count(const uint32_t* __restric
     if (HC < (H + kMaxHypChunk - 1) / kMaxHypChunk) HC = (H + kMaxHypChunk - 1) / kMaxHypChunk;
     if (HC < 1) HC = 1;
     const uint32_t chunk = (H + HC - 1) / HC;
-    const uint64_t items = (uint64_t)T * HC;
+    // Workgroups are dispatched round-robin over the XCDs, each with its own
+    // L2: tile t is handled on XCD t mod kXcds only, so the hypothesis chunks
+    // of a tile (run at about the same time) fetch its points from memory once.
+    const uint32_t xcd = blockIdx.x % kXcds, sub = blockIdx.x / kXcds, nsub = gridDim.x / kXcds;
+    const uint32_t tiles_x = T > xcd ? (T - xcd + kXcds - 1) / kXcds : 0u;
+    const uint64_t items = (uint64_t)tiles_x * HC;
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-    for (uint64_t item = blockIdx.x; item < items; item += gridDim.x) {
-        const uint32_t t = (uint32_t)(item / HC), hc = (uint32_t)(item % HC);
+    for (uint64_t item = sub; item < items; item += nsub) {
+        const uint32_t t = (uint32_t)(item / HC) * kXcds + xcd, hc = (uint32_t)(item % HC);
         const uint32_t k = tile_k[t];
         const uint32_t p0 = off[k] + (t - tile_off[k]) * kTile;
         const uint32_t pend = off[k + 1];
@@ -421,7 +428,7 @@ vm_status ransac_planes(const vm_clusters& cl, const vm_ransac_params& p, const 
     }
     {
         StageScope t(VM_STAGE_COUNT, s);
-        k_count<<<4096, kCountBlock, 0, s>>>(w.small, w.tile_off, w.tile_k, cl.d_off, cl.d_x, cl.d_y, cl.d_z, H, p.eps, w.hyp,
+        k_count<<<kCountGrid, kCountBlock, 0, s>>>(w.small, w.tile_off, w.tile_k, cl.d_off, cl.d_x, cl.d_y, cl.d_z, H, p.eps, w.hyp,
                                              w.counts);
         VM_HIP(hipGetLastError());
     }
