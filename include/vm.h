@@ -80,7 +80,7 @@ typedef struct {
     double   voxel_size;          /* s, metres, > 0 */
     int32_t  dims[3];             /* NX, NY, NZ, each >= 1 */
     uint32_t hash_capacity_log2;  /* 10..30 */
-    uint32_t insert_batch_log2;   /* largest point batch one sorted insert pass takes
+    uint32_t insert_batch_log2;   /* largest point batch one grouped insert pass takes
                                      (0: 2^22); larger calls are split. 16..26 */
     uint32_t reserved;            /* must be 0 */
 } vm_map_desc;
@@ -99,8 +99,10 @@ typedef struct {
     uint32_t status_flags;    /* VM_FLAG_* seen since create/clear */
     uint32_t hash_capacity_log2;
     uint64_t last_touched;    /* voxel slot updates of the last vm_insert call on its
-                                 sorted path: one per distinct voxel of each sorted
-                                 batch (0 for calls small enough for per-point atomics) */
+                                 grouped path: one per distinct voxel of each batch
+                                 (a voxel with more than 1024 points in one batch may
+                                 take more; 0 for calls small enough for per-point
+                                 atomics) */
 } vm_map_stats_t;
 
 /* Allocate a map on the current device (hipMalloc; the map owns the memory
@@ -125,9 +127,9 @@ vm_status vm_map_stats_async(vm_map map, vm_map_stats_t* d_out, void* stream);
  * the 2^-20-voxel fixed-point offset added to the voxel's integer sums, so
  * the stored mean is the arithmetic mean that Eq. (1)'s recurrence computes,
  * independent of arrival order.  Non-finite points and points outside the
- * grid are counted and dropped.  Large calls sort the points by voxel first
- * and update each touched voxel once; small ones update per point with
- * integer atomics; both give the same map.  n = 0 is a no-op; n < 0 is
+ * grid are counted and dropped.  Large calls group the points by voxel first
+ * (hash buckets, then per-bucket sums) and update each touched voxel once;
+ * small ones update per point with integer atomics; both give the same map.  n = 0 is a no-op; n < 0 is
  * VM_E_ARG. */
 vm_status vm_insert(vm_map map, const float* d_xyz, int64_t n, const vm_pose* pose, void* stream);
 

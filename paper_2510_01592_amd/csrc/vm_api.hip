@@ -280,7 +280,7 @@ vm_status vm_map_create(const vm_map_desc* d, vm_map* out)
     A((void**)&b.wrank, ((size_t)m->g.nwords + 1) * 4);
     const uint32_t batch = 1u << (d->insert_batch_log2 ? d->insert_batch_log2 : 22);
     const uint64_t scan_n = std::max<uint64_t>(std::max<uint64_t>(cap, m->g.nwords),
-                                               std::max<uint64_t>(radix_hist_words(cap), radix_hist_words(batch)));
+                                               std::max<uint64_t>(radix_hist_words(cap), bucket_hist_words(batch)));
     // scan partials; also the fused scans' per-tile totals (3 words per 1024 items)
     A((void**)&b.blk, std::max<size_t>(scan_blk_words(scan_n), 3 * (size_t)ts_tiles(scan_n)) * 4);
     A((void**)&b.hist, radix_hist_words(cap) * 4);
@@ -293,7 +293,7 @@ vm_status vm_map_create(const vm_map_desc* d, vm_map* out)
         A((void**)&ins.val[i], (size_t)batch * 4);
     }
     A((void**)&ins.packed, (size_t)batch * 8);
-    A((void**)&ins.hist, radix_hist_words(batch) * 4);
+    A((void**)&ins.hist, bucket_hist_words(batch) * 4);
     ins.blk = b.blk;
     if (st != VM_OK) {
         map_free_all(m);

@@ -214,6 +214,8 @@ struct InsertScratch {
 
 // ---- map stages (vm_map.hip) ------------------------------------------------
 constexpr int64_t kSortedInsertMin = 1 << 17;   // smaller calls use per-point atomics
+uint32_t bucket_log2(uint32_t batch_points);    // log2 of the bucket count of a grouped batch
+size_t bucket_hist_words(uint32_t batch);       // histogram words of the largest batch
 hipError_t launch_insert(const float* xyz, int64_t n, const Pose& pose, const Geom& g, const Hash& h,
                          uint32_t* bits, DevCounters* ctr, const InsertScratch& sc, hipStream_t s);
 hipError_t launch_stats(const DevCounters* ctr, uint32_t log2cap, vm_map_stats_t* out, hipStream_t s);

@@ -87,22 +87,56 @@ __global__ void __launch_bounds__(kBlock) k_insert(const float* __restrict__ xyz
 // ---- sorted insert path -------------------------------------------------------
 // 1. voxelise every point: (key, point index) pairs plus its packed offsets;
 //    points outside the grid get a key above every valid one.
-__global__ void __launch_bounds__(kBlock) k_voxelize(const float* __restrict__ xyz, uint32_t n, Pose pose, Geom g,
-                                                     uint32_t invalid_key, bool first_batch,
-                                                     uint32_t* __restrict__ key_out, uint32_t* __restrict__ val_out,
-                                                     unsigned long long* __restrict__ packed,
-                                                     DevCounters* __restrict__ ctr)
+
+// 3. after the sort by key: one lane per run of equal keys sums the run and
+//    updates the voxel's slot once.  Every key occurs in one run only, so no
+//    other lane touches that slot in this pass: the payload is a plain
+//    read-modify-write; only claiming an empty slot needs a CAS.
+// ---- grouped insert (large calls) ---------------------------------------------
+// The points of a batch are voxelised, partitioned into hash buckets of about
+// kBucketAvg points (a bucket is a range of home slots of the map's hash, so
+// every point of a voxel lands in the same bucket), and each bucket is then
+// aggregated by one workgroup in an LDS table: one slot update per distinct
+// voxel, a plain read-modify-write since no other workgroup touches those
+// voxels.
+constexpr uint32_t kBucketTile = 4096;    // points per workgroup in the partition passes (at least)
+constexpr uint32_t kBucketBlocks = 1024;  // partition workgroups per batch (at most)
+constexpr uint32_t kBucketAvg = 512;      // target points per bucket
+constexpr uint32_t kBucketMaxLog2 = 12;   // at most 4096 buckets (LDS counters)
+constexpr uint32_t kBucketChunk = 1024;   // points aggregated per LDS table fill
+constexpr uint32_t kBucketTable = 2048;   // LDS table slots (load at most 1/2)
+
+__device__ __forceinline__ uint32_t bucket_of(uint32_t key, uint32_t lb)
 {
+    // the top lb bits of the map's own slot hash
+    return lb ? (key * 2654435769u) >> (32 - lb) : 0u;
+}
+
+__device__ __forceinline__ uint32_t table_slot(uint32_t key)
+{
+    // independent of the bucket bits: a different multiplier
+    return (key * 0xCC9E2D51u) >> (32 - 11);   // kBucketTable = 2^11
+}
+
+__global__ void __launch_bounds__(kBlock) k_vox_bucket(const float* __restrict__ xyz, uint32_t n, Pose pose, Geom g,
+                                                       uint32_t lb, uint32_t nblk, uint32_t tile, bool first_batch,
+                                                       uint32_t* __restrict__ key_out,
+                                                       unsigned long long* __restrict__ packed,
+                                                       uint32_t* __restrict__ hist, DevCounters* __restrict__ ctr)
+{
+    __shared__ uint32_t cnt[1u << kBucketMaxLog2];
+    const uint32_t B = 1u << lb;
+    for (uint32_t b = threadIdx.x; b < B; b += kBlock) cnt[b] = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && first_batch) ctr->touched = 0;
+    __syncthreads();
     uint32_t n_in = 0, n_drop = 0;
     const double lim0 = (double)g.dims[0] * 1048576.0;
     const double lim1 = (double)g.dims[1] * 1048576.0;
     const double lim2 = (double)g.dims[2] * 1048576.0;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        ctr->sort_n = n;
-        ctr->sort_max = invalid_key;
-        if (first_batch) ctr->touched = 0;
-    }
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const uint64_t base = (uint64_t)blockIdx.x * tile;
+    for (uint32_t j = 0; j < tile / kBlock; ++j) {
+        const uint64_t i = base + (uint64_t)j * kBlock + threadIdx.x;
+        if (i >= n) break;
         const double px = (double)xyz[3 * (size_t)i + 0];
         const double py = (double)xyz[3 * (size_t)i + 1];
         const double pz = (double)xyz[3 * (size_t)i + 2];
@@ -112,88 +146,134 @@ __global__ void __launch_bounds__(kBlock) k_voxelize(const float* __restrict__ x
         const double fx = floor((wx - g.origin[0]) * g.inv_q);
         const double fy = floor((wy - g.origin[1]) * g.inv_q);
         const double fz = floor((wz - g.origin[2]) * g.inv_q);
-        uint32_t key = invalid_key;
+        uint32_t key = kEmpty;
         unsigned long long pk = 0;
+        // negated range tests also reject NaN
         if (fx >= 0.0 && fx < lim0 && fy >= 0.0 && fy < lim1 && fz >= 0.0 && fz < lim2) {
             const int64_t qx = (int64_t)fx, qy = (int64_t)fy, qz = (int64_t)fz;
             key = (uint32_t)((uint64_t)(qx >> 20) +
                              (uint64_t)g.dims[0] * ((uint64_t)(qy >> 20) + (uint64_t)g.dims[1] * (uint64_t)(qz >> 20)));
             pk = (unsigned long long)(qx & 0xFFFFF) | ((unsigned long long)(qy & 0xFFFFF) << 20) |
                  ((unsigned long long)(qz & 0xFFFFF) << 40);
+            atomicAdd(&cnt[bucket_of(key, lb)], 1u);
             ++n_in;
         } else {
             ++n_drop;
         }
         key_out[i] = key;
-        val_out[i] = i;
         packed[i] = pk;
     }
+    __syncthreads();
+    for (uint32_t b = threadIdx.x; b < B; b += kBlock) hist[(uint64_t)b * nblk + blockIdx.x] = cnt[b];
     unsigned long long* const dst[2] = {&ctr->points_in, &ctr->points_dropped};
     const uint32_t v[2] = {n_in, n_drop};
     block_add_counters<2>(dst, v);
 }
 
-// 3. after the sort by key: one lane per run of equal keys sums the run and
-//    updates the voxel's slot once.  Every key occurs in one run only, so no
-//    other lane touches that slot in this pass: the payload is a plain
-//    read-modify-write; only claiming an empty slot needs a CAS.
-__global__ void __launch_bounds__(kBlock) k_insert_runs(const uint32_t* __restrict__ key0,
-                                                        const uint32_t* __restrict__ key1,
-                                                        const uint32_t* __restrict__ val0,
-                                                        const uint32_t* __restrict__ val1,
-                                                        const unsigned long long* __restrict__ packed, Hash h,
-                                                        uint32_t* __restrict__ bits, DevCounters* __restrict__ ctr)
+// Points to their buckets (hist holds the exclusive scan, bucket-major).
+__global__ void __launch_bounds__(kBlock) k_bucket_scatter(const uint32_t* __restrict__ key_in,
+                                                           const unsigned long long* __restrict__ packed, uint32_t n,
+                                                           uint32_t lb, uint32_t nblk, uint32_t tile,
+                                                           const uint32_t* __restrict__ hist,
+                                                           uint32_t* __restrict__ key_out,
+                                                           uint32_t* __restrict__ lo_out, uint32_t* __restrict__ hi_out)
 {
-    // the sort left the batch in buffer ctr->sort_sel
-    const uint32_t* __restrict__ key = ctr->sort_sel ? key1 : key0;
-    const uint32_t* __restrict__ val = ctr->sort_sel ? val1 : val0;
-    const uint32_t n = ctr->sort_n;
-    const uint32_t invalid_key = ctr->sort_max;
-    uint32_t n_lost = 0, n_new = 0, n_runs = 0;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const uint32_t k = key[i];
-        if (k == invalid_key) continue;
-        if (i > 0 && key[i - 1] == k) continue;   // not the start of a run
-        uint32_t c = 0;
-        unsigned long long sx = 0, sy = 0, sz = 0;
-        for (uint32_t j = i; j < n && key[j] == k; ++j) {
-            const unsigned long long pk = packed[val[j]];
-            ++c;
-            sx += pk & 0xFFFFF;
-            sy += (pk >> 20) & 0xFFFFF;
-            sz += (pk >> 40) & 0xFFFFF;
-        }
-        ++n_runs;
-        uint32_t s = hash_slot(k, h.log2cap);
-        bool ok = false;
-        for (uint32_t p = 0; p < kMaxProbe && p <= h.mask; ++p) {
-            const uint32_t kk = h.slot[s].key;
-            if (kk == k) { ok = true; break; }
-            if (kk == kEmpty) {
-                const uint32_t old = atomicCAS(&h.slot[s].key, kEmpty, k);
-                if (old == kEmpty) {
-                    atomicOr(&bits[k >> 5], 1u << (k & 31));
-                    ++n_new;
-                    ok = true;
-                    break;
-                }
-                if (old == k) { ok = true; break; }
+    __shared__ uint32_t pos[1u << kBucketMaxLog2];
+    const uint32_t B = 1u << lb;
+    for (uint32_t b = threadIdx.x; b < B; b += kBlock) pos[b] = hist[(uint64_t)b * nblk + blockIdx.x];
+    __syncthreads();
+    const uint64_t base = (uint64_t)blockIdx.x * tile;
+    for (uint32_t j = 0; j < tile / kBlock; ++j) {
+        const uint64_t i = base + (uint64_t)j * kBlock + threadIdx.x;
+        if (i >= n) break;
+        const uint32_t k = key_in[i];
+        if (k == kEmpty) continue;
+        const unsigned long long pk = packed[i];
+        const uint32_t p = atomicAdd(&pos[bucket_of(k, lb)], 1u);
+        key_out[p] = k;
+        lo_out[p] = (uint32_t)pk;
+        hi_out[p] = (uint32_t)(pk >> 32);
+    }
+}
+
+// One workgroup per bucket: sum its points per voxel in LDS (at most
+// kBucketChunk points per fill, so the 32-bit sums of 20-bit offsets cannot
+// overflow), then update each voxel's slot once per fill.
+__global__ void __launch_bounds__(kBlock) k_bucket_insert(const uint32_t* __restrict__ key_in,
+                                                          const uint32_t* __restrict__ lo_in,
+                                                          const uint32_t* __restrict__ hi_in, uint32_t lb, uint32_t nblk,
+                                                          const uint32_t* __restrict__ hist, Hash h,
+                                                          uint32_t* __restrict__ bits, DevCounters* __restrict__ ctr)
+{
+    __shared__ uint32_t tkey[kBucketTable];
+    __shared__ uint32_t tcnt[kBucketTable];
+    __shared__ uint32_t tsum[3][kBucketTable];
+    const uint32_t B = 1u << lb;
+    const uint32_t total = ctr->sort_n;
+    uint32_t n_lost = 0, n_new = 0, n_upd = 0;
+    for (uint32_t b = blockIdx.x; b < B; b += gridDim.x) {
+        const uint32_t start = hist[(uint64_t)b * nblk];
+        const uint32_t end = b + 1 < B ? hist[(uint64_t)(b + 1) * nblk] : total;
+        for (uint32_t c0 = start; c0 < end; c0 += kBucketChunk) {
+            const uint32_t c1 = min(end, c0 + kBucketChunk);
+            for (uint32_t q = threadIdx.x; q < kBucketTable; q += kBlock) {
+                tkey[q] = kEmpty;
+                tcnt[q] = 0;
+                tsum[0][q] = tsum[1][q] = tsum[2][q] = 0;
             }
-            s = (s + 1) & h.mask;
+            __syncthreads();
+            for (uint32_t i = c0 + threadIdx.x; i < c1; i += kBlock) {
+                const uint32_t k = key_in[i];
+                const unsigned long long pk = (unsigned long long)lo_in[i] | ((unsigned long long)hi_in[i] << 32);
+                uint32_t q = table_slot(k);
+                for (;;) {   // at most kBucketChunk keys in a table of kBucketTable slots: ends
+                    const uint32_t old = atomicCAS(&tkey[q], kEmpty, k);
+                    if (old == kEmpty || old == k) break;
+                    q = (q + 1) & (kBucketTable - 1);
+                }
+                atomicAdd(&tcnt[q], 1u);
+                atomicAdd(&tsum[0][q], (uint32_t)(pk & 0xFFFFF));
+                atomicAdd(&tsum[1][q], (uint32_t)((pk >> 20) & 0xFFFFF));
+                atomicAdd(&tsum[2][q], (uint32_t)((pk >> 40) & 0xFFFFF));
+            }
+            __syncthreads();
+            for (uint32_t q = threadIdx.x; q < kBucketTable; q += kBlock) {
+                const uint32_t k = tkey[q];
+                if (k == kEmpty) continue;
+                ++n_upd;
+                uint32_t sl = hash_slot(k, h.log2cap);
+                bool ok = false;
+                for (uint32_t p = 0; p < kMaxProbe && p <= h.mask; ++p) {
+                    const uint32_t kk = h.slot[sl].key;
+                    if (kk == k) { ok = true; break; }
+                    if (kk == kEmpty) {
+                        const uint32_t old = atomicCAS(&h.slot[sl].key, kEmpty, k);
+                        if (old == kEmpty) {
+                            atomicOr(&bits[k >> 5], 1u << (k & 31));
+                            ++n_new;
+                            ok = true;
+                            break;
+                        }
+                        if (old == k) { ok = true; break; }
+                    }
+                    sl = (sl + 1) & h.mask;
+                }
+                if (!ok) {
+                    n_lost += tcnt[q];
+                    continue;
+                }
+                Slot* s = &h.slot[sl];
+                s->cnt += tcnt[q];
+                s->sum[0] += tsum[0][q];
+                s->sum[1] += tsum[1][q];
+                s->sum[2] += tsum[2][q];
+            }
+            __syncthreads();
         }
-        if (!ok) {
-            n_lost += c;
-            continue;
-        }
-        Slot* sl = &h.slot[s];
-        sl->cnt += c;
-        sl->sum[0] += sx;
-        sl->sum[1] += sy;
-        sl->sum[2] += sz;
     }
     {
         unsigned long long* const dst[3] = {&ctr->points_lost, &ctr->occupied, &ctr->touched};
-        const uint32_t v[3] = {n_lost, n_new, n_runs};
+        const uint32_t v[3] = {n_lost, n_new, n_upd};
         block_add_counters<3>(dst, v);
     }
     if (n_lost) {
@@ -327,6 +407,29 @@ hipError_t launch_stats(const DevCounters* ctr, uint32_t log2cap, vm_map_stats_t
     return hipGetLastError();
 }
 
+uint32_t bucket_log2(uint32_t m)
+{
+    uint32_t lb = 0;
+    while (lb < kBucketMaxLog2 && ((uint64_t)kBucketAvg << lb) < m) ++lb;
+    return lb;
+}
+
+// points per partition workgroup: kBucketTile, or more so that a batch takes
+// at most kBucketBlocks workgroups (bounds the histogram)
+static uint32_t bucket_tile(uint32_t m)
+{
+    uint32_t t = kBucketTile;
+    while ((uint64_t)t * kBucketBlocks < m) t <<= 1;
+    return t;
+}
+
+size_t bucket_hist_words(uint32_t batch)
+{
+    const uint32_t tile = bucket_tile(batch);
+    const uint32_t nblk = (batch + tile - 1) / tile;
+    return ((size_t)nblk << bucket_log2(batch)) + 64;
+}
+
 hipError_t launch_insert(const float* xyz, int64_t n, const Pose& pose, const Geom& g, const Hash& h,
                          uint32_t* bits, DevCounters* ctr, const InsertScratch& sc, hipStream_t s)
 {
@@ -335,24 +438,19 @@ hipError_t launch_insert(const float* xyz, int64_t n, const Pose& pose, const Ge
         k_insert<<<grid_for((uint64_t)n, kBlock, kMapGrid), kBlock, 0, s>>>(xyz, n, pose, g, h, bits, ctr);
         return hipGetLastError();
     }
-    // keys below ncell; the sort covers bit_width(ncell) bits and dropped
-    // points carry the all-ones key of that width, after every valid key
-    const uint64_t ncell = (uint64_t)g.dims[0] * (uint64_t)g.dims[1] * (uint64_t)g.dims[2];
-    int bits_needed = 0;
-    while (bits_needed < 32 && (1ull << bits_needed) <= ncell) ++bits_needed;
-    const uint32_t invalid_key = bits_needed >= 32 ? 0xFFFFFFFFu : (uint32_t)((1ull << bits_needed) - 1);
-    uint32_t* keys[2] = {sc.key[0], sc.key[1]};
-    uint32_t* vals[2] = {sc.val[0], sc.val[1]};
     for (int64_t done = 0; done < n; done += sc.cap) {
         const uint32_t m = (uint32_t)((n - done) < (int64_t)sc.cap ? (n - done) : (int64_t)sc.cap);
-        k_voxelize<<<grid_for(m, kBlock, kMapGrid), kBlock, 0, s>>>(xyz + 3 * done, m, pose, g, invalid_key, done == 0,
-                                                                     keys[0], vals[0], sc.packed, ctr);
-        // the batch size is known here, so the sort's grids are sized by it
-        hipError_t e = radix_sort_pairs_dev(keys, vals, &ctr->sort_n, m, bits_needed, &ctr->sort_max, sc.hist,
-                                            sc.blk, &ctr->sort_sel, s);
+        // the batch size is known here, so grids and the bucket count follow it
+        const uint32_t lb = bucket_log2(m);
+        const uint32_t tile = bucket_tile(m);
+        const uint32_t nblk = (m + tile - 1) / tile;
+        k_vox_bucket<<<nblk, kBlock, 0, s>>>(xyz + 3 * done, m, pose, g, lb, nblk, tile, done == 0, sc.key[0],
+                                            sc.packed, sc.hist, ctr);
+        hipError_t e = scan_exclusive_dev(sc.hist, sc.hist, nullptr, (nblk << lb), &ctr->sort_n, sc.blk, s);
         if (e != hipSuccess) return e;
-        k_insert_runs<<<grid_for(m, kBlock, kMapGrid), kBlock, 0, s>>>(keys[0], keys[1], vals[0], vals[1], sc.packed,
-                                                                       h, bits, ctr);
+        k_bucket_scatter<<<nblk, kBlock, 0, s>>>(sc.key[0], sc.packed, m, lb, nblk, tile, sc.hist, sc.key[1],
+                                                sc.val[0], sc.val[1]);
+        k_bucket_insert<<<1u << lb, kBlock, 0, s>>>(sc.key[1], sc.val[0], sc.val[1], lb, nblk, sc.hist, h, bits, ctr);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     return hipSuccess;

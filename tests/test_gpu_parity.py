@@ -62,13 +62,13 @@ def test_insert_posed_frames(vm):
 
 
 @pytest.mark.parametrize("batch_log2", [0, 16])
-def test_insert_sorted_and_atomic_paths_agree(vm, batch_log2):
-    # one large call (sorted path, split into batches of 2^16 when batch_log2=16)
+def test_insert_grouped_and_atomic_paths_agree(vm, batch_log2):
+    # one large call (grouped path, split into batches of 2^16 when batch_log2=16)
     # against many small calls (per-point atomics) and against the oracle
     sc = scenes.scene_full_map(1)
     g = sc.geom
     pts = scenes.frame_points(sc, 77, n=400_000)
-    note(f"insert sorted vs atomic, batch_log2={batch_log2}")
+    note(f"insert grouped vs atomic, batch_log2={batch_log2}")
     a = vm.Map(g.origin, g.voxel_size, g.dims, 21, insert_batch_log2=batch_log2)
     a.insert(_t(pts))
     b = vm.Map(g.origin, g.voxel_size, g.dims, 21)
@@ -82,7 +82,7 @@ def test_insert_sorted_and_atomic_paths_agree(vm, batch_log2):
     assert sa.points_in == sb.points_in == om.points_in
     assert sa.points_dropped == sb.points_dropped == om.points_dropped
     key, _, _ = oracle.voxelize(pts, np.eye(3), np.zeros(3), g.origin, g.voxel_size, g.dims)
-    if batch_log2 == 0:      # one sorted batch: one update per distinct voxel
+    if batch_log2 == 0:      # one grouped batch: one update per distinct voxel
         assert sa.last_touched == len(np.unique(key[key != oracle.NO_KEY]))
     else:                    # one update per distinct voxel of each 2^16-point batch
         B = 1 << batch_log2
