@@ -288,10 +288,8 @@ vm_status vm_map_create(const vm_map_desc* d, vm_map* out)
     A((void**)&b.npair, ccl_tiles(m->g) * 4);
     InsertScratch& ins = m->ins;
     ins.cap = batch;
-    for (int i = 0; i < 2; ++i) {
-        A((void**)&ins.key[i], (size_t)batch * 4);
-        A((void**)&ins.val[i], (size_t)batch * 4);
-    }
+    A((void**)&ins.key, (size_t)batch * 4);
+    A((void**)&ins.rec, (size_t)batch * 16);
     A((void**)&ins.packed, (size_t)batch * 8);
     A((void**)&ins.hist, bucket_hist_words(batch) * 4);
     ins.blk = b.blk;

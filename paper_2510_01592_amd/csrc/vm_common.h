@@ -202,12 +202,12 @@ hipError_t radix_sort_pairs_dev(uint32_t* keys[2], uint32_t* vals[2], const uint
                                 int bits, const uint32_t* d_max_key, uint32_t* hist, uint32_t* blk,
                                 uint32_t* d_sel, hipStream_t s);
 
-// Scratch of the sorted insert path (sized for `cap` points per batch).
+// Scratch of the grouped insert path (sized for `cap` points per batch).
 struct InsertScratch {
-    uint32_t* key[2];
-    uint32_t* val[2];
-    unsigned long long* packed;   // fixed-point offsets of each point, 20 bits per axis
-    uint32_t* hist;
+    uint32_t* key;                // [cap] voxel key of each point (kEmpty if dropped)
+    unsigned long long* packed;   // [cap] fixed-point offsets of each point, 20 bits per axis
+    uint4* rec;                   // [cap] (key, offsets) records grouped by bucket
+    uint32_t* hist;               // bucket histograms, bucket-major
     uint32_t* blk;
     uint32_t cap;
 };

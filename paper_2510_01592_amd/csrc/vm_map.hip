@@ -175,8 +175,7 @@ __global__ void __launch_bounds__(kBlock) k_bucket_scatter(const uint32_t* __res
                                                            const unsigned long long* __restrict__ packed, uint32_t n,
                                                            uint32_t lb, uint32_t nblk, uint32_t tile,
                                                            const uint32_t* __restrict__ hist,
-                                                           uint32_t* __restrict__ key_out,
-                                                           uint32_t* __restrict__ lo_out, uint32_t* __restrict__ hi_out)
+                                                           uint4* __restrict__ rec_out)
 {
     __shared__ uint32_t pos[1u << kBucketMaxLog2];
     const uint32_t B = 1u << lb;
@@ -190,18 +189,14 @@ __global__ void __launch_bounds__(kBlock) k_bucket_scatter(const uint32_t* __res
         if (k == kEmpty) continue;
         const unsigned long long pk = packed[i];
         const uint32_t p = atomicAdd(&pos[bucket_of(k, lb)], 1u);
-        key_out[p] = k;
-        lo_out[p] = (uint32_t)pk;
-        hi_out[p] = (uint32_t)(pk >> 32);
+        rec_out[p] = make_uint4(k, (uint32_t)pk, (uint32_t)(pk >> 32), 0u);   // one 16-byte store
     }
 }
 
 // One workgroup per bucket: sum its points per voxel in LDS (at most
 // kBucketChunk points per fill, so the 32-bit sums of 20-bit offsets cannot
 // overflow), then update each voxel's slot once per fill.
-__global__ void __launch_bounds__(kBlock) k_bucket_insert(const uint32_t* __restrict__ key_in,
-                                                          const uint32_t* __restrict__ lo_in,
-                                                          const uint32_t* __restrict__ hi_in, uint32_t lb, uint32_t nblk,
+__global__ void __launch_bounds__(kBlock) k_bucket_insert(const uint4* __restrict__ rec, uint32_t lb, uint32_t nblk,
                                                           const uint32_t* __restrict__ hist, Hash h,
                                                           uint32_t* __restrict__ bits, DevCounters* __restrict__ ctr)
 {
@@ -223,8 +218,9 @@ __global__ void __launch_bounds__(kBlock) k_bucket_insert(const uint32_t* __rest
             }
             __syncthreads();
             for (uint32_t i = c0 + threadIdx.x; i < c1; i += kBlock) {
-                const uint32_t k = key_in[i];
-                const unsigned long long pk = (unsigned long long)lo_in[i] | ((unsigned long long)hi_in[i] << 32);
+                const uint4 r = rec[i];
+                const uint32_t k = r.x;
+                const unsigned long long pk = (unsigned long long)r.y | ((unsigned long long)r.z << 32);
                 uint32_t q = table_slot(k);
                 for (;;) {   // at most kBucketChunk keys in a table of kBucketTable slots: ends
                     const uint32_t old = atomicCAS(&tkey[q], kEmpty, k);
@@ -262,11 +258,18 @@ __global__ void __launch_bounds__(kBlock) k_bucket_insert(const uint32_t* __rest
                     n_lost += tcnt[q];
                     continue;
                 }
-                Slot* s = &h.slot[sl];
-                s->cnt += tcnt[q];
-                s->sum[0] += tsum[0][q];
-                s->sum[1] += tsum[1][q];
-                s->sum[2] += tsum[2][q];
+                // the slot as two 16-byte halves: {key, cnt, sum0}, {sum1, sum2}
+                uint4* sp = reinterpret_cast<uint4*>(&h.slot[sl]);
+                uint4 a = sp[0], b2 = sp[1];
+                const unsigned long long s0 = ((unsigned long long)a.w << 32 | a.z) + tsum[0][q];
+                const unsigned long long s1 = ((unsigned long long)b2.y << 32 | b2.x) + tsum[1][q];
+                const unsigned long long s2 = ((unsigned long long)b2.w << 32 | b2.z) + tsum[2][q];
+                a.y += tcnt[q];
+                a.z = (uint32_t)s0;
+                a.w = (uint32_t)(s0 >> 32);
+                b2 = make_uint4((uint32_t)s1, (uint32_t)(s1 >> 32), (uint32_t)s2, (uint32_t)(s2 >> 32));
+                sp[0] = a;
+                sp[1] = b2;
             }
             __syncthreads();
         }
@@ -444,13 +447,12 @@ hipError_t launch_insert(const float* xyz, int64_t n, const Pose& pose, const Ge
         const uint32_t lb = bucket_log2(m);
         const uint32_t tile = bucket_tile(m);
         const uint32_t nblk = (m + tile - 1) / tile;
-        k_vox_bucket<<<nblk, kBlock, 0, s>>>(xyz + 3 * done, m, pose, g, lb, nblk, tile, done == 0, sc.key[0],
+        k_vox_bucket<<<nblk, kBlock, 0, s>>>(xyz + 3 * done, m, pose, g, lb, nblk, tile, done == 0, sc.key,
                                             sc.packed, sc.hist, ctr);
         hipError_t e = scan_exclusive_dev(sc.hist, sc.hist, nullptr, (nblk << lb), &ctr->sort_n, sc.blk, s);
         if (e != hipSuccess) return e;
-        k_bucket_scatter<<<nblk, kBlock, 0, s>>>(sc.key[0], sc.packed, m, lb, nblk, tile, sc.hist, sc.key[1],
-                                                sc.val[0], sc.val[1]);
-        k_bucket_insert<<<1u << lb, kBlock, 0, s>>>(sc.key[1], sc.val[0], sc.val[1], lb, nblk, sc.hist, h, bits, ctr);
+        k_bucket_scatter<<<nblk, kBlock, 0, s>>>(sc.key, sc.packed, m, lb, nblk, tile, sc.hist, sc.rec);
+        k_bucket_insert<<<1u << lb, kBlock, 0, s>>>(sc.rec, lb, nblk, sc.hist, h, bits, ctr);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     return hipSuccess;
