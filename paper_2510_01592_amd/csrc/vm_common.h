@@ -241,6 +241,8 @@ struct WorkLayout {
     float4* hyp;            // [k_cap * H]
     uint32_t* tile_off;     // [k_cap + 1]
     uint32_t* tile_k;       // [n_cap / tile + k_cap + 1] cluster of each point tile
+    uint32_t* tile_off_big;  // the same for the clusters beyond one wave's points
+    uint32_t* tile_k_big;
     uint32_t* flags;        // [n_cap]
     uint32_t* blk;          // scan partials
     uint32_t* hull_cnt;     // [k_cap + 2]
@@ -254,7 +256,7 @@ struct WorkLayout {
     uint32_t* ext_i;        // [hull tiles * 8]
     double* poly;           // [k_cap * 18]
     uint32_t* surv_cnt;     // [k_cap]
-    uint32_t* small;        // [64] device scalars: K, tiles, inliers, -, K (hull), vertices, hull tiles
+    uint32_t* small;        // [64] device scalars: K, tiles, inliers, large-cluster tiles, K (hull), vertices, hull tiles
     size_t bytes;
 };
 WorkLayout work_layout(void* base, uint32_t k_cap, uint32_t n_cap, uint32_t n_hyp);

@@ -31,6 +31,7 @@ constexpr int kTileThreads = 256;
 constexpr int kTileItems = 4;
 constexpr int kHullTile = kTileThreads * kTileItems;   // inliers per tile
 constexpr int kChainBlock = 256;
+constexpr int kSmallGrid = 2048;   // workgroups of the wave-per-cluster kernels (8192 waves)
 constexpr int kLdsCap = 2048;                           // survivors sorted in LDS
 
 __device__ __forceinline__ bool p2_less(double au, double av, uint32_t ai, double bu, double bv, uint32_t bi)
@@ -163,7 +164,9 @@ __global__ void __launch_bounds__(kBlock) k_hull_tiles(const uint32_t* __restric
     const uint32_t K = small[4];
     for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < K; k += gridDim.x * blockDim.x) {
         const bool ok = cluster_ok(k, off, best, in_off, in_idx, in_cap);
-        ntiles[k] = ok ? (in_off[k + 1] - in_off[k] + kHullTile - 1) / kHullTile : 0u;
+        const uint32_t m = ok ? in_off[k + 1] - in_off[k] : 0u;
+        // clusters with at most one wave of inliers skip the tiled filter
+        ntiles[k] = m > (uint32_t)kWave ? (m + kHullTile - 1) / kHullTile : 0u;
         if (best[k] >= 0 && in_off[k + 1] > in_cap) atomicOr(status, (uint32_t)VM_FLAG_INLIERS_CAP);
     }
 }
@@ -226,7 +229,7 @@ __global__ void __launch_bounds__(kTileThreads) k_hull_extremes(
 // ---- C: per-cluster extreme polygon -----------------------------------------------
 // poly layout per cluster (18 doubles): u[8], v[8], margin, vertex count
 // (-1: no polygon for the cluster, 0: no filtering)
-__global__ void __launch_bounds__(kWave) k_hull_poly(const uint32_t* __restrict__ small,
+__global__ void __launch_bounds__(kBlock) k_hull_poly(const uint32_t* __restrict__ small,
                                                      const uint32_t* __restrict__ tile_off,
                                                      const uint32_t* __restrict__ off, const float* __restrict__ X,
                                                      const float* __restrict__ Y, const float* __restrict__ Z,
@@ -239,8 +242,10 @@ __global__ void __launch_bounds__(kWave) k_hull_poly(const uint32_t* __restrict_
 {
     const uint32_t K = small[4];
     const uint32_t T = small[6];
-    const int lane = threadIdx.x;
-    for (uint32_t k = blockIdx.x; k < K; k += gridDim.x) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const uint32_t waves = gridDim.x * (kBlock / kWave);
+    const uint32_t w0 = __builtin_amdgcn_readfirstlane(blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave);
+    for (uint32_t k = w0; k < K; k += waves) {   // a wave per cluster (wave-uniform index: scalar loads)
         const uint32_t t0 = tile_off[k], t1 = tiles_end(tile_off, k, K, T);
         if (lane == 0) surv_cnt[k] = 0;
         double* P = poly + 18 * (size_t)k;
@@ -489,8 +494,115 @@ __device__ __forceinline__ uint32_t chain_level3(const double* U, const double* 
     return h;
 }
 
+// Clusters with at most 64 points to chain -- survivors of the filter, or
+// (clusters the filter skips) all inliers, projected here exactly as the
+// filter projects them -- one wave each, four per workgroup.  The points are
+// sorted across the wave's lanes (bitonic network on shuffles, same order:
+// u, then v, then inlier position), then one lane runs the lower and the
+// upper chain; the result is the same as the workgroup path's.
+__global__ void __launch_bounds__(kBlock) k_hull_small(
+    const uint32_t* __restrict__ small, const uint32_t* __restrict__ tile_off, const uint32_t* __restrict__ off,
+    const float* __restrict__ X, const float* __restrict__ Y, const float* __restrict__ Z,
+    const float4* __restrict__ plane, const int32_t* __restrict__ best, uint32_t in_cap,
+    const uint32_t* __restrict__ in_off, const uint32_t* __restrict__ in_idx, const uint32_t* __restrict__ surv_cnt,
+    const double* __restrict__ gu, const double* __restrict__ gv, const uint32_t* __restrict__ gi,
+    uint32_t* __restrict__ hull_cnt, uint32_t* __restrict__ hull_tmp, double* __restrict__ area_out)
+{
+    __shared__ double su[kBlock / kWave][kWave];
+    __shared__ double sv[kBlock / kWave][kWave];
+    __shared__ uint32_t si[kBlock / kWave][kWave];
+    __shared__ uint8_t st[kBlock / kWave][2 * kWave + 2];
+    const uint32_t K = small[4];
+    const uint32_t T = small[6];
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    const uint32_t waves = gridDim.x * (kBlock / kWave);
+    // wave-uniform cluster index: the cluster's own loads become scalar
+    const uint32_t w0 = __builtin_amdgcn_readfirstlane(blockIdx.x * (kBlock / kWave) + wv);
+    for (uint32_t k = w0; k < K; k += waves) {
+        const bool tiled = tile_off[k] != tiles_end(tile_off, k, K, T);
+        uint32_t ns;
+        double u = INFINITY, v = INFINITY;
+        uint32_t i = 0xFFFFFFFFu;
+        const uint32_t ib = in_off[k];
+        if (tiled) {
+            ns = surv_cnt[k];
+            if (ns > (uint32_t)kWave) continue;   // the workgroup path
+            if ((uint32_t)lane < ns) {
+                u = gu[ib + lane];
+                v = gv[ib + lane];
+                i = gi[ib + lane];
+            }
+        } else {
+            if (!cluster_ok(k, off, best, in_off, in_idx, in_cap)) continue;   // no polygon
+            ns = in_off[k + 1] - ib;
+            const ClusterFrame f = cluster_frame(k, off, X, Y, Z, plane, in_off, in_idx);
+            if ((uint32_t)lane < ns) {
+                const uint32_t p = f.pb + in_idx[ib + lane];
+                project(f, X[p], Y[p], Z[p], &u, &v);
+                i = (uint32_t)lane;
+            }
+        }
+        for (int kk = 2; kk <= kWave; kk <<= 1) {
+            for (int j = kk >> 1; j > 0; j >>= 1) {
+                const double ou = __shfl_xor(u, j, kWave), ov = __shfl_xor(v, j, kWave);
+                const uint32_t oi = __shfl_xor(i, j, kWave);
+                const bool up = (lane & kk) == 0, low = (lane & j) == 0;
+                const bool mine_less = p2_less(u, v, i, ou, ov, oi);
+                if ((low == up) != mine_less) {
+                    u = ou;
+                    v = ov;
+                    i = oi;
+                }
+            }
+        }
+        su[wv][lane] = u;
+        sv[wv][lane] = v;
+        si[wv][lane] = i;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        uint32_t h = 0;
+        if (lane == 0) {
+            const double* U = su[wv];
+            const double* V = sv[wv];
+            uint8_t* S = st[wv];
+            // lower chain
+            for (uint32_t q = 0; q < ns; ++q) {
+                while (h >= 2 && cross3(U[S[h - 2]], V[S[h - 2]], U[S[h - 1]], V[S[h - 1]], U[q], V[q]) <= 0.0) --h;
+                S[h++] = (uint8_t)q;
+            }
+            // upper chain (kept past the lower one), appended without its end
+            // points (the lower chain's last and first points)
+            uint32_t hu = 0;
+            uint8_t* Su = S + kWave + 1;
+            for (int32_t q = (int32_t)ns - 1; q >= 0; --q) {
+                while (hu >= 2 && cross3(U[Su[hu - 2]], V[Su[hu - 2]], U[Su[hu - 1]], V[Su[hu - 1]], U[q], V[q]) <= 0.0)
+                    --hu;
+                Su[hu++] = (uint8_t)q;
+            }
+            for (uint32_t q = 1; q + 1 < hu; ++q) S[h++] = Su[q];
+            double sarea = 0.0;
+            if (h >= 3) {
+                for (uint32_t q = 0; q < h; ++q) {
+                    const uint32_t p0 = S[q], p1 = S[q + 1 == h ? 0 : q + 1];
+                    sarea = sarea + (U[p0] * V[p1] - U[p1] * V[p0]);
+                }
+            }
+            area_out[k] = h >= 3 ? 0.5 * sarea : 0.0;
+            hull_cnt[k] = h;
+        }
+        h = __shfl(h, 0, kWave);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if ((uint32_t)lane < h) hull_tmp[ib + k + lane] = in_idx[ib + si[wv][st[wv][lane]]];
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
 __global__ void __launch_bounds__(kChainBlock) k_hull_chain(
-    const uint32_t* __restrict__ small, const uint32_t* __restrict__ tile_off, const uint32_t* __restrict__ in_off,
+    const uint32_t* __restrict__ small, const uint32_t* __restrict__ tile_off, const uint32_t* __restrict__ off,
+    const int32_t* __restrict__ best, uint32_t in_cap, const uint32_t* __restrict__ in_off,
     const uint32_t* __restrict__ in_idx, const uint32_t* __restrict__ surv_cnt, double* __restrict__ gu,
     double* __restrict__ gv, uint32_t* __restrict__ gi, uint32_t* __restrict__ hull_cnt,
     uint32_t* __restrict__ hull_tmp, double* __restrict__ area_out)
@@ -510,8 +622,9 @@ __global__ void __launch_bounds__(kChainBlock) k_hull_chain(
     const uint32_t K = small[4];
     const uint32_t T = small[6];
     for (uint32_t k = blockIdx.x; k < K; k += gridDim.x) {
-        if (tile_off[k] == tiles_end(tile_off, k, K, T)) {   // no polygon
-            if (threadIdx.x == 0) {
+        if (tile_off[k] == tiles_end(tile_off, k, K, T)) {
+            // no tiles: no polygon, or at most one wave of inliers (k_hull_small)
+            if (threadIdx.x == 0 && !cluster_ok(k, off, best, in_off, in_idx, in_cap)) {
                 hull_cnt[k] = 0;
                 area_out[k] = 0.0;
             }
@@ -519,6 +632,7 @@ __global__ void __launch_bounds__(kChainBlock) k_hull_chain(
         }
         const uint32_t ib = in_off[k];
         const uint32_t ns = surv_cnt[k];
+        if (ns <= (uint32_t)kWave) continue;   // one wave of survivors: k_hull_small
         if (ns <= (uint32_t)kLdsCap) {
             uint32_t N = 1;
             while (N < ns) N <<= 1;
@@ -704,13 +818,17 @@ vm_status hulls(const vm_clusters& cl, const vm_planes& planes, const vm_hulls_o
                                                    planes.d_in_off, planes.d_in_idx, w.ext_v, w.ext_i);
     const int kgrid = kc < 1024 ? (int)(kc ? kc : 1) : 1024;
     const int cgrid = kc < 512 ? (int)(kc ? kc : 1) : 512;   // the chain kernel holds ~70 KB of LDS
-    k_hull_poly<<<kgrid, kWave, 0, s>>>(w.small, w.hull_tile_off, cl.d_off, cl.d_x, cl.d_y, cl.d_z, pl,
+    k_hull_poly<<<kSmallGrid, kBlock, 0, s>>>(w.small, w.hull_tile_off, cl.d_off, cl.d_x, cl.d_y, cl.d_z, pl,
                                         planes.d_in_off, planes.d_in_idx, w.ext_v, w.ext_i, w.poly, w.surv_cnt);
     k_hull_filter<<<tgrid, kTileThreads, 0, s>>>(w.small, w.hull_tile_off, cl.d_off, cl.d_x, cl.d_y, cl.d_z, pl,
                                                  planes.d_in_off, planes.d_in_idx, w.poly, w.surv_cnt, w.hull_u,
                                                  w.hull_v, w.hull_i);
-    k_hull_chain<<<cgrid, kChainBlock, 0, s>>>(w.small, w.hull_tile_off, planes.d_in_off, planes.d_in_idx,
-                                               w.surv_cnt, w.hull_u, w.hull_v, w.hull_i, w.hull_cnt, w.hull_tmp,
+    k_hull_small<<<kSmallGrid, kBlock, 0, s>>>(w.small, w.hull_tile_off, cl.d_off, cl.d_x, cl.d_y, cl.d_z, pl,
+                                              planes.d_best_h, planes.in_cap, planes.d_in_off, planes.d_in_idx,
+                                              w.surv_cnt, w.hull_u, w.hull_v, w.hull_i, w.hull_cnt, w.hull_tmp,
+                                              out.d_area);
+    k_hull_chain<<<cgrid, kChainBlock, 0, s>>>(w.small, w.hull_tile_off, cl.d_off, planes.d_best_h, planes.in_cap,
+                                               planes.d_in_off, planes.d_in_idx, w.surv_cnt, w.hull_u, w.hull_v, w.hull_i, w.hull_cnt, w.hull_tmp,
                                                out.d_area);
     VM_HIP(hipGetLastError());
     VM_HIP(scan_exclusive_dev(w.hull_cnt, w.hull_off, w.small + 4, kc, w.small + 5, w.blk, s));

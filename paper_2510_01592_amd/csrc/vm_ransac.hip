@@ -61,6 +61,8 @@ __global__ void __launch_bounds__(kBlock) k_hypotheses(const uint32_t* __restric
                                                        const uint32_t* __restrict__ d_frame,
                                                        const uint32_t* __restrict__ tile_off,
                                                        uint32_t* __restrict__ tile_k,
+                                                       const uint32_t* __restrict__ tile_off_big,
+                                                       uint32_t* __restrict__ tile_k_big,
                                                        int32_t* __restrict__ counts, float4* __restrict__ hyp)
 {
     const uint32_t frame = d_frame ? *d_frame : frame_arg;
@@ -71,9 +73,12 @@ __global__ void __launch_bounds__(kBlock) k_hypotheses(const uint32_t* __restric
         const uint32_t k = (uint32_t)(idx / H), h = (uint32_t)(idx % H);
         const uint32_t base = off[k];
         const uint64_t n = (uint64_t)(off[k + 1] - base);
-        // the cluster of each of its point tiles, for the counting and inlier kernels
+        // the cluster of each of its point tiles, for the inlier kernels and
+        // (clusters beyond one wave's points) for the tiled counting kernel
         const uint32_t nt = (uint32_t)((n + kTile - 1) / kTile);
         for (uint32_t q = h; q < nt; q += H) tile_k[tile_off[k] + q] = k;
+        if (n > (uint64_t)kWave * kPtsPerLane)
+            for (uint32_t q = h; q < nt; q += H) tile_k_big[tile_off_big[k] + q] = k;
         const float qnan = __builtin_nanf("");
         float4 pl = make_float4(qnan, qnan, qnan, qnan);
         if (n >= 3) {
@@ -131,11 +136,15 @@ __global__ void __launch_bounds__(kBlock) k_validate(const uint32_t* __restrict_
 
 // tiles per cluster (for the device-built tile list)
 __global__ void __launch_bounds__(kBlock) k_tiles(const uint32_t* __restrict__ small,
-                                                  const uint32_t* __restrict__ off, uint32_t* __restrict__ ntiles)
+                                                  const uint32_t* __restrict__ off, uint32_t* __restrict__ ntiles,
+                                                  uint32_t* __restrict__ ntiles_big)
 {
     const uint32_t K = small[0];
-    for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < K; k += gridDim.x * blockDim.x)
-        ntiles[k] = (off[k + 1] - off[k] + kTile - 1) / kTile;
+    for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < K; k += gridDim.x * blockDim.x) {
+        const uint32_t n = off[k + 1] - off[k];
+        ntiles[k] = (n + kTile - 1) / kTile;
+        ntiles_big[k] = n > kWave * kPtsPerLane ? (n + kTile - 1) / kTile : 0u;   // counted by the tiled kernel
+    }
 }
 
 // (b) inlier counting over (tile, hypothesis-chunk) items.  The number of
@@ -158,10 +167,37 @@ __device__ __forceinline__ uint32_t count_rows(const float4 pl, const float* px,
     return acc;
 }
 
-// Planes h0..h1 against the wave's points.  A wave's count for a plane is
-// uniform; the counts of up to 64 consecutive planes are gathered in one
-// register (lane q keeps plane hb + q) and added to the block's LDS counters
-// with one vector LDS add per 64 planes.
+// Planes hb..he (at most 64) against the wave's points.  A wave's count for
+// a plane is uniform; the counts are gathered in one register, lane q
+// keeping plane hb + q.
+template <int R>
+__device__ __forceinline__ int count_batch(const float4* __restrict__ hk, uint32_t hb, uint32_t he, const float* px,
+                                           const float* py, const float* pz, float eps, int lane)
+{
+    int cv = 0;
+    uint32_t h = hb;
+    for (; h + kHypBatch <= he; h += kHypBatch) {
+        float4 pl[kHypBatch];
+#pragma unroll
+        for (int b = 0; b < kHypBatch; ++b) pl[b] = hk[h + b];
+#pragma unroll
+        for (int b = 0; b < kHypBatch; ++b) {
+            if (pl[b].x != pl[b].x) continue;   // degenerate hypothesis
+            const uint32_t acc = count_rows<R>(pl[b], px, py, pz, eps);
+            cv = (lane == (int)(h + b - hb)) ? (int)acc : cv;
+        }
+    }
+    for (; h < he; ++h) {
+        const float4 pl = hk[h];
+        if (pl.x != pl.x) continue;
+        const uint32_t acc = count_rows<R>(pl, px, py, pz, eps);
+        cv = (lane == (int)(h - hb)) ? (int)acc : cv;
+    }
+    return cv;
+}
+
+// Planes h0..h1 of a tile: one vector LDS add per 64 planes into the block's
+// counters.
 template <int R>
 __device__ __forceinline__ void count_planes(const float4* __restrict__ hk, uint32_t h0, uint32_t h1,
                                              const float* px, const float* py, const float* pz, float eps,
@@ -169,26 +205,112 @@ __device__ __forceinline__ void count_planes(const float4* __restrict__ hk, uint
 {
     for (uint32_t hb = h0; hb < h1; hb += kWave) {
         const uint32_t he = min(h1, hb + (uint32_t)kWave);
+        const int cv = count_batch<R>(hk, hb, he, px, py, pz, eps, lane);
+        if ((uint32_t)lane < he - hb && cv) atomicAdd(&lcnt[hb - h0 + (uint32_t)lane], (uint32_t)cv);
+    }
+}
+
+// All planes of a cluster that one wave holds: the counts are final, stored.
+// With few points per lane the work per plane is short, so the planes of a
+// 64-plane batch are fetched with one vector load (lane q loads plane
+// hb + q) and broadcast lane by lane, instead of one scalar load per few
+// planes whose latency the short work cannot hide.
+template <int R>
+__device__ __forceinline__ void count_all(const float4* __restrict__ hk, uint32_t H, const float* px, const float* py,
+                                          const float* pz, float eps, int32_t* __restrict__ ck, int lane)
+{
+    for (uint32_t hb = 0; hb < H; hb += kWave) {
+        const uint32_t nb = min(H - hb, (uint32_t)kWave);
+        const float4 mine = (uint32_t)lane < nb ? hk[hb + lane] : make_float4(0.f, 0.f, 0.f, 0.f);
         int cv = 0;
-        uint32_t h = hb;
-        for (; h + kHypBatch <= he; h += kHypBatch) {
-            float4 pl[kHypBatch];
+        for (uint32_t b = 0; b < nb; ++b) {
+            float4 pl;
+            pl.x = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mine.x), (int)b));
+            pl.y = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mine.y), (int)b));
+            pl.z = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mine.z), (int)b));
+            pl.w = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mine.w), (int)b));
+            if (pl.x != pl.x) continue;   // degenerate hypothesis
+            const uint32_t acc = count_rows<R>(pl, px, py, pz, eps);
+            cv = (lane == (int)b) ? (int)acc : cv;
+        }
+        if ((uint32_t)lane < nb) ck[hb + (uint32_t)lane] = cv;
+    }
+}
+
+// Clusters of at most a few rows of points: the lanes take the planes
+// instead (lane q counts plane hb + q) and loop over the points, whose
+// coordinates are wave-uniform loads (scalar loads, 16 points per step),
+// so no lane idles and no per-plane reduction is needed.  The count is the
+// same sum of the same tests.
+__device__ __forceinline__ void count_by_planes(const float4* __restrict__ hk, uint32_t H, uint32_t n,
+                                                const float* __restrict__ X, const float* __restrict__ Y,
+                                                const float* __restrict__ Z, float eps, int32_t* __restrict__ ck,
+                                                int lane)
+{
+    for (uint32_t hb = 0; hb < H; hb += kWave) {
+        const bool has = hb + (uint32_t)lane < H;
+        const float4 pl = has ? hk[hb + lane] : make_float4(0.f, 0.f, 0.f, 0.f);
+        uint32_t c = 0;
+        uint32_t j = 0;
+        for (; j + 16 <= n; j += 16) {
+            float x[16], y[16], z[16];
 #pragma unroll
-            for (int b = 0; b < kHypBatch; ++b) pl[b] = hk[h + b];
+            for (int q = 0; q < 16; ++q) {
+                x[q] = X[j + q];
+                y[q] = Y[j + q];
+                z[q] = Z[j + q];
+            }
 #pragma unroll
-            for (int b = 0; b < kHypBatch; ++b) {
-                if (pl[b].x != pl[b].x) continue;   // degenerate hypothesis
-                const uint32_t acc = count_rows<R>(pl[b], px, py, pz, eps);
-                cv = (lane == (int)(h + b - hb)) ? (int)acc : cv;
+            for (int q = 0; q < 16; ++q) {
+                const float dd = fmaf(pl.z, z[q], fmaf(pl.y, y[q], fmaf(pl.x, x[q], pl.w)));
+                c += fabsf(dd) < eps ? 1u : 0u;   // a degenerate (NaN) plane never passes
             }
         }
-        for (; h < he; ++h) {
-            const float4 pl = hk[h];
-            if (pl.x != pl.x) continue;
-            const uint32_t acc = count_rows<R>(pl, px, py, pz, eps);
-            cv = (lane == (int)(h - hb)) ? (int)acc : cv;
+        for (; j < n; ++j) {
+            const float dd = fmaf(pl.z, Z[j], fmaf(pl.y, Y[j], fmaf(pl.x, X[j], pl.w)));
+            c += fabsf(dd) < eps ? 1u : 0u;
         }
-        if ((uint32_t)lane < he - hb && cv) atomicAdd(&lcnt[hb - h0 + (uint32_t)lane], (uint32_t)cv);
+        if (has) ck[hb + lane] = (int32_t)c;
+    }
+}
+
+// Clusters of at most kSmallPts points (one wave's registers) are counted by
+// one wave each, all hypotheses, without LDS or workgroup barriers; larger
+// clusters go through the tiled kernel below.
+constexpr uint32_t kSmallPts = kWave * kPtsPerLane;   // 1024
+
+__global__ void __launch_bounds__(kCountBlock) k_count_small(const uint32_t* __restrict__ small,
+                                                             const uint32_t* __restrict__ off,
+                                                             const float* __restrict__ X, const float* __restrict__ Y,
+                                                             const float* __restrict__ Z, uint32_t H, float eps,
+                                                             const float4* __restrict__ hyp,
+                                                             int32_t* __restrict__ counts)
+{
+    const uint32_t K = small[0];
+    const int lane = threadIdx.x & (kWave - 1);
+    const uint32_t waves = gridDim.x * (kCountBlock / kWave);
+    const float qnan = __builtin_nanf("");
+    // the wave's cluster index, made explicitly wave-uniform so that its
+    // loads (offsets, points, planes' addresses) are scalar
+    const uint32_t w0 = __builtin_amdgcn_readfirstlane(blockIdx.x * (kCountBlock / kWave) + threadIdx.x / kWave);
+    for (uint32_t k = w0; k < K; k += waves) {
+        const uint32_t base = off[k], n = off[k + 1] - base;
+        if (n < 3 || n > kSmallPts) continue;   // fewer than 3: no planes; more: the tiled kernel
+        const int rows = (int)((n + kWave - 1) / kWave);
+        float px[kPtsPerLane], py[kPtsPerLane], pz[kPtsPerLane];
+#pragma unroll
+        for (int j = 0; j < kPtsPerLane; ++j) {
+            const uint32_t i = (uint32_t)(j * kWave + lane);
+            const bool v = i < n;
+            px[j] = v ? X[base + i] : qnan;   // NaN never passes |d| < eps
+            py[j] = v ? Y[base + i] : qnan;
+            pz[j] = v ? Z[base + i] : qnan;
+        }
+        const float4* hk = hyp + (size_t)k * H;
+        int32_t* ck = counts + (size_t)k * H;
+        if (rows <= 4) count_by_planes(hk, H, n, X + base, Y + base, Z + base, eps, ck, lane);
+        else if (rows > 8) count_all<16>(hk, H, px, py, pz, eps, ck, lane);
+        else count_all<8>(hk, H, px, py, pz, eps, ck, lane);
     }
 }
 
@@ -200,7 +322,7 @@ __global__ void __launch_bounds__(kCountBlock) k_count(const uint32_t* __restric
                                                        int32_t* __restrict__ counts)
 {
     __shared__ uint32_t lcnt[kMaxHypChunk];
-    const uint32_t T = small[1];
+    const uint32_t T = small[3];   // tiles of the clusters beyond one wave
     if (T == 0) return;
     // chunks per tile: enough items for two per block of the grid, chunks of
     // at least 32 hypotheses, at most kMaxHypChunk
@@ -387,6 +509,8 @@ WorkLayout work_layout(void* base, uint32_t k_cap, uint32_t n_cap, uint32_t n_hy
     w.hyp = (float4*)take(kh * sizeof(float4));
     w.tile_off = (uint32_t*)take(((size_t)k_cap + 2) * sizeof(uint32_t));
     w.tile_k = (uint32_t*)take(((size_t)n_cap / kTile + k_cap + 2) * sizeof(uint32_t));
+    w.tile_off_big = (uint32_t*)take(((size_t)k_cap + 2) * sizeof(uint32_t));
+    w.tile_k_big = (uint32_t*)take(((size_t)n_cap / kTile + k_cap + 2) * sizeof(uint32_t));
     w.flags = (uint32_t*)take(((size_t)n_cap + 1) * sizeof(uint32_t));
     const size_t blk_words = scan_blk_words((uint64_t)n_cap + k_cap + 2) + 64;
     w.blk = (uint32_t*)take(blk_words * sizeof(uint32_t));
@@ -414,22 +538,26 @@ vm_status ransac_planes(const vm_clusters& cl, const vm_ransac_params& p, const 
     const uint32_t kc = cl.k_cap < out.k_cap ? cl.k_cap : out.k_cap;
     if (kc > w.k_cap) return VM_E_STATE;
     const uint32_t H = p.n_hyp;
-    // small[0] = K (clamped), small[1] = tiles, small[2] = inliers
+    // small[0] = K (clamped), small[1] = tiles, small[2] = inliers, small[3] = tiles of clusters beyond one wave
     {
         StageScope t(VM_STAGE_HYPOTHESES, s);
         k_validate<<<1, kBlock, 0, s>>>(cl.d_meta, kc, out.k_cap, cl.n_cap, cl.d_off, w.small, out.d_status);
-        k_tiles<<<grid_for(kc), kBlock, 0, s>>>(w.small, cl.d_off, w.tile_off);
+        k_tiles<<<grid_for(kc), kBlock, 0, s>>>(w.small, cl.d_off, w.tile_off, w.tile_off_big);
         VM_HIP(scan_exclusive_dev(w.tile_off, w.tile_off, w.small, kc, w.small + 1, w.blk, s));
+        VM_HIP(scan_exclusive_dev(w.tile_off_big, w.tile_off_big, w.small, kc, w.small + 3, w.blk, s));
         const uint64_t kh = (uint64_t)kc * H;
         k_hypotheses<<<grid_for(kh, kBlock, 16384), kBlock, 0, s>>>(w.small, cl.d_off, cl.d_tag, cl.d_x, cl.d_y,
                                                                     cl.d_z, H, p.seed, p.frame, p.d_frame,
-                                                                    w.tile_off, w.tile_k, w.counts, w.hyp);
+                                                                    w.tile_off, w.tile_k, w.tile_off_big, w.tile_k_big,
+                                                                    w.counts, w.hyp);
         VM_HIP(hipGetLastError());
     }
     {
         StageScope t(VM_STAGE_COUNT, s);
-        k_count<<<kCountGrid, kCountBlock, 0, s>>>(w.small, w.tile_off, w.tile_k, cl.d_off, cl.d_x, cl.d_y, cl.d_z, H, p.eps, w.hyp,
-                                             w.counts);
+        k_count_small<<<grid_for((uint64_t)kc * kWave, kCountBlock, 1024), kCountBlock, 0, s>>>(
+            w.small, cl.d_off, cl.d_x, cl.d_y, cl.d_z, H, p.eps, w.hyp, w.counts);
+        k_count<<<kCountGrid, kCountBlock, 0, s>>>(w.small, w.tile_off_big, w.tile_k_big, cl.d_off, cl.d_x, cl.d_y,
+                                                   cl.d_z, H, p.eps, w.hyp, w.counts);
         VM_HIP(hipGetLastError());
     }
     {
