@@ -441,19 +441,36 @@ __global__ void __launch_bounds__(kBlock) k_ccl_flatten(const DevCounters* __res
                                                         uint32_t* csize)
 {
     const uint32_t V = ctr->n_occ;
-    for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < V; r += gridDim.x * blockDim.x) {
-        uint32_t x = r, p = ld_parent(&parent[r]);
-        while (p != x) {
-            x = p;
-            p = ld_parent(&parent[x]);
+    const int lane = threadIdx.x & (kWave - 1);
+    const uint32_t stride = gridDim.x * blockDim.x;
+    // every lane runs the same iterations (the wave-wide sums below need them all)
+    for (uint32_t b0 = blockIdx.x * blockDim.x + (threadIdx.x & ~(kWave - 1)); b0 < V; b0 += stride) {
+        const uint32_t r = b0 + (uint32_t)lane;
+        uint32_t x = r, cs = 0;
+        if (r < V) {
+            uint32_t p = ld_parent(&parent[r]);
+            while (p != x) {
+                x = p;
+                p = ld_parent(&parent[x]);
+            }
+            st_parent(&parent[r], x);
+            // a tile-local root joined to another tile's component hands its
+            // count to the component's root (only roots receive counts, so
+            // the count read here is final)
+            if (x != r) cs = csize[r];
         }
-        st_parent(&parent[r], x);
-        // a tile-local root joined to another tile's component hands its
-        // count to the component's root (only roots receive counts, so the
-        // count read here is final)
-        if (x != r) {
-            const uint32_t cs = csize[r];
-            if (cs) atomicAdd(&csize[x], cs);
+        // one atomic per distinct root in the wave (a large component has
+        // many local roots)
+        uint64_t pending = __ballot(cs != 0);
+        while (pending) {
+            const int leader = __ffsll((long long)pending) - 1;
+            const uint32_t root = __shfl(x, leader, kWave);
+            const bool same = cs != 0 && x == root;
+            uint32_t v = same ? cs : 0u;
+#pragma unroll
+            for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, kWave);
+            if (lane == leader) atomicAdd(&csize[root], v);
+            pending &= ~__ballot(same);
         }
     }
 }
