@@ -226,6 +226,37 @@ size_t vm_workspace_bytes(uint32_t k_cap, uint32_t n_cap, uint32_t n_hyp);
 vm_status vm_ransac_planes(const vm_clusters* cl, const vm_ransac_params* params, vm_planes* out,
                            void* d_work, size_t work_bytes, void* stream);
 
+/* Work decomposition of the inlier counting of Sec. III-C (b).  Counts are
+ * integer sums of the same tests, so every valid setting gives identical
+ * results; only the speed differs.  The setting is process-wide and read
+ * when a call is enqueued (a captured graph keeps the one it was captured
+ * with). */
+typedef struct {
+    uint32_t count_grid;        /* workgroups of the tiled counting kernel: a multiple of 8
+                                   (one per XCD), 8..65536; default 4096 */
+    uint32_t chunk_mult;        /* the hypotheses of a point tile are split into chunks so that
+                                   there are about chunk_mult work items per workgroup, 1..16;
+                                   default 2 */
+    uint32_t wave_max_points;   /* clusters of at most this many points are counted by one wave
+                                   each, 0..1024 (0: all tiled); default 1024 */
+    uint32_t plane_max_points;  /* of those, clusters of at most this many points put the lanes
+                                   over hypotheses instead of points, 0..min(256, wave_max_points);
+                                   default 256 */
+} vm_count_config;
+
+/* Set the counting decomposition (NULL: the defaults).  VM_E_ARG if a field
+ * is out of range (nothing changes then). */
+vm_status vm_set_count_config(const vm_count_config* cfg);
+vm_status vm_get_count_config(vm_count_config* out);
+
+/* Time vm_ransac_planes on this workload under candidate decompositions
+ * (one field at a time, starting from the current setting; `reps` calls
+ * each, 1..16) and keep the fastest, which is set and returned in *best.
+ * Synchronises `stream`; the outputs hold the last call's (identical)
+ * results.  Arguments as for vm_ransac_planes; VM_E_STATE while capturing. */
+vm_status vm_autotune_count(const vm_clusters* cl, const vm_ransac_params* params, vm_planes* out, void* d_work,
+                            size_t work_bytes, void* stream, uint32_t reps, vm_count_config* best);
+
 /* ---- polygons (Sec. III-C "Boundary polygon generation") -------------- */
 
 /* For cluster k with a plane: the 2D convex hull of its inliers in the

@@ -3,7 +3,7 @@
 Every step of the path runs in the library's HIP kernels; this module only
 turns torch tensors into device pointers and the current HIP stream, and
 mirrors the C structs with ctypes.  Importing it loads the library and fails
-loudly if it has not been built (``python -m paper_2510_01592_amd.build``).
+loudly if it has not been built (``python paper_2510_01592_amd/build.py``).
 """
 from __future__ import annotations
 
@@ -26,6 +26,7 @@ EXPORTED = [
     "vm_map_stats_async",
     "vm_insert", "vm_map_export", "vm_map_import", "vm_ccl", "vm_workspace_bytes", "vm_ransac_planes",
     "vm_hulls", "vm_segment_frame", "vm_set_stage_timing", "vm_stage_times",
+    "vm_set_count_config", "vm_get_count_config", "vm_autotune_count",
     "vm_capture_begin", "vm_capture_end", "vm_graph_launch", "vm_graph_destroy",
 ]
 
@@ -74,6 +75,14 @@ class SegParams(ctypes.Structure):
     _fields_ = [("min_cluster", ctypes.c_uint32), ("reserved", ctypes.c_uint32), ("ransac", RansacParams)]
 
 
+class CountConfig(ctypes.Structure):
+    _fields_ = [("count_grid", ctypes.c_uint32), ("chunk_mult", ctypes.c_uint32),
+                ("wave_max_points", ctypes.c_uint32), ("plane_max_points", ctypes.c_uint32)]
+
+    def as_dict(self) -> dict:
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
 class VMError(RuntimeError):
     def __init__(self, status: int, what: str):
         super().__init__(f"{what}: {status_string(status)} ({status})")
@@ -91,7 +100,7 @@ def lib() -> ctypes.CDLL:
         # loaded (same SONAME), so both share one runtime and one device context
         import torch  # noqa: F401
         if not os.path.exists(LIB_PATH):
-            raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2510_01592_amd.build`")
+            raise ImportError(f"{LIB_PATH} is not built; run `python paper_2510_01592_amd/build.py`")
         L = ctypes.CDLL(LIB_PATH)
         i32, u32, u64, i64, sz = ctypes.c_int32, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int64, ctypes.c_size_t
         sig = {
@@ -118,6 +127,10 @@ def lib() -> ctypes.CDLL:
             "vm_capture_end": ([_P, ctypes.POINTER(_P)], i32),
             "vm_graph_launch": ([_P, _P], i32),
             "vm_graph_destroy": ([_P], i32),
+            "vm_set_count_config": ([ctypes.POINTER(CountConfig)], i32),
+            "vm_get_count_config": ([ctypes.POINTER(CountConfig)], i32),
+            "vm_autotune_count": ([ctypes.POINTER(Clusters), ctypes.POINTER(RansacParams), ctypes.POINTER(Planes),
+                                   _P, sz, _P, u32, ctypes.POINTER(CountConfig)], i32),
             "vm_set_stage_timing": ([i32], i32),
             "vm_stage_times": ([ctypes.POINTER(ctypes.c_double), ctypes.POINTER(u64), i32], i32),
         }
@@ -370,6 +383,34 @@ def ransac_planes(cl: Clusters, params: RansacParams, out: PlaneBuffers, work, s
     pc = out.c()
     _check(lib().vm_ransac_planes(ctypes.byref(cl), ctypes.byref(params), ctypes.byref(pc), _ptr(work),
                                   int(work.numel() * work.element_size()), _stream(stream)), "vm_ransac_planes")
+
+
+def set_count_config(cfg: Optional[dict] = None) -> None:
+    """Set the counting decomposition (None: the defaults); keys as CountConfig."""
+    if cfg is None:
+        _check(lib().vm_set_count_config(None), "vm_set_count_config")
+        return
+    c = get_count_config()
+    for k, v in cfg.items():
+        if k not in c:
+            raise KeyError(k)
+        c[k] = int(v)
+    _check(lib().vm_set_count_config(ctypes.byref(CountConfig(**c))), "vm_set_count_config")
+
+
+def get_count_config() -> dict:
+    c = CountConfig()
+    _check(lib().vm_get_count_config(ctypes.byref(c)), "vm_get_count_config")
+    return c.as_dict()
+
+
+def autotune_count(cl: Clusters, params: RansacParams, out: PlaneBuffers, work, stream=None, reps: int = 3) -> dict:
+    """Time the counting decompositions on this workload, keep and return the fastest."""
+    pc, best = out.c(), CountConfig()
+    _check(lib().vm_autotune_count(ctypes.byref(cl), ctypes.byref(params), ctypes.byref(pc), _ptr(work),
+                                   int(work.numel() * work.element_size()), _stream(stream), int(reps),
+                                   ctypes.byref(best)), "vm_autotune_count")
+    return best.as_dict()
 
 
 def hulls(cl: Clusters, planes: PlaneBuffers, out: HullBuffers, work, stream=None) -> None:

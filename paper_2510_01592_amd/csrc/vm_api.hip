@@ -419,6 +419,96 @@ vm_status vm_ransac_planes(const vm_clusters* cl, const vm_ransac_params* params
     return ransac_planes(*cl, *params, *out, w, (hipStream_t)stream);
 }
 
+vm_status vm_set_count_config(const vm_count_config* cfg)
+{
+    const vm_count_config c = cfg ? *cfg : count_config_default();
+    if (!count_config_valid(c)) return VM_E_ARG;
+    count_config_set(c);
+    return VM_OK;
+}
+
+vm_status vm_get_count_config(vm_count_config* out)
+{
+    if (!out) return VM_E_ARG;
+    *out = count_config_get();
+    return VM_OK;
+}
+
+namespace {
+// one field of the counting decomposition and the values tried for it
+struct TuneAxis {
+    uint32_t vm_count_config::*field;
+    uint32_t values[6];
+    int n;
+};
+}   // namespace
+
+vm_status vm_autotune_count(const vm_clusters* cl, const vm_ransac_params* params, vm_planes* out, void* d_work,
+                            size_t work_bytes, void* stream, uint32_t reps, vm_count_config* best)
+{
+    if (reps < 1 || reps > 16) return VM_E_ARG;
+    const hipStream_t s = (hipStream_t)stream;
+    if (capturing(s)) return VM_E_STATE;
+    const vm_count_config start = count_config_get();
+    // validates the arguments and warms up under the current setting
+    vm_status st = vm_ransac_planes(cl, params, out, d_work, work_bytes, stream);
+    if (st != VM_OK) return st;
+    hipEvent_t e0, e1;
+    VM_HIP(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return VM_E_DEVICE;
+    }
+    // average milliseconds of `reps` calls under c (after one untimed call)
+    auto time_of = [&](const vm_count_config& c, float* ms) -> vm_status {
+        count_config_set(c);
+        vm_status r = vm_ransac_planes(cl, params, out, d_work, work_bytes, stream);
+        if (r != VM_OK) return r;
+        if (hipEventRecord(e0, s) != hipSuccess) return VM_E_DEVICE;
+        for (uint32_t i = 0; i < reps && r == VM_OK; ++i) r = vm_ransac_planes(cl, params, out, d_work, work_bytes, stream);
+        if (r != VM_OK) return r;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(ms, e0, e1) != hipSuccess)
+            return VM_E_DEVICE;
+        *ms /= (float)reps;
+        return VM_OK;
+    };
+    const TuneAxis axes[] = {
+        {&vm_count_config::wave_max_points, {0, 256, 512, 768, 1024}, 5},
+        {&vm_count_config::plane_max_points, {0, 64, 128, 192, 256}, 5},
+        {&vm_count_config::count_grid, {1024, 2048, 4096, 8192, 16384}, 5},
+        {&vm_count_config::chunk_mult, {1, 2, 4, 8}, 4},
+    };
+    vm_count_config cur = start;
+    float cur_ms = 0.f;
+    st = time_of(cur, &cur_ms);
+    for (const TuneAxis& a : axes) {
+        for (int i = 0; i < a.n && st == VM_OK; ++i) {
+            vm_count_config c = cur;
+            c.*a.field = a.values[i];
+            if (c.*a.field == cur.*a.field) continue;
+            // a smaller wave bound caps the plane bound
+            if (c.plane_max_points > c.wave_max_points) c.plane_max_points = c.wave_max_points;
+            if (!count_config_valid(c)) continue;
+            float ms = 0.f;
+            st = time_of(c, &ms);
+            if (st == VM_OK && ms < cur_ms) {
+                cur = c;
+                cur_ms = ms;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != VM_OK) {
+        count_config_set(start);
+        return st;
+    }
+    count_config_set(cur);
+    if (best) *best = cur;
+    return VM_OK;
+}
+
 vm_status vm_hulls(const vm_clusters* cl, const vm_planes* planes, vm_hulls_out* out, void* d_work, size_t work_bytes,
                    void* stream)
 {

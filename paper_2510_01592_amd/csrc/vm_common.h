@@ -264,6 +264,11 @@ uint64_t hull_tiles_bound(uint32_t k_cap, uint32_t n_cap);
 
 vm_status ransac_planes(const vm_clusters& cl, const vm_ransac_params& p, const vm_planes& out,
                         const WorkLayout& w, hipStream_t s);
+// the process-wide counting decomposition (vm_count_config)
+bool count_config_valid(const vm_count_config& c);
+vm_count_config count_config_default();
+vm_count_config count_config_get();
+void count_config_set(const vm_count_config& c);
 vm_status hulls(const vm_clusters& cl, const vm_planes& planes, const vm_hulls_out& out, const WorkLayout& w,
                 hipStream_t s);
 

@@ -15,6 +15,8 @@
 // with atomics, hence independent of the order of tiles.
 #include "vm_common.h"
 
+#include <mutex>
+
 #include <math.h>
 
 namespace vm {
@@ -26,7 +28,6 @@ constexpr int kTile = kCountBlock * kPtsPerLane;   // points per tile (4096)
 constexpr int kMaxHypChunk = 4096;                 // hypotheses per work item (LDS counters)
 constexpr int kHypBatch = 4;                       // planes loaded together
 constexpr uint32_t kXcds = 8;                      // accelerator complex dies (separate L2s)
-constexpr int kCountGrid = 4096;                   // a multiple of kXcds
 
 __device__ __forceinline__ void philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3, uint64_t k0,
                                               uint64_t k1, uint64_t out[4])
@@ -62,7 +63,7 @@ __global__ void __launch_bounds__(kBlock) k_hypotheses(const uint32_t* __restric
                                                        const uint32_t* __restrict__ tile_off,
                                                        uint32_t* __restrict__ tile_k,
                                                        const uint32_t* __restrict__ tile_off_big,
-                                                       uint32_t* __restrict__ tile_k_big,
+                                                       uint32_t* __restrict__ tile_k_big, uint32_t wave_max,
                                                        int32_t* __restrict__ counts, float4* __restrict__ hyp)
 {
     const uint32_t frame = d_frame ? *d_frame : frame_arg;
@@ -77,7 +78,7 @@ __global__ void __launch_bounds__(kBlock) k_hypotheses(const uint32_t* __restric
         // (clusters beyond one wave's points) for the tiled counting kernel
         const uint32_t nt = (uint32_t)((n + kTile - 1) / kTile);
         for (uint32_t q = h; q < nt; q += H) tile_k[tile_off[k] + q] = k;
-        if (n > (uint64_t)kWave * kPtsPerLane)
+        if (n > wave_max)
             for (uint32_t q = h; q < nt; q += H) tile_k_big[tile_off_big[k] + q] = k;
         const float qnan = __builtin_nanf("");
         float4 pl = make_float4(qnan, qnan, qnan, qnan);
@@ -137,13 +138,13 @@ __global__ void __launch_bounds__(kBlock) k_validate(const uint32_t* __restrict_
 // tiles per cluster (for the device-built tile list)
 __global__ void __launch_bounds__(kBlock) k_tiles(const uint32_t* __restrict__ small,
                                                   const uint32_t* __restrict__ off, uint32_t* __restrict__ ntiles,
-                                                  uint32_t* __restrict__ ntiles_big)
+                                                  uint32_t* __restrict__ ntiles_big, uint32_t wave_max)
 {
     const uint32_t K = small[0];
     for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < K; k += gridDim.x * blockDim.x) {
         const uint32_t n = off[k + 1] - off[k];
         ntiles[k] = (n + kTile - 1) / kTile;
-        ntiles_big[k] = n > kWave * kPtsPerLane ? (n + kTile - 1) / kTile : 0u;   // counted by the tiled kernel
+        ntiles_big[k] = n > wave_max ? (n + kTile - 1) / kTile : 0u;   // counted by the tiled kernel
     }
 }
 
@@ -274,17 +275,20 @@ __device__ __forceinline__ void count_by_planes(const float4* __restrict__ hk, u
     }
 }
 
-// Clusters of at most kSmallPts points (one wave's registers) are counted by
-// one wave each, all hypotheses, without LDS or workgroup barriers; larger
-// clusters go through the tiled kernel below.
-constexpr uint32_t kSmallPts = kWave * kPtsPerLane;   // 1024
+// Clusters of at most wave_max points (at most 1024: one wave's registers)
+// are counted by one wave each, all hypotheses, without LDS or workgroup
+// barriers; larger clusters go through the tiled kernel below.  Of those, the
+// ones of at most plane_max points (at most 256) put the lanes over planes.
+constexpr uint32_t kWaveMaxPts = kWave * kPtsPerLane;   // 1024
+constexpr uint32_t kPlaneMaxPts = 4 * kWave;            // 256
 
 __global__ void __launch_bounds__(kCountBlock) k_count_small(const uint32_t* __restrict__ small,
                                                              const uint32_t* __restrict__ off,
                                                              const float* __restrict__ X, const float* __restrict__ Y,
                                                              const float* __restrict__ Z, uint32_t H, float eps,
                                                              const float4* __restrict__ hyp,
-                                                             int32_t* __restrict__ counts)
+                                                             int32_t* __restrict__ counts, uint32_t wave_max,
+                                                             uint32_t plane_max)
 {
     const uint32_t K = small[0];
     const int lane = threadIdx.x & (kWave - 1);
@@ -295,7 +299,7 @@ __global__ void __launch_bounds__(kCountBlock) k_count_small(const uint32_t* __r
     const uint32_t w0 = __builtin_amdgcn_readfirstlane(blockIdx.x * (kCountBlock / kWave) + threadIdx.x / kWave);
     for (uint32_t k = w0; k < K; k += waves) {
         const uint32_t base = off[k], n = off[k + 1] - base;
-        if (n < 3 || n > kSmallPts) continue;   // fewer than 3: no planes; more: the tiled kernel
+        if (n < 3 || n > wave_max) continue;   // fewer than 3: no planes; more: the tiled kernel
         const int rows = (int)((n + kWave - 1) / kWave);
         float px[kPtsPerLane], py[kPtsPerLane], pz[kPtsPerLane];
 #pragma unroll
@@ -308,9 +312,12 @@ __global__ void __launch_bounds__(kCountBlock) k_count_small(const uint32_t* __r
         }
         const float4* hk = hyp + (size_t)k * H;
         int32_t* ck = counts + (size_t)k * H;
-        if (rows <= 4) count_by_planes(hk, H, n, X + base, Y + base, Z + base, eps, ck, lane);
+        if (n <= plane_max) count_by_planes(hk, H, n, X + base, Y + base, Z + base, eps, ck, lane);
         else if (rows > 8) count_all<16>(hk, H, px, py, pz, eps, ck, lane);
-        else count_all<8>(hk, H, px, py, pz, eps, ck, lane);
+        else if (rows > 4) count_all<8>(hk, H, px, py, pz, eps, ck, lane);
+        else if (rows > 2) count_all<4>(hk, H, px, py, pz, eps, ck, lane);
+        else if (rows > 1) count_all<2>(hk, H, px, py, pz, eps, ck, lane);
+        else count_all<1>(hk, H, px, py, pz, eps, ck, lane);
     }
 }
 
@@ -319,14 +326,14 @@ __global__ void __launch_bounds__(kCountBlock) k_count(const uint32_t* __restric
                                                        const uint32_t* __restrict__ off, const float* __restrict__ X,
                                                        const float* __restrict__ Y, const float* __restrict__ Z,
                                                        uint32_t H, float eps, const float4* __restrict__ hyp,
-                                                       int32_t* __restrict__ counts)
+                                                       int32_t* __restrict__ counts, uint32_t chunk_mult)
 {
     __shared__ uint32_t lcnt[kMaxHypChunk];
     const uint32_t T = small[3];   // tiles of the clusters beyond one wave
     if (T == 0) return;
     // chunks per tile: enough items for two per block of the grid, chunks of
     // at least 32 hypotheses, at most kMaxHypChunk
-    uint32_t HC = (2u * gridDim.x + T - 1) / T;
+    uint32_t HC = (chunk_mult * gridDim.x + T - 1) / T;
     const uint32_t hc_max = (H + 31) / 32;
     if (HC > hc_max) HC = hc_max;
     if (HC < (H + kMaxHypChunk - 1) / kMaxHypChunk) HC = (H + kMaxHypChunk - 1) / kMaxHypChunk;
@@ -531,6 +538,41 @@ WorkLayout work_layout(void* base, uint32_t k_cap, uint32_t n_cap, uint32_t n_hy
     return w;
 }
 
+namespace {
+std::mutex g_count_mu;
+vm_count_config g_count_cfg = count_config_default();
+}   // namespace
+
+vm_count_config count_config_default()
+{
+    vm_count_config c;
+    c.count_grid = 4096;
+    c.chunk_mult = 2;
+    c.wave_max_points = kWaveMaxPts;
+    c.plane_max_points = kPlaneMaxPts;
+    return c;
+}
+
+bool count_config_valid(const vm_count_config& c)
+{
+    if (c.count_grid < kXcds || c.count_grid > 65536 || c.count_grid % kXcds != 0) return false;
+    if (c.chunk_mult < 1 || c.chunk_mult > 16) return false;
+    if (c.wave_max_points > kWaveMaxPts) return false;
+    return c.plane_max_points <= kPlaneMaxPts && c.plane_max_points <= c.wave_max_points;
+}
+
+vm_count_config count_config_get()
+{
+    std::lock_guard<std::mutex> g(g_count_mu);
+    return g_count_cfg;
+}
+
+void count_config_set(const vm_count_config& c)
+{
+    std::lock_guard<std::mutex> g(g_count_mu);
+    g_count_cfg = c;
+}
+
 vm_status ransac_planes(const vm_clusters& cl, const vm_ransac_params& p, const vm_planes& out,
                         const WorkLayout& w, hipStream_t s)
 {
@@ -538,26 +580,29 @@ vm_status ransac_planes(const vm_clusters& cl, const vm_ransac_params& p, const 
     const uint32_t kc = cl.k_cap < out.k_cap ? cl.k_cap : out.k_cap;
     if (kc > w.k_cap) return VM_E_STATE;
     const uint32_t H = p.n_hyp;
+    const vm_count_config cc = count_config_get();
     // small[0] = K (clamped), small[1] = tiles, small[2] = inliers, small[3] = tiles of clusters beyond one wave
     {
         StageScope t(VM_STAGE_HYPOTHESES, s);
         k_validate<<<1, kBlock, 0, s>>>(cl.d_meta, kc, out.k_cap, cl.n_cap, cl.d_off, w.small, out.d_status);
-        k_tiles<<<grid_for(kc), kBlock, 0, s>>>(w.small, cl.d_off, w.tile_off, w.tile_off_big);
+        k_tiles<<<grid_for(kc), kBlock, 0, s>>>(w.small, cl.d_off, w.tile_off, w.tile_off_big, cc.wave_max_points);
         VM_HIP(scan_exclusive_dev(w.tile_off, w.tile_off, w.small, kc, w.small + 1, w.blk, s));
         VM_HIP(scan_exclusive_dev(w.tile_off_big, w.tile_off_big, w.small, kc, w.small + 3, w.blk, s));
         const uint64_t kh = (uint64_t)kc * H;
         k_hypotheses<<<grid_for(kh, kBlock, 16384), kBlock, 0, s>>>(w.small, cl.d_off, cl.d_tag, cl.d_x, cl.d_y,
                                                                     cl.d_z, H, p.seed, p.frame, p.d_frame,
                                                                     w.tile_off, w.tile_k, w.tile_off_big, w.tile_k_big,
-                                                                    w.counts, w.hyp);
+                                                                    cc.wave_max_points, w.counts, w.hyp);
         VM_HIP(hipGetLastError());
     }
     {
         StageScope t(VM_STAGE_COUNT, s);
-        k_count_small<<<grid_for((uint64_t)kc * kWave, kCountBlock, 1024), kCountBlock, 0, s>>>(
-            w.small, cl.d_off, cl.d_x, cl.d_y, cl.d_z, H, p.eps, w.hyp, w.counts);
-        k_count<<<kCountGrid, kCountBlock, 0, s>>>(w.small, w.tile_off_big, w.tile_k_big, cl.d_off, cl.d_x, cl.d_y,
-                                                   cl.d_z, H, p.eps, w.hyp, w.counts);
+        if (cc.wave_max_points >= 3)
+            k_count_small<<<grid_for((uint64_t)kc * kWave, kCountBlock, 1024), kCountBlock, 0, s>>>(
+                w.small, cl.d_off, cl.d_x, cl.d_y, cl.d_z, H, p.eps, w.hyp, w.counts, cc.wave_max_points,
+                cc.plane_max_points);
+        k_count<<<cc.count_grid, kCountBlock, 0, s>>>(w.small, w.tile_off_big, w.tile_k_big, cl.d_off, cl.d_x, cl.d_y,
+                                                      cl.d_z, H, p.eps, w.hyp, w.counts, cc.chunk_mult);
         VM_HIP(hipGetLastError());
     }
     {

@@ -101,3 +101,38 @@ def test_struct_layouts_match_header_sizes():
     assert ctypes.sizeof(vm.Clusters) == 8 + 7 * 8
     assert ctypes.sizeof(vm.Planes) == 8 + 8 * 8
     assert ctypes.sizeof(vm.HullsOut) == 8 + 5 * 8
+
+
+def test_count_config_set_get_and_validation():
+    """The counting decomposition is host state: set/get round-trip, out-of-range
+    fields are rejected with nothing changed, NULL restores the defaults."""
+    import paper_2510_01592_amd as vm
+    L = vm.lib()
+    vm.set_count_config(None)
+    d = vm.get_count_config()
+    assert d == {"count_grid": 4096, "chunk_mult": 2, "wave_max_points": 1024, "plane_max_points": 256}
+    try:
+        vm.set_count_config({"count_grid": 1024, "chunk_mult": 4, "wave_max_points": 512, "plane_max_points": 64})
+        assert vm.get_count_config() == {"count_grid": 1024, "chunk_mult": 4, "wave_max_points": 512,
+                                         "plane_max_points": 64}
+        cur = vm.get_count_config()
+        bad = [dict(count_grid=0), dict(count_grid=12), dict(count_grid=65544), dict(chunk_mult=0),
+               dict(chunk_mult=17), dict(wave_max_points=1025), dict(plane_max_points=257),
+               dict(wave_max_points=32, plane_max_points=64)]
+        for b in bad:
+            c = dict(cur)
+            c.update(b)
+            assert L.vm_set_count_config(ctypes.byref(vm.CountConfig(**c))) == vm.VM_E_ARG, b
+            assert vm.get_count_config() == cur
+        # the extremes of the ranges are accepted
+        for c in (dict(count_grid=8, chunk_mult=1, wave_max_points=0, plane_max_points=0),
+                  dict(count_grid=65536, chunk_mult=16, wave_max_points=1024, plane_max_points=256)):
+            vm.set_count_config(c)
+            assert vm.get_count_config() == c
+        assert L.vm_get_count_config(None) == vm.VM_E_ARG
+        # the autotuner rejects a bad repeat count before any device work
+        assert L.vm_autotune_count(None, None, None, None, 0, None, 0, None) == vm.VM_E_ARG
+        assert L.vm_autotune_count(None, None, None, None, 0, None, 17, None) == vm.VM_E_ARG
+    finally:
+        vm.set_count_config(None)
+    assert vm.get_count_config() == d
