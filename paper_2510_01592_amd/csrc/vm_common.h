@@ -157,6 +157,77 @@ __device__ __forceinline__ void block_add_counters(unsigned long long* const (&d
     }
 }
 
+// Exclusive scan over elements [0, n) of N counters each by one workgroup of
+// T threads (every thread calls it): chunks of T*I elements, I consecutive
+// ones per thread, with the running totals carried from chunk to chunk.
+// get(i, v) fills element i's counters, put(i, excl) receives its exclusive
+// prefix; the totals are returned in `total` (on every thread).  Used where
+// the element count is a per-cluster count, so that the counts, the scan and
+// what consumes the totals take one launch instead of three.
+constexpr int kOneBlockThreads = 1024;
+constexpr uint32_t kOneBlockMax = 65536;   // capacities up to this use the one-workgroup form
+
+template <int T, int I, int N, class Get, class Put>
+__device__ __forceinline__ void one_block_scan(uint32_t n, Get get, Put put, uint32_t (&total)[N])
+{
+    __shared__ uint32_t wsum[N][T / kWave];
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    uint32_t carry[N];
+#pragma unroll
+    for (int c = 0; c < N; ++c) carry[c] = 0;
+    for (uint32_t c0 = 0; c0 < n; c0 += (uint32_t)(T * I)) {
+        const uint32_t mine = c0 + threadIdx.x * I;
+        uint32_t v[I][N], sum[N], inc[N];
+#pragma unroll
+        for (int c = 0; c < N; ++c) sum[c] = 0;
+#pragma unroll
+        for (int j = 0; j < I; ++j) {
+            if (mine + j < n) {
+                get(mine + j, v[j]);
+            } else {
+#pragma unroll
+                for (int c = 0; c < N; ++c) v[j][c] = 0;
+            }
+#pragma unroll
+            for (int c = 0; c < N; ++c) sum[c] += v[j][c];
+        }
+#pragma unroll
+        for (int c = 0; c < N; ++c) {
+            uint32_t x = sum[c];
+#pragma unroll
+            for (int d = 1; d < kWave; d <<= 1) {
+                const uint32_t o = __shfl_up(x, d, kWave);
+                if (lane >= d) x += o;
+            }
+            inc[c] = x;
+            if (lane == kWave - 1) wsum[c][wave] = x;
+        }
+        __syncthreads();
+        uint32_t run[N];
+#pragma unroll
+        for (int c = 0; c < N; ++c) {
+            uint32_t before = 0, tot = 0;
+#pragma unroll
+            for (int w = 0; w < T / kWave; ++w) {
+                const uint32_t t = wsum[c][w];
+                before += (w < wave) ? t : 0u;
+                tot += t;
+            }
+            run[c] = carry[c] + before + inc[c] - sum[c];
+            carry[c] += tot;
+        }
+        __syncthreads();   // wsum is rewritten by the next chunk
+#pragma unroll
+        for (int j = 0; j < I; ++j) {
+            if (mine + j < n) put(mine + j, run);
+#pragma unroll
+            for (int c = 0; c < N; ++c) run[c] += v[j][c];
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < N; ++c) total[c] = carry[c];
+}
+
 // ---- host-side error plumbing ------------------------------------------
 #define VM_HIP(call)                                                    \
     do {                                                                \

@@ -171,6 +171,31 @@ __global__ void __launch_bounds__(kBlock) k_hull_tiles(const uint32_t* __restric
     }
 }
 
+// validate, tiles per cluster and their offsets in one workgroup (the
+// capacity is at most kOneBlockMax clusters)
+__global__ void __launch_bounds__(kOneBlockThreads) k_hull_prepare(
+    const uint32_t* __restrict__ meta, uint32_t kc, uint32_t n_cap, const uint32_t* __restrict__ off,
+    const int32_t* __restrict__ best, const uint32_t* __restrict__ in_off, const uint32_t* __restrict__ in_idx,
+    uint32_t in_cap, uint32_t* __restrict__ small, uint32_t* __restrict__ tile_off, uint32_t* __restrict__ status)
+{
+    __shared__ int bad;
+    const uint32_t K = validate_clusters(meta, off, kc, n_cap, status, &bad);
+    uint32_t total[1];
+    one_block_scan<kOneBlockThreads, 4, 1>(
+        K,
+        [&](uint32_t k, uint32_t(&v)[1]) {
+            const bool ok = cluster_ok(k, off, best, in_off, in_idx, in_cap);
+            const uint32_t m = ok ? in_off[k + 1] - in_off[k] : 0u;
+            v[0] = m > (uint32_t)kWave ? (m + kHullTile - 1) / kHullTile : 0u;
+            if (best[k] >= 0 && in_off[k + 1] > in_cap) atomicOr(status, (uint32_t)VM_FLAG_INLIERS_CAP);
+        },
+        [&](uint32_t k, const uint32_t(&e)[1]) { tile_off[k] = e[0]; }, total);
+    if (threadIdx.x == 0) {
+        small[4] = K;
+        small[6] = total[0];
+    }
+}
+
 // ---- B: projection + 8 directional extremes per tile ------------------------------
 __global__ void __launch_bounds__(kTileThreads) k_hull_extremes(
     const uint32_t* __restrict__ small, const uint32_t* __restrict__ tile_off, const uint32_t* __restrict__ off,
@@ -807,10 +832,16 @@ vm_status hulls(const vm_clusters& cl, const vm_planes& planes, const vm_hulls_o
     if (kc > w.k_cap) return VM_E_STATE;
     StageScope t(VM_STAGE_HULL, s);
     const float4* pl = (const float4*)planes.d_plane;
-    k_hull_validate<<<1, kBlock, 0, s>>>(cl.d_meta, kc, cl.n_cap, cl.d_off, w.small, out.d_status);
-    k_hull_tiles<<<grid_for(kc), kBlock, 0, s>>>(w.small, cl.d_off, planes.d_best_h, planes.d_in_off,
-                                                 planes.d_in_idx, planes.in_cap, w.hull_tile_off, out.d_status);
-    VM_HIP(scan_exclusive_dev(w.hull_tile_off, w.hull_tile_off, w.small + 4, kc, w.small + 6, w.blk, s));
+    if (kc <= kOneBlockMax) {
+        k_hull_prepare<<<1, kOneBlockThreads, 0, s>>>(cl.d_meta, kc, cl.n_cap, cl.d_off, planes.d_best_h,
+                                                      planes.d_in_off, planes.d_in_idx, planes.in_cap, w.small,
+                                                      w.hull_tile_off, out.d_status);
+    } else {
+        k_hull_validate<<<1, kBlock, 0, s>>>(cl.d_meta, kc, cl.n_cap, cl.d_off, w.small, out.d_status);
+        k_hull_tiles<<<grid_for(kc), kBlock, 0, s>>>(w.small, cl.d_off, planes.d_best_h, planes.d_in_off,
+                                                     planes.d_in_idx, planes.in_cap, w.hull_tile_off, out.d_status);
+        VM_HIP(scan_exclusive_dev(w.hull_tile_off, w.hull_tile_off, w.small + 4, kc, w.small + 6, w.blk, s));
+    }
     // grids sized for a few workgroups per CU; the kernels stride over the
     // device-side counts, so empty workgroups are not launched by the thousand
     const int tgrid = grid_for(hull_tiles_bound(kc, cl.n_cap), 1, 2048);

@@ -135,6 +135,39 @@ __global__ void __launch_bounds__(kBlock) k_validate(const uint32_t* __restrict_
     }
 }
 
+// validate, tiles per cluster and both tile-offset scans in one workgroup
+// (the capacity is at most kOneBlockMax clusters)
+__global__ void __launch_bounds__(kOneBlockThreads) k_prepare(const uint32_t* __restrict__ meta, uint32_t k_cap,
+                                                              uint32_t out_k_cap, uint32_t n_cap,
+                                                              const uint32_t* __restrict__ off,
+                                                              uint32_t* __restrict__ small,
+                                                              uint32_t* __restrict__ tile_off,
+                                                              uint32_t* __restrict__ tile_off_big, uint32_t wave_max,
+                                                              uint32_t* __restrict__ status)
+{
+    __shared__ int bad;
+    const uint32_t K = validate_clusters(meta, off, k_cap, n_cap, status, &bad);
+    uint32_t total[2];
+    one_block_scan<kOneBlockThreads, 4, 2>(
+        K,
+        [&](uint32_t k, uint32_t(&v)[2]) {
+            const uint32_t n = off[k + 1] - off[k];
+            v[0] = (n + kTile - 1) / kTile;
+            v[1] = n > wave_max ? v[0] : 0u;   // counted by the tiled kernel
+        },
+        [&](uint32_t k, const uint32_t(&e)[2]) {
+            tile_off[k] = e[0];
+            tile_off_big[k] = e[1];
+        },
+        total);
+    if (threadIdx.x == 0) {
+        small[0] = K;
+        small[1] = total[0];
+        small[3] = total[1];
+        if (meta[0] > out_k_cap) atomicOr(status, (uint32_t)VM_FLAG_CLUSTERS_CAP);
+    }
+}
+
 // tiles per cluster (for the device-built tile list)
 __global__ void __launch_bounds__(kBlock) k_tiles(const uint32_t* __restrict__ small,
                                                   const uint32_t* __restrict__ off, uint32_t* __restrict__ ntiles,
@@ -217,11 +250,12 @@ __device__ __forceinline__ void count_planes(const float4* __restrict__ hk, uint
 // hb + q) and broadcast lane by lane, instead of one scalar load per few
 // planes whose latency the short work cannot hide.
 template <int R>
-__device__ __forceinline__ void count_all(const float4* __restrict__ hk, uint32_t H, const float* px, const float* py,
-                                          const float* pz, float eps, int32_t* __restrict__ ck, int lane)
+__device__ __forceinline__ void count_all(const float4* __restrict__ hk, uint32_t h0, uint32_t h1, const float* px,
+                                          const float* py, const float* pz, float eps, int32_t* __restrict__ ck,
+                                          int lane)
 {
-    for (uint32_t hb = 0; hb < H; hb += kWave) {
-        const uint32_t nb = min(H - hb, (uint32_t)kWave);
+    for (uint32_t hb = h0; hb < h1; hb += kWave) {
+        const uint32_t nb = min(h1 - hb, (uint32_t)kWave);
         const float4 mine = (uint32_t)lane < nb ? hk[hb + lane] : make_float4(0.f, 0.f, 0.f, 0.f);
         int cv = 0;
         for (uint32_t b = 0; b < nb; ++b) {
@@ -243,13 +277,13 @@ __device__ __forceinline__ void count_all(const float4* __restrict__ hk, uint32_
 // coordinates are wave-uniform loads (scalar loads, 16 points per step),
 // so no lane idles and no per-plane reduction is needed.  The count is the
 // same sum of the same tests.
-__device__ __forceinline__ void count_by_planes(const float4* __restrict__ hk, uint32_t H, uint32_t n,
+__device__ __forceinline__ void count_by_planes(const float4* __restrict__ hk, uint32_t h0, uint32_t h1, uint32_t n,
                                                 const float* __restrict__ X, const float* __restrict__ Y,
                                                 const float* __restrict__ Z, float eps, int32_t* __restrict__ ck,
                                                 int lane)
 {
-    for (uint32_t hb = 0; hb < H; hb += kWave) {
-        const bool has = hb + (uint32_t)lane < H;
+    for (uint32_t hb = h0; hb < h1; hb += kWave) {
+        const bool has = hb + (uint32_t)lane < h1;
         const float4 pl = has ? hk[hb + lane] : make_float4(0.f, 0.f, 0.f, 0.f);
         uint32_t c = 0;
         uint32_t j = 0;
@@ -276,9 +310,12 @@ __device__ __forceinline__ void count_by_planes(const float4* __restrict__ hk, u
 }
 
 // Clusters of at most wave_max points (at most 1024: one wave's registers)
-// are counted by one wave each, all hypotheses, without LDS or workgroup
-// barriers; larger clusters go through the tiled kernel below.  Of those, the
-// ones of at most plane_max points (at most 256) put the lanes over planes.
+// are counted by waves without LDS or workgroup barriers, a wave per
+// (cluster, chunk of hypotheses) item: the counts of a chunk are final.  The
+// hypotheses are split into chunks (multiples of 64) only as far as needed
+// for about chunk_mult items per wave, so few clusters still fill the chip.
+// Larger clusters go through the tiled kernel below.  Clusters of at most
+// plane_max points (at most 256) put the lanes over planes.
 constexpr uint32_t kWaveMaxPts = kWave * kPtsPerLane;   // 1024
 constexpr uint32_t kPlaneMaxPts = 4 * kWave;            // 256
 
@@ -288,16 +325,26 @@ __global__ void __launch_bounds__(kCountBlock) k_count_small(const uint32_t* __r
                                                              const float* __restrict__ Z, uint32_t H, float eps,
                                                              const float4* __restrict__ hyp,
                                                              int32_t* __restrict__ counts, uint32_t wave_max,
-                                                             uint32_t plane_max)
+                                                             uint32_t plane_max, uint32_t chunk_mult)
 {
     const uint32_t K = small[0];
+    if (K == 0) return;
     const int lane = threadIdx.x & (kWave - 1);
     const uint32_t waves = gridDim.x * (kCountBlock / kWave);
     const float qnan = __builtin_nanf("");
-    // the wave's cluster index, made explicitly wave-uniform so that its
-    // loads (offsets, points, planes' addresses) are scalar
+    // chunks of cb 64-plane batches, HC chunks per cluster
+    const uint32_t nb64 = (H + kWave - 1) / kWave;
+    uint32_t HC = (uint32_t)min((uint64_t)nb64, ((uint64_t)chunk_mult * waves + K - 1) / K);
+    if (HC < 1) HC = 1;
+    const uint32_t cb = (nb64 + HC - 1) / HC;
+    HC = (nb64 + cb - 1) / cb;
+    const uint64_t items = (uint64_t)K * HC;
+    // the wave's item index, made explicitly wave-uniform so that its loads
+    // (offsets, points, planes' addresses) are scalar
     const uint32_t w0 = __builtin_amdgcn_readfirstlane(blockIdx.x * (kCountBlock / kWave) + threadIdx.x / kWave);
-    for (uint32_t k = w0; k < K; k += waves) {
+    for (uint64_t item = w0; item < items; item += waves) {
+        const uint32_t k = (uint32_t)(item / HC), hc = (uint32_t)(item % HC);
+        const uint32_t h0 = hc * cb * kWave, h1 = min(H, h0 + cb * kWave);
         const uint32_t base = off[k], n = off[k + 1] - base;
         if (n < 3 || n > wave_max) continue;   // fewer than 3: no planes; more: the tiled kernel
         const int rows = (int)((n + kWave - 1) / kWave);
@@ -312,12 +359,12 @@ __global__ void __launch_bounds__(kCountBlock) k_count_small(const uint32_t* __r
         }
         const float4* hk = hyp + (size_t)k * H;
         int32_t* ck = counts + (size_t)k * H;
-        if (n <= plane_max) count_by_planes(hk, H, n, X + base, Y + base, Z + base, eps, ck, lane);
-        else if (rows > 8) count_all<16>(hk, H, px, py, pz, eps, ck, lane);
-        else if (rows > 4) count_all<8>(hk, H, px, py, pz, eps, ck, lane);
-        else if (rows > 2) count_all<4>(hk, H, px, py, pz, eps, ck, lane);
-        else if (rows > 1) count_all<2>(hk, H, px, py, pz, eps, ck, lane);
-        else count_all<1>(hk, H, px, py, pz, eps, ck, lane);
+        if (n <= plane_max) count_by_planes(hk, h0, h1, n, X + base, Y + base, Z + base, eps, ck, lane);
+        else if (rows > 8) count_all<16>(hk, h0, h1, px, py, pz, eps, ck, lane);
+        else if (rows > 4) count_all<8>(hk, h0, h1, px, py, pz, eps, ck, lane);
+        else if (rows > 2) count_all<4>(hk, h0, h1, px, py, pz, eps, ck, lane);
+        else if (rows > 1) count_all<2>(hk, h0, h1, px, py, pz, eps, ck, lane);
+        else count_all<1>(hk, h0, h1, px, py, pz, eps, ck, lane);
     }
 }
 
@@ -584,10 +631,16 @@ vm_status ransac_planes(const vm_clusters& cl, const vm_ransac_params& p, const 
     // small[0] = K (clamped), small[1] = tiles, small[2] = inliers, small[3] = tiles of clusters beyond one wave
     {
         StageScope t(VM_STAGE_HYPOTHESES, s);
-        k_validate<<<1, kBlock, 0, s>>>(cl.d_meta, kc, out.k_cap, cl.n_cap, cl.d_off, w.small, out.d_status);
-        k_tiles<<<grid_for(kc), kBlock, 0, s>>>(w.small, cl.d_off, w.tile_off, w.tile_off_big, cc.wave_max_points);
-        VM_HIP(scan_exclusive_dev(w.tile_off, w.tile_off, w.small, kc, w.small + 1, w.blk, s));
-        VM_HIP(scan_exclusive_dev(w.tile_off_big, w.tile_off_big, w.small, kc, w.small + 3, w.blk, s));
+        if (kc <= kOneBlockMax) {
+            k_prepare<<<1, kOneBlockThreads, 0, s>>>(cl.d_meta, kc, out.k_cap, cl.n_cap, cl.d_off, w.small, w.tile_off,
+                                                     w.tile_off_big, cc.wave_max_points, out.d_status);
+        } else {
+            k_validate<<<1, kBlock, 0, s>>>(cl.d_meta, kc, out.k_cap, cl.n_cap, cl.d_off, w.small, out.d_status);
+            k_tiles<<<grid_for(kc), kBlock, 0, s>>>(w.small, cl.d_off, w.tile_off, w.tile_off_big,
+                                                    cc.wave_max_points);
+            VM_HIP(scan_exclusive_dev(w.tile_off, w.tile_off, w.small, kc, w.small + 1, w.blk, s));
+            VM_HIP(scan_exclusive_dev(w.tile_off_big, w.tile_off_big, w.small, kc, w.small + 3, w.blk, s));
+        }
         const uint64_t kh = (uint64_t)kc * H;
         k_hypotheses<<<grid_for(kh, kBlock, 16384), kBlock, 0, s>>>(w.small, cl.d_off, cl.d_tag, cl.d_x, cl.d_y,
                                                                     cl.d_z, H, p.seed, p.frame, p.d_frame,
@@ -598,9 +651,10 @@ vm_status ransac_planes(const vm_clusters& cl, const vm_ransac_params& p, const 
     {
         StageScope t(VM_STAGE_COUNT, s);
         if (cc.wave_max_points >= 3)
-            k_count_small<<<grid_for((uint64_t)kc * kWave, kCountBlock, 1024), kCountBlock, 0, s>>>(
+            k_count_small<<<grid_for((uint64_t)kc * ((H + kWave - 1) / kWave) * kWave, kCountBlock, 1024), kCountBlock,
+                            0, s>>>(
                 w.small, cl.d_off, cl.d_x, cl.d_y, cl.d_z, H, p.eps, w.hyp, w.counts, cc.wave_max_points,
-                cc.plane_max_points);
+                cc.plane_max_points, cc.chunk_mult);
         k_count<<<cc.count_grid, kCountBlock, 0, s>>>(w.small, w.tile_off_big, w.tile_k_big, cl.d_off, cl.d_x, cl.d_y,
                                                       cl.d_z, H, p.eps, w.hyp, w.counts, cc.chunk_mult);
         VM_HIP(hipGetLastError());

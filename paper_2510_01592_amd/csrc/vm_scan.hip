@@ -104,6 +104,21 @@ __global__ void __launch_bounds__(kBlock) k_scan_down(const uint32_t* in, uint32
     if (d_total && threadIdx.x == 0 && base + kScanTile >= n) *d_total = prefix + tot;
 }
 
+// Short arrays (per-cluster counts) are scanned by one workgroup in one
+// launch; a two-kernel scan would cost a second launch, which is most of its
+// time at these sizes.
+__global__ void __launch_bounds__(kOneBlockThreads) k_scan_small(const uint32_t* in, uint32_t* out,
+                                                                 const uint32_t* d_n, uint32_t n_fixed,
+                                                                 uint32_t* d_total)
+{
+    const uint32_t n = d_n ? min(*d_n, n_fixed) : n_fixed;
+    uint32_t total[1];
+    one_block_scan<kOneBlockThreads, 4, 1>(
+        n, [&](uint32_t i, uint32_t(&v)[1]) { v[0] = in[i]; }, [&](uint32_t i, const uint32_t(&e)[1]) { out[i] = e[0]; },
+        total);
+    if (threadIdx.x == 0 && d_total) *d_total = total[0];
+}
+
 // ---- radix sort ---------------------------------------------------------------
 // A pass runs if it is the first or the bound's digits from `shift` up are
 // not all zero (keys are at most the bound).
@@ -215,6 +230,10 @@ size_t scan_blk_words(uint64_t n_cap)
 hipError_t scan_exclusive_dev(const uint32_t* in, uint32_t* out, const uint32_t* d_n, uint32_t n_cap,
                               uint32_t* d_total, uint32_t* blk, hipStream_t s)
 {
+    if (n_cap <= kOneBlockMax) {
+        k_scan_small<<<1, kOneBlockThreads, 0, s>>>(in, out, d_n, n_cap, d_total);
+        return hipGetLastError();
+    }
     uint32_t nblk = (uint32_t)((uint64_t(n_cap) + kScanTile - 1) / kScanTile);
     if (nblk == 0) nblk = 1;   // still writes the total (0)
     k_scan_reduce<<<nblk, kBlock, 0, s>>>(in, d_n, n_cap, blk);

@@ -307,3 +307,49 @@ def test_stage_timing(vm):
     finally:
         vm.set_stage_timing(False)
     assert np.all(n >= 1) and np.all(ms > 0)
+
+
+def test_many_clusters_both_launch_forms(vm):
+    """More clusters than the one-workgroup preparation handles (65536): the
+    multi-kernel form runs; the first 60000 clusters alone take the
+    one-workgroup form.  Both agree bit for bit on every shared output and a
+    sample of clusters matches the oracle."""
+    rng = np.random.default_rng(21)
+    src_off, src = scenes.batched_clusters(seed=5, n_clusters=8, n_min=20_000, n_max=20_001)
+    K, H = 70_000, 64
+    sizes = rng.integers(0, 41, size=K)
+    sizes[[17, 40_000, 65_600]] = [5000, 4097, 3000]
+    parts = []
+    for k, n in enumerate(sizes):
+        j = k % 8
+        a = int(src_off[j]) + int(rng.integers(0, 20_000 - int(n)))
+        parts.append(src[a:a + int(n)])
+    off = np.zeros(K + 1, np.uint32)
+    off[1:] = np.cumsum(sizes)
+    xyz = np.concatenate(parts).astype(np.float32)
+    tag = (np.arange(K, dtype=np.uint64) * 2654435761 % (1 << 32)).astype(np.uint32)
+    note(f"many clusters K={K} N={len(xyz)}")
+    out = {}
+    for kk in (K, 60_000):
+        n = int(off[kk])
+        T = cluster_tensors(off[:kk + 1], xyz[:n], tag[:kk])
+        cl = vm.cluster_view(T["off"], T["x"], T["y"], T["z"], T["tag"], T["meta"])
+        pb, hb = run_planes_and_hulls(vm, cl, kk, n, H, 0.01, SEED, 2)
+        out[kk] = (planes_np(pb), hulls_np(hb))
+    (Pa, Ha), (Pb, Hb) = out[K], out[60_000]
+    k2 = 60_000
+    assert Pa["status"] == Pb["status"] == 0 and Ha["status"] == Hb["status"] == 0
+    for key in ("plane", "best", "nin", "counts", "hyp"):
+        assert np.array_equal(np.asarray(Pa[key][:k2]).view(np.uint8), np.asarray(Pb[key]).view(np.uint8)), key
+    assert np.array_equal(Pa["in_off"][:k2 + 1], Pb["in_off"])
+    assert np.array_equal(Pa["in_idx"][:Pb["in_off"][k2]], Pb["in_idx"][:Pb["in_off"][k2]])
+    assert np.array_equal(Ha["v_off"][:k2 + 1], Hb["v_off"])
+    assert np.array_equal(Ha["area"][:k2], Hb["area"])
+    nv = int(Hb["v_off"][k2])
+    assert np.array_equal(Ha["v_idx"][:nv], Hb["v_idx"][:nv])
+    assert np.array_equal(bits(Ha["v_xyz"][:nv]), bits(Hb["v_xyz"][:nv]))
+    sample = sorted(set(rng.choice(K, 120, replace=False).tolist()) | {0, 17, 40_000, 65_535, 65_536, 65_600, K - 1})
+    for k in sample:
+        a, b = int(off[k]), int(off[k + 1])
+        r = oracle.plane_and_hull(xyz[a:b, 0], xyz[a:b, 1], xyz[a:b, 2], H, 0.01, SEED, int(tag[k]), 2)
+        compare_cluster(k, Pa, Ha, r)
