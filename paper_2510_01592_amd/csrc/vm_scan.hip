@@ -9,8 +9,12 @@ namespace {
 constexpr int kScanItems = 16;                      // per thread
 constexpr int kScanTile = kBlock * kScanItems;      // 4096 values per block
 
-constexpr int kRadixBits = 8;
+// 10-bit digits: cluster ids below 1024 (the usual case) sort in one pass
+// that runs, and ids up to 2^20 in two
+constexpr int kRadixBits = 10;
 constexpr int kRadixBins = 1 << kRadixBits;
+constexpr int kBinsPerThread = kRadixBins / kBlock;
+static_assert(kRadixBins % kBlock == 0, "bins are spread evenly over the threads");
 constexpr int kRadixIters = 8;
 constexpr int kRadixTile = kBlock * kRadixIters;    // 2048 pairs per block
 
@@ -155,7 +159,8 @@ __global__ void __launch_bounds__(kBlock) k_radix_hist(const uint32_t* __restric
         }
     }
     if (!runs || blockIdx.x >= nt) return;
-    cnt[threadIdx.x] = 0;
+#pragma unroll
+    for (int q = 0; q < kBinsPerThread; ++q) cnt[q * kBlock + threadIdx.x] = 0;
     __syncthreads();
     const uint64_t base = (uint64_t)blockIdx.x * kRadixTile;
     for (int j = 0; j < kRadixIters; ++j) {
@@ -163,7 +168,11 @@ __global__ void __launch_bounds__(kBlock) k_radix_hist(const uint32_t* __restric
         if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & (kRadixBins - 1)], 1u);
     }
     __syncthreads();
-    hist[(uint64_t)threadIdx.x * nt + blockIdx.x] = cnt[threadIdx.x];
+#pragma unroll
+    for (int q = 0; q < kBinsPerThread; ++q) {
+        const uint32_t d = q * kBlock + threadIdx.x;
+        hist[(uint64_t)d * nt + blockIdx.x] = cnt[d];
+    }
 }
 
 __global__ void __launch_bounds__(kBlock) k_radix_scatter(const uint32_t* __restrict__ kin,
@@ -180,9 +189,13 @@ __global__ void __launch_bounds__(kBlock) k_radix_scatter(const uint32_t* __rest
     const uint64_t tile = (uint64_t)blockIdx.x * kRadixTile;
     if (blockIdx.x >= nt) return;
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-    base[threadIdx.x] = hist[(uint64_t)threadIdx.x * nt + blockIdx.x];
 #pragma unroll
-    for (int w = 0; w < kBlock / kWave; ++w) wcnt[w][threadIdx.x] = 0;
+    for (int q = 0; q < kBinsPerThread; ++q) {
+        const uint32_t d = q * kBlock + threadIdx.x;
+        base[d] = hist[(uint64_t)d * nt + blockIdx.x];
+#pragma unroll
+        for (int w = 0; w < kBlock / kWave; ++w) wcnt[w][d] = 0;
+    }
     __syncthreads();
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     for (int j = 0; j < kRadixIters; ++j) {
@@ -209,8 +222,9 @@ __global__ void __launch_bounds__(kBlock) k_radix_scatter(const uint32_t* __rest
             vout[pos] = v;
         }
         __syncthreads();
-        {
-            const int d = threadIdx.x;
+#pragma unroll
+        for (int q = 0; q < kBinsPerThread; ++q) {
+            const uint32_t d = q * kBlock + threadIdx.x;
             uint32_t add = 0;
 #pragma unroll
             for (int w = 0; w < kBlock / kWave; ++w) { add += wcnt[w][d]; wcnt[w][d] = 0; }

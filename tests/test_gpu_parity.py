@@ -111,8 +111,11 @@ def _grid_points(grid, origin=(0.0, 0.0, 0.0), s=0.01):
 
 
 @pytest.mark.parametrize("shape,p,seed", [((11, 23, 37), 0.3, 0), ((16, 64, 64), 0.08, 1), ((5, 5, 5), 0.6, 2),
-                                          ((30, 70, 33), 0.15, 3), ((1, 1, 200), 0.5, 4), ((40, 1, 1), 0.5, 5)])
+                                          ((30, 70, 33), 0.15, 3), ((1, 1, 200), 0.5, 4), ((40, 1, 1), 0.5, 5),
+                                          ((40, 96, 96), 0.06, 6)])
 def test_ccl_random_grids(vm, shape, p, seed):
+    """Labels and the cluster CSR; the last grid has 8693 components, so the
+    grouping sort takes two digit passes (cluster ids of 1024 and more)."""
     import torch
     grid = np.random.default_rng(seed).random(shape) < p
     nz, ny, nx = shape
@@ -121,13 +124,23 @@ def test_ccl_random_grids(vm, shape, p, seed):
     m = vm.Map((0.0, 0.0, 0.0), 0.01, (nx, ny, nz), 18)
     m.insert(_t(pts))
     V = int(m.stats().occupied)
-    labels = torch.zeros(max(V, 1), dtype=torch.int32, device="cuda")
-    m.ccl(1, labels=labels)
-    torch.cuda.synchronize()
     keys = np.flatnonzero(grid.ravel()).astype(np.uint32)
     ref, _ = oracle.ccl26(keys, (nx, ny, nz))
     assert V == len(keys)
-    assert np.array_equal(labels.cpu().numpy()[:V].view(np.uint32), ref)
+    om = oracle.OracleMap((0.0, 0.0, 0.0), 0.01, (nx, ny, nz))
+    om.insert(pts)
+    assert np.array_equal(om.key, keys)
+    mu = om.means()
+    for minc in (1, 2, 3):
+        labels = torch.zeros(max(V, 1), dtype=torch.int32, device="cuda")
+        cl = m.ccl(minc, labels=labels)
+        got = vm.read_clusters(cl)
+        assert np.array_equal(labels.cpu().numpy()[:V].view(np.uint32), ref)
+        c = oracle.group(keys, ref, mu, minc)
+        assert got["K"] == len(c.tag) and got["N"] == int(c.off[-1]), minc
+        assert np.array_equal(got["off"], c.off) and np.array_equal(got["tag"], c.tag)
+        assert np.array_equal(got["key"], c.key)
+        assert np.array_equal(bits(np.c_[got["x"], got["y"], got["z"]]), bits(c.xyz))
 
 
 def _oracle_frame(sc, frames, n_hyp=None, subset=None):
