@@ -156,6 +156,24 @@ __device__ __forceinline__ void hook_segments(uint32_t v, uint32_t w, F&& f)
     }
 }
 
+// The calls hook_segments(v, w, f) makes, as masks of the cells xl of v:
+// f(xl, xl) for the bits of a, f(xl, xl - 1) for those of b and
+// f(xl, xl + 1) for those of c.
+struct HookMasks {
+    uint32_t a, b, c;
+};
+
+__device__ __forceinline__ HookMasks hook_masks(uint32_t v, uint32_t w)
+{
+    const uint32_t sv = run_starts(v), ev = run_ends(v);
+    const uint32_t m = v & (sv | ev | run_starts(w));
+    HookMasks h;
+    h.a = m & w & (sv | ~(w << 1));
+    h.b = m & sv & (w << 1);
+    h.c = m & ev & (w >> 1);
+    return h;
+}
+
 // LDS union-find.  Finds halve the path (a node is re-pointed at its
 // grandparent: a store of an ancestor, harmless to concurrent finds), hooks
 // put the larger root under the smaller one with a CAS on the root.
@@ -212,9 +230,10 @@ __global__ void __launch_bounds__(kBlock) k_ccl_tile(const uint32_t* __restrict_
     __shared__ uint32_t members[kTileCells / 32];
     __shared__ uint32_t par[kTileCells];
     __shared__ uint32_t pairs[kPairCap];
-    __shared__ uint32_t npairs;
+    __shared__ uint32_t wtot[kBlock / kWave];
     const uint32_t ntiles = tg.ntx * tg.nty * tg.ntz;
     const uint32_t j = threadIdx.x;
+    const int lane = (int)(j & (kWave - 1)), wave = (int)(j / kWave);
     const int yl = (int)(j % kTY), zl = (int)(j / kTY);
     for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const uint32_t tx = t % tg.ntx, ty = (t / tg.ntx) % tg.nty, tz = t / (tg.ntx * tg.nty);
@@ -224,8 +243,9 @@ __global__ void __launch_bounds__(kBlock) k_ccl_tile(const uint32_t* __restrict_
         const uint32_t sv = run_starts(v), ev = run_ends(v);
         rowv[j] = v;
         members[j] = 0;
-        rowrank[j] = v ? seg_rank0(bits, wrank, key0) : 0u;
-        if (j == 0) npairs = 0;
+        // (unconditional, so that its loads overlap those of the row; rows
+        // outside the grid read key 0, and empty rows' ranks are never used)
+        rowrank[j] = seg_rank0(bits, wrank, key0);
         // the union-find runs over run starts (cells of a run share its start)
         for (uint32_t m = sv; m; m &= m - 1) {
             const uint32_t c = j * kTX + (uint32_t)(__ffs(m) - 1);
@@ -234,23 +254,51 @@ __global__ void __launch_bounds__(kBlock) k_ccl_tile(const uint32_t* __restrict_
         // barrier + vote: a tile without occupied cells is skipped by all threads
         if (!__syncthreads_or(v != 0u)) continue;
         // hooks between the runs of the (up to) four neighbouring rows with
-        // smaller keys; the pairs are collected first and then united by all
-        // threads, so that rows with many hooks do not hold up their wave
-        if (v) {
+        // smaller keys.  Each thread counts its row's hooks from bit masks,
+        // a block scan places them in the pair list (plain LDS stores), and
+        // all threads then unite the list, so that rows with many hooks do
+        // not hold up their wave; hooks past the list's end are united at once.
+        HookMasks hm[4];
+        uint32_t nrow[4];
+        uint32_t cnt = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int dy = (q == 0) ? -1 : (q - 2);
+            const int dz = (q == 0) ? 0 : -1;
+            const int ny2 = yl + dy, nz2 = zl + dz;
+            const bool in = v && ny2 >= 0 && ny2 < kTY && nz2 >= 0;
+            nrow[q] = in ? (uint32_t)(ny2 + kTY * nz2) : 0u;
+            hm[q] = hook_masks(in ? v : 0u, in ? rowv[nrow[q]] : 0u);
+            cnt += (uint32_t)(__popc(hm[q].a) + __popc(hm[q].b) + __popc(hm[q].c));
+        }
+        uint32_t inc = cnt;
+#pragma unroll
+        for (int dd = 1; dd < kWave; dd <<= 1) {
+            const uint32_t o = __shfl_up(inc, dd, kWave);
+            if (lane >= dd) inc += o;
+        }
+        if (lane == kWave - 1) wtot[wave] = inc;
+        __syncthreads();
+        uint32_t slot = inc - cnt, npairs = 0;
+#pragma unroll
+        for (int w2 = 0; w2 < kBlock / kWave; ++w2) {
+            const uint32_t t2 = wtot[w2];
+            slot += (w2 < wave) ? t2 : 0u;
+            npairs += t2;
+        }
+        if (cnt) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int dy = (q == 0) ? -1 : (q - 2);
-                const int dz = (q == 0) ? 0 : -1;
-                const int ny2 = yl + dy, nz2 = zl + dz;
-                if (ny2 < 0 || ny2 >= kTY || nz2 < 0) continue;
-                const uint32_t nr = (uint32_t)(ny2 + kTY * nz2);
-                const uint32_t w = rowv[nr], sw = run_starts(w);
-                hook_segments(v, w, [&](int xa, int xb) {
+                const uint32_t nr = nrow[q], sw = run_starts(rowv[nr]);
+                auto put = [&](int xa, int xb) {
                     const uint32_t a = j * kTX + run_start_of(sv, xa), b = nr * kTX + run_start_of(sw, xb);
-                    const uint32_t i = atomicAdd(&npairs, 1u);
-                    if (i < kPairCap) pairs[i] = (a << 16) | b;
+                    if (slot < kPairCap) pairs[slot] = (a << 16) | b;
                     else lds_unite(par, a, b);
-                });
+                    ++slot;
+                };
+                for (uint32_t m = hm[q].a; m; m &= m - 1) put(__ffs(m) - 1, __ffs(m) - 1);
+                for (uint32_t m = hm[q].b; m; m &= m - 1) put(__ffs(m) - 1, __ffs(m) - 2);
+                for (uint32_t m = hm[q].c; m; m &= m - 1) put(__ffs(m) - 1, __ffs(m));
             }
         }
         __syncthreads();
@@ -285,11 +333,19 @@ __global__ void __launch_bounds__(kBlock) k_ccl_tile(const uint32_t* __restrict_
             const uint32_t rrow = rt / kTX, rx = rt % kTX;
             const uint32_t rr = rowrank[rrow] + __popc(rowv[rrow] & ((1u << rx) - 1u));
             const uint32_t r = rowrank[j] + __popc(v & ((1u << s0) - 1u));
-            for (int i = 0; i <= e0 - s0; ++i) parent[r + i] = rr;
+            // the run's entries: single stores up to a 16-byte boundary, then
+            // 16-byte stores, then the rest
+            uint32_t p0 = r;
+            const uint32_t pe = r + (uint32_t)(e0 - s0 + 1);
+            for (; p0 < pe && (p0 & 3u); ++p0) parent[p0] = rr;
+            for (; p0 + 4 <= pe; p0 += 4) *reinterpret_cast<uint4*>(parent + p0) = make_uint4(rr, rr, rr, rr);
+            for (; p0 < pe; ++p0) parent[p0] = rr;
             if (e0 == s0 && rt == c && !((members[c >> 5] >> (c & 31)) & 1u)) csize[r] = 1u;
             else atomicAdd(&csize[rr], (uint32_t)(e0 - s0 + 1));
         }
-        __syncthreads();   // LDS is reused by the next tile
+        // LDS is reused by the next tile (a block with no next tile skips the
+        // barrier, which would wait for the stores above to complete)
+        if (t + gridDim.x < ntiles) __syncthreads();
     }
 }
 
