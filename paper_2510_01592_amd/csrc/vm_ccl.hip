@@ -89,15 +89,17 @@ struct Dims {
 // The grid is cut into 32 x 16 x 16-cell tiles, one workgroup each.  Thread
 // j of the workgroup owns local row j (y = j % 16, z = j / 16), 32 cells along
 // x as one 32-bit occupancy word.  Inside a tile the components are found with
-// a union-find in LDS (parents are local cell indices, hooked with LDS CAS);
-// local cell order is the same as key order, so every local root is the
+// a union-find in LDS over the runs of the rows (a row holds at most 16
+// runs; run q of row j has index 16 j + q, hooked with LDS CAS); run index
+// order is the order of the runs' first keys, so every local root is the
 // smallest key of its local component.  Each occupied voxel then stores, as
 // its global parent, the rank of its local root.  Adjacencies that cross a
 // tile face are hooked afterwards by k_ccl_boundary with the global
 // union-find; only those need device-wide atomics.
 constexpr int kTX = 32, kTY = 16, kTZ = 16;
-constexpr int kTileCells = kTX * kTY * kTZ;   // 8192
 constexpr int kTileRows = kTY * kTZ;          // 256 = threads per workgroup
+constexpr int kRowRuns = kTX / 2;             // runs per row at most
+constexpr int kTileRuns = kTileRows * kRowRuns;   // 4096
 static_assert(kTileRows == kBlock, "one thread per tile row");
 
 struct TileGrid {
@@ -219,6 +221,12 @@ __device__ __forceinline__ uint32_t run_start_of(uint32_t starts, int x)
     return 31u - __clz(starts & ((2u << x) - 1u));   // x = 31: (2u << 31) - 1 wraps to all ones
 }
 
+// ordinal of that run in its row (runs counted from x = 0)
+__device__ __forceinline__ uint32_t run_ordinal(uint32_t starts, int x)
+{
+    return (uint32_t)__popc(starts & ((2u << x) - 1u)) - 1u;
+}
+
 constexpr uint32_t kPairCap = 1024;   // hook pairs buffered per tile (more are united at once)
 
 __global__ void __launch_bounds__(kBlock) k_ccl_tile(const uint32_t* __restrict__ bits, uint32_t nwords,
@@ -227,8 +235,9 @@ __global__ void __launch_bounds__(kBlock) k_ccl_tile(const uint32_t* __restrict_
 {
     __shared__ uint32_t rowv[kTileRows];
     __shared__ uint32_t rowrank[kTileRows];
-    __shared__ uint32_t members[kTileCells / 32];
-    __shared__ uint32_t par[kTileCells];
+    __shared__ uint32_t members[kTileRuns / 32];
+    __shared__ uint32_t par[kTileRuns];
+    __shared__ uint8_t runx[kTileRuns];   // first cell of each run
     __shared__ uint32_t pairs[kPairCap];
     __shared__ uint32_t wtot[kBlock / kWave];
     const uint32_t ntiles = tg.ntx * tg.nty * tg.ntz;
@@ -242,14 +251,17 @@ __global__ void __launch_bounds__(kBlock) k_ccl_tile(const uint32_t* __restrict_
         const uint32_t v = row_bits(bits, nwords, d, x0, y, z, &key0);
         const uint32_t sv = run_starts(v), ev = run_ends(v);
         rowv[j] = v;
-        members[j] = 0;
+        if (j < kTileRuns / 32) members[j] = 0;
         // (unconditional, so that its loads overlap those of the row; rows
         // outside the grid read key 0, and empty rows' ranks are never used)
         rowrank[j] = seg_rank0(bits, wrank, key0);
-        // the union-find runs over run starts (cells of a run share its start)
-        for (uint32_t m = sv; m; m &= m - 1) {
-            const uint32_t c = j * kTX + (uint32_t)(__ffs(m) - 1);
-            par[c] = c;
+        // one union-find node per run
+        {
+            uint32_t c = j * kRowRuns;
+            for (uint32_t m = sv; m; m &= m - 1, ++c) {
+                par[c] = c;
+                runx[c] = (uint8_t)(__ffs(m) - 1);
+            }
         }
         // barrier + vote: a tile without occupied cells is skipped by all threads
         if (!__syncthreads_or(v != 0u)) continue;
@@ -257,7 +269,8 @@ __global__ void __launch_bounds__(kBlock) k_ccl_tile(const uint32_t* __restrict_
         // smaller keys.  Each thread counts its row's hooks from bit masks,
         // a block scan places them in the pair list (plain LDS stores), and
         // all threads then unite the list, so that rows with many hooks do
-        // not hold up their wave; hooks past the list's end are united at once.
+        // not hold up their wave.  More hooks than the list holds are taken
+        // in rounds of kPairCap.
         HookMasks hm[4];
         uint32_t nrow[4];
         uint32_t cnt = 0;
@@ -286,51 +299,56 @@ __global__ void __launch_bounds__(kBlock) k_ccl_tile(const uint32_t* __restrict_
             slot += (w2 < wave) ? t2 : 0u;
             npairs += t2;
         }
-        if (cnt) {
+        for (uint32_t r0 = 0; r0 < npairs; r0 += kPairCap) {   // npairs is block-uniform
+            if (cnt && slot < r0 + kPairCap && slot + cnt > r0) {
+                uint32_t sl = slot;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const uint32_t nr = nrow[q], sw = run_starts(rowv[nr]);
-                auto put = [&](int xa, int xb) {
-                    const uint32_t a = j * kTX + run_start_of(sv, xa), b = nr * kTX + run_start_of(sw, xb);
-                    if (slot < kPairCap) pairs[slot] = (a << 16) | b;
-                    else lds_unite(par, a, b);
-                    ++slot;
-                };
-                for (uint32_t m = hm[q].a; m; m &= m - 1) put(__ffs(m) - 1, __ffs(m) - 1);
-                for (uint32_t m = hm[q].b; m; m &= m - 1) put(__ffs(m) - 1, __ffs(m) - 2);
-                for (uint32_t m = hm[q].c; m; m &= m - 1) put(__ffs(m) - 1, __ffs(m));
+                for (int q = 0; q < 4; ++q) {
+                    const uint32_t nr = nrow[q], sw = run_starts(rowv[nr]);
+                    auto put = [&](int xa, int xb) {
+                        if (sl >= r0 && sl < r0 + kPairCap) {
+                            const uint32_t a = j * kRowRuns + run_ordinal(sv, xa);
+                            const uint32_t b = nr * kRowRuns + run_ordinal(sw, xb);
+                            pairs[sl - r0] = (a << 16) | b;
+                        }
+                        ++sl;
+                    };
+                    for (uint32_t m = hm[q].a; m; m &= m - 1) put(__ffs(m) - 1, __ffs(m) - 1);
+                    for (uint32_t m = hm[q].b; m; m &= m - 1) put(__ffs(m) - 1, __ffs(m) - 2);
+                    for (uint32_t m = hm[q].c; m; m &= m - 1) put(__ffs(m) - 1, __ffs(m));
+                }
             }
-        }
-        __syncthreads();
-        {
-            const uint32_t np = min(npairs, kPairCap);
+            __syncthreads();
+            const uint32_t np = min(npairs - r0, kPairCap);
             for (uint32_t i = j; i < np; i += kBlock) {
                 const uint32_t pr = pairs[i];
                 lds_unite(par, pr >> 16, pr & 0xFFFFu);
             }
+            __syncthreads();
         }
-        __syncthreads();
-        // roots of the run starts (a start's entry then holds its root); a
-        // root with another run or another cell is marked
-        for (uint32_t m = sv; m; m &= m - 1) {
-            const int s0 = __ffs(m) - 1;
-            const int e0 = __ffs(ev & ~((1u << s0) - 1u)) - 1;
-            const uint32_t c = j * kTX + (uint32_t)s0;
-            const uint32_t rt = lds_find(par, c);
-            lds_st(&par[c], rt);
-            if (rt != c || e0 > s0) atomicOr(&members[rt >> 5], 1u << (rt & 31));
+        // roots of the runs (a run's entry then holds its root); a root with
+        // another run or another cell is marked
+        {
+            uint32_t c = j * kRowRuns;
+            for (uint32_t m = sv; m; m &= m - 1, ++c) {
+                const int s0 = __ffs(m) - 1;
+                const int e0 = __ffs(ev & ~((1u << s0) - 1u)) - 1;
+                const uint32_t rt = lds_find(par, c);
+                lds_st(&par[c], rt);
+                if (rt != c || e0 > s0) atomicOr(&members[rt >> 5], 1u << (rt & 31));
+            }
         }
         __syncthreads();
         // global parents: the rank of the local root, for a whole run at once
         // (consecutive cells of a run have consecutive ranks); the local
         // root's rank counts its component's voxels in the tile (a lone voxel
         // stores its 1, other runs add their lengths)
-        for (uint32_t m = sv; m; m &= m - 1) {
+        uint32_t c = j * kRowRuns;
+        for (uint32_t m = sv; m; m &= m - 1, ++c) {
             const int s0 = __ffs(m) - 1;
             const int e0 = __ffs(ev & ~((1u << s0) - 1u)) - 1;
-            const uint32_t c = j * kTX + (uint32_t)s0;
             const uint32_t rt = par[c];
-            const uint32_t rrow = rt / kTX, rx = rt % kTX;
+            const uint32_t rrow = rt / kRowRuns, rx = runx[rt];
             const uint32_t rr = rowrank[rrow] + __popc(rowv[rrow] & ((1u << rx) - 1u));
             const uint32_t r = rowrank[j] + __popc(v & ((1u << s0) - 1u));
             // the run's entries: single stores up to a 16-byte boundary, then

@@ -112,10 +112,12 @@ def _grid_points(grid, origin=(0.0, 0.0, 0.0), s=0.01):
 
 @pytest.mark.parametrize("shape,p,seed", [((11, 23, 37), 0.3, 0), ((16, 64, 64), 0.08, 1), ((5, 5, 5), 0.6, 2),
                                           ((30, 70, 33), 0.15, 3), ((1, 1, 200), 0.5, 4), ((40, 1, 1), 0.5, 5),
-                                          ((40, 96, 96), 0.06, 6)])
+                                          ((40, 96, 96), 0.06, 6), ((32, 48, 64), 0.5, 8), ((16, 32, 96), 0.3, 9)])
 def test_ccl_random_grids(vm, shape, p, seed):
-    """Labels and the cluster CSR; the last grid has 8693 components, so the
-    grouping sort takes two digit passes (cluster ids of 1024 and more)."""
+    """Labels and the cluster CSR.  The (40, 96, 96) grid has 8693 components,
+    so the grouping sort takes two digit passes (cluster ids of 1024 and
+    more); the dense grids give labelling tiles thousands of run hooks, more
+    than one round of the tile's pair list."""
     import torch
     grid = np.random.default_rng(seed).random(shape) < p
     nz, ny, nx = shape
