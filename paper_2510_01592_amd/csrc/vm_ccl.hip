@@ -399,7 +399,7 @@ __global__ void __launch_bounds__(kBlock) k_ccl_boundary(const uint32_t* __restr
     __shared__ uint64_t raw[kRawPairs];
     __shared__ uint64_t buf[kCclTilePairs];
     __shared__ unsigned long long hset[kPairHash];
-    __shared__ uint32_t nraw, nbuf;
+    __shared__ uint32_t nbuf;
     const uint32_t ntiles = tg.ntx * tg.nty * tg.ntz;
     const uint32_t j = threadIdx.x;
     const int yl = (int)(j % kTY), zl = (int)(j / kTY);
@@ -417,28 +417,31 @@ __global__ void __launch_bounds__(kBlock) k_ccl_boundary(const uint32_t* __restr
         if (i < kCclTilePairs) buf[i] = key;
         else uf_unite(parent, ra, rb);
     };
+    __shared__ uint32_t wtot[kBlock / kWave];
+    const int lane = (int)(j & (kWave - 1)), wave = (int)(j / kWave);
     for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        if (j == 0) {
-            nraw = 0;
-            nbuf = 0;
-        }
+        if (j == 0) nbuf = 0;
         for (uint32_t i = j; i < kPairHash; i += kBlock) hset[i] = ~0ull;
-        __syncthreads();
         const uint32_t tx = t % tg.ntx, ty = (t / tg.ntx) % tg.nty, tz = t / (tg.ntx * tg.nty);
         const uint32_t x0 = tx * kTX;
         const int y = (int)(ty * kTY) + yl, z = (int)(tz * kTZ) + zl;
         uint32_t key0;
         const uint32_t v = row_bits(bits, nwords, d, x0, (uint32_t)y, (uint32_t)z, &key0);
-        // first the voxel pairs (no loads of parents yet), ...
-        auto emit = [&](uint32_t a, uint32_t b) {
-            const uint32_t i = atomicAdd(&nraw, 1u);
-            if (i < kRawPairs) raw[i] = ((uint64_t)a << 32) | b;
-            else add_roots(ld_parent(&parent[a]), ld_parent(&parent[b]));
-        };
+        // first the voxel pairs (no loads of parents yet): each thread finds
+        // and counts its row's, a block scan places them in the raw list
         const bool face = yl == 0 || yl == kTY - 1 || zl == 0;
         const bool first = (v & 1u) && x0 > 0, last = (v >> 31) & 1u;
+        uint32_t r0 = 0, cnt = 0;
+        HookMasks hm[4];
+        uint32_t fw[4], fn0[4];
+        uint32_t fr[5], lr[4], fmask = 0, lmask = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            hm[q].a = hm[q].b = hm[q].c = 0;
+            fw[q] = fn0[q] = 0;
+        }
         if (v && (face || first || last)) {
-            const uint32_t r0 = seg_rank0(bits, wrank, key0);
+            r0 = seg_rank0(bits, wrank, key0);
             if (face) {
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
@@ -449,10 +452,10 @@ __global__ void __launch_bounds__(kBlock) k_ccl_boundary(const uint32_t* __restr
                     uint32_t nkey0;
                     const uint32_t w = row_bits(bits, nwords, d, x0, (uint32_t)(y + dy), (uint32_t)(z + dz), &nkey0);
                     if (!w) continue;
-                    const uint32_t n0 = seg_rank0(bits, wrank, nkey0);
-                    hook_segments(v, w, [&](int xa, int xb) {
-                        emit(r0 + __popc(v & ((1u << xa) - 1u)), n0 + __popc(w & ((1u << xb) - 1u)));
-                    });
+                    fw[q] = w;
+                    fn0[q] = seg_rank0(bits, wrank, nkey0);
+                    hm[q] = hook_masks(v, w);
+                    cnt += (uint32_t)(__popc(hm[q].a) + __popc(hm[q].b) + __popc(hm[q].c));
                 }
             }
             if (first) {
@@ -461,36 +464,90 @@ __global__ void __launch_bounds__(kBlock) k_ccl_boundary(const uint32_t* __restr
                 for (int q = 0; q < 5; ++q) {
                     const int dy = (q < 3) ? q - 1 : (q == 3 ? -1 : 0);
                     const int dz = (q < 3) ? -1 : 0;
+                    fr[q] = 0;
                     if (!occ_cell(bits, d, x - 1, y + dy, z + dz)) continue;
                     const uint32_t nk = (uint32_t)(x - 1) + d.nx * ((uint32_t)(y + dy) + d.ny * (uint32_t)(z + dz));
-                    emit(r0, rank_of(bits, wrank, nk));
+                    fr[q] = rank_of(bits, wrank, nk);
+                    fmask |= 1u << q;
                 }
             }
             if (last) {
                 const int x = (int)x0 + 31;
-                const uint32_t r = r0 + (uint32_t)__popc(v) - 1u;
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int dy = (q < 3) ? q - 1 : -1;
                     const int dz = (q < 3) ? -1 : 0;
+                    lr[q] = 0;
                     if (!occ_cell(bits, d, x + 1, y + dy, z + dz)) continue;
                     const uint32_t nk = (uint32_t)(x + 1) + d.nx * ((uint32_t)(y + dy) + d.ny * (uint32_t)(z + dz));
-                    emit(r, rank_of(bits, wrank, nk));
+                    lr[q] = rank_of(bits, wrank, nk);
+                    lmask |= 1u << q;
                 }
             }
+            cnt += (uint32_t)(__popc(fmask) + __popc(lmask));
         }
-        __syncthreads();
-        // ... then the local roots of all of them at once, deduplicated
-        const uint32_t nr = min(nraw, kRawPairs);
-        for (uint32_t i = j; i < nr; i += kBlock) {
-            const uint64_t pr = raw[i];
-            add_roots(ld_parent(&parent[(uint32_t)(pr >> 32)]), ld_parent(&parent[(uint32_t)pr]));
+        uint32_t inc = cnt;
+#pragma unroll
+        for (int dd = 1; dd < kWave; dd <<= 1) {
+            const uint32_t o = __shfl_up(inc, dd, kWave);
+            if (lane >= dd) inc += o;
         }
+        if (lane == kWave - 1) wtot[wave] = inc;
         __syncthreads();
+        uint32_t slot = inc - cnt, nraw = 0;
+#pragma unroll
+        for (int w2 = 0; w2 < kBlock / kWave; ++w2) {
+            const uint32_t t2 = wtot[w2];
+            slot += (w2 < wave) ? t2 : 0u;
+            nraw += t2;
+        }
+        // ... then, a list's worth at a time, the local roots of the pairs,
+        // deduplicated (nraw is block-uniform)
+        for (uint32_t q0 = 0; q0 < nraw; q0 += kRawPairs) {
+            if (cnt && slot < q0 + kRawPairs && slot + cnt > q0) {
+                uint32_t sl = slot;
+                auto emit = [&](uint32_t a, uint32_t b) {
+                    if (sl >= q0 && sl < q0 + kRawPairs) raw[sl - q0] = ((uint64_t)a << 32) | b;
+                    ++sl;
+                };
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const uint32_t w = fw[q], n0 = fn0[q];
+                    for (uint32_t m = hm[q].a; m; m &= m - 1) {
+                        const int xa = __ffs(m) - 1;
+                        emit(r0 + __popc(v & ((1u << xa) - 1u)), n0 + __popc(w & ((1u << xa) - 1u)));
+                    }
+                    for (uint32_t m = hm[q].b; m; m &= m - 1) {
+                        const int xa = __ffs(m) - 1;
+                        emit(r0 + __popc(v & ((1u << xa) - 1u)), n0 + __popc(w & ((1u << (xa - 1)) - 1u)));
+                    }
+                    for (uint32_t m = hm[q].c; m; m &= m - 1) {
+                        const int xa = __ffs(m) - 1;
+                        emit(r0 + __popc(v & ((1u << xa) - 1u)), n0 + __popc(w & ((1u << (xa + 1)) - 1u)));
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < 5; ++q)
+                    if ((fmask >> q) & 1u) emit(r0, fr[q]);
+                const uint32_t rl = r0 + (uint32_t)__popc(v) - 1u;
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if ((lmask >> q) & 1u) emit(rl, lr[q]);
+            }
+            __syncthreads();
+            const uint32_t nr = min(nraw - q0, kRawPairs);
+            for (uint32_t i = j; i < nr; i += kBlock) {
+                const uint64_t pr = raw[i];
+                add_roots(ld_parent(&parent[(uint32_t)(pr >> 32)]), ld_parent(&parent[(uint32_t)pr]));
+            }
+            __syncthreads();
+        }
         const uint32_t np = min(nbuf, kCclTilePairs);
         for (uint32_t i = j; i < np; i += kBlock) pairs[(uint64_t)t * kCclTilePairs + i] = buf[i];
         if (j == 0) npair[t] = np;
-        __syncthreads();   // LDS is reused by the next tile
+        // LDS is reused by the next tile (a block with no next tile skips the
+        // barrier, which would wait for the stores above to complete)
+        if (t + gridDim.x < ntiles) __syncthreads();
     }
 }
 
