@@ -586,41 +586,60 @@ __global__ void __launch_bounds__(kBlock) k_hull_small(
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // lane 0 builds the lower chain (points in sorted order), lane 1 at
+        // the same time the upper one (reverse order), each with the two top
+        // points of its stack held in registers
         uint32_t h = 0;
-        if (lane == 0) {
+        if (lane < 2) {
             const double* U = su[wv];
             const double* V = sv[wv];
-            uint8_t* S = st[wv];
-            // lower chain
-            for (uint32_t q = 0; q < ns; ++q) {
-                while (h >= 2 && cross3(U[S[h - 2]], V[S[h - 2]], U[S[h - 1]], V[S[h - 1]], U[q], V[q]) <= 0.0) --h;
-                S[h++] = (uint8_t)q;
-            }
-            // upper chain (kept past the lower one), appended without its end
-            // points (the lower chain's last and first points)
-            uint32_t hu = 0;
-            uint8_t* Su = S + kWave + 1;
-            for (int32_t q = (int32_t)ns - 1; q >= 0; --q) {
-                while (hu >= 2 && cross3(U[Su[hu - 2]], V[Su[hu - 2]], U[Su[hu - 1]], V[Su[hu - 1]], U[q], V[q]) <= 0.0)
-                    --hu;
-                Su[hu++] = (uint8_t)q;
-            }
-            for (uint32_t q = 1; q + 1 < hu; ++q) S[h++] = Su[q];
-            double sarea = 0.0;
-            if (h >= 3) {
-                for (uint32_t q = 0; q < h; ++q) {
-                    const uint32_t p0 = S[q], p1 = S[q + 1 == h ? 0 : q + 1];
-                    sarea = sarea + (U[p0] * V[p1] - U[p1] * V[p0]);
+            uint8_t* S = st[wv] + (lane ? kWave + 1 : 0);
+            double ua = 0.0, va = 0.0, ub = 0.0, vb = 0.0;   // S[h - 2], S[h - 1]
+            for (uint32_t n = 0; n < ns; ++n) {
+                const uint32_t q = lane ? ns - 1 - n : n;
+                const double uq = U[q], vq = V[q];
+                while (h >= 2 && cross3(ua, va, ub, vb, uq, vq) <= 0.0) {
+                    --h;
+                    ub = ua;
+                    vb = va;
+                    if (h >= 2) {
+                        const uint32_t s2 = S[h - 2];
+                        ua = U[s2];
+                        va = V[s2];
+                    }
                 }
+                S[h++] = (uint8_t)q;
+                ua = ub;
+                va = vb;
+                ub = uq;
+                vb = vq;
             }
-            area_out[k] = h >= 3 ? 0.5 * sarea : 0.0;
-            hull_cnt[k] = h;
         }
-        h = __shfl(h, 0, kWave);
+        const uint32_t hl = __shfl(h, 0, kWave), hu = __shfl(h, 1, kWave);
+        // the polygon: the lower chain, then the upper one without its end
+        // points (the lower chain's last and first points)
+        h = hl + (hu >= 2 ? hu - 2 : 0u);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        if ((uint32_t)lane < h) hull_tmp[ib + k + lane] = in_idx[ib + si[wv][st[wv][lane]]];
+        auto vertex = [&](uint32_t p) -> uint32_t {
+            return p < hl ? st[wv][p] : st[wv][kWave + 1 + (p - hl + 1)];
+        };
+        double term = 0.0;
+        uint32_t vi = 0;
+        if ((uint32_t)lane < h) {
+            vi = vertex((uint32_t)lane);
+            const uint32_t v1 = vertex((uint32_t)lane + 1 == h ? 0u : (uint32_t)lane + 1);
+            term = su[wv][vi] * sv[wv][v1] - su[wv][v1] * sv[wv][vi];
+        }
+        // shoelace sum over the vertices (a wave reduction)
+#pragma unroll
+        for (int dd = kWave / 2; dd >= 1; dd >>= 1) term += __shfl_xor(term, dd, kWave);
+        if (lane == 0) {
+            area_out[k] = h >= 3 ? 0.5 * term : 0.0;
+            hull_cnt[k] = h;
+        }
+        if ((uint32_t)lane < h) hull_tmp[ib + k + lane] = in_idx[ib + si[wv][vi]];
         __builtin_amdgcn_wave_barrier();
     }
 }
