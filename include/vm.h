@@ -234,9 +234,9 @@ vm_status vm_ransac_planes(const vm_clusters* cl, const vm_ransac_params* params
 typedef struct {
     uint32_t count_grid;        /* workgroups of the tiled counting kernel: a multiple of 8
                                    (one per XCD), 8..65536; default 4096 */
-    uint32_t chunk_mult;        /* the hypotheses of a point tile are split into chunks so that
-                                   there are about chunk_mult work items per workgroup, 1..16;
-                                   default 2 */
+    uint32_t chunk_mult;        /* the hypotheses of a point tile (of a wave-counted cluster) are
+                                   split into chunks so that there are about chunk_mult work items
+                                   per workgroup (per wave), 1..16; default 2 */
     uint32_t wave_max_points;   /* clusters of at most this many points are counted by one wave
                                    each, 0..1024 (0: all tiled); default 1024 */
     uint32_t plane_max_points;  /* of those, clusters of at most this many points put the lanes

@@ -306,6 +306,8 @@ hipError_t launch_group(const Geom& g, const Hash& h, SegBuffers& b, uint32_t ca
                         uint32_t* d_labels, DevCounters* ctr, hipStream_t s);
 
 // ---- RANSAC and hulls (vm_ransac.hip, vm_hull.hip) --------------------------
+constexpr int kHullDirs = 8;   // support directions of the hull pre-filter
+
 struct WorkLayout {
     uint32_t k_cap;         // clusters the layout was made for
     int32_t* counts;        // [k_cap * H]
@@ -323,9 +325,9 @@ struct WorkLayout {
     double* hull_v;         // [n_cap]
     uint32_t* hull_i;       // [n_cap]
     uint32_t* hull_tile_off;  // [k_cap + 2]
-    double* ext_v;          // [hull tiles * 8]
-    uint32_t* ext_i;        // [hull tiles * 8]
-    double* poly;           // [k_cap * 18]
+    double* ext_v;          // [hull tiles * kHullDirs]
+    uint32_t* ext_i;        // [hull tiles * kHullDirs]
+    double* poly;           // [k_cap * (2 kHullDirs + 2)]
     uint32_t* surv_cnt;     // [k_cap]
     uint32_t* small;        // [64] device scalars: K, tiles, inliers, large-cluster tiles, K (hull), vertices, hull tiles
     size_t bytes;

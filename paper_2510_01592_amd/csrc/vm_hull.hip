@@ -12,12 +12,13 @@
 //      far above the fp64 rounding of the test) cannot be a hull vertex;
 //   D. per tile: keep only the points not strictly inside that polygon
 //      (block-aggregated compaction into the cluster's own region);
-//   E. per cluster: sort the survivors by (u, v, inlier index) -- bitonic in
-//      LDS, or in global memory for very large survivor sets -- and run
-//      Andrew's monotone chain, popping on every non-left turn (strictly
-//      convex, counter-clockwise from the smallest point).  In LDS the lower
-//      and the upper chain run on two lanes at once; joined at their shared
-//      end points they give exactly the single-stack chain's output;
+//   E. per cluster: sort the survivors by (u, v, inlier index) -- in a
+//      wave's registers for at most 64, bitonic in LDS, or in global memory
+//      for very large survivor sets -- and run Andrew's monotone chain,
+//      popping on every non-left turn (strictly convex, counter-clockwise
+//      from the smallest point).  Up to LDS size the lower and the upper
+//      chain run at once; joined at their shared end points they give
+//      exactly the single-stack chain's output;
 //   F. scan the vertex counts and pack the polygons, each vertex projected
 //      onto the plane.
 #include "vm_common.h"
@@ -71,6 +72,15 @@ __device__ __forceinline__ Basis plane_basis(float4 pl)
 }
 
 // directional functional of direction d (0..7, every 45 degrees, CCW from +u)
+// Support directions of the extreme-point polygon, in counter-clockwise
+// order (every 45 degrees).  A point strictly inside the polygon of the
+// extremes is no hull vertex; a disc keeps about 10 % of its points outside
+// this octagon.  (Sixteen directions keep 3 %, but the extra tests cost more
+// than the shorter sorts save.)
+constexpr int kDirs = kHullDirs;
+constexpr int kPolyWords = 2 * kDirs + 2;   // u[kDirs], v[kDirs], margin, vertex count
+static_assert(kDirs == 8, "dir_val lists 8 directions");
+
 __device__ __forceinline__ double dir_val(int d, double u, double v)
 {
     switch (d) {
@@ -196,15 +206,15 @@ __global__ void __launch_bounds__(kOneBlockThreads) k_hull_prepare(
     }
 }
 
-// ---- B: projection + 8 directional extremes per tile ------------------------------
+// ---- B: projection + directional extremes per tile --------------------------------
 __global__ void __launch_bounds__(kTileThreads) k_hull_extremes(
     const uint32_t* __restrict__ small, const uint32_t* __restrict__ tile_off, const uint32_t* __restrict__ off,
     const float* __restrict__ X, const float* __restrict__ Y, const float* __restrict__ Z,
     const float4* __restrict__ plane, const uint32_t* __restrict__ in_off, const uint32_t* __restrict__ in_idx,
     double* __restrict__ ext_v, uint32_t* __restrict__ ext_i)
 {
-    __shared__ double rv[kTileThreads / kWave][8];
-    __shared__ uint32_t ri[kTileThreads / kWave][8];
+    __shared__ double rv[kTileThreads / kWave][kDirs];
+    __shared__ uint32_t ri[kTileThreads / kWave][kDirs];
     const uint32_t K = small[4];
     const uint32_t T = small[6];
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
@@ -212,10 +222,10 @@ __global__ void __launch_bounds__(kTileThreads) k_hull_extremes(
         const uint32_t k = cluster_of_tile(tile_off, K, t);
         const ClusterFrame f = cluster_frame(k, off, X, Y, Z, plane, in_off, in_idx);
         const uint32_t j0 = (t - tile_off[k]) * kHullTile, j1 = min(j0 + kHullTile, f.m);
-        double bv[8];
-        uint32_t bi[8];
+        double bv[kDirs];
+        uint32_t bi[kDirs];
 #pragma unroll
-        for (int d = 0; d < 8; ++d) { bv[d] = -INFINITY; bi[d] = 0xFFFFFFFFu; }
+        for (int d = 0; d < kDirs; ++d) { bv[d] = -INFINITY; bi[d] = 0xFFFFFFFFu; }
         for (uint32_t j = j0 + threadIdx.x; j < j1; j += kTileThreads) {
             const uint32_t li = in_idx[f.ib + j];
             if (li >= f.nk) continue;
@@ -223,13 +233,13 @@ __global__ void __launch_bounds__(kTileThreads) k_hull_extremes(
             double pu, pv;
             project(f, X[i], Y[i], Z[i], &pu, &pv);
 #pragma unroll
-            for (int d = 0; d < 8; ++d) {
+            for (int d = 0; d < kDirs; ++d) {
                 const double v = dir_val(d, pu, pv);
                 if (v > bv[d]) { bv[d] = v; bi[d] = j; }   // j ascends per thread: first maximum kept
             }
         }
 #pragma unroll
-        for (int d = 0; d < 8; ++d) {
+        for (int d = 0; d < kDirs; ++d) {
             for (int s = kWave / 2; s >= 1; s >>= 1) {
                 const double ov = __shfl_xor(bv[d], s, kWave);
                 const uint32_t oi = __shfl_xor(bi[d], s, kWave);
@@ -238,22 +248,22 @@ __global__ void __launch_bounds__(kTileThreads) k_hull_extremes(
             if (lane == 0) { rv[wave][d] = bv[d]; ri[wave][d] = bi[d]; }
         }
         __syncthreads();
-        if (threadIdx.x < 8) {
+        if (threadIdx.x < kDirs) {
             const int d = threadIdx.x;
             double v = rv[0][d];
             uint32_t ix = ri[0][d];
             for (int w = 1; w < kTileThreads / kWave; ++w)
                 if (rv[w][d] > v || (rv[w][d] == v && ri[w][d] < ix)) { v = rv[w][d]; ix = ri[w][d]; }
-            ext_v[8 * (size_t)t + d] = v;
-            ext_i[8 * (size_t)t + d] = ix;
+            ext_v[kDirs * (size_t)t + d] = v;
+            ext_i[kDirs * (size_t)t + d] = ix;
         }
         __syncthreads();
     }
 }
 
 // ---- C: per-cluster extreme polygon -----------------------------------------------
-// poly layout per cluster (18 doubles): u[8], v[8], margin, vertex count
-// (-1: no polygon for the cluster, 0: no filtering)
+// poly layout per cluster (kPolyWords doubles): u[kDirs], v[kDirs], margin,
+// vertex count (-1: no polygon for the cluster, 0: no filtering)
 __global__ void __launch_bounds__(kBlock) k_hull_poly(const uint32_t* __restrict__ small,
                                                      const uint32_t* __restrict__ tile_off,
                                                      const uint32_t* __restrict__ off, const float* __restrict__ X,
@@ -273,27 +283,27 @@ __global__ void __launch_bounds__(kBlock) k_hull_poly(const uint32_t* __restrict
     for (uint32_t k = w0; k < K; k += waves) {   // a wave per cluster (wave-uniform index: scalar loads)
         const uint32_t t0 = tile_off[k], t1 = tiles_end(tile_off, k, K, T);
         if (lane == 0) surv_cnt[k] = 0;
-        double* P = poly + 18 * (size_t)k;
+        double* P = poly + kPolyWords * (size_t)k;
         if (t0 == t1) {
-            if (lane == 0) P[17] = -1.0;
+            if (lane == 0) P[kPolyWords - 1] = -1.0;
             continue;
         }
         // the wave strides over the cluster's tiles, then reduces each direction
-        double bv[8];
-        uint32_t bi[8];
+        double bv[kDirs];
+        uint32_t bi[kDirs];
 #pragma unroll
-        for (int d = 0; d < 8; ++d) { bv[d] = -INFINITY; bi[d] = 0xFFFFFFFFu; }
+        for (int d = 0; d < kDirs; ++d) { bv[d] = -INFINITY; bi[d] = 0xFFFFFFFFu; }
         for (uint32_t t = t0 + lane; t < t1; t += kWave) {
 #pragma unroll
-            for (int d = 0; d < 8; ++d) {
-                const double tv = ext_v[8 * (size_t)t + d];
-                const uint32_t ti = ext_i[8 * (size_t)t + d];
+            for (int d = 0; d < kDirs; ++d) {
+                const double tv = ext_v[kDirs * (size_t)t + d];
+                const uint32_t ti = ext_i[kDirs * (size_t)t + d];
                 if (tv > bv[d] || (tv == bv[d] && ti < bi[d])) { bv[d] = tv; bi[d] = ti; }
             }
         }
-        uint32_t e[8];
+        uint32_t e[kDirs];
 #pragma unroll
-        for (int d = 0; d < 8; ++d) {
+        for (int d = 0; d < kDirs; ++d) {
             for (int sft = kWave / 2; sft >= 1; sft >>= 1) {
                 const double ov = __shfl_xor(bv[d], sft, kWave);
                 const uint32_t oi = __shfl_xor(bi[d], sft, kWave);
@@ -304,13 +314,13 @@ __global__ void __launch_bounds__(kBlock) k_hull_poly(const uint32_t* __restrict
         if (lane == 0) {
             const ClusterFrame f = cluster_frame(k, off, X, Y, Z, plane, in_off, in_idx);
             int np = 0;
-            uint32_t q[8];
+            uint32_t q[kDirs];
             bool found = true;
-            for (int d = 0; d < 8; ++d) found = found && e[d] < f.m;
-            for (int d = 0; found && d < 8; ++d)
+            for (int d = 0; d < kDirs; ++d) found = found && e[d] < f.m;
+            for (int d = 0; found && d < kDirs; ++d)
                 if (np == 0 || q[np - 1] != e[d]) q[np++] = e[d];
             while (np > 1 && q[np - 1] == q[0]) --np;
-            double pu[8], pv[8];
+            double pu[kDirs], pv[kDirs];
             double umin = INFINITY, umax = -INFINITY, vmin = INFINITY, vmax = -INFINITY;
             for (int a = 0; a < np; ++a) {
                 const uint32_t i = f.pb + in_idx[f.ib + q[a]];
@@ -323,17 +333,30 @@ __global__ void __launch_bounds__(kBlock) k_hull_poly(const uint32_t* __restrict
             const double span = np > 0 ? fmax(umax - umin, vmax - vmin) : 0.0;
             // far above the fp64 rounding of a cross product at this scale
             const double margin = 1e-9 * span * span + 1e-300;
-            bool convex = np >= 3;
-            for (int a = 0; convex && a < np; ++a) {
-                const int b = (a + 1) % np, c = (a + 2) % np;
-                if (cross3(pu[a], pv[a], pu[b], pv[b], pu[c], pv[c]) <= margin) convex = false;
+            // vertices that do not turn left by more than the margin (on an
+            // edge of the others, or repeated) are dropped until every corner
+            // is strictly convex; the rest bound a convex polygon inside the
+            // hull (fewer than 3: no filtering)
+            for (bool changed = np >= 3; changed && np >= 3;) {
+                changed = false;
+                for (int a = 0; a < np && np >= 3; ++a) {
+                    const int b = (a + 1) % np, c = (a + 2) % np;
+                    if (cross3(pu[a], pv[a], pu[b], pv[b], pu[c], pv[c]) <= margin) {
+                        for (int r = b; r + 1 < np; ++r) {
+                            pu[r] = pu[r + 1];
+                            pv[r] = pv[r + 1];
+                        }
+                        --np;
+                        changed = true;
+                    }
+                }
             }
-            for (int a = 0; a < 8; ++a) {
+            for (int a = 0; a < kDirs; ++a) {
                 P[a] = a < np ? pu[a] : 0.0;
-                P[8 + a] = a < np ? pv[a] : 0.0;
+                P[kDirs + a] = a < np ? pv[a] : 0.0;
             }
-            P[16] = margin;
-            P[17] = convex ? (double)np : 0.0;
+            P[2 * kDirs] = margin;
+            P[2 * kDirs + 1] = np >= 3 ? (double)np : 0.0;
         }
     }
 }
@@ -346,19 +369,19 @@ __global__ void __launch_bounds__(kTileThreads) k_hull_filter(
     const double* __restrict__ poly, uint32_t* __restrict__ surv_cnt, double* __restrict__ gu,
     double* __restrict__ gv, uint32_t* __restrict__ gi)
 {
-    __shared__ double P[18];
+    __shared__ double P[kPolyWords];
     __shared__ uint32_t lcount, lbase;
     const uint32_t K = small[4];
     const uint32_t T = small[6];
     for (uint32_t t = blockIdx.x; t < T; t += gridDim.x) {
         const uint32_t k = cluster_of_tile(tile_off, K, t);
-        if (threadIdx.x < 18) P[threadIdx.x] = poly[18 * (size_t)k + threadIdx.x];
+        if (threadIdx.x < kPolyWords) P[threadIdx.x] = poly[kPolyWords * (size_t)k + threadIdx.x];
         if (threadIdx.x == 0) lcount = 0;
         __syncthreads();
         const ClusterFrame f = cluster_frame(k, off, X, Y, Z, plane, in_off, in_idx);
         const uint32_t j0 = (t - tile_off[k]) * kHullTile;
-        const int np = (int)P[17];
-        const double mg = P[16];
+        const int np = (int)P[kPolyWords - 1];
+        const double mg = P[kPolyWords - 2];
         double su[kTileItems], sv[kTileItems];
         uint32_t sj[kTileItems], slot[kTileItems];
         int ns = 0;
@@ -374,7 +397,7 @@ __global__ void __launch_bounds__(kTileThreads) k_hull_filter(
             bool inside = np >= 3;
             for (int a = 0; inside && a < np; ++a) {
                 const int b = (a + 1 == np) ? 0 : a + 1;
-                inside = cross3(P[a], P[8 + a], P[b], P[8 + b], pu, pv) > mg;
+                inside = cross3(P[a], P[kDirs + a], P[b], P[kDirs + b], pu, pv) > mg;
             }
             if (!inside) {
                 su[ns] = pu;
@@ -456,21 +479,44 @@ __device__ __forceinline__ void chain_level1(const double* U, const double* V, u
     if (lane == kWave - 1) offs[kWave] = inc;
 }
 
-// level 2 for window w (called by one lane per window); returns its length
+// level 2 for window w (called by one lane per window); returns its length.
+// As in level 3 below, the two top stack entries stay in registers and the
+// next point is fetched one step ahead.
 template <typename S>
 __device__ __forceinline__ uint32_t chain_level2(const double* U, const double* V, S* seq, const uint32_t* offs,
                                                  uint32_t w)
 {
     const uint32_t a0 = offs[w * (kWave / kChainL2)], a1 = offs[(w + 1) * (kWave / kChainL2)];
     uint32_t h = 0;
+    double au = 0.0, av = 0.0, bu = 0.0, bv = 0.0;   // seq[a0 + h - 2], seq[a0 + h - 1]
+    uint32_t inext = a0 < a1 ? (uint32_t)seq[a0] : 0u;
+    double nu = a0 < a1 ? U[inext] : 0.0, nv = a0 < a1 ? V[inext] : 0.0;
     for (uint32_t j = a0; j < a1; ++j) {
-        const uint32_t i = seq[j];
-        while (h >= 2) {
-            const uint32_t a = seq[a0 + h - 2], b = seq[a0 + h - 1];
-            if (cross3(U[a], V[a], U[b], V[b], U[i], V[i]) < 0.0) --h;
-            else break;
+        const uint32_t i = inext;
+        const double iu = nu, iv = nv;
+        if (j + 1 < a1) {
+            inext = seq[j + 1];   // read before this step's store (which lands at or below j)
+            nu = U[inext];
+            nv = V[inext];
         }
-        seq[a0 + h++] = (S)i;   // the stack never runs ahead of the read position
+        while (h >= 2 && cross3(au, av, bu, bv, iu, iv) < 0.0) {
+            --h;
+            bu = au;
+            bv = av;
+            if (h >= 2) {
+                const uint32_t a = seq[a0 + h - 2];
+                au = U[a];
+                av = V[a];
+            }
+        }
+        seq[a0 + h] = (S)i;   // the stack never runs ahead of the read position
+        if (h >= 1) {
+            au = bu;
+            av = bv;
+        }
+        bu = iu;
+        bv = iv;
+        ++h;
     }
     return h;
 }
@@ -663,6 +709,7 @@ __global__ void __launch_bounds__(kChainBlock) k_hull_chain(
     __shared__ uint32_t offs_lo[kWave + 1], offs_up[kWave + 1];
     __shared__ uint32_t len2_lo[kChainL2], len2_up[kChainL2];
     __shared__ uint32_t hlo, hup;
+    __shared__ double red[kChainBlock / kWave];
     const uint32_t K = small[4];
     const uint32_t T = small[6];
     for (uint32_t k = blockIdx.x; k < K; k += gridDim.x) {
@@ -713,25 +760,30 @@ __global__ void __launch_bounds__(kChainBlock) k_hull_chain(
             if (threadIdx.x == 0) hlo = chain_level3(su, sv, seq_lo, offs_lo, len2_lo, st_lo);
             if (threadIdx.x == kWave) hup = chain_level3(su, sv, seq_up, offs_up, len2_up, st_up);
             __syncthreads();
-            if (threadIdx.x == 0) {
-                // hull = lower chain, then the upper chain without its end points
-                // (they are the lower chain's last and first points)
-                uint32_t h = hlo;
-                for (uint32_t q = 1; q + 1 < hup; ++q) st_lo[h++] = st_up[q];
-                double s = 0.0;
-                if (h >= 3) {
-                    for (uint32_t q = 0; q < h; ++q) {
-                        const uint32_t p0 = st_lo[q], p1 = st_lo[q + 1 == h ? 0 : q + 1];
-                        s = s + (su[p0] * sv[p1] - su[p1] * sv[p0]);
-                    }
+            // hull = lower chain, then the upper chain without its end points
+            // (they are the lower chain's last and first points); the
+            // vertices and the shoelace terms are taken in parallel
+            {
+                const uint32_t hl = hlo, hu = hup;
+                const uint32_t h = hl + (hu >= 2 ? hu - 2 : 0u);
+                auto vertex = [&](uint32_t q) -> uint32_t { return q < hl ? st_lo[q] : st_up[q - hl + 1]; };
+                double term = 0.0;
+                for (uint32_t q = threadIdx.x; q < h; q += kChainBlock) {
+                    const uint32_t p0 = vertex(q), p1 = vertex(q + 1 == h ? 0u : q + 1);
+                    term += su[p0] * sv[p1] - su[p1] * sv[p0];
+                    hull_tmp[ib + k + q] = in_idx[ib + si[p0]];   // vertex indices
                 }
-                area_out[k] = h >= 3 ? 0.5 * s : 0.0;
-                hull_cnt[k] = h;
-                hlo = h;
+#pragma unroll
+                for (int dd = kWave / 2; dd >= 1; dd >>= 1) term += __shfl_xor(term, dd, kWave);
+                if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = term;
+                __syncthreads();
+                if (threadIdx.x == 0) {
+                    double tot = 0.0;
+                    for (int w2 = 0; w2 < kChainBlock / kWave; ++w2) tot += red[w2];
+                    area_out[k] = h >= 3 ? 0.5 * tot : 0.0;
+                    hull_cnt[k] = h;
+                }
             }
-            __syncthreads();
-            // vertex indices, one per thread (each needs a load of its own)
-            for (uint32_t q = threadIdx.x; q < hlo; q += kChainBlock) hull_tmp[ib + k + q] = in_idx[ib + si[st_lo[q]]];
         } else {
             // bitonic network in global memory; partners beyond ns are +infinity
             uint32_t N = 1;

@@ -576,9 +576,9 @@ WorkLayout work_layout(void* base, uint32_t k_cap, uint32_t n_cap, uint32_t n_hy
     w.hull_i = (uint32_t*)take(((size_t)n_cap + 1) * sizeof(uint32_t));
     w.hull_tile_off = (uint32_t*)take(((size_t)k_cap + 2) * sizeof(uint32_t));
     const size_t ht = hull_tiles_bound(k_cap, n_cap);
-    w.ext_v = (double*)take(ht * 8 * sizeof(double));
-    w.ext_i = (uint32_t*)take(ht * 8 * sizeof(uint32_t));
-    w.poly = (double*)take((size_t)k_cap * 18 * sizeof(double) + 8);
+    w.ext_v = (double*)take(ht * kHullDirs * sizeof(double));
+    w.ext_i = (uint32_t*)take(ht * kHullDirs * sizeof(uint32_t));
+    w.poly = (double*)take((size_t)k_cap * (2 * kHullDirs + 2) * sizeof(double) + 8);
     w.surv_cnt = (uint32_t*)take(((size_t)k_cap + 1) * sizeof(uint32_t));
     w.small = (uint32_t*)take(64 * sizeof(uint32_t));
     w.bytes = o;
