@@ -233,7 +233,8 @@ def main() -> int:
     ach = evals / (count_ms * 1e-3) / 1e9
     roof = {"bound": "alu", "achieved": ach, "peak": COUNT_PEAK_GEVAL, "unit": "Geval/s",
             "frac": ach / COUNT_PEAK_GEVAL, "traffic": _traffic(),
-            "kernel": "inlier counting: k_count_small (a wave per cluster of <= 1024 points) + k_count (tiles)",
+            "kernel": "inlier counting: k_count_small (a wave per cluster of <= %d points) + k_count (tiles)"
+                      % vm.get_count_config()["wave_max_points"],
             "work_per_launch": f"{n_pts} points x {H} hypotheses",
             "peak_derivation": "256 CU x 64 lanes x 2.4 GHz / 4 VALU instructions per point-plane test"}
 

@@ -238,7 +238,7 @@ typedef struct {
                                    split into chunks so that there are about chunk_mult work items
                                    per workgroup (per wave), 1..16; default 2 */
     uint32_t wave_max_points;   /* clusters of at most this many points are counted by one wave
-                                   each, 0..1024 (0: all tiled); default 1024 */
+                                   each, 0..1024 (0: all tiled); default 256 */
     uint32_t plane_max_points;  /* of those, clusters of at most this many points put the lanes
                                    over hypotheses instead of points, 0..min(256, wave_max_points);
                                    default 256 */

@@ -282,10 +282,20 @@ __device__ __forceinline__ void count_by_planes(const float4* __restrict__ hk, u
                                                 const float* __restrict__ Z, float eps, int32_t* __restrict__ ck,
                                                 int lane)
 {
-    for (uint32_t hb = h0; hb < h1; hb += kWave) {
-        const bool has = hb + (uint32_t)lane < h1;
-        const float4 pl = has ? hk[hb + lane] : make_float4(0.f, 0.f, 0.f, 0.f);
-        uint32_t c = 0;
+    // four 64-plane batches at a time: their plane loads are issued
+    // together and each point is loaded once for all four
+    constexpr int kB = 4;
+    for (uint32_t hb = h0; hb < h1; hb += kB * kWave) {
+        float4 pl[kB];
+        bool has[kB];
+        uint32_t c[kB];
+#pragma unroll
+        for (int b = 0; b < kB; ++b) {
+            const uint32_t h = hb + (uint32_t)(b * kWave + lane);
+            has[b] = h < h1;
+            pl[b] = has[b] ? hk[h] : make_float4(0.f, 0.f, 0.f, 0.f);
+            c[b] = 0;
+        }
         uint32_t j = 0;
         for (; j + 16 <= n; j += 16) {
             float x[16], y[16], z[16];
@@ -296,16 +306,25 @@ __device__ __forceinline__ void count_by_planes(const float4* __restrict__ hk, u
                 z[q] = Z[j + q];
             }
 #pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                const float dd = fmaf(pl.z, z[q], fmaf(pl.y, y[q], fmaf(pl.x, x[q], pl.w)));
-                c += fabsf(dd) < eps ? 1u : 0u;   // a degenerate (NaN) plane never passes
+            for (int b = 0; b < kB; ++b) {
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    const float dd = fmaf(pl[b].z, z[q], fmaf(pl[b].y, y[q], fmaf(pl[b].x, x[q], pl[b].w)));
+                    c[b] += fabsf(dd) < eps ? 1u : 0u;   // a degenerate (NaN) plane never passes
+                }
             }
         }
         for (; j < n; ++j) {
-            const float dd = fmaf(pl.z, Z[j], fmaf(pl.y, Y[j], fmaf(pl.x, X[j], pl.w)));
-            c += fabsf(dd) < eps ? 1u : 0u;
+            const float x = X[j], y = Y[j], z = Z[j];
+#pragma unroll
+            for (int b = 0; b < kB; ++b) {
+                const float dd = fmaf(pl[b].z, z, fmaf(pl[b].y, y, fmaf(pl[b].x, x, pl[b].w)));
+                c[b] += fabsf(dd) < eps ? 1u : 0u;
+            }
         }
-        if (has) ck[hb + lane] = (int32_t)c;
+#pragma unroll
+        for (int b = 0; b < kB; ++b)
+            if (has[b]) ck[hb + (uint32_t)(b * kWave + lane)] = (int32_t)c[b];
     }
 }
 
@@ -595,7 +614,7 @@ vm_count_config count_config_default()
     vm_count_config c;
     c.count_grid = 4096;
     c.chunk_mult = 2;
-    c.wave_max_points = kWaveMaxPts;
+    c.wave_max_points = kPlaneMaxPts;   // larger clusters: the tiled kernel splits their hypotheses
     c.plane_max_points = kPlaneMaxPts;
     return c;
 }
