@@ -71,7 +71,16 @@ __global__ void __launch_bounds__(kBlock) k_hypotheses(const uint32_t* __restric
     const uint64_t total = (uint64_t)K * H;
     for (uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
          idx += (uint64_t)gridDim.x * blockDim.x) {
-        const uint32_t k = (uint32_t)(idx / H), h = (uint32_t)(idx % H);
+        // (32-bit division where the index fits: the 64-bit one is a long
+        // instruction sequence per hypothesis)
+        uint32_t k, h;
+        if (total <= 0xFFFFFFFFull) {
+            k = (uint32_t)idx / H;
+            h = (uint32_t)idx - k * H;
+        } else {
+            k = (uint32_t)(idx / H);
+            h = (uint32_t)(idx % H);
+        }
         const uint32_t base = off[k];
         const uint64_t n = (uint64_t)(off[k + 1] - base);
         // the cluster of each of its point tiles, for the inlier kernels and
@@ -116,7 +125,10 @@ __global__ void __launch_bounds__(kBlock) k_hypotheses(const uint32_t* __restric
                 pl = make_float4((float)nx, (float)ny, (float)nz, (float)d);
             }
         }
-        counts[idx] = 0;
+        // the tiled kernel adds into the counts; the wave kernel stores every
+        // count of its clusters, and clusters of fewer than 3 points have no
+        // valid hypothesis (their counts are never read)
+        if (n > wave_max) counts[idx] = 0;
         hyp[idx] = pl;
     }
 }
