@@ -329,7 +329,9 @@ struct WorkLayout {
     uint32_t* ext_i;        // [hull tiles * kHullDirs]
     double* poly;           // [k_cap * (2 kHullDirs + 2)]
     uint32_t* surv_cnt;     // [k_cap]
-    uint32_t* small;        // [64] device scalars: K, tiles, inliers, large-cluster tiles, K (hull), vertices, hull tiles
+    uint32_t* chain_list;   // [k_cap] clusters for the workgroup hull chain (count in small[7])
+    uint32_t* small;        // [64] device scalars: K, tiles, inliers, large-cluster tiles, K (hull), vertices,
+                            // hull tiles, chain-list length
     size_t bytes;
 };
 WorkLayout work_layout(void* base, uint32_t k_cap, uint32_t n_cap, uint32_t n_hyp);

@@ -161,7 +161,10 @@ __global__ void __launch_bounds__(kBlock) k_hull_validate(const uint32_t* __rest
 {
     __shared__ int bad;
     const uint32_t K = validate_clusters(meta, off, kc, n_cap, status, &bad);
-    if (threadIdx.x == 0) small[4] = K;
+    if (threadIdx.x == 0) {
+        small[4] = K;
+        small[7] = 0;   // chain list
+    }
 }
 
 __global__ void __launch_bounds__(kBlock) k_hull_tiles(const uint32_t* __restrict__ small,
@@ -203,6 +206,7 @@ __global__ void __launch_bounds__(kOneBlockThreads) k_hull_prepare(
     if (threadIdx.x == 0) {
         small[4] = K;
         small[6] = total[0];
+        small[7] = 0;   // chain list
     }
 }
 
@@ -572,7 +576,8 @@ __device__ __forceinline__ uint32_t chain_level3(const double* U, const double* 
 // u, then v, then inlier position), then one lane runs the lower and the
 // upper chain; the result is the same as the workgroup path's.
 __global__ void __launch_bounds__(kBlock) k_hull_small(
-    const uint32_t* __restrict__ small, const uint32_t* __restrict__ tile_off, const uint32_t* __restrict__ off,
+    uint32_t* __restrict__ small, uint32_t* __restrict__ chain_list, const uint32_t* __restrict__ tile_off,
+    const uint32_t* __restrict__ off,
     const float* __restrict__ X, const float* __restrict__ Y, const float* __restrict__ Z,
     const float4* __restrict__ plane, const int32_t* __restrict__ best, uint32_t in_cap,
     const uint32_t* __restrict__ in_off, const uint32_t* __restrict__ in_idx, const uint32_t* __restrict__ surv_cnt,
@@ -597,14 +602,23 @@ __global__ void __launch_bounds__(kBlock) k_hull_small(
         const uint32_t ib = in_off[k];
         if (tiled) {
             ns = surv_cnt[k];
-            if (ns > (uint32_t)kWave) continue;   // the workgroup path
+            if (ns > (uint32_t)kWave) {   // the workgroup path takes it from the list
+                if (lane == 0) chain_list[atomicAdd(&small[7], 1u)] = k;
+                continue;
+            }
             if ((uint32_t)lane < ns) {
                 u = gu[ib + lane];
                 v = gv[ib + lane];
                 i = gi[ib + lane];
             }
         } else {
-            if (!cluster_ok(k, off, best, in_off, in_idx, in_cap)) continue;   // no polygon
+            if (!cluster_ok(k, off, best, in_off, in_idx, in_cap)) {   // no polygon
+                if (lane == 0) {
+                    hull_cnt[k] = 0;
+                    area_out[k] = 0.0;
+                }
+                continue;
+            }
             ns = in_off[k + 1] - ib;
             const ClusterFrame f = cluster_frame(k, off, X, Y, Z, plane, in_off, in_idx);
             if ((uint32_t)lane < ns) {
@@ -691,8 +705,7 @@ __global__ void __launch_bounds__(kBlock) k_hull_small(
 }
 
 __global__ void __launch_bounds__(kChainBlock) k_hull_chain(
-    const uint32_t* __restrict__ small, const uint32_t* __restrict__ tile_off, const uint32_t* __restrict__ off,
-    const int32_t* __restrict__ best, uint32_t in_cap, const uint32_t* __restrict__ in_off,
+    const uint32_t* __restrict__ small, const uint32_t* __restrict__ chain_list, const uint32_t* __restrict__ in_off,
     const uint32_t* __restrict__ in_idx, const uint32_t* __restrict__ surv_cnt, double* __restrict__ gu,
     double* __restrict__ gv, uint32_t* __restrict__ gi, uint32_t* __restrict__ hull_cnt,
     uint32_t* __restrict__ hull_tmp, double* __restrict__ area_out)
@@ -710,20 +723,12 @@ __global__ void __launch_bounds__(kChainBlock) k_hull_chain(
     __shared__ uint32_t len2_lo[kChainL2], len2_up[kChainL2];
     __shared__ uint32_t hlo, hup;
     __shared__ double red[kChainBlock / kWave];
-    const uint32_t K = small[4];
-    const uint32_t T = small[6];
-    for (uint32_t k = blockIdx.x; k < K; k += gridDim.x) {
-        if (tile_off[k] == tiles_end(tile_off, k, K, T)) {
-            // no tiles: no polygon, or at most one wave of inliers (k_hull_small)
-            if (threadIdx.x == 0 && !cluster_ok(k, off, best, in_off, in_idx, in_cap)) {
-                hull_cnt[k] = 0;
-                area_out[k] = 0.0;
-            }
-            continue;
-        }
+    // the clusters with more than one wave of survivors, listed by k_hull_small
+    const uint32_t nc = small[7];
+    for (uint32_t c = blockIdx.x; c < nc; c += gridDim.x) {
+        const uint32_t k = chain_list[c];
         const uint32_t ib = in_off[k];
         const uint32_t ns = surv_cnt[k];
-        if (ns <= (uint32_t)kWave) continue;   // one wave of survivors: k_hull_small
         if (ns <= (uint32_t)kLdsCap) {
             uint32_t N = 1;
             while (N < ns) N <<= 1;
@@ -925,13 +930,13 @@ vm_status hulls(const vm_clusters& cl, const vm_planes& planes, const vm_hulls_o
     k_hull_filter<<<tgrid, kTileThreads, 0, s>>>(w.small, w.hull_tile_off, cl.d_off, cl.d_x, cl.d_y, cl.d_z, pl,
                                                  planes.d_in_off, planes.d_in_idx, w.poly, w.surv_cnt, w.hull_u,
                                                  w.hull_v, w.hull_i);
-    k_hull_small<<<kSmallGrid, kBlock, 0, s>>>(w.small, w.hull_tile_off, cl.d_off, cl.d_x, cl.d_y, cl.d_z, pl,
+    k_hull_small<<<kSmallGrid, kBlock, 0, s>>>(w.small, w.chain_list, w.hull_tile_off, cl.d_off, cl.d_x, cl.d_y,
+                                              cl.d_z, pl,
                                               planes.d_best_h, planes.in_cap, planes.d_in_off, planes.d_in_idx,
                                               w.surv_cnt, w.hull_u, w.hull_v, w.hull_i, w.hull_cnt, w.hull_tmp,
                                               out.d_area);
-    k_hull_chain<<<cgrid, kChainBlock, 0, s>>>(w.small, w.hull_tile_off, cl.d_off, planes.d_best_h, planes.in_cap,
-                                               planes.d_in_off, planes.d_in_idx, w.surv_cnt, w.hull_u, w.hull_v, w.hull_i, w.hull_cnt, w.hull_tmp,
-                                               out.d_area);
+    k_hull_chain<<<cgrid, kChainBlock, 0, s>>>(w.small, w.chain_list, planes.d_in_off, planes.d_in_idx, w.surv_cnt,
+                                               w.hull_u, w.hull_v, w.hull_i, w.hull_cnt, w.hull_tmp, out.d_area);
     VM_HIP(hipGetLastError());
     VM_HIP(scan_exclusive_dev(w.hull_cnt, w.hull_off, w.small + 4, kc, w.small + 5, w.blk, s));
     k_hull_pack<<<kgrid, kBlock, 0, s>>>(w.small, cl.d_off, cl.d_x, cl.d_y, cl.d_z, pl, planes.d_in_off, w.hull_cnt,

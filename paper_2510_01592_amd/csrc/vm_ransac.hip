@@ -611,6 +611,7 @@ WorkLayout work_layout(void* base, uint32_t k_cap, uint32_t n_cap, uint32_t n_hy
     w.ext_i = (uint32_t*)take(ht * kHullDirs * sizeof(uint32_t));
     w.poly = (double*)take((size_t)k_cap * (2 * kHullDirs + 2) * sizeof(double) + 8);
     w.surv_cnt = (uint32_t*)take(((size_t)k_cap + 1) * sizeof(uint32_t));
+    w.chain_list = (uint32_t*)take(((size_t)k_cap + 1) * sizeof(uint32_t));
     w.small = (uint32_t*)take(64 * sizeof(uint32_t));
     w.bytes = o;
     return w;
