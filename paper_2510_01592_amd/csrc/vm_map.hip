@@ -104,7 +104,11 @@ constexpr uint32_t kBucketBlocks = 1024;  // partition workgroups per batch (at 
 constexpr uint32_t kBucketAvg = 512;      // target points per bucket
 constexpr uint32_t kBucketMaxLog2 = 12;   // at most 4096 buckets (LDS counters)
 constexpr uint32_t kBucketChunk = 1024;   // points aggregated per LDS table fill
-constexpr uint32_t kBucketTable = 2048;   // LDS table slots (load at most 1/2)
+constexpr uint32_t kBucketTableLog2 = 10;
+constexpr uint32_t kBucketTable = 1u << kBucketTableLog2;   // LDS table slots: 20 KB, so eight workgroups
+                                                             // fit on a CU; a bucket averages kBucketAvg
+                                                             // points, so the table is about half full
+static_assert(kBucketTable >= kBucketChunk, "a chunk's distinct keys always fit: every probe ends");
 
 __device__ __forceinline__ uint32_t bucket_of(uint32_t key, uint32_t lb)
 {
@@ -115,7 +119,7 @@ __device__ __forceinline__ uint32_t bucket_of(uint32_t key, uint32_t lb)
 __device__ __forceinline__ uint32_t table_slot(uint32_t key)
 {
     // independent of the bucket bits: a different multiplier
-    return (key * 0xCC9E2D51u) >> (32 - 11);   // kBucketTable = 2^11
+    return (key * 0xCC9E2D51u) >> (32 - kBucketTableLog2);
 }
 
 __global__ void __launch_bounds__(kBlock) k_vox_bucket(const float* __restrict__ xyz, uint32_t n, Pose pose, Geom g,
