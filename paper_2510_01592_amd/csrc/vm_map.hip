@@ -306,11 +306,29 @@ __global__ void __launch_bounds__(kBlock) k_compact(const uint32_t* __restrict__
     for (uint32_t w = blockIdx.x * blockDim.x + threadIdx.x; w < nwords; w += gridDim.x * blockDim.x) {
         uint32_t b = bits[w];
         uint32_t r = wrank[w];
-        while (b) {
-            const uint32_t j = __ffs(b) - 1;
+        // the word's keys go to consecutive entries: single stores up to a
+        // 16-byte boundary, then four keys per store, then the rest
+        for (; b && (r & 3u); b &= b - 1, ++r) {
             csize[r] = 0u;
-            occ_key[r++] = (w << 5) | j;
+            occ_key[r] = (w << 5) | (uint32_t)(__ffs(b) - 1);
+        }
+        while (__popc(b) >= 4) {
+            uint4 k;
+            k.x = (w << 5) | (uint32_t)(__ffs(b) - 1);
             b &= b - 1;
+            k.y = (w << 5) | (uint32_t)(__ffs(b) - 1);
+            b &= b - 1;
+            k.z = (w << 5) | (uint32_t)(__ffs(b) - 1);
+            b &= b - 1;
+            k.w = (w << 5) | (uint32_t)(__ffs(b) - 1);
+            b &= b - 1;
+            *reinterpret_cast<uint4*>(csize + r) = make_uint4(0u, 0u, 0u, 0u);
+            *reinterpret_cast<uint4*>(occ_key + r) = k;
+            r += 4;
+        }
+        for (; b; b &= b - 1, ++r) {
+            csize[r] = 0u;
+            occ_key[r] = (w << 5) | (uint32_t)(__ffs(b) - 1);
         }
     }
 }
