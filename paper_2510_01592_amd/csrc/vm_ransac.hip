@@ -508,70 +508,113 @@ __device__ __forceinline__ bool inlier_test(const float4 pl, float x, float y, f
     return fabsf(fmaf(pl.z, z, fmaf(pl.y, y, fmaf(pl.x, x, pl.w)))) < eps;
 }
 
-// inlier flags of the winning plane, over the same tiles
-__global__ void __launch_bounds__(kCountBlock) k_inlier_flags(const uint32_t* __restrict__ small,
-                                                              const uint32_t* __restrict__ tile_off, const uint32_t* __restrict__ tile_k,
+// (c) the inlier lists of the winning planes, over the same point tiles, in
+// three launches: inliers per tile; one workgroup's scan of the tile counts
+// (which also gives each cluster's list offset); the lists, each workgroup
+// placing its tile's inliers in point order with a block scan.
+__global__ void __launch_bounds__(kCountBlock) k_inlier_count(const uint32_t* __restrict__ small,
+                                                              const uint32_t* __restrict__ tile_off,
+                                                              const uint32_t* __restrict__ tile_k,
                                                               const uint32_t* __restrict__ off,
                                                               const float* __restrict__ X, const float* __restrict__ Y,
                                                               const float* __restrict__ Z, float eps,
                                                               const int32_t* __restrict__ best,
                                                               const float4* __restrict__ plane,
-                                                              uint32_t* __restrict__ flags)
+                                                              uint32_t* __restrict__ tile_cnt)
 {
+    __shared__ uint32_t wsum[kCountBlock / kWave];
     const uint32_t T = small[1];
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     for (uint32_t t = blockIdx.x; t < T; t += gridDim.x) {
         const uint32_t k = tile_k[t];
         const uint32_t p0 = off[k] + (t - tile_off[k]) * kTile;
         const uint32_t pend = min(p0 + kTile, off[k + 1]);
-        const bool has = best[k] >= 0;
-        const float4 pl = plane[k];
-        for (uint32_t i = p0 + threadIdx.x; i < pend; i += kCountBlock)
-            flags[i] = (has && inlier_test(pl, X[i], Y[i], Z[i], eps)) ? 1u : 0u;
+        uint32_t c = 0;
+        if (best[k] >= 0) {
+            const float4 pl = plane[k];
+            for (uint32_t i = p0 + threadIdx.x; i < pend; i += kCountBlock) c += inlier_test(pl, X[i], Y[i], Z[i], eps);
+        }
+#pragma unroll
+        for (int d = kWave / 2; d >= 1; d >>= 1) c += __shfl_xor(c, d, kWave);
+        if (lane == 0) wsum[wave] = c;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t tot = 0;
+#pragma unroll
+            for (int w = 0; w < kCountBlock / kWave; ++w) tot += wsum[w];
+            tile_cnt[t] = tot;
+        }
+        __syncthreads();   // wsum is reused by the next tile
     }
 }
 
+__global__ void __launch_bounds__(kOneBlockThreads) k_inlier_scan(uint32_t* __restrict__ small,
+                                                                  const uint32_t* __restrict__ tile_off,
+                                                                  uint32_t* __restrict__ tile_cnt,
+                                                                  uint32_t* __restrict__ in_off)
+{
+    const uint32_t K = small[0], T = small[1];
+    uint32_t total[1];
+    one_block_scan<kOneBlockThreads, 4, 1>(
+        T, [&](uint32_t t, uint32_t(&v)[1]) { v[0] = tile_cnt[t]; },
+        [&](uint32_t t, const uint32_t(&e)[1]) { tile_cnt[t] = e[0]; }, total);
+    __syncthreads();   // the prefixes other threads wrote
+    // a cluster's list starts at the prefix of its first tile (a cluster
+    // without points has no tile: the next cluster's start, or the total)
+    for (uint32_t k = threadIdx.x; k <= K; k += blockDim.x)
+        in_off[k] = (k < K && tile_off[k] < T) ? tile_cnt[tile_off[k]] : total[0];
+    if (threadIdx.x == 0) small[2] = total[0];
+}
+
 __global__ void __launch_bounds__(kCountBlock) k_inlier_write(const uint32_t* __restrict__ small,
-                                                              const uint32_t* __restrict__ tile_off, const uint32_t* __restrict__ tile_k,
+                                                              const uint32_t* __restrict__ tile_off,
+                                                              const uint32_t* __restrict__ tile_k,
                                                               const uint32_t* __restrict__ off,
                                                               const float* __restrict__ X, const float* __restrict__ Y,
                                                               const float* __restrict__ Z, float eps,
                                                               const int32_t* __restrict__ best,
                                                               const float4* __restrict__ plane,
-                                                              const uint32_t* __restrict__ pos, uint32_t in_cap,
+                                                              const uint32_t* __restrict__ tile_pre, uint32_t in_cap,
                                                               uint32_t* __restrict__ in_idx, uint32_t* __restrict__ status)
 {
+    static_assert(kCountBlock * kPtsPerLane == kTile, "a thread takes kPtsPerLane consecutive points of a tile");
+    __shared__ uint32_t wsum[kCountBlock / kWave];
     const uint32_t T = small[1];
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     bool over = false;
     for (uint32_t t = blockIdx.x; t < T; t += gridDim.x) {
         const uint32_t k = tile_k[t];
+        if (best[k] < 0) continue;   // workgroup-uniform
         const uint32_t base = off[k];
         const uint32_t p0 = base + (t - tile_off[k]) * kTile;
         const uint32_t pend = min(p0 + kTile, off[k + 1]);
-        if (best[k] < 0) continue;
         const float4 pl = plane[k];
-        for (uint32_t i = p0 + threadIdx.x; i < pend; i += kCountBlock) {
-            if (inlier_test(pl, X[i], Y[i], Z[i], eps)) {
-                const uint32_t p = pos[i];
-                if (p < in_cap) in_idx[p] = i - base;
-                else over = true;
-            }
+        const uint32_t q0 = p0 + threadIdx.x * kPtsPerLane;
+        uint32_t m = 0;
+#pragma unroll
+        for (int j = 0; j < kPtsPerLane; ++j) {
+            const uint32_t i = q0 + (uint32_t)j;
+            if (i < pend && inlier_test(pl, X[i], Y[i], Z[i], eps)) m |= 1u << j;
         }
+        const uint32_t c = (uint32_t)__popc(m);
+        uint32_t inc = c;
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+            const uint32_t o = __shfl_up(inc, d, kWave);
+            if (lane >= d) inc += o;
+        }
+        if (lane == kWave - 1) wsum[wave] = inc;
+        __syncthreads();
+        uint32_t p = tile_pre[t] + inc - c;
+#pragma unroll
+        for (int w = 0; w < kCountBlock / kWave; ++w) p += (w < wave) ? wsum[w] : 0u;
+        for (; m; m &= m - 1, ++p) {
+            if (p < in_cap) in_idx[p] = q0 + (uint32_t)(__ffs(m) - 1) - base;
+            else over = true;
+        }
+        __syncthreads();   // wsum is reused by the next tile
     }
     if (over) atomicOr(status, (uint32_t)VM_FLAG_INLIERS_CAP);
-}
-
-__global__ void __launch_bounds__(kBlock) k_inlier_off(const uint32_t* __restrict__ small,
-                                                       const uint32_t* __restrict__ off,
-                                                       const uint32_t* __restrict__ pos,
-                                                       const uint32_t* __restrict__ meta, uint32_t* __restrict__ in_off)
-{
-    const uint32_t K = small[0];
-    const uint32_t n = meta[1];
-    const uint32_t total = small[2];
-    for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k <= K; k += gridDim.x * blockDim.x) {
-        const uint32_t o = off[k];
-        in_off[k] = o < n ? pos[o] : total;
-    }
 }
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -697,14 +740,13 @@ vm_status ransac_planes(const vm_clusters& cl, const vm_ransac_params& p, const 
                                                                    out.d_best_h, out.d_n_inliers, out.d_counts,
                                                                    (float4*)out.d_hyp);
         const int tgrid = grid_for((uint64_t)cl.n_cap / kTile + kc + 1, 1, 2048);
-        k_inlier_flags<<<tgrid, kCountBlock, 0, s>>>(w.small, w.tile_off, w.tile_k, cl.d_off, cl.d_x, cl.d_y, cl.d_z, p.eps,
-                                                     out.d_best_h, (const float4*)out.d_plane, w.flags);
-        VM_HIP(scan_exclusive_dev(w.flags, w.flags, cl.d_meta + 1, cl.n_cap, w.small + 2, w.blk, s));
+        // w.flags holds the per-tile counts, then their prefixes (tiles <= points)
+        k_inlier_count<<<tgrid, kCountBlock, 0, s>>>(w.small, w.tile_off, w.tile_k, cl.d_off, cl.d_x, cl.d_y, cl.d_z,
+                                                     p.eps, out.d_best_h, (const float4*)out.d_plane, w.flags);
+        k_inlier_scan<<<1, kOneBlockThreads, 0, s>>>(w.small, w.tile_off, w.flags, out.d_in_off);
         k_inlier_write<<<tgrid, kCountBlock, 0, s>>>(w.small, w.tile_off, w.tile_k, cl.d_off, cl.d_x, cl.d_y, cl.d_z, p.eps,
                                                      out.d_best_h, (const float4*)out.d_plane, w.flags, out.in_cap,
                                                      out.d_in_idx, out.d_status);
-        k_inlier_off<<<grid_for((uint64_t)kc + 1), kBlock, 0, s>>>(w.small, cl.d_off, w.flags, cl.d_meta,
-                                                                    out.d_in_off);
         VM_HIP(hipGetLastError());
     }
     return VM_OK;
