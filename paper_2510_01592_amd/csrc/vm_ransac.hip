@@ -739,7 +739,7 @@ vm_status ransac_planes(const vm_clusters& cl, const vm_ransac_params& p, const 
         k_select<<<grid_for((uint64_t)kc * kWave), kBlock, 0, s>>>(w.small, H, w.counts, w.hyp, (float4*)out.d_plane,
                                                                    out.d_best_h, out.d_n_inliers, out.d_counts,
                                                                    (float4*)out.d_hyp);
-        const int tgrid = grid_for((uint64_t)cl.n_cap / kTile + kc + 1, 1, 2048);
+        const int tgrid = grid_for((uint64_t)cl.n_cap / kTile + kc + 1, 1, 8192);   // most tiles are small: many workgroups
         // w.flags holds the per-tile counts, then their prefixes (tiles <= points)
         k_inlier_count<<<tgrid, kCountBlock, 0, s>>>(w.small, w.tile_off, w.tile_k, cl.d_off, cl.d_x, cl.d_y, cl.d_z,
                                                      p.eps, out.d_best_h, (const float4*)out.d_plane, w.flags);
