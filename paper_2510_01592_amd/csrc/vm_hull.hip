@@ -483,37 +483,44 @@ __device__ __forceinline__ void chain_level1(const double* U, const double* V, u
     if (lane == kWave - 1) offs[kWave] = inc;
 }
 
-// level 2 for window w (called by one lane per window); returns its length.
-// As in level 3 below, the two top stack entries stay in registers and the
-// next point is fetched one step ahead.
-template <typename S>
-__device__ __forceinline__ uint32_t chain_level2(const double* U, const double* V, S* seq, const uint32_t* offs,
-                                                 uint32_t w)
+// One thread's chain over the points idx[0..m) (indices into U, V) in that
+// order: a point pops the stack top while it turns right of the top two
+// (strict: only strictly right; otherwise also collinear and repeated
+// points); the kept indices go to out[0..h) and h is returned.  out may be
+// idx itself (a store lands at or below the read position).  The two top
+// entries' coordinates stay in registers, the next point's coordinates and
+// the index after it are loaded a step ahead, so a step waits for one LDS
+// load at most when it does not pop.
+template <bool kStrict, typename S>
+__device__ __forceinline__ uint32_t chain_run(const double* U, const double* V, const S* idx, uint32_t m, S* out)
 {
-    const uint32_t a0 = offs[w * (kWave / kChainL2)], a1 = offs[(w + 1) * (kWave / kChainL2)];
     uint32_t h = 0;
-    double au = 0.0, av = 0.0, bu = 0.0, bv = 0.0;   // seq[a0 + h - 2], seq[a0 + h - 1]
-    uint32_t inext = a0 < a1 ? (uint32_t)seq[a0] : 0u;
-    double nu = a0 < a1 ? U[inext] : 0.0, nv = a0 < a1 ? V[inext] : 0.0;
-    for (uint32_t j = a0; j < a1; ++j) {
-        const uint32_t i = inext;
-        const double iu = nu, iv = nv;
-        if (j + 1 < a1) {
-            inext = seq[j + 1];   // read before this step's store (which lands at or below j)
-            nu = U[inext];
-            nv = V[inext];
+    double au = 0.0, av = 0.0, bu = 0.0, bv = 0.0;   // out[h - 2], out[h - 1]
+    uint32_t i1 = m > 0 ? (uint32_t)idx[0] : 0u;
+    double u1 = m > 0 ? U[i1] : 0.0, v1 = m > 0 ? V[i1] : 0.0;
+    uint32_t i2 = m > 1 ? (uint32_t)idx[1] : 0u;
+    for (uint32_t j = 0; j < m; ++j) {
+        const uint32_t i = i1;
+        const double iu = u1, iv = v1;
+        if (j + 1 < m) {
+            i1 = i2;
+            u1 = U[i1];
+            v1 = V[i1];
         }
-        while (h >= 2 && cross3(au, av, bu, bv, iu, iv) < 0.0) {
+        if (j + 2 < m) i2 = idx[j + 2];
+        while (h >= 2) {
+            const double c = cross3(au, av, bu, bv, iu, iv);
+            if (!(kStrict ? c < 0.0 : c <= 0.0)) break;
             --h;
             bu = au;
             bv = av;
             if (h >= 2) {
-                const uint32_t a = seq[a0 + h - 2];
+                const uint32_t a = out[h - 2];
                 au = U[a];
                 av = V[a];
             }
         }
-        seq[a0 + h] = (S)i;   // the stack never runs ahead of the read position
+        out[h] = (S)i;
         if (h >= 1) {
             au = bu;
             av = bv;
@@ -525,48 +532,28 @@ __device__ __forceinline__ uint32_t chain_level2(const double* U, const double* 
     return h;
 }
 
-// level 3 by one thread.  The coordinates of the two top stack entries stay
-// in registers and the next point is fetched one step ahead, so a step waits
-// on LDS only when it pops.
+// level 2 for window w (called by one lane per window), in place; returns
+// its length
 template <typename S>
-__device__ __forceinline__ uint32_t chain_level3(const double* U, const double* V, const S* seq,
-                                                 const uint32_t* offs, const uint32_t* len2, S* st)
+__device__ __forceinline__ uint32_t chain_level2(const double* U, const double* V, S* seq, const uint32_t* offs,
+                                                 uint32_t w)
 {
-    uint32_t h = 0;
-    double au = 0.0, av = 0.0, bu = 0.0, bv = 0.0;   // st[h - 2], st[h - 1]
+    const uint32_t a0 = offs[w * (kWave / kChainL2)], a1 = offs[(w + 1) * (kWave / kChainL2)];
+    return chain_run<true>(U, V, seq + a0, a1 - a0, seq + a0);
+}
+
+// the level-2 results of all windows, in order, copied to dst by the
+// threads of the workgroup; returns their total
+template <typename S>
+__device__ __forceinline__ uint32_t chain_gather2(const S* seq, const uint32_t* offs, const uint32_t* len2, S* dst)
+{
+    uint32_t pre = 0;
     for (uint32_t w = 0; w < (uint32_t)kChainL2; ++w) {
         const uint32_t a0 = offs[w * (kWave / kChainL2)], m = len2[w];
-        uint32_t inext = m ? (uint32_t)seq[a0] : 0u;
-        double nu = m ? U[inext] : 0.0, nv = m ? V[inext] : 0.0;
-        for (uint32_t j = 0; j < m; ++j) {
-            const uint32_t i = inext;
-            const double iu = nu, iv = nv;
-            if (j + 1 < m) {
-                inext = seq[a0 + j + 1];
-                nu = U[inext];
-                nv = V[inext];
-            }
-            while (h >= 2 && cross3(au, av, bu, bv, iu, iv) <= 0.0) {
-                --h;
-                bu = au;
-                bv = av;
-                if (h >= 2) {
-                    const uint32_t a = st[h - 2];
-                    au = U[a];
-                    av = V[a];
-                }
-            }
-            st[h] = (S)i;
-            if (h >= 1) {
-                au = bu;
-                av = bv;
-            }
-            bu = iu;
-            bv = iv;
-            ++h;
-        }
+        for (uint32_t q = threadIdx.x; q < m; q += blockDim.x) dst[pre + q] = seq[a0 + q];
+        pre += m;
     }
-    return h;
+    return pre;
 }
 
 // Clusters with at most 64 points to chain -- survivors of the filter, or
@@ -732,26 +719,64 @@ __global__ void __launch_bounds__(kChainBlock) k_hull_chain(
         if (ns <= (uint32_t)kLdsCap) {
             uint32_t N = 1;
             while (N < ns) N <<= 1;
-            for (uint32_t t = threadIdx.x; t < N; t += kChainBlock) {
-                if (t < ns) {
-                    su[t] = gu[ib + t];
-                    sv[t] = gv[ib + t];
-                    si[t] = gi[ib + t];
-                } else {
-                    su[t] = INFINITY;
-                    sv[t] = INFINITY;
-                    si[t] = 0xFFFFFFFFu;
-                }
-            }
-            __syncthreads();
-            for (uint32_t size = 2; size <= N; size <<= 1) {
-                for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
-                    for (uint32_t t = threadIdx.x; t < N / 2; t += kChainBlock) {
-                        const uint32_t a = 2 * t - (t & (stride - 1)), b = a + stride;
-                        const bool upw = (a & size) == 0;
-                        if (p2_less(su[b], sv[b], si[b], su[a], sv[a], si[a]) == upw) swap3(su, sv, si, a, b);
+            if (N <= (uint32_t)kChainBlock) {
+                // one point per thread: bitonic stages over distances below 64
+                // are shuffles inside a wave, the others go through LDS
+                const uint32_t t = threadIdx.x;
+                double u = t < ns ? gu[ib + t] : INFINITY, v = t < ns ? gv[ib + t] : INFINITY;
+                uint32_t id = t < ns ? gi[ib + t] : 0xFFFFFFFFu;
+                for (uint32_t size = 2; size <= N; size <<= 1) {
+                    for (uint32_t j = size >> 1; j > 0; j >>= 1) {
+                        double ou, ov;
+                        uint32_t oi;
+                        if (j >= (uint32_t)kWave) {
+                            su[t] = u;
+                            sv[t] = v;
+                            si[t] = id;
+                            __syncthreads();
+                            ou = su[t ^ j];
+                            ov = sv[t ^ j];
+                            oi = si[t ^ j];
+                            __syncthreads();
+                        } else {
+                            ou = __shfl_xor(u, (int)j, kWave);
+                            ov = __shfl_xor(v, (int)j, kWave);
+                            oi = __shfl_xor(id, (int)j, kWave);
+                        }
+                        const bool up = (t & size) == 0, low = (t & j) == 0;
+                        if ((low == up) != p2_less(u, v, id, ou, ov, oi)) {
+                            u = ou;
+                            v = ov;
+                            id = oi;
+                        }
                     }
-                    __syncthreads();
+                }
+                su[t] = u;
+                sv[t] = v;
+                si[t] = id;
+                __syncthreads();
+            } else {
+                for (uint32_t t = threadIdx.x; t < N; t += kChainBlock) {
+                    if (t < ns) {
+                        su[t] = gu[ib + t];
+                        sv[t] = gv[ib + t];
+                        si[t] = gi[ib + t];
+                    } else {
+                        su[t] = INFINITY;
+                        sv[t] = INFINITY;
+                        si[t] = 0xFFFFFFFFu;
+                    }
+                }
+                __syncthreads();
+                for (uint32_t size = 2; size <= N; size <<= 1) {
+                    for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+                        for (uint32_t t = threadIdx.x; t < N / 2; t += kChainBlock) {
+                            const uint32_t a = 2 * t - (t & (stride - 1)), b = a + stride;
+                            const bool upw = (a & size) == 0;
+                            if (p2_less(su[b], sv[b], si[b], su[a], sv[a], si[a]) == upw) swap3(su, sv, si, a, b);
+                        }
+                        __syncthreads();
+                    }
                 }
             }
             // lower chain on wave 0, upper chain on wave 1
@@ -762,8 +787,13 @@ __global__ void __launch_bounds__(kChainBlock) k_hull_chain(
             else if (threadIdx.x >= kWave && threadIdx.x < kWave + kChainL2)
                 len2_up[threadIdx.x - kWave] = chain_level2(su, sv, seq_up, offs_up, threadIdx.x - kWave);
             __syncthreads();
-            if (threadIdx.x == 0) hlo = chain_level3(su, sv, seq_lo, offs_lo, len2_lo, st_lo);
-            if (threadIdx.x == kWave) hup = chain_level3(su, sv, seq_up, offs_up, len2_up, st_up);
+            // level 3: the plain chain over the level-2 results, made contiguous
+            // (the level-1 scratch is free again)
+            const uint32_t l2lo = chain_gather2(seq_lo, offs_lo, len2_lo, tmp_lo);
+            const uint32_t l2up = chain_gather2(seq_up, offs_up, len2_up, tmp_up);
+            __syncthreads();
+            if (threadIdx.x == 0) hlo = chain_run<false>(su, sv, tmp_lo, l2lo, st_lo);
+            if (threadIdx.x == kWave) hup = chain_run<false>(su, sv, tmp_up, l2up, st_up);
             __syncthreads();
             // hull = lower chain, then the upper chain without its end points
             // (they are the lower chain's last and first points); the
