@@ -233,7 +233,7 @@ vm_status vm_ransac_planes(const vm_clusters* cl, const vm_ransac_params* params
  * with). */
 typedef struct {
     uint32_t count_grid;        /* workgroups of the tiled counting kernel: a multiple of 8
-                                   (one per XCD), 8..65536; default 4096 */
+                                   (one per XCD), 8..65536; default 16384 */
     uint32_t chunk_mult;        /* the hypotheses of a point tile (of a wave-counted cluster) are
                                    split into chunks so that there are about chunk_mult work items
                                    per workgroup (per wave), 1..16; default 2 */

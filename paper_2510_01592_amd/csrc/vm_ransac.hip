@@ -668,7 +668,7 @@ vm_count_config g_count_cfg = count_config_default();
 vm_count_config count_config_default()
 {
     vm_count_config c;
-    c.count_grid = 4096;
+    c.count_grid = 16384;
     c.chunk_mult = 2;
     c.wave_max_points = kPlaneMaxPts;   // larger clusters: the tiled kernel splits their hypotheses
     c.plane_max_points = kPlaneMaxPts;

@@ -110,7 +110,7 @@ def test_count_config_set_get_and_validation():
     L = vm.lib()
     vm.set_count_config(None)
     d = vm.get_count_config()
-    assert d == {"count_grid": 4096, "chunk_mult": 2, "wave_max_points": 256, "plane_max_points": 256}
+    assert d == {"count_grid": 16384, "chunk_mult": 2, "wave_max_points": 256, "plane_max_points": 256}
     try:
         vm.set_count_config({"count_grid": 1024, "chunk_mult": 4, "wave_max_points": 512, "plane_max_points": 64})
         assert vm.get_count_config() == {"count_grid": 1024, "chunk_mult": 4, "wave_max_points": 512,

@@ -19,7 +19,7 @@ FRAME = 3
 SIZES = [0, 1, 2, 3, 5, 63, 64, 65, 100, 191, 192, 193, 255, 256, 257, 500, 511, 512, 513, 767, 768, 769,
          1000, 1023, 1024, 1025, 2000, 4095, 4096, 4097, 9000, 17000]
 CONFIGS = [
-    dict(count_grid=4096, chunk_mult=2, wave_max_points=256, plane_max_points=256),    # the defaults
+    dict(count_grid=16384, chunk_mult=2, wave_max_points=256, plane_max_points=256),   # the defaults
     dict(count_grid=4096, chunk_mult=2, wave_max_points=1024, plane_max_points=256),
     dict(count_grid=4096, chunk_mult=2, wave_max_points=0, plane_max_points=0),        # all tiled
     dict(count_grid=4096, chunk_mult=2, wave_max_points=1024, plane_max_points=0),
