@@ -577,7 +577,13 @@ __global__ void __launch_bounds__(kCountBlock) k_inlier_write(const uint32_t* __
                                                               const uint32_t* __restrict__ tile_pre, uint32_t in_cap,
                                                               uint32_t* __restrict__ in_idx, uint32_t* __restrict__ status)
 {
-    static_assert(kCountBlock * kPtsPerLane == kTile, "a thread takes kPtsPerLane consecutive points of a tile");
+    // The tile's tests are made with coalesced loads (consecutive lanes,
+    // consecutive points) and collected as a bit mask in LDS, 64 bits per
+    // wave step by a ballot; then thread w takes mask word w (32 points), a
+    // block scan of the words' counts places their inliers in point order.
+    constexpr uint32_t kWords = kTile / 32;   // 128
+    static_assert(kWords <= kCountBlock, "a thread per mask word");
+    __shared__ uint32_t mask[kWords];
     __shared__ uint32_t wsum[kCountBlock / kWave];
     const uint32_t T = small[1];
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
@@ -589,13 +595,19 @@ __global__ void __launch_bounds__(kCountBlock) k_inlier_write(const uint32_t* __
         const uint32_t p0 = base + (t - tile_off[k]) * kTile;
         const uint32_t pend = min(p0 + kTile, off[k + 1]);
         const float4 pl = plane[k];
-        const uint32_t q0 = p0 + threadIdx.x * kPtsPerLane;
-        uint32_t m = 0;
-#pragma unroll
-        for (int j = 0; j < kPtsPerLane; ++j) {
-            const uint32_t i = q0 + (uint32_t)j;
-            if (i < pend && inlier_test(pl, X[i], Y[i], Z[i], eps)) m |= 1u << j;
+#pragma unroll 4
+        for (uint32_t j0 = 0; j0 < kTile; j0 += kCountBlock) {
+            const uint32_t i = p0 + j0 + threadIdx.x;
+            const bool in = i < pend && inlier_test(pl, X[i], Y[i], Z[i], eps);
+            const uint64_t b = __ballot(in);
+            if (lane == 0) {
+                const uint32_t w = (j0 + (uint32_t)wave * kWave) / 32;
+                mask[w] = (uint32_t)b;
+                mask[w + 1] = (uint32_t)(b >> 32);
+            }
         }
+        __syncthreads();
+        uint32_t m = threadIdx.x < kWords ? mask[threadIdx.x] : 0u;
         const uint32_t c = (uint32_t)__popc(m);
         uint32_t inc = c;
 #pragma unroll
@@ -608,11 +620,12 @@ __global__ void __launch_bounds__(kCountBlock) k_inlier_write(const uint32_t* __
         uint32_t p = tile_pre[t] + inc - c;
 #pragma unroll
         for (int w = 0; w < kCountBlock / kWave; ++w) p += (w < wave) ? wsum[w] : 0u;
+        const uint32_t q0 = p0 + threadIdx.x * 32 - base;   // cluster-local index of the word's first point
         for (; m; m &= m - 1, ++p) {
-            if (p < in_cap) in_idx[p] = q0 + (uint32_t)(__ffs(m) - 1) - base;
+            if (p < in_cap) in_idx[p] = q0 + (uint32_t)(__ffs(m) - 1);
             else over = true;
         }
-        __syncthreads();   // wsum is reused by the next tile
+        __syncthreads();   // mask and wsum are reused by the next tile
     }
     if (over) atomicOr(status, (uint32_t)VM_FLAG_INLIERS_CAP);
 }
