@@ -47,7 +47,12 @@ def test_results_alone_equal_results_in_the_mix():
     robots = [0, 1, 2, 3]
     n_frames = 5
     inputs = {r: _robot_inputs(r, n_frames) for r in robots}
+    # every robot's first frame arrives at once (so frames of different
+    # robots are in flight together however fast they run), the rest over
+    # 50 ms
     arrivals = {r: np.sort(np.random.default_rng(90 + r).uniform(0, 0.05, n_frames)) for r in robots}
+    for r in robots:
+        arrivals[r][0] = 0.0
     note("serve: 4 robots in the mix")
     mix, sch = _run(robots, inputs, arrivals)
     assert len(mix) == len(robots) * n_frames and not sch.rejected
