@@ -29,6 +29,19 @@ constexpr int kMaxHypChunk = 4096;                 // hypotheses per work item (
 constexpr int kHypBatch = 4;                       // planes loaded together
 constexpr uint32_t kXcds = 8;                      // accelerator complex dies (separate L2s)
 
+// The 128-bit product of two 64-bit words from four 32 x 32 -> 64 bit
+// multiply-adds (the high and the low half of one product; computing them
+// as separate 64-bit operations repeats partial products).
+__device__ __forceinline__ void mul_64x64_128(uint64_t a, uint64_t b, uint64_t& hi, uint64_t& lo)
+{
+    const uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32), b0 = (uint32_t)b, b1 = (uint32_t)(b >> 32);
+    const uint64_t p00 = (uint64_t)a0 * b0;
+    const uint64_t t = (uint64_t)a0 * b1 + (p00 >> 32);             // < 2^64
+    const uint64_t t2 = (uint64_t)a1 * b0 + (uint32_t)t;            // < 2^64
+    lo = (t2 << 32) | (uint32_t)p00;
+    hi = (uint64_t)a1 * b1 + (t >> 32) + (t2 >> 32);
+}
+
 __device__ __forceinline__ void philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3, uint64_t k0,
                                               uint64_t k1, uint64_t out[4])
 {
@@ -36,8 +49,9 @@ __device__ __forceinline__ void philox4x64_10(uint64_t c0, uint64_t c1, uint64_t
     const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint64_t hi0 = __umul64hi(M0, c0), lo0 = M0 * c0;
-        const uint64_t hi1 = __umul64hi(M1, c2), lo1 = M1 * c2;
+        uint64_t hi0, lo0, hi1, lo1;
+        mul_64x64_128(M0, c0, hi0, lo0);
+        mul_64x64_128(M1, c2, hi1, lo1);
         const uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
         c0 = n0;
         c1 = lo1;
