@@ -182,6 +182,14 @@ def main() -> int:
 
     lat = {"plain": [], "graph": []}
     with torch.cuda.stream(stream):
+        # one untimed pass over the host frames first (the first copy from a
+        # pinned buffer pays for mapping it)
+        for i, hf in enumerate(host_frames):
+            stage.copy_(hf, non_blocking=True)
+            frame_t.fill_(19000 + i)
+            graph.launch(stream)
+            fetch()
+            stream.synchronize()
         for i in range(args.latency_frames):
             hf = host_frames[i % len(host_frames)]
             for form in ("graph", "plain"):
