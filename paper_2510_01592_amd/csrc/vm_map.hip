@@ -10,6 +10,7 @@
 // dense rank in ascending key order, which the clustering stages use as their
 // index space (4 MB of bits for a 400x400x200 grid).
 #include "vm_common.h"
+#include "vm_tilescan.h"
 
 namespace vm {
 namespace {
@@ -290,13 +291,6 @@ __global__ void __launch_bounds__(kBlock) k_bucket_insert(const uint4* __restric
     }
 }
 
-__global__ void __launch_bounds__(kBlock) k_popc(const uint32_t* __restrict__ bits, uint32_t nwords,
-                                                 uint32_t* __restrict__ out)
-{
-    for (uint32_t w = blockIdx.x * blockDim.x + threadIdx.x; w < nwords; w += gridDim.x * blockDim.x)
-        out[w] = __popc(bits[w]);
-}
-
 // Occupied keys in rank order; the component-size counters of the ranks are
 // cleared on the way (the labelling accumulates into them).
 __global__ void __launch_bounds__(kBlock) k_compact(const uint32_t* __restrict__ bits, uint32_t nwords,
@@ -480,12 +474,31 @@ hipError_t launch_insert(const float* xyz, int64_t n, const Pose& pose, const Ge
     return hipSuccess;
 }
 
+namespace {
+// the occupancy index's scan: the popcount of each word is taken as the
+// scan reads it, and the exclusive prefixes are the word ranks
+struct RankF {
+    const uint32_t* bits;
+    __device__ Vec<1> operator()(uint32_t w) const
+    {
+        Vec<1> x;
+        x.v[0] = (uint32_t)__popc(bits[w]);
+        return x;
+    }
+};
+
+struct RankG {
+    uint32_t* wrank;
+    DevCounters* ctr;
+    __device__ void operator()(uint32_t w, const Vec<1>&, const Vec<1>& pre) const { wrank[w] = pre.v[0]; }
+    __device__ void total(const Vec<1>& t) const { ctr->n_occ = t.v[0]; }
+};
+}   // namespace
+
 hipError_t launch_rank(const Geom& g, const uint32_t* bits, SegBuffers& b, uint32_t /*cap*/, DevCounters* ctr,
                        hipStream_t s)
 {
-    k_popc<<<grid_for(g.nwords), kBlock, 0, s>>>(bits, g.nwords, b.wrank);
-    hipError_t e = scan_exclusive_dev(b.wrank, b.wrank, nullptr, g.nwords, &ctr->n_occ, b.blk, s);
-    if (e != hipSuccess) return e;
+    tile_scan<1>(RankF{bits}, RankG{b.wrank, ctr}, nullptr, g.nwords, reinterpret_cast<Vec<1>*>(b.blk), s);
     k_compact<<<grid_for(g.nwords), kBlock, 0, s>>>(bits, g.nwords, b.wrank, b.occ_key, b.csize);
     return hipGetLastError();
 }
