@@ -316,7 +316,7 @@ struct WorkLayout {
     uint32_t* tile_k;       // [n_cap / tile + k_cap + 1] cluster of each point tile
     uint32_t* tile_off_big;  // the same for the clusters beyond one wave's points
     uint32_t* tile_k_big;
-    uint32_t* flags;        // [n_cap]
+    uint32_t* flags;        // [n_cap + 1] inliers per point tile, then their prefixes
     uint32_t* blk;          // scan partials
     uint32_t* hull_cnt;     // [k_cap + 2]
     uint32_t* hull_off;     // [k_cap + 2]
