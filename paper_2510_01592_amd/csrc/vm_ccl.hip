@@ -227,7 +227,26 @@ __device__ __forceinline__ uint32_t run_ordinal(uint32_t starts, int x)
     return (uint32_t)__popc(starts & ((2u << x) - 1u)) - 1u;
 }
 
-constexpr uint32_t kPairCap = 1024;   // hook pairs buffered per tile (more are united at once)
+// cell of the n-th (0-based) set bit of w (w has more than n set bits):
+// a branch-free binary search over popcounts of halves
+__device__ __forceinline__ uint32_t nth_set_bit(uint32_t w, uint32_t n)
+{
+    uint32_t pos = 0;
+#pragma unroll
+    for (uint32_t h = 16; h; h >>= 1) {
+        const uint32_t c = (uint32_t)__popc(w & ((1u << h) - 1u));
+        const bool up = n >= c;
+        n -= up ? c : 0u;
+        w >>= up ? h : 0u;
+        pos += up ? h : 0u;
+    }
+    return pos;
+}
+
+// Hook pairs buffered per tile (more are united in further rounds).  With
+// the run table the workgroup holds about 22 KB of LDS, so that seven
+// workgroups share a compute unit.
+constexpr uint32_t kPairCap = 768;
 
 __global__ void __launch_bounds__(kBlock) k_ccl_tile(const uint32_t* __restrict__ bits, uint32_t nwords,
                                                      const uint32_t* __restrict__ wrank, Dims d, TileGrid tg,
@@ -237,7 +256,6 @@ __global__ void __launch_bounds__(kBlock) k_ccl_tile(const uint32_t* __restrict_
     __shared__ uint32_t rowrank[kTileRows];
     __shared__ uint32_t members[kTileRuns / 32];
     __shared__ uint32_t par[kTileRuns];
-    __shared__ uint8_t runx[kTileRuns];   // first cell of each run
     __shared__ uint32_t pairs[kPairCap];
     __shared__ uint32_t wtot[kBlock / kWave];
     const uint32_t ntiles = tg.ntx * tg.nty * tg.ntz;
@@ -258,10 +276,7 @@ __global__ void __launch_bounds__(kBlock) k_ccl_tile(const uint32_t* __restrict_
         // one union-find node per run
         {
             uint32_t c = j * kRowRuns;
-            for (uint32_t m = sv; m; m &= m - 1, ++c) {
-                par[c] = c;
-                runx[c] = (uint8_t)(__ffs(m) - 1);
-            }
+            for (uint32_t m = sv; m; m &= m - 1, ++c) par[c] = c;
         }
         // barrier + vote: a tile without occupied cells is skipped by all threads
         if (!__syncthreads_or(v != 0u)) continue;
@@ -348,7 +363,7 @@ __global__ void __launch_bounds__(kBlock) k_ccl_tile(const uint32_t* __restrict_
             const int s0 = __ffs(m) - 1;
             const int e0 = __ffs(ev & ~((1u << s0) - 1u)) - 1;
             const uint32_t rt = par[c];
-            const uint32_t rrow = rt / kRowRuns, rx = runx[rt];
+            const uint32_t rrow = rt / kRowRuns, rx = nth_set_bit(run_starts(rowv[rrow]), rt % kRowRuns);
             const uint32_t rr = rowrank[rrow] + __popc(rowv[rrow] & ((1u << rx) - 1u));
             const uint32_t r = rowrank[j] + __popc(v & ((1u << s0) - 1u));
             // the run's entries: single stores up to a 16-byte boundary, then
@@ -579,6 +594,9 @@ __global__ void __launch_bounds__(kBlock) k_ccl_flatten(const DevCounters* __res
         const uint32_t r = b0 + (uint32_t)lane;
         uint32_t x = r, cs = 0;
         if (r < V) {
+            // only roots receive counts below, and the count is used only
+            // when r is not a root: it can be read before the walk
+            const uint32_t own = csize[r];
             uint32_t p = ld_parent(&parent[r]);
             while (p != x) {
                 x = p;
@@ -588,7 +606,7 @@ __global__ void __launch_bounds__(kBlock) k_ccl_flatten(const DevCounters* __res
             // a tile-local root joined to another tile's component hands its
             // count to the component's root (only roots receive counts, so
             // the count read here is final)
-            if (x != r) cs = csize[r];
+            if (x != r) cs = own;
         }
         // one atomic per distinct root in the wave (a large component has
         // many local roots)
@@ -659,7 +677,8 @@ __global__ void __launch_bounds__(kBlock) k_group_pairs(const DevCounters* __res
                                                         const uint32_t* __restrict__ csize, uint32_t min_cluster,
                                                         const uint32_t* __restrict__ cid_scan,
                                                         const uint32_t* __restrict__ pos_scan,
-                                                        uint32_t* __restrict__ out_cid, uint32_t* __restrict__ out_rank)
+                                                        const uint32_t* __restrict__ occ_key,
+                                                        uint32_t* __restrict__ out_cid, uint32_t* __restrict__ out_key)
 {
     const uint32_t V = ctr->n_occ;
     for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < V; r += gridDim.x * blockDim.x) {
@@ -667,24 +686,23 @@ __global__ void __launch_bounds__(kBlock) k_group_pairs(const DevCounters* __res
         if (csize[root] >= min_cluster) {
             const uint32_t p = pos_scan[r];
             out_cid[p] = cid_scan[root];
-            out_rank[p] = r;
+            out_key[p] = occ_key[r];
         }
     }
 }
 
 // CSR points: key and Eq. (1) mean of each kept voxel, cluster-major
 __global__ void __launch_bounds__(kBlock) k_group_gather(Geom g, Hash h, const DevCounters* __restrict__ ctr,
-                                                         const uint32_t* __restrict__ sorted_rank0,
-                                                         const uint32_t* __restrict__ sorted_rank1,
-                                                         const uint32_t* __restrict__ occ_key,
+                                                         const uint32_t* __restrict__ sorted_key0,
+                                                         const uint32_t* __restrict__ sorted_key1,
                                                          uint32_t* __restrict__ cl_key, float* __restrict__ cl_x,
                                                          float* __restrict__ cl_y, float* __restrict__ cl_z)
 {
-    const uint32_t* __restrict__ sorted_rank = ctr->group_sel ? sorted_rank1 : sorted_rank0;
+    const uint32_t* __restrict__ sorted_key = ctr->group_sel ? sorted_key1 : sorted_key0;
     const uint32_t n = ctr->meta[1];
     const uint32_t nx = (uint32_t)g.dims[0], ny = (uint32_t)g.dims[1];
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const uint32_t k = occ_key[sorted_rank[i]];
+        const uint32_t k = sorted_key[i];
         const uint32_t s = hash_find(h, k);
         float mx = 0.0f, my = 0.0f, mz = 0.0f;
         if (s != kEmpty) {
@@ -764,7 +782,7 @@ hipError_t launch_group(const Geom& g, const Hash& h, SegBuffers& b, uint32_t ca
     Vec<3>* tiles = reinterpret_cast<Vec<3>*>(b.blk);
     tile_scan<3>(f, gg, &ctr->n_occ, cap, tiles, s);
     hipError_t e;
-    k_group_pairs<<<grid, kBlock, 0, s>>>(ctr, b.parent, b.csize, min_cluster, cid, keep, b.sort_k[0],
+    k_group_pairs<<<grid, kBlock, 0, s>>>(ctr, b.parent, b.csize, min_cluster, cid, keep, b.occ_key, b.sort_k[0],
                                           b.sort_v[0]);
     // stable sort by cluster id keeps ascending keys inside each cluster
     const uint32_t kbound = cap / min_cluster + 1;
@@ -772,8 +790,7 @@ hipError_t launch_group(const Geom& g, const Hash& h, SegBuffers& b, uint32_t ca
     if ((e = radix_sort_pairs_dev(b.sort_k, b.sort_v, &ctr->meta[1], cap, bits_needed, &ctr->kmax, b.hist, b.blk,
                                   &ctr->group_sel, s)) != hipSuccess)
         return e;
-    k_group_gather<<<grid, kBlock, 0, s>>>(g, h, ctr, b.sort_v[0], b.sort_v[1], b.occ_key, b.cl_key, b.cl_x, b.cl_y,
-                                           b.cl_z);
+    k_group_gather<<<grid, kBlock, 0, s>>>(g, h, ctr, b.sort_v[0], b.sort_v[1], b.cl_key, b.cl_x, b.cl_y, b.cl_z);
     if (d_labels) k_labels<<<grid, kBlock, 0, s>>>(ctr, b.parent, b.occ_key, d_labels);
     return hipGetLastError();
 }

@@ -101,7 +101,7 @@ struct SegBuffers {
     uint32_t* scan_a;      // [cap] scan scratch
     uint32_t* scan_b;      // [cap]
     uint32_t* sort_k[2];   // [cap] radix keys (cluster id), ping-pong
-    uint32_t* sort_v[2];   // [cap] radix values (rank), ping-pong
+    uint32_t* sort_v[2];   // [cap] radix values (voxel key), ping-pong
     uint32_t* cl_off;      // [cap+1]
     uint32_t* cl_tag;      // [cap]
     uint32_t* cl_key;      // [cap]
