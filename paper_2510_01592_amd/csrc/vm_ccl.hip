@@ -106,6 +106,28 @@ struct TileGrid {
     uint32_t ntx, nty, ntz;
 };
 
+// Workgroups are dealt to the eight XCDs in turn, each with its own L2.  The
+// loop index v (v % 8 names its XCD while the grid is a multiple of 8) is
+// mapped so that every row of tiles along x (which share bitmap, rank and
+// parent lines) is visited on one XCD, and rows go to the XCDs in turn (the
+// map's dense regions stay spread over all of them).  Indices past the last
+// row map to no tile.
+constexpr uint32_t kXcds = 8;
+
+__host__ __device__ inline uint32_t xcd_virtual_tiles(const TileGrid& tg)
+{
+    const uint32_t rows = tg.nty * tg.ntz;
+    return kXcds * tg.ntx * ((rows + kXcds - 1) / kXcds);
+}
+
+__device__ __forceinline__ bool xcd_tile(uint32_t v, const TileGrid& tg, uint32_t* t)
+{
+    const uint32_t x = v % kXcds, i = v / kXcds;
+    const uint32_t row = x + kXcds * (i / tg.ntx);
+    *t = row * tg.ntx + i % tg.ntx;
+    return row < tg.nty * tg.ntz;
+}
+
 // 32 occupancy bits of grid row (y, z) starting at x0 (bits beyond NX cleared)
 __device__ __forceinline__ uint32_t row_bits(const uint32_t* __restrict__ bits, uint32_t nwords, const Dims& d,
                                              uint32_t x0, uint32_t y, uint32_t z, uint32_t* key0_out)
@@ -258,10 +280,12 @@ __global__ void __launch_bounds__(kBlock) k_ccl_tile(const uint32_t* __restrict_
     __shared__ uint32_t par[kTileRuns];
     __shared__ uint32_t pairs[kPairCap];
     __shared__ uint32_t wtot[kBlock / kWave];
-    const uint32_t ntiles = tg.ntx * tg.nty * tg.ntz;
     const uint32_t j = threadIdx.x;
     const int lane = (int)(j & (kWave - 1)), wave = (int)(j / kWave);
     const int yl = (int)(j % kTY), zl = (int)(j / kTY);
+    const uint32_t ntiles = tg.ntx * tg.nty * tg.ntz;
+    // (tiles in launch order: dense regions are spread over the XCDs, which
+    // measured faster here than the XCD-ordered walk of the face kernel)
     for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const uint32_t tx = t % tg.ntx, ty = (t / tg.ntx) % tg.nty, tz = t / (tg.ntx * tg.nty);
         const uint32_t x0 = tx * kTX, y = ty * kTY + yl, z = tz * kTZ + zl;
@@ -415,7 +439,6 @@ __global__ void __launch_bounds__(kBlock) k_ccl_boundary(const uint32_t* __restr
     __shared__ uint64_t buf[kCclTilePairs];
     __shared__ unsigned long long hset[kPairHash];
     __shared__ uint32_t nbuf;
-    const uint32_t ntiles = tg.ntx * tg.nty * tg.ntz;
     const uint32_t j = threadIdx.x;
     const int yl = (int)(j % kTY), zl = (int)(j / kTY);
     // a distinct root pair goes to the tile's list (united in place if full)
@@ -434,7 +457,10 @@ __global__ void __launch_bounds__(kBlock) k_ccl_boundary(const uint32_t* __restr
     };
     __shared__ uint32_t wtot[kBlock / kWave];
     const int lane = (int)(j & (kWave - 1)), wave = (int)(j / kWave);
-    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const uint32_t nv = xcd_virtual_tiles(tg);
+    for (uint32_t v0 = blockIdx.x; v0 < nv; v0 += gridDim.x) {
+        uint32_t t;
+        if (!xcd_tile(v0, tg, &t)) continue;   // uniform over the workgroup
         if (j == 0) nbuf = 0;
         for (uint32_t i = j; i < kPairHash; i += kBlock) hset[i] = ~0ull;
         const uint32_t tx = t % tg.ntx, ty = (t / tg.ntx) % tg.nty, tz = t / (tg.ntx * tg.nty);
@@ -562,7 +588,7 @@ __global__ void __launch_bounds__(kBlock) k_ccl_boundary(const uint32_t* __restr
         if (j == 0) npair[t] = np;
         // LDS is reused by the next tile (a block with no next tile skips the
         // barrier, which would wait for the stores above to complete)
-        if (t + gridDim.x < ntiles) __syncthreads();
+        if (v0 + gridDim.x < nv) __syncthreads();
     }
 }
 
@@ -756,13 +782,17 @@ hipError_t launch_ccl(const Geom& g, const uint32_t* bits, SegBuffers& b, uint32
     tg.ntz = (d.nz + kTZ - 1) / kTZ;
     const uint64_t ntiles = (uint64_t)tg.ntx * tg.nty * tg.ntz;
     const int tgrid = (int)(ntiles < 16384 ? ntiles : 16384);
+    // the face kernel walks the XCD-ordered tile indices (a multiple of 8,
+    // and so is 16384)
+    const uint32_t nv = xcd_virtual_tiles(tg);
+    const int vgrid = (int)(nv < 16384u ? nv : 16384u);
     {
         StageScope t(VM_STAGE_CCL, s);
         k_ccl_tile<<<tgrid, kBlock, 0, s>>>(bits, g.nwords, b.wrank, d, tg, b.parent, b.csize);
     }
     {
         StageScope t(VM_STAGE_CCL_LINK, s);
-        k_ccl_boundary<<<tgrid, kBlock, 0, s>>>(bits, g.nwords, b.wrank, d, tg, b.parent, b.pairs, b.npair);
+        k_ccl_boundary<<<vgrid, kBlock, 0, s>>>(bits, g.nwords, b.wrank, d, tg, b.parent, b.pairs, b.npair);
         k_ccl_pairs<<<tgrid, kBlock, 0, s>>>((uint32_t)ntiles, b.pairs, b.npair, b.parent);
         k_ccl_flatten<<<grid, kBlock, 0, s>>>(ctr, b.parent, b.csize);
     }
