@@ -269,6 +269,9 @@ __global__ void __launch_bounds__(kBlock) k_bucket_insert(const uint4* __restric
                 const unsigned long long s0 = ((unsigned long long)a.w << 32 | a.z) + tsum[0][q];
                 const unsigned long long s1 = ((unsigned long long)b2.y << 32 | b2.x) + tsum[1][q];
                 const unsigned long long s2 = ((unsigned long long)b2.w << 32 | b2.z) + tsum[2][q];
+                // the key is stored as claimed, not as loaded: a load served
+                // from a line fetched before the claim would read it empty
+                a.x = k;
                 a.y += tcnt[q];
                 a.z = (uint32_t)s0;
                 a.w = (uint32_t)(s0 >> 32);
