@@ -226,6 +226,21 @@ size_t vm_workspace_bytes(uint32_t k_cap, uint32_t n_cap, uint32_t n_hyp);
 vm_status vm_ransac_planes(const vm_clusters* cl, const vm_ransac_params* params, vm_planes* out,
                            void* d_work, size_t work_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): vm_ransac_planes
+ * with the library's own fixed workspace instead of d_work.  The workspace is
+ * one device array of VM_NOALLOC_WORK_BYTES per GPU, held from the first call
+ * on that GPU until the process ends; this call allocates nothing.  Calls with
+ * vm_workspace_bytes(min(cl->k_cap, out->k_cap), cl->n_cap, params->n_hyp) >
+ * VM_NOALLOC_WORK_BYTES return VM_E_CAPACITY before anything is enqueued.
+ * Every call on one GPU shares that GPU's array: calls that may overlap on
+ * one GPU (different streams, or host threads) race and must be serialised by
+ * the caller.  Results are identical to vm_ransac_planes'.  VM_E_DEVICE if the
+ * array's device address cannot be obtained. */
+#define VM_NOALLOC_WORK_BYTES (64u << 20)
+vm_status vm_ransac_planes_noalloc(const vm_clusters* cl, const vm_ransac_params* params, vm_planes* out,
+                                   void* stream);
+
 /* Work decomposition of the inlier counting of Sec. III-C (b).  Counts are
  * integer sums of the same tests, so every valid setting gives identical
  * results; only the speed differs.  The setting is process-wide and read

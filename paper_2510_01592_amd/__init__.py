@@ -25,6 +25,7 @@ EXPORTED = [
     "vm_status_string", "vm_version", "vm_map_create", "vm_map_destroy", "vm_map_clear", "vm_map_stats",
     "vm_map_stats_async",
     "vm_insert", "vm_map_export", "vm_map_import", "vm_ccl", "vm_workspace_bytes", "vm_ransac_planes",
+    "vm_ransac_planes_noalloc",
     "vm_hulls", "vm_segment_frame", "vm_set_stage_timing", "vm_stage_times",
     "vm_set_count_config", "vm_get_count_config", "vm_autotune_count",
     "vm_capture_begin", "vm_capture_end", "vm_graph_launch", "vm_graph_destroy",
@@ -118,6 +119,8 @@ def lib() -> ctypes.CDLL:
             "vm_workspace_bytes": ([u32, u32, u32], sz),
             "vm_ransac_planes": ([ctypes.POINTER(Clusters), ctypes.POINTER(RansacParams), ctypes.POINTER(Planes),
                                   _P, sz, _P], i32),
+            "vm_ransac_planes_noalloc": ([ctypes.POINTER(Clusters), ctypes.POINTER(RansacParams),
+                                          ctypes.POINTER(Planes), _P], i32),
             "vm_hulls": ([ctypes.POINTER(Clusters), ctypes.POINTER(Planes), ctypes.POINTER(HullsOut), _P, sz, _P],
                          i32),
             "vm_segment_frame": ([_P, _P, i64, ctypes.POINTER(Pose), ctypes.POINTER(SegParams),
@@ -383,6 +386,16 @@ def ransac_planes(cl: Clusters, params: RansacParams, out: PlaneBuffers, work, s
     pc = out.c()
     _check(lib().vm_ransac_planes(ctypes.byref(cl), ctypes.byref(params), ctypes.byref(pc), _ptr(work),
                                   int(work.numel() * work.element_size()), _stream(stream)), "vm_ransac_planes")
+
+
+NOALLOC_WORK_BYTES = 64 << 20   # VM_NOALLOC_WORK_BYTES
+
+
+def ransac_planes_noalloc(cl: Clusters, params: RansacParams, out: PlaneBuffers, stream=None) -> None:
+    """vm_ransac_planes with the library's fixed per-GPU workspace (allocates nothing)."""
+    pc = out.c()
+    _check(lib().vm_ransac_planes_noalloc(ctypes.byref(cl), ctypes.byref(params), ctypes.byref(pc), _stream(stream)),
+           "vm_ransac_planes_noalloc")
 
 
 def set_count_config(cfg: Optional[dict] = None) -> None:

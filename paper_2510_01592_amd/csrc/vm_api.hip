@@ -419,6 +419,49 @@ vm_status vm_ransac_planes(const vm_clusters* cl, const vm_ransac_params* params
     return ransac_planes(*cl, *params, *out, w, (hipStream_t)stream);
 }
 
+// ---- the allocation-free form of vm_ransac_planes -------------------------------
+// Its workspace is this file-scope device array: every GPU the library runs
+// on holds one copy, at its own address, until the process ends.  In host code
+// the array's name is only a stand-in, so the device address is looked up
+// once per device (with that device current) and only that address is used.
+namespace {
+constexpr size_t kNoAllocWorkBytes = VM_NOALLOC_WORK_BYTES;
+static __device__ __align__(256) unsigned char scratch[kNoAllocWorkBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// the current device's copy of `scratch` (nullptr on failure)
+void* scratch_of_current_device()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    return g_scratch_ptr[dev];
+}
+}   // namespace
+
+vm_status vm_ransac_planes_noalloc(const vm_clusters* cl, const vm_ransac_params* params, vm_planes* out,
+                                   void* stream)
+{
+    if (check_clusters(cl) != VM_OK || check_params(params) != VM_OK || check_planes(out, params ? params->n_hyp : 0) != VM_OK)
+        return VM_E_ARG;
+    const uint32_t kc = std::min(cl->k_cap, out->k_cap);
+    if (work_layout(nullptr, kc, cl->n_cap, params->n_hyp).bytes > kNoAllocWorkBytes) return VM_E_CAPACITY;
+    void* base = scratch_of_current_device();
+    if (!base) return VM_E_DEVICE;
+    const WorkLayout w = work_layout(base, kc, cl->n_cap, params->n_hyp);
+    return ransac_planes(*cl, *params, *out, w, (hipStream_t)stream);
+}
+
 vm_status vm_set_count_config(const vm_count_config* cfg)
 {
     const vm_count_config c = cfg ? *cfg : count_config_default();

@@ -85,6 +85,14 @@ def test_argument_errors_without_device_work():
     assert L.vm_ransac_planes(ctypes.byref(cl), ctypes.byref(bad), ctypes.byref(pl), 8, 1 << 20, None) == vm.VM_E_ARG
     ok = vm.RansacParams(16, 0.01, 1, 0, 0)
     assert L.vm_ransac_planes(ctypes.byref(cl), ctypes.byref(ok), ctypes.byref(pl), 8, 16, None) == vm.VM_E_CAPACITY
+    # the allocation-free form: the same argument checks, and a workspace
+    # beyond its fixed size is refused before any device work
+    bad = vm.RansacParams(0, 0.01, 1, 0, 0)
+    assert L.vm_ransac_planes_noalloc(ctypes.byref(cl), ctypes.byref(bad), ctypes.byref(pl), None) == vm.VM_E_ARG
+    assert L.vm_ransac_planes_noalloc(None, ctypes.byref(ok), ctypes.byref(pl), None) == vm.VM_E_ARG
+    huge = vm.Clusters(1, 1 << 30, 8, 8, 8, 8, 8, None, 8)
+    assert vm.workspace_bytes(1, 1 << 30, 16) > vm.NOALLOC_WORK_BYTES
+    assert L.vm_ransac_planes_noalloc(ctypes.byref(huge), ctypes.byref(ok), ctypes.byref(pl), None) == vm.VM_E_CAPACITY
     ms = (ctypes.c_double * 8)()
     n = (ctypes.c_uint64 * 8)()
     assert L.vm_stage_times(ms, n, -1) == vm.VM_E_ARG
