@@ -18,12 +18,23 @@ HBM before a timed region starts.  Two forms run on the same starting map
 `value` is the plain form's throughput (the graph form adds a copy of the
 frame into the captured buffer per step); the graph form is reported beside.
 
+Beside the headline: frame latency over 100 frames per form, per-stage
+device time, the rooflines of the labelling (HBM), counting (fp32 VALU),
+insert and grouping stages with the published peaks and the peaks measured
+by microbenchmarks in the same run, the 2000-cluster batched set, the
+8-robot served stream (and the same trace one frame at a time), the
+0.005 m stress map, and the oracle on the host cores.
+
 Prints one JSON line."""
 from __future__ import annotations
 
 import argparse
+import concurrent.futures
+import ctypes
+import hashlib
 import json
 import os
+import platform
 import sys
 import time
 
@@ -34,15 +45,31 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "occupied voxels segmented/s and p50/p99 frame latency, plain vs batched/served @0.01 m"
-HBM_PEAK_GBS = 8000.0
-# vector ALU: 256 CUs x 64 lanes x 2.4 GHz lane-instructions/s; one inlier
-# test is 3 v_fma_f32 + 1 v_cmp (packed fp32 off), so 4 lane-instructions
-VALU_LANE_OPS = 256 * 64 * 2.4e9
-COUNT_PEAK_GEVAL = VALU_LANE_OPS / 4 / 1e9
+HBM_PEAK_GBS = 8000.0           # MI355X HBM3E, published
+FP32_PEAK_TFLOPS = 157.3        # MI355X fp32 vector, published
+FLOP_PER_TEST = 6               # an inlier test is three fused multiply-adds (and a compare)
+COUNT_PEAK_TTESTS = FP32_PEAK_TFLOPS / FLOP_PER_TEST   # the published fp32 peak in inlier tests/s (26.2 T)
+PEAKS_LIB = os.path.join(ROOT, "paper_2510_01592_amd", "libvm_peaks.so")
+CSRC = os.path.join(ROOT, "paper_2510_01592_amd", "csrc")
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "kernel_traffic.json")
+COPY_BYTES = 256 << 20
+HOST_THREADS = max(1, min(16, os.cpu_count() or 1))
+
+# kernels of each measured unit, and the source file each lives in
+UNITS = {
+    "ccl": (["k_ccl_tile", "k_ccl_boundary", "k_ccl_pairs", "k_ccl_flatten"], "vm_ccl.hip"),
+    "count": (["k_count_small", "k_count"], "vm_ransac.hip"),
+    "insert": (["k_vox_bucket", "k_bucket_scatter", "k_bucket_insert"], "vm_map.hip"),
+    "group": (["k_group_pairs", "k_group_gather"], "vm_ccl.hip"),
+}
 
 
 def _log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def _pct(v, q):
+    return float(np.percentile(np.asarray(v), q)) if len(v) else None
 
 
 def main() -> int:
@@ -51,16 +78,20 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--prewarm", type=int, default=30, help="frames inserted before the first step")
-    ap.add_argument("--latency-frames", type=int, default=20)
+    ap.add_argument("--latency-frames", type=int, default=100, help="frames per form in the latency measurement")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-frames", type=int, default=1)
+    ap.add_argument("--cpu-frames", type=int, default=3)
     ap.add_argument("--no-batched", action="store_true", help="skip the 2000-cluster batched measurement")
     ap.add_argument("--no-served", action="store_true", help="skip the multi-robot served measurement")
-    ap.add_argument("--served-seconds", type=float, default=3.0, help="span of the served arrival process")
+    ap.add_argument("--no-stress", action="store_true", help="skip the 0.005 m stress map")
+    ap.add_argument("--served-seconds", type=float, default=4.0, help="span of the served arrival process")
+    ap.add_argument("--only", choices=["batched", "served", "stress"],
+                    help="run one side measurement alone (no headline line; for profiling)")
     ap.add_argument("--counters", action="store_true",
-                    help="run only the inlier-counting launches of the roofline and a 256 MiB copy (for rocprofv3 --pmc)")
+                    help="run only the frames, counting passes and a 256 MiB copy whose counters "
+                         "rocprofv3 --pmc collects")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
-                    help="turn two rocprofv3 --pmc counter files of a --counters run into profiles/k_count_traffic.json")
+                    help="turn two rocprofv3 --pmc counter files of a --counters run into profiles/kernel_traffic.json")
     args = ap.parse_args()
     if args.traffic_from:
         return _traffic_from(*args.traffic_from)
@@ -80,6 +111,16 @@ def main() -> int:
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.Stream()
+
+    if args.only == "batched":
+        print(json.dumps({"batched": _batched(vm, torch, dev, stream)}), flush=True)
+        return 0
+    if args.only == "served":
+        print(json.dumps({"served": _served(vm, torch, args.served_seconds)}), flush=True)
+        return 0
+    if args.only == "stress":
+        print(json.dumps({"stress": _stress(vm, torch, dev, stream, with_oracle=False)}), flush=True)
+        return 0
 
     sc = scenes.scene_full_map(1)
     g = sc.geom
@@ -180,6 +221,8 @@ def main() -> int:
         res_stat[0:1].copy_(planes.status, non_blocking=True)
         res_stat[1:2].copy_(hulls.status, non_blocking=True)
 
+    # the latency frames grow the map further; they start from the snapshot
+    restore()
     lat = {"plain": [], "graph": []}
     with torch.cuda.stream(stream):
         # one untimed pass over the host frames first (the first copy from a
@@ -204,65 +247,96 @@ def main() -> int:
                 fetch()
                 stream.synchronize()
                 lat[form].append(1e3 * (time.perf_counter() - ta))
-    lat_out = {}
-    for form, v in lat.items():
-        a = np.array(v)
-        lat_out[form] = {"p50": float(np.percentile(a, 50)), "p99": float(np.percentile(a, 99)), "frames": len(a)}
+    lat_out = {form: {"p50": _pct(v, 50), "p99": _pct(v, 99), "max": float(max(v)), "frames": len(v)}
+               for form, v in lat.items()}
+    lat_occ = int(m.stats(stream).occupied)
     _log(f"latency graph p50 {lat_out['graph']['p50']:.2f} p99 {lat_out['graph']['p99']:.2f} ms; "
-         f"plain p50 {lat_out['plain']['p50']:.2f} p99 {lat_out['plain']['p99']:.2f} ms")
+         f"plain p50 {lat_out['plain']['p50']:.2f} p99 {lat_out['plain']['p99']:.2f} ms "
+         f"({args.latency_frames} frames each, map grows to {lat_occ} voxels)")
 
     # ---- per-stage device time (HIP events on the library's stream) -------------
     restore()
     vm.set_stage_timing(True)
     n_stage = min(5, args.steps)
+    st_stats = torch.zeros((n_stage, 6), dtype=torch.int64, device=dev)
     with torch.cuda.stream(stream):
         for i in range(n_stage):
             last["cl"] = m.segment_frame(frames[args.warmup + i], planes, hulls, frame=args.warmup + i,
                                          stream=stream, **kw)
+            m.stats_async(st_stats[i], stream=stream)
         stream.synchronize()
     ms, _ = vm.stage_times()
     stage_ms = {name: float(ms[j]) / n_stage for j, name in enumerate(vm.STAGES)}
+    st_np = st_stats.cpu().numpy()
+    v_stage = float(st_np[:, 0].mean())              # occupied voxels segmented per stage frame
+    touched = float(st_np[:, 5].mean())              # slot updates of each frame's insert
+    cl_meta = vm.read_clusters(last["cl"])
+    kept = float(cl_meta["N"])
+    key_np = m.export(stream=stream)[0].cpu().numpy().view(np.uint32)
+    bricks = _touched_bricks(key_np, g.dims)
     # inlier counting timed alone (standalone calls keep the GPU busy, so the
-    # events bracket the kernel itself); the last frame's clusters, all of them
+    # events bracket the kernels themselves); the last frame's clusters
     work = torch.empty(vm.workspace_bytes(k_cap, last["cl"].n_cap, H), dtype=torch.uint8, device=dev)
     reps = 10
     with torch.cuda.stream(stream):
         for r in range(reps):
             vm.ransac_planes(last["cl"], vm.ransac_params(H, eps, seed, r), planes, work, stream=stream)
         stream.synchronize()
-    ms2, n2 = vm.stage_times()
+    ms2, _ = vm.stage_times()
     vm.set_stage_timing(False)
     count_ms = float(ms2[vm.STAGES.index("count")]) / reps
-    cl_meta = vm.read_clusters(last["cl"])
     n_pts = cl_meta["N"]
-    evals = float(n_pts) * H
+    tests = float(n_pts) * H
     _log("stage ms/frame: " + ", ".join(f"{k}={v:.3f}" for k, v in stage_ms.items()) +
-         f"; k_count alone {count_ms:.3f} ms for {evals / 1e6:.0f}M evaluations")
-    ach = evals / (count_ms * 1e-3) / 1e9
-    roof = {"bound": "alu", "achieved": ach, "peak": COUNT_PEAK_GEVAL, "unit": "Geval/s",
-            "frac": ach / COUNT_PEAK_GEVAL, "traffic": _traffic(),
-            "kernel": "inlier counting: k_count_small (a wave per cluster of <= %d points) + k_count (tiles)"
-                      % vm.get_count_config()["wave_max_points"],
-            "work_per_launch": f"{n_pts} points x {H} hypotheses",
-            "peak_derivation": "256 CU x 64 lanes x 2.4 GHz / 4 VALU instructions per point-plane test"}
+         f"; counting pass alone {count_ms:.3f} ms for {tests / 1e6:.0f}M tests")
+
+    # ---- measured peaks (microbenchmarks, same run) --------------------------------
+    peaks = _measured_peaks(torch, stream)
+    _log(f"measured peaks: {peaks}")
+
+    traffic = _traffic_per_unit()
+    ccl_ms = stage_ms["ccl"] + stage_ms["ccl_link"]
+    rooflines = {
+        "ccl": _hbm_roof("labelling + linking (k_ccl_tile, k_ccl_boundary, k_ccl_pairs, k_ccl_flatten), one frame",
+                         8.0 * v_stage + 64.0 * bricks, ccl_ms, peaks, traffic.get("ccl"),
+                         f"8 B per occupied voxel x {v_stage:.0f} + 64 B per touched 8^3 brick x {bricks}"),
+        "insert": _hbm_roof("grouped insert (k_vox_bucket, scan, k_bucket_scatter, k_bucket_insert), one frame",
+                            12.0 * sc.n_points + 64.0 * touched, stage_ms["insert"], peaks, traffic.get("insert"),
+                            f"12 B per point x {sc.n_points} + 64 B per touched voxel x {touched:.0f}"),
+        "group": _hbm_roof("grouping (scan, sort, gather), one frame", 24.0 * kept, stage_ms["group"], peaks,
+                           traffic.get("group"), f"24 B per kept voxel x {kept:.0f}"),
+        "count": _alu_roof(tests, count_ms, peaks, traffic.get("count"),
+                           f"{n_pts} points x {H} hypotheses (the last stage frame's clusters)",
+                           "inlier counting: k_count_small (a wave per cluster of <= %d points) + k_count (tiles)"
+                           % vm.get_count_config()["wave_max_points"]),
+    }
+    roof = dict(rooflines["ccl"])
 
     # ---- batched clusters: 2000 log-uniform clusters, one pass, graph replays ------
     batched = None
     if not args.no_batched:
-        batched = _batched(vm, torch, dev, stream)
-        _log(f"batched: {batched}")
+        batched = _batched(vm, torch, dev, stream, peaks=peaks)
+        _log(f"batched: {json.dumps(batched)}")
 
     # ---- served: 8 robots, Poisson arrivals, continuous admission ---------------
     served = None
     if not args.no_served:
         served = _served(vm, torch, args.served_seconds)
-        _log(f"served: {served}")
+        _log(f"served: {json.dumps(served)}")
+
+    # ---- stress: 0.005 m, 800x800x400 cells, 8M points per frame -----------------
+    stress = None
+    if not args.no_stress:
+        stress = _stress(vm, torch, dev, stream, with_oracle=not args.no_cpu_baseline)
+        _log(f"stress: {json.dumps(stress)}")
 
     # ---- the oracle on the host, bounded sample ---------------------------------
     cpu = None
     if not args.no_cpu_baseline:
         cpu = _cpu_baseline(sc, args.prewarm, args.cpu_frames, H, eps, minc, seed)
-        _log(f"cpu baseline: {cpu}")
+        if stress and "oracle_ms_per_frame_all_cores" in stress:
+            cpu["stress_frame_ms_all_cores"] = stress.pop("oracle_ms_per_frame_all_cores")
+        _log(f"cpu baseline: {json.dumps(cpu)}")
 
     graph.close()
     out = {
@@ -294,22 +368,104 @@ def main() -> int:
             "graph": {"value": value, "ms_per_step": ms_per_step},
         },
         "latency_ms": dict(lat_out, includes="H2D of the frame from pinned host memory, the frame, D2H of planes, "
-                                             "areas, polygon offsets and status words"),
+                                             "areas, polygon offsets and status words",
+                           occupied_at_end=lat_occ),
         "stage_ms_per_frame": stage_ms,
         "roofline": roof,
+        "rooflines": rooflines,
+        "measured_peaks": peaks,
         "batched": batched,
         "served": served,
+        "stress": stress,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
     return 0
 
 
-def _batched(vm, torch, dev, stream, replays: int = 100):
+# ---------------------------------------------------------------------------
+# rooflines and measured peaks
+# ---------------------------------------------------------------------------
+def _touched_bricks(keys: np.ndarray, dims) -> int:
+    """Distinct 8x8x8 bricks holding an occupied voxel."""
+    k = keys.astype(np.int64)
+    nx, ny = int(dims[0]), int(dims[1])
+    x, y, z = k % nx, (k // nx) % ny, k // (nx * ny)
+    bx, by = (nx + 7) // 8, (ny + 7) // 8
+    return int(np.unique((x // 8) + bx * ((y // 8) + by * (z // 8))).size)
+
+
+def _hbm_roof(kernel, alg_bytes, ms, peaks, traffic, per_unit):
+    ach = alg_bytes / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+            "traffic": traffic, "kernel": kernel, "algorithmic_bytes": alg_bytes, "ms": ms,
+            "work_per_launch": per_unit,
+            "measured_peak": peaks.get("copy_gbs"), "frac_of_measured": ach / peaks["copy_gbs"]
+            if peaks.get("copy_gbs") else None}
+
+
+def _alu_roof(tests, ms, peaks, traffic, per_unit, kernel):
+    tflops = tests * FLOP_PER_TEST / (ms * 1e-3) / 1e12
+    tt = tests / (ms * 1e-3) / 1e12
+    return {"bound": "alu", "achieved": tflops, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": tflops / FP32_PEAK_TFLOPS, "traffic": traffic, "kernel": kernel, "ms": ms,
+            "work_per_launch": per_unit, "tests_per_s": tt * 1e12,
+            "peak_derivation": f"published fp32 vector peak; an inlier test counted as {FLOP_PER_TEST} flop "
+                               "(three fused multiply-adds), i.e. %.1f T tests/s" % COUNT_PEAK_TTESTS,
+            "measured_test_loop_peak_tests_per_s": peaks.get("test_loop_tests_per_s"),
+            "frac_of_measured_test_loop": tt * 1e12 / peaks["test_loop_tests_per_s"]
+            if peaks.get("test_loop_tests_per_s") else None}
+
+
+def _measured_peaks(torch, stream) -> dict:
+    """Attainable peaks measured in this run: a streaming copy (HBM), an
+    independent fp32 fma loop, and a register-resident loop of the inlier
+    test exactly as the counting kernels issue it (libvm_peaks.so)."""
+    if not os.path.exists(PEAKS_LIB):
+        return {}
+    L = ctypes.CDLL(PEAKS_LIB)
+    sink = torch.zeros(1 << 16, dtype=torch.float32, device="cuda")
+    P = ctypes.c_void_p
+    s = P(stream.cuda_stream)
+
+    def timed(f, reps=5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        with torch.cuda.stream(stream):
+            assert f() == 0
+            stream.synchronize()
+            e0.record(stream)
+            for _ in range(reps):
+                f()
+            e1.record(stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps * 1e-3
+
+    blocks, it = 8192, 4096
+    t_fma = timed(lambda: L.vmp_fma_loop(blocks, it, P(sink.data_ptr()), s))
+    t_test = timed(lambda: L.vmp_test_loop(blocks, 1024, ctypes.c_float(0.01), P(sink.data_ptr()), s))
+    n = 1 << 30
+    a = torch.ones(n // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    t_copy = timed(lambda: L.vmp_copy(P(a.data_ptr()), P(b.data_ptr()), ctypes.c_uint64(n // 16), 32768, s))
+    del a, b
+    return {"fma_loop_tflops": 2.0 * blocks * 256 * 8 * it / t_fma / 1e12,
+            "test_loop_tests_per_s": blocks * 256 * 16 * 1024 / t_test,
+            "copy_gbs": 2.0 * n / t_copy / 1e9,
+            "note": "fma loop: independent v_fma_f32 chains; test loop: the counting kernels' inlier test on "
+                    "register-resident points and wave-uniform planes; copy: 1 GiB read + 1 GiB written"}
+
+
+# ---------------------------------------------------------------------------
+# batched clusters (2000 log-uniform clusters)
+# ---------------------------------------------------------------------------
+def _batched(vm, torch, dev, stream, replays: int = 100, peaks=None):
     """2000 clusters of log-uniform size (50..200k points, about 48.5M in all),
-    1024 hypotheses: planes and hulls of all clusters in one pass, captured as
-    a graph and replayed `replays` times with the frame number advanced in
-    device memory (the data stays resident)."""
+    1024 hypotheses: planes and polygons of all clusters per frame.  Forms:
+    two-pass (vm_ransac_planes + vm_hulls, a dozen dependent launches) and
+    persistent (vm_planes_hulls: one preparation, one persistent launch, the
+    tail chain, one pack); the persistent form's split is autotuned, the frame
+    captured as a graph and replayed `replays` times with the frame number
+    advanced in device memory (the data stays resident)."""
     import scenes
     t0 = time.perf_counter()
     off, xyz = scenes.batched_clusters(seed=3)
@@ -320,19 +476,46 @@ def _batched(vm, torch, dev, stream, replays: int = 100):
     planes = vm.PlaneBuffers.alloc(K, N, H)
     hulls = vm.HullBuffers.alloc(K, N)
     frame_t = torch.zeros(1, dtype=torch.int32, device=dev)
-    with torch.cuda.stream(stream):
-        vm.ransac_planes(cl, vm.ransac_params(H, 0.01, 0x5EED, 0), planes, work, stream=stream)
+
+    def two_pass(f):
+        vm.ransac_planes(cl, vm.ransac_params(H, 0.01, 0x5EED, f), planes, work, stream=stream)
         vm.hulls(cl, planes, hulls, work, stream=stream)
+
+    def fused(f):
+        vm.planes_hulls(cl, vm.ransac_params(H, 0.01, 0x5EED, f), planes, hulls, work, stream=stream)
+
+    def per_frame(fn, reps=3):
+        fn(0)
         stream.synchronize()
         t_s = time.perf_counter()
-        for f in range(3):
-            vm.ransac_planes(cl, vm.ransac_params(H, 0.01, 0x5EED, f), planes, work, stream=stream)
-            vm.hulls(cl, planes, hulls, work, stream=stream)
+        for f in range(reps):
+            fn(f)
         stream.synchronize()
-        plain_ms = 1e3 * (time.perf_counter() - t_s) / 3
+        return 1e3 * (time.perf_counter() - t_s) / reps
+
+    def stages(fn, reps=3):
+        vm.set_stage_timing(True)
+        for f in range(reps):
+            fn(f)
+        stream.synchronize()
+        ms, _ = vm.stage_times()
+        vm.set_stage_timing(False)
+        return {name: float(ms[j]) / reps for j, name in enumerate(vm.STAGES) if ms[j] > 0}
+
+    with torch.cuda.stream(stream):
+        vm.set_fused_config(None)
+        two_ms = per_frame(two_pass)
+        two_st = stages(two_pass)
+        fused_ms = per_frame(fused)
+        t_s = time.perf_counter()
+        tuned = vm.autotune_fused(cl, vm.ransac_params(H, 0.01, 0x5EED, 0), planes, hulls, work, stream=stream,
+                                  reps=2)
+        tune_s = time.perf_counter() - t_s
+        tuned_ms = per_frame(fused)
+        fused_st = stages(fused)
         with vm.capture(stream) as cap:
-            vm.ransac_planes(cl, vm.ransac_params(H, 0.01, 0x5EED, d_frame=frame_t), planes, work, stream=stream)
-            vm.hulls(cl, planes, hulls, work, stream=stream)
+            vm.planes_hulls(cl, vm.ransac_params(H, 0.01, 0x5EED, d_frame=frame_t), planes, hulls, work,
+                            stream=stream)
         cap.graph.launch(stream)
         stream.synchronize()
         t_s = time.perf_counter()
@@ -341,107 +524,228 @@ def _batched(vm, torch, dev, stream, replays: int = 100):
             cap.graph.launch(stream)
         stream.synchronize()
         graph_ms = 1e3 * (time.perf_counter() - t_s) / replays
-        vm.set_stage_timing(True)
-        for f in range(3):
-            vm.ransac_planes(cl, vm.ransac_params(H, 0.01, 0x5EED, f), planes, work, stream=stream)
-        stream.synchronize()
-        ms, _ = vm.stage_times()
-        vm.set_stage_timing(False)
-        # the counting decomposition tuned on this workload (results are
-        # identical under every setting; only the counting time changes)
-        t_s = time.perf_counter()
-        tuned = vm.autotune_count(cl, vm.ransac_params(H, 0.01, 0x5EED, 0), planes, work, stream=stream, reps=2)
-        tune_s = time.perf_counter() - t_s
-        vm.set_stage_timing(True)
-        for f in range(3):
-            vm.ransac_planes(cl, vm.ransac_params(H, 0.01, 0x5EED, f), planes, work, stream=stream)
-        stream.synchronize()
-        ms_t, _ = vm.stage_times()
-        vm.set_stage_timing(False)
-        vm.set_count_config(None)
+        vm.set_fused_config(None)
     cap.graph.close()
-    count_ms = float(ms[vm.STAGES.index("count")]) / 3
-    count_ms_tuned = float(ms_t[vm.STAGES.index("count")]) / 3
-    evals = float(N) * H
-    ach = evals / (count_ms * 1e-3) / 1e9
+    tests = float(N) * H
     st = int(planes.status.cpu()[0]) | int(hulls.status.cpu()[0])
     del keep
+    count_ms = two_st.get("count", 0.0)
     return {"workload": f"{K} clusters, log-uniform 50..200k points ({N} in all), {H} hypotheses, "
-                        "planes + hulls of all clusters per frame",
-            "ms_per_frame_graph": graph_ms, "ms_per_frame_plain": plain_ms, "replays": replays,
-            "points_per_s_graph": N / (graph_ms * 1e-3), "evaluations_per_s_graph": evals / (graph_ms * 1e-3),
-            "k_count_ms": count_ms,
-            "count_autotune": {"config": tuned, "k_count_ms": count_ms_tuned, "tuning_s": tune_s,
-                               "default": vm.get_count_config()},
-            "roofline_k_count": {"bound": "alu", "achieved": ach, "peak": COUNT_PEAK_GEVAL, "unit": "Geval/s",
-                                 "frac": ach / COUNT_PEAK_GEVAL},
+                        "planes + polygons of all clusters per frame",
+            "ms_per_frame_graph": graph_ms, "replays": replays,
+            "ms_per_frame_persistent": tuned_ms, "ms_per_frame_persistent_default_split": fused_ms,
+            "ms_per_frame_two_pass": two_ms,
+            "tests_per_s_graph": tests / (graph_ms * 1e-3),
+            "stage_ms_two_pass": two_st, "stage_ms_persistent": fused_st,
+            "autotune": {"config": tuned, "tuning_s": tune_s},
+            "roofline_persistent_frame": _alu_roof(tests, graph_ms, peaks or {}, None,
+                                                   f"{N} points x {H} hypotheses, whole frame",
+                                                   "persistent planes + polygons (graph replay)"),
+            "roofline_count_two_pass": _alu_roof(tests, count_ms, peaks or {}, None, f"{N} points x {H} hypotheses",
+                                                 "inlier counting of the two-pass form (k_count_small + k_count)")
+            if count_ms else None,
             "status_flags": st, "generation_s": gen_s}
 
 
-def _served(vm, torch, seconds: float, n_robots: int = 8, rate_hz: float = 30.0, pool: int = 3):
-    """Several robots, each with its own map of the full-map workload (scene
-    seed = robot), send frames as Poisson processes at `rate_hz`; a frame has
-    U(200k, 2M) points (a prefix of one of the robot's `pool` shuffled
-    pre-generated frames, each taken at its own pose of a random walk).  The
-    scheduler admits frames as they arrive, subject to per-robot order, result
-    slots and an HBM budget for in-flight frames; latency is arrival ->
-    results in pinned host memory."""
+# ---------------------------------------------------------------------------
+# served: 8 robots, Poisson arrivals at 30 Hz, U(200k, 2M)-point posed frames
+# ---------------------------------------------------------------------------
+def _served(vm, torch, seconds: float, n_robots: int = 8, rate_hz: float = 30.0, warm_frames: int = 30,
+            speedup: float = 5.0):
+    """Robot r maps the full-map scene with scene seed 10 + r into its own map
+    (2^24 slots), warmed with `warm_frames` 1M-point frames (about 2M occupied
+    voxels).  Frames arrive as Poisson processes at `rate_hz` per robot over
+    `seconds`; a frame has U(200k, 2M) points -- a random window of the
+    robot's 8M-sample surface pool plus fresh outliers -- seen from its own
+    pose of a 6-DoF random walk.  The same trace runs three times from the
+    warmed maps: served (continuous admission, one stream per robot),
+    one frame at a time on one stream (the plain form), and served again with
+    the arrival times divided by `speedup` (a saturating rate)."""
     import scenes
-    from paper_2510_01592_amd.serve import GpuBackend, Request, Scheduler, latency_summary, poisson_arrivals
+    from paper_2510_01592_amd.serve import GpuBackend, Request, Scheduler, latency_summary
     t0 = time.perf_counter()
-    maps, host = [], []
-    n_max = 2_000_000
-    for r in range(n_robots):
-        sc = scenes.scene_full_map(1 + r)
-        g = sc.geom
-        maps.append(vm.Map(g.origin, g.voxel_size, g.dims, 23))
-        poses = scenes.random_walk_poses(100 + r, pool, sigma_t=0.01, sigma_rot_deg=0.5)
-        host.append([(torch.from_numpy(scenes.frame_points(sc, 7000 + 10 * r + k, n=n_max, pose=poses[k])).pin_memory(),
-                      poses[k][0], poses[k][1]) for k in range(pool)])
+    scs = [scenes.scene_full_map(10 + r) for r in range(n_robots)]
+    pools = [scenes.surface_pool(sc, 30 + r, 8_000_000) for r, sc in enumerate(scs)]
+    trace = scenes.served_trace(n_robots, seconds, rate_hz, seed=20)
+    # frames in the sensor frame of their poses, in pinned host memory
+    with concurrent.futures.ThreadPoolExecutor(max_workers=HOST_THREADS) as ex:
+        host = list(ex.map(lambda f: scenes.stream_frame(scs[f.robot], pools[f.robot], f.frame_seed, f.n_points,
+                                                         f.pose), trace))
+    pinned = []
+    for h in host:
+        t = torch.empty(h.shape, dtype=torch.float32, pin_memory=True)
+        t.numpy()[:] = h
+        pinned.append(t)
+    del host
     gen_s = time.perf_counter() - t0
-    n_slots, budget = 16, 256 << 20
+    maps, snaps = [], []
+    s = torch.cuda.Stream()
+    for r, sc in enumerate(scs):
+        g = sc.geom
+        mp = vm.Map(g.origin, g.voxel_size, g.dims, 24)
+        with torch.cuda.stream(s):
+            for f in range(warm_frames):
+                pts = scenes.stream_frame(sc, pools[r], 900_000 + 100 * r + f, 1_000_000)
+                mp.insert(torch.from_numpy(pts).cuda(), stream=s)
+        s.synchronize()
+        snaps.append(mp.export(stream=s))
+        maps.append(mp)
+    warm_occ = [int(sn[0].shape[0]) for sn in snaps]
+    del pools
+    n_slots, budget = 16, 8 << 30
     be = GpuBackend(maps, n_slots=n_slots, n_hyp=512)
-    rng = np.random.default_rng(12345)
-    reqs = []
-    # one untimed warm-up frame per robot (allocates each map's workspace)
-    warm = [Request(r, 0, 0.0, 1_000_000, (host[r][0][0][:1_000_000], host[r][0][1], host[r][0][2]))
-            for r in range(n_robots)]
-    Scheduler(be, n_robots, n_slots, budget).run(warm)
-    for r in range(n_robots):
-        for k, ta in enumerate(poisson_arrivals(rate_hz, seconds, 500 + r)):
-            n = int(rng.integers(200_000, n_max + 1))
-            src = host[r][k % pool]
-            reqs.append(Request(r, k + 1, float(ta), n, (src[0][:n], src[1], src[2])))
-    sch = Scheduler(be, n_robots, n_slots, budget)
-    torch.cuda.synchronize()
-    t_s = time.perf_counter()
-    done = sch.run(reqs, t0=t_s)
-    t_span = time.perf_counter() - t_s
-    summ = latency_summary(done, t_span)
-    vox = sum(c.result["occupied"] for c in done)
-    bad = sum(1 for c in done if c.result["status"].any())
-    for m in maps:
-        m.close()
-    return dict(summ, robots=n_robots, rate_hz_per_robot=rate_hz, arrival_span_s=seconds, wall_s=t_span,
-                points_per_frame="U(200k, 2M)", n_hyp=512, slots=n_slots, budget_mib=budget >> 20,
-                peak_inflight=sch.peak_inflight, rejected=len(sch.rejected), frames_with_status_flags=bad,
-                voxels_per_s=vox / t_span, points_per_s=sum(c.request.n_points for c in done) / t_span,
-                generation_s=gen_s)
+    be_b = GpuBackend(maps, n_slots=n_slots, n_hyp=512, batch=True, batch_k_cap=65536, batch_n_cap=1 << 24)
+
+    def reset():
+        with torch.cuda.stream(s):
+            for mp, sn in zip(maps, snaps):
+                mp.import_(sn[0], sn[1], sn[2], stream=s)
+        s.synchronize()
+
+    def requests(scale):
+        return [Request(f.robot, f.seq, f.arrival / scale, f.n_points, (pinned[i], f.pose[0], f.pose[1]))
+                for i, f in enumerate(trace)]
+
+    # one untimed frame per robot in each form (allocates each map's workspace)
+    first = [Request(r, 0, 0.0, 200_000, (pinned[i][:200_000], f.pose[0], f.pose[1]))
+             for r in range(n_robots) for i, f in enumerate(trace) if f.robot == r and f.seq == 0]
+    for b in (be, be_b):
+        reset()
+        Scheduler(b, n_robots, n_slots, budget).run(first)
+
+    def run(scale, per_robot, slots, label, backend=be):
+        reset()
+        sch = Scheduler(backend, n_robots, slots, budget, per_robot_inflight=per_robot)
+        torch.cuda.synchronize()
+        t_s = time.perf_counter()
+        done = sch.run(requests(scale), t0=t_s)
+        t_span = time.perf_counter() - t_s
+        summ = latency_summary(done, t_span)
+        vox = sum(c.result["occupied"] for c in done)
+        occ_end = max(c.result["occupied"] for c in done)
+        bad = sum(1 for c in done if c.result["status"].any())
+        out = dict(summ, wall_s=t_span, voxels_per_s=vox / t_span,
+                   points_per_s=sum(c.request.n_points for c in done) / t_span, peak_inflight=sch.peak_inflight,
+                   rejected=len(sch.rejected), frames_with_status_flags=bad, max_occupied=occ_end)
+        if sch.batches:
+            out["batches"] = sch.batches
+            out["mean_batch"] = sch.batched_frames / sch.batches
+        _log(f"served [{label}]: {out}")
+        return out, {(c.request.robot, c.request.seq): c.result for c in done}
+
+    served, res_a = run(1.0, 2, n_slots, "served (streams), 30 Hz")
+    batched, res_c = run(1.0, 2, n_slots, "served (batched), 30 Hz", be_b)
+    one, res_b = run(1.0, 1, 1, "one at a time, 30 Hz")
+    fast, _ = run(speedup, 2, n_slots, f"served (streams), x{speedup:g}")
+    fast_b, _ = run(speedup, 2, n_slots, f"served (batched), x{speedup:g}", be_b)
+    fast_one, _ = run(speedup, 1, 1, f"one at a time, x{speedup:g}")
+    # the same frames give the same results in every schedule
+    same = all(np.array_equal(res_a[k]["plane"].view(np.uint32), res_b[k]["plane"].view(np.uint32)) and
+               np.array_equal(res_a[k]["plane"].view(np.uint32), res_c[k]["plane"].view(np.uint32)) and
+               np.array_equal(res_a[k]["area"], res_b[k]["area"]) and
+               np.array_equal(res_a[k]["area"], res_c[k]["area"]) for k in res_a)
+    for mp in maps:
+        mp.close()
+    return dict(served, robots=n_robots, rate_hz_per_robot=rate_hz, arrival_span_s=seconds,
+                frames_in_trace=len(trace), points_per_frame="U(200k, 2M)", n_hyp=512, slots=n_slots,
+                budget_mib=budget >> 20, warm_occupied=warm_occ,
+                form="streams: one vm_segment_frame per frame on its robot's stream",
+                batched=dict(batched, form="continuous batching: frames admitted together share one "
+                                           "vm_planes_hulls_multi pass"),
+                one_at_a_time=one, saturating={"rate_hz_per_robot": rate_hz * speedup, "served": fast,
+                                               "batched": fast_b, "one_at_a_time": fast_one},
+                results_equal_in_every_form=bool(same), generation_s=gen_s)
 
 
-COPY_BYTES = 256 << 20
-TRAFFIC_JSON = os.path.join(ROOT, "profiles", "k_count_traffic.json")
-COUNT_SRC = os.path.join(ROOT, "paper_2510_01592_amd", "csrc", "vm_ransac.hip")
+# ---------------------------------------------------------------------------
+# stress: 0.005 m voxels, 800x800x400 cells, 8M points per frame
+# ---------------------------------------------------------------------------
+def _stress(vm, torch, dev, stream, warm: int = 5, timed: int = 5, with_oracle: bool = True):
+    """The stress scene (floor, staircase, two tables, 500 floating boxes) at
+    0.005 m: `warm` 8M-point frames warm the map, then `timed` frames run the
+    whole path (1024 hypotheses) one at a time from pinned host memory
+    (latency = H2D of the frame -> results in host memory)."""
+    import scenes
+    t0 = time.perf_counter()
+    sc = scenes.scene_stress(5)
+    g = sc.geom
+    H = sc.n_hyp
+    with concurrent.futures.ThreadPoolExecutor(max_workers=HOST_THREADS) as ex:
+        warm_pts = list(ex.map(lambda f: scenes.frame_points(sc, 100 + f), range(warm)))
+        timed_pts = list(ex.map(lambda f: scenes.frame_points(sc, 200 + f), range(timed)))
+    gen_s = time.perf_counter() - t0
+    m = vm.Map(g.origin, g.voxel_size, g.dims, 25)
+    with torch.cuda.stream(stream):
+        for p in warm_pts:
+            m.insert(torch.from_numpy(p).to(dev), stream=stream)
+    stream.synchronize()
+    warm_occ = int(m.stats(stream).occupied)
+    k_cap = 1 << 16
+    planes = vm.PlaneBuffers.alloc(k_cap, 1 << 24, H)
+    hulls = vm.HullBuffers.alloc(k_cap, 1 << 22)
+    stage = torch.empty((sc.n_points, 3), dtype=torch.float32, device=dev)
+    res = torch.empty(2, dtype=torch.int32).pin_memory()
+    res_area = torch.empty(k_cap, dtype=torch.float64).pin_memory()
+    host = [torch.from_numpy(p).pin_memory() for p in timed_pts]
+    kw = dict(min_cluster=sc.min_cluster, n_hyp=H, eps=sc.eps, seed=0x5EED)
+    lat, occ, kk = [], [], []
+    stats = torch.zeros(6, dtype=torch.int64, device=dev)
+    with torch.cuda.stream(stream):
+        # an untimed first frame (allocates the map's workspace)
+        stage.copy_(host[0], non_blocking=True)
+        m.segment_frame(stage, planes, hulls, frame=0, stream=stream, **kw)
+        stream.synchronize()
+        for i, hf in enumerate(host):
+            stream.synchronize()
+            ta = time.perf_counter()
+            stage.copy_(hf, non_blocking=True)
+            cl = m.segment_frame(stage, planes, hulls, frame=1 + i, stream=stream, **kw)
+            res[0:1].copy_(planes.status, non_blocking=True)
+            res[1:2].copy_(hulls.status, non_blocking=True)
+            res_area.copy_(hulls.area, non_blocking=True)
+            stream.synchronize()
+            lat.append(1e3 * (time.perf_counter() - ta))
+            m.stats_async(stats, stream=stream)
+            occ.append(int(stats.cpu()[0]))
+            kk.append(vm.read_clusters(cl)["K"])
+    vm.set_stage_timing(True)
+    with torch.cuda.stream(stream):
+        m.segment_frame(stage, planes, hulls, frame=99, stream=stream, **kw)
+        stream.synchronize()
+    ms, _ = vm.stage_times()
+    vm.set_stage_timing(False)
+    out = {"workload": "stress: 4x4x2 m at 0.005 m (800x800x400 cells), floor + staircase + 2 tables + 500 floating "
+                       "boxes, 8M float32 points/frame, N(0,1.5 mm), 5% outliers, 1024 hypotheses, min cluster 30",
+           "warm_frames": warm, "occupied_after_warm": warm_occ, "timed_frames": timed,
+           "occupied_per_frame": occ, "clusters_per_frame": kk,
+           "ms_per_frame": float(np.mean(lat)), "p50_ms": _pct(lat, 50), "p99_ms": _pct(lat, 99),
+           "voxels_per_s": float(np.sum(occ)) / (np.sum(lat) * 1e-3),
+           "latency_includes": "H2D of the 96 MB frame from pinned host memory, the frame, D2H of status and areas",
+           "stage_ms_one_frame": {name: float(ms[j]) for j, name in enumerate(vm.STAGES)},
+           "status_flags": int(res[0]) | int(res[1]), "generation_s": gen_s}
+    if with_oracle:
+        import oracle
+        om = oracle.OracleMap(g.origin, g.voxel_size, g.dims)
+        for p in warm_pts + timed_pts[:1]:
+            om.insert(p)
+        t_s = time.perf_counter()
+        oracle.segment(om, sc.min_cluster, H, sc.eps, 0x5EED, 1, threads=HOST_THREADS)
+        out["oracle_ms_per_frame_all_cores"] = {"ms": 1e3 * (time.perf_counter() - t_s), "threads": HOST_THREADS,
+                                                "occupied": int(len(om.key))}
+    m.close()
+    return out
 
 
+# ---------------------------------------------------------------------------
+# rocprofv3 counters: HBM traffic per kernel
+# ---------------------------------------------------------------------------
 def _sha256(path: str) -> str:
-    import hashlib
     with open(path, "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()
 
 
 def _counters_run(vm, torch, m, frames, planes, hulls, k_cap, H, eps, seed, kw, stream, dev, restore, first, n):
-    """The launches the roofline is measured on -- n frames, then 10
+    """The launches the rooflines are measured on -- n frames, then 10
     standalone inlier-counting passes over the last frame's clusters -- and a
     256 MiB device copy whose counters scale FETCH_SIZE/WRITE_SIZE to bytes."""
     restore()
@@ -457,7 +761,7 @@ def _counters_run(vm, torch, m, frames, planes, hulls, k_cap, H, eps, seed, kw, 
         dst.copy_(src)
         stream.synchronize()
     meta = vm.read_clusters(cl)
-    print(json.dumps({"counters_run": True, "k_count_launches": 10, "points": int(meta["N"]),
+    print(json.dumps({"counters_run": True, "frames": n, "count_passes": 10, "points": int(meta["N"]),
                       "clusters": int(meta["K"]), "n_hyp": H, "copy_bytes": COPY_BYTES}), flush=True)
     return 0
 
@@ -469,66 +773,116 @@ def _pmc_rows(path: str):
 
 
 def _traffic_from(fetch_csv: str, write_csv: str) -> int:
-    """HBM bytes per counting pass (the last 10 passes, two dispatches each):
-    FETCH_SIZE and WRITE_SIZE (KiB per dispatch) each scaled by what the same
-    counter reads for the 256 MiB copy of the --counters run."""
-    out = {"kernel": "k_count_small + k_count (one counting pass)", "source": os.path.relpath(COUNT_SRC, ROOT),
-           "source_sha256": _sha256(COUNT_SRC)}
+    """HBM bytes per dispatch of every kernel of a --counters run: FETCH_SIZE
+    and WRITE_SIZE (KiB per dispatch) each scaled by what the same counter
+    reads for the 256 MiB copy.  The counting kernels are averaged over the
+    10 standalone passes (their last 10 dispatches), the others over the
+    run's frames.  Each unit keeps the SHA-256 of its source file, so the
+    bench reports the figure only while the kernels are unchanged."""
+    out = {"units": {}, "kernels": {}}
+    per = {}
     for name, path in (("fetch", fetch_csv), ("write", write_csv)):
         rows = _pmc_rows(path)
         cnt = "FETCH_SIZE" if name == "fetch" else "WRITE_SIZE"
         rows = [r for r in rows if r["Counter_Name"] == cnt]
-        # each counting pass is two dispatches (clusters of one wave, then tiled)
-        kc = [float(r["Counter_Value"]) for r in rows if "k_count" in r["Kernel_Name"]][-20:]
         cp = max(float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"]
                  or "elementwise" in r["Kernel_Name"])
         scale = COPY_BYTES / (cp * 1024.0)
-        out[f"{name}_kib_per_launch_raw"] = sum(kc) / 10
         out[f"{name}_copy_kib_raw"] = cp
         out[f"{name}_scale"] = scale
-        out[f"{name}_bytes_per_launch"] = sum(kc) / 10 * 1024.0 * scale
-    out["traffic_bytes_per_launch"] = out["fetch_bytes_per_launch"] + out["write_bytes_per_launch"]
+        by = {}
+        for r in rows:
+            kn = r["Kernel_Name"]
+            short = kn.split("(")[0].split("::")[-1].split("<")[0].strip()
+            by.setdefault(short, []).append(float(r["Counter_Value"]) * 1024.0 * scale)
+        for short, v in by.items():
+            if short in ("k_count", "k_count_small"):
+                v = v[-10:]
+            per.setdefault(short, {})[name] = float(np.mean(v))
+            per[short]["dispatches"] = len(v)
+    out["kernels"] = per
+    for unit, (kernels, src) in UNITS.items():
+        if all(k in per for k in kernels):
+            f = sum(per[k]["fetch"] for k in kernels)
+            w = sum(per[k]["write"] for k in kernels)
+            out["units"][unit] = {"kernels": kernels, "fetch_bytes": f, "write_bytes": w, "bytes": f + w,
+                                  "source": os.path.relpath(os.path.join(CSRC, src), ROOT),
+                                  "source_sha256": _sha256(os.path.join(CSRC, src))}
     os.makedirs(os.path.dirname(TRAFFIC_JSON), exist_ok=True)
     with open(TRAFFIC_JSON, "w") as f:
         json.dump(out, f, indent=1)
-    print(json.dumps(out), flush=True)
+    print(json.dumps(out["units"]), flush=True)
     return 0
 
 
-def _traffic():
-    """Measured HBM bytes per k_count launch, if the counters were taken on the
-    kernel source as it is now; else None."""
+def _traffic_per_unit() -> dict:
+    """Measured HBM bytes per launch of each unit, for the units whose kernel
+    source is unchanged since the counters were taken."""
     try:
         with open(TRAFFIC_JSON) as f:
             t = json.load(f)
-        if t.get("source_sha256") != _sha256(COUNT_SRC):
-            return None
-        return float(t["traffic_bytes_per_launch"])
-    except (OSError, ValueError, KeyError):
-        return None
+    except (OSError, ValueError):
+        return {}
+    out = {}
+    for unit, u in t.get("units", {}).items():
+        try:
+            if u["source_sha256"] == _sha256(os.path.join(ROOT, u["source"])):
+                out[unit] = float(u["bytes"])
+        except (OSError, KeyError):
+            pass
+    return out
+
+
+# ---------------------------------------------------------------------------
+# the oracle on the host cores
+# ---------------------------------------------------------------------------
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
 
 
 def _cpu_baseline(sc, prewarm, n_frames, H, eps, minc, seed):
-    """The oracle (single-threaded C + numpy grouping) on the same workload:
-    the warmed map is rebuilt untimed, then n_frames frames are inserted and
-    segmented (all clusters) and timed."""
+    """The oracle (C, with numpy grouping) on the same workload: the warmed
+    map is rebuilt untimed, then n_frames frames are inserted and segmented
+    (all clusters), once on one thread and once with the clusters' planes and
+    hulls spread over the host cores (identical results); plus one frame of
+    the 2000-cluster batched set on all cores."""
     import oracle
     import scenes
     g = sc.geom
-    om = oracle.OracleMap(g.origin, g.voxel_size, g.dims)
-    for f in range(prewarm):
-        om.insert(scenes.frame_points(sc, 2 + f))
     frames = [scenes.frame_points(sc, 1000 + i) for i in range(n_frames)]
-    voxels = 0
+    res = {}
+    for label, threads in (("single", 1), ("all_cores", HOST_THREADS)):
+        om = oracle.OracleMap(g.origin, g.voxel_size, g.dims)
+        for f in range(prewarm):
+            om.insert(scenes.frame_points(sc, 2 + f))
+        voxels = 0
+        t0 = time.perf_counter()
+        for i, pts in enumerate(frames):
+            om.insert(pts)
+            voxels += len(om.key)
+            oracle.segment(om, minc, H, eps, seed, i, threads=threads)
+        t = time.perf_counter() - t0
+        res[label] = {"value": voxels / t, "s": t, "voxels": voxels, "threads": threads}
+    off, xyz = scenes.batched_clusters(seed=3)
     t0 = time.perf_counter()
-    for i, pts in enumerate(frames):
-        om.insert(pts)
-        voxels += len(om.key)
-        oracle.segment(om, minc, H, eps, seed, i)
-    t = time.perf_counter() - t0
-    return {"value": voxels / t, "unit": "voxels/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n_frames} frame(s) of the same workload after the same {prewarm}-frame warm-up "
-                      f"({voxels} occupied voxels segmented in {t:.1f} s, single thread)"}
+    oracle.planes_and_hulls(off, xyz, np.arange(len(off) - 1, dtype=np.uint32), 1024, 0.01, 0x5EED, 0,
+                            threads=HOST_THREADS)
+    batched_s = time.perf_counter() - t0
+    a = res["all_cores"]
+    return {"value": a["value"], "unit": "voxels/s", "cores": a["threads"], "kind": "oracle",
+            "sample": f"{n_frames} frame(s) of the full-map workload after the same {prewarm}-frame warm-up "
+                      f"({a['voxels']} occupied voxels segmented in {a['s']:.1f} s; labelling and grouping on one "
+                      f"thread, planes and hulls of the clusters over {a['threads']} threads)",
+            "single_thread": {"value": res["single"]["value"], "cores": 1, "s": res["single"]["s"]},
+            "batched_frame_s_all_cores": batched_s,
+            "host": {"nproc": os.cpu_count(), "threads_used": HOST_THREADS, "cpu_model": _cpu_model()}}
 
 
 if __name__ == "__main__":

@@ -213,7 +213,7 @@ typedef struct {
     uint32_t* d_status;    /* [1] device word, VM_FLAG_* OR-ed in (never cleared by the library) */
 } vm_planes;
 
-/* Device scratch for vm_ransac_planes / vm_hulls, in bytes: k_cap is the
+/* Device scratch for vm_ransac_planes / vm_hulls / vm_planes_hulls, in bytes: k_cap is the
  * number of clusters a call may process, min(clusters.k_cap, outputs'
  * k_cap); n_cap the clusters' point bound; n_hyp the hypotheses per cluster
  * (1 for a buffer that only serves vm_hulls). */
@@ -295,6 +295,68 @@ typedef struct {
  * reused: the calls are ordered on the stream). */
 vm_status vm_hulls(const vm_clusters* cl, const vm_planes* planes, vm_hulls_out* out,
                    void* d_work, size_t work_bytes, void* stream);
+
+/* ---- planes and polygons in one persistent launch ---------------------- */
+/* Sec. III-C (a)-(c) and "Boundary polygon generation" for every cluster of
+ * `cl`, run cluster-parallel as one persistent launch over a device work
+ * queue (the batched form for thousands of clusters of very uneven size):
+ * clusters sorted by size, largest first, are cut into (point tile,
+ * hypothesis chunk) items; each item's integer counts go to their own slot;
+ * the workgroup that completes a cluster's last item selects its best
+ * hypothesis, lists its inliers and builds its polygon.  The outputs --
+ * planes (including the optional d_counts / d_hyp), inlier CSR, polygons,
+ * areas, status flags -- are bit-identical to vm_ransac_planes followed by
+ * vm_hulls, for every work split (vm_fused_config).  d_work: at least
+ * vm_workspace_bytes(min(cl->k_cap, planes->k_cap, hulls->k_cap), cl->n_cap,
+ * params->n_hyp) bytes.  That cluster bound must be at most 65536
+ * (VM_E_CAPACITY otherwise).  Asynchronous. */
+vm_status vm_planes_hulls(const vm_clusters* cl, const vm_ransac_params* params, vm_planes* planes,
+                          vm_hulls_out* hulls, void* d_work, size_t work_bytes, void* stream);
+
+/* Work split of vm_planes_hulls.  Every valid setting gives identical
+ * results; only the speed differs. */
+typedef struct {
+    uint32_t hyp_chunk;      /* hypotheses per work item: a multiple of 64, 64..512; default 256 */
+    uint32_t small_max;      /* clusters of at most this many points are counted with the lanes over the
+                                hypotheses (one item per chunk), larger ones in 4096-point tiles; 0..256,
+                                default 256 */
+    uint32_t groups_per_cu;  /* persistent workgroups per compute unit, 1..8; default 4 */
+    uint32_t reserved;       /* must be 0 */
+} vm_fused_config;
+
+/* The process-wide split (NULL: the defaults), used by vm_planes_hulls
+ * calls whose shape has no autotuned entry; VM_E_ARG if a field is out of
+ * range (nothing changes then). */
+vm_status vm_set_fused_config(const vm_fused_config* cfg);
+vm_status vm_get_fused_config(vm_fused_config* out);
+
+/* Time vm_planes_hulls on this workload under candidate splits (one field
+ * at a time from the current setting, `reps` calls each, 1..16), keep the
+ * fastest for this call's shape bucket (log2 of the cluster bound, of n_cap
+ * and of n_hyp; later calls in the bucket use it) and return it in *best.
+ * Synchronises `stream`; the outputs hold the last call's (identical)
+ * results.  VM_E_STATE while capturing.  vm_set_fused_config(NULL) also
+ * clears the per-shape entries. */
+vm_status vm_autotune_fused(const vm_clusters* cl, const vm_ransac_params* params, vm_planes* planes,
+                            vm_hulls_out* hulls, void* d_work, size_t work_bytes, void* stream, uint32_t reps,
+                            vm_fused_config* best);
+
+/* Several cluster sets -- e.g. the clusters of several robots' maps, one
+ * frame each -- in one persistent pass (the served form's continuous
+ * batching): the sets are merged into one cluster list in d_work (at most
+ * k_cap clusters, 1..65536, and n_cap points in all), set i's clusters use
+ * RNG counter word frames[i] (params->frame and params->d_frame are not
+ * used), and set i's results go to planes[i] / hulls[i] exactly as
+ * vm_planes_hulls on that set alone with params->frame = frames[i] would
+ * write them (same capacity rules per set).  A set that no longer fits the
+ * merged bounds (in set order) contributes no clusters and gets
+ * VM_FLAG_CLUSTERS_CAP in both its status words.  n: 1..16 sets, whose
+ * outputs must not overlap.  d_work: vm_multi_workspace_bytes(k_cap, n_cap,
+ * params->n_hyp) bytes.  Asynchronous. */
+vm_status vm_planes_hulls_multi(uint32_t n, const vm_clusters* sets, const uint32_t* frames,
+                                const vm_ransac_params* params, vm_planes* planes, vm_hulls_out* hulls, uint32_t k_cap,
+                                uint32_t n_cap, void* d_work, size_t work_bytes, void* stream);
+size_t vm_multi_workspace_bytes(uint32_t k_cap, uint32_t n_cap, uint32_t n_hyp);
 
 /* ---- one frame (Sec. III-A overview) ------------------------------------ */
 typedef struct {

@@ -257,16 +257,36 @@ class FrameResult:
     results: List[ClusterResult]
 
 
+def planes_and_hulls(off, xyz, tag, n_hyp: int, eps: float, seed: int, frame, ks=None,
+                     threads: int = 1) -> List[ClusterResult]:
+    """:func:`plane_and_hull` for the clusters ``ks`` (default: all) of a CSR
+    (off[K+1], xyz[N,3], tag[K]); ``frame`` is one number or one per cluster.
+    With threads > 1 the clusters are spread over a thread pool (the C calls
+    release the interpreter lock); every cluster is computed by the same
+    single-threaded code, so the results do not depend on ``threads``."""
+    ks = range(len(tag)) if ks is None else list(ks)
+    fr = np.broadcast_to(np.asarray(frame, dtype=np.uint64), (len(tag),))
+
+    def one(k):
+        a, b = int(off[k]), int(off[k + 1])
+        p = xyz[a:b]
+        return plane_and_hull(p[:, 0], p[:, 1], p[:, 2], n_hyp, eps, seed, int(tag[k]), int(fr[k]))
+
+    if threads <= 1:
+        return [one(k) for k in ks]
+    import concurrent.futures
+    # largest clusters first, so a big one does not start last
+    order = sorted(ks, key=lambda k: -(int(off[k + 1]) - int(off[k])))
+    with concurrent.futures.ThreadPoolExecutor(max_workers=threads) as ex:
+        done = dict(zip(order, ex.map(one, order)))
+    return [done[k] for k in ks]
+
+
 def segment(m: OracleMap, min_cluster: int, n_hyp: int, eps: float, seed: int, frame: int,
-            cluster_subset: Optional[List[int]] = None) -> FrameResult:
+            cluster_subset: Optional[List[int]] = None, threads: int = 1) -> FrameResult:
     """Sec. III-C on the whole accumulated map: label, group, then one plane
     and one hull per kept cluster (optionally only for ``cluster_subset``)."""
     labels, _ = ccl26(m.key, m.dims)
     cl = group(m.key, labels, m.means(), min_cluster)
-    res = []
-    ks = range(len(cl.tag)) if cluster_subset is None else cluster_subset
-    for k in ks:
-        a, b = int(cl.off[k]), int(cl.off[k + 1])
-        p = cl.xyz[a:b]
-        res.append(plane_and_hull(p[:, 0], p[:, 1], p[:, 2], n_hyp, eps, seed, int(cl.tag[k]), frame))
+    res = planes_and_hulls(cl.off, cl.xyz, cl.tag, n_hyp, eps, seed, frame, cluster_subset, threads)
     return FrameResult(labels, cl, res)

@@ -25,7 +25,8 @@ EXPORTED = [
     "vm_status_string", "vm_version", "vm_map_create", "vm_map_destroy", "vm_map_clear", "vm_map_stats",
     "vm_map_stats_async",
     "vm_insert", "vm_map_export", "vm_map_import", "vm_ccl", "vm_workspace_bytes", "vm_ransac_planes",
-    "vm_ransac_planes_noalloc",
+    "vm_ransac_planes_noalloc", "vm_planes_hulls", "vm_set_fused_config", "vm_get_fused_config",
+    "vm_autotune_fused", "vm_planes_hulls_multi", "vm_multi_workspace_bytes",
     "vm_hulls", "vm_segment_frame", "vm_set_stage_timing", "vm_stage_times",
     "vm_set_count_config", "vm_get_count_config", "vm_autotune_count",
     "vm_capture_begin", "vm_capture_end", "vm_graph_launch", "vm_graph_destroy",
@@ -84,6 +85,14 @@ class CountConfig(ctypes.Structure):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
 
 
+class FusedConfig(ctypes.Structure):
+    _fields_ = [("hyp_chunk", ctypes.c_uint32), ("small_max", ctypes.c_uint32), ("groups_per_cu", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+    def as_dict(self) -> dict:
+        return {f: int(getattr(self, f)) for f, _ in self._fields_ if f != "reserved"}
+
+
 class VMError(RuntimeError):
     def __init__(self, status: int, what: str):
         super().__init__(f"{what}: {status_string(status)} ({status})")
@@ -121,6 +130,15 @@ def lib() -> ctypes.CDLL:
                                   _P, sz, _P], i32),
             "vm_ransac_planes_noalloc": ([ctypes.POINTER(Clusters), ctypes.POINTER(RansacParams),
                                           ctypes.POINTER(Planes), _P], i32),
+            "vm_planes_hulls": ([ctypes.POINTER(Clusters), ctypes.POINTER(RansacParams), ctypes.POINTER(Planes),
+                                 ctypes.POINTER(HullsOut), _P, sz, _P], i32),
+            "vm_planes_hulls_multi": ([u32, ctypes.POINTER(Clusters), ctypes.POINTER(u32), ctypes.POINTER(RansacParams),
+                                       ctypes.POINTER(Planes), ctypes.POINTER(HullsOut), u32, u32, _P, sz, _P], i32),
+            "vm_multi_workspace_bytes": ([u32, u32, u32], sz),
+            "vm_set_fused_config": ([ctypes.POINTER(FusedConfig)], i32),
+            "vm_get_fused_config": ([ctypes.POINTER(FusedConfig)], i32),
+            "vm_autotune_fused": ([ctypes.POINTER(Clusters), ctypes.POINTER(RansacParams), ctypes.POINTER(Planes),
+                                   ctypes.POINTER(HullsOut), _P, sz, _P, u32, ctypes.POINTER(FusedConfig)], i32),
             "vm_hulls": ([ctypes.POINTER(Clusters), ctypes.POINTER(Planes), ctypes.POINTER(HullsOut), _P, sz, _P],
                          i32),
             "vm_segment_frame": ([_P, _P, i64, ctypes.POINTER(Pose), ctypes.POINTER(SegParams),
@@ -430,6 +448,62 @@ def hulls(cl: Clusters, planes: PlaneBuffers, out: HullBuffers, work, stream=Non
     pc, hc = planes.c(), out.c()
     _check(lib().vm_hulls(ctypes.byref(cl), ctypes.byref(pc), ctypes.byref(hc), _ptr(work),
                           int(work.numel() * work.element_size()), _stream(stream)), "vm_hulls")
+
+
+def planes_hulls(cl: Clusters, params: RansacParams, planes: PlaneBuffers, hulls_out: "HullBuffers", work,
+                 stream=None) -> None:
+    """vm_planes_hulls: RANSAC planes and polygons of every cluster in one persistent launch."""
+    pc, hc = planes.c(), hulls_out.c()
+    _check(lib().vm_planes_hulls(ctypes.byref(cl), ctypes.byref(params), ctypes.byref(pc), ctypes.byref(hc),
+                                 _ptr(work), int(work.numel() * work.element_size()), _stream(stream)),
+           "vm_planes_hulls")
+
+
+def multi_workspace_bytes(k_cap: int, n_cap: int, n_hyp: int) -> int:
+    return int(lib().vm_multi_workspace_bytes(int(k_cap), int(n_cap), int(n_hyp)))
+
+
+def planes_hulls_multi(sets, frames, params: RansacParams, planes, hulls_out, k_cap: int, n_cap: int, work,
+                       stream=None) -> None:
+    """vm_planes_hulls_multi: several cluster sets (vm_clusters views) in one persistent pass; set i uses
+    RNG frame word frames[i] and writes planes[i] / hulls_out[i]."""
+    n = len(sets)
+    cs = (Clusters * n)(*sets)
+    fr = (ctypes.c_uint32 * n)(*[int(f) & 0xFFFFFFFF for f in frames])
+    ps = (Planes * n)(*[p.c() for p in planes])
+    hs = (HullsOut * n)(*[h.c() for h in hulls_out])
+    _check(lib().vm_planes_hulls_multi(n, cs, fr, ctypes.byref(params), ps, hs, int(k_cap), int(n_cap), _ptr(work),
+                                       int(work.numel() * work.element_size()), _stream(stream)),
+           "vm_planes_hulls_multi")
+
+
+def set_fused_config(cfg: Optional[dict] = None) -> None:
+    """Set the persistent pass's work split (None: the defaults, and forget autotuned entries)."""
+    if cfg is None:
+        _check(lib().vm_set_fused_config(None), "vm_set_fused_config")
+        return
+    c = get_fused_config()
+    for k, v in cfg.items():
+        if k not in c:
+            raise KeyError(k)
+        c[k] = int(v)
+    _check(lib().vm_set_fused_config(ctypes.byref(FusedConfig(**c))), "vm_set_fused_config")
+
+
+def get_fused_config() -> dict:
+    c = FusedConfig()
+    _check(lib().vm_get_fused_config(ctypes.byref(c)), "vm_get_fused_config")
+    return c.as_dict()
+
+
+def autotune_fused(cl: Clusters, params: RansacParams, planes: PlaneBuffers, hulls_out: "HullBuffers", work,
+                   stream=None, reps: int = 2) -> dict:
+    """Time the persistent pass's splits on this workload; the fastest is kept for the call's shape bucket."""
+    pc, hc, best = planes.c(), hulls_out.c(), FusedConfig()
+    _check(lib().vm_autotune_fused(ctypes.byref(cl), ctypes.byref(params), ctypes.byref(pc), ctypes.byref(hc),
+                                   _ptr(work), int(work.numel() * work.element_size()), _stream(stream), int(reps),
+                                   ctypes.byref(best)), "vm_autotune_fused")
+    return best.as_dict()
 
 
 class Graph:

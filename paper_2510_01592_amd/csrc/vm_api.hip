@@ -404,7 +404,8 @@ vm_status vm_ccl(vm_map m, uint32_t min_cluster, uint32_t* d_labels, vm_clusters
 
 size_t vm_workspace_bytes(uint32_t k_cap, uint32_t n_cap, uint32_t n_hyp)
 {
-    return work_layout(nullptr, k_cap, n_cap, n_hyp).bytes;
+    // one buffer serves both the multi-launch passes and the persistent one
+    return std::max(work_layout(nullptr, k_cap, n_cap, n_hyp).bytes, fused_workspace_bytes(k_cap, n_cap, n_hyp));
 }
 
 vm_status vm_ransac_planes(const vm_clusters* cl, const vm_ransac_params* params, vm_planes* out, void* d_work,
@@ -548,6 +549,124 @@ vm_status vm_autotune_count(const vm_clusters* cl, const vm_ransac_params* param
         return st;
     }
     count_config_set(cur);
+    if (best) *best = cur;
+    return VM_OK;
+}
+
+vm_status vm_planes_hulls(const vm_clusters* cl, const vm_ransac_params* params, vm_planes* planes,
+                          vm_hulls_out* hulls, void* d_work, size_t work_bytes, void* stream)
+{
+    if (check_clusters(cl) != VM_OK || check_params(params) != VM_OK || check_planes(planes, 1) != VM_OK ||
+        check_hulls(hulls) != VM_OK || !d_work)
+        return VM_E_ARG;
+    const uint32_t kc = std::min(cl->k_cap, std::min(planes->k_cap, hulls->k_cap));
+    if (kc > kOneBlockMax) return VM_E_CAPACITY;
+    if (work_bytes < vm_workspace_bytes(kc, cl->n_cap, params->n_hyp)) return VM_E_CAPACITY;
+    vm_fused_config cfg;
+    if (!fused_cache_get(kc, cl->n_cap, params->n_hyp, &cfg)) cfg = fused_config_get();
+    return planes_and_hulls(*cl, *params, nullptr, *planes, *hulls, d_work, work_bytes, cfg, (hipStream_t)stream);
+}
+
+size_t vm_multi_workspace_bytes(uint32_t k_cap, uint32_t n_cap, uint32_t n_hyp)
+{
+    return multi_workspace_bytes(k_cap, n_cap, n_hyp);
+}
+
+vm_status vm_planes_hulls_multi(uint32_t n, const vm_clusters* sets, const uint32_t* frames,
+                                const vm_ransac_params* params, vm_planes* planes, vm_hulls_out* hulls, uint32_t k_cap,
+                                uint32_t n_cap, void* d_work, size_t work_bytes, void* stream)
+{
+    if (n < 1 || n > 16 || !sets || !frames || !planes || !hulls || !d_work || check_params(params) != VM_OK ||
+        k_cap < 1 || k_cap > kOneBlockMax)
+        return VM_E_ARG;
+    for (uint32_t i = 0; i < n; ++i)
+        if (check_clusters(&sets[i]) != VM_OK || check_planes(&planes[i], 1) != VM_OK ||
+            check_hulls(&hulls[i]) != VM_OK)
+            return VM_E_ARG;
+    if (work_bytes < multi_workspace_bytes(k_cap, n_cap, params->n_hyp)) return VM_E_CAPACITY;
+    vm_fused_config cfg;
+    if (!fused_cache_get(k_cap, n_cap, params->n_hyp, &cfg)) cfg = fused_config_get();
+    return planes_hulls_multi(n, sets, frames, *params, planes, hulls, k_cap, n_cap, d_work, work_bytes, cfg,
+                              (hipStream_t)stream);
+}
+
+vm_status vm_set_fused_config(const vm_fused_config* cfg)
+{
+    const vm_fused_config c = cfg ? *cfg : fused_config_default();
+    if (!fused_config_valid(c)) return VM_E_ARG;
+    fused_config_set(c);
+    if (!cfg) fused_cache_clear();
+    return VM_OK;
+}
+
+vm_status vm_get_fused_config(vm_fused_config* out)
+{
+    if (!out) return VM_E_ARG;
+    *out = fused_config_get();
+    return VM_OK;
+}
+
+vm_status vm_autotune_fused(const vm_clusters* cl, const vm_ransac_params* params, vm_planes* planes,
+                            vm_hulls_out* hulls, void* d_work, size_t work_bytes, void* stream, uint32_t reps,
+                            vm_fused_config* best)
+{
+    if (reps < 1 || reps > 16) return VM_E_ARG;
+    const hipStream_t s = (hipStream_t)stream;
+    if (capturing(s)) return VM_E_STATE;
+    // validates the arguments and warms up
+    vm_status st = vm_planes_hulls(cl, params, planes, hulls, d_work, work_bytes, stream);
+    if (st != VM_OK) return st;
+    const uint32_t kc = std::min(cl->k_cap, std::min(planes->k_cap, hulls->k_cap));
+    hipEvent_t e0, e1;
+    VM_HIP(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return VM_E_DEVICE;
+    }
+    auto time_of = [&](const vm_fused_config& c, float* ms) -> vm_status {
+        vm_status r = planes_and_hulls(*cl, *params, nullptr, *planes, *hulls, d_work, work_bytes, c, s);
+        if (r != VM_OK) return r;
+        if (hipEventRecord(e0, s) != hipSuccess) return VM_E_DEVICE;
+        for (uint32_t i = 0; i < reps && r == VM_OK; ++i)
+            r = planes_and_hulls(*cl, *params, nullptr, *planes, *hulls, d_work, work_bytes, c, s);
+        if (r != VM_OK) return r;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(ms, e0, e1) != hipSuccess)
+            return VM_E_DEVICE;
+        *ms /= (float)reps;
+        return VM_OK;
+    };
+    struct Axis {
+        uint32_t vm_fused_config::*field;
+        uint32_t values[6];
+        int n;
+    };
+    const Axis axes[] = {
+        {&vm_fused_config::groups_per_cu, {2, 3, 4, 5, 6, 8}, 6},
+        {&vm_fused_config::hyp_chunk, {128, 256, 384, 512}, 4},
+        {&vm_fused_config::small_max, {0, 64, 128, 256}, 4},
+    };
+    vm_fused_config cur;
+    if (!fused_cache_get(kc, cl->n_cap, params->n_hyp, &cur)) cur = fused_config_get();
+    float cur_ms = 0.f;
+    st = time_of(cur, &cur_ms);
+    for (const Axis& a : axes) {
+        for (int i = 0; i < a.n && st == VM_OK; ++i) {
+            vm_fused_config c = cur;
+            c.*a.field = a.values[i];
+            if (c.*a.field == cur.*a.field || !fused_config_valid(c)) continue;
+            float ms = 0.f;
+            st = time_of(c, &ms);
+            if (st == VM_OK && ms < cur_ms) {
+                cur = c;
+                cur_ms = ms;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != VM_OK) return st;
+    fused_cache_put(kc, cl->n_cap, params->n_hyp, cur);
     if (best) *best = cur;
     return VM_OK;
 }

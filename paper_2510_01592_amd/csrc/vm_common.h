@@ -346,5 +346,28 @@ vm_count_config count_config_get();
 void count_config_set(const vm_count_config& c);
 vm_status hulls(const vm_clusters& cl, const vm_planes& planes, const vm_hulls_out& out, const WorkLayout& w,
                 hipStream_t s);
+// the workgroup chain over listed clusters (count in small[7]) whose survivors
+// sit at gu/gv/gi[in_off[k] + s]; vertices to hull_tmp[in_off[k] + k + q]
+hipError_t launch_hull_chain_list(const uint32_t* small, const uint32_t* list, const uint32_t* in_off,
+                                  const uint32_t* in_idx, const uint32_t* surv_cnt, double* gu, double* gv, uint32_t* gi,
+                                  uint32_t* hull_cnt, uint32_t* hull_tmp, double* area_out, uint32_t grid, hipStream_t s);
+
+// ---- RANSAC and polygons in one persistent launch (vm_fused.hip) ---------------
+bool fused_config_valid(const vm_fused_config& c);
+vm_fused_config fused_config_default();
+vm_fused_config fused_config_get();
+void fused_config_set(const vm_fused_config& c);
+void fused_cache_put(uint32_t k_cap, uint32_t n_cap, uint32_t H, const vm_fused_config& c);
+bool fused_cache_get(uint32_t k_cap, uint32_t n_cap, uint32_t H, vm_fused_config* c);
+void fused_cache_clear();
+size_t fused_workspace_bytes(uint32_t k_cap, uint32_t n_cap, uint32_t H);
+// d_cframe: optional per-cluster frame numbers (else params' frame)
+vm_status planes_and_hulls(const vm_clusters& cl, const vm_ransac_params& p, const uint32_t* d_cframe,
+                           const vm_planes& planes, const vm_hulls_out& hulls, void* d_work, size_t work_bytes,
+                           const vm_fused_config& cfg, hipStream_t s);
+size_t multi_workspace_bytes(uint32_t k_cap, uint32_t n_cap, uint32_t H);
+vm_status planes_hulls_multi(uint32_t n, const vm_clusters* sets, const uint32_t* frames, const vm_ransac_params& p,
+                             const vm_planes* planes, const vm_hulls_out* hulls, uint32_t k_cap, uint32_t n_cap,
+                             void* d_work, size_t work_bytes, const vm_fused_config& cfg, hipStream_t s);
 
 }  // namespace vm

@@ -22,85 +22,20 @@
 //   F. scan the vertex counts and pack the polygons, each vertex projected
 //      onto the plane.
 #include "vm_common.h"
+#include "vm_dev.h"
 
 #include <math.h>
 
 namespace vm {
 namespace {
 
+using namespace dev;
+
 constexpr int kTileThreads = 256;
 constexpr int kTileItems = 4;
 constexpr int kHullTile = kTileThreads * kTileItems;   // inliers per tile
-constexpr int kChainBlock = 256;
 constexpr int kSmallGrid = 2048;   // workgroups of the wave-per-cluster kernels (8192 waves)
 constexpr int kLdsCap = 2048;                           // survivors sorted in LDS
-
-__device__ __forceinline__ bool p2_less(double au, double av, uint32_t ai, double bu, double bv, uint32_t bi)
-{
-    if (au != bu) return au < bu;
-    if (av != bv) return av < bv;
-    return ai < bi;
-}
-
-__device__ __forceinline__ double cross3(double ou, double ov, double au, double av, double bu, double bv)
-{
-    return (au - ou) * (bv - ov) - (av - ov) * (bu - ou);
-}
-
-struct Basis {
-    double u[3], v[3];
-};
-
-__device__ __forceinline__ Basis plane_basis(float4 pl)
-{
-    Basis b;
-    const double n0 = pl.x, n1 = pl.y, n2 = pl.z;
-    double a[3] = {0.0, 0.0, 0.0};
-    if (fabs(n0) < 0.9) a[0] = 1.0;
-    else a[1] = 1.0;
-    const double c0 = a[1] * n2 - a[2] * n1;
-    const double c1 = a[2] * n0 - a[0] * n2;
-    const double c2 = a[0] * n1 - a[1] * n0;
-    const double inv = 1.0 / sqrt(c0 * c0 + c1 * c1 + c2 * c2);
-    b.u[0] = c0 * inv;
-    b.u[1] = c1 * inv;
-    b.u[2] = c2 * inv;
-    b.v[0] = n1 * b.u[2] - n2 * b.u[1];
-    b.v[1] = n2 * b.u[0] - n0 * b.u[2];
-    b.v[2] = n0 * b.u[1] - n1 * b.u[0];
-    return b;
-}
-
-// directional functional of direction d (0..7, every 45 degrees, CCW from +u)
-// Support directions of the extreme-point polygon, in counter-clockwise
-// order (every 45 degrees).  A point strictly inside the polygon of the
-// extremes is no hull vertex; a disc keeps about 10 % of its points outside
-// this octagon.  (Sixteen directions keep 3 %, but the extra tests cost more
-// than the shorter sorts save.)
-constexpr int kDirs = kHullDirs;
-constexpr int kPolyWords = 2 * kDirs + 2;   // u[kDirs], v[kDirs], margin, vertex count
-static_assert(kDirs == 8, "dir_val lists 8 directions");
-
-__device__ __forceinline__ double dir_val(int d, double u, double v)
-{
-    switch (d) {
-        case 0: return u;
-        case 1: return u + v;
-        case 2: return v;
-        case 3: return v - u;
-        case 4: return -u;
-        case 5: return -u - v;
-        case 6: return -v;
-        default: return u - v;
-    }
-}
-
-// per-cluster constants of the passes over inliers
-struct ClusterFrame {
-    uint32_t ib, m, pb, nk;   // inlier offset/count, point offset/count
-    Basis B;
-    double ox, oy, oz;        // origin = first inlier
-};
 
 // Whether cluster k gets a polygon: it has a plane, its inlier list fits the
 // output and indexes its own points.
@@ -129,12 +64,6 @@ __device__ __forceinline__ ClusterFrame cluster_frame(uint32_t k, const uint32_t
     return f;
 }
 
-__device__ __forceinline__ void project(const ClusterFrame& f, float x, float y, float z, double* pu, double* pv)
-{
-    const double dx = (double)x - f.ox, dy = (double)y - f.oy, dz = (double)z - f.oz;
-    *pu = f.B.u[0] * dx + f.B.u[1] * dy + f.B.u[2] * dz;
-    *pv = f.B.v[0] * dx + f.B.v[1] * dy + f.B.v[2] * dz;
-}
 
 // largest k with tile_off[k] <= t (tile_off is an exclusive scan of K entries)
 __device__ __forceinline__ uint32_t cluster_of_tile(const uint32_t* __restrict__ tile_off, uint32_t K, uint32_t t)
@@ -317,50 +246,10 @@ __global__ void __launch_bounds__(kBlock) k_hull_poly(const uint32_t* __restrict
         }
         if (lane == 0) {
             const ClusterFrame f = cluster_frame(k, off, X, Y, Z, plane, in_off, in_idx);
-            int np = 0;
-            uint32_t q[kDirs];
-            bool found = true;
-            for (int d = 0; d < kDirs; ++d) found = found && e[d] < f.m;
-            for (int d = 0; found && d < kDirs; ++d)
-                if (np == 0 || q[np - 1] != e[d]) q[np++] = e[d];
-            while (np > 1 && q[np - 1] == q[0]) --np;
-            double pu[kDirs], pv[kDirs];
-            double umin = INFINITY, umax = -INFINITY, vmin = INFINITY, vmax = -INFINITY;
-            for (int a = 0; a < np; ++a) {
-                const uint32_t i = f.pb + in_idx[f.ib + q[a]];
-                project(f, X[i], Y[i], Z[i], &pu[a], &pv[a]);
-                umin = fmin(umin, pu[a]);
-                umax = fmax(umax, pu[a]);
-                vmin = fmin(vmin, pv[a]);
-                vmax = fmax(vmax, pv[a]);
-            }
-            const double span = np > 0 ? fmax(umax - umin, vmax - vmin) : 0.0;
-            // far above the fp64 rounding of a cross product at this scale
-            const double margin = 1e-9 * span * span + 1e-300;
-            // vertices that do not turn left by more than the margin (on an
-            // edge of the others, or repeated) are dropped until every corner
-            // is strictly convex; the rest bound a convex polygon inside the
-            // hull (fewer than 3: no filtering)
-            for (bool changed = np >= 3; changed && np >= 3;) {
-                changed = false;
-                for (int a = 0; a < np && np >= 3; ++a) {
-                    const int b = (a + 1) % np, c = (a + 2) % np;
-                    if (cross3(pu[a], pv[a], pu[b], pv[b], pu[c], pv[c]) <= margin) {
-                        for (int r = b; r + 1 < np; ++r) {
-                            pu[r] = pu[r + 1];
-                            pv[r] = pv[r + 1];
-                        }
-                        --np;
-                        changed = true;
-                    }
-                }
-            }
-            for (int a = 0; a < kDirs; ++a) {
-                P[a] = a < np ? pu[a] : 0.0;
-                P[kDirs + a] = a < np ? pv[a] : 0.0;
-            }
-            P[2 * kDirs] = margin;
-            P[2 * kDirs + 1] = np >= 3 ? (double)np : 0.0;
+            extreme_polygon(e, f.m, P, [&](uint32_t j, double* pu, double* pv) {
+                const uint32_t i = f.pb + in_idx[f.ib + j];
+                project(f, X[i], Y[i], Z[i], pu, pv);
+            });
         }
     }
 }
@@ -424,138 +313,6 @@ __global__ void __launch_bounds__(kTileThreads) k_hull_filter(
     }
 }
 
-// ---- E: sort + monotone chain per cluster ------------------------------------------
-__device__ __forceinline__ void swap3(double* U, double* V, uint32_t* I, uint32_t a, uint32_t b)
-{
-    const double tu = U[a], tv = V[a];
-    const uint32_t ti = I[a];
-    U[a] = U[b];
-    V[a] = V[b];
-    I[a] = I[b];
-    U[b] = tu;
-    V[b] = tv;
-    I[b] = ti;
-}
-
-// One monotone chain over n sorted points (forward: lower chain, backward:
-// upper chain), computed by one wave in three levels.  The first two levels
-// drop only points that lie strictly on the inner side of a segment between
-// two other points (such a point is no vertex of the hull of any set holding
-// those three; collinear and coincident points are kept, so the choice among
-// them is left to the full rule):
-//   level 1: lane l chains its contiguous chunk of the n points into tmp,
-//            and the chunk results are concatenated into seq;
-//   level 2: lane w < 8 chains the concatenated results of chunks 8w..8w+7
-//            in place;
-//   level 3: one thread runs the full chain (dropping collinear and
-//            coincident points as well) over the level-2 results in order,
-//            which gives the output of the plain chain over all n points.
-constexpr int kChainL2 = 8;   // level-2 windows (of kWave / kChainL2 chunks each)
-
-template <typename S>
-__device__ __forceinline__ void chain_level1(const double* U, const double* V, uint32_t n, bool forward, S* tmp,
-                                             S* seq, uint32_t* offs)
-{
-    const uint32_t lane = threadIdx.x & (kWave - 1);
-    const uint32_t c = (n + kWave - 1) / kWave;
-    const uint32_t s0 = lane * c < n ? lane * c : n;
-    const uint32_t s1 = s0 + c < n ? s0 + c : n;
-    uint32_t h = 0;
-    for (uint32_t s = s0; s < s1; ++s) {
-        const uint32_t i = forward ? s : n - 1 - s;
-        while (h >= 2) {
-            const uint32_t a = tmp[s0 + h - 2], b = tmp[s0 + h - 1];
-            if (cross3(U[a], V[a], U[b], V[b], U[i], V[i]) < 0.0) --h;
-            else break;
-        }
-        tmp[s0 + h++] = (S)i;
-    }
-    // concatenate the chunk results into seq (wave prefix sum of the lengths)
-    uint32_t inc = h;
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        const uint32_t t = __shfl_up(inc, d, kWave);
-        if ((int)lane >= d) inc += t;
-    }
-    const uint32_t off = inc - h;
-    for (uint32_t q = 0; q < h; ++q) seq[off + q] = tmp[s0 + q];
-    offs[lane] = off;
-    if (lane == kWave - 1) offs[kWave] = inc;
-}
-
-// One thread's chain over the points idx[0..m) (indices into U, V) in that
-// order: a point pops the stack top while it turns right of the top two
-// (strict: only strictly right; otherwise also collinear and repeated
-// points); the kept indices go to out[0..h) and h is returned.  out may be
-// idx itself (a store lands at or below the read position).  The two top
-// entries' coordinates stay in registers, the next point's coordinates and
-// the index after it are loaded a step ahead, so a step waits for one LDS
-// load at most when it does not pop.
-template <bool kStrict, typename S>
-__device__ __forceinline__ uint32_t chain_run(const double* U, const double* V, const S* idx, uint32_t m, S* out)
-{
-    uint32_t h = 0;
-    double au = 0.0, av = 0.0, bu = 0.0, bv = 0.0;   // out[h - 2], out[h - 1]
-    uint32_t i1 = m > 0 ? (uint32_t)idx[0] : 0u;
-    double u1 = m > 0 ? U[i1] : 0.0, v1 = m > 0 ? V[i1] : 0.0;
-    uint32_t i2 = m > 1 ? (uint32_t)idx[1] : 0u;
-    for (uint32_t j = 0; j < m; ++j) {
-        const uint32_t i = i1;
-        const double iu = u1, iv = v1;
-        if (j + 1 < m) {
-            i1 = i2;
-            u1 = U[i1];
-            v1 = V[i1];
-        }
-        if (j + 2 < m) i2 = idx[j + 2];
-        while (h >= 2) {
-            const double c = cross3(au, av, bu, bv, iu, iv);
-            if (!(kStrict ? c < 0.0 : c <= 0.0)) break;
-            --h;
-            bu = au;
-            bv = av;
-            if (h >= 2) {
-                const uint32_t a = out[h - 2];
-                au = U[a];
-                av = V[a];
-            }
-        }
-        out[h] = (S)i;
-        if (h >= 1) {
-            au = bu;
-            av = bv;
-        }
-        bu = iu;
-        bv = iv;
-        ++h;
-    }
-    return h;
-}
-
-// level 2 for window w (called by one lane per window), in place; returns
-// its length
-template <typename S>
-__device__ __forceinline__ uint32_t chain_level2(const double* U, const double* V, S* seq, const uint32_t* offs,
-                                                 uint32_t w)
-{
-    const uint32_t a0 = offs[w * (kWave / kChainL2)], a1 = offs[(w + 1) * (kWave / kChainL2)];
-    return chain_run<true>(U, V, seq + a0, a1 - a0, seq + a0);
-}
-
-// the level-2 results of all windows, in order, copied to dst by the
-// threads of the workgroup; returns their total
-template <typename S>
-__device__ __forceinline__ uint32_t chain_gather2(const S* seq, const uint32_t* offs, const uint32_t* len2, S* dst)
-{
-    uint32_t pre = 0;
-    for (uint32_t w = 0; w < (uint32_t)kChainL2; ++w) {
-        const uint32_t a0 = offs[w * (kWave / kChainL2)], m = len2[w];
-        for (uint32_t q = threadIdx.x; q < m; q += blockDim.x) dst[pre + q] = seq[a0 + q];
-        pre += m;
-    }
-    return pre;
-}
-
 // Clusters with at most 64 points to chain -- survivors of the filter, or
 // (clusters the filter skips) all inliers, projected here exactly as the
 // filter projects them -- one wave each, four per workgroup.  The points are
@@ -614,79 +371,12 @@ __global__ void __launch_bounds__(kBlock) k_hull_small(
                 i = (uint32_t)lane;
             }
         }
-        for (int kk = 2; kk <= kWave; kk <<= 1) {
-            for (int j = kk >> 1; j > 0; j >>= 1) {
-                const double ou = __shfl_xor(u, j, kWave), ov = __shfl_xor(v, j, kWave);
-                const uint32_t oi = __shfl_xor(i, j, kWave);
-                const bool up = (lane & kk) == 0, low = (lane & j) == 0;
-                const bool mine_less = p2_less(u, v, i, ou, ov, oi);
-                if ((low == up) != mine_less) {
-                    u = ou;
-                    v = ov;
-                    i = oi;
-                }
-            }
-        }
-        su[wv][lane] = u;
-        sv[wv][lane] = v;
-        si[wv][lane] = i;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        // lane 0 builds the lower chain (points in sorted order), lane 1 at
-        // the same time the upper one (reverse order), each with the two top
-        // points of its stack held in registers
-        uint32_t h = 0;
-        if (lane < 2) {
-            const double* U = su[wv];
-            const double* V = sv[wv];
-            uint8_t* S = st[wv] + (lane ? kWave + 1 : 0);
-            double ua = 0.0, va = 0.0, ub = 0.0, vb = 0.0;   // S[h - 2], S[h - 1]
-            for (uint32_t n = 0; n < ns; ++n) {
-                const uint32_t q = lane ? ns - 1 - n : n;
-                const double uq = U[q], vq = V[q];
-                while (h >= 2 && cross3(ua, va, ub, vb, uq, vq) <= 0.0) {
-                    --h;
-                    ub = ua;
-                    vb = va;
-                    if (h >= 2) {
-                        const uint32_t s2 = S[h - 2];
-                        ua = U[s2];
-                        va = V[s2];
-                    }
-                }
-                S[h++] = (uint8_t)q;
-                ua = ub;
-                va = vb;
-                ub = uq;
-                vb = vq;
-            }
-        }
-        const uint32_t hl = __shfl(h, 0, kWave), hu = __shfl(h, 1, kWave);
-        // the polygon: the lower chain, then the upper one without its end
-        // points (the lower chain's last and first points)
-        h = hl + (hu >= 2 ? hu - 2 : 0u);
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        auto vertex = [&](uint32_t p) -> uint32_t {
-            return p < hl ? st[wv][p] : st[wv][kWave + 1 + (p - hl + 1)];
-        };
-        double term = 0.0;
-        uint32_t vi = 0;
-        if ((uint32_t)lane < h) {
-            vi = vertex((uint32_t)lane);
-            const uint32_t v1 = vertex((uint32_t)lane + 1 == h ? 0u : (uint32_t)lane + 1);
-            term = su[wv][vi] * sv[wv][v1] - su[wv][v1] * sv[wv][vi];
-        }
-        // shoelace sum over the vertices (a wave reduction)
-#pragma unroll
-        for (int dd = kWave / 2; dd >= 1; dd >>= 1) term += __shfl_xor(term, dd, kWave);
+        const WaveHull r = wave_hull(u, v, i, ns, lane, su[wv], sv[wv], si[wv], st[wv]);
         if (lane == 0) {
-            area_out[k] = h >= 3 ? 0.5 * term : 0.0;
-            hull_cnt[k] = h;
+            area_out[k] = r.area;
+            hull_cnt[k] = r.h;
         }
-        if ((uint32_t)lane < h) hull_tmp[ib + k + lane] = in_idx[ib + si[wv][vi]];
+        if ((uint32_t)lane < r.h) hull_tmp[ib + k + lane] = in_idx[ib + si[wv][r.vi]];
         __builtin_amdgcn_wave_barrier();
     }
 }
@@ -697,19 +387,7 @@ __global__ void __launch_bounds__(kChainBlock) k_hull_chain(
     double* __restrict__ gv, uint32_t* __restrict__ gi, uint32_t* __restrict__ hull_cnt,
     uint32_t* __restrict__ hull_tmp, double* __restrict__ area_out)
 {
-    __shared__ double su[kLdsCap];
-    __shared__ double sv[kLdsCap];
-    __shared__ uint32_t si[kLdsCap];
-    __shared__ uint16_t st_lo[2 * kLdsCap];
-    __shared__ uint16_t st_up[kLdsCap + 1];
-    __shared__ uint16_t tmp_lo[kLdsCap];
-    __shared__ uint16_t tmp_up[kLdsCap];
-    __shared__ uint16_t seq_lo[kLdsCap];
-    __shared__ uint16_t seq_up[kLdsCap];
-    __shared__ uint32_t offs_lo[kWave + 1], offs_up[kWave + 1];
-    __shared__ uint32_t len2_lo[kChainL2], len2_up[kChainL2];
-    __shared__ uint32_t hlo, hup;
-    __shared__ double red[kChainBlock / kWave];
+    __shared__ ChainLds<kLdsCap> L;
     // the clusters with more than one wave of survivors, listed by k_hull_small
     const uint32_t nc = small[7];
     for (uint32_t c = blockIdx.x; c < nc; c += gridDim.x) {
@@ -717,107 +395,18 @@ __global__ void __launch_bounds__(kChainBlock) k_hull_chain(
         const uint32_t ib = in_off[k];
         const uint32_t ns = surv_cnt[k];
         if (ns <= (uint32_t)kLdsCap) {
-            uint32_t N = 1;
-            while (N < ns) N <<= 1;
-            if (N <= (uint32_t)kChainBlock) {
-                // one point per thread: bitonic stages over distances below 64
-                // are shuffles inside a wave, the others go through LDS
-                const uint32_t t = threadIdx.x;
-                double u = t < ns ? gu[ib + t] : INFINITY, v = t < ns ? gv[ib + t] : INFINITY;
-                uint32_t id = t < ns ? gi[ib + t] : 0xFFFFFFFFu;
-                for (uint32_t size = 2; size <= N; size <<= 1) {
-                    for (uint32_t j = size >> 1; j > 0; j >>= 1) {
-                        double ou, ov;
-                        uint32_t oi;
-                        if (j >= (uint32_t)kWave) {
-                            su[t] = u;
-                            sv[t] = v;
-                            si[t] = id;
-                            __syncthreads();
-                            ou = su[t ^ j];
-                            ov = sv[t ^ j];
-                            oi = si[t ^ j];
-                            __syncthreads();
-                        } else {
-                            ou = __shfl_xor(u, (int)j, kWave);
-                            ov = __shfl_xor(v, (int)j, kWave);
-                            oi = __shfl_xor(id, (int)j, kWave);
-                        }
-                        const bool up = (t & size) == 0, low = (t & j) == 0;
-                        if ((low == up) != p2_less(u, v, id, ou, ov, oi)) {
-                            u = ou;
-                            v = ov;
-                            id = oi;
-                        }
-                    }
-                }
-                su[t] = u;
-                sv[t] = v;
-                si[t] = id;
-                __syncthreads();
-            } else {
-                for (uint32_t t = threadIdx.x; t < N; t += kChainBlock) {
-                    if (t < ns) {
-                        su[t] = gu[ib + t];
-                        sv[t] = gv[ib + t];
-                        si[t] = gi[ib + t];
-                    } else {
-                        su[t] = INFINITY;
-                        sv[t] = INFINITY;
-                        si[t] = 0xFFFFFFFFu;
-                    }
-                }
-                __syncthreads();
-                for (uint32_t size = 2; size <= N; size <<= 1) {
-                    for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
-                        for (uint32_t t = threadIdx.x; t < N / 2; t += kChainBlock) {
-                            const uint32_t a = 2 * t - (t & (stride - 1)), b = a + stride;
-                            const bool upw = (a & size) == 0;
-                            if (p2_less(su[b], sv[b], si[b], su[a], sv[a], si[a]) == upw) swap3(su, sv, si, a, b);
-                        }
-                        __syncthreads();
-                    }
-                }
-            }
-            // lower chain on wave 0, upper chain on wave 1
-            if (threadIdx.x < kWave) chain_level1(su, sv, ns, true, tmp_lo, seq_lo, offs_lo);
-            else if (threadIdx.x < 2 * kWave) chain_level1(su, sv, ns, false, tmp_up, seq_up, offs_up);
-            __syncthreads();
-            if (threadIdx.x < kChainL2) len2_lo[threadIdx.x] = chain_level2(su, sv, seq_lo, offs_lo, threadIdx.x);
-            else if (threadIdx.x >= kWave && threadIdx.x < kWave + kChainL2)
-                len2_up[threadIdx.x - kWave] = chain_level2(su, sv, seq_up, offs_up, threadIdx.x - kWave);
-            __syncthreads();
-            // level 3: the plain chain over the level-2 results, made contiguous
-            // (the level-1 scratch is free again)
-            const uint32_t l2lo = chain_gather2(seq_lo, offs_lo, len2_lo, tmp_lo);
-            const uint32_t l2up = chain_gather2(seq_up, offs_up, len2_up, tmp_up);
-            __syncthreads();
-            if (threadIdx.x == 0) hlo = chain_run<false>(su, sv, tmp_lo, l2lo, st_lo);
-            if (threadIdx.x == kWave) hup = chain_run<false>(su, sv, tmp_up, l2up, st_up);
-            __syncthreads();
-            // hull = lower chain, then the upper chain without its end points
-            // (they are the lower chain's last and first points); the
-            // vertices and the shoelace terms are taken in parallel
-            {
-                const uint32_t hl = hlo, hu = hup;
-                const uint32_t h = hl + (hu >= 2 ? hu - 2 : 0u);
-                auto vertex = [&](uint32_t q) -> uint32_t { return q < hl ? st_lo[q] : st_up[q - hl + 1]; };
-                double term = 0.0;
-                for (uint32_t q = threadIdx.x; q < h; q += kChainBlock) {
-                    const uint32_t p0 = vertex(q), p1 = vertex(q + 1 == h ? 0u : q + 1);
-                    term += su[p0] * sv[p1] - su[p1] * sv[p0];
-                    hull_tmp[ib + k + q] = in_idx[ib + si[p0]];   // vertex indices
-                }
-#pragma unroll
-                for (int dd = kWave / 2; dd >= 1; dd >>= 1) term += __shfl_xor(term, dd, kWave);
-                if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = term;
-                __syncthreads();
-                if (threadIdx.x == 0) {
-                    double tot = 0.0;
-                    for (int w2 = 0; w2 < kChainBlock / kWave; ++w2) tot += red[w2];
-                    area_out[k] = h >= 3 ? 0.5 * tot : 0.0;
-                    hull_cnt[k] = h;
-                }
+            double area = 0.0;
+            const uint32_t hh = block_chain(L, ns,
+                                            [&](uint32_t t, double* u, double* v, uint32_t* id) {
+                                                *u = gu[ib + t];
+                                                *v = gv[ib + t];
+                                                *id = gi[ib + t];
+                                            },
+                                            [&](uint32_t q, uint32_t p) { hull_tmp[ib + k + q] = in_idx[ib + L.si[p]]; },
+                                            &area);
+            if (threadIdx.x == 0) {
+                area_out[k] = area;
+                hull_cnt[k] = hh;
             }
         } else {
             // bitonic network in global memory; partners beyond ns are +infinity
@@ -923,6 +512,15 @@ __global__ void __launch_bounds__(kBlock) k_hull_pack(const uint32_t* __restrict
 }
 
 }  // namespace
+
+hipError_t launch_hull_chain_list(const uint32_t* small, const uint32_t* list, const uint32_t* in_off,
+                                  const uint32_t* in_idx, const uint32_t* surv_cnt, double* gu, double* gv, uint32_t* gi,
+                                  uint32_t* hull_cnt, uint32_t* hull_tmp, double* area_out, uint32_t grid, hipStream_t s)
+{
+    k_hull_chain<<<grid ? grid : 1, kChainBlock, 0, s>>>(small, list, in_off, in_idx, surv_cnt, gu, gv, gi, hull_cnt,
+                                                         hull_tmp, area_out);
+    return hipGetLastError();
+}
 
 uint64_t hull_tiles_bound(uint32_t k_cap, uint32_t n_cap)
 {

@@ -14,6 +14,7 @@
 // whole wave is a ballot and one scalar popcount.  Counts are integers added
 // with atomics, hence independent of the order of tiles.
 #include "vm_common.h"
+#include "vm_dev.h"
 
 #include <mutex>
 
@@ -22,49 +23,14 @@
 namespace vm {
 namespace {
 
+using namespace dev;
+
 constexpr int kCountBlock = 256;
 constexpr int kPtsPerLane = 16;
 constexpr int kTile = kCountBlock * kPtsPerLane;   // points per tile (4096)
 constexpr int kMaxHypChunk = 4096;                 // hypotheses per work item (LDS counters)
 constexpr int kHypBatch = 4;                       // planes loaded together
 constexpr uint32_t kXcds = 8;                      // accelerator complex dies (separate L2s)
-
-// The 128-bit product of two 64-bit words from four 32 x 32 -> 64 bit
-// multiply-adds (the high and the low half of one product; computing them
-// as separate 64-bit operations repeats partial products).
-__device__ __forceinline__ void mul_64x64_128(uint64_t a, uint64_t b, uint64_t& hi, uint64_t& lo)
-{
-    const uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32), b0 = (uint32_t)b, b1 = (uint32_t)(b >> 32);
-    const uint64_t p00 = (uint64_t)a0 * b0;
-    const uint64_t t = (uint64_t)a0 * b1 + (p00 >> 32);             // < 2^64
-    const uint64_t t2 = (uint64_t)a1 * b0 + (uint32_t)t;            // < 2^64
-    lo = (t2 << 32) | (uint32_t)p00;
-    hi = (uint64_t)a1 * b1 + (t >> 32) + (t2 >> 32);
-}
-
-__device__ __forceinline__ void philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3, uint64_t k0,
-                                              uint64_t k1, uint64_t out[4])
-{
-    const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
-    const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        uint64_t hi0, lo0, hi1, lo1;
-        mul_64x64_128(M0, c0, hi0, lo0);
-        mul_64x64_128(M1, c2, hi1, lo1);
-        const uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
-        c0 = n0;
-        c1 = lo1;
-        c2 = n2;
-        c3 = lo0;
-        k0 += W0;
-        k1 += W1;
-    }
-    out[0] = c0;
-    out[1] = c1;
-    out[2] = c2;
-    out[3] = c3;
-}
 
 // (a) hypothesis (k, h): three distinct points -> unit normal (+z first) and
 // offset in fp64, rounded to float32.  Degenerate triples get a NaN plane.
@@ -103,42 +69,7 @@ __global__ void __launch_bounds__(kBlock) k_hypotheses(const uint32_t* __restric
         for (uint32_t q = h; q < nt; q += H) tile_k[tile_off[k] + q] = k;
         if (n > wave_max)
             for (uint32_t q = h; q < nt; q += H) tile_k_big[tile_off_big[k] + q] = k;
-        const float qnan = __builtin_nanf("");
-        float4 pl = make_float4(qnan, qnan, qnan, qnan);
-        if (n >= 3) {
-            uint64_t r[4];
-            philox4x64_10(h, tag[k], frame, 0, seed, 0, r);
-            const uint64_t u0 = r[0] >> 32, u1 = r[1] >> 32, u2 = r[2] >> 32;
-            const uint64_t ia = (u0 * n) >> 32;
-            uint64_t ib = (u1 * (n - 1)) >> 32;
-            if (ib >= ia) ib += 1;
-            uint64_t ic = (u2 * (n - 2)) >> 32;
-            const uint64_t lo = ia < ib ? ia : ib, hi = ia < ib ? ib : ia;
-            if (ic >= lo) ic += 1;
-            if (ic >= hi) ic += 1;
-            const double ax = X[base + ia], ay = Y[base + ia], az = Z[base + ia];
-            const double e1x = (double)X[base + ib] - ax, e1y = (double)Y[base + ib] - ay,
-                         e1z = (double)Z[base + ib] - az;
-            const double e2x = (double)X[base + ic] - ax, e2y = (double)Y[base + ic] - ay,
-                         e2z = (double)Z[base + ic] - az;
-            double nx = e1y * e2z - e1z * e2y;
-            double ny = e1z * e2x - e1x * e2z;
-            double nz = e1x * e2y - e1y * e2x;
-            const double nn = nx * nx + ny * ny + nz * nz;
-            if (nn >= 1e-24) {
-                const double inv = 1.0 / sqrt(nn);
-                nx = nx * inv;
-                ny = ny * inv;
-                nz = nz * inv;
-                if (nz < 0.0 || (nz == 0.0 && (ny < 0.0 || (ny == 0.0 && nx < 0.0)))) {
-                    nx = -nx;
-                    ny = -ny;
-                    nz = -nz;
-                }
-                const double d = -(nx * ax + ny * ay + nz * az);
-                pl = make_float4((float)nx, (float)ny, (float)nz, (float)d);
-            }
-        }
+        const float4 pl = hyp_plane(X + base, Y + base, Z + base, n, h, tag[k], frame, seed);
         // the tiled kernel adds into the counts; the wave kernel stores every
         // count of its clusters, and clusters of fewer than 3 points have no
         // valid hypothesis (their counts are never read)
@@ -515,11 +446,6 @@ __global__ void __launch_bounds__(kBlock) k_select(const uint32_t* __restrict__ 
             }
         }
     }
-}
-
-__device__ __forceinline__ bool inlier_test(const float4 pl, float x, float y, float z, float eps)
-{
-    return fabsf(fmaf(pl.z, z, fmaf(pl.y, y, fmaf(pl.x, x, pl.w)))) < eps;
 }
 
 // (c) the inlier lists of the winning planes, over the same point tiles, in

@@ -48,7 +48,11 @@ class Completion:
 
 
 class Backend:
-    """What the scheduler needs from the device side."""
+    """What the scheduler needs from the device side.  A backend that sets
+    ``batching`` receives every admission round's frames together through
+    submit_batch (at most one frame per robot per round)."""
+
+    batching = False
 
     def bytes_for(self, req: Request) -> int:
         raise NotImplementedError
@@ -56,6 +60,10 @@ class Backend:
     def submit(self, req: Request, slot: int):
         """Enqueue the frame; returns a handle polled with done()."""
         raise NotImplementedError
+
+    def submit_batch(self, items):
+        """Enqueue frames [(req, slot)] as one batch; returns one handle per item."""
+        return [self.submit(req, slot) for req, slot in items]
 
     def done(self, handle) -> bool:
         raise NotImplementedError
@@ -70,7 +78,9 @@ class Scheduler:
 
     def __init__(self, backend: Backend, n_robots: int, n_slots: int, budget_bytes: int,
                  per_robot_inflight: int = 2, clock: Callable[[], float] = time.perf_counter,
-                 sleep: Callable[[float], None] = time.sleep):
+                 sleep: Callable[[float], None] = time.sleep, max_batches_inflight: int = 2):
+        """max_batches_inflight: with a batching backend, frames that arrive
+        while this many batches run wait and join the next batch together."""
         if n_slots < 1 or per_robot_inflight < 1 or budget_bytes <= 0:
             raise ValueError("need at least one slot, one in-flight frame per robot and a positive budget")
         self.backend = backend
@@ -84,6 +94,9 @@ class Scheduler:
         self.peak_used = 0
         self.peak_inflight = 0
         self.rejected: List[Request] = []
+        self.max_batches = max(1, int(max_batches_inflight))
+        self.batches = 0
+        self.batched_frames = 0
 
     def run(self, requests: Sequence[Request], t0: Optional[float] = None, idle_sleep: float = 50e-6,
             on_complete: Optional[Callable[[Completion], None]] = None) -> List[Completion]:
@@ -118,8 +131,11 @@ class Scheduler:
                 else:
                     still.append((h, slot, req, adm, nb))
             inflight = still
-            # admit: oldest arrivals first, across robots
-            progressed = True
+            # admit: oldest arrivals first, across robots; a batching backend
+            # gets the round's frames together (one per robot)
+            batching = getattr(self.backend, "batching", False)
+            batch = []
+            progressed = not batching or len({id(h[0]) for h in inflight}) < self.max_batches
             while progressed:
                 progressed = False
                 cands = [(q[0].arrival, r) for r, q in waiting.items() if q]
@@ -133,16 +149,28 @@ class Scheduler:
                         break
                     if per_robot[r] >= self.per_robot or not self.free_slots or self.used + nb > self.budget:
                         continue
+                    if batching and any(b[0].robot == r for b in batch):
+                        continue
                     q.pop(0)
                     slot = self.free_slots.pop()
                     self.used += nb
                     self.peak_used = max(self.peak_used, self.used)
                     per_robot[r] += 1
-                    h = self.backend.submit(req, slot)
-                    inflight.append((h, slot, req, self.clock() - t0, nb))
-                    self.peak_inflight = max(self.peak_inflight, len(inflight))
+                    if batching:
+                        batch.append((req, slot, nb))
+                    else:
+                        h = self.backend.submit(req, slot)
+                        inflight.append((h, slot, req, self.clock() - t0, nb))
+                    self.peak_inflight = max(self.peak_inflight, len(inflight) + len(batch))
                     progressed = True
                     break
+            if batch:
+                hs = self.backend.submit_batch([(req, slot) for req, slot, _ in batch])
+                adm = self.clock() - t0
+                for (req, slot, nb), h in zip(batch, hs):
+                    inflight.append((h, slot, req, adm, nb))
+                self.batches += 1
+                self.batched_frames += len(batch)
             if not inflight and i < total and not any(waiting.values()):
                 # nothing to do until the next arrival
                 wait = pending[i].arrival - (self.clock() - t0)
@@ -175,15 +203,31 @@ def latency_summary(done: Sequence[Completion], t_span: Optional[float] = None) 
 
 
 class GpuBackend(Backend):
-    """Frames through vm_segment_frame on one stream per robot.
+    """Frames on the device, one stream per robot.
 
     payload of a Request: (pinned host float32 [N,3] tensor, R, t).  Each
     result slot owns its plane/hull output buffers and pinned host copies of
     the per-cluster results; the D2H copies are enqueued behind the frame, so a
-    completed frame's results are already in host memory."""
+    completed frame's results are already in host memory.
+
+    batch=False: each frame is one vm_segment_frame on its robot's stream, so
+    frames of different robots overlap on the device.
+    batch=True (continuous batching): the frames admitted together are
+    inserted and labelled on their robots' streams (concurrently), then the
+    planes and polygons of all their clusters are computed in one persistent
+    pass (vm_planes_hulls_multi) on a batch stream, each cluster with its own
+    robot's frame number.  A robot's next frame is labelled only after the
+    batch that read its map's clusters; its insert may run before.  The
+    results are the same in both modes and the same alone or in the mix."""
 
     def __init__(self, maps, n_slots: int, n_hyp: int, min_cluster: int = 30, eps: float = 0.01,
-                 seed: int = 0x5EED, k_cap: int = 8192, in_cap: int = 1 << 23, v_cap: int = 1 << 21):
+                 seed: int = 0x5EED, k_cap: int = 8192, in_cap: int = 1 << 23, v_cap: int = 1 << 21,
+                 capture_cap: int = 0, batch: bool = False, batch_k_cap: int = 65536, batch_n_cap: int = 1 << 24):
+        """capture_cap > 0: every frame's full results (labels, cluster CSR,
+        inlier and hull lists) are copied to host memory too, behind the
+        frame on its stream, for maps of at most capture_cap occupied voxels
+        (for checks; costs large copies).  batch_k_cap / batch_n_cap bound the
+        clusters and points of one batch (frames beyond them are flagged)."""
         import torch
 
         import paper_2510_01592_amd as vm
@@ -193,8 +237,16 @@ class GpuBackend(Backend):
         self.streams = [torch.cuda.Stream() for _ in maps]
         self.kw = dict(min_cluster=min_cluster, n_hyp=n_hyp, eps=eps, seed=seed)
         self.k_cap = k_cap
+        self.in_cap, self.v_cap, self.capture_cap = in_cap, v_cap, int(capture_cap)
         self.planes = [vm.PlaneBuffers.alloc(k_cap, in_cap, n_hyp) for _ in range(n_slots)]
         self.hulls = [vm.HullBuffers.alloc(k_cap, v_cap) for _ in range(n_slots)]
+        self.batching = bool(batch)
+        if self.batching:
+            self.batch_stream = torch.cuda.Stream()
+            self.bk, self.bn = int(batch_k_cap), int(batch_n_cap)
+            self.mwork = torch.empty(vm.multi_workspace_bytes(self.bk, self.bn, n_hyp), dtype=torch.uint8,
+                                     device="cuda")
+            self.robot_last = [None] * len(maps)
         self.host = [dict(plane=torch.empty((k_cap, 4), dtype=torch.float32).pin_memory(),
                           best=torch.empty(k_cap, dtype=torch.int32).pin_memory(),
                           area=torch.empty(k_cap, dtype=torch.float64).pin_memory(),
@@ -204,32 +256,124 @@ class GpuBackend(Backend):
                           stats=torch.empty(6, dtype=torch.int64).pin_memory())
                      for _ in range(n_slots)]
         self.stats_dev = [torch.empty(6, dtype=torch.int64, device="cuda") for _ in range(n_slots)]
+        self.capture = None
+        if self.capture_cap:
+            c = self.capture_cap
+
+            def pin(n, dt):
+                return torch.empty(n, dtype=dt).pin_memory()
+            i32, f32 = torch.int32, torch.float32
+            self.labels_dev = [torch.empty(c, dtype=i32, device="cuda") for _ in range(n_slots)]
+            self.capture = [dict(labels=pin(c, i32), off=pin(k_cap + 1, i32), tag=pin(k_cap, i32), x=pin(c, f32),
+                                 y=pin(c, f32), z=pin(c, f32), key=pin(c, i32), nin=pin(k_cap, i32),
+                                 in_off=pin(k_cap + 1, i32), in_idx=pin(in_cap, i32), v_idx=pin(v_cap, i32),
+                                 v_xyz=pin((v_cap, 3), f32)) for _ in range(n_slots)]
 
     def bytes_for(self, req: Request) -> int:
         return 12 * int(req.n_points)
 
+    def _upload(self, req: Request):
+        torch = self.torch
+        pts = req.payload[0]
+        d = torch.empty((req.n_points, 3), dtype=torch.float32, device="cuda")
+        d.copy_(pts, non_blocking=True)
+        return d
+
+    def _capture_clusters(self, slot: int, cl) -> None:
+        """the map's cluster CSR and labels (right after its labelling)"""
+        if not self.capture:
+            return
+        vm = self.vm
+        c, kc, nc = self.capture[slot], self.k_cap, self.capture_cap
+        c["labels"].copy_(self.labels_dev[slot], non_blocking=True)
+        for name, ptr, n, dt in (("off", cl.d_off, kc + 1, np.uint32), ("tag", cl.d_tag, kc, np.uint32),
+                                 ("x", cl.d_x, nc, np.float32), ("y", cl.d_y, nc, np.float32),
+                                 ("z", cl.d_z, nc, np.float32), ("key", cl.d_key, nc, np.uint32)):
+            c[name].copy_(vm.device_view(ptr, n, dt), non_blocking=True)
+
+    def _fetch(self, slot: int, cl) -> None:
+        """the frame's results to the slot's pinned host buffers (current stream)"""
+        vm = self.vm
+        pb, hb, h = self.planes[slot], self.hulls[slot], self.host[slot]
+        if self.capture:
+            c = self.capture[slot]
+            c["nin"].copy_(pb.n_inliers, non_blocking=True)
+            c["in_off"].copy_(pb.in_off, non_blocking=True)
+            c["in_idx"].copy_(pb.in_idx[:self.in_cap], non_blocking=True)
+            c["v_idx"].copy_(hb.v_idx[:self.v_cap], non_blocking=True)
+            c["v_xyz"].copy_(hb.v_xyz[:self.v_cap], non_blocking=True)
+        h["plane"].copy_(pb.plane, non_blocking=True)
+        h["best"].copy_(pb.best_h, non_blocking=True)
+        h["area"].copy_(hb.area, non_blocking=True)
+        h["v_off"].copy_(hb.v_off, non_blocking=True)
+        h["meta"].copy_(vm.device_view(cl.d_meta, 2, np.int32), non_blocking=True)
+        h["status"][0:1].copy_(pb.status, non_blocking=True)
+        h["status"][1:2].copy_(hb.status, non_blocking=True)
+        h["stats"].copy_(self.stats_dev[slot], non_blocking=True)
+
     def submit(self, req: Request, slot: int):
-        torch, vm = self.torch, self.vm
-        pts, R, t = req.payload
+        torch = self.torch
+        _, R, t = req.payload
         s = self.streams[req.robot]
         with torch.cuda.stream(s):
-            d = torch.empty((req.n_points, 3), dtype=torch.float32, device="cuda")
-            d.copy_(pts, non_blocking=True)
-            pb, hb, h = self.planes[slot], self.hulls[slot], self.host[slot]
-            cl = self.maps[req.robot].segment_frame(d, pb, hb, R=R, t=t, frame=req.seq, stream=s, **self.kw)
-            h["plane"].copy_(pb.plane, non_blocking=True)
-            h["best"].copy_(pb.best_h, non_blocking=True)
-            h["area"].copy_(hb.area, non_blocking=True)
-            h["v_off"].copy_(hb.v_off, non_blocking=True)
-            h["meta"].copy_(vm.device_view(cl.d_meta, 2, np.int32), non_blocking=True)
-            h["status"][0:1].copy_(pb.status, non_blocking=True)
-            h["status"][1:2].copy_(hb.status, non_blocking=True)
+            d = self._upload(req)
+            pb, hb = self.planes[slot], self.hulls[slot]
+            pb.status.zero_()
+            hb.status.zero_()
+            labels = self.labels_dev[slot] if self.capture else None
+            cl = self.maps[req.robot].segment_frame(d, pb, hb, R=R, t=t, frame=req.seq, labels=labels, stream=s,
+                                                    **self.kw)
+            self._capture_clusters(slot, cl)
             self.maps[req.robot].stats_async(self.stats_dev[slot], stream=s)
-            h["stats"].copy_(self.stats_dev[slot], non_blocking=True)
+            self._fetch(slot, cl)
             ev = torch.cuda.Event()
             ev.record(s)
             d.record_stream(s)
         return ev
+
+    def submit_batch(self, items):
+        if not self.batching:
+            return super().submit_batch(items)
+        torch, vm = self.torch, self.vm
+        views, frames, pbs, hbs, ready = [], [], [], [], []
+        for req, slot in items:
+            _, R, t = req.payload
+            s = self.streams[req.robot]
+            m = self.maps[req.robot]
+            with torch.cuda.stream(s):
+                d = self._upload(req)
+                m.insert(d, R, t, stream=s)
+                if self.robot_last[req.robot] is not None:
+                    # the batch that read this map's previous clusters
+                    s.wait_event(self.robot_last[req.robot])
+                labels = self.labels_dev[slot] if self.capture else None
+                cl = m.ccl(self.kw["min_cluster"], labels=labels, stream=s)
+                self._capture_clusters(slot, cl)
+                m.stats_async(self.stats_dev[slot], stream=s)
+                self.planes[slot].status.zero_()
+                self.hulls[slot].status.zero_()
+                ev = torch.cuda.Event()
+                ev.record(s)
+                d.record_stream(s)
+            views.append(cl)
+            frames.append(req.seq)
+            pbs.append(self.planes[slot])
+            hbs.append(self.hulls[slot])
+            ready.append(ev)
+        bs = self.batch_stream
+        for ev in ready:
+            bs.wait_event(ev)
+        with torch.cuda.stream(bs):
+            kw = self.kw
+            vm.planes_hulls_multi(views, frames, vm.ransac_params(kw["n_hyp"], kw["eps"], kw["seed"]), pbs, hbs,
+                                  self.bk, self.bn, self.mwork, stream=bs)
+            for (req, slot), cl in zip(items, views):
+                self._fetch(slot, cl)
+            done = torch.cuda.Event()
+            done.record(bs)
+        for req, _ in items:
+            self.robot_last[req.robot] = done
+        return [done] * len(items)
 
     def done(self, handle) -> bool:
         return handle.query()
@@ -237,6 +381,20 @@ class GpuBackend(Backend):
     def result(self, handle, slot: int):
         h = self.host[slot]
         K = min(int(h["meta"][0]), self.k_cap)
-        return dict(K=int(h["meta"][0]), plane=h["plane"][:K].numpy().copy(), best=h["best"][:K].numpy().copy(),
-                    area=h["area"][:K].numpy().copy(), v_off=h["v_off"][:K + 1].numpy().copy(),
-                    status=h["status"].numpy().copy(), occupied=int(h["stats"][0]))
+        out = dict(K=int(h["meta"][0]), plane=h["plane"][:K].numpy().copy(), best=h["best"][:K].numpy().copy(),
+                   area=h["area"][:K].numpy().copy(), v_off=h["v_off"][:K + 1].numpy().copy(),
+                   status=h["status"].numpy().copy(), occupied=int(h["stats"][0]))
+        if self.capture:
+            c = self.capture[slot]
+            N, V = int(h["meta"][1]), out["occupied"]
+            u32 = np.uint32
+            out.update(N=N, labels=c["labels"][:V].numpy().view(u32).copy(), off=c["off"][:K + 1].numpy().view(u32).copy(),
+                       tag=c["tag"][:K].numpy().view(u32).copy(),
+                       xyz=np.stack([c[a][:N].numpy() for a in "xyz"], axis=1),
+                       key=c["key"][:N].numpy().view(u32).copy(), nin=c["nin"][:K].numpy().copy())
+            in_off = c["in_off"][:K + 1].numpy().view(u32).copy()
+            v_off = out["v_off"].view(u32)
+            out.update(in_off=in_off, in_idx=c["in_idx"][:int(in_off[K])].numpy().view(u32).copy(),
+                       v_idx=c["v_idx"][:int(v_off[K])].numpy().view(u32).copy(),
+                       v_xyz=c["v_xyz"][:int(v_off[K])].numpy().copy())
+        return out

@@ -28,7 +28,7 @@ __all__ = [
     "Rect", "Scene", "MapGeom",
     "scene_tiny", "scene_tiny_exact", "scene_full_map", "scene_stress",
     "frame_points", "identity_pose", "pose_inverse_apply",
-    "random_walk_poses", "batched_clusters",
+    "random_walk_poses", "batched_clusters", "surface_pool", "stream_frame", "StreamFrame", "served_trace",
 ]
 
 
@@ -190,20 +190,50 @@ def scene_full_map(seed: int = 1) -> Scene:
     return Scene("full_map", geom, fixed + patches, 1_000_000, 0.003, 0.05, n_hyp=512, seed=seed)
 
 
+class _ClearanceGrid:
+    """Occupancy of placed surfaces on a coarse grid (cell = ``cell`` metres),
+    each placed sample marking every cell within ``reach`` cells, so that a
+    candidate whose samples all fall in unmarked cells keeps roughly
+    reach*cell metres from everything placed before it."""
+
+    def __init__(self, lo, hi, cell: float, reach: int):
+        self.lo = np.asarray(lo, np.float64)
+        self.cell = cell
+        self.reach = reach
+        self.dims = np.ceil((np.asarray(hi, np.float64) - self.lo) / cell).astype(np.int64) + 1
+        self.occ = np.zeros(tuple(self.dims), dtype=bool)
+        r = np.arange(-reach, reach + 1)
+        self.offsets = np.stack(np.meshgrid(r, r, r, indexing="ij"), axis=-1).reshape(-1, 3)
+
+    def _cells(self, pts: np.ndarray) -> np.ndarray:
+        c = np.floor((pts - self.lo) / self.cell).astype(np.int64)
+        return np.clip(c, 0, self.dims - 1)
+
+    def free(self, pts: np.ndarray) -> bool:
+        c = self._cells(pts)
+        return not self.occ[c[:, 0], c[:, 1], c[:, 2]].any()
+
+    def mark(self, pts: np.ndarray) -> None:
+        c = np.unique(self._cells(pts), axis=0)
+        for o in self.offsets:
+            q = np.clip(c + o, 0, self.dims - 1)
+            self.occ[q[:, 0], q[:, 1], q[:, 2]] = True
+
+
 def scene_stress(seed: int = 5, n_boxes: int = 500) -> Scene:
     """4x4x2 m at 0.005 m (800x800x400 cells): floor, staircase, two tables
-    and ``n_boxes`` floating yawed boxes (sides 0.05-0.4 m, all 6 faces);
+    and ``n_boxes`` floating yawed boxes (sides 0.05-0.4 m, all 6 faces,
+    about 0.04 m apart from each other and from the fixed surfaces);
     8M points per frame, N(0, 1.5 mm), 5 % outliers, 1024 hypotheses."""
-    from scipy.spatial import cKDTree
     geom = MapGeom((-2.0, -2.0, -0.1), 0.005, (800, 800, 400))
     rng = np.random.default_rng(seed)
     fixed = [_hrect(-2.0, 2.0, -2.0, 2.0, 0.0)]
     fixed += _staircase(12, -1.5, -1.9, -0.9, 0.28, 0.18)
     fixed += [_hrect(0.3, 1.5, 0.5, 1.3, 0.72), _hrect(-1.2, -0.4, 0.6, 1.4, 0.76)]
-    cloud = [_rect_grid(r, 0.02) for r in fixed]
-    tree = cKDTree(np.concatenate(cloud))
+    grid = _ClearanceGrid(geom.origin, geom.hi, 0.02, 2)
+    for r in fixed:
+        grid.mark(_rect_grid(r, 0.02))
     boxes: List[Rect] = []
-    placed_pts = []
     tries = 0
     while len(boxes) < 6 * n_boxes:
         tries += 1
@@ -227,14 +257,10 @@ def scene_stress(seed: int = 5, n_boxes: int = 500) -> Scene:
         g = np.concatenate([_rect_grid(f, 0.02) for f in faces])
         if g[:, 2].min() < 0.03 or g[:, 2].max() > 1.85:
             continue
-        if tree.query(g, k=1)[0].min() < 0.04:
+        if not grid.free(g):
             continue
-        if placed_pts:
-            t2 = cKDTree(np.concatenate(placed_pts))
-            if t2.query(g, k=1)[0].min() < 0.04:
-                continue
         boxes += faces
-        placed_pts.append(g)
+        grid.mark(g)
     return Scene("stress", geom, fixed + boxes, 8_000_000, 0.0015, 0.05, n_hyp=1024, seed=seed)
 
 
@@ -273,6 +299,72 @@ def frame_points(scene: Scene, frame_seed: int, n: Optional[int] = None,
     if pose is not None:
         pw = pose_inverse_apply(np.asarray(pose[0]), np.asarray(pose[1]), pw)
     return np.ascontiguousarray(pw.astype(np.float32))
+
+
+def surface_pool(scene: Scene, seed: int, n: int) -> np.ndarray:
+    """``n`` noisy surface samples of ``scene`` in the map frame (float32,
+    shuffled, no outliers): drawn once per robot, frames of a served stream
+    take random windows of it."""
+    rng = np.random.default_rng(seed)
+    areas = np.array([r.area for r in scene.rects])
+    per = rng.multinomial(n, areas / areas.sum())
+    pw = np.concatenate([r.sample(rng, int(k), scene.sigma) for r, k in zip(scene.rects, per) if k > 0])
+    return np.ascontiguousarray(pw[rng.permutation(len(pw))].astype(np.float32))
+
+
+def stream_frame(scene: Scene, pool: np.ndarray, frame_seed: int, n: int,
+                 pose: Optional[Tuple[np.ndarray, np.ndarray]] = None) -> np.ndarray:
+    """One frame of a served stream: a random window of the robot's surface
+    pool (the pool is shuffled, so a window is a uniform subsample) plus
+    fresh outliers uniform in the map box, ``outlier_frac`` of the ``n``
+    points; expressed in the sensor frame of ``pose`` (map_from_sensor) and
+    rounded to float32, like :func:`frame_points`."""
+    rng = np.random.default_rng(frame_seed)
+    n_out = int(round(n * scene.outlier_frac))
+    n_surf = n - n_out
+    if n_surf > len(pool):
+        raise ValueError("surface pool smaller than the frame")
+    start = int(rng.integers(0, len(pool) - n_surf + 1))
+    lo = np.asarray(scene.geom.origin, dtype=np.float64)
+    pw = np.empty((n, 3), np.float64)
+    pw[:n_surf] = pool[start:start + n_surf]
+    pw[n_surf:] = rng.uniform(lo, scene.geom.hi, size=(n_out, 3))
+    if pose is not None:
+        pw = pose_inverse_apply(np.asarray(pose[0]), np.asarray(pose[1]), pw)
+    return np.ascontiguousarray(pw.astype(np.float32))
+
+
+@dataclasses.dataclass
+class StreamFrame:
+    robot: int
+    seq: int                 # the robot's own frame number
+    arrival: float           # seconds from the start of the stream
+    n_points: int
+    frame_seed: int
+    pose: Tuple[np.ndarray, np.ndarray]
+
+
+def served_trace(n_robots: int = 8, seconds: float = 4.0, rate_hz: float = 30.0, n_min: int = 200_000,
+                 n_max: int = 2_000_000, seed: int = 20) -> List[StreamFrame]:
+    """Arrivals of a multi-robot stream: per robot r, a Poisson process at
+    ``rate_hz`` (exponential gaps, seed + r), frame sizes uniform in
+    [n_min, n_max] and a 6-DoF random-walk pose per frame (sigma_t = 0.01 m,
+    sigma_rot = 0.5 deg, seed + 100 + r).  Sorted by arrival."""
+    out: List[StreamFrame] = []
+    for r in range(n_robots):
+        rng = np.random.default_rng(seed + r)
+        t, arr = 0.0, []
+        while True:
+            t += rng.exponential(1.0 / rate_hz)
+            if t >= seconds:
+                break
+            arr.append(t)
+        sizes = rng.integers(n_min, n_max + 1, size=len(arr))
+        poses = random_walk_poses(seed + 100 + r, len(arr), sigma_t=0.01, sigma_rot_deg=0.5)
+        for k, (ta, nk) in enumerate(zip(arr, sizes)):
+            out.append(StreamFrame(r, k, float(ta), int(nk), 1_000_000 * (r + 1) + k, poses[k]))
+    out.sort(key=lambda f: (f.arrival, f.robot, f.seq))
+    return out
 
 
 def _so3_exp(w: np.ndarray) -> np.ndarray:

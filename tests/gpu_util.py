@@ -89,3 +89,46 @@ def compare_cluster(k: int, P: dict, Hh: dict, ref: oracle.ClusterResult, check_
     assert abs(Hh["area"][k] - ref.hull.area) <= 1e-5 * abs(ref.hull.area) + 1e-12, (k, Hh["area"][k], ref.hull.area)
     assert np.array_equal(Hh["v_idx"][va:vb], ref.hull_local), (k, Hh["v_idx"][va:vb], ref.hull_local)
     assert np.array_equal(bits(Hh["v_xyz"][va:vb]), bits(ref.hull.xyz)), k
+
+
+def hull_path_clusters():
+    """Discs (about a tenth of their inliers survive the octagon filter) and
+    rotated squares (few survivors) whose hulls reach every path: one wave,
+    the workgroup chain, and the sort in global memory; (off, xyz, tag)."""
+    rng = np.random.default_rng(33)
+    parts = []
+    for n in (40, 200, 700, 1500, 3000, 8000, 30000, 60000):
+        rad = 0.0056 * np.sqrt(n)
+        r = rad * np.sqrt(rng.random(n))
+        th = rng.random(n) * 2 * np.pi
+        nrm = np.array([0.1, -0.2, 1.0]) / np.linalg.norm([0.1, -0.2, 1.0])
+        a = np.cross(nrm, [1.0, 0.0, 0.0])
+        a /= np.linalg.norm(a)
+        b = np.cross(nrm, a)
+        p = (r * np.cos(th))[:, None] * a + (r * np.sin(th))[:, None] * b + rng.normal(0, 0.002, n)[:, None] * nrm
+        parts.append((p + [0.5, 0.5, 1.0]).astype(np.float32))
+    for n, ang in ((500, 0.3), (5000, 1.1)):
+        s = (rng.random((n, 2)) - 0.5) * 0.01 * np.sqrt(n)
+        c, si = np.cos(ang), np.sin(ang)
+        uv = s @ np.array([[c, -si], [si, c]])
+        parts.append(np.c_[uv, rng.normal(0, 0.002, n)].astype(np.float32))
+    off = np.zeros(len(parts) + 1, np.uint32)
+    off[1:] = np.cumsum([len(p) for p in parts])
+    xyz = np.concatenate(parts)
+    tag = np.arange(len(parts), dtype=np.uint32) * 7717 + 5
+    return off, xyz, tag
+
+
+def ragged_clusters(seed=7, n_clusters=60, n_max=30_000):
+    """Log-uniform cluster sizes plus the degenerate sizes 0, 1, 2, 3 and a
+    collinear cluster; (off, xyz, tag)."""
+    import scenes
+    off, xyz = scenes.batched_clusters(seed=seed, n_clusters=n_clusters, n_min=3, n_max=n_max)
+    parts = [xyz[off[i]:off[i + 1]] for i in range(n_clusters)]
+    t = np.linspace(0, 1, 40)
+    parts += [np.zeros((0, 3), np.float32), xyz[:1], xyz[:2], xyz[:3], np.c_[t, 2 * t, t].astype(np.float32)]
+    off = np.zeros(len(parts) + 1, np.uint32)
+    off[1:] = np.cumsum([len(p) for p in parts])
+    xyz = np.concatenate(parts).astype(np.float32)
+    tag = np.arange(len(parts), dtype=np.uint32) * 7919 + 3
+    return off, xyz, tag

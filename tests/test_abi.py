@@ -93,6 +93,18 @@ def test_argument_errors_without_device_work():
     huge = vm.Clusters(1, 1 << 30, 8, 8, 8, 8, 8, None, 8)
     assert vm.workspace_bytes(1, 1 << 30, 16) > vm.NOALLOC_WORK_BYTES
     assert L.vm_ransac_planes_noalloc(ctypes.byref(huge), ctypes.byref(ok), ctypes.byref(pl), None) == vm.VM_E_CAPACITY
+    # the persistent form: argument checks and its cluster bound, before any device work
+    hl = vm.HullsOut(1, 1, 8, 8, 8, 8, 8)
+    assert L.vm_planes_hulls(ctypes.byref(cl), ctypes.byref(bad), ctypes.byref(pl), ctypes.byref(hl), 8, 1 << 20,
+                             None) == vm.VM_E_ARG
+    assert L.vm_planes_hulls(ctypes.byref(cl), ctypes.byref(ok), ctypes.byref(pl), None, 8, 1 << 20, None) == vm.VM_E_ARG
+    many = vm.Clusters(70000, 1000, 8, 8, 8, 8, 8, None, 8)
+    plm = vm.Planes(70000, 1, 8, 8, 8, 8, 8, None, None, 8)
+    hlm = vm.HullsOut(70000, 1, 8, 8, 8, 8, 8)
+    assert L.vm_planes_hulls(ctypes.byref(many), ctypes.byref(ok), ctypes.byref(plm), ctypes.byref(hlm), 8, 1 << 40,
+                             None) == vm.VM_E_CAPACITY
+    assert L.vm_planes_hulls(ctypes.byref(cl), ctypes.byref(ok), ctypes.byref(pl), ctypes.byref(hl), 8, 16,
+                             None) == vm.VM_E_CAPACITY
     ms = (ctypes.c_double * 8)()
     n = (ctypes.c_uint64 * 8)()
     assert L.vm_stage_times(ms, n, -1) == vm.VM_E_ARG
@@ -144,3 +156,25 @@ def test_count_config_set_get_and_validation():
     finally:
         vm.set_count_config(None)
     assert vm.get_count_config() == d
+
+
+def test_fused_config_set_get_and_validation():
+    import paper_2510_01592_amd as vm
+    L = vm.lib()
+    vm.set_fused_config(None)
+    d = vm.get_fused_config()
+    assert d == {"hyp_chunk": 256, "small_max": 256, "groups_per_cu": 4}
+    try:
+        for b in (dict(hyp_chunk=32), dict(hyp_chunk=96), dict(hyp_chunk=576), dict(small_max=257),
+                  dict(groups_per_cu=0), dict(groups_per_cu=9)):
+            c = dict(d)
+            c.update(b)
+            assert L.vm_set_fused_config(ctypes.byref(vm.FusedConfig(**c))) == vm.VM_E_ARG, b
+            assert vm.get_fused_config() == d
+        vm.set_fused_config(dict(hyp_chunk=512, small_max=0, groups_per_cu=8))
+        assert vm.get_fused_config() == {"hyp_chunk": 512, "small_max": 0, "groups_per_cu": 8}
+        assert L.vm_get_fused_config(None) == vm.VM_E_ARG
+        assert L.vm_autotune_fused(None, None, None, None, None, 0, None, 0, None) == vm.VM_E_ARG
+    finally:
+        vm.set_fused_config(None)
+    assert vm.get_fused_config() == d

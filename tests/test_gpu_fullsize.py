@@ -1,8 +1,11 @@
 """Parity at full workload sizes, in the launch configuration the benchmark
 times: the 4x4x2 m map at 0.01 m (400x400x200 cells, 1M points per frame,
 512 hypotheses) and the 2000-cluster batched set (log-uniform 50..200k
-points, 1024 hypotheses).  The map, labels and clusters are compared in full;
-RANSAC and hulls on sampled clusters the oracle computes one by one."""
+points, 1024 hypotheses).  The map, labels and clusters are compared in full,
+and so are the planes, inlier lists and polygons of every cluster (the
+oracle's clusters spread over the host's cores)."""
+import os
+
 import numpy as np
 import pytest
 
@@ -14,6 +17,7 @@ from tests.gpu_util import (assert_map_equal, bits, cluster_tensors, compare_clu
 pytestmark = pytest.mark.gpu
 
 SEED = 0x5EED
+THREADS = max(1, min(16, os.cpu_count() or 1))
 
 
 def _t(a):
@@ -21,7 +25,7 @@ def _t(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
-def test_full_map_frame_sampled():
+def test_full_map_frame_all_clusters():
     import torch
     import paper_2510_01592_amd as vm
     sc = scenes.scene_full_map(1)
@@ -55,17 +59,14 @@ def test_full_map_frame_sampled():
     assert np.array_equal(bits(np.c_[got["x"], got["y"], got["z"]]), bits(c.xyz))
     P, H = planes_np(pb), hulls_np(hb)
     assert P["status"] == 0 and H["status"] == 0
-    sizes = np.diff(c.off.astype(np.int64))
-    rng = np.random.default_rng(0)
-    sample = sorted(set([int(np.argmax(sizes))] + list(rng.choice(len(sizes), size=min(6, len(sizes)), replace=False))))
-    for k in sample:
-        a, b = int(c.off[k]), int(c.off[k + 1])
-        r = oracle.plane_and_hull(c.xyz[a:b, 0], c.xyz[a:b, 1], c.xyz[a:b, 2], sc.n_hyp, sc.eps, SEED, int(c.tag[k]), 7)
+    note(f"full map: oracle planes and hulls of all {len(c.tag)} clusters")
+    refs = oracle.planes_and_hulls(c.off, c.xyz, c.tag, sc.n_hyp, sc.eps, SEED, 7, threads=THREADS)
+    for k, r in enumerate(refs):
         compare_cluster(k, P, H, r, check_all_hyp=False)
     m.close()
 
 
-def test_batched_fullsize_sampled():
+def test_batched_fullsize_all_clusters():
     import paper_2510_01592_amd as vm
     off, xyz = scenes.batched_clusters(seed=3)
     K = len(off) - 1
@@ -78,11 +79,9 @@ def test_batched_fullsize_sampled():
     P, Hh = planes_np(pb), hulls_np(hb)
     assert P["status"] == 0 and Hh["status"] == 0
     sizes = np.diff(off.astype(np.int64))
-    rng = np.random.default_rng(1)
-    sample = sorted(set([int(np.argmax(sizes)), int(np.argmin(sizes))] + list(rng.choice(K, size=8, replace=False))))
-    for k in sample:
-        a, b = int(off[k]), int(off[k + 1])
-        r = oracle.plane_and_hull(xyz[a:b, 0], xyz[a:b, 1], xyz[a:b, 2], H, 0.01, SEED, int(tag[k]), 0)
+    note(f"batched: oracle planes and hulls of all {K} clusters on {THREADS} threads")
+    refs = oracle.planes_and_hulls(off, xyz, tag, H, 0.01, SEED, 0, threads=THREADS)
+    for k, r in enumerate(refs):
         compare_cluster(k, P, Hh, r, check_all_hyp=False)
     # every cluster found its plane, with most of its points as inliers
     assert np.all(P["best"] >= 0)

@@ -52,3 +52,28 @@ def test_group_drops_small_and_counts_add_up():
     u, c = np.unique(lab, return_counts=True)
     assert int(fr.clusters.off[-1]) == int(c[c >= 30].sum())
     assert len(fr.clusters.tag) == int((c >= 30).sum())
+
+
+def test_threaded_oracle_is_identical():
+    """The all-cores column of the CPU baseline: clusters spread over threads
+    give exactly the single-threaded results (per-cluster frame numbers too)."""
+    off, xyz = scenes.batched_clusters(seed=11, n_clusters=40, n_min=3, n_max=3000)
+    tag = np.arange(40, dtype=np.uint32) * 13 + 1
+    frames = np.arange(40, dtype=np.uint64) % 3
+    a = oracle.planes_and_hulls(off, xyz, tag, 96, 0.01, 0x5EED, frames, threads=1)
+    b = oracle.planes_and_hulls(off, xyz, tag, 96, 0.01, 0x5EED, frames, threads=8)
+    assert len(a) == len(b) == 40
+    for ra, rb in zip(a, b):
+        assert ra.ransac.best_h == rb.ransac.best_h
+        assert np.array_equal(ra.ransac.counts, rb.ransac.counts)
+        assert np.array_equal(ra.ransac.plane.view(np.uint32), rb.ransac.plane.view(np.uint32))
+        assert np.array_equal(ra.ransac.inliers, rb.ransac.inliers)
+        if ra.hull is None:
+            assert rb.hull is None
+        else:
+            assert np.array_equal(ra.hull_local, rb.hull_local) and ra.hull.area == rb.hull.area
+    # a per-cluster frame number is the cluster's own RNG counter word
+    c = oracle.planes_and_hulls(off, xyz, tag, 96, 0.01, 0x5EED, 2, ks=[5])
+    r = oracle.plane_and_hull(xyz[off[5]:off[6], 0], xyz[off[5]:off[6], 1], xyz[off[5]:off[6], 2], 96, 0.01,
+                              0x5EED, int(tag[5]), 2)
+    assert np.array_equal(c[0].ransac.counts, r.ransac.counts)

@@ -112,3 +112,43 @@ def test_slot_and_per_robot_limits():
     assert len(done) == 5 and sch.peak_inflight <= 2
     with pytest.raises(ValueError):
         Scheduler(be, 1, 0, 1 << 20)
+
+
+class SimBatchBackend(SimBackend):
+    """Frames admitted together form one batch: it starts when its slowest
+    robot is free and all of its frames finish together."""
+
+    batching = True
+
+    def __init__(self, clock, **kw):
+        super().__init__(clock, **kw)
+        self.batches = []
+
+    def submit_batch(self, items):
+        now = self.clock()
+        robots = [req.robot for req, _ in items]
+        assert len(set(robots)) == len(robots), "one frame per robot per batch"
+        start = max([now] + [self.robot_free.get(r, 0.0) for r in robots])
+        fin = start + self.fixed_s + self.per_point_s * sum(req.n_points for req, _ in items)
+        for req, slot in items:
+            assert all(sl != slot for f, sl, _r, _q in self.active if f > now), "slot reused while in flight"
+            self.robot_free[req.robot] = fin
+            self.active.append((fin, slot, req.robot, req.seq))
+            self.log.append(("submit", now, req.robot, req.seq, slot))
+        self.batches.append(len(items))
+        return [fin] * len(items)
+
+
+def test_batching_admission_rounds():
+    clock = Clock()
+    be = SimBatchBackend(clock, per_point_s=2e-10, fixed_s=2e-3)
+    reqs = _requests(n_robots=6, rate=60.0, dur=0.5, seed=3)
+    sch = Scheduler(be, 6, n_slots=8, budget_bytes=1 << 30, clock=clock, sleep=clock.sleep)
+    done = sch.run(reqs)
+    assert len(done) == len(reqs) and not sch.rejected
+    assert sch.batches == len(be.batches) and sch.batched_frames == len(reqs)
+    assert max(be.batches) > 1          # robots do share batches
+    # per-robot order is kept
+    for r in range(6):
+        seqs = [e[3] for e in be.log if e[2] == r]
+        assert seqs == sorted(seqs)
