@@ -23,6 +23,12 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "vm_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 NO_KEY = 0xFFFFFFFF
+# Eq. (4) and Alg. 1 thresholds of the paper: N_th = 3 neighbour points,
+# theta_th = 15 degrees (cos 15 deg = (sqrt 6 + sqrt 2) / 4, rounded to fp64),
+# d_th = 0.05 m
+N_TH = 3
+COS_15 = float.fromhex("0x1.ee8dd4748bf15p-1")
+D_TH = 0.05
 
 
 def build(force: bool = True) -> str:
@@ -64,6 +70,12 @@ def lib() -> ctypes.CDLL:
         L.vo_hull.restype = i64
         L.vo_hull_project.argtypes = [P, P, P, i64, P, P, P]
         L.vo_hull_project.restype = None
+        L.vo_jacobi3.argtypes = [P, P]
+        L.vo_jacobi3.restype = None
+        L.vo_classify.argtypes = [P, P, i64, P, ctypes.c_int32, u32, f64, P, P, P]
+        L.vo_classify.restype = None
+        L.vo_ccl_gated.argtypes = [P, P, P, P, i64, P, f64, f64, P]
+        L.vo_ccl_gated.restype = i64
         _lib = L
     return _lib
 
@@ -172,6 +184,41 @@ def hull_project(x, y, z, plane) -> Tuple[np.ndarray, np.ndarray]:
     return u, v
 
 
+def jacobi3(A) -> Tuple[np.ndarray, np.ndarray]:
+    """(diagonal after the cyclic Jacobi sweeps, eigenvectors as columns)."""
+    a = np.array(A, dtype=np.float64).reshape(3, 3).copy(order="C")
+    v = np.empty((3, 3), np.float64)
+    lib().vo_jacobi3(_p(a), _p(v))
+    return np.diag(a).copy(), v
+
+
+def classify(keys, mu, dims, radius: int = 1, n_th: int = N_TH, cos_th: float = COS_15):
+    """Eq. (3)-(4) for every occupied voxel: (normal float32[n,3], steppable
+    bool[n], neighbour count uint32[n])."""
+    keys, mu = _c(keys, np.uint32), _c(mu, np.float32).reshape(-1, 3)
+    n = len(keys)
+    nrm = np.empty((n, 3), np.float32)
+    st = np.empty(n, np.uint8)
+    nb = np.empty(n, np.uint32)
+    lib().vo_classify(_p(keys), _p(mu), n, _p(_c(dims, np.int32)), int(radius), int(n_th), float(cos_th), _p(nrm),
+                      _p(st), _p(nb))
+    return nrm, st.astype(bool), nb
+
+
+def ccl_gated(keys, mu, normal, steppable, dims, d_th: float = D_TH, cos_th: float = COS_15):
+    """Alg. 1 with its gates: (labels uint32[n], NO_KEY for voxels that are not
+    steppable; number of components)."""
+    keys, mu = _c(keys, np.uint32), _c(mu, np.float32).reshape(-1, 3)
+    normal = _c(normal, np.float32).reshape(-1, 3)
+    st = _c(np.asarray(steppable).astype(np.uint8), np.uint8)
+    lab = np.empty(len(keys), np.uint32)
+    nc = lib().vo_ccl_gated(_p(keys), _p(mu), _p(normal), _p(st), len(keys), _p(_c(dims, np.int32)), float(d_th),
+                            float(cos_th), _p(lab))
+    if nc < 0:
+        raise MemoryError("oracle gated CCL allocation failed")
+    return lab, int(nc)
+
+
 # --------------------------------------------------------------------------
 # the map and the per-frame path
 # --------------------------------------------------------------------------
@@ -220,7 +267,11 @@ class Clusters:
 def group(keys: np.ndarray, labels: np.ndarray, mu: np.ndarray, min_cluster: int) -> Clusters:
     """Voxels sharing a label form a cluster (Sec. III-C, clustering); clusters
     below ``min_cluster`` voxels are dropped; clusters are ordered by label and
-    the voxels of a cluster by key (both inputs are in ascending key order)."""
+    the voxels of a cluster by key (both inputs are in ascending key order).
+    Voxels labelled NO_KEY (not steppable) belong to no cluster."""
+    sel0 = np.nonzero(labels != NO_KEY)[0]
+    if len(sel0) != len(labels):
+        keys, labels, mu = keys[sel0], labels[sel0], mu[sel0]
     uniq, inv, counts = np.unique(labels, return_inverse=True, return_counts=True)
     keep = counts[inv] >= min_cluster
     sel = np.nonzero(keep)[0]
@@ -282,10 +333,32 @@ def planes_and_hulls(off, xyz, tag, n_hyp: int, eps: float, seed: int, frame, ks
     return [done[k] for k in ks]
 
 
+@dataclasses.dataclass
+class Steppable:
+    normal: np.ndarray       # float32[n, 3] per occupied voxel
+    steppable: np.ndarray    # bool[n]
+    n_nb: np.ndarray         # uint32[n] neighbour points
+
+
 def segment(m: OracleMap, min_cluster: int, n_hyp: int, eps: float, seed: int, frame: int,
-            cluster_subset: Optional[List[int]] = None, threads: int = 1) -> FrameResult:
+            cluster_subset: Optional[List[int]] = None, threads: int = 1,
+            steppable: Optional[dict] = None) -> FrameResult:
     """Sec. III-C on the whole accumulated map: label, group, then one plane
-    and one hull per kept cluster (optionally only for ``cluster_subset``)."""
+    and one hull per kept cluster (optionally only for ``cluster_subset``).
+    With ``steppable`` (dict of radius, n_th, cos_th, d_th) the voxels are
+    classified first (Eq. (3)-(4)) and only steppable voxels are clustered,
+    with Alg. 1's distance and normal-angle gates; the classification is
+    returned in the result's ``steppable`` field."""
+    if steppable is not None:
+        mu = m.means()
+        nrm, st, nb = classify(m.key, mu, m.dims, steppable.get("radius", 1), steppable.get("n_th", N_TH),
+                               steppable.get("cos_th", COS_15))
+        labels, _ = ccl_gated(m.key, mu, nrm, st, m.dims, steppable.get("d_th", D_TH), steppable.get("cos_th", COS_15))
+        cl = group(m.key, labels, mu, min_cluster)
+        res = planes_and_hulls(cl.off, cl.xyz, cl.tag, n_hyp, eps, seed, frame, cluster_subset, threads)
+        fr = FrameResult(labels, cl, res)
+        fr.steppable = Steppable(nrm, st, nb)
+        return fr
     labels, _ = ccl26(m.key, m.dims)
     cl = group(m.key, labels, m.means(), min_cluster)
     res = planes_and_hulls(cl.off, cl.xyz, cl.tag, n_hyp, eps, seed, frame, cluster_subset, threads)

@@ -399,3 +399,185 @@ int64_t vo_hull(const float* x, const float* y, const float* z, int64_t m, const
     free(uu); free(vv); free(p); free(st);
     return h;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Sec. III-C "Steppable point classification", Eq. (3) and Eq. (4).       */
+/* ------------------------------------------------------------------------ */
+
+/* index of key k among the n ascending keys, or -1 */
+static int64_t find_key(const uint32_t* keys, int64_t n, uint32_t k)
+{
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (keys[mid] < k) lo = mid + 1;
+        else hi = mid;
+    }
+    return (lo < n && keys[lo] == k) ? lo : -1;
+}
+
+/* Cyclic Jacobi method for a symmetric 3x3 matrix (Golub & Van Loan): rotations
+ * in the planes (0,1), (0,2), (1,2) in turn, each annihilating one
+ * off-diagonal entry with the symmetric Schur rotation, sweeps repeated until
+ * the off-diagonal part is negligible against the diagonal (at most 16).  On
+ * return A is (nearly) diagonal and the columns of V are the eigenvectors. */
+void vo_jacobi3(double A[3][3], double V[3][3])
+{
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) V[i][j] = (i == j) ? 1.0 : 0.0;
+    static const int P[3] = {0, 0, 1}, Q[3] = {1, 2, 2};
+    for (int sweep = 0; sweep < 16; ++sweep) {
+        const double off = A[0][1] * A[0][1] + A[0][2] * A[0][2] + A[1][2] * A[1][2];
+        const double dia = A[0][0] * A[0][0] + A[1][1] * A[1][1] + A[2][2] * A[2][2];
+        if (off <= 1e-30 * dia) break;
+        for (int r = 0; r < 3; ++r) {
+            const int p = P[r], q = Q[r];
+            const double apq = A[p][q];
+            if (apq == 0.0) continue;
+            /* the rotation angle: cot(2 theta) = tau, t = tan(theta), the smaller root */
+            const double tau = (A[q][q] - A[p][p]) / (2.0 * apq);
+            const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+            const double c = 1.0 / sqrt(1.0 + t * t);
+            const double s = t * c;
+            /* A <- J^T A J and V <- V J, J the identity but for
+             * J[p][p] = c, J[p][q] = s, J[q][p] = -s, J[q][q] = c */
+            for (int k = 0; k < 3; ++k) {
+                const double akp = A[k][p], akq = A[k][q];
+                A[k][p] = c * akp - s * akq;
+                A[k][q] = s * akp + c * akq;
+            }
+            for (int k = 0; k < 3; ++k) {
+                const double apk = A[p][k], aqk = A[q][k];
+                A[p][k] = c * apk - s * aqk;
+                A[q][k] = s * apk + c * aqk;
+            }
+            for (int k = 0; k < 3; ++k) {
+                const double vkp = V[k][p], vkq = V[k][q];
+                V[k][p] = c * vkp - s * vkq;
+                V[k][q] = s * vkp + c * vkq;
+            }
+        }
+    }
+}
+
+void vo_classify(const uint32_t* keys, const float* mu, int64_t n, const int32_t dims[3], int32_t radius,
+                 uint32_t n_th, double cos_th, float* normal, uint8_t* steppable, uint32_t* n_nb)
+{
+    const int64_t NX = dims[0], NY = dims[1], NZ = dims[2];
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t k = keys[i];
+        const int64_t x = k % NX, y = (k / NX) % NY, z = k / (NX * NY);
+        /* the neighbour points, in ascending key order (i itself included) */
+        double px[125], py[125], pz[125];
+        uint32_t cnt = 0;
+        for (int dz = -radius; dz <= radius; ++dz)
+            for (int dy = -radius; dy <= radius; ++dy)
+                for (int dx = -radius; dx <= radius; ++dx) {
+                    const int64_t xx = x + dx, yy = y + dy, zz = z + dz;
+                    if (xx < 0 || yy < 0 || zz < 0 || xx >= NX || yy >= NY || zz >= NZ) continue;
+                    const int64_t j = find_key(keys, n, (uint32_t)(xx + NX * (yy + NY * zz)));
+                    if (j < 0) continue;
+                    px[cnt] = mu[3 * j + 0];
+                    py[cnt] = mu[3 * j + 1];
+                    pz[cnt] = mu[3 * j + 2];
+                    ++cnt;
+                }
+        /* their scatter matrix about their mean (the covariance up to a factor) */
+        double mx = 0.0, my = 0.0, mz = 0.0;
+        for (uint32_t a = 0; a < cnt; ++a) {
+            mx += px[a];
+            my += py[a];
+            mz += pz[a];
+        }
+        mx /= (double)cnt;
+        my /= (double)cnt;
+        mz /= (double)cnt;
+        double A[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+        for (uint32_t a = 0; a < cnt; ++a) {
+            const double ex = px[a] - mx, ey = py[a] - my, ez = pz[a] - mz;
+            A[0][0] += ex * ex;
+            A[0][1] += ex * ey;
+            A[0][2] += ex * ez;
+            A[1][1] += ey * ey;
+            A[1][2] += ey * ez;
+            A[2][2] += ez * ez;
+        }
+        A[1][0] = A[0][1];
+        A[2][0] = A[0][2];
+        A[2][1] = A[1][2];
+        double V[3][3];
+        vo_jacobi3(A, V);
+        /* Eq. (3): the eigenvector of the smallest eigenvalue (first on ties),
+         * unit length, oriented to +z (then +y, then +x) */
+        int m = 0;
+        for (int e = 1; e < 3; ++e)
+            if (A[e][e] < A[m][m]) m = e;
+        double nx = V[0][m], ny = V[1][m], nz = V[2][m];
+        const double len = sqrt(nx * nx + ny * ny + nz * nz);
+        nx /= len;
+        ny /= len;
+        nz /= len;
+        if (nz < 0.0 || (nz == 0.0 && (ny < 0.0 || (ny == 0.0 && nx < 0.0)))) {
+            nx = -nx;
+            ny = -ny;
+            nz = -nz;
+        }
+        normal[3 * i + 0] = (float)nx;
+        normal[3 * i + 1] = (float)ny;
+        normal[3 * i + 2] = (float)nz;
+        /* Eq. (4): enough neighbours and a normal within theta_th of the vertical */
+        steppable[i] = (cnt >= n_th && nz >= cos_th) ? 1 : 0;
+        if (n_nb) n_nb[i] = cnt;
+    }
+}
+
+/* Alg. 1 with its gates, to its fixed point: among steppable voxels, i and j
+ * (26-neighbours) are adjacent when |mu_i - mu_j| < d_th and the angle
+ * between their normals is below theta_th (n_i . n_j > cos_th); label[i] is
+ * the smallest key of i's component, VO_NO_KEY for voxels that are not
+ * steppable.  Breadth-first search from each unlabelled steppable voxel in
+ * ascending key order.  Returns the number of components (-1: no memory). */
+int64_t vo_ccl_gated(const uint32_t* keys, const float* mu, const float* normal, const uint8_t* steppable,
+                     int64_t n, const int32_t dims[3], double d_th, double cos_th, uint32_t* label)
+{
+    const int64_t NX = dims[0], NY = dims[1], NZ = dims[2];
+    int64_t* queue = (int64_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+    if (!queue) return -1;
+    for (int64_t i = 0; i < n; ++i) label[i] = VO_NO_KEY;
+    const double d2_th = d_th * d_th;
+    int64_t ncomp = 0;
+    for (int64_t s = 0; s < n; ++s) {
+        if (!steppable[s] || label[s] != VO_NO_KEY) continue;
+        const uint32_t lab = keys[s];
+        int64_t head = 0, tail = 0;
+        queue[tail++] = s;
+        label[s] = lab;
+        while (head < tail) {
+            const int64_t v = queue[head++];
+            const int64_t k = keys[v];
+            const int64_t x = k % NX, y = (k / NX) % NY, z = k / (NX * NY);
+            for (int dz = -1; dz <= 1; ++dz)
+                for (int dy = -1; dy <= 1; ++dy)
+                    for (int dx = -1; dx <= 1; ++dx) {
+                        if (!dx && !dy && !dz) continue;
+                        const int64_t xx = x + dx, yy = y + dy, zz = z + dz;
+                        if (xx < 0 || yy < 0 || zz < 0 || xx >= NX || yy >= NY || zz >= NZ) continue;
+                        const int64_t u = find_key(keys, n, (uint32_t)(xx + NX * (yy + NY * zz)));
+                        if (u < 0 || !steppable[u] || label[u] != VO_NO_KEY) continue;
+                        const double ddx = (double)mu[3 * v] - (double)mu[3 * u];
+                        const double ddy = (double)mu[3 * v + 1] - (double)mu[3 * u + 1];
+                        const double ddz = (double)mu[3 * v + 2] - (double)mu[3 * u + 2];
+                        if (!(ddx * ddx + ddy * ddy + ddz * ddz < d2_th)) continue;
+                        const double dot = (double)normal[3 * v] * (double)normal[3 * u] +
+                                           (double)normal[3 * v + 1] * (double)normal[3 * u + 1] +
+                                           (double)normal[3 * v + 2] * (double)normal[3 * u + 2];
+                        if (!(dot > cos_th)) continue;
+                        label[u] = lab;
+                        queue[tail++] = u;
+                    }
+        }
+        ++ncomp;
+    }
+    free(queue);
+    return ncomp;
+}

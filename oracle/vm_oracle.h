@@ -82,6 +82,29 @@ int64_t vo_hull(const float* x, const float* y, const float* z, int64_t m, const
 void vo_hull_project(const float* x, const float* y, const float* z, int64_t m,
                      const float plane[4], double* u_out, double* v_out);
 
+/* Cyclic Jacobi eigen-decomposition of a symmetric 3x3 matrix (fp64): A is
+ * diagonalised in place, V receives the eigenvectors as columns. */
+void vo_jacobi3(double A[3][3], double V[3][3]);
+
+/* Sec. III-C "Steppable point classification", Eq. (3)-(4).  For each of the
+ * n occupied voxels (keys strictly ascending, means mu float32 xyz): the
+ * neighbour points are the means of the occupied voxels at most `radius`
+ * cells away on every axis (itself included, visited in ascending key
+ * order), N their number (n_nb, optional); the normal is the unit eigenvector
+ * of the smallest eigenvalue of their scatter matrix about their mean (fp64,
+ * vo_jacobi3), oriented to +z (ties +y, +x), rounded to float32;
+ * steppable = N >= n_th and n_z >= cos_th.  radius 1..2. */
+void vo_classify(const uint32_t* keys, const float* mu, int64_t n, const int32_t dims[3], int32_t radius,
+                 uint32_t n_th, double cos_th, float* normal, uint8_t* steppable, uint32_t* n_nb);
+
+/* Alg. 1 with its distance and normal-angle gates, to its fixed point:
+ * steppable 26-neighbours i, j are adjacent when |mu_i - mu_j|^2 < d_th^2 and
+ * n_i . n_j > cos_th (float32 normals, fp64 arithmetic); label = smallest key
+ * of the component, VO_NO_KEY for voxels that are not steppable.  Returns the
+ * number of components, -1 on allocation failure. */
+int64_t vo_ccl_gated(const uint32_t* keys, const float* mu, const float* normal, const uint8_t* steppable,
+                     int64_t n, const int32_t dims[3], double d_th, double cos_th, uint32_t* label);
+
 #ifdef __cplusplus
 }
 #endif
