@@ -70,6 +70,10 @@ def lib() -> ctypes.CDLL:
         L.vo_hull.restype = i64
         L.vo_hull_project.argtypes = [P, P, P, i64, P, P, P]
         L.vo_hull_project.restype = None
+        L.vo_ray_voxels.argtypes = [P, P, P, P, i64]
+        L.vo_ray_voxels.restype = i64
+        L.vo_clear_rays.argtypes = [P, P, P, i64, P, i64, P, P, P, f64, P]
+        L.vo_clear_rays.restype = i64
         L.vo_jacobi3.argtypes = [P, P]
         L.vo_jacobi3.restype = None
         L.vo_classify.argtypes = [P, P, i64, P, ctypes.c_int32, u32, f64, P, P, P]
@@ -184,6 +188,16 @@ def hull_project(x, y, z, plane) -> Tuple[np.ndarray, np.ndarray]:
     return u, v
 
 
+def ray_voxels(a, b, dims) -> np.ndarray:
+    """Voxel coordinates [m, 3] of the ray from voxel a to voxel b (Bresenham,
+    a included, b excluded, cut at the grid's faces)."""
+    a, b = _c(a, np.int64), _c(b, np.int64)
+    cap = int(np.abs(b - a).max()) + 1
+    out = np.empty((cap, 3), np.int64)
+    m = lib().vo_ray_voxels(_p(a), _p(b), _p(_c(dims, np.int32)), _p(out), cap)
+    return out[:m].copy()
+
+
 def jacobi3(A) -> Tuple[np.ndarray, np.ndarray]:
     """(diagonal after the cyclic Jacobi sweeps, eigenvectors as columns)."""
     a = np.array(A, dtype=np.float64).reshape(3, 3).copy(order="C")
@@ -254,6 +268,22 @@ class OracleMap:
 
     def means(self) -> np.ndarray:
         return voxel_mean(self.key, self.cnt, self.sums, self.origin, self.voxel_size, self.dims)
+
+    def clear_rays(self, xyz: np.ndarray, R=None, t=None) -> int:
+        """Eq. (2) for one frame: remove the occupied voxels the frame's rays
+        pass through (the sensor at the pose's translation), except those
+        holding one of its points.  Returns the number removed."""
+        R = np.eye(3) if R is None else R
+        t = np.zeros(3) if t is None else t
+        xyz = _c(xyz, np.float32).reshape(-1, 3)
+        n0 = len(self.key)
+        key, cnt, sums = self.key.copy(), self.cnt.copy(), self.sums.copy()
+        n = lib().vo_clear_rays(_p(key), _p(cnt), _p(sums), n0, _p(xyz), len(xyz), _p(_c(R, np.float64)),
+                                _p(_c(t, np.float64)), _p(self.origin), self.voxel_size, _p(self.dims))
+        if n < 0:
+            raise ValueError("sensor outside the grid (or no memory)")
+        self.key, self.cnt, self.sums = key[:n].copy(), cnt[:n].copy(), sums[:n].copy()
+        return n0 - int(n)
 
 
 @dataclasses.dataclass

@@ -581,3 +581,121 @@ int64_t vo_ccl_gated(const uint32_t* keys, const float* mu, const float* normal,
     free(queue);
     return ncomp;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Sec. III-B "Voxel information clearing", Eq. (2).                         */
+/* ------------------------------------------------------------------------ */
+
+/* floor(q / 2^20) of an integral fp64 value q */
+static int64_t voxel_index(double q)
+{
+    const int64_t v = (int64_t)q;
+    return v >= 0 ? v / 1048576 : -((-v + 1048575) / 1048576);
+}
+
+/* The voxels of a ray from voxel a to voxel b: the 3D Bresenham line (the
+ * axis with the largest extent drives, x before y before z on ties; each
+ * minor axis steps when its error term reaches zero), a included, b
+ * excluded, cut where it leaves the grid.  Writes at most cap voxel
+ * coordinates (xyz triples) and returns their number. */
+int64_t vo_ray_voxels(const int64_t a[3], const int64_t b[3], const int32_t dims[3], int64_t* out, int64_t cap)
+{
+    int64_t p[3] = {a[0], a[1], a[2]};
+    int64_t d[3], sgn[3];
+    for (int k = 0; k < 3; ++k) {
+        const int64_t v = b[k] - a[k];
+        d[k] = v < 0 ? -v : v;
+        sgn[k] = v < 0 ? -1 : 1;
+    }
+    int m = 0;                                   /* driving axis */
+    if (d[1] > d[m]) m = 1;
+    if (d[2] > d[m]) m = 2;
+    const int u = (m + 1) % 3, w = (m + 2) % 3;  /* the minor axes */
+    int64_t eu = 2 * d[u] - d[m], ew = 2 * d[w] - d[m];
+    int64_t cnt = 0;
+    for (int64_t step = 0; step < d[m]; ++step) {
+        if (p[0] < 0 || p[1] < 0 || p[2] < 0 || p[0] >= dims[0] || p[1] >= dims[1] || p[2] >= dims[2]) break;
+        if (cnt < cap) {
+            out[3 * cnt + 0] = p[0];
+            out[3 * cnt + 1] = p[1];
+            out[3 * cnt + 2] = p[2];
+        }
+        ++cnt;
+        if (eu >= 0) {
+            p[u] += sgn[u];
+            eu -= 2 * d[m];
+        }
+        if (ew >= 0) {
+            p[w] += sgn[w];
+            ew -= 2 * d[m];
+        }
+        eu += 2 * d[u];
+        ew += 2 * d[w];
+        p[m] += sgn[m];
+    }
+    return cnt;
+}
+
+/* Eq. (2) for one frame: every occupied voxel that a ray from the sensor
+ * (the pose's translation t) to one of the frame's points passes through is
+ * cleared, unless it holds one of the frame's points itself.  Rays run on
+ * voxel indices, from the sensor's voxel to the point's voxel (the floor of
+ * the fp64 transformed coordinates, as in vo_voxelize); points that are not
+ * finite cast no ray.  The map arrays (keys ascending) are filtered in place;
+ * returns the new occupied count, or -1 (no memory, or the sensor outside
+ * the grid). */
+int64_t vo_clear_rays(uint32_t* key, uint32_t* cnt, uint64_t* sum, int64_t n, const float* xyz, int64_t npts,
+                      const double R[9], const double t[3], const double origin[3], double voxel_size,
+                      const int32_t dims[3])
+{
+    const int64_t NX = dims[0], NY = dims[1], NZ = dims[2];
+    const int64_t ncell = NX * NY * NZ;
+    uint8_t* mark = (uint8_t*)calloc((size_t)ncell, 1);   /* 1: on a ray, 2: a point's own voxel */
+    int64_t* path = (int64_t*)malloc(sizeof(int64_t) * 3 * (size_t)(NX + NY + NZ + 3));
+    if (!mark || !path) { free(mark); free(path); return -1; }
+    /* voxel indices exactly as vo_voxelize finds them: the 2^-20-voxel
+     * fixed-point coordinate, then its integer part (floor division) */
+    const double inv_q = 1048576.0 / voxel_size;
+    int64_t s[3];
+    for (int k = 0; k < 3; ++k) s[k] = voxel_index(floor((t[k] - origin[k]) * inv_q));
+    if (s[0] < 0 || s[1] < 0 || s[2] < 0 || s[0] >= NX || s[1] >= NY || s[2] >= NZ) {
+        free(mark);
+        free(path);
+        return -1;
+    }
+    for (int64_t i = 0; i < npts; ++i) {
+        const double px = xyz[3 * i], py = xyz[3 * i + 1], pz = xyz[3 * i + 2];
+        const double w[3] = {fma(R[2], pz, fma(R[1], py, fma(R[0], px, t[0]))),
+                             fma(R[5], pz, fma(R[4], py, fma(R[3], px, t[1]))),
+                             fma(R[8], pz, fma(R[7], py, fma(R[6], px, t[2])))};
+        if (!isfinite(w[0]) || !isfinite(w[1]) || !isfinite(w[2])) continue;
+        int64_t e[3];
+        int inside = 1;
+        for (int k = 0; k < 3; ++k) {
+            const double f = floor((w[k] - origin[k]) * inv_q);
+            if (f < -1e15 || f > 1e15) { inside = -1; break; }   /* no ray to a point this far */
+            e[k] = voxel_index(f);
+            if (e[k] < 0 || e[k] >= dims[k]) inside = 0;
+        }
+        if (inside < 0) continue;
+        if (inside) mark[e[0] + NX * (e[1] + NY * e[2])] = 2;
+        const int64_t np = vo_ray_voxels(s, e, dims, path, NX + NY + NZ + 3);
+        for (int64_t q = 0; q < np; ++q) {
+            const int64_t c = path[3 * q] + NX * (path[3 * q + 1] + NY * path[3 * q + 2]);
+            if (mark[c] == 0) mark[c] = 1;
+        }
+    }
+    int64_t m = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (mark[key[i]] == 1) continue;         /* cleared: on a ray, holding none of the frame's points */
+        key[m] = key[i];
+        cnt[m] = cnt[i];
+        sum[3 * m + 0] = sum[3 * i + 0];
+        sum[3 * m + 1] = sum[3 * i + 1];
+        sum[3 * m + 2] = sum[3 * i + 2];
+        ++m;
+    }
+    free(mark);
+    free(path);
+    return m;
+}

@@ -105,6 +105,21 @@ void vo_classify(const uint32_t* keys, const float* mu, int64_t n, const int32_t
 int64_t vo_ccl_gated(const uint32_t* keys, const float* mu, const float* normal, const uint8_t* steppable,
                      int64_t n, const int32_t dims[3], double d_th, double cos_th, uint32_t* label);
 
+/* Sec. III-B "Voxel information clearing": the voxels of the ray from voxel a
+ * to voxel b on the 3D Bresenham line (largest extent drives, ties x, y, z),
+ * a included, b excluded, cut where it leaves the grid; up to cap xyz
+ * triples in out; returns their number. */
+int64_t vo_ray_voxels(const int64_t a[3], const int64_t b[3], const int32_t dims[3], int64_t* out, int64_t cap);
+
+/* Eq. (2) for one frame (pose R, t; the sensor at t, inside the grid):
+ * occupied voxels on the ray of any of the frame's points and holding none
+ * of them are removed from the map arrays (filtered in place, keys stay
+ * ascending).  Returns the new voxel count, -1 on allocation failure or a
+ * sensor outside the grid. */
+int64_t vo_clear_rays(uint32_t* key, uint32_t* cnt, uint64_t* sum, int64_t n, const float* xyz, int64_t npts,
+                      const double R[9], const double t[3], const double origin[3], double voxel_size,
+                      const int32_t dims[3]);
+
 #ifdef __cplusplus
 }
 #endif
