@@ -180,6 +180,33 @@ typedef struct {
 vm_status vm_ccl(vm_map map, uint32_t min_cluster, uint32_t* d_labels, vm_clusters* out,
                  void* stream);
 
+/* ---- steppable points (Sec. III-C "Steppable point classification" and
+ *      "Clustering of steppable points") --------------------------------- */
+typedef struct {
+    uint32_t radius;   /* neighbourhood of Eq. (3): occupied voxels at most this many cells away on
+                          every axis (the voxel itself included); 1..2 */
+    uint32_t n_th;     /* Eq. (4)'s N_th: least neighbour points of a steppable voxel (3) */
+    double   cos_th;   /* cos of theta_th (15 deg): Eq. (4) needs n_z >= cos_th; Alg. 1's angle gate
+                          needs n_i . n_j > cos_th; in [-1, 1] */
+    double   d_th;     /* Alg. 1's distance gate |mu_i - mu_j| < d_th, metres (0.05), > 0 */
+} vm_step_params;
+
+/* Eq. (3)-(4) for every occupied voxel of `map`: the normal is the unit
+ * eigenvector of the smallest eigenvalue (cyclic Jacobi, fp64) of the scatter
+ * matrix of the neighbour voxels' means about their mean (gathered in
+ * ascending key order), oriented to +z (ties +y, +x), rounded to float32; a
+ * voxel is steppable when it has at least n_th neighbour points and
+ * n_z >= cos_th.  Then Alg. 1 over the steppable voxels with both gates, to
+ * its fixed point: every steppable voxel gets the smallest key of its gated
+ * component; voxels that are not steppable belong to no cluster.  Then the
+ * grouping of vm_ccl (components of at least min_cluster voxels, ordered by
+ * label).  Optional outputs, ascending key order, sized by the occupied
+ * count: d_normal (float32 x 3), d_steppable (uint8), d_labels (0xFFFFFFFF
+ * where not steppable).  The map allocates its classification buffers on the
+ * first call (VM_E_STATE if that first call is captured).  Asynchronous. */
+vm_status vm_ccl_steppable(vm_map map, const vm_step_params* sp, uint32_t min_cluster, float* d_normal,
+                           uint8_t* d_steppable, uint32_t* d_labels, vm_clusters* out, void* stream);
+
 /* ---- planes (Sec. III-C "Multi-plane estimation") --------------------- */
 typedef struct {
     uint32_t n_hyp;      /* hypotheses per cluster, 1..65536 */
@@ -372,6 +399,13 @@ typedef struct {
 vm_status vm_segment_frame(vm_map map, const float* d_xyz, int64_t n, const vm_pose* pose,
                            const vm_seg_params* params, vm_planes* planes, vm_hulls_out* hulls,
                            uint32_t* d_labels, vm_clusters* clusters_out, void* stream);
+
+/* vm_segment_frame with vm_ccl_steppable in place of vm_ccl: the paper's
+ * full Sec. III-C path (classification, gated clustering, planes, polygons). */
+vm_status vm_segment_frame_steppable(vm_map map, const float* d_xyz, int64_t n, const vm_pose* pose,
+                                     const vm_seg_params* params, const vm_step_params* sp, vm_planes* planes,
+                                     vm_hulls_out* hulls, uint32_t* d_labels, vm_clusters* clusters_out,
+                                     void* stream);
 
 /* ---- graph capture and replay ------------------------------------------- */
 /* Record the library calls enqueued on `stream` between vm_capture_begin and

@@ -26,7 +26,8 @@ EXPORTED = [
     "vm_map_stats_async",
     "vm_insert", "vm_map_export", "vm_map_import", "vm_ccl", "vm_workspace_bytes", "vm_ransac_planes",
     "vm_ransac_planes_noalloc", "vm_planes_hulls", "vm_set_fused_config", "vm_get_fused_config",
-    "vm_autotune_fused", "vm_planes_hulls_multi", "vm_multi_workspace_bytes",
+    "vm_autotune_fused", "vm_planes_hulls_multi", "vm_multi_workspace_bytes", "vm_ccl_steppable",
+    "vm_segment_frame_steppable",
     "vm_hulls", "vm_segment_frame", "vm_set_stage_timing", "vm_stage_times",
     "vm_set_count_config", "vm_get_count_config", "vm_autotune_count",
     "vm_capture_begin", "vm_capture_end", "vm_graph_launch", "vm_graph_destroy",
@@ -83,6 +84,19 @@ class CountConfig(ctypes.Structure):
 
     def as_dict(self) -> dict:
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
+class StepParams(ctypes.Structure):
+    _fields_ = [("radius", ctypes.c_uint32), ("n_th", ctypes.c_uint32), ("cos_th", ctypes.c_double),
+                ("d_th", ctypes.c_double)]
+
+
+# the paper's thresholds: N_th = 3, theta_th = 15 deg (cos = (sqrt 6 + sqrt 2) / 4 in fp64), d_th = 0.05 m
+COS_15 = float.fromhex("0x1.ee8dd4748bf15p-1")
+
+
+def step_params(radius: int = 1, n_th: int = 3, cos_th: float = COS_15, d_th: float = 0.05) -> StepParams:
+    return StepParams(int(radius), int(n_th), float(cos_th), float(d_th))
 
 
 class FusedConfig(ctypes.Structure):
@@ -144,6 +158,10 @@ def lib() -> ctypes.CDLL:
             "vm_segment_frame": ([_P, _P, i64, ctypes.POINTER(Pose), ctypes.POINTER(SegParams),
                                   ctypes.POINTER(Planes), ctypes.POINTER(HullsOut), _P, ctypes.POINTER(Clusters), _P],
                                  i32),
+            "vm_ccl_steppable": ([_P, ctypes.POINTER(StepParams), u32, _P, _P, _P, ctypes.POINTER(Clusters), _P], i32),
+            "vm_segment_frame_steppable": ([_P, _P, i64, ctypes.POINTER(Pose), ctypes.POINTER(SegParams),
+                                            ctypes.POINTER(StepParams), ctypes.POINTER(Planes), ctypes.POINTER(HullsOut),
+                                            _P, ctypes.POINTER(Clusters), _P], i32),
             "vm_capture_begin": ([_P], i32),
             "vm_capture_end": ([_P, ctypes.POINTER(_P)], i32),
             "vm_graph_launch": ([_P, _P], i32),
@@ -356,18 +374,35 @@ class Map:
         _check(lib().vm_ccl(self._h, int(min_cluster), _ptr(labels), ctypes.byref(cl), _stream(stream)), "vm_ccl")
         return cl
 
+    def ccl_steppable(self, min_cluster: int = 30, step: Optional[StepParams] = None, normals=None, steppable=None,
+                      labels=None, stream=None) -> Clusters:
+        """vm_ccl_steppable: classification, gated clustering, grouping.  normals (float32 [V, 3]),
+        steppable (uint8 [V]) and labels (int32 [V]) are optional device outputs."""
+        cl = Clusters()
+        stp = step_params() if step is None else step
+        _check(lib().vm_ccl_steppable(self._h, ctypes.byref(stp), int(min_cluster), _ptr(normals), _ptr(steppable),
+                                      _ptr(labels), ctypes.byref(cl), _stream(stream)), "vm_ccl_steppable")
+        return cl
+
     def segment_frame(self, xyz, planes: PlaneBuffers, hulls: HullBuffers, R=None, t=None, min_cluster: int = 30,
                       n_hyp: int = 256, eps: float = 0.01, seed: int = 0x5EED, frame: int = 0, labels=None,
-                      stream=None, d_frame=None) -> Clusters:
+                      stream=None, d_frame=None, step: Optional[StepParams] = None) -> Clusters:
+        """vm_segment_frame, or vm_segment_frame_steppable when ``step`` is given."""
         pose = make_pose(R, t)
         sp = SegParams(int(min_cluster), 0, ransac_params(n_hyp, eps, seed, frame, d_frame))
         cl = Clusters()
         pc, hc = planes.c(), hulls.c()
         n = 0 if xyz is None else int(xyz.shape[0])
-        st = lib().vm_segment_frame(self._h, _ptr(xyz) if n else None, n, ctypes.byref(pose), ctypes.byref(sp),
-                                    ctypes.byref(pc), ctypes.byref(hc), _ptr(labels), ctypes.byref(cl),
-                                    _stream(stream))
-        _check(st, "vm_segment_frame")
+        if step is None:
+            st = lib().vm_segment_frame(self._h, _ptr(xyz) if n else None, n, ctypes.byref(pose), ctypes.byref(sp),
+                                        ctypes.byref(pc), ctypes.byref(hc), _ptr(labels), ctypes.byref(cl),
+                                        _stream(stream))
+            _check(st, "vm_segment_frame")
+        else:
+            st = lib().vm_segment_frame_steppable(self._h, _ptr(xyz) if n else None, n, ctypes.byref(pose),
+                                                  ctypes.byref(sp), ctypes.byref(step), ctypes.byref(pc),
+                                                  ctypes.byref(hc), _ptr(labels), ctypes.byref(cl), _stream(stream))
+            _check(st, "vm_segment_frame_steppable")
         return cl
 
 

@@ -31,6 +31,9 @@ struct vm_map_s {
     uint32_t work_k = 0, work_hyp = 0;
     bool have_clusters = false;
     uint32_t last_min_cluster = 1;
+    // classification buffers (allocated on the first steppable call)
+    StepBuffers sb{};
+    void* step_mem = nullptr;
 };
 
 namespace vm {
@@ -128,6 +131,14 @@ void map_free_all(vm_map m)
     m->allocs.clear();
     if (m->work) (void)hipFree(m->work);
     m->work = nullptr;
+    if (m->step_mem) (void)hipFree(m->step_mem);
+    m->step_mem = nullptr;
+}
+
+bool step_params_ok(const vm_step_params* sp)
+{
+    return sp && sp->radius >= 1 && sp->radius <= 2 && sp->cos_th >= -1.0 && sp->cos_th <= 1.0 && sp->d_th > 0.0 &&
+           sp->d_th < 1e30;
 }
 
 Pose pose_of(const vm_pose* p)
@@ -396,6 +407,42 @@ vm_status vm_ccl(vm_map m, uint32_t min_cluster, uint32_t* d_labels, vm_clusters
     }
     VM_HIP(launch_ccl(m->g, m->bits, m->b, m->cap, m->ctr, s));
     VM_HIP(launch_group(m->g, m->h, m->b, m->cap, min_cluster, d_labels, m->ctr, s));
+    m->have_clusters = true;
+    m->last_min_cluster = min_cluster;
+    if (out) fill_cluster_view(m, min_cluster, out);
+    return VM_OK;
+}
+
+vm_status vm_ccl_steppable(vm_map m, const vm_step_params* sp, uint32_t min_cluster, float* d_normal,
+                           uint8_t* d_steppable, uint32_t* d_labels, vm_clusters* out, void* stream)
+{
+    if (!m || !step_params_ok(sp)) return VM_E_ARG;
+    if (min_cluster < 1) min_cluster = 1;
+    hipStream_t s = (hipStream_t)stream;
+    if (!m->step_mem) {
+        if (capturing(s)) return VM_E_STATE;   // no allocation inside a capture
+        const size_t cap = m->cap;
+        if (hipMalloc(&m->step_mem, cap * 16 * 2 + cap + 256) != hipSuccess) {
+            (void)hipGetLastError();
+            m->step_mem = nullptr;
+            return VM_E_OOM;
+        }
+        char* p = (char*)m->step_mem;
+        m->sb.mean = (float4*)p;
+        m->sb.normal = (float4*)(p + cap * 16);
+        m->sb.step = (uint8_t*)(p + cap * 32);
+    }
+    {
+        StageScope t(VM_STAGE_RANK, s);
+        VM_HIP(launch_rank(m->g, m->bits, m->b, m->cap, m->ctr, s));
+    }
+    {
+        StageScope t(VM_STAGE_CCL, s);
+        VM_HIP(launch_steppable(m->g, m->h, m->bits, m->b, m->cap, m->sb, sp->radius, sp->n_th, sp->cos_th, sp->d_th,
+                                d_normal, d_steppable, m->ctr, s));
+    }
+    VM_HIP(launch_group(m->g, m->h, m->b, m->cap, min_cluster, nullptr, m->ctr, s));
+    if (d_labels) VM_HIP(launch_step_labels(m->b, m->sb, m->cap, m->ctr, d_labels, s));
     m->have_clusters = true;
     m->last_min_cluster = min_cluster;
     if (out) fill_cluster_view(m, min_cluster, out);
@@ -683,9 +730,34 @@ vm_status vm_hulls(const vm_clusters* cl, const vm_planes* planes, vm_hulls_out*
     return hulls(*cl, *planes, *out, w, (hipStream_t)stream);
 }
 
+namespace {
+vm_status segment_frame_impl(vm_map m, const float* d_xyz, int64_t n, const vm_pose* pose, const vm_seg_params* params,
+                             const vm_step_params* sp, vm_planes* planes, vm_hulls_out* hulls_out, uint32_t* d_labels,
+                             vm_clusters* clusters_out, void* stream);
+}
+
 vm_status vm_segment_frame(vm_map m, const float* d_xyz, int64_t n, const vm_pose* pose, const vm_seg_params* params,
                            vm_planes* planes, vm_hulls_out* hulls_out, uint32_t* d_labels, vm_clusters* clusters_out,
                            void* stream)
+{
+    return segment_frame_impl(m, d_xyz, n, pose, params, nullptr, planes, hulls_out, d_labels, clusters_out, stream);
+}
+
+vm_status vm_segment_frame_steppable(vm_map m, const float* d_xyz, int64_t n, const vm_pose* pose,
+                                     const vm_seg_params* params, const vm_step_params* sp, vm_planes* planes,
+                                     vm_hulls_out* hulls_out, uint32_t* d_labels, vm_clusters* clusters_out,
+                                     void* stream)
+{
+    if (!step_params_ok(sp)) return VM_E_ARG;
+    return segment_frame_impl(m, d_xyz, n, pose, params, sp, planes, hulls_out, d_labels, clusters_out, stream);
+}
+
+}  // extern "C"
+
+namespace {
+vm_status segment_frame_impl(vm_map m, const float* d_xyz, int64_t n, const vm_pose* pose, const vm_seg_params* params,
+                             const vm_step_params* sp, vm_planes* planes, vm_hulls_out* hulls_out, uint32_t* d_labels,
+                             vm_clusters* clusters_out, void* stream)
 {
     if (!m || !params || params->reserved != 0 || check_params(&params->ransac) != VM_OK) return VM_E_ARG;
     if (check_planes(planes, params->ransac.n_hyp) != VM_OK || check_hulls(hulls_out) != VM_OK) return VM_E_ARG;
@@ -713,7 +785,8 @@ vm_status vm_segment_frame(vm_map m, const float* d_xyz, int64_t n, const vm_pos
     vm_status st = vm_insert(m, d_xyz, n, pose, stream);
     if (st != VM_OK) return st;
     vm_clusters cl;
-    st = vm_ccl(m, minc, d_labels, &cl, stream);
+    st = sp ? vm_ccl_steppable(m, sp, minc, nullptr, nullptr, d_labels, &cl, stream)
+            : vm_ccl(m, minc, d_labels, &cl, stream);
     if (st != VM_OK) return st;
     if (clusters_out) *clusters_out = cl;
     const WorkLayout w = work_layout(m->work, kb, cl.n_cap, params->ransac.n_hyp);
@@ -722,6 +795,9 @@ vm_status vm_segment_frame(vm_map m, const float* d_xyz, int64_t n, const vm_pos
     if (st != VM_OK) return st;
     return hulls(cl, *planes, *hulls_out, w, (hipStream_t)stream);
 }
+}  // namespace
+
+extern "C" {
 
 vm_status vm_capture_begin(void* stream)
 {

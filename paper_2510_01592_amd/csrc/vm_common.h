@@ -305,6 +305,20 @@ hipError_t launch_ccl(const Geom& g, const uint32_t* bits, SegBuffers& b, uint32
 hipError_t launch_group(const Geom& g, const Hash& h, SegBuffers& b, uint32_t cap, uint32_t min_cluster,
                         uint32_t* d_labels, DevCounters* ctr, hipStream_t s);
 
+// ---- steppable classification and gated clustering (vm_step.hip) -------------
+struct StepBuffers {
+    float4* mean;      // [cap] Eq. (1) mean of each occupied voxel, by rank
+    float4* normal;    // [cap] Eq. (3) normal (xyz, pad)
+    uint8_t* step;     // [cap] Eq. (4) steppability
+};
+// classification of every ranked voxel, then the gated union-find and the
+// component sizes of steppable roots in b.parent / b.csize (ready for launch_group)
+hipError_t launch_steppable(const Geom& g, const Hash& h, const uint32_t* bits, SegBuffers& b, uint32_t cap,
+                            const StepBuffers& sb, uint32_t radius, uint32_t n_th, double cos_th, double d_th,
+                            float* d_normal, uint8_t* d_steppable, DevCounters* ctr, hipStream_t s);
+hipError_t launch_step_labels(const SegBuffers& b, const StepBuffers& sb, uint32_t cap, DevCounters* ctr,
+                              uint32_t* d_labels, hipStream_t s);
+
 // ---- RANSAC and hulls (vm_ransac.hip, vm_hull.hip) --------------------------
 constexpr int kHullDirs = 8;   // support directions of the hull pre-filter
 

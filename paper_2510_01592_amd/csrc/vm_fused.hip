@@ -220,21 +220,42 @@ union FusedLds {
 };
 
 // planes hb..he (at most 64) of the LDS chunk against the wave's rows of
-// points; lane q of the result holds the count of plane hb + q
+// points; lane q of the result holds the count of plane hb + q.  The planes
+// are read four at a time (their LDS loads are issued together) and counted
+// without a branch: a degenerate plane is NaN and passes no test.
+constexpr int kLdsBatch = 4;
+
+template <int R>
+__device__ __forceinline__ uint32_t plane_count(const float4 p, const float* px, const float* py, const float* pz,
+                                                float eps)
+{
+    uint32_t acc = 0;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        const float dd = fmaf(p.z, pz[j], fmaf(p.y, py[j], fmaf(p.x, px[j], p.w)));
+        acc += (uint32_t)__popcll(__ballot(fabsf(dd) < eps));
+    }
+    return acc;
+}
+
 template <int R>
 __device__ __forceinline__ uint32_t lds_batch(const float4* pl, uint32_t hb, uint32_t he, const float* px,
                                               const float* py, const float* pz, float eps, int lane)
 {
     uint32_t cv = 0;
-    for (uint32_t h = hb; h < he; ++h) {
-        const float4 p = pl[h];
-        if (p.x != p.x) continue;   // degenerate hypothesis
-        uint32_t acc = 0;
+    uint32_t h = hb;
+    for (; h + kLdsBatch <= he; h += kLdsBatch) {
+        float4 p[kLdsBatch];
 #pragma unroll
-        for (int j = 0; j < R; ++j) {
-            const float dd = fmaf(p.z, pz[j], fmaf(p.y, py[j], fmaf(p.x, px[j], p.w)));
-            acc += (uint32_t)__popcll(__ballot(fabsf(dd) < eps));
+        for (int b = 0; b < kLdsBatch; ++b) p[b] = pl[h + b];
+#pragma unroll
+        for (int b = 0; b < kLdsBatch; ++b) {
+            const uint32_t acc = plane_count<R>(p[b], px, py, pz, eps);
+            cv = (lane == (int)(h + b - hb)) ? acc : cv;
         }
+    }
+    for (; h < he; ++h) {
+        const uint32_t acc = plane_count<R>(pl[h], px, py, pz, eps);
         cv = (lane == (int)(h - hb)) ? acc : cv;
     }
     return cv;
@@ -513,10 +534,25 @@ __global__ void __launch_bounds__(kFBlock) k_fused(FusedArgs a)
             for (uint32_t h = h0 + threadIdx.x; h < h1; h += kFBlock) {
                 const float4 pl = hyp_plane(a.X + base, a.Y + base, a.Z + base, n, h, tg, frame, a.seed);
                 w.hyp[(size_t)k * H + h] = pl;
-                uint32_t cnt = 0;
-                for (uint32_t i = 0; i < n; ++i) {
+                // points read eight at a time (broadcast LDS loads issued together)
+                uint32_t cnt = 0, i = 0;
+                for (; i + 8 <= n; i += 8) {
+                    float qx[8], qy[8], qz[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        qx[u] = L.s.x[i + u];
+                        qy[u] = L.s.y[i + u];
+                        qz[u] = L.s.z[i + u];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const float dd = fmaf(pl.z, qz[u], fmaf(pl.y, qy[u], fmaf(pl.x, qx[u], pl.w)));
+                        cnt += fabsf(dd) < a.eps ? 1u : 0u;   // a degenerate (NaN) plane never passes
+                    }
+                }
+                for (; i < n; ++i) {
                     const float dd = fmaf(pl.z, L.s.z[i], fmaf(pl.y, L.s.y[i], fmaf(pl.x, L.s.x[i], pl.w)));
-                    cnt += fabsf(dd) < a.eps ? 1u : 0u;   // a degenerate (NaN) plane never passes
+                    cnt += fabsf(dd) < a.eps ? 1u : 0u;
                 }
                 part[h] = (int32_t)cnt;
             }

@@ -105,6 +105,11 @@ def test_argument_errors_without_device_work():
                              None) == vm.VM_E_CAPACITY
     assert L.vm_planes_hulls(ctypes.byref(cl), ctypes.byref(ok), ctypes.byref(pl), ctypes.byref(hl), 8, 16,
                              None) == vm.VM_E_CAPACITY
+    # steppable path: parameter checks before anything else
+    for bad_sp in (vm.StepParams(0, 3, 0.9, 0.05), vm.StepParams(3, 3, 0.9, 0.05), vm.StepParams(1, 3, 1.5, 0.05),
+                   vm.StepParams(1, 3, 0.9, 0.0)):
+        assert L.vm_ccl_steppable(8, ctypes.byref(bad_sp), 30, None, None, None, None, None) == vm.VM_E_ARG
+    assert L.vm_ccl_steppable(None, ctypes.byref(vm.step_params()), 30, None, None, None, None, None) == vm.VM_E_ARG
     ms = (ctypes.c_double * 8)()
     n = (ctypes.c_uint64 * 8)()
     assert L.vm_stage_times(ms, n, -1) == vm.VM_E_ARG
@@ -121,6 +126,8 @@ def test_struct_layouts_match_header_sizes():
     assert ctypes.sizeof(vm.Clusters) == 8 + 7 * 8
     assert ctypes.sizeof(vm.Planes) == 8 + 8 * 8
     assert ctypes.sizeof(vm.HullsOut) == 8 + 5 * 8
+    assert ctypes.sizeof(vm.StepParams) == 8 + 2 * 8
+    assert vm.COS_15 == float.fromhex("0x1.ee8dd4748bf15p-1")
 
 
 def test_count_config_set_get_and_validation():
