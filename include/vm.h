@@ -5,6 +5,7 @@
  * Multi-Plane Segmentation Based on GPU Accelerated High-Resolution 3D Voxel
  * Mapping for Legged Robot Locomotion" (arXiv 2510.01592):
  *   vm_insert        Sec. III-B, Eq. (1)    points + pose -> sparse voxel map
+ *   vm_clear_rays    Sec. III-B, Eq. (2)    free the voxels the frame's rays cross
  *   vm_ccl           Sec. III-C, Alg. 1     occupied voxels -> component labels,
  *                                           clusters (grouping)
  *   vm_ransac_planes Sec. III-C (a)-(c)     one plane + inlier set per cluster
@@ -103,6 +104,7 @@ typedef struct {
                                  (a voxel with more than 1024 points in one batch may
                                  take more; 0 for calls small enough for per-point
                                  atomics) */
+    uint64_t voxels_cleared;  /* voxels cleared by vm_clear_rays since create/clear */
 } vm_map_stats_t;
 
 /* Allocate a map on the current device (hipMalloc; the map owns the memory
@@ -132,6 +134,26 @@ vm_status vm_map_stats_async(vm_map map, vm_map_stats_t* d_out, void* stream);
  * small ones update per point with integer atomics; both give the same map.  n = 0 is a no-op; n < 0 is
  * VM_E_ARG. */
 vm_status vm_insert(vm_map map, const float* d_xyz, int64_t n, const vm_pose* pose, void* stream);
+
+/* Sec. III-B "Voxel information clearing", Eq. (2): free space along the
+ * frame's rays.  The sensor sits at the pose's translation t; each of the n
+ * points (sensor frame, transformed as in vm_insert) casts a ray on voxel
+ * indices from the sensor's voxel to its own voxel: the 3D Bresenham line
+ * (the axis of largest extent drives, x before y before z on ties, a minor
+ * axis steps when its error term reaches zero), the sensor's voxel included,
+ * the point's voxel excluded, cut where the line leaves the grid.  Every
+ * occupied voxel on some ray that holds none of the frame's points becomes
+ * free: its count and sums return to zero and it leaves the occupancy index
+ * (its hash slot keeps the key, so a later vm_insert that lands there simply
+ * occupies it again).  The removal set is deduplicated in two bitmaps (cells
+ * on a ray, cells holding a point) before any slot is touched, so the result
+ * does not depend on point order or scheduling.  Non-finite points and
+ * points more than 10^15 quanta (s*2^-20) from the origin cast no ray.  Call
+ * it before vm_insert of the same frame.  VM_E_ARG if the sensor lies outside
+ * the grid or n < 0; the two bitmaps (2 * NX*NY*NZ/8 bytes) are allocated on
+ * the first call (VM_E_STATE if that first call is being captured, VM_E_OOM
+ * if the allocation fails). */
+vm_status vm_clear_rays(vm_map map, const float* d_xyz, int64_t n, const vm_pose* pose, void* stream);
 
 /* Export the occupied voxels in ascending key order (e.g. for checkpoints
  * and checks).  Synchronises `stream`.  Writes min(occupied, cap) entries:
@@ -388,11 +410,14 @@ size_t vm_multi_workspace_bytes(uint32_t k_cap, uint32_t n_cap, uint32_t n_hyp);
 /* ---- one frame (Sec. III-A overview) ------------------------------------ */
 typedef struct {
     uint32_t         min_cluster;   /* clusters below this many voxels are dropped (30) */
-    uint32_t         reserved;      /* must be 0 */
+    uint32_t         flags;         /* VM_SEG_* bits; others must be 0 */
     vm_ransac_params ransac;
 } vm_seg_params;
 
-/* vm_insert of the frame, then vm_ccl, vm_ransac_planes and vm_hulls over the
+#define VM_SEG_CLEAR_RAYS 0x1u   /* vm_clear_rays of the frame before its vm_insert */
+
+/* vm_insert of the frame (after vm_clear_rays of it when params->flags has
+ * VM_SEG_CLEAR_RAYS), then vm_ccl, vm_ransac_planes and vm_hulls over the
  * whole accumulated map, using the map's own workspace.  Outputs as for the
  * individual calls; d_labels and clusters_out may be NULL.  Asynchronous:
  * nothing waits for the host. */
@@ -439,7 +464,8 @@ vm_status vm_graph_destroy(vm_graph graph);
 #define VM_STAGE_COUNT       6   /* inlier counting (one kernel) */
 #define VM_STAGE_SELECT      7   /* best hypothesis, inlier CSR */
 #define VM_STAGE_HULL        8   /* polygons */
-#define VM_STAGE_N           9
+#define VM_STAGE_CLEAR       9   /* ray casting and voxel clearing */
+#define VM_STAGE_N           10
 vm_status vm_set_stage_timing(int32_t enable);
 vm_status vm_stage_times(double* ms_out, uint64_t* launches_out, int32_t n);
 

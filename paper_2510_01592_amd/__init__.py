@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libvm.so")
 
 VM_OK, VM_E_ARG, VM_E_OOM, VM_E_CAPACITY, VM_E_DEVICE, VM_E_STATE = 0, -1, -2, -3, -4, -5
 FLAG_HASH_FULL, FLAG_CLUSTERS_CAP, FLAG_INLIERS_CAP, FLAG_HULL_CAP = 0x1, 0x2, 0x4, 0x8
-STAGES = ["insert", "rank", "ccl", "ccl_link", "group", "hypotheses", "count", "select", "hull"]
+STAGES = ["insert", "rank", "ccl", "ccl_link", "group", "hypotheses", "count", "select", "hull", "clear"]
 
 EXPORTED = [
     "vm_status_string", "vm_version", "vm_map_create", "vm_map_destroy", "vm_map_clear", "vm_map_stats",
@@ -27,7 +27,7 @@ EXPORTED = [
     "vm_insert", "vm_map_export", "vm_map_import", "vm_ccl", "vm_workspace_bytes", "vm_ransac_planes",
     "vm_ransac_planes_noalloc", "vm_planes_hulls", "vm_set_fused_config", "vm_get_fused_config",
     "vm_autotune_fused", "vm_planes_hulls_multi", "vm_multi_workspace_bytes", "vm_ccl_steppable",
-    "vm_segment_frame_steppable",
+    "vm_segment_frame_steppable", "vm_clear_rays",
     "vm_hulls", "vm_segment_frame", "vm_set_stage_timing", "vm_stage_times",
     "vm_set_count_config", "vm_get_count_config", "vm_autotune_count",
     "vm_capture_begin", "vm_capture_end", "vm_graph_launch", "vm_graph_destroy",
@@ -50,7 +50,7 @@ class MapStats(ctypes.Structure):
     _fields_ = [("occupied", ctypes.c_uint64), ("points_in", ctypes.c_uint64),
                 ("points_dropped", ctypes.c_uint64), ("points_lost", ctypes.c_uint64),
                 ("status_flags", ctypes.c_uint32), ("hash_capacity_log2", ctypes.c_uint32),
-                ("last_touched", ctypes.c_uint64)]
+                ("last_touched", ctypes.c_uint64), ("voxels_cleared", ctypes.c_uint64)]
 
 
 class Clusters(ctypes.Structure):
@@ -75,7 +75,10 @@ class HullsOut(ctypes.Structure):
 
 
 class SegParams(ctypes.Structure):
-    _fields_ = [("min_cluster", ctypes.c_uint32), ("reserved", ctypes.c_uint32), ("ransac", RansacParams)]
+    _fields_ = [("min_cluster", ctypes.c_uint32), ("flags", ctypes.c_uint32), ("ransac", RansacParams)]
+
+
+SEG_CLEAR_RAYS = 0x1
 
 
 class CountConfig(ctypes.Structure):
@@ -136,6 +139,7 @@ def lib() -> ctypes.CDLL:
             "vm_map_stats": ([_P, _P, ctypes.POINTER(MapStats)], i32),
             "vm_map_stats_async": ([_P, _P, _P], i32),
             "vm_insert": ([_P, _P, i64, ctypes.POINTER(Pose), _P], i32),
+            "vm_clear_rays": ([_P, _P, i64, ctypes.POINTER(Pose), _P], i32),
             "vm_map_export": ([_P, _P, _P, _P, _P, u64, ctypes.POINTER(u64), _P], i32),
             "vm_map_import": ([_P, _P, _P, _P, u64, _P], i32),
             "vm_ccl": ([_P, u32, _P, ctypes.POINTER(Clusters), _P], i32),
@@ -348,6 +352,15 @@ class Map:
         _check(lib().vm_insert(self._h, _ptr(xyz), int(xyz.shape[0]), ctypes.byref(pose), _stream(stream)),
                "vm_insert")
 
+    def clear_rays(self, xyz, R=None, t=None, stream=None) -> None:
+        """vm_clear_rays: free the occupied voxels the frame's rays pass through
+        (the sensor at t), except those holding one of its points."""
+        if xyz.dtype.__str__() != "torch.float32" or xyz.dim() != 2 or xyz.shape[1] != 3:
+            raise ValueError("float32 [N, 3] tensor expected")
+        pose = make_pose(R, t)
+        _check(lib().vm_clear_rays(self._h, _ptr(xyz), int(xyz.shape[0]), ctypes.byref(pose), _stream(stream)),
+               "vm_clear_rays")
+
     def export(self, cap: Optional[int] = None, stream=None):
         """(key, count, sums, mean) of every occupied voxel, ascending keys (torch, device)."""
         import torch
@@ -386,10 +399,13 @@ class Map:
 
     def segment_frame(self, xyz, planes: PlaneBuffers, hulls: HullBuffers, R=None, t=None, min_cluster: int = 30,
                       n_hyp: int = 256, eps: float = 0.01, seed: int = 0x5EED, frame: int = 0, labels=None,
-                      stream=None, d_frame=None, step: Optional[StepParams] = None) -> Clusters:
-        """vm_segment_frame, or vm_segment_frame_steppable when ``step`` is given."""
+                      stream=None, d_frame=None, step: Optional[StepParams] = None,
+                      clear: bool = False) -> Clusters:
+        """vm_segment_frame, or vm_segment_frame_steppable when ``step`` is given;
+        ``clear`` casts the frame's rays first (VM_SEG_CLEAR_RAYS)."""
         pose = make_pose(R, t)
-        sp = SegParams(int(min_cluster), 0, ransac_params(n_hyp, eps, seed, frame, d_frame))
+        sp = SegParams(int(min_cluster), SEG_CLEAR_RAYS if clear else 0,
+                       ransac_params(n_hyp, eps, seed, frame, d_frame))
         cl = Clusters()
         pc, hc = planes.c(), hulls.c()
         n = 0 if xyz is None else int(xyz.shape[0])

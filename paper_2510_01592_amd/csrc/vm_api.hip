@@ -34,6 +34,8 @@ struct vm_map_s {
     // classification buffers (allocated on the first steppable call)
     StepBuffers sb{};
     void* step_mem = nullptr;
+    // ray and keep bitmaps of the clearing pass (allocated on the first call)
+    uint32_t* clr_mem = nullptr;
 };
 
 namespace vm {
@@ -133,6 +135,8 @@ void map_free_all(vm_map m)
     m->work = nullptr;
     if (m->step_mem) (void)hipFree(m->step_mem);
     m->step_mem = nullptr;
+    if (m->clr_mem) (void)hipFree(m->clr_mem);
+    m->clr_mem = nullptr;
 }
 
 bool step_params_ok(const vm_step_params* sp)
@@ -350,6 +354,7 @@ vm_status vm_map_stats(vm_map m, void* stream, vm_map_stats_t* out)
     out->status_flags = c.flags;
     out->hash_capacity_log2 = m->h.log2cap;
     out->last_touched = c.touched;
+    out->voxels_cleared = c.cleared;
     return VM_OK;
 }
 
@@ -366,6 +371,38 @@ vm_status vm_insert(vm_map m, const float* d_xyz, int64_t n, const vm_pose* pose
     if (n == 0) return VM_OK;
     StageScope t(VM_STAGE_INSERT, (hipStream_t)stream);
     VM_HIP(launch_insert(d_xyz, n, pose_of(pose), m->g, m->h, m->bits, m->ctr, m->ins, (hipStream_t)stream));
+    return VM_OK;
+}
+
+vm_status vm_clear_rays(vm_map m, const float* d_xyz, int64_t n, const vm_pose* pose, void* stream)
+{
+    if (!m || n < 0 || (n > 0 && !d_xyz) || !finite_pose(pose)) return VM_E_ARG;
+    // the sensor's voxel, found as a point's voxel is: the floor of the
+    // fixed-point coordinate, then its floor division by 2^20
+    const Pose q = pose_of(pose);
+    int32_t sv[3];
+    for (int k = 0; k < 3; ++k) {
+        const double f = floor((q.t[k] - m->g.origin[k]) * m->g.inv_q);
+        if (!(f >= 0.0 && f < (double)m->g.dims[k] * 1048576.0)) return VM_E_ARG;   // outside the grid
+        sv[k] = (int32_t)((int64_t)f >> 20);
+    }
+    hipStream_t s = (hipStream_t)stream;
+    if (!m->clr_mem) {
+        if (capturing(s)) return VM_E_STATE;   // no allocation inside a capture
+        const size_t bytes = (size_t)m->g.nwords * 4 * 2;
+        if (hipMalloc((void**)&m->clr_mem, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            m->clr_mem = nullptr;
+            return VM_E_OOM;
+        }
+        if (hipMemset(m->clr_mem, 0, bytes) != hipSuccess) {
+            (void)hipFree(m->clr_mem);
+            m->clr_mem = nullptr;
+            return VM_E_DEVICE;
+        }
+    }
+    StageScope t(VM_STAGE_CLEAR, s);
+    VM_HIP(launch_clear_rays(d_xyz, n, q, m->g, sv, m->h, m->bits, m->clr_mem, m->clr_mem + m->g.nwords, m->ctr, s));
     return VM_OK;
 }
 
@@ -759,7 +796,8 @@ vm_status segment_frame_impl(vm_map m, const float* d_xyz, int64_t n, const vm_p
                              const vm_step_params* sp, vm_planes* planes, vm_hulls_out* hulls_out, uint32_t* d_labels,
                              vm_clusters* clusters_out, void* stream)
 {
-    if (!m || !params || params->reserved != 0 || check_params(&params->ransac) != VM_OK) return VM_E_ARG;
+    if (!m || !params || (params->flags & ~VM_SEG_CLEAR_RAYS) != 0 || check_params(&params->ransac) != VM_OK)
+        return VM_E_ARG;
     if (check_planes(planes, params->ransac.n_hyp) != VM_OK || check_hulls(hulls_out) != VM_OK) return VM_E_ARG;
     if (n < 0 || (n > 0 && !d_xyz) || !finite_pose(pose)) return VM_E_ARG;
     const uint32_t minc = params->min_cluster < 1 ? 1 : params->min_cluster;
@@ -782,7 +820,12 @@ vm_status segment_frame_impl(vm_map m, const float* d_xyz, int64_t n, const vm_p
         m->work_k = k;
         m->work_hyp = hh;
     }
-    vm_status st = vm_insert(m, d_xyz, n, pose, stream);
+    vm_status st = VM_OK;
+    if (params->flags & VM_SEG_CLEAR_RAYS) {
+        st = vm_clear_rays(m, d_xyz, n, pose, stream);
+        if (st != VM_OK) return st;
+    }
+    st = vm_insert(m, d_xyz, n, pose, stream);
     if (st != VM_OK) return st;
     vm_clusters cl;
     st = sp ? vm_ccl_steppable(m, sp, minc, nullptr, nullptr, d_labels, &cl, stream)

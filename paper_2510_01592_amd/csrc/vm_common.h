@@ -31,7 +31,8 @@ struct DevCounters {
     unsigned long long touched;       // distinct voxels updated by the last insert call
     uint32_t sort_sel;                // buffer (0/1) holding the sorted insert batch
     uint32_t group_sel;               // buffer (0/1) holding the voxels sorted by cluster
-    uint32_t pad[9];
+    unsigned long long cleared;       // voxels cleared by ray casting since create/clear
+    uint32_t pad[7];
 };
 
 struct Geom {
@@ -318,6 +319,14 @@ hipError_t launch_steppable(const Geom& g, const Hash& h, const uint32_t* bits, 
                             float* d_normal, uint8_t* d_steppable, DevCounters* ctr, hipStream_t s);
 hipError_t launch_step_labels(const SegBuffers& b, const StepBuffers& sb, uint32_t cap, DevCounters* ctr,
                               uint32_t* d_labels, hipStream_t s);
+
+// ---- ray casting and clearing (vm_clear.hip) ---------------------------------
+// Eq. (2) for one frame: cast every point's ray from the sensor's voxel,
+// then free the occupied cells on a ray that hold none of the frame's points.
+// ray and keep are zero on entry (nwords words each) and zero again on exit.
+hipError_t launch_clear_rays(const float* xyz, int64_t n, const Pose& pose, const Geom& g, const int32_t sensor[3],
+                             const Hash& h, uint32_t* bits, uint32_t* ray, uint32_t* keep, DevCounters* ctr,
+                             hipStream_t s);
 
 // ---- RANSAC and hulls (vm_ransac.hip, vm_hull.hip) --------------------------
 constexpr int kHullDirs = 8;   // support directions of the hull pre-filter

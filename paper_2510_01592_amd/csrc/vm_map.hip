@@ -56,13 +56,7 @@ __global__ void __launch_bounds__(kBlock) k_insert(const float* __restrict__ xyz
             if (k == key) { ok = true; break; }
             if (k == kEmpty) {
                 const uint32_t old = atomicCAS(&h.slot[s].key, kEmpty, key);
-                if (old == kEmpty) {
-                    atomicOr(&bits[key >> 5], 1u << (key & 31));
-                    ++n_new;
-                    ok = true;
-                    break;
-                }
-                if (old == key) { ok = true; break; }
+                if (old == kEmpty || old == key) { ok = true; break; }
             }
             s = (s + 1) & h.mask;
         }
@@ -71,7 +65,13 @@ __global__ void __launch_bounds__(kBlock) k_insert(const float* __restrict__ xyz
             continue;
         }
         Slot* sl = &h.slot[s];
-        atomicAdd(&sl->cnt, 1u);
+        // the point that takes a slot's count from 0 marks the voxel occupied:
+        // a newly claimed slot, or one whose voxel was cleared (cleared voxels
+        // keep their key, so probe chains stay intact)
+        if (atomicAdd(&sl->cnt, 1u) == 0u) {
+            atomicOr(&bits[key >> 5], 1u << (key & 31));
+            ++n_new;
+        }
         atomicAdd(&sl->sum[0], (unsigned long long)(qx & 0xFFFFF));
         atomicAdd(&sl->sum[1], (unsigned long long)(qy & 0xFFFFF));
         atomicAdd(&sl->sum[2], (unsigned long long)(qz & 0xFFFFF));
@@ -249,13 +249,7 @@ __global__ void __launch_bounds__(kBlock) k_bucket_insert(const uint4* __restric
                     if (kk == k) { ok = true; break; }
                     if (kk == kEmpty) {
                         const uint32_t old = atomicCAS(&h.slot[sl].key, kEmpty, k);
-                        if (old == kEmpty) {
-                            atomicOr(&bits[k >> 5], 1u << (k & 31));
-                            ++n_new;
-                            ok = true;
-                            break;
-                        }
-                        if (old == k) { ok = true; break; }
+                        if (old == kEmpty || old == k) { ok = true; break; }
                     }
                     sl = (sl + 1) & h.mask;
                 }
@@ -272,6 +266,10 @@ __global__ void __launch_bounds__(kBlock) k_bucket_insert(const uint4* __restric
                 // the key is stored as claimed, not as loaded: a load served
                 // from a line fetched before the claim would read it empty
                 a.x = k;
+                if (a.y == 0u) {   // new, or cleared since: occupied again
+                    atomicOr(&bits[k >> 5], 1u << (k & 31));
+                    ++n_new;
+                }
                 a.y += tcnt[q];
                 a.z = (uint32_t)s0;
                 a.w = (uint32_t)(s0 >> 32);
@@ -418,6 +416,7 @@ __global__ void k_stats(const DevCounters* __restrict__ c, uint32_t log2cap, vm_
         out->points_lost = c->points_lost;
         out->status_flags = c->flags;
         out->hash_capacity_log2 = log2cap;
+        out->voxels_cleared = c->cleared;
     }
 }
 

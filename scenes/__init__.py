@@ -29,6 +29,7 @@ __all__ = [
     "scene_tiny", "scene_tiny_exact", "scene_full_map", "scene_stress",
     "frame_points", "identity_pose", "pose_inverse_apply",
     "random_walk_poses", "batched_clusters", "surface_pool", "stream_frame", "StreamFrame", "served_trace",
+    "raycast_frame",
 ]
 
 
@@ -329,6 +330,61 @@ def stream_frame(scene: Scene, pool: np.ndarray, frame_seed: int, n: int,
     pw = np.empty((n, 3), np.float64)
     pw[:n_surf] = pool[start:start + n_surf]
     pw[n_surf:] = rng.uniform(lo, scene.geom.hi, size=(n_out, 3))
+    if pose is not None:
+        pw = pose_inverse_apply(np.asarray(pose[0]), np.asarray(pose[1]), pw)
+    return np.ascontiguousarray(pw.astype(np.float32))
+
+
+def raycast_frame(scene: Scene, sensor, frame_seed: int, n: int,
+                  pose: Optional[Tuple[np.ndarray, np.ndarray]] = None, rects: Optional[List[Rect]] = None,
+                  outlier_frac: Optional[float] = None, max_range: float = 8.0) -> np.ndarray:
+    """A frame that a sensor at ``sensor`` (map frame) could have seen: ``n``
+    returns of rays with directions uniform on the sphere, each the first hit
+    among the scene's rectangles (``rects`` overrides them, e.g. for a moved
+    object) within ``max_range``, moved by N(0, sigma) along the ray; rays
+    that hit nothing return nothing.  A fraction ``outlier_frac`` (default:
+    the scene's) are spurious early returns at a uniform fraction in
+    [0.05, 0.95) of their ray's hit range.  With ``pose`` (map_from_sensor,
+    its translation normally ``sensor``) the points are returned in the
+    sensor frame; float32."""
+    rng = np.random.default_rng(frame_seed)
+    rs = scene.rects if rects is None else rects
+    o = np.asarray(sensor, dtype=np.float64)
+    C = np.array([r.centre for r in rs], np.float64)
+    A = np.array([r.axis_a for r in rs], np.float64)
+    B = np.array([r.axis_b for r in rs], np.float64)
+    N = np.cross(A, B)
+    N /= np.linalg.norm(N, axis=1, keepdims=True)
+    ha = np.array([r.half_a for r in rs])
+    hb = np.array([r.half_b for r in rs])
+    of = scene.outlier_frac if outlier_frac is None else float(outlier_frac)
+    out, have = [], 0
+    while have < n:
+        m = max(2 * (n - have), 4096)
+        d = rng.normal(size=(m, 3))
+        d /= np.linalg.norm(d, axis=1, keepdims=True)
+        best = np.full(m, np.inf)
+        for j in range(len(rs)):
+            den = d @ N[j]
+            with np.errstate(divide="ignore", invalid="ignore"):
+                t = ((C[j] - o) @ N[j]) / den
+            ok = (np.abs(den) > 1e-12) & (t > 1e-6) & (t < best) & (t <= max_range)
+            if not ok.any():
+                continue
+            q = o[None, :] + t[ok, None] * d[ok] - C[j][None, :]
+            inside = (np.abs(q @ A[j]) <= ha[j]) & (np.abs(q @ B[j]) <= hb[j])
+            idx = np.nonzero(ok)[0][inside]
+            best[idx] = t[idx]
+        hit = np.isfinite(best)
+        d, t = d[hit], best[hit]
+        k = min(len(t), n - have)
+        d, t = d[:k], t[:k]
+        r = t + rng.normal(0.0, scene.sigma, size=k)
+        spur = rng.uniform(size=k) < of
+        r[spur] = t[spur] * rng.uniform(0.05, 0.95, size=int(spur.sum()))
+        out.append(o[None, :] + r[:, None] * d)
+        have += k
+    pw = np.concatenate(out, axis=0)
     if pose is not None:
         pw = pose_inverse_apply(np.asarray(pose[0]), np.asarray(pose[1]), pw)
     return np.ascontiguousarray(pw.astype(np.float32))

@@ -317,7 +317,7 @@ def test_stage_timing(vm):
         m = vm.Map(g.origin, g.voxel_size, g.dims, 17)
         pb = vm.PlaneBuffers.alloc(64, 1 << 17, sc.n_hyp)
         hb = vm.HullBuffers.alloc(64, 1 << 17)
-        m.segment_frame(_t(pts), pb, hb, min_cluster=30, n_hyp=sc.n_hyp)
+        m.segment_frame(_t(pts), pb, hb, min_cluster=30, n_hyp=sc.n_hyp, clear=True)   # every stage runs
         ms, n = vm.stage_times()
     finally:
         vm.set_stage_timing(False)
