@@ -85,7 +85,8 @@ def main() -> int:
     ap.add_argument("--no-served", action="store_true", help="skip the multi-robot served measurement")
     ap.add_argument("--no-stress", action="store_true", help="skip the 0.005 m stress map")
     ap.add_argument("--served-seconds", type=float, default=4.0, help="span of the served arrival process")
-    ap.add_argument("--only", choices=["batched", "served", "stress"],
+    ap.add_argument("--no-clearing", action="store_true", help="skip the ray-cast clearing measurement")
+    ap.add_argument("--only", choices=["batched", "served", "stress", "clearing"],
                     help="run one side measurement alone (no headline line; for profiling)")
     ap.add_argument("--counters", action="store_true",
                     help="run only the frames, counting passes and a 256 MiB copy whose counters "
@@ -121,6 +122,9 @@ def main() -> int:
     if args.only == "stress":
         print(json.dumps({"stress": _stress(vm, torch, dev, stream, with_oracle=False)}), flush=True)
         return 0
+    if args.only == "clearing":
+        print(json.dumps({"clearing": _clearing(vm, torch, dev, stream)}), flush=True)
+        return 0
 
     sc = scenes.scene_full_map(1)
     g = sc.geom
@@ -147,7 +151,7 @@ def main() -> int:
     k_cap = 16384
     planes = vm.PlaneBuffers.alloc(k_cap, 1 << 23, H)
     hulls = vm.HullBuffers.alloc(k_cap, 1 << 22)
-    stats_dev = torch.zeros((n_frames + 1, 6), dtype=torch.int64, device=dev)
+    stats_dev = torch.zeros((n_frames + 1, vm.STATS_WORDS), dtype=torch.int64, device=dev)
     stage = torch.empty((sc.n_points, 3), dtype=torch.float32, device=dev)
     frame_t = torch.zeros(1, dtype=torch.int32, device=dev)
     kw = dict(min_cluster=minc, n_hyp=H, eps=eps, seed=seed)
@@ -178,7 +182,7 @@ def main() -> int:
 
     # ---- graph form: the frame captured once, replayed per frame ---------------
     restore()
-    stats_slot = torch.zeros(6, dtype=torch.int64, device=dev)
+    stats_slot = torch.zeros(vm.STATS_WORDS, dtype=torch.int64, device=dev)
     with torch.cuda.stream(stream):
         with vm.capture(stream) as cap:
             last["cl"] = m.segment_frame(stage, planes, hulls, d_frame=frame_t, stream=stream, **kw)
@@ -258,7 +262,7 @@ def main() -> int:
     restore()
     vm.set_stage_timing(True)
     n_stage = min(5, args.steps)
-    st_stats = torch.zeros((n_stage, 6), dtype=torch.int64, device=dev)
+    st_stats = torch.zeros((n_stage, vm.STATS_WORDS), dtype=torch.int64, device=dev)
     with torch.cuda.stream(stream):
         for i in range(n_stage):
             last["cl"] = m.segment_frame(frames[args.warmup + i], planes, hulls, frame=args.warmup + i,
@@ -330,6 +334,12 @@ def main() -> int:
         stress = _stress(vm, torch, dev, stream, with_oracle=not args.no_cpu_baseline)
         _log(f"stress: {json.dumps(stress)}")
 
+    # ---- ray-cast clearing: physically consistent frames, clear + insert + segment --
+    clearing = None
+    if not args.no_clearing:
+        clearing = _clearing(vm, torch, dev, stream)
+        _log(f"clearing: {json.dumps(clearing)}")
+
     # ---- the oracle on the host, bounded sample ---------------------------------
     cpu = None
     if not args.no_cpu_baseline:
@@ -377,6 +387,7 @@ def main() -> int:
         "batched": batched,
         "served": served,
         "stress": stress,
+        "clearing": clearing,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
@@ -689,7 +700,7 @@ def _stress(vm, torch, dev, stream, warm: int = 5, timed: int = 5, with_oracle: 
     host = [torch.from_numpy(p).pin_memory() for p in timed_pts]
     kw = dict(min_cluster=sc.min_cluster, n_hyp=H, eps=sc.eps, seed=0x5EED)
     lat, occ, kk = [], [], []
-    stats = torch.zeros(6, dtype=torch.int64, device=dev)
+    stats = torch.zeros(vm.STATS_WORDS, dtype=torch.int64, device=dev)
     with torch.cuda.stream(stream):
         # an untimed first frame (allocates the map's workspace)
         stage.copy_(host[0], non_blocking=True)
@@ -739,6 +750,66 @@ def _stress(vm, torch, dev, stream, warm: int = 5, timed: int = 5, with_oracle: 
 # ---------------------------------------------------------------------------
 # rocprofv3 counters: HBM traffic per kernel
 # ---------------------------------------------------------------------------
+def _clearing(vm, torch, dev, stream, n_distinct: int = 4, timed: int = 12):
+    """Sec. III-B's clearing on the full map: frames ray-cast from a sensor
+    about 1 m above the floor (each return the first surface hit, 5 % spurious
+    early returns), 1M points each; the map is segmented every frame with and
+    without VM_SEG_CLEAR_RAYS.  Reports the clearing stage's device time, the
+    frame time of both forms and how the occupied count evolves."""
+    import scenes
+    sc = scenes.scene_full_map(1)
+    g = sc.geom
+    t_gen = time.perf_counter()
+    poses = scenes.random_walk_poses(41, n_distinct, sigma_t=0.05, sigma_rot_deg=2.0)
+    lift = np.array([0.0, 0.0, 1.0])
+    frames = []
+    for f, (R, t) in enumerate(poses):
+        tt = t + lift
+        pts = scenes.raycast_frame(sc, tt, 600 + f, sc.n_points, pose=(R, tt))
+        frames.append((torch.from_numpy(pts).to(dev), R, tt))
+    gen_s = time.perf_counter() - t_gen
+    H, eps, minc = sc.n_hyp, sc.eps, sc.min_cluster
+    planes = vm.PlaneBuffers.alloc(16384, 1 << 23, H)
+    hulls = vm.HullBuffers.alloc(16384, 1 << 22)
+    out = {"workload": f"full map 400x400x200 at 0.01 m, {n_distinct} ray-cast frames of {sc.n_points} points "
+                       f"(sensor 1 m above the floor, random-walk poses) repeated, {timed} timed frames after "
+                       f"{n_distinct} warm-up frames", "generation_s": gen_s}
+    for clear in (True, False):
+        m = vm.Map(g.origin, g.voxel_size, g.dims, 23)
+        occ = []
+        with torch.cuda.stream(stream):
+            for f in range(n_distinct):
+                pts, R, t = frames[f]
+                m.segment_frame(pts, planes, hulls, R, t, min_cluster=minc, n_hyp=H, eps=eps, frame=f,
+                                stream=stream, clear=clear)
+            stream.synchronize()
+            ta = time.perf_counter()
+            for i in range(timed):
+                pts, R, t = frames[i % n_distinct]
+                m.segment_frame(pts, planes, hulls, R, t, min_cluster=minc, n_hyp=H, eps=eps, frame=100 + i,
+                                stream=stream, clear=clear)
+            stream.synchronize()
+            frame_ms = 1e3 * (time.perf_counter() - ta) / timed
+            vm.set_stage_timing(True)
+            for i in range(4):
+                pts, R, t = frames[i % n_distinct]
+                m.segment_frame(pts, planes, hulls, R, t, min_cluster=minc, n_hyp=H, eps=eps, frame=200 + i,
+                                stream=stream, clear=clear)
+                occ.append(int(m.stats(stream).occupied))
+            ms, _ = vm.stage_times()
+            vm.set_stage_timing(False)
+        st = m.stats(stream)
+        key = "with_clearing" if clear else "without_clearing"
+        out[key] = {"frame_ms": frame_ms, "stage_ms": {n: float(ms[j]) / 4 for j, n in enumerate(vm.STAGES)},
+                    "occupied_last_frames": occ, "voxels_cleared_total": int(st.voxels_cleared),
+                    "frames_total": n_distinct + timed + 4}
+        if clear:
+            c_ms = out[key]["stage_ms"]["clear"]
+            out[key]["rays_per_s"] = sc.n_points / (c_ms * 1e-3) if c_ms > 0 else None
+        m.close()
+    return out
+
+
 def _sha256(path: str) -> str:
     with open(path, "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()

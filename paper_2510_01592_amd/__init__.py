@@ -53,6 +53,10 @@ class MapStats(ctypes.Structure):
                 ("last_touched", ctypes.c_uint64), ("voxels_cleared", ctypes.c_uint64)]
 
 
+# vm_map_stats_t in 64-bit words (the size of a device buffer for Map.stats_async)
+STATS_WORDS = ctypes.sizeof(MapStats) // 8
+
+
 class Clusters(ctypes.Structure):
     _fields_ = [("k_cap", ctypes.c_uint32), ("n_cap", ctypes.c_uint32), ("d_meta", _P), ("d_off", _P),
                 ("d_x", _P), ("d_y", _P), ("d_z", _P), ("d_key", _P), ("d_tag", _P)]
@@ -340,7 +344,7 @@ class Map:
         return s
 
     def stats_async(self, out, stream=None) -> None:
-        """Enqueue the counters into ``out`` (device int64 tensor of >= 5 entries)."""
+        """Enqueue the counters into ``out`` (device int64 tensor of >= STATS_WORDS entries)."""
         if out.numel() * out.element_size() < ctypes.sizeof(MapStats):
             raise ValueError("stats buffer too small")
         _check(lib().vm_map_stats_async(self._h, _ptr(out), _stream(stream)), "vm_map_stats_async")

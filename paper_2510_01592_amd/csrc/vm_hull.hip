@@ -381,6 +381,160 @@ __global__ void __launch_bounds__(kBlock) k_hull_small(
     }
 }
 
+// Survivor sets beyond the LDS sort are thinned once more before sorting:
+// the extremes of the survivors in kRefineDirs directions (every 360/64
+// degrees, counter-clockwise) bound a convex polygon inside the hull, and the
+// survivors strictly inside it (by the same margin as the octagon's) are
+// dropped.  The hull of what is left is the same polygon, since every vertex
+// survives; a disc keeps about 0.2 % of its points outside a 64-gon.
+constexpr int kRefineDirs = 64;
+constexpr int kRefineBatch = 8;   // directions reduced per pass over the survivors
+
+struct RefineLds {
+    double rv[kChainBlock / kWave][kRefineBatch];
+    uint32_t ri[kChainBlock / kWave][kRefineBatch];
+    uint32_t ext[kRefineDirs];
+    double pu[kRefineDirs], pv[kRefineDirs];
+    double margin;
+    int np;
+    uint32_t wcnt[kChainBlock / kWave];
+};
+
+// compacts U/V/I[0, ns) in place to the points not strictly inside the
+// refinement polygon; returns their number (every thread of the block calls it)
+__device__ uint32_t refine_survivors(RefineLds& R, double* U, double* V, uint32_t* I, uint32_t ns)
+{
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    for (int d0 = 0; d0 < kRefineDirs; d0 += kRefineBatch) {
+        double cs[kRefineBatch], sn[kRefineBatch], bv[kRefineBatch];
+        uint32_t bi[kRefineBatch];
+#pragma unroll
+        for (int j = 0; j < kRefineBatch; ++j) {
+            sincospi((double)(d0 + j) / (kRefineDirs / 2), &sn[j], &cs[j]);
+            bv[j] = -INFINITY;
+            bi[j] = 0xFFFFFFFFu;
+        }
+        for (uint32_t t = threadIdx.x; t < ns; t += kChainBlock) {
+            const double u = U[t], v = V[t];
+#pragma unroll
+            for (int j = 0; j < kRefineBatch; ++j) {
+                const double val = u * cs[j] + v * sn[j];
+                if (val > bv[j]) {   // t ascends per thread: the first maximum is kept
+                    bv[j] = val;
+                    bi[j] = t;
+                }
+            }
+        }
+        // the largest value, lowest position on ties
+#pragma unroll
+        for (int j = 0; j < kRefineBatch; ++j) {
+            for (int o = kWave / 2; o > 0; o >>= 1) {
+                const double ov = __shfl_xor(bv[j], o, kWave);
+                const uint32_t oi = __shfl_xor(bi[j], o, kWave);
+                if (ov > bv[j] || (ov == bv[j] && oi < bi[j])) {
+                    bv[j] = ov;
+                    bi[j] = oi;
+                }
+            }
+            if (lane == 0) {
+                R.rv[wv][j] = bv[j];
+                R.ri[wv][j] = bi[j];
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x < kRefineBatch) {
+            const int j = threadIdx.x;
+            double b = R.rv[0][j];
+            uint32_t i = R.ri[0][j];
+            for (int w = 1; w < kChainBlock / kWave; ++w)
+                if (R.rv[w][j] > b || (R.rv[w][j] == b && R.ri[w][j] < i)) {
+                    b = R.rv[w][j];
+                    i = R.ri[w][j];
+                }
+            R.ext[d0 + j] = i;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        // the extremes in direction order, repeats merged, then pruned to
+        // strictly convex corners (as the octagon is)
+        int np = 0;
+        for (int d = 0; d < kRefineDirs; ++d)   // in place: np <= d
+            if (R.ext[d] < ns && (np == 0 || R.ext[np - 1] != R.ext[d])) R.ext[np++] = R.ext[d];
+        while (np > 1 && R.ext[np - 1] == R.ext[0]) --np;
+        double umin = INFINITY, umax = -INFINITY, vmin = INFINITY, vmax = -INFINITY;
+        for (int a = 0; a < np; ++a) {
+            R.pu[a] = U[R.ext[a]];
+            R.pv[a] = V[R.ext[a]];
+            umin = fmin(umin, R.pu[a]);
+            umax = fmax(umax, R.pu[a]);
+            vmin = fmin(vmin, R.pv[a]);
+            vmax = fmax(vmax, R.pv[a]);
+        }
+        const double span = np > 0 ? fmax(umax - umin, vmax - vmin) : 0.0;
+        const double margin = 1e-9 * span * span + 1e-300;
+        for (bool changed = np >= 3; changed && np >= 3;) {
+            changed = false;
+            for (int a = 0; a < np && np >= 3; ++a) {
+                const int b = (a + 1) % np, c = (a + 2) % np;
+                if (cross3(R.pu[a], R.pv[a], R.pu[b], R.pv[b], R.pu[c], R.pv[c]) <= margin) {
+                    for (int r = b; r + 1 < np; ++r) {
+                        R.pu[r] = R.pu[r + 1];
+                        R.pv[r] = R.pv[r + 1];
+                    }
+                    --np;
+                    changed = true;
+                }
+            }
+        }
+        R.margin = margin;
+        R.np = np;
+    }
+    __syncthreads();
+    const int np = R.np;
+    if (np < 3) return ns;
+    const double mg = R.margin;
+    // in-place compaction, a block-wide chunk at a time: every thread of a
+    // chunk has read its point before any is written, and writes land at or
+    // below the chunk's positions
+    uint32_t nout = 0;
+    for (uint32_t base = 0; base < ns; base += kChainBlock) {
+        const uint32_t t = base + threadIdx.x;
+        double u = 0.0, v = 0.0;
+        uint32_t id = 0;
+        bool keep = false;
+        if (t < ns) {
+            u = U[t];
+            v = V[t];
+            id = I[t];
+            bool inside = true;
+            for (int a = 0; inside && a < np; ++a) {
+                const int b = a + 1 == np ? 0 : a + 1;
+                inside = cross3(R.pu[a], R.pv[a], R.pu[b], R.pv[b], u, v) > mg;
+            }
+            keep = !inside;
+        }
+        const uint64_t bal = __ballot(keep);
+        const uint32_t below = (uint32_t)__popcll(bal & ((1ull << lane) - 1ull));
+        if (lane == 0) R.wcnt[wv] = (uint32_t)__popcll(bal);
+        __syncthreads();
+        uint32_t pre = 0, tot = 0;
+        for (int w = 0; w < kChainBlock / kWave; ++w) {
+            if (w < wv) pre += R.wcnt[w];
+            tot += R.wcnt[w];
+        }
+        if (keep) {
+            const uint32_t o = nout + pre + below;
+            U[o] = u;
+            V[o] = v;
+            I[o] = id;
+        }
+        nout += tot;
+        __syncthreads();
+    }
+    return nout;
+}
+
 __global__ void __launch_bounds__(kChainBlock) k_hull_chain(
     const uint32_t* __restrict__ small, const uint32_t* __restrict__ chain_list, const uint32_t* __restrict__ in_off,
     const uint32_t* __restrict__ in_idx, const uint32_t* __restrict__ surv_cnt, double* __restrict__ gu,
@@ -388,12 +542,14 @@ __global__ void __launch_bounds__(kChainBlock) k_hull_chain(
     uint32_t* __restrict__ hull_tmp, double* __restrict__ area_out)
 {
     __shared__ ChainLds<kLdsCap> L;
+    __shared__ RefineLds R;
     // the clusters with more than one wave of survivors, listed by k_hull_small
     const uint32_t nc = small[7];
     for (uint32_t c = blockIdx.x; c < nc; c += gridDim.x) {
         const uint32_t k = chain_list[c];
         const uint32_t ib = in_off[k];
-        const uint32_t ns = surv_cnt[k];
+        uint32_t ns = surv_cnt[k];
+        if (ns > (uint32_t)kLdsCap) ns = refine_survivors(R, gu + ib, gv + ib, gi + ib, ns);
         if (ns <= (uint32_t)kLdsCap) {
             double area = 0.0;
             const uint32_t hh = block_chain(L, ns,

@@ -253,9 +253,9 @@ class GpuBackend(Backend):
                           v_off=torch.empty(k_cap + 1, dtype=torch.int32).pin_memory(),
                           meta=torch.empty(2, dtype=torch.int32).pin_memory(),
                           status=torch.empty(2, dtype=torch.int32).pin_memory(),
-                          stats=torch.empty(6, dtype=torch.int64).pin_memory())
+                          stats=torch.empty(vm.STATS_WORDS, dtype=torch.int64).pin_memory())
                      for _ in range(n_slots)]
-        self.stats_dev = [torch.empty(6, dtype=torch.int64, device="cuda") for _ in range(n_slots)]
+        self.stats_dev = [torch.empty(vm.STATS_WORDS, dtype=torch.int64, device="cuda") for _ in range(n_slots)]
         self.capture = None
         if self.capture_cap:
             c = self.capture_cap

@@ -92,20 +92,28 @@ def compare_cluster(k: int, P: dict, Hh: dict, ref: oracle.ClusterResult, check_
 
 
 def hull_path_clusters():
-    """Discs (about a tenth of their inliers survive the octagon filter) and
-    rotated squares (few survivors) whose hulls reach every path: one wave,
-    the workgroup chain, and the sort in global memory; (off, xyz, tag)."""
+    """Discs (about a tenth of their inliers survive the octagon filter),
+    rotated squares (few survivors) and thin rings (nearly every point on the
+    hull) whose hulls reach every path: one wave, the workgroup chain, the
+    64-direction refinement of large survivor sets (the 30000- and
+    60000-point discs drop below the workgroup sort's size with it), and the
+    sort in global memory (the rings stay above it); (off, xyz, tag)."""
     rng = np.random.default_rng(33)
     parts = []
+    nrm = np.array([0.1, -0.2, 1.0]) / np.linalg.norm([0.1, -0.2, 1.0])
+    a = np.cross(nrm, [1.0, 0.0, 0.0])
+    a /= np.linalg.norm(a)
+    b = np.cross(nrm, a)
     for n in (40, 200, 700, 1500, 3000, 8000, 30000, 60000):
         rad = 0.0056 * np.sqrt(n)
         r = rad * np.sqrt(rng.random(n))
         th = rng.random(n) * 2 * np.pi
-        nrm = np.array([0.1, -0.2, 1.0]) / np.linalg.norm([0.1, -0.2, 1.0])
-        a = np.cross(nrm, [1.0, 0.0, 0.0])
-        a /= np.linalg.norm(a)
-        b = np.cross(nrm, a)
         p = (r * np.cos(th))[:, None] * a + (r * np.sin(th))[:, None] * b + rng.normal(0, 0.002, n)[:, None] * nrm
+        parts.append((p + [0.5, 0.5, 1.0]).astype(np.float32))
+    for n in (3000, 6000):
+        r = 0.3 + rng.normal(0, 1e-5, n)
+        th = rng.random(n) * 2 * np.pi
+        p = (r * np.cos(th))[:, None] * a + (r * np.sin(th))[:, None] * b
         parts.append((p + [0.5, 0.5, 1.0]).astype(np.float32))
     for n, ang in ((500, 0.3), (5000, 1.1)):
         s = (rng.random((n, 2)) - 0.5) * 0.01 * np.sqrt(n)

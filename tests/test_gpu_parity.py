@@ -9,7 +9,8 @@ import pytest
 
 import oracle
 import scenes
-from tests.gpu_util import (assert_map_equal, bits, cluster_tensors, compare_cluster, export_np, hulls_np, note,
+from tests.gpu_util import (assert_map_equal, bits, cluster_tensors, compare_cluster, export_np, hull_path_clusters,
+                            hulls_np, note,
                             planes_np, run_planes_and_hulls)
 
 pytestmark = pytest.mark.gpu
@@ -371,34 +372,13 @@ def test_many_clusters_both_launch_forms(vm):
 
 
 def test_hull_paths_by_survivor_count(vm):
-    """Discs keep about a tenth of their inliers past the octagon filter, so
-    these clusters reach every hull path: one wave (at most 64 points or
-    survivors), the workgroup chain with a one-wave sort (up to 256
-    survivors) and a workgroup sort (up to 2048), and the sort in global
-    memory beyond that.  Rotated squares keep few survivors.  All against the
-    oracle, vertex lists bit for bit."""
-    rng = np.random.default_rng(33)
-    parts = []
-    for n in (40, 200, 700, 1500, 3000, 8000, 30000, 60000):
-        rad = 0.0056 * np.sqrt(n)
-        r = rad * np.sqrt(rng.random(n))
-        th = rng.random(n) * 2 * np.pi
-        nrm = np.array([0.1, -0.2, 1.0]) / np.linalg.norm([0.1, -0.2, 1.0])
-        a = np.cross(nrm, [1.0, 0.0, 0.0])
-        a /= np.linalg.norm(a)
-        b = np.cross(nrm, a)
-        p = (r * np.cos(th))[:, None] * a + (r * np.sin(th))[:, None] * b + rng.normal(0, 0.002, n)[:, None] * nrm
-        parts.append((p + [0.5, 0.5, 1.0]).astype(np.float32))
-    for n, ang in ((500, 0.3), (5000, 1.1)):
-        s = (rng.random((n, 2)) - 0.5) * 0.01 * np.sqrt(n)
-        c, si = np.cos(ang), np.sin(ang)
-        uv = s @ np.array([[c, -si], [si, c]])
-        parts.append(np.c_[uv, rng.normal(0, 0.002, n)].astype(np.float32))
-    sizes = [len(p) for p in parts]
-    off = np.zeros(len(parts) + 1, np.uint32)
-    off[1:] = np.cumsum(sizes)
-    xyz = np.concatenate(parts)
-    tag = np.arange(len(parts), dtype=np.uint32) * 7717 + 5
+    """The clusters of hull_path_clusters reach every hull path: one wave (at
+    most 64 points or survivors), the workgroup chain with a one-wave sort (up
+    to 256 survivors) and a workgroup sort (up to 2048), the 64-direction
+    refinement of larger survivor sets, and the sort in global memory beyond
+    that.  All against the oracle, vertex lists bit for bit."""
+    off, xyz, tag = hull_path_clusters()
+    parts = [xyz[off[k]:off[k + 1]] for k in range(len(tag))]
     T = cluster_tensors(off, xyz, tag)
     cl = vm.cluster_view(T["off"], T["x"], T["y"], T["z"], T["tag"], T["meta"])
     H = 128
