@@ -86,7 +86,8 @@ def main() -> int:
     ap.add_argument("--no-stress", action="store_true", help="skip the 0.005 m stress map")
     ap.add_argument("--served-seconds", type=float, default=4.0, help="span of the served arrival process")
     ap.add_argument("--no-clearing", action="store_true", help="skip the ray-cast clearing measurement")
-    ap.add_argument("--only", choices=["batched", "served", "stress", "clearing"],
+    ap.add_argument("--no-ablation", action="store_true", help="skip the cluster-parallel ablation")
+    ap.add_argument("--only", choices=["batched", "served", "stress", "clearing", "ablation"],
                     help="run one side measurement alone (no headline line; for profiling)")
     ap.add_argument("--counters", action="store_true",
                     help="run only the frames, counting passes and a 256 MiB copy whose counters "
@@ -124,6 +125,9 @@ def main() -> int:
         return 0
     if args.only == "clearing":
         print(json.dumps({"clearing": _clearing(vm, torch, dev, stream)}), flush=True)
+        return 0
+    if args.only == "ablation":
+        print(json.dumps({"cluster_ablation": _cluster_ablation(vm, torch, dev, stream)}), flush=True)
         return 0
 
     sc = scenes.scene_full_map(1)
@@ -294,6 +298,11 @@ def main() -> int:
     _log("stage ms/frame: " + ", ".join(f"{k}={v:.3f}" for k, v in stage_ms.items()) +
          f"; counting pass alone {count_ms:.3f} ms for {tests / 1e6:.0f}M tests")
 
+    # ---- Alg. 1's label propagation against the union-find labelling (same map) --
+    restore()
+    ccl_cmp = _ccl_compare(vm, m, stream)
+    _log(f"ccl compare: {json.dumps(ccl_cmp)}")
+
     # ---- measured peaks (microbenchmarks, same run) --------------------------------
     peaks = _measured_peaks(torch, stream)
     _log(f"measured peaks: {peaks}")
@@ -333,6 +342,12 @@ def main() -> int:
     if not args.no_stress:
         stress = _stress(vm, torch, dev, stream, with_oracle=not args.no_cpu_baseline)
         _log(f"stress: {json.dumps(stress)}")
+
+    # ---- cluster-level parallelism: 1..16 clusters of 10k..30k points -------------
+    ablation = None
+    if not args.no_ablation:
+        ablation = _cluster_ablation(vm, torch, dev, stream)
+        _log(f"cluster ablation: {json.dumps(ablation)}")
 
     # ---- ray-cast clearing: physically consistent frames, clear + insert + segment --
     clearing = None
@@ -388,6 +403,8 @@ def main() -> int:
         "served": served,
         "stress": stress,
         "clearing": clearing,
+        "ccl_compare": ccl_cmp,
+        "cluster_ablation": ablation,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
@@ -750,6 +767,71 @@ def _stress(vm, torch, dev, stream, warm: int = 5, timed: int = 5, with_oracle: 
 # ---------------------------------------------------------------------------
 # rocprofv3 counters: HBM traffic per kernel
 # ---------------------------------------------------------------------------
+def _ccl_compare(vm, m, stream, reps: int = 5) -> dict:
+    """The map's labelling and grouping by union-find (vm_ccl) and by Alg. 1's
+    label propagation (vm_ccl_propagate, the host checking between batches of
+    sweeps); both give the same clusters."""
+    occ = int(m.stats(stream).occupied)
+    out = {"occupied": occ}
+    for name, fn in (("union_find", lambda: m.ccl(30, stream=stream)),
+                     ("label_propagation", lambda: m.ccl_propagate(30, stream=stream))):
+        fn()
+        stream.synchronize()
+        t_s = time.perf_counter()
+        r = None
+        for _ in range(reps):
+            r = fn()
+        stream.synchronize()
+        out[name] = {"ms": 1e3 * (time.perf_counter() - t_s) / reps}
+        if name == "label_propagation":
+            out[name]["sweeps"] = r[1]
+            out[name]["clusters"] = int(vm.read_clusters(r[0])["K"])
+        else:
+            out[name]["clusters"] = int(vm.read_clusters(r)["K"])
+    out["speedup_union_find"] = out["label_propagation"]["ms"] / out["union_find"]["ms"]
+    return out
+
+
+def _cluster_ablation(vm, torch, dev, stream, runs: int = 1000, n_hyp: int = 100) -> dict:
+    """Cluster-level parallelism (the paper's ablation of Sec. IV-C): sets of
+    1, 2, 4, 8 and 16 clusters of 10k..30k points (log-uniform), planes and
+    polygons of all clusters of a set in one call (vm_planes_hulls) against
+    one call per cluster in turn, each timed as the mean of `runs` runs with
+    I = 100 hypotheses."""
+    import scenes
+    out = {"workload": f"1..16 clusters of 10k..30k points, {n_hyp} hypotheses, mean of {runs} runs", "sets": []}
+    for nc in (1, 2, 4, 8, 16):
+        off, xyz = scenes.batched_clusters(seed=50 + nc, n_clusters=nc, n_min=10_000, n_max=30_000)
+        N = len(xyz)
+        cl, keep = vm.clusters_from_host(off, xyz, np.arange(nc, dtype=np.uint32))
+        singles = [vm.clusters_from_host(off[k:k + 2] - off[k], xyz[off[k]:off[k + 1]],
+                                         np.array([k], dtype=np.uint32)) for k in range(nc)]
+        work = torch.empty(vm.workspace_bytes(nc, N, n_hyp), dtype=torch.uint8, device=dev)
+        planes = vm.PlaneBuffers.alloc(nc, N, n_hyp)
+        hulls = vm.HullBuffers.alloc(nc, N)
+        with torch.cuda.stream(stream):
+            def together(f):
+                vm.planes_hulls(cl, vm.ransac_params(n_hyp, 0.01, 0x5EED, f), planes, hulls, work, stream=stream)
+
+            def one_by_one(f):
+                for c, _k in singles:
+                    vm.planes_hulls(c, vm.ransac_params(n_hyp, 0.01, 0x5EED, f), planes, hulls, work, stream=stream)
+
+            res = {}
+            for name, fn in (("all_clusters_one_call_ms", together), ("one_call_per_cluster_ms", one_by_one)):
+                fn(0)
+                stream.synchronize()
+                t_s = time.perf_counter()
+                for f in range(runs):
+                    fn(f)
+                stream.synchronize()
+                res[name] = 1e3 * (time.perf_counter() - t_s) / runs
+        del keep, singles
+        out["sets"].append({"clusters": nc, "points": N, **res,
+                            "speedup": res["one_call_per_cluster_ms"] / res["all_clusters_one_call_ms"]})
+    return out
+
+
 def _clearing(vm, torch, dev, stream, n_distinct: int = 4, timed: int = 12):
     """Sec. III-B's clearing on the full map: frames ray-cast from a sensor
     about 1 m above the floor (each return the first surface hit, 5 % spurious

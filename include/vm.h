@@ -202,6 +202,18 @@ typedef struct {
 vm_status vm_ccl(vm_map map, uint32_t min_cluster, uint32_t* d_labels, vm_clusters* out,
                  void* stream);
 
+/* Alg. 1 run as the paper runs it, as a comparison baseline for vm_ccl:
+ * every occupied voxel starts with its own key as label, and sweeps over the
+ * 26-adjacency (each edge once) let both ends of an edge take the smaller
+ * label with atomic minima, until a sweep changes no label.  The labels, the
+ * clusters and every output are those of vm_ccl (the same fixed point); the
+ * number of sweeps run, the last one changing nothing, goes to *sweeps
+ * (optional).  Synchronises `stream` between batches of sweeps (the host
+ * decides when to stop), so it cannot be captured (VM_E_STATE); a small flag
+ * buffer is allocated on the first call (VM_E_OOM if that fails). */
+vm_status vm_ccl_propagate(vm_map map, uint32_t min_cluster, uint32_t* d_labels, vm_clusters* out,
+                           uint32_t* sweeps, void* stream);
+
 /* ---- steppable points (Sec. III-C "Steppable point classification" and
  *      "Clustering of steppable points") --------------------------------- */
 typedef struct {

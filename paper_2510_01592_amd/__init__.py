@@ -27,7 +27,7 @@ EXPORTED = [
     "vm_insert", "vm_map_export", "vm_map_import", "vm_ccl", "vm_workspace_bytes", "vm_ransac_planes",
     "vm_ransac_planes_noalloc", "vm_planes_hulls", "vm_set_fused_config", "vm_get_fused_config",
     "vm_autotune_fused", "vm_planes_hulls_multi", "vm_multi_workspace_bytes", "vm_ccl_steppable",
-    "vm_segment_frame_steppable", "vm_clear_rays",
+    "vm_segment_frame_steppable", "vm_clear_rays", "vm_ccl_propagate",
     "vm_hulls", "vm_segment_frame", "vm_set_stage_timing", "vm_stage_times",
     "vm_set_count_config", "vm_get_count_config", "vm_autotune_count",
     "vm_capture_begin", "vm_capture_end", "vm_graph_launch", "vm_graph_destroy",
@@ -144,6 +144,7 @@ def lib() -> ctypes.CDLL:
             "vm_map_stats_async": ([_P, _P, _P], i32),
             "vm_insert": ([_P, _P, i64, ctypes.POINTER(Pose), _P], i32),
             "vm_clear_rays": ([_P, _P, i64, ctypes.POINTER(Pose), _P], i32),
+            "vm_ccl_propagate": ([_P, u32, _P, ctypes.POINTER(Clusters), ctypes.POINTER(u32), _P], i32),
             "vm_map_export": ([_P, _P, _P, _P, _P, u64, ctypes.POINTER(u64), _P], i32),
             "vm_map_import": ([_P, _P, _P, _P, u64, _P], i32),
             "vm_ccl": ([_P, u32, _P, ctypes.POINTER(Clusters), _P], i32),
@@ -390,6 +391,15 @@ class Map:
         cl = Clusters()
         _check(lib().vm_ccl(self._h, int(min_cluster), _ptr(labels), ctypes.byref(cl), _stream(stream)), "vm_ccl")
         return cl
+
+    def ccl_propagate(self, min_cluster: int = 30, labels=None, stream=None):
+        """vm_ccl_propagate (Alg. 1's label propagation, the union-find's baseline):
+        (clusters, sweeps run).  Synchronises the stream."""
+        cl = Clusters()
+        n = ctypes.c_uint32()
+        _check(lib().vm_ccl_propagate(self._h, int(min_cluster), _ptr(labels), ctypes.byref(cl), ctypes.byref(n),
+                                      _stream(stream)), "vm_ccl_propagate")
+        return cl, int(n.value)
 
     def ccl_steppable(self, min_cluster: int = 30, step: Optional[StepParams] = None, normals=None, steppable=None,
                       labels=None, stream=None) -> Clusters:

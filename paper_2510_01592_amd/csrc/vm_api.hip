@@ -36,6 +36,9 @@ struct vm_map_s {
     void* step_mem = nullptr;
     // ray and keep bitmaps of the clearing pass (allocated on the first call)
     uint32_t* clr_mem = nullptr;
+    // per-sweep change flags of label propagation (device) and their host copy
+    uint32_t* lp_flags = nullptr;
+    uint32_t* lp_host = nullptr;
 };
 
 namespace vm {
@@ -137,6 +140,10 @@ void map_free_all(vm_map m)
     m->step_mem = nullptr;
     if (m->clr_mem) (void)hipFree(m->clr_mem);
     m->clr_mem = nullptr;
+    if (m->lp_flags) (void)hipFree(m->lp_flags);
+    m->lp_flags = nullptr;
+    if (m->lp_host) (void)hipHostFree(m->lp_host);
+    m->lp_host = nullptr;
 }
 
 bool step_params_ok(const vm_step_params* sp)
@@ -446,6 +453,63 @@ vm_status vm_ccl(vm_map m, uint32_t min_cluster, uint32_t* d_labels, vm_clusters
     VM_HIP(launch_group(m->g, m->h, m->b, m->cap, min_cluster, d_labels, m->ctr, s));
     m->have_clusters = true;
     m->last_min_cluster = min_cluster;
+    if (out) fill_cluster_view(m, min_cluster, out);
+    return VM_OK;
+}
+
+vm_status vm_ccl_propagate(vm_map m, uint32_t min_cluster, uint32_t* d_labels, vm_clusters* out, uint32_t* sweeps,
+                           void* stream)
+{
+    if (!m) return VM_E_ARG;
+    if (min_cluster < 1) min_cluster = 1;
+    hipStream_t s = (hipStream_t)stream;
+    if (capturing(s)) return VM_E_STATE;   // the host decides when to stop
+    if (!m->lp_flags) {
+        if (hipMalloc((void**)&m->lp_flags, kLpBatchMax * 4) != hipSuccess) {
+            (void)hipGetLastError();
+            m->lp_flags = nullptr;
+            return VM_E_OOM;
+        }
+        if (hipHostMalloc((void**)&m->lp_host, kLpBatchMax * 4, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            m->lp_host = nullptr;
+            (void)hipFree(m->lp_flags);
+            m->lp_flags = nullptr;
+            return VM_E_OOM;
+        }
+    }
+    {
+        StageScope t(VM_STAGE_RANK, s);
+        VM_HIP(launch_rank(m->g, m->bits, m->b, m->cap, m->ctr, s));
+    }
+    uint32_t* label = m->b.sort_v[1];   // free until the grouping step
+    uint32_t total = 0;
+    {
+        StageScope t(VM_STAGE_CCL, s);
+        VM_HIP(launch_lp_init(m->b, m->cap, label, m->ctr, s));
+        // batches of 1, 2, 4, ... sweeps; the first sweep that changes nothing
+        // ends the loop (the sweeps after it in its batch change nothing either)
+        uint32_t batch = 1;
+        for (;;) {
+            VM_HIP(launch_lp_sweeps(m->g, m->bits, m->b, m->cap, label, m->lp_flags, batch, m->ctr, s));
+            VM_HIP(hipMemcpyAsync(m->lp_host, m->lp_flags, batch * 4, hipMemcpyDeviceToHost, s));
+            VM_HIP(hipStreamSynchronize(s));
+            uint32_t i = 0;
+            while (i < batch && m->lp_host[i]) ++i;
+            total += i < batch ? i + 1 : batch;
+            if (i < batch) break;
+            if (total > (1u << 24)) return VM_E_STATE;   // cannot happen: labels only decrease
+            batch = batch * 2 < kLpBatchMax ? batch * 2 : kLpBatchMax;
+        }
+    }
+    {
+        StageScope t(VM_STAGE_CCL_LINK, s);
+        VM_HIP(launch_lp_finish(m->bits, m->b, m->cap, label, m->ctr, s));
+    }
+    VM_HIP(launch_group(m->g, m->h, m->b, m->cap, min_cluster, d_labels, m->ctr, s));
+    m->have_clusters = true;
+    m->last_min_cluster = min_cluster;
+    if (sweeps) *sweeps = total;
     if (out) fill_cluster_view(m, min_cluster, out);
     return VM_OK;
 }

@@ -320,6 +320,15 @@ hipError_t launch_steppable(const Geom& g, const Hash& h, const uint32_t* bits, 
 hipError_t launch_step_labels(const SegBuffers& b, const StepBuffers& sb, uint32_t cap, DevCounters* ctr,
                               uint32_t* d_labels, hipStream_t s);
 
+// ---- label propagation (vm_propagate.hip) ------------------------------------
+constexpr uint32_t kLpBatchMax = 32;   // sweeps enqueued between two host checks
+hipError_t launch_lp_init(const SegBuffers& b, uint32_t cap, uint32_t* label, DevCounters* ctr, hipStream_t s);
+// `sweeps` (<= kLpBatchMax) sweeps; sweep i ORs 1 into changed[i] when it lowered a label
+hipError_t launch_lp_sweeps(const Geom& g, const uint32_t* bits, const SegBuffers& b, uint32_t cap, uint32_t* label,
+                            uint32_t* changed, uint32_t sweeps, DevCounters* ctr, hipStream_t s);
+hipError_t launch_lp_finish(const uint32_t* bits, SegBuffers& b, uint32_t cap, const uint32_t* label,
+                            DevCounters* ctr, hipStream_t s);
+
 // ---- ray casting and clearing (vm_clear.hip) ---------------------------------
 // Eq. (2) for one frame: cast every point's ray from the sensor's voxel,
 // then free the occupied cells on a ray that hold none of the frame's points.

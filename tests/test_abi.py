@@ -72,6 +72,7 @@ def test_argument_errors_without_device_work():
     assert L.vm_clear_rays(None, None, 0, None, None) == vm.VM_E_ARG
     assert L.vm_map_destroy(None) == vm.VM_E_ARG
     assert L.vm_ccl(None, 30, None, None, None) == vm.VM_E_ARG
+    assert L.vm_ccl_propagate(None, 30, None, None, None, None) == vm.VM_E_ARG
     # bad RANSAC parameters are rejected before any device pointer is touched
     cl = vm.Clusters(1, 1, 8, 8, 8, 8, 8, None, 8)
     pl = vm.Planes(1, 1, 8, 8, 8, 8, 8, None, None, 8)
