@@ -269,6 +269,24 @@ class OracleMap:
     def means(self) -> np.ndarray:
         return voxel_mean(self.key, self.cnt, self.sums, self.origin, self.voxel_size, self.dims)
 
+    def shift(self, dx: int, dy: int, dz: int) -> int:
+        """Sec. III-B's robot-centric map: the grid moves by (dx, dy, dz) whole
+        voxels.  The origin becomes origin + s * shift (fp64); voxel (x, y, z)
+        becomes (x - dx, y - dy, z - dz) with its count and sums unchanged;
+        voxels leaving the grid are dropped.  Returns how many were dropped."""
+        d = np.array([dx, dy, dz], np.int64)
+        NX, NY, NZ = (int(v) for v in self.dims)
+        k = self.key.astype(np.int64)
+        x, y, z = k % NX - d[0], (k // NX) % NY - d[1], k // (NX * NY) - d[2]
+        keep = (x >= 0) & (y >= 0) & (z >= 0) & (x < NX) & (y < NY) & (z < NZ)
+        nk = (x + NX * (y + NY * z))[keep]
+        order = np.argsort(nk, kind="stable")    # the order is kept anyway: a constant offset
+        self.key = nk[order].astype(np.uint32)
+        self.cnt = self.cnt[keep][order].copy()
+        self.sums = self.sums[keep][order].copy()
+        self.origin = np.array([self.origin[i] + float(d[i]) * self.voxel_size for i in range(3)], np.float64)
+        return int((~keep).sum())
+
     def clear_rays(self, xyz: np.ndarray, R=None, t=None) -> int:
         """Eq. (2) for one frame: remove the occupied voxels the frame's rays
         pass through (the sensor at the pose's translation), except those
