@@ -184,6 +184,16 @@ def main() -> int:
     _log(f"plain: {1e3 * t_plain / args.steps:.3f} ms/step, {plain_value / 1e6:.1f} M voxels/s, "
          f"occupied {occ[0]}..{occ[-1]}")
 
+    # ---- accuracy: plane IoU against the generator's rectangles (last frame) ------
+    iou = {"plain": _plane_iou(vm, sc, planes, hulls, last["cl"])}
+    with torch.cuda.stream(stream):
+        cl_st = m.segment_frame(frames[n_frames - 1], planes, hulls, frame=n_frames - 1, stream=stream,
+                                step=vm.step_params(), **kw)
+        stream.synchronize()
+    # the steppable path keeps only near-horizontal surfaces: scored on those
+    iou["steppable"] = _plane_iou(vm, sc, planes, hulls, cl_st, max_tilt_deg=15.0)
+    _log(f"plane IoU: {json.dumps(iou)}")
+
     # ---- graph form: the frame captured once, replayed per frame ---------------
     restore()
     stats_slot = torch.zeros(vm.STATS_WORDS, dtype=torch.int64, device=dev)
@@ -395,6 +405,7 @@ def main() -> int:
         "latency_ms": dict(lat_out, includes="H2D of the frame from pinned host memory, the frame, D2H of planes, "
                                              "areas, polygon offsets and status words",
                            occupied_at_end=lat_occ),
+        "plane_iou": iou,
         "stage_ms_per_frame": stage_ms,
         "roofline": roof,
         "rooflines": rooflines,
@@ -767,6 +778,26 @@ def _stress(vm, torch, dev, stream, warm: int = 5, timed: int = 5, with_oracle: 
 # ---------------------------------------------------------------------------
 # rocprofv3 counters: HBM traffic per kernel
 # ---------------------------------------------------------------------------
+def _plane_iou(vm, sc, planes, hulls, cl, max_tilt_deg: float = 90.0) -> dict:
+    """The analogue of Table I's IoU: every ground-truth rectangle lying wholly
+    inside the grid (and tilted at most max_tilt_deg from horizontal) against
+    the detected polygons (best match with a normal within 10 degrees and the
+    plane within 5 cm of the rectangle's centre)."""
+    import scenes
+    K = int(vm.read_clusters(cl)["K"])
+    K = min(K, planes.k_cap, hulls.k_cap)
+    P = planes.plane[:K].cpu().numpy().astype(np.float64)
+    voff = hulls.v_off[:K + 1].cpu().numpy().astype(np.int64)
+    vxyz = hulls.v_xyz[:max(int(voff[-1]) if K else 0, 1)].cpu().numpy().astype(np.float64)
+    polys = [vxyz[voff[k]:voff[k + 1]] for k in range(K)]
+    lo, hi = np.asarray(sc.geom.origin), sc.geom.hi
+    cos_tilt = np.cos(np.deg2rad(max_tilt_deg)) - 1e-12
+    rects = [r for r in sc.rects if np.all((r.corners() >= lo) & (r.corners() < hi)) and abs(r.normal[2]) >= cos_tilt]
+    v = scenes.plane_iou(rects, P, polys)
+    return {"mean": float(v.mean()) if len(v) else None, "min": float(v.min()) if len(v) else None,
+            "rects": len(rects), "rects_over_0_5": int((v > 0.5).sum()), "planes": K}
+
+
 def _ccl_compare(vm, m, stream, reps: int = 5) -> dict:
     """The map's labelling and grouping by union-find (vm_ccl) and by Alg. 1's
     label propagation (vm_ccl_propagate, the host checking between batches of

@@ -105,6 +105,7 @@ typedef struct {
                                  take more; 0 for calls small enough for per-point
                                  atomics) */
     uint64_t voxels_cleared;  /* voxels cleared by vm_clear_rays since create/clear */
+    uint64_t voxels_shifted_out; /* voxels dropped by vm_map_shift since create/clear */
 } vm_map_stats_t;
 
 /* Allocate a map on the current device (hipMalloc; the map owns the memory
@@ -169,6 +170,26 @@ vm_status vm_map_export(vm_map map, uint32_t* d_key, uint32_t* d_count, uint64_t
  * Asynchronous. */
 vm_status vm_map_import(vm_map map, const uint32_t* d_key, const uint32_t* d_count,
                         const uint64_t* d_sum, uint64_t n, void* stream);
+
+/* Sec. III-B: the local map is robot-centric, its grid follows the robot.
+ * Moves the grid by (dx, dy, dz) whole voxels: the origin becomes
+ * origin + s*(dx, dy, dz) (fp64), voxel (x, y, z) becomes (x-dx, y-dy, z-dz)
+ * with its count and integer sums unchanged (so its mean stays where it was,
+ * exactly), and voxels leaving the grid are dropped (counted in
+ * voxels_shifted_out).  The hash is rebuilt, which also frees the slots that
+ * cleared voxels kept.  The segmentation buffers serve as staging: cluster
+ * views of earlier vm_ccl calls become invalid.  Host state changes (the
+ * origin), so it cannot be captured (VM_E_STATE).  A zero shift is a no-op;
+ * a shift of 2^30 voxels or more on an axis is VM_E_ARG. */
+vm_status vm_map_shift(vm_map map, int32_t dx, int32_t dy, int32_t dz, void* stream);
+
+/* The shift that puts the voxel containing `center` (map frame) at the grid's
+ * middle voxel (dims/2, integer division), applied with vm_map_shift; the
+ * shift goes to shift_out (optional).  VM_E_ARG for a non-finite centre. */
+vm_status vm_map_recenter(vm_map map, const double center[3], int32_t shift_out[3], void* stream);
+
+/* The grid's current origin (host memory, immediate). */
+vm_status vm_map_origin(vm_map map, double origin_out[3]);
 
 /* ---- clusters (Sec. III-C, Alg. 1 and grouping) ----------------------- */
 

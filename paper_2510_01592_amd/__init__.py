@@ -27,7 +27,8 @@ EXPORTED = [
     "vm_insert", "vm_map_export", "vm_map_import", "vm_ccl", "vm_workspace_bytes", "vm_ransac_planes",
     "vm_ransac_planes_noalloc", "vm_planes_hulls", "vm_set_fused_config", "vm_get_fused_config",
     "vm_autotune_fused", "vm_planes_hulls_multi", "vm_multi_workspace_bytes", "vm_ccl_steppable",
-    "vm_segment_frame_steppable", "vm_clear_rays", "vm_ccl_propagate",
+    "vm_segment_frame_steppable", "vm_clear_rays", "vm_ccl_propagate", "vm_map_shift", "vm_map_recenter",
+    "vm_map_origin",
     "vm_hulls", "vm_segment_frame", "vm_set_stage_timing", "vm_stage_times",
     "vm_set_count_config", "vm_get_count_config", "vm_autotune_count",
     "vm_capture_begin", "vm_capture_end", "vm_graph_launch", "vm_graph_destroy",
@@ -50,7 +51,8 @@ class MapStats(ctypes.Structure):
     _fields_ = [("occupied", ctypes.c_uint64), ("points_in", ctypes.c_uint64),
                 ("points_dropped", ctypes.c_uint64), ("points_lost", ctypes.c_uint64),
                 ("status_flags", ctypes.c_uint32), ("hash_capacity_log2", ctypes.c_uint32),
-                ("last_touched", ctypes.c_uint64), ("voxels_cleared", ctypes.c_uint64)]
+                ("last_touched", ctypes.c_uint64), ("voxels_cleared", ctypes.c_uint64),
+                ("voxels_shifted_out", ctypes.c_uint64)]
 
 
 # vm_map_stats_t in 64-bit words (the size of a device buffer for Map.stats_async)
@@ -144,6 +146,9 @@ def lib() -> ctypes.CDLL:
             "vm_map_stats_async": ([_P, _P, _P], i32),
             "vm_insert": ([_P, _P, i64, ctypes.POINTER(Pose), _P], i32),
             "vm_clear_rays": ([_P, _P, i64, ctypes.POINTER(Pose), _P], i32),
+            "vm_map_shift": ([_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P], i32),
+            "vm_map_recenter": ([_P, _P, _P, _P], i32),
+            "vm_map_origin": ([_P, _P], i32),
             "vm_ccl_propagate": ([_P, u32, _P, ctypes.POINTER(Clusters), ctypes.POINTER(u32), _P], i32),
             "vm_map_export": ([_P, _P, _P, _P, _P, u64, ctypes.POINTER(u64), _P], i32),
             "vm_map_import": ([_P, _P, _P, _P, u64, _P], i32),
@@ -317,7 +322,6 @@ class Map:
         h = _P()
         _check(lib().vm_map_create(ctypes.byref(d), ctypes.byref(h)), "vm_map_create")
         self._h = h
-        self.origin = tuple(float(v) for v in origin)
         self.voxel_size = float(voxel_size)
         self.dims = tuple(int(v) for v in dims)
 
@@ -356,6 +360,23 @@ class Map:
         pose = make_pose(R, t)
         _check(lib().vm_insert(self._h, _ptr(xyz), int(xyz.shape[0]), ctypes.byref(pose), _stream(stream)),
                "vm_insert")
+
+    def shift(self, dx: int, dy: int, dz: int, stream=None) -> None:
+        """vm_map_shift: move the grid by whole voxels (the robot-centric map)."""
+        _check(lib().vm_map_shift(self._h, int(dx), int(dy), int(dz), _stream(stream)), "vm_map_shift")
+
+    def recenter(self, center, stream=None) -> Tuple[int, int, int]:
+        """vm_map_recenter: shift so that ``center`` lies in the grid's middle voxel; returns the shift."""
+        c = (ctypes.c_double * 3)(*[float(v) for v in center])
+        d = (ctypes.c_int32 * 3)()
+        _check(lib().vm_map_recenter(self._h, c, d, _stream(stream)), "vm_map_recenter")
+        return int(d[0]), int(d[1]), int(d[2])
+
+    @property
+    def origin(self) -> Tuple[float, float, float]:
+        o = (ctypes.c_double * 3)()
+        _check(lib().vm_map_origin(self._h, o), "vm_map_origin")
+        return float(o[0]), float(o[1]), float(o[2])
 
     def clear_rays(self, xyz, R=None, t=None, stream=None) -> None:
         """vm_clear_rays: free the occupied voxels the frame's rays pass through

@@ -362,6 +362,7 @@ vm_status vm_map_stats(vm_map m, void* stream, vm_map_stats_t* out)
     out->hash_capacity_log2 = m->h.log2cap;
     out->last_touched = c.touched;
     out->voxels_cleared = c.cleared;
+    out->voxels_shifted_out = c.shifted_out;
     return VM_OK;
 }
 
@@ -378,6 +379,44 @@ vm_status vm_insert(vm_map m, const float* d_xyz, int64_t n, const vm_pose* pose
     if (n == 0) return VM_OK;
     StageScope t(VM_STAGE_INSERT, (hipStream_t)stream);
     VM_HIP(launch_insert(d_xyz, n, pose_of(pose), m->g, m->h, m->bits, m->ctr, m->ins, (hipStream_t)stream));
+    return VM_OK;
+}
+
+vm_status vm_map_shift(vm_map m, int32_t dx, int32_t dy, int32_t dz, void* stream)
+{
+    if (!m) return VM_E_ARG;
+    const int32_t lim = 1 << 30;
+    if (dx <= -lim || dx >= lim || dy <= -lim || dy >= lim || dz <= -lim || dz >= lim) return VM_E_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    if (capturing(s)) return VM_E_STATE;
+    if (dx == 0 && dy == 0 && dz == 0) return VM_OK;
+    VM_HIP(launch_rank(m->g, m->bits, m->b, m->cap, m->ctr, s));
+    VM_HIP(launch_scroll(m->g, m->h, m->bits, m->b, m->cap, dx, dy, dz, m->ctr, s));
+    const int32_t d[3] = {dx, dy, dz};
+    for (int k = 0; k < 3; ++k) m->g.origin[k] = m->g.origin[k] + (double)d[k] * m->g.voxel_size;
+    m->have_clusters = false;
+    return VM_OK;
+}
+
+vm_status vm_map_recenter(vm_map m, const double center[3], int32_t shift_out[3], void* stream)
+{
+    if (!m || !center) return VM_E_ARG;
+    int32_t d[3];
+    for (int k = 0; k < 3; ++k) {
+        if (!std::isfinite(center[k])) return VM_E_ARG;
+        const double c = floor((center[k] - m->g.origin[k]) / m->g.voxel_size) - (double)(m->g.dims[k] / 2);
+        if (!(c > -1073741824.0 && c < 1073741824.0)) return VM_E_ARG;
+        d[k] = (int32_t)c;
+    }
+    if (shift_out)
+        for (int k = 0; k < 3; ++k) shift_out[k] = d[k];
+    return vm_map_shift(m, d[0], d[1], d[2], stream);
+}
+
+vm_status vm_map_origin(vm_map m, double origin_out[3])
+{
+    if (!m || !origin_out) return VM_E_ARG;
+    for (int k = 0; k < 3; ++k) origin_out[k] = m->g.origin[k];
     return VM_OK;
 }
 

@@ -32,7 +32,8 @@ struct DevCounters {
     uint32_t sort_sel;                // buffer (0/1) holding the sorted insert batch
     uint32_t group_sel;               // buffer (0/1) holding the voxels sorted by cluster
     unsigned long long cleared;       // voxels cleared by ray casting since create/clear
-    uint32_t pad[7];
+    unsigned long long shifted_out;   // voxels dropped by grid shifts since create/clear
+    uint32_t pad[5];
 };
 
 struct Geom {
@@ -294,6 +295,10 @@ hipError_t launch_stats(const DevCounters* ctr, uint32_t log2cap, vm_map_stats_t
 hipError_t launch_rank(const Geom& g, const uint32_t* bits, SegBuffers& b, uint32_t cap,
                        DevCounters* ctr, hipStream_t s);
 hipError_t launch_clear(const Geom& g, const Hash& h, uint32_t* bits, DevCounters* ctr, hipStream_t s);
+// the map's content shifted by whole voxels (after launch_rank; uses the
+// segmentation buffers as staging)
+hipError_t launch_scroll(const Geom& g, const Hash& h, uint32_t* bits, SegBuffers& b, uint32_t cap, int32_t dx,
+                         int32_t dy, int32_t dz, DevCounters* ctr, hipStream_t s);
 hipError_t launch_export(const Geom& g, const Hash& h, const SegBuffers& b, const DevCounters* ctr,
                          uint32_t* key, uint32_t* cnt, unsigned long long* sum, float* mean, uint64_t cap,
                          hipStream_t s);

@@ -395,6 +395,91 @@ __global__ void __launch_bounds__(kBlock) k_import(Geom g, Hash h, uint32_t* __r
     if (n_lost) atomicOr(&ctr->flags, (uint32_t)VM_FLAG_HASH_FULL);
 }
 
+// ---- scrolling (the robot-centric map): a whole-voxel shift of the grid ------------
+// 1. k_scroll_gather: every ranked voxel's slot content, with its key in the
+//    shifted grid (kEmpty when it leaves), into staging arrays (32 bytes per
+//    voxel: new key, count, the three sums as 32-bit halves);
+// 2. the hash and the occupancy bits are emptied (fill kernels);
+// 3. k_scroll_scatter: the staged voxels that stay are inserted under their
+//    new keys.  Rebuilding the hash also drops the slots of cleared voxels.
+struct ScrollStage {
+    uint32_t* key;
+    uint32_t* cnt;
+    uint32_t* s[6];   // sum0 lo, hi, sum1 lo, hi, sum2 lo, hi
+};
+
+__global__ void __launch_bounds__(kBlock) k_scroll_gather(Geom g, Hash h, const DevCounters* __restrict__ ctr,
+                                                          const uint32_t* __restrict__ occ_key, int32_t dx, int32_t dy,
+                                                          int32_t dz, ScrollStage st)
+{
+    const uint32_t V = ctr->n_occ;
+    const int64_t NX = g.dims[0], NY = g.dims[1], NZ = g.dims[2];
+    for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < V; r += gridDim.x * blockDim.x) {
+        const uint32_t k = occ_key[r];
+        const int64_t x = (int64_t)(k % (uint32_t)NX) - dx, y = (int64_t)((k / (uint32_t)NX) % (uint32_t)NY) - dy,
+                      z = (int64_t)(k / ((uint32_t)NX * (uint32_t)NY)) - dz;
+        const bool in = x >= 0 && y >= 0 && z >= 0 && x < NX && y < NY && z < NZ;
+        const uint32_t s = hash_find(h, k);
+        Slot sl{};
+        if (s != kEmpty) sl = h.slot[s];
+        st.key[r] = in && s != kEmpty ? (uint32_t)(x + NX * (y + NY * z)) : kEmpty;
+        st.cnt[r] = sl.cnt;
+        for (int a = 0; a < 3; ++a) {
+            st.s[2 * a][r] = (uint32_t)sl.sum[a];
+            st.s[2 * a + 1][r] = (uint32_t)(sl.sum[a] >> 32);
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_fill_zero(uint32_t* __restrict__ p, uint32_t n)
+{
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0u;
+}
+
+// occupied restarts from zero (the scatter counts the voxels that stay); the
+// voxels that leave are added to the scrolled-out counter
+__global__ void k_scroll_counters(DevCounters* ctr)
+{
+    if (threadIdx.x == 0) ctr->occupied = 0ull;
+}
+
+__global__ void __launch_bounds__(kBlock) k_scroll_scatter(Hash h, uint32_t* __restrict__ bits, ScrollStage st,
+                                                           DevCounters* ctr)
+{
+    uint32_t n_new = 0, n_out = 0, n_lost = 0;
+    const uint32_t V = ctr->n_occ;
+    for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < V; r += gridDim.x * blockDim.x) {
+        const uint32_t k = st.key[r];
+        if (k == kEmpty) {
+            ++n_out;
+            continue;
+        }
+        uint32_t s = hash_slot(k, h.log2cap);
+        bool ok = false;
+        for (uint32_t p = 0; p < kMaxProbe && p <= h.mask; ++p) {
+            const uint32_t old = atomicCAS(&h.slot[s].key, kEmpty, k);
+            if (old == kEmpty) { ok = true; break; }   // keys are distinct: never old == k
+            s = (s + 1) & h.mask;
+        }
+        if (!ok) {
+            ++n_lost;
+            continue;
+        }
+        Slot* sl = &h.slot[s];
+        sl->cnt = st.cnt[r];
+        for (int a = 0; a < 3; ++a)
+            sl->sum[a] = (unsigned long long)st.s[2 * a][r] | ((unsigned long long)st.s[2 * a + 1][r] << 32);
+        atomicOr(&bits[k >> 5], 1u << (k & 31));
+        ++n_new;
+    }
+    {
+        unsigned long long* const dst[2] = {&ctr->occupied, &ctr->shifted_out};
+        const uint32_t v[2] = {n_new, n_out};
+        block_add_counters<2>(dst, v);
+    }
+    if (n_lost) atomicOr(&ctr->flags, (uint32_t)VM_FLAG_HASH_FULL);
+}
+
 __global__ void __launch_bounds__(kBlock) k_clear_slots(Slot* __restrict__ slot, uint32_t cap)
 {
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < cap; i += gridDim.x * blockDim.x) {
@@ -417,6 +502,7 @@ __global__ void k_stats(const DevCounters* __restrict__ c, uint32_t log2cap, vm_
         out->status_flags = c->flags;
         out->hash_capacity_log2 = log2cap;
         out->voxels_cleared = c->cleared;
+        out->voxels_shifted_out = c->shifted_out;
     }
 }
 
@@ -513,6 +599,28 @@ hipError_t launch_clear(const Geom& g, const Hash& h, uint32_t* bits, DevCounter
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = hipMemsetAsync(bits, 0, (size_t)g.nwords * sizeof(uint32_t), s)) != hipSuccess) return e;
     return hipMemsetAsync(ctr, 0, sizeof(DevCounters), s);
+}
+
+hipError_t launch_scroll(const Geom& g, const Hash& h, uint32_t* bits, SegBuffers& b, uint32_t cap, int32_t dx,
+                         int32_t dy, int32_t dz, DevCounters* ctr, hipStream_t s)
+{
+    // staging in segmentation buffers that are free between frames
+    ScrollStage st;
+    st.key = b.parent;
+    st.cnt = b.csize;
+    st.s[0] = b.scan_a;
+    st.s[1] = b.scan_b;
+    st.s[2] = b.sort_k[0];
+    st.s[3] = b.sort_k[1];
+    st.s[4] = b.sort_v[0];
+    st.s[5] = b.sort_v[1];
+    k_scroll_gather<<<grid_for(cap), kBlock, 0, s>>>(g, h, ctr, b.occ_key, dx, dy, dz, st);
+    const uint32_t hcap = h.mask + 1;
+    k_clear_slots<<<grid_for(hcap, kBlock, 16384), kBlock, 0, s>>>(h.slot, hcap);
+    k_fill_zero<<<grid_for(g.nwords), kBlock, 0, s>>>(bits, g.nwords);
+    k_scroll_counters<<<1, kWave, 0, s>>>(ctr);
+    k_scroll_scatter<<<grid_for(cap, kBlock, kMapGrid), kBlock, 0, s>>>(h, bits, st, ctr);
+    return hipGetLastError();
 }
 
 hipError_t launch_export(const Geom& g, const Hash& h, const SegBuffers& b, const DevCounters* ctr, uint32_t* key,

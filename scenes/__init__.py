@@ -29,7 +29,7 @@ __all__ = [
     "scene_tiny", "scene_tiny_exact", "scene_full_map", "scene_stress",
     "frame_points", "identity_pose", "pose_inverse_apply",
     "random_walk_poses", "batched_clusters", "surface_pool", "stream_frame", "StreamFrame", "served_trace",
-    "raycast_frame",
+    "raycast_frame", "polygon_iou_with_rect", "plane_iou",
 ]
 
 
@@ -482,3 +482,70 @@ def batched_clusters(seed: int = 3, n_clusters: int = 2000, n_min: int = 50, n_m
         p = p[rng.permutation(n)]
         xyz[off[k]:off[k + 1]] = p.astype(np.float32)
     return off.astype(np.uint32), xyz
+
+
+# ---------------------------------------------------------------------------
+# accuracy against the generator's ground truth (the analogue of Table I's IoU)
+# ---------------------------------------------------------------------------
+def _clip_convex(poly: np.ndarray, a: float, b: float) -> np.ndarray:
+    """Sutherland-Hodgman: the part of the convex polygon ``poly`` (k x 2,
+    either orientation) inside the box [-a, a] x [-b, b]."""
+    out = np.asarray(poly, np.float64)
+    for axis, lim, sign in ((0, a, 1.0), (0, a, -1.0), (1, b, 1.0), (1, b, -1.0)):
+        if len(out) == 0:
+            break
+        inp, out = out, []
+        for i in range(len(inp)):
+            p, q = inp[i - 1], inp[i]
+            pin, qin = sign * p[axis] <= lim, sign * q[axis] <= lim
+            if qin:
+                if not pin:
+                    t = (lim - sign * p[axis]) / (sign * (q[axis] - p[axis]))
+                    out.append(p + t * (q - p))
+                out.append(q)
+            elif pin:
+                t = (lim - sign * p[axis]) / (sign * (q[axis] - p[axis]))
+                out.append(p + t * (q - p))
+        out = np.asarray(out, np.float64).reshape(-1, 2)
+    return out
+
+
+def _area(poly: np.ndarray) -> float:
+    if len(poly) < 3:
+        return 0.0
+    x, y = poly[:, 0], poly[:, 1]
+    return 0.5 * abs(float(np.dot(x, np.roll(y, -1)) - np.dot(y, np.roll(x, -1))))
+
+
+def polygon_iou_with_rect(rect: Rect, vertices_xyz: np.ndarray) -> float:
+    """Intersection over union of a convex polygon (vertices in 3D, lying in
+    or near the rectangle's plane) and the rectangle, both taken in the
+    rectangle's own 2D frame."""
+    v = np.asarray(vertices_xyz, np.float64).reshape(-1, 3)
+    if len(v) < 3:
+        return 0.0
+    c, a, b = np.asarray(rect.centre), np.asarray(rect.axis_a), np.asarray(rect.axis_b)
+    uv = np.c_[(v - c) @ a, (v - c) @ b]
+    inter = _area(_clip_convex(uv, rect.half_a, rect.half_b))
+    union = rect.area + _area(uv) - inter
+    return inter / union if union > 0 else 0.0
+
+
+def plane_iou(rects: List[Rect], planes: np.ndarray, polygons: List[np.ndarray], max_angle_deg: float = 10.0,
+              max_offset: float = 0.05) -> np.ndarray:
+    """For each ground-truth rectangle, the best IoU among the detected planes
+    (n, d: n.x + d = 0) whose normal is within ``max_angle_deg`` of the
+    rectangle's (either sign) and which pass within ``max_offset`` m of its
+    centre; 0 when none qualifies."""
+    out = np.zeros(len(rects))
+    P = np.asarray(planes, np.float64).reshape(-1, 4)
+    cos_max = np.cos(np.deg2rad(max_angle_deg))
+    fin = np.all(np.isfinite(P), axis=1)
+    Pf = np.where(fin[:, None], P, 0.0)
+    for i, r in enumerate(rects):
+        c = np.asarray(r.centre)
+        ok = fin & (np.abs(Pf[:, :3] @ r.normal) >= cos_max) & (np.abs(Pf[:, :3] @ c + Pf[:, 3]) <= max_offset)
+        for j in np.nonzero(ok)[0]:
+            out[i] = max(out[i], polygon_iou_with_rect(r, polygons[j]))
+    return out
+

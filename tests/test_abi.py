@@ -70,6 +70,9 @@ def test_argument_errors_without_device_work():
     # null map handles
     assert L.vm_insert(None, None, 0, None, None) == vm.VM_E_ARG
     assert L.vm_clear_rays(None, None, 0, None, None) == vm.VM_E_ARG
+    assert L.vm_map_shift(None, 1, 0, 0, None) == vm.VM_E_ARG
+    assert L.vm_map_recenter(None, None, None, None) == vm.VM_E_ARG
+    assert L.vm_map_origin(None, None) == vm.VM_E_ARG
     assert L.vm_map_destroy(None) == vm.VM_E_ARG
     assert L.vm_ccl(None, 30, None, None, None) == vm.VM_E_ARG
     assert L.vm_ccl_propagate(None, 30, None, None, None, None) == vm.VM_E_ARG
@@ -121,7 +124,7 @@ def test_struct_layouts_match_header_sizes():
     import paper_2510_01592_amd as vm
     # natural C alignment on x86-64 / amdgcn host ABI
     assert ctypes.sizeof(vm.MapDesc) == 3 * 8 + 8 + 3 * 4 + 4 + 4 + 4
-    assert ctypes.sizeof(vm.MapStats) == 4 * 8 + 2 * 4 + 8 + 8
+    assert ctypes.sizeof(vm.MapStats) == 4 * 8 + 2 * 4 + 8 + 8 + 8
     assert ctypes.sizeof(vm.Pose) == 12 * 8
     assert ctypes.sizeof(vm.RansacParams) == 32
     assert ctypes.sizeof(vm.SegParams) == 40
