@@ -398,11 +398,11 @@ vm_status vm_planes_hulls(const vm_clusters* cl, const vm_ransac_params* params,
 /* Work split of vm_planes_hulls.  Every valid setting gives identical
  * results; only the speed differs. */
 typedef struct {
-    uint32_t hyp_chunk;      /* hypotheses per work item: a multiple of 64, 64..512; default 256 */
+    uint32_t hyp_chunk;      /* hypotheses per work item: a multiple of 64, 64..512; default 512 */
     uint32_t small_max;      /* clusters of at most this many points are counted with the lanes over the
                                 hypotheses (one item per chunk), larger ones in 4096-point tiles; 0..256,
-                                default 256 */
-    uint32_t groups_per_cu;  /* persistent workgroups per compute unit, 1..8; default 4 */
+                                default 0 (every cluster in tiles) */
+    uint32_t groups_per_cu;  /* persistent workgroups per compute unit, 1..8; default 5 */
     uint32_t reserved;       /* must be 0 */
 } vm_fused_config;
 

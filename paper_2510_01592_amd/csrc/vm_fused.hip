@@ -9,17 +9,19 @@
 //     hypotheses: the lanes take the planes and loop over the points (LDS);
 //   * a larger cluster is one item per (4096-point tile, hypothesis chunk):
 //     each lane keeps 16 points in registers, the chunk's planes come from LDS.
-// The persistent workgroups take items from the queue with one atomic each
-// (no workgroup ever waits for another) and store each item's integer
-// counts in its own slot, so the sums do not depend on the order.  An
-// item's hypotheses are computed by the first items of their chunk and
-// published with a ready flag; later items load them (or compute them again
-// if the flag is not set yet: the values are the same).  Every item adds one
-// to its cluster's completion counter; the workgroup that completes a
-// cluster runs (c) for it -- the best hypothesis, its inlier list -- and the
-// polygon: projection, the extreme-point filter, sort and monotone chain of
-// the survivors (in one wave's registers up to 64, in LDS up to 1024; larger
-// survivor sets are listed for one tail launch).  A scan and a copy then pack
+// Every hypothesis plane of the set is drawn and fitted by a grid-wide pass
+// first (fp64 arithmetic and the Philox stream stay out of the persistent
+// kernel's registers).  The persistent workgroups take items from the queue
+// with one atomic each (no workgroup ever waits for another) and store each
+// item's integer counts in its own slot, so the sums do not depend on the
+// order.  Every item adds one to its cluster's completion counter; the
+// workgroup that completes a cluster runs (c) for it -- the best
+// hypothesis, its inlier list -- and the polygon: projection, the
+// extreme-point filter, and the sort and monotone chain of up to 64
+// survivors in one wave's registers; larger survivor sets are listed for one
+// tail launch (the workgroup chain in LDS stays out of the persistent
+// kernel, whose register and LDS budget sets how many of its workgroups
+// share a compute unit).  A scan and a copy then pack
 // the per-cluster lists into the caller's compact CSR outputs.  Results are
 // bit-identical to vm_ransac_planes followed by vm_hulls.
 #include "vm_common.h"
@@ -42,15 +44,12 @@ constexpr int kFRows = 16;                           // points per lane in a til
 constexpr uint32_t kFTile = kFBlock * kFRows;        // 4096 points per tile item
 constexpr uint32_t kFMaxChunk = 512;                 // hypotheses per item (LDS planes)
 constexpr uint32_t kFSmallMax = 256;                 // clusters whose lanes take the planes
-constexpr int kFChainCap = 1024;                     // survivors chained in LDS by the finisher
 constexpr int kFWaves = kFBlock / kWave;
 constexpr int kBuckets = 33;                         // cost classes: floor(log2(points)) + 1
-static_assert(kFBlock == kChainBlock, "the finisher runs block_chain with its own threads");
 
 struct FusedWork {
     int32_t* part;          // [tiles][H] per-tile partial counts
     float4* hyp;            // [k_cap][H] hypothesis planes
-    uint32_t* ready;        // [k_cap][ceil(H / 64)] chunk-published flags
     uint32_t* order;        // [k_cap] clusters by cost, largest first
     uint32_t* item_off;     // [k_cap + 1] first queue item of order[i]
     uint32_t* tbase;        // [k_cap] first partial-count row of cluster k
@@ -83,7 +82,6 @@ FusedWork fused_layout(void* base, uint32_t k_cap, uint32_t n_cap, uint32_t H)
     const size_t rows = (size_t)n_cap / kFTile + (size_t)k_cap + 1;
     w.part = (int32_t*)take(rows * H * sizeof(int32_t));
     w.hyp = (float4*)take((size_t)k_cap * H * sizeof(float4));
-    w.ready = (uint32_t*)take((size_t)k_cap * ((H + kWave - 1) / kWave) * sizeof(uint32_t));
     w.order = (uint32_t*)take(((size_t)k_cap + 1) * 4);
     w.item_off = (uint32_t*)take(((size_t)k_cap + 1) * 4);
     w.tbase = (uint32_t*)take(((size_t)k_cap + 1) * 4);
@@ -136,13 +134,12 @@ __global__ void __launch_bounds__(kOneBlockThreads) k_fused_prepare(const uint32
         for (int b = 1; b <= kBuckets; ++b) bucket[b] += bucket[b - 1];   // class starts
     __syncthreads();
     for (uint32_t k = threadIdx.x; k < K; k += blockDim.x) w.order[atomicAdd(&bucket[cls(off[k + 1] - off[k])], 1u)] = k;
-    // per-cluster state, and the ready flags of the hypothesis chunks
+    // per-cluster state
     for (uint32_t k = threadIdx.x; k < K; k += blockDim.x) {
         w.done[k] = 0;
         w.nin[k] = 0;
         w.hcnt[k] = 0;
     }
-    for (uint32_t q = threadIdx.x; q < K * sp.nch; q += blockDim.x) w.ready[q] = 0;
     __syncthreads();
     // queue offsets in cost order, partial-count rows in cluster order
     uint32_t tot[1];
@@ -211,7 +208,6 @@ struct FinishLds {
     double wu[kWave], wv[kWave];
     uint32_t wi[kWave];
     uint8_t wst[2 * kWave + 2];
-    ChainLds<kFChainCap> chain;
 };
 union FusedLds {
     TileLds t;
@@ -472,22 +468,8 @@ __device__ void finish_cluster(const FusedArgs& a, uint32_t k, uint32_t frame, F
             }
             if ((uint32_t)lane < r.h) vout[lane] = inl[L.wi[r.vi]];
         }
-    } else if (ns <= (uint32_t)kFChainCap) {
-        double area = 0.0;
-        const uint32_t hh = block_chain(
-            L.chain, ns,
-            [&](uint32_t t, double* u, double* v, uint32_t* id) {
-                *u = w.su[base + t];
-                *v = w.sv[base + t];
-                *id = w.si[base + t];
-            },
-            [&](uint32_t q, uint32_t p) { vout[q] = inl[L.chain.si[p]]; }, &area);
-        if (threadIdx.x == 0) {
-            a.area_out[k] = area;
-            w.hcnt[k] = hh;
-        }
     } else if (threadIdx.x == 0) {
-        // more survivors than LDS holds: the tail launch chains them
+        // more survivors than one wave: the tail launch sorts and chains them
         w.surv[k] = ns;
         w.tail[atomicAdd(&w.small[7], 1u)] = k;
     }
@@ -518,7 +500,6 @@ __global__ void __launch_bounds__(kFBlock) k_fused(FusedArgs a)
         const uint32_t k = w.order[lo], j = item - w.item_off[lo];
         const uint32_t base = a.off[k], n = a.off[k + 1] - base;
         const uint32_t frame = a.cframe ? a.cframe[k] : frame_all;
-        const uint32_t tg = a.tag[k];
         const bool small = is_small(n, sp);
         const uint32_t c = small ? j : j % sp.nch, t = small ? 0u : j / sp.nch;
         const uint32_t h0 = c * sp.chunk, h1 = min(H, h0 + sp.chunk);
@@ -532,8 +513,7 @@ __global__ void __launch_bounds__(kFBlock) k_fused(FusedArgs a)
             }
             __syncthreads();
             for (uint32_t h = h0 + threadIdx.x; h < h1; h += kFBlock) {
-                const float4 pl = hyp_plane(a.X + base, a.Y + base, a.Z + base, n, h, tg, frame, a.seed);
-                w.hyp[(size_t)k * H + h] = pl;
+                const float4 pl = w.hyp[(size_t)k * H + h];
                 // points read eight at a time (broadcast LDS loads issued together)
                 uint32_t cnt = 0, i = 0;
                 for (; i + 8 <= n; i += 8) {
@@ -557,25 +537,10 @@ __global__ void __launch_bounds__(kFBlock) k_fused(FusedArgs a)
                 part[h] = (int32_t)cnt;
             }
         } else {
-            // the chunk's planes: published by an earlier item, or computed here
-            uint32_t* flag = w.ready + (size_t)k * sp.nch + c;
-            if (threadIdx.x == 0) s_flag = __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __syncthreads();
-            const bool have = s_flag != 0;
-            if (have) {
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-                for (uint32_t h = h0 + threadIdx.x; h < h1; h += kFBlock) L.t.pl[h - h0] = w.hyp[(size_t)k * H + h];
-            } else {
-                for (uint32_t h = h0 + threadIdx.x; h < h1; h += kFBlock) {
-                    const float4 pl = hyp_plane(a.X + base, a.Y + base, a.Z + base, n, h, tg, frame, a.seed);
-                    L.t.pl[h - h0] = pl;
-                    w.hyp[(size_t)k * H + h] = pl;
-                }
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            }
+            // the chunk's planes into LDS
+            for (uint32_t h = h0 + threadIdx.x; h < h1; h += kFBlock) L.t.pl[h - h0] = w.hyp[(size_t)k * H + h];
             for (uint32_t h = threadIdx.x; h < h1 - h0; h += kFBlock) L.t.cnt[h] = 0;
             __syncthreads();
-            if (!have && threadIdx.x == 0) __hip_atomic_store(flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             // this wave's rows of the tile
             const uint32_t p0 = base + t * kFTile, pend = base + n;
             const uint32_t wb = p0 + (uint32_t)(wave * kWave * kFRows);
@@ -610,6 +575,21 @@ __global__ void __launch_bounds__(kFBlock) k_fused(FusedArgs a)
             finish_cluster(a, k, frame, L.f);
         }
         __syncthreads();   // LDS and s_item are reused by the next item
+    }
+}
+
+// (a) for the whole set: plane h of cluster k for every k < K, h < H
+__global__ void __launch_bounds__(kFBlock) k_fused_hyp(FusedArgs a)
+{
+    const uint32_t H = a.sp.H, K = a.w.small[0];
+    const uint32_t frame_all = a.d_frame ? *a.d_frame : a.frame;
+    const uint64_t total = (uint64_t)K * H;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t k = (uint32_t)(i / H), h = (uint32_t)(i % H);
+        const uint32_t base = a.off[k], n = a.off[k + 1] - base;
+        const uint32_t frame = a.cframe ? a.cframe[k] : frame_all;
+        a.w.hyp[i] = hyp_plane(a.X + base, a.Y + base, a.Z + base, n, h, a.tag[k], frame, a.seed);
     }
 }
 
@@ -710,7 +690,7 @@ bool fused_config_valid(const vm_fused_config& c)
            c.groups_per_cu >= 1 && c.groups_per_cu <= 8 && c.reserved == 0;
 }
 
-vm_fused_config fused_config_default() { return vm_fused_config{256, 256, 4, 0}; }
+vm_fused_config fused_config_default() { return vm_fused_config{512, 0, 5, 0}; }
 
 vm_fused_config fused_config_get()
 {
@@ -785,9 +765,8 @@ vm_status fused_core(const vm_clusters& cl, const vm_ransac_params& p, const uin
         k_fused_prepare<<<1, kOneBlockThreads, 0, s>>>(cl.d_meta, kc, out_k_cap, cl.n_cap, cl.d_off, sp, w, status);
         VM_HIP(hipGetLastError());
     }
+    FusedArgs a;
     {
-        StageScope t(VM_STAGE_COUNT, s);
-        FusedArgs a;
         a.off = cl.d_off;
         a.X = cl.d_x;
         a.Y = cl.d_y;
@@ -806,6 +785,14 @@ vm_status fused_core(const vm_clusters& cl, const vm_ransac_params& p, const uin
         a.counts_out = counts_out;
         a.hyp_out = hyp_out;
         a.area_out = area_out;
+    }
+    {
+        StageScope t(VM_STAGE_HYPOTHESES, s);
+        k_fused_hyp<<<grid_for((uint64_t)kc * sp.H, kFBlock, 4096), kFBlock, 0, s>>>(a);
+        VM_HIP(hipGetLastError());
+    }
+    {
+        StageScope t(VM_STAGE_COUNT, s);
         k_fused<<<device_cus() * (int)groups_per_cu, kFBlock, 0, s>>>(a);
         VM_HIP(hipGetLastError());
     }

@@ -175,7 +175,7 @@ def test_fused_config_set_get_and_validation():
     L = vm.lib()
     vm.set_fused_config(None)
     d = vm.get_fused_config()
-    assert d == {"hyp_chunk": 256, "small_max": 256, "groups_per_cu": 4}
+    assert d == {"hyp_chunk": 512, "small_max": 0, "groups_per_cu": 5}
     try:
         for b in (dict(hyp_chunk=32), dict(hyp_chunk=96), dict(hyp_chunk=576), dict(small_max=257),
                   dict(groups_per_cu=0), dict(groups_per_cu=9)):
