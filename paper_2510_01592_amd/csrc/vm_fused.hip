@@ -225,12 +225,17 @@ template <int R>
 __device__ __forceinline__ uint32_t plane_count(const float4 p, const float* px, const float* py, const float* pz,
                                                 float eps)
 {
+    // stage by stage over the rows, so that their chains interleave
+    float dd[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) dd[j] = fmaf(p.x, px[j], p.w);
+#pragma unroll
+    for (int j = 0; j < R; ++j) dd[j] = fmaf(p.y, py[j], dd[j]);
+#pragma unroll
+    for (int j = 0; j < R; ++j) dd[j] = fmaf(p.z, pz[j], dd[j]);
     uint32_t acc = 0;
 #pragma unroll
-    for (int j = 0; j < R; ++j) {
-        const float dd = fmaf(p.z, pz[j], fmaf(p.y, py[j], fmaf(p.x, px[j], p.w)));
-        acc += (uint32_t)__popcll(__ballot(fabsf(dd) < eps));
-    }
+    for (int j = 0; j < R; ++j) acc += (uint32_t)__popcll(__ballot(fabsf(dd[j]) < eps));
     return acc;
 }
 
