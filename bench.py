@@ -61,7 +61,10 @@ UNITS = {
     "count": (["k_count_small", "k_count"], "vm_ransac.hip"),
     "insert": (["k_vox_bucket", "k_bucket_scatter", "k_bucket_insert"], "vm_map.hip"),
     "group": (["k_group_pairs", "k_group_gather"], "vm_ccl.hip"),
+    "fused": (["k_fused_hyp", "k_fused"], "vm_fused.hip"),
 }
+# headers every kernel file includes: part of each unit's source fingerprint
+SHARED_HEADERS = ("vm_common.h", "vm_dev.h", "vm_tilescan.h")
 
 
 def _log(msg: str) -> None:
@@ -577,7 +580,7 @@ def _batched(vm, torch, dev, stream, replays: int = 100, peaks=None):
             "tests_per_s_graph": tests / (graph_ms * 1e-3),
             "stage_ms_two_pass": two_st, "stage_ms_persistent": fused_st,
             "autotune": {"config": tuned, "tuning_s": tune_s},
-            "roofline_persistent_frame": _alu_roof(tests, graph_ms, peaks or {}, None,
+            "roofline_persistent_frame": _alu_roof(tests, graph_ms, peaks or {}, _traffic_per_unit().get("fused"),
                                                    f"{N} points x {H} hypotheses, whole frame",
                                                    "persistent planes + polygons (graph replay)"),
             "roofline_count_two_pass": _alu_roof(tests, count_ms, peaks or {}, None, f"{N} points x {H} hypotheses",
@@ -924,8 +927,12 @@ def _clearing(vm, torch, dev, stream, n_distinct: int = 4, timed: int = 12):
 
 
 def _sha256(path: str) -> str:
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    """SHA-256 of a kernel file followed by the headers it shares with the others."""
+    h = hashlib.sha256()
+    for q in [path] + [os.path.join(os.path.dirname(path), x) for x in SHARED_HEADERS]:
+        with open(q, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def _counters_run(vm, torch, m, frames, planes, hulls, k_cap, H, eps, seed, kw, stream, dev, restore, first, n):
@@ -940,13 +947,24 @@ def _counters_run(vm, torch, m, frames, planes, hulls, k_cap, H, eps, seed, kw, 
         work = torch.empty(vm.workspace_bytes(k_cap, cl.n_cap, H), dtype=torch.uint8, device=dev)
         for r in range(10):
             vm.ransac_planes(cl, vm.ransac_params(H, eps, seed, r), planes, work, stream=stream)
+        # three persistent passes over the 2000-cluster set
+        import scenes
+        off, xyz = scenes.batched_clusters(seed=3)
+        K2, N2, H2 = len(off) - 1, len(xyz), 1024
+        cl2, keep = vm.clusters_from_host(off, xyz, np.arange(K2, dtype=np.uint32))
+        work2 = torch.empty(vm.workspace_bytes(K2, N2, H2), dtype=torch.uint8, device=dev)
+        pl2, hl2 = vm.PlaneBuffers.alloc(K2, N2, H2), vm.HullBuffers.alloc(K2, N2)
+        for r in range(3):
+            vm.planes_hulls(cl2, vm.ransac_params(H2, 0.01, 0x5EED, r), pl2, hl2, work2, stream=stream)
         src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
         dst.copy_(src)
         stream.synchronize()
+        del keep
     meta = vm.read_clusters(cl)
     print(json.dumps({"counters_run": True, "frames": n, "count_passes": 10, "points": int(meta["N"]),
-                      "clusters": int(meta["K"]), "n_hyp": H, "copy_bytes": COPY_BYTES}), flush=True)
+                      "clusters": int(meta["K"]), "n_hyp": H, "persistent_passes": 3, "persistent_points": N2,
+                      "copy_bytes": COPY_BYTES}), flush=True)
     return 0
 
 

@@ -967,6 +967,13 @@ vm_status vm_capture_end(void* stream, vm_graph* out)
         (void)hipGraphDestroy(g);
         return VM_E_DEVICE;
     }
+    // the executable graph's resources go to the device now, not on its first launch
+    if (hipGraphUpload(e, s) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipGraphExecDestroy(e);
+        (void)hipGraphDestroy(g);
+        return VM_E_DEVICE;
+    }
     vm_graph r = new (std::nothrow) vm_graph_s{g, e};
     if (!r) {
         (void)hipGraphExecDestroy(e);

@@ -5,10 +5,10 @@
 //                  occupied, and walks the 3D Bresenham line from the
 //                  sensor's voxel towards it (its own voxel excluded, cut at
 //                  the grid's faces), marking every occupied voxel it passes
-//                  in the `ray` bitmap.  The occupancy word under the walk is
-//                  cached in a register while the walk stays inside it, and a
-//                  mark is an atomic OR only when a plain read shows the bit
-//                  still clear.
+//                  in the `ray` bitmap.  The walk takes four steps at a time
+//                  (their occupancy loads in flight together), and a mark is
+//                  an atomic OR only when a plain read shows the bit still
+//                  clear.
 //   k_clear_apply: a thread per 32-cell word frees the cells marked on a ray
 //                  and not kept (count and sums zeroed in the hash slot, the
 //                  occupancy bit cleared), and leaves both bitmaps zero for
@@ -36,6 +36,56 @@ struct CastArgs {
     uint32_t* ray;           // cells on a ray (occupied ones only)
     uint32_t* keep;          // cells holding a point of the frame (occupied ones only)
 };
+
+// constants of one ray's walk along (driving axis m, minor axes u, w)
+struct Walk {
+    int32_t gm, gu, gw;      // step signs
+    uint32_t Dm, Du, Dw;     // grid extents
+    uint32_t Sm, Su, Sw;     // signed key strides (modulo 2^32)
+};
+
+// The Bresenham walk from the sensor's voxel, dm steps at most, stopping at
+// the first cell outside the grid (each coordinate moves one way, so the
+// walk never comes back).  Four steps are taken at a time: their keys come
+// from the error terms alone, so the four occupancy loads are issued
+// together instead of one after another.
+template <typename T>
+__device__ __forceinline__ void walk(const CastArgs& a, const Walk& k, T dm, T du, T dw, int32_t cm, int32_t cu,
+                                     int32_t cw, uint32_t key)
+{
+    T eu = 2 * du - dm, ew = 2 * dw - dm;
+    const T tdm = 2 * dm, tdu = 2 * du, tdw = 2 * dw;
+    for (T step = 0; step < dm; step += 4) {
+        uint32_t kq[4];
+        bool vq[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            vq[q] = step + q < dm && (uint32_t)cm < k.Dm && (uint32_t)cu < k.Du && (uint32_t)cw < k.Dw;
+            kq[q] = key;
+            if (eu >= 0) {
+                cu += k.gu;
+                key += k.Su;
+                eu -= tdm;
+            }
+            if (ew >= 0) {
+                cw += k.gw;
+                key += k.Sw;
+                ew -= tdm;
+            }
+            eu += tdu;
+            ew += tdw;
+            cm += k.gm;
+            key += k.Sm;
+        }
+        uint32_t wq[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) wq[q] = a.bits[vq[q] ? kq[q] >> 5 : 0u] & (vq[q] ? 0xFFFFFFFFu : 0u);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if ((wq[q] >> (kq[q] & 31)) & 1u) mark_bit(a.ray, kq[q]);
+        if (!vq[3]) break;
+    }
+}
 
 __global__ void __launch_bounds__(kBlock) k_clear_cast(const float* __restrict__ xyz, int64_t n, CastArgs a)
 {
@@ -81,36 +131,14 @@ __global__ void __launch_bounds__(kBlock) k_clear_cast(const float* __restrict__
         const uint32_t Sm = (m == 0 ? sx : (m == 1 ? sy : sz)) * (uint32_t)gm;
         const uint32_t Su = (m == 0 ? sy : (m == 1 ? sz : sx)) * (uint32_t)gu;
         const uint32_t Sw = (m == 0 ? sz : (m == 1 ? sx : sy)) * (uint32_t)gw;
-        int32_t cm = m == 0 ? a.s[0] : (m == 1 ? a.s[1] : a.s[2]);
-        int32_t cu = m == 0 ? a.s[1] : (m == 1 ? a.s[2] : a.s[0]);
-        int32_t cw = m == 0 ? a.s[2] : (m == 1 ? a.s[0] : a.s[1]);
-        uint32_t key = (uint32_t)a.s[0] + (uint32_t)NX * ((uint32_t)a.s[1] + (uint32_t)NY * (uint32_t)a.s[2]);
-        int64_t eu = 2 * du - dm, ew = 2 * dw - dm;
-        uint32_t wi = 0xFFFFFFFFu, wv = 0;
-        // the walk leaves the grid after at most Dm steps along m, so it ends
-        // within min(dm, Dm + 1) iterations
-        for (int64_t step = 0; step < dm; ++step) {
-            if ((uint32_t)cm >= (uint32_t)Dm || (uint32_t)cu >= (uint32_t)Du || (uint32_t)cw >= (uint32_t)Dw) break;
-            if ((key >> 5) != wi) {
-                wi = key >> 5;
-                wv = a.bits[wi];
-            }
-            if ((wv >> (key & 31)) & 1u) mark_bit(a.ray, key);
-            if (eu >= 0) {
-                cu += gu;
-                key += Su;
-                eu -= 2 * dm;
-            }
-            if (ew >= 0) {
-                cw += gw;
-                key += Sw;
-                ew -= 2 * dm;
-            }
-            eu += 2 * du;
-            ew += 2 * dw;
-            cm += gm;
-            key += Sm;
-        }
+        const int32_t cm = m == 0 ? a.s[0] : (m == 1 ? a.s[1] : a.s[2]);
+        const int32_t cu = m == 0 ? a.s[1] : (m == 1 ? a.s[2] : a.s[0]);
+        const int32_t cw = m == 0 ? a.s[2] : (m == 1 ? a.s[0] : a.s[1]);
+        const uint32_t key = (uint32_t)a.s[0] + (uint32_t)NX * ((uint32_t)a.s[1] + (uint32_t)NY * (uint32_t)a.s[2]);
+        const Walk wk{gm, gu, gw, (uint32_t)Dm, (uint32_t)Du, (uint32_t)Dw, Sm, Su, Sw};
+        // 32-bit error terms while they cannot overflow (|e| stays below 2 dm)
+        if (dm < ((int64_t)1 << 29)) walk<int32_t>(a, wk, (int32_t)dm, (int32_t)du, (int32_t)dw, cm, cu, cw, key);
+        else walk<int64_t>(a, wk, dm, du, dw, cm, cu, cw, key);
     }
 }
 
