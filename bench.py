@@ -956,9 +956,13 @@ def _counters_run(vm, torch, m, frames, planes, hulls, k_cap, H, eps, seed, kw, 
         pl2, hl2 = vm.PlaneBuffers.alloc(K2, N2, H2), vm.HullBuffers.alloc(K2, N2)
         for r in range(3):
             vm.planes_hulls(cl2, vm.ransac_params(H2, 0.01, 0x5EED, r), pl2, hl2, work2, stream=stream)
+        # the reference: a plain copy kernel over COPY_BYTES (libvm_peaks.so's k_copy)
         src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
-        dst.copy_(src)
+        stream.synchronize()
+        PL = ctypes.CDLL(PEAKS_LIB)
+        assert PL.vmp_copy(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
+                           ctypes.c_uint64(COPY_BYTES // 16), 32768, ctypes.c_void_p(stream.cuda_stream)) == 0
         stream.synchronize()
         del keep
     meta = vm.read_clusters(cl)
@@ -987,15 +991,14 @@ def _traffic_from(fetch_csv: str, write_csv: str) -> int:
         rows = _pmc_rows(path)
         cnt = "FETCH_SIZE" if name == "fetch" else "WRITE_SIZE"
         rows = [r for r in rows if r["Counter_Name"] == cnt]
-        cp = max(float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"]
-                 or "elementwise" in r["Kernel_Name"])
+        cp = max(float(r["Counter_Value"]) for r in rows if "k_copy" in r["Kernel_Name"])
         scale = COPY_BYTES / (cp * 1024.0)
         out[f"{name}_copy_kib_raw"] = cp
         out[f"{name}_scale"] = scale
         by = {}
         for r in rows:
             kn = r["Kernel_Name"]
-            short = kn.split("(")[0].split("::")[-1].split("<")[0].strip()
+            short = kn.replace("(anonymous namespace)::", "").split("(")[0].split("::")[-1].split("<")[0].strip()
             by.setdefault(short, []).append(float(r["Counter_Value"]) * 1024.0 * scale)
         for short, v in by.items():
             if short in ("k_count", "k_count_small"):
