@@ -635,8 +635,10 @@ def _served(vm, torch, seconds: float, n_robots: int = 8, rate_hz: float = 30.0,
     warm_occ = [int(sn[0].shape[0]) for sn in snaps]
     del pools
     n_slots, budget = 16, 8 << 30
-    be = GpuBackend(maps, n_slots=n_slots, n_hyp=512)
-    be_b = GpuBackend(maps, n_slots=n_slots, n_hyp=512, batch=True, batch_k_cap=65536, batch_n_cap=1 << 24)
+    # an accumulating map's outliers form thousands of small clusters: room for 65536 per frame
+    be = GpuBackend(maps, n_slots=n_slots, n_hyp=512, k_cap=65536)
+    be_b = GpuBackend(maps, n_slots=n_slots, n_hyp=512, k_cap=65536, batch=True, batch_k_cap=65536,
+                      batch_n_cap=1 << 24)
 
     def reset():
         with torch.cuda.stream(s):
@@ -658,6 +660,7 @@ def _served(vm, torch, seconds: float, n_robots: int = 8, rate_hz: float = 30.0,
     def run(scale, per_robot, slots, label, backend=be):
         reset()
         sch = Scheduler(backend, n_robots, slots, budget, per_robot_inflight=per_robot)
+        g0 = getattr(backend, "groups", 0)
         torch.cuda.synchronize()
         t_s = time.perf_counter()
         done = sch.run(requests(scale), t0=t_s)
@@ -666,12 +669,21 @@ def _served(vm, torch, seconds: float, n_robots: int = 8, rate_hz: float = 30.0,
         vox = sum(c.result["occupied"] for c in done)
         occ_end = max(c.result["occupied"] for c in done)
         bad = sum(1 for c in done if c.result["status"].any())
+        flags = {}
+        for c in done:
+            f = int(np.bitwise_or.reduce(c.result["status"].astype(np.uint32)))
+            for bit, name in ((1, "hash_full"), (2, "clusters_cap"), (4, "inliers_cap"), (8, "hull_cap"),
+                              (16, "bad_clusters")):
+                if f & bit:
+                    flags[name] = flags.get(name, 0) + 1
         out = dict(summ, wall_s=t_span, voxels_per_s=vox / t_span,
                    points_per_s=sum(c.request.n_points for c in done) / t_span, peak_inflight=sch.peak_inflight,
-                   rejected=len(sch.rejected), frames_with_status_flags=bad, max_occupied=occ_end)
+                   rejected=len(sch.rejected), frames_with_status_flags=bad, status_flag_counts=flags,
+                   max_occupied=occ_end)
         if sch.batches:
             out["batches"] = sch.batches
             out["mean_batch"] = sch.batched_frames / sch.batches
+            out["persistent_passes"] = getattr(backend, "groups", 0) - g0
         _log(f"served [{label}]: {out}")
         return out, {(c.request.robot, c.request.seq): c.result for c in done}
 

@@ -276,7 +276,6 @@ __global__ void __launch_bounds__(kBlock) k_ccl_tile(const uint32_t* __restrict_
 {
     __shared__ uint32_t rowv[kTileRows];
     __shared__ uint32_t rowrank[kTileRows];
-    __shared__ uint32_t members[kTileRuns / 32];
     __shared__ uint32_t par[kTileRuns];
     __shared__ uint32_t pairs[kPairCap];
     __shared__ uint32_t wtot[kBlock / kWave];
@@ -293,7 +292,6 @@ __global__ void __launch_bounds__(kBlock) k_ccl_tile(const uint32_t* __restrict_
         const uint32_t v = row_bits(bits, nwords, d, x0, y, z, &key0);
         const uint32_t sv = run_starts(v), ev = run_ends(v);
         rowv[j] = v;
-        if (j < kTileRuns / 32) members[j] = 0;
         // (unconditional, so that its loads overlap those of the row; rows
         // outside the grid read key 0, and empty rows' ranks are never used)
         rowrank[j] = seg_rank0(bits, wrank, key0);
@@ -365,28 +363,33 @@ __global__ void __launch_bounds__(kBlock) k_ccl_tile(const uint32_t* __restrict_
             }
             __syncthreads();
         }
-        // roots of the runs (a run's entry then holds its root); a root with
-        // another run or another cell is marked
+        // roots of the runs (a run's entry then holds its root) ...
+        {
+            uint32_t c = j * kRowRuns;
+            for (uint32_t m = sv; m; m &= m - 1, ++c) lds_st(&par[c], lds_find(par, c));
+        }
+        __syncthreads();
+        // ... then each run adds its length to its root's count, kept in the
+        // upper 16 bits of the root's entry (run indices take 12 bits, a tile
+        // holds at most 8192 cells)
         {
             uint32_t c = j * kRowRuns;
             for (uint32_t m = sv; m; m &= m - 1, ++c) {
                 const int s0 = __ffs(m) - 1;
                 const int e0 = __ffs(ev & ~((1u << s0) - 1u)) - 1;
-                const uint32_t rt = lds_find(par, c);
-                lds_st(&par[c], rt);
-                if (rt != c || e0 > s0) atomicOr(&members[rt >> 5], 1u << (rt & 31));
+                atomicAdd(&par[par[c] & 0xFFFFu], (uint32_t)(e0 - s0 + 1) << 16);
             }
         }
         __syncthreads();
         // global parents: the rank of the local root, for a whole run at once
         // (consecutive cells of a run have consecutive ranks); the local
-        // root's rank counts its component's voxels in the tile (a lone voxel
-        // stores its 1, other runs add their lengths)
+        // root's entry of csize receives its component's voxel count in the
+        // tile
         uint32_t c = j * kRowRuns;
         for (uint32_t m = sv; m; m &= m - 1, ++c) {
             const int s0 = __ffs(m) - 1;
             const int e0 = __ffs(ev & ~((1u << s0) - 1u)) - 1;
-            const uint32_t rt = par[c];
+            const uint32_t pc = par[c], rt = pc & 0xFFFFu;
             const uint32_t rrow = rt / kRowRuns, rx = nth_set_bit(run_starts(rowv[rrow]), rt % kRowRuns);
             const uint32_t rr = rowrank[rrow] + __popc(rowv[rrow] & ((1u << rx) - 1u));
             const uint32_t r = rowrank[j] + __popc(v & ((1u << s0) - 1u));
@@ -397,8 +400,9 @@ __global__ void __launch_bounds__(kBlock) k_ccl_tile(const uint32_t* __restrict_
             for (; p0 < pe && (p0 & 3u); ++p0) parent[p0] = rr;
             for (; p0 + 4 <= pe; p0 += 4) *reinterpret_cast<uint4*>(parent + p0) = make_uint4(rr, rr, rr, rr);
             for (; p0 < pe; ++p0) parent[p0] = rr;
-            if (e0 == s0 && rt == c && !((members[c >> 5] >> (c & 31)) & 1u)) csize[r] = 1u;
-            else atomicAdd(&csize[rr], (uint32_t)(e0 - s0 + 1));
+            // the local root's count, stored once by the tile that owns it (no
+            // device atomic: other tiles never write this entry here)
+            if (rt == c) csize[r] = pc >> 16;
         }
         // LDS is reused by the next tile (a block with no next tile skips the
         // barrier, which would wait for the stores above to complete)

@@ -227,7 +227,8 @@ class GpuBackend(Backend):
         inlier and hull lists) are copied to host memory too, behind the
         frame on its stream, for maps of at most capture_cap occupied voxels
         (for checks; costs large copies).  batch_k_cap / batch_n_cap bound the
-        clusters and points of one batch (frames beyond them are flagged)."""
+        clusters and points of one persistent pass; a batch whose frames exceed them is split into
+        several passes (its frames' sizes are read back once their clustering is done)."""
         import torch
 
         import paper_2510_01592_amd as vm
@@ -247,6 +248,8 @@ class GpuBackend(Backend):
             self.mwork = torch.empty(vm.multi_workspace_bytes(self.bk, self.bn, n_hyp), dtype=torch.uint8,
                                      device="cuda")
             self.robot_last = [None] * len(maps)
+            self.swork = None    # workspace of single-frame groups, if the batch's is too small
+            self.groups = 0      # persistent passes run (a batch splits where its clusters exceed the caps)
         self.host = [dict(plane=torch.empty((k_cap, 4), dtype=torch.float32).pin_memory(),
                           best=torch.empty(k_cap, dtype=torch.int32).pin_memory(),
                           area=torch.empty(k_cap, dtype=torch.float64).pin_memory(),
@@ -360,13 +363,48 @@ class GpuBackend(Backend):
             pbs.append(self.planes[slot])
             hbs.append(self.hulls[slot])
             ready.append(ev)
+        # the frames' cluster and point counts (a host wait for their
+        # clustering), then groups of consecutive frames within the batch
+        # capacities: nothing is truncated by merging
+        sizes = []
+        for ev, cl in zip(ready, views):
+            ev.synchronize()
+            meta = vm.device_view(cl.d_meta, 2, np.int32).cpu().numpy()
+            sizes.append((int(meta[0]), int(meta[1])))
+        groups, cur, ck, cn = [], [], 0, 0
+        for i, (k, n) in enumerate(sizes):
+            if cur and (ck + k > self.bk or cn + n > self.bn):
+                groups.append(cur)
+                cur, ck, cn = [], 0, 0
+            cur.append(i)
+            ck += k
+            cn += n
+        if cur:
+            groups.append(cur)
         bs = self.batch_stream
         for ev in ready:
             bs.wait_event(ev)
         with torch.cuda.stream(bs):
             kw = self.kw
-            vm.planes_hulls_multi(views, frames, vm.ransac_params(kw["n_hyp"], kw["eps"], kw["seed"]), pbs, hbs,
-                                  self.bk, self.bn, self.mwork, stream=bs)
+            for g in groups:
+                if len(g) == 1:
+                    # a frame alone: the single-set persistent pass with its own frame word
+                    i = g[0]
+                    need = vm.workspace_bytes(min(views[i].k_cap, pbs[i].k_cap, hbs[i].k_cap), views[i].n_cap,
+                                              kw["n_hyp"])
+                    work = self.mwork
+                    if work.numel() < need:
+                        if self.swork is None or self.swork.numel() < need:
+                            self.swork = torch.empty(need, dtype=torch.uint8, device="cuda")
+                        work = self.swork
+                    vm.planes_hulls(views[i], vm.ransac_params(kw["n_hyp"], kw["eps"], kw["seed"], frames[i]),
+                                    pbs[i], hbs[i], work, stream=bs)
+                else:
+                    vm.planes_hulls_multi([views[i] for i in g], [frames[i] for i in g],
+                                          vm.ransac_params(kw["n_hyp"], kw["eps"], kw["seed"]),
+                                          [pbs[i] for i in g], [hbs[i] for i in g], self.bk, self.bn, self.mwork,
+                                          stream=bs)
+            self.groups += len(groups)
             for (req, slot), cl in zip(items, views):
                 self._fetch(slot, cl)
             done = torch.cuda.Event()

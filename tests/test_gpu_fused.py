@@ -3,8 +3,9 @@ whole cluster set in one persistent launch.  Every output -- planes, every
 hypothesis' count and plane, inlier CSR, polygons, areas, status flags -- is
 bit-identical to vm_ransac_planes followed by vm_hulls, under every work
 split, and matches the oracle; the sets cover ragged and degenerate sizes,
-every hull path (one wave, the workgroup chain in LDS, the tail launch past
-1024 survivors), output capacity overflows and the 2000-cluster set."""
+every hull path (one wave in the finisher; the tail launch for more than 64
+survivors, with its LDS chain, its 64-direction refinement and its sort in
+global memory), output capacity overflows and the 2000-cluster set."""
 import numpy as np
 import pytest
 
