@@ -634,8 +634,14 @@ __global__ void __launch_bounds__(kOneBlockThreads) k_fused_scan(FusedWork w, ui
     }
 }
 
-// The lists of each cluster (a workgroup per cluster at a time): inlier
-// indices, and polygon vertices with their positions projected onto the plane.
+// The lists into the caller's compact outputs.  Inlier indices go by output
+// position, a 4096-entry chunk per workgroup at a time (its first cluster
+// found by a binary search over the offsets, later ones by stepping), so a
+// 200k-inlier cluster is copied by many workgroups, not one; polygon
+// vertices (a few dozen per cluster) go a workgroup per cluster, each
+// projected onto its plane.
+constexpr uint32_t kCopyChunk = 4096;
+
 __global__ void __launch_bounds__(kFBlock) k_fused_copy(FusedWork w, const uint32_t* __restrict__ off,
                                                         const float* __restrict__ X, const float* __restrict__ Y,
                                                         const float* __restrict__ Z,
@@ -646,15 +652,34 @@ __global__ void __launch_bounds__(kFBlock) k_fused_copy(FusedWork w, const uint3
                                                         uint32_t* __restrict__ v_idx, float* __restrict__ v_xyz,
                                                         uint32_t* __restrict__ hstatus)
 {
+    __shared__ uint32_t s_k;
     const uint32_t K = w.small[0];
+    const uint32_t total = min(w.small[8], in_cap);   // inlier entries that fit the output
+    for (uint32_t c0 = blockIdx.x * kCopyChunk; c0 < total; c0 += gridDim.x * kCopyChunk) {
+        if (threadIdx.x == 0) {
+            // the last cluster whose list starts at or before c0
+            uint32_t lo = 0, hi = K;
+            while (hi - lo > 1) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (in_off[mid] <= c0) lo = mid;
+                else hi = mid;
+            }
+            s_k = lo;
+        }
+        __syncthreads();
+        uint32_t k = s_k;
+        const uint32_t c1 = min(c0 + kCopyChunk, total);
+        for (uint32_t p = c0 + threadIdx.x; p < c1; p += kFBlock) {
+            while (in_off[k + 1] <= p) ++k;   // p < total <= in_off[K]: ends
+            in_idx[p] = w.slot_in[off[k] + (p - in_off[k])];
+        }
+        __syncthreads();   // s_k is rewritten for the next chunk
+    }
     bool over = false;
     for (uint32_t k = blockIdx.x; k < K; k += gridDim.x) {
-        const uint32_t base = off[k];
-        const uint32_t ib = in_off[k], m = w.nin[k];
-        for (uint32_t j = threadIdx.x; j < m; j += kFBlock)
-            if (ib + j < in_cap) in_idx[ib + j] = w.slot_in[base + j];
         const uint32_t h = w.hcnt[k];
         if (h == 0) continue;
+        const uint32_t base = off[k];
         const uint32_t vb = v_off[k];
         const float4 pl = plane[k];
         const double nx = pl.x, ny = pl.y, nz = pl.z, d = pl.w;
@@ -678,7 +703,7 @@ __global__ void __launch_bounds__(kFBlock) k_fused_copy(FusedWork w, const uint3
 
 // ---- the work split: process-wide setting and per-shape autotuned choices ------
 std::mutex g_fused_mu;
-vm_fused_config g_fused_cfg = {256, 256, 4, 0};
+vm_fused_config g_fused_cfg = {512, 0, 5, 0};   // fused_config_default()
 std::map<std::tuple<uint32_t, uint32_t, uint32_t>, vm_fused_config> g_fused_cache;
 
 std::tuple<uint32_t, uint32_t, uint32_t> shape_bucket(uint32_t k_cap, uint32_t n_cap, uint32_t H)
@@ -826,8 +851,7 @@ vm_status planes_and_hulls(const vm_clusters& cl, const vm_ransac_params& p, con
     StageScope t(VM_STAGE_HULL, s);
     k_fused_scan<<<1, kOneBlockThreads, 0, s>>>(w, planes.in_cap, planes.d_in_off, hulls.d_v_off, hulls.d_area,
                                                 planes.d_status, hulls.d_status);
-    const int cgrid = (int)std::min<uint32_t>(kc ? kc : 1, 2048);
-    k_fused_copy<<<cgrid, kFBlock, 0, s>>>(w, cl.d_off, cl.d_x, cl.d_y, cl.d_z, (const float4*)planes.d_plane,
+    k_fused_copy<<<2048, kFBlock, 0, s>>>(w, cl.d_off, cl.d_x, cl.d_y, cl.d_z, (const float4*)planes.d_plane,
                                            planes.d_in_off, planes.in_cap, planes.d_in_idx, hulls.d_v_off,
                                            hulls.v_cap, hulls.d_v_idx, hulls.d_v_xyz, hulls.d_status);
     VM_HIP(hipGetLastError());
