@@ -632,12 +632,13 @@ __global__ void __launch_bounds__(kBlock) k_ccl_flatten(const DevCounters* __res
             // only roots receive counts below, and the count is used only
             // when r is not a root: it can be read before the walk
             const uint32_t own = csize[r];
-            uint32_t p = ld_parent(&parent[r]);
+            const uint32_t p0 = ld_parent(&parent[r]);
+            uint32_t p = p0;
             while (p != x) {
                 x = p;
                 p = ld_parent(&parent[x]);
             }
-            st_parent(&parent[r], x);
+            if (x != p0) st_parent(&parent[r], x);   // most voxels already point at their root
             // a tile-local root joined to another tile's component hands its
             // count to the component's root (only roots receive counts, so
             // the count read here is final)

@@ -381,13 +381,14 @@ __global__ void __launch_bounds__(kBlock) k_hull_small(
     }
 }
 
-// Survivor sets beyond the LDS sort are thinned once more before sorting:
+// Survivor sets of more than kRefineMin points are thinned once more before sorting:
 // the extremes of the survivors in kRefineDirs directions (every 360/64
 // degrees, counter-clockwise) bound a convex polygon inside the hull, and the
 // survivors strictly inside it (by the same margin as the octagon's) are
 // dropped.  The hull of what is left is the same polygon, since every vertex
 // survives; a disc keeps about 0.2 % of its points outside a 64-gon.
 constexpr int kRefineDirs = 64;
+constexpr uint32_t kRefineMin = 512;   // survivor sets above this are refined (a few passes beat a long sort)
 constexpr int kRefineBatch = 8;   // directions reduced per pass over the survivors
 
 struct RefineLds {
@@ -549,7 +550,7 @@ __global__ void __launch_bounds__(kChainBlock) k_hull_chain(
         const uint32_t k = chain_list[c];
         const uint32_t ib = in_off[k];
         uint32_t ns = surv_cnt[k];
-        if (ns > (uint32_t)kLdsCap) ns = refine_survivors(R, gu + ib, gv + ib, gi + ib, ns);
+        if (ns > kRefineMin) ns = refine_survivors(R, gu + ib, gv + ib, gi + ib, ns);
         if (ns <= (uint32_t)kLdsCap) {
             double area = 0.0;
             const uint32_t hh = block_chain(L, ns,

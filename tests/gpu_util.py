@@ -95,9 +95,10 @@ def hull_path_clusters():
     """Discs (about a tenth of their inliers survive the octagon filter),
     rotated squares (few survivors) and thin rings (nearly every point on the
     hull) whose hulls reach every path: one wave, the workgroup chain, the
-    64-direction refinement of large survivor sets (the 30000- and
-    60000-point discs drop below the workgroup sort's size with it), and the
-    sort in global memory (the rings stay above it); (off, xyz, tag)."""
+    64-direction refinement of survivor sets above 512 (the larger discs drop
+    far below the workgroup sort's size with it; the 1500-point ring stays
+    large and is sorted in LDS), and the sort in global memory (the larger
+    rings stay above 2048); (off, xyz, tag)."""
     rng = np.random.default_rng(33)
     parts = []
     nrm = np.array([0.1, -0.2, 1.0]) / np.linalg.norm([0.1, -0.2, 1.0])
@@ -110,7 +111,7 @@ def hull_path_clusters():
         th = rng.random(n) * 2 * np.pi
         p = (r * np.cos(th))[:, None] * a + (r * np.sin(th))[:, None] * b + rng.normal(0, 0.002, n)[:, None] * nrm
         parts.append((p + [0.5, 0.5, 1.0]).astype(np.float32))
-    for n in (3000, 6000):
+    for n in (1500, 3000, 6000):
         r = 0.3 + rng.normal(0, 1e-5, n)
         th = rng.random(n) * 2 * np.pi
         p = (r * np.cos(th))[:, None] * a + (r * np.sin(th))[:, None] * b
