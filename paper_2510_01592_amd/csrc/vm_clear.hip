@@ -1,14 +1,13 @@
 // vm_clear.hip -- free space along the sensor rays (Sec. III-B, Eq. (2)).
 //
-//   k_clear_cast:  a thread per point transforms it as the insert does, marks
+//   k_clear_cast:  a wave per point transforms it as the insert does, marks
 //                  its voxel in the `keep` bitmap when that voxel is
 //                  occupied, and walks the 3D Bresenham line from the
 //                  sensor's voxel towards it (its own voxel excluded, cut at
-//                  the grid's faces), marking every occupied voxel it passes
-//                  in the `ray` bitmap.  The walk takes four steps at a time
-//                  (their occupancy loads in flight together), and a mark is
-//                  an atomic OR only when a plain read shows the bit still
-//                  clear.
+//                  the grid's faces) with its lanes over the steps, marking
+//                  every occupied voxel it passes in the `ray` bitmap.  A
+//                  mark is an atomic OR only when a plain read shows the bit
+//                  still clear.
 //   k_clear_apply: a thread per 32-cell word frees the cells marked on a ray
 //                  and not kept (count and sums zeroed in the hash slot, the
 //                  occupancy bit cleared), and leaves both bitmaps zero for
@@ -37,61 +36,62 @@ struct CastArgs {
     uint32_t* keep;          // cells holding a point of the frame (occupied ones only)
 };
 
-// constants of one ray's walk along (driving axis m, minor axes u, w)
-struct Walk {
-    int32_t gm, gu, gw;      // step signs
-    uint32_t Dm, Du, Dw;     // grid extents
-    uint32_t Sm, Su, Sw;     // signed key strides (modulo 2^32)
-};
-
-// The Bresenham walk from the sensor's voxel, dm steps at most, stopping at
-// the first cell outside the grid (each coordinate moves one way, so the
-// walk never comes back).  Four steps are taken at a time: their keys come
-// from the error terms alone, so the four occupancy loads are issued
-// together instead of one after another.
+// One wave per ray.  The Bresenham walk has a closed form: after k steps
+// along the driving axis m, a minor axis with extent d has moved
+// floor((2 d k + dm) / (2 dm)) times (the error-term rule, a step when the
+// term reaches zero, unrolled), so lane l takes steps l, l + 64, ... and
+// keeps each minor coordinate as a quotient and remainder, advanced by the
+// constant increments of 64 steps.  The walk leaves the grid at the first
+// step where some coordinate does (each moves one way only); that step is
+// computed up front per axis, so every lane knows where to stop.
 template <typename T>
-__device__ __forceinline__ void walk(const CastArgs& a, const Walk& k, T dm, T du, T dw, int32_t cm, int32_t cu,
-                                     int32_t cw, uint32_t key)
+__device__ __forceinline__ void walk_lanes(const CastArgs& a, int lane, T dm, T du, T dw, T nsteps, uint32_t key0,
+                                           uint32_t Sm, uint32_t Su, uint32_t Sw)
 {
-    T eu = 2 * du - dm, ew = 2 * dw - dm;
-    const T tdm = 2 * dm, tdu = 2 * du, tdw = 2 * dw;
-    for (T step = 0; step < dm; step += 4) {
-        uint32_t kq[4];
-        bool vq[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            vq[q] = step + q < dm && (uint32_t)cm < k.Dm && (uint32_t)cu < k.Du && (uint32_t)cw < k.Dw;
-            kq[q] = key;
-            if (eu >= 0) {
-                cu += k.gu;
-                key += k.Su;
-                eu -= tdm;
-            }
-            if (ew >= 0) {
-                cw += k.gw;
-                key += k.Sw;
-                ew -= tdm;
-            }
-            eu += tdu;
-            ew += tdw;
-            cm += k.gm;
-            key += k.Sm;
+    const T two_dm = 2 * dm;
+    T k = (T)lane;
+    // the minor axes' moves after k steps: quotient and remainder of 2 d k + dm by 2 dm
+    int64_t nu = 2 * (int64_t)du * (int64_t)lane + (int64_t)dm, nw = 2 * (int64_t)dw * (int64_t)lane + (int64_t)dm;
+    T U = (T)(nu / (int64_t)two_dm), ru = (T)(nu % (int64_t)two_dm);
+    T W = (T)(nw / (int64_t)two_dm), rw = (T)(nw % (int64_t)two_dm);
+    // their increments over 64 steps
+    const int64_t iu = 2 * (int64_t)du * kWave, iw = 2 * (int64_t)dw * kWave;
+    const T qu = (T)(iu / (int64_t)two_dm), pu = (T)(iu % (int64_t)two_dm);
+    const T qw = (T)(iw / (int64_t)two_dm), pw = (T)(iw % (int64_t)two_dm);
+    for (; k < nsteps; k += kWave) {
+        const uint32_t key = key0 + Sm * (uint32_t)k + Su * (uint32_t)U + Sw * (uint32_t)W;
+        if ((a.bits[key >> 5] >> (key & 31)) & 1u) mark_bit(a.ray, key);
+        U += qu;
+        ru += pu;
+        if (ru >= two_dm) {
+            ++U;
+            ru -= two_dm;
         }
-        uint32_t wq[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) wq[q] = a.bits[vq[q] ? kq[q] >> 5 : 0u] & (vq[q] ? 0xFFFFFFFFu : 0u);
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-            if ((wq[q] >> (kq[q] & 31)) & 1u) mark_bit(a.ray, kq[q]);
-        if (!vq[3]) break;
+        W += qw;
+        rw += pw;
+        if (rw >= two_dm) {
+            ++W;
+            rw -= two_dm;
+        }
     }
+}
+
+// first step at which a coordinate starting at c and moving by g per move
+// leaves [0, D), in steps of the driving axis: moves = floor((2 d k + dm) / (2 dm))
+__device__ __forceinline__ int64_t exit_step(int64_t c, int32_t g, int64_t D, int64_t d, int64_t dm)
+{
+    const int64_t L = g > 0 ? D - c : c + 1;   // moves that stay inside
+    if (d == 0) return (int64_t)0x7FFFFFFFFFFFFFFFll;
+    return (2 * dm * L - dm + 2 * d - 1) / (2 * d);
 }
 
 __global__ void __launch_bounds__(kBlock) k_clear_cast(const float* __restrict__ xyz, int64_t n, CastArgs a)
 {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
     const int32_t NX = a.g.dims[0], NY = a.g.dims[1], NZ = a.g.dims[2];
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave; i < n; i += nwaves) {
+        // the point (every lane of the wave computes the same values)
         const double px = (double)xyz[3 * i + 0];
         const double py = (double)xyz[3 * i + 1];
         const double pz = (double)xyz[3 * i + 2];
@@ -106,7 +106,7 @@ __global__ void __launch_bounds__(kBlock) k_clear_cast(const float* __restrict__
         if (!(fx >= -1e15 && fx <= 1e15 && fy >= -1e15 && fy <= 1e15 && fz >= -1e15 && fz <= 1e15)) continue;
         // the point's voxel: floor division of the fixed-point coordinate
         const int64_t e0 = (int64_t)fx >> 20, e1 = (int64_t)fy >> 20, e2 = (int64_t)fz >> 20;
-        if (e0 >= 0 && e1 >= 0 && e2 >= 0 && e0 < NX && e1 < NY && e2 < NZ) {
+        if (lane == 0 && e0 >= 0 && e1 >= 0 && e2 >= 0 && e0 < NX && e1 < NY && e2 < NZ) {
             const uint32_t k = (uint32_t)e0 + (uint32_t)NX * ((uint32_t)e1 + (uint32_t)NY * (uint32_t)e2);
             if ((a.bits[k >> 5] >> (k & 31)) & 1u) mark_bit(a.keep, k);
         }
@@ -117,28 +117,36 @@ __global__ void __launch_bounds__(kBlock) k_clear_cast(const float* __restrict__
         if (ad1 > ad0) m = 1;
         if (ad2 > (m == 0 ? ad0 : ad1)) m = 2;
         const int64_t dm = m == 0 ? ad0 : (m == 1 ? ad1 : ad2);
+        if (dm == 0) continue;
         const int64_t du = m == 0 ? ad1 : (m == 1 ? ad2 : ad0);
         const int64_t dw = m == 0 ? ad2 : (m == 1 ? ad0 : ad1);
         const int32_t gm = (m == 0 ? d0 : (m == 1 ? d1 : d2)) < 0 ? -1 : 1;
         const int32_t gu = (m == 0 ? d1 : (m == 1 ? d2 : d0)) < 0 ? -1 : 1;
         const int32_t gw = (m == 0 ? d2 : (m == 1 ? d0 : d1)) < 0 ? -1 : 1;
-        const int32_t Dm = m == 0 ? NX : (m == 1 ? NY : NZ);
-        const int32_t Du = m == 0 ? NY : (m == 1 ? NZ : NX);
-        const int32_t Dw = m == 0 ? NZ : (m == 1 ? NX : NY);
+        const int64_t Dm = m == 0 ? NX : (m == 1 ? NY : NZ);
+        const int64_t Du = m == 0 ? NY : (m == 1 ? NZ : NX);
+        const int64_t Dw = m == 0 ? NZ : (m == 1 ? NX : NY);
+        const int64_t cm = m == 0 ? a.s[0] : (m == 1 ? a.s[1] : a.s[2]);
+        const int64_t cu = m == 0 ? a.s[1] : (m == 1 ? a.s[2] : a.s[0]);
+        const int64_t cw = m == 0 ? a.s[2] : (m == 1 ? a.s[0] : a.s[1]);
+        int64_t nsteps = dm;
+        const int64_t xm = gm > 0 ? Dm - cm : cm + 1;
+        nsteps = nsteps < xm ? nsteps : xm;
+        const int64_t xu = exit_step(cu, gu, Du, du, dm), xw = exit_step(cw, gw, Dw, dw, dm);
+        nsteps = nsteps < xu ? nsteps : xu;
+        nsteps = nsteps < xw ? nsteps : xw;
         // key strides, applied with the step's sign in modulo-2^32 arithmetic
         // (the grid has fewer than 2^32 cells, so keys inside it are exact)
         const uint32_t sx = 1u, sy = (uint32_t)NX, sz = (uint32_t)NX * (uint32_t)NY;
         const uint32_t Sm = (m == 0 ? sx : (m == 1 ? sy : sz)) * (uint32_t)gm;
         const uint32_t Su = (m == 0 ? sy : (m == 1 ? sz : sx)) * (uint32_t)gu;
         const uint32_t Sw = (m == 0 ? sz : (m == 1 ? sx : sy)) * (uint32_t)gw;
-        const int32_t cm = m == 0 ? a.s[0] : (m == 1 ? a.s[1] : a.s[2]);
-        const int32_t cu = m == 0 ? a.s[1] : (m == 1 ? a.s[2] : a.s[0]);
-        const int32_t cw = m == 0 ? a.s[2] : (m == 1 ? a.s[0] : a.s[1]);
-        const uint32_t key = (uint32_t)a.s[0] + (uint32_t)NX * ((uint32_t)a.s[1] + (uint32_t)NY * (uint32_t)a.s[2]);
-        const Walk wk{gm, gu, gw, (uint32_t)Dm, (uint32_t)Du, (uint32_t)Dw, Sm, Su, Sw};
-        // 32-bit error terms while they cannot overflow (|e| stays below 2 dm)
-        if (dm < ((int64_t)1 << 29)) walk<int32_t>(a, wk, (int32_t)dm, (int32_t)du, (int32_t)dw, cm, cu, cw, key);
-        else walk<int64_t>(a, wk, dm, du, dw, cm, cu, cw, key);
+        const uint32_t key0 = (uint32_t)a.s[0] + (uint32_t)NX * ((uint32_t)a.s[1] + (uint32_t)NY * (uint32_t)a.s[2]);
+        // 32-bit walk state while 2 dm fits comfortably (quotients < dm, remainders < 2 dm)
+        if (dm < ((int64_t)1 << 29))
+            walk_lanes<int32_t>(a, lane, (int32_t)dm, (int32_t)du, (int32_t)dw, (int32_t)nsteps, key0, Sm, Su, Sw);
+        else
+            walk_lanes<int64_t>(a, lane, dm, du, dw, nsteps, key0, Sm, Su, Sw);
     }
 }
 
