@@ -968,11 +968,14 @@ def _counters_run(vm, torch, m, frames, planes, hulls, k_cap, H, eps, seed, kw, 
         pl2, hl2 = vm.PlaneBuffers.alloc(K2, N2, H2), vm.HullBuffers.alloc(K2, N2)
         for r in range(3):
             vm.planes_hulls(cl2, vm.ransac_params(H2, 0.01, 0x5EED, r), pl2, hl2, work2, stream=stream)
-        # the reference: a plain copy kernel over COPY_BYTES (libvm_peaks.so's k_copy)
+        # the reference: a plain copy kernel over COPY_BYTES (libvm_peaks.so's k_copy),
+        # and the register-only loop of the inlier test (instruction counters per test)
         src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
         stream.synchronize()
         PL = ctypes.CDLL(PEAKS_LIB)
+        assert PL.vmp_test_loop(2048, 256, ctypes.c_float(0.01), ctypes.c_void_p(dst.data_ptr()),
+                                ctypes.c_void_p(stream.cuda_stream)) == 0
         assert PL.vmp_copy(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
                            ctypes.c_uint64(COPY_BYTES // 16), 32768, ctypes.c_void_p(stream.cuda_stream)) == 0
         stream.synchronize()
