@@ -704,8 +704,19 @@ def _served(vm, torch, seconds: float, n_robots: int = 8, rate_hz: float = 30.0,
     for name, dk in (("one at a time", diff_b), ("batched", diff_c)):
         for k in dk[:3]:
             x, y = res_a[k], (res_b if name == "one at a time" else res_c)[k]
+            kk = min(x["K"], y["K"])
+            bad = [c for c in range(kk) if x["best"][c] != y["best"][c] or
+                   x["plane"][c].view(np.uint32).tolist() != y["plane"][c].view(np.uint32).tolist() or
+                   x["area"][c].view(np.uint64) != y["area"][c].view(np.uint64) or
+                   x["v_off"][c + 1] - x["v_off"][c] != y["v_off"][c + 1] - y["v_off"][c]]
+            first = ""
+            if bad:
+                c = bad[0]
+                first = (f"; {len(bad)} clusters, first {c}: best {x['best'][c]} / {y['best'][c]}, area "
+                         f"{x['area'][c]!r} / {y['area'][c]!r}, vertices {x['v_off'][c + 1] - x['v_off'][c]} / "
+                         f"{y['v_off'][c + 1] - y['v_off'][c]}")
             _log(f"served: frame {k} differs from the streams form in the {name} form: K {x['K']} / {y['K']}, "
-                 f"occupied {x['occupied']} / {y['occupied']}")
+                 f"occupied {x['occupied']} / {y['occupied']}{first}")
     same = not diff_b and not diff_c
     for mp in maps:
         mp.close()

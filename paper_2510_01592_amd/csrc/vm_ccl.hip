@@ -224,6 +224,20 @@ __device__ __forceinline__ uint32_t lds_find(uint32_t* par, uint32_t x)
     return x;
 }
 
+// Root of x without writing anything on the way, for when the unions are
+// done and other threads are storing roots: a path-halving store could
+// replace the root another thread has just stored for a node by an
+// intermediate ancestor.
+__device__ __forceinline__ uint32_t lds_root(const uint32_t* par, uint32_t x)
+{
+    uint32_t p = lds_ld(&par[x]);
+    while (p != x) {
+        x = p;
+        p = lds_ld(&par[x]);
+    }
+    return x;
+}
+
 __device__ __forceinline__ void lds_unite(uint32_t* par, uint32_t a, uint32_t b)
 {
     a = lds_find(par, a);
@@ -368,10 +382,11 @@ __global__ void __launch_bounds__(kBlock) k_ccl_tile(const uint32_t* __restrict_
             }
             __syncthreads();
         }
-        // roots of the runs (a run's entry then holds its root) ...
+        // roots of the runs (a run's entry then holds its root; every value
+        // a walk reads is an ancestor or the root) ...
         {
             uint32_t c = j * kRowRuns;
-            for (uint32_t m = sv; m; m &= m - 1, ++c) lds_st(&par[c], lds_find(par, c));
+            for (uint32_t m = sv; m; m &= m - 1, ++c) lds_st(&par[c], lds_root(par, c));
         }
         __syncthreads();
         // ... then each run adds its length to its root's count, kept in the
