@@ -1,0 +1,97 @@
+"""Labelling and grouping repeated on the same large maps: every call gives
+the oracle's labels and cluster CSR (offsets, tags, keys, means).  The
+labelling tile's union-find is lock-free, so these maps -- thousands of
+tiles, deep run trees, thousands of small components -- exercise its
+interleavings; a component size that depended on them would move cluster
+offsets from one call to the next."""
+import numpy as np
+import pytest
+
+import oracle
+import scenes
+from tests.gpu_util import bits, note
+
+pytestmark = pytest.mark.gpu
+
+
+def _t(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _check_repeated(vm, m, om, dims, minc, reps):
+    import torch
+    keys = om.key
+    V = len(keys)
+    ref, _ = oracle.ccl26(keys, dims)
+    c = oracle.group(keys, ref, om.means(), minc)
+    for rep in range(reps):
+        note(f"ccl repeat {rep}: {V} voxels, {len(c.tag)} clusters of at least {minc}")
+        labels = torch.zeros(max(V, 1), dtype=torch.int32, device="cuda")
+        got = vm.read_clusters(m.ccl(minc, labels=labels))
+        assert np.array_equal(labels.cpu().numpy()[:V].view(np.uint32), ref), rep
+        assert got["K"] == len(c.tag) and got["N"] == int(c.off[-1]), rep
+        assert np.array_equal(got["off"], c.off) and np.array_equal(got["tag"], c.tag), rep
+        assert np.array_equal(got["key"], c.key), rep
+        assert np.array_equal(bits(np.c_[got["x"], got["y"], got["z"]]), bits(c.xyz)), rep
+
+
+@pytest.mark.parametrize("p", [0.3, 0.09])
+def test_random_grid_repeated(p):
+    """p = 0.3: one component of 590k voxels spanning every tile; p = 0.09
+    (near the 26-neighbour percolation threshold): 32k components of every
+    size."""
+    import paper_2510_01592_amd as vm
+    shape = (64, 160, 192)
+    grid = np.random.default_rng(12).random(shape) < p
+    nz, ny, nx = shape
+    zz, yy, xx = np.nonzero(grid)
+    pts = (np.c_[xx, yy, zz] * 0.01 + 0.005).astype(np.float32)
+    m = vm.Map((0.0, 0.0, 0.0), 0.01, (nx, ny, nz), 22)
+    m.insert(_t(pts))
+    om = oracle.OracleMap((0.0, 0.0, 0.0), 0.01, (nx, ny, nz))
+    om.insert(pts)
+    for minc in (2, 30):
+        _check_repeated(vm, m, om, (nx, ny, nz), minc, 3)
+    m.close()
+
+
+def test_accumulated_map_repeated():
+    """The full map after twelve 1M-point frames: with a minimum size of 3
+    its outliers and surface fringes form 25k clusters."""
+    import paper_2510_01592_amd as vm
+    sc = scenes.scene_full_map(3)
+    g = sc.geom
+    m = vm.Map(g.origin, g.voxel_size, g.dims, 23)
+    om = oracle.OracleMap(g.origin, g.voxel_size, g.dims)
+    for f in range(12):
+        pts = scenes.frame_points(sc, 300 + f)
+        m.insert(_t(pts))
+        om.insert(pts)
+    for minc in (3, 30):
+        _check_repeated(vm, m, om, g.dims, minc, 3)
+    m.close()
+
+
+def test_served_robot_map_repeated():
+    """A served robot's map: 30 warm 1M-point frames from its surface pool,
+    then 14 posed frames of 200k..2M points; 2.55M voxels, 3365 clusters of
+    at least 30 (most of them accumulated outliers a few voxels above the
+    minimum).  Labelled four times."""
+    import paper_2510_01592_amd as vm
+    sc = scenes.scene_full_map(10)
+    g = sc.geom
+    pool = scenes.surface_pool(sc, 30, 8_000_000)
+    trace = [f for f in scenes.served_trace(8, 4.0, 30.0, seed=20) if f.robot == 0][:14]
+    m = vm.Map(g.origin, g.voxel_size, g.dims, 24)
+    om = oracle.OracleMap(g.origin, g.voxel_size, g.dims)
+    for f in range(30):
+        pts = scenes.stream_frame(sc, pool, 900_000 + f, 1_000_000)
+        m.insert(_t(pts))
+        om.insert(pts)
+    for f in trace:
+        pts = scenes.stream_frame(sc, pool, f.frame_seed, f.n_points, f.pose)
+        m.insert(_t(pts), f.pose[0], f.pose[1])
+        om.insert(pts, f.pose[0], f.pose[1])
+    _check_repeated(vm, m, om, g.dims, 30, 4)
+    m.close()
