@@ -35,9 +35,11 @@ __device__ __forceinline__ uint32_t ld_rel(const uint32_t* p)
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
 }
 
+// path-halving and flattening stores are device-scope (written through to
+// memory), as in the unconditional labelling's union-find
 __device__ __forceinline__ void st_rel(uint32_t* p, uint32_t v)
 {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // root of x with path halving (parents only ever move to ancestors)

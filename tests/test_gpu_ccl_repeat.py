@@ -77,7 +77,8 @@ def test_served_robot_map_repeated():
     """A served robot's map: 30 warm 1M-point frames from its surface pool,
     then 14 posed frames of 200k..2M points; 2.55M voxels, 3365 clusters of
     at least 30 (most of them accumulated outliers a few voxels above the
-    minimum).  Labelled four times."""
+    minimum).  Labelled four times against the whole CSR, then 200 times
+    against the labels."""
     import paper_2510_01592_amd as vm
     sc = scenes.scene_full_map(10)
     g = sc.geom
@@ -94,4 +95,15 @@ def test_served_robot_map_repeated():
         m.insert(_t(pts), f.pose[0], f.pose[1])
         om.insert(pts, f.pose[0], f.pose[1])
     _check_repeated(vm, m, om, g.dims, 30, 4)
+    # then the labels alone, many more times (a stale parent store showed up
+    # in about 1 call in 130 on such maps)
+    import torch
+    ref, _ = oracle.ccl26(om.key, g.dims)
+    V = len(om.key)
+    labels = torch.zeros(V, dtype=torch.int32, device="cuda")
+    note("ccl repeat: 200 more labellings")
+    for rep in range(200):
+        m.ccl(30, labels=labels)
+        got = labels.cpu().numpy().view(np.uint32)
+        assert np.array_equal(got, ref), (rep, np.flatnonzero(got != ref)[:5])
     m.close()
