@@ -696,7 +696,9 @@ def _served(vm, torch, seconds: float, n_robots: int = 8, rate_hz: float = 30.0,
     # the same frames give the same results in every schedule (bit patterns:
     # a NaN compares equal to itself)
     def differ(x, y):
-        return [k for k in x if not (x[k]["K"] == y[k]["K"] and np.array_equal(x[k]["best"], y[k]["best"]) and
+        return [k for k in x if not (x[k]["K"] == y[k]["K"] and x[k]["N"] == y[k]["N"] and
+                                     np.array_equal(x[k]["best"], y[k]["best"]) and
+                                     np.array_equal(x[k]["nin"], y[k]["nin"]) and
                                      np.array_equal(x[k]["plane"].view(np.uint32), y[k]["plane"].view(np.uint32)) and
                                      np.array_equal(x[k]["area"].view(np.uint64), y[k]["area"].view(np.uint64)) and
                                      np.array_equal(x[k]["v_off"], y[k]["v_off"]))]
@@ -712,11 +714,12 @@ def _served(vm, torch, seconds: float, n_robots: int = 8, rate_hz: float = 30.0,
             first = ""
             if bad:
                 c = bad[0]
-                first = (f"; {len(bad)} clusters, first {c}: best {x['best'][c]} / {y['best'][c]}, area "
+                first = (f"; {len(bad)} clusters, first {c}: best {x['best'][c]} / {y['best'][c]}, inliers "
+                         f"{x['nin'][c]} / {y['nin'][c]}, area "
                          f"{x['area'][c]!r} / {y['area'][c]!r}, vertices {x['v_off'][c + 1] - x['v_off'][c]} / "
                          f"{y['v_off'][c + 1] - y['v_off'][c]}")
             _log(f"served: frame {k} differs from the streams form in the {name} form: K {x['K']} / {y['K']}, "
-                 f"occupied {x['occupied']} / {y['occupied']}{first}")
+                 f"N {x['N']} / {y['N']}, occupied {x['occupied']} / {y['occupied']}{first}")
     same = not diff_b and not diff_c
     for mp in maps:
         mp.close()

@@ -424,9 +424,11 @@ vm_status vm_autotune_fused(const vm_clusters* cl, const vm_ransac_params* param
                             vm_fused_config* best);
 
 /* Several cluster sets -- e.g. the clusters of several robots' maps, one
- * frame each -- in one persistent pass (the served form's continuous
+ * frame each -- in one sequence of launches (the served form's continuous
  * batching): the sets are merged into one cluster list in d_work (at most
- * k_cap clusters, 1..65536, and n_cap points in all), set i's clusters use
+ * k_cap clusters, 1..65536, and n_cap points in all), the two-pass kernels
+ * of vm_ransac_planes and vm_hulls run once over the merged list (their
+ * tiled passes spread a very large cluster over the chip), set i's clusters use
  * RNG counter word frames[i] (params->frame and params->d_frame are not
  * used), and set i's results go to planes[i] / hulls[i] exactly as
  * vm_planes_hulls on that set alone with params->frame = frames[i] would

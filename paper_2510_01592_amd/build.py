@@ -17,7 +17,7 @@ OBJ_DIR = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["vm_api.hip", "vm_map.hip", "vm_scan.hip", "vm_ccl.hip", "vm_ransac.hip", "vm_hull.hip", "vm_fused.hip", "vm_step.hip", "vm_clear.hip", "vm_propagate.hip"]
+SOURCES = ["vm_api.hip", "vm_map.hip", "vm_scan.hip", "vm_ccl.hip", "vm_ransac.hip", "vm_hull.hip", "vm_fused.hip", "vm_multi.hip", "vm_step.hip", "vm_clear.hip", "vm_propagate.hip"]
 # the measured-roofline microbenchmarks (used by the benchmark only)
 PEAKS_SRC = "vm_peaks.hip"
 PEAKS_LIB = os.path.join(HERE, "libvm_peaks.so")

@@ -771,9 +771,7 @@ vm_status vm_planes_hulls_multi(uint32_t n, const vm_clusters* sets, const uint3
             check_hulls(&hulls[i]) != VM_OK)
             return VM_E_ARG;
     if (work_bytes < multi_workspace_bytes(k_cap, n_cap, params->n_hyp)) return VM_E_CAPACITY;
-    vm_fused_config cfg;
-    if (!fused_cache_get(k_cap, n_cap, params->n_hyp, &cfg)) cfg = fused_config_get();
-    return planes_hulls_multi(n, sets, frames, *params, planes, hulls, k_cap, n_cap, d_work, work_bytes, cfg,
+    return planes_hulls_multi(n, sets, frames, *params, planes, hulls, k_cap, n_cap, d_work, work_bytes,
                               (hipStream_t)stream);
 }
 

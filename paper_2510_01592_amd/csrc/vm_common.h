@@ -374,8 +374,10 @@ struct WorkLayout {
 WorkLayout work_layout(void* base, uint32_t k_cap, uint32_t n_cap, uint32_t n_hyp);
 uint64_t hull_tiles_bound(uint32_t k_cap, uint32_t n_cap);
 
+// d_cframe: optional per-cluster RNG frame word (merged cluster sets); when
+// null every cluster uses p.d_frame / p.frame
 vm_status ransac_planes(const vm_clusters& cl, const vm_ransac_params& p, const vm_planes& out,
-                        const WorkLayout& w, hipStream_t s);
+                        const WorkLayout& w, hipStream_t s, const uint32_t* d_cframe = nullptr);
 // the process-wide counting decomposition (vm_count_config)
 bool count_config_valid(const vm_count_config& c);
 vm_count_config count_config_default();
@@ -402,9 +404,10 @@ size_t fused_workspace_bytes(uint32_t k_cap, uint32_t n_cap, uint32_t H);
 vm_status planes_and_hulls(const vm_clusters& cl, const vm_ransac_params& p, const uint32_t* d_cframe,
                            const vm_planes& planes, const vm_hulls_out& hulls, void* d_work, size_t work_bytes,
                            const vm_fused_config& cfg, hipStream_t s);
+// ---- several cluster sets merged into one two-pass sequence (vm_multi.hip) -----
 size_t multi_workspace_bytes(uint32_t k_cap, uint32_t n_cap, uint32_t H);
 vm_status planes_hulls_multi(uint32_t n, const vm_clusters* sets, const uint32_t* frames, const vm_ransac_params& p,
                              const vm_planes* planes, const vm_hulls_out* hulls, uint32_t k_cap, uint32_t n_cap,
-                             void* d_work, size_t work_bytes, const vm_fused_config& cfg, hipStream_t s);
+                             void* d_work, size_t work_bytes, hipStream_t s);
 
 }  // namespace vm

@@ -570,13 +570,20 @@ __global__ void __launch_bounds__(kFBlock) k_fused(FusedArgs a)
             __syncthreads();
             for (uint32_t h = threadIdx.x; h < nc; h += kFBlock) part[h0 + h] = (int32_t)L.t.cnt[h];
         }
-        // completion: the item's stores become visible before its count
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        // completion.  A cluster of one item is finished by the workgroup
+        // that counted it (its counts are this workgroup's own stores, made
+        // visible by the barrier).  Otherwise the item's stores become
+        // visible device-wide before its count, and the workgroup that
+        // completes the cluster acquires them: on this chip an agent-scope
+        // release writes the XCD's L2 back and an acquire invalidates it,
+        // so they are kept to the clusters that need them.
+        const bool single = items_of(n, sp) == 1u;
+        if (!single) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         __syncthreads();
-        if (threadIdx.x == 0) s_flag = atomicAdd(&w.done[k], 1u) + 1u == items_of(n, sp);
+        if (threadIdx.x == 0) s_flag = single || atomicAdd(&w.done[k], 1u) + 1u == items_of(n, sp);
         __syncthreads();
         if (s_flag) {
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            if (!single) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             finish_cluster(a, k, frame, L.f);
         }
         __syncthreads();   // LDS and s_item are reused by the next item
@@ -854,348 +861,6 @@ vm_status planes_and_hulls(const vm_clusters& cl, const vm_ransac_params& p, con
     k_fused_copy<<<2048, kFBlock, 0, s>>>(w, cl.d_off, cl.d_x, cl.d_y, cl.d_z, (const float4*)planes.d_plane,
                                            planes.d_in_off, planes.in_cap, planes.d_in_idx, hulls.d_v_off,
                                            hulls.v_cap, hulls.d_v_idx, hulls.d_v_xyz, hulls.d_status);
-    VM_HIP(hipGetLastError());
-    return VM_OK;
-}
-
-
-// ---- several cluster sets in one persistent pass -----------------------------------
-namespace {
-
-constexpr uint32_t kMultiMax = 16;   // sets per call (the table travels as a kernel argument)
-
-struct MultiSet {
-    const uint32_t* meta;
-    const uint32_t* off;
-    const float* x;
-    const float* y;
-    const float* z;
-    const uint32_t* tag;
-    uint32_t k_in;        // clusters this set may contribute: min(set, planes, hulls k_cap)
-    uint32_t out_k_cap;   // min(planes, hulls k_cap)
-    uint32_t n_cap;       // the set's point bound
-    uint32_t frame;       // RNG counter word of its clusters
-    float4* plane;
-    int32_t* best;
-    int32_t* nin;
-    uint32_t* in_off;
-    uint32_t* in_idx;
-    int32_t* counts;
-    float4* hyp;
-    uint32_t* pstatus;
-    uint32_t in_cap;
-    uint32_t v_cap;
-    uint32_t* v_off;
-    uint32_t* v_idx;
-    float* v_xyz;
-    double* area;
-    uint32_t* hstatus;
-};
-
-struct MultiTab {
-    MultiSet s[kMultiMax];
-    uint32_t n;
-};
-
-struct MultiWork {
-    uint32_t* meta;     // [2] merged K, N
-    uint32_t* off;      // [k_cap + 1]
-    uint32_t* tag;      // [k_cap]
-    uint32_t* cframe;   // [k_cap]
-    float* x;           // [n_cap]
-    float* y;
-    float* z;
-    uint32_t* status;   // [1] the merged pass's own flags (each set's are set per set)
-    float4* plane;      // [k_cap]
-    int32_t* best;
-    int32_t* nin;
-    double* area;
-    int32_t* counts;    // [k_cap][H]
-    float4* hyp;        // [k_cap][H]
-    uint32_t* gin;      // [k_cap + 1] merged inlier prefix
-    uint32_t* gv;       // [k_cap + 1] merged vertex prefix
-    uint32_t* mset;     // [kMultiMax][4]: K, N, first merged cluster, first merged point
-    FusedWork fw;
-    size_t bytes;
-};
-
-MultiWork multi_layout(void* base, uint32_t k_cap, uint32_t n_cap, uint32_t H)
-{
-    MultiWork m{};
-    char* p = (char*)base;
-    size_t o = 0;
-    auto take = [&](size_t bytes) {
-        char* r = p ? p + o : nullptr;
-        o += align256(bytes);
-        return r;
-    };
-    m.meta = (uint32_t*)take(64);
-    m.off = (uint32_t*)take(((size_t)k_cap + 1) * 4);
-    m.tag = (uint32_t*)take(((size_t)k_cap + 1) * 4);
-    m.cframe = (uint32_t*)take(((size_t)k_cap + 1) * 4);
-    m.x = (float*)take(((size_t)n_cap + 1) * 4);
-    m.y = (float*)take(((size_t)n_cap + 1) * 4);
-    m.z = (float*)take(((size_t)n_cap + 1) * 4);
-    m.status = (uint32_t*)take(64);
-    m.plane = (float4*)take(((size_t)k_cap + 1) * 16);
-    m.best = (int32_t*)take(((size_t)k_cap + 1) * 4);
-    m.nin = (int32_t*)take(((size_t)k_cap + 1) * 4);
-    m.area = (double*)take(((size_t)k_cap + 1) * 8);
-    m.counts = (int32_t*)take((size_t)k_cap * H * 4);
-    m.hyp = (float4*)take((size_t)k_cap * H * 16);
-    m.gin = (uint32_t*)take(((size_t)k_cap + 1) * 4);
-    m.gv = (uint32_t*)take(((size_t)k_cap + 1) * 4);
-    m.mset = (uint32_t*)take(kMultiMax * 4 * 4);
-    char* fbase = p ? p + o : nullptr;
-    m.fw = fused_layout(fbase, k_cap, n_cap, H);
-    m.bytes = o + m.fw.bytes;
-    return m;
-}
-
-// the set holding merged cluster k (largest i with first cluster <= k)
-__device__ __forceinline__ uint32_t set_of(const uint32_t* mset, uint32_t n, uint32_t k, int field)
-{
-    uint32_t i = 0;
-    for (uint32_t q = 1; q < n; ++q)
-        if (mset[4 * q + field] <= k) i = q;
-    return i;
-}
-
-// validate every set, place it in the merged CSR (sets that no longer fit
-// contribute nothing and are flagged), write the merged counts
-__global__ void __launch_bounds__(kOneBlockThreads) k_multi_prep(MultiTab tab, MultiWork m, uint32_t k_cap,
-                                                                 uint32_t n_cap)
-{
-    __shared__ int bad;
-    __shared__ uint32_t sk[kMultiMax], sn[kMultiMax];
-    for (uint32_t i = 0; i < tab.n; ++i) {
-        const MultiSet& S = tab.s[i];
-        const uint32_t K = validate_clusters(S.meta, S.off, S.k_in, S.n_cap, S.pstatus, &bad);
-        if (threadIdx.x == 0) {
-            sk[i] = K;
-            sn[i] = K ? S.off[K] : 0u;
-            if (S.meta[0] > S.out_k_cap) atomicOr(S.pstatus, (uint32_t)VM_FLAG_CLUSTERS_CAP);
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        uint32_t kb = 0, pb = 0;
-        for (uint32_t i = 0; i < tab.n; ++i) {
-            uint32_t K = sk[i], N = sn[i];
-            if (kb + K > k_cap || pb + N > n_cap) {   // no room left: the set is skipped
-                atomicOr(tab.s[i].pstatus, (uint32_t)VM_FLAG_CLUSTERS_CAP);
-                atomicOr(tab.s[i].hstatus, (uint32_t)VM_FLAG_CLUSTERS_CAP);
-                K = 0;
-                N = 0;
-            }
-            m.mset[4 * i + 0] = K;
-            m.mset[4 * i + 1] = N;
-            m.mset[4 * i + 2] = kb;
-            m.mset[4 * i + 3] = pb;
-            kb += K;
-            pb += N;
-        }
-        m.meta[0] = kb;
-        m.meta[1] = pb;
-        m.off[kb] = pb;
-        m.status[0] = 0;
-    }
-}
-
-// the merged CSR: offsets, tags, frame words and points of every set
-__global__ void __launch_bounds__(kFBlock) k_multi_gather(MultiTab tab, MultiWork m)
-{
-    const uint32_t Kt = m.meta[0], Nt = m.meta[1];
-    const uint32_t stride = gridDim.x * blockDim.x;
-    for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < Kt; k += stride) {
-        const uint32_t i = set_of(m.mset, tab.n, k, 2);
-        const uint32_t kl = k - m.mset[4 * i + 2];
-        m.off[k] = m.mset[4 * i + 3] + tab.s[i].off[kl];
-        m.tag[k] = tab.s[i].tag[kl];
-        m.cframe[k] = tab.s[i].frame;
-    }
-    for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < Nt; q += stride) {
-        const uint32_t i = set_of(m.mset, tab.n, q, 3);
-        const uint32_t ql = q - m.mset[4 * i + 3];
-        m.x[q] = tab.s[i].x[ql];
-        m.y[q] = tab.s[i].y[ql];
-        m.z[q] = tab.s[i].z[ql];
-    }
-}
-
-// per-set inlier and vertex offsets, as each set alone would get them (a
-// cluster whose inlier list does not fit its set's in_cap gets no polygon)
-__global__ void __launch_bounds__(kOneBlockThreads) k_multi_scan(MultiTab tab, MultiWork m)
-{
-    const FusedWork& w = m.fw;
-    const uint32_t Kt = m.meta[0];
-    uint32_t tot[1];
-    one_block_scan<kOneBlockThreads, 4, 1>(
-        Kt, [&](uint32_t k, uint32_t(&v)[1]) { v[0] = w.nin[k]; },
-        [&](uint32_t k, const uint32_t(&e)[1]) { m.gin[k] = e[0]; }, tot);
-    if (threadIdx.x == 0) m.gin[Kt] = tot[0];
-    __syncthreads();
-    uint32_t vt[1];
-    one_block_scan<kOneBlockThreads, 4, 1>(
-        Kt,
-        [&](uint32_t k, uint32_t(&v)[1]) {
-            const uint32_t i = set_of(m.mset, tab.n, k, 2);
-            const uint32_t local = m.gin[k] - m.gin[m.mset[4 * i + 2]];
-            if (local + w.nin[k] > tab.s[i].in_cap && w.hcnt[k]) {
-                w.hcnt[k] = 0;
-                m.area[k] = 0.0;
-            }
-            v[0] = w.hcnt[k];
-        },
-        [&](uint32_t k, const uint32_t(&e)[1]) { m.gv[k] = e[0]; }, vt);
-    if (threadIdx.x == 0) m.gv[Kt] = vt[0];
-    __syncthreads();
-    // the sets' totals (and the offsets of sets without clusters)
-    for (uint32_t i = threadIdx.x; i < tab.n; i += blockDim.x) {
-        const MultiSet& S = tab.s[i];
-        const uint32_t K = m.mset[4 * i], k0 = m.mset[4 * i + 2];
-        const uint32_t ti = m.gin[k0 + K] - m.gin[k0], tv = m.gv[k0 + K] - m.gv[k0];
-        S.in_off[K] = ti;
-        S.v_off[K] = tv;
-        if (ti > S.in_cap) {
-            atomicOr(S.pstatus, (uint32_t)VM_FLAG_INLIERS_CAP);
-            atomicOr(S.hstatus, (uint32_t)VM_FLAG_INLIERS_CAP);
-        }
-    }
-}
-
-// each set's outputs from the merged pass (a workgroup per merged cluster at a time)
-__global__ void __launch_bounds__(kFBlock) k_multi_scatter(MultiTab tab, MultiWork m, uint32_t H, int with_all)
-{
-    const FusedWork& w = m.fw;
-    const uint32_t Kt = m.meta[0];
-    __shared__ bool over;
-    if (threadIdx.x == 0) over = false;
-    __syncthreads();
-    for (uint32_t k = blockIdx.x; k < Kt; k += gridDim.x) {
-        const uint32_t i = set_of(m.mset, tab.n, k, 2);
-        const MultiSet& S = tab.s[i];
-        const uint32_t k0 = m.mset[4 * i + 2], kl = k - k0;
-        const uint32_t pb = m.mset[4 * i + 3];
-        const uint32_t ib = m.gin[k] - m.gin[k0], vb = m.gv[k] - m.gv[k0];
-        const uint32_t base = m.off[k];
-        if (threadIdx.x == 0) {
-            S.plane[kl] = m.plane[k];
-            S.best[kl] = m.best[k];
-            S.nin[kl] = m.nin[k];
-            S.in_off[kl] = ib;
-            S.v_off[kl] = vb;
-            S.area[kl] = m.area[k];
-        }
-        if (with_all) {
-            for (uint32_t h = threadIdx.x; h < H; h += kFBlock) {
-                if (S.counts) S.counts[(size_t)kl * H + h] = m.counts[(size_t)k * H + h];
-                if (S.hyp) S.hyp[(size_t)kl * H + h] = m.hyp[(size_t)k * H + h];
-            }
-        }
-        const uint32_t nk = w.nin[k];
-        for (uint32_t j = threadIdx.x; j < nk; j += kFBlock)
-            if (ib + j < S.in_cap) S.in_idx[ib + j] = w.slot_in[base + j];
-        const uint32_t h = w.hcnt[k];
-        if (h == 0) continue;
-        const float4 pl = m.plane[k];
-        const double nx = pl.x, ny = pl.y, nz = pl.z, d = pl.w;
-        for (uint32_t q = threadIdx.x; q < h; q += kFBlock) {
-            const uint32_t pos = vb + q;
-            if (pos >= S.v_cap) {
-                over = true;
-                continue;
-            }
-            const uint32_t jj = w.slot_hull[base + k + q];
-            const uint32_t src = base + jj - pb;   // the set's own point index
-            const double px = S.x[src], py = S.y[src], pz = S.z[src];
-            const double dist = nx * px + ny * py + nz * pz + d;
-            S.v_idx[pos] = jj;
-            S.v_xyz[3 * (size_t)pos + 0] = (float)(px - dist * nx);
-            S.v_xyz[3 * (size_t)pos + 1] = (float)(py - dist * ny);
-            S.v_xyz[3 * (size_t)pos + 2] = (float)(pz - dist * nz);
-        }
-        __syncthreads();
-        if (threadIdx.x == 0 && over) {
-            atomicOr(S.hstatus, (uint32_t)VM_FLAG_HULL_CAP);
-            over = false;
-        }
-        __syncthreads();
-    }
-}
-
-}  // namespace
-
-size_t multi_workspace_bytes(uint32_t k_cap, uint32_t n_cap, uint32_t H)
-{
-    return multi_layout(nullptr, k_cap, n_cap, H).bytes;
-}
-
-vm_status planes_hulls_multi(uint32_t n, const vm_clusters* sets, const uint32_t* frames, const vm_ransac_params& p,
-                             const vm_planes* planes, const vm_hulls_out* hulls, uint32_t k_cap, uint32_t n_cap,
-                             void* d_work, size_t work_bytes, const vm_fused_config& cfg, hipStream_t s)
-{
-    if (n < 1 || n > kMultiMax || k_cap > kOneBlockMax) return VM_E_CAPACITY;
-    const uint32_t H = p.n_hyp;
-    const MultiWork m = multi_layout(d_work, k_cap, n_cap, H);
-    if (m.bytes > work_bytes) return VM_E_CAPACITY;
-    MultiTab tab{};
-    tab.n = n;
-    bool with_all = false;
-    for (uint32_t i = 0; i < n; ++i) {
-        MultiSet& S = tab.s[i];
-        const vm_clusters& c = sets[i];
-        S.meta = c.d_meta;
-        S.off = c.d_off;
-        S.x = c.d_x;
-        S.y = c.d_y;
-        S.z = c.d_z;
-        S.tag = c.d_tag;
-        S.out_k_cap = std::min(planes[i].k_cap, hulls[i].k_cap);
-        S.k_in = std::min(c.k_cap, S.out_k_cap);
-        S.n_cap = c.n_cap;
-        S.frame = frames[i];
-        S.plane = (float4*)planes[i].d_plane;
-        S.best = planes[i].d_best_h;
-        S.nin = planes[i].d_n_inliers;
-        S.in_off = planes[i].d_in_off;
-        S.in_idx = planes[i].d_in_idx;
-        S.counts = planes[i].d_counts;
-        S.hyp = (float4*)planes[i].d_hyp;
-        S.pstatus = planes[i].d_status;
-        S.in_cap = planes[i].in_cap;
-        S.v_cap = hulls[i].v_cap;
-        S.v_off = hulls[i].d_v_off;
-        S.v_idx = hulls[i].d_v_idx;
-        S.v_xyz = hulls[i].d_v_xyz;
-        S.area = hulls[i].d_area;
-        S.hstatus = hulls[i].d_status;
-        with_all = with_all || S.counts || S.hyp;
-    }
-    {
-        StageScope t(VM_STAGE_GROUP, s);
-        k_multi_prep<<<1, kOneBlockThreads, 0, s>>>(tab, m, k_cap, n_cap);
-        k_multi_gather<<<1024, kFBlock, 0, s>>>(tab, m);
-        VM_HIP(hipGetLastError());
-    }
-    vm_clusters mc;
-    mc.k_cap = k_cap;
-    mc.n_cap = n_cap;
-    mc.d_meta = m.meta;
-    mc.d_off = m.off;
-    mc.d_x = m.x;
-    mc.d_y = m.y;
-    mc.d_z = m.z;
-    mc.d_key = nullptr;
-    mc.d_tag = m.tag;
-    const Split sp = make_split(H, cfg);
-    vm_status st = fused_core(mc, p, m.cframe, k_cap, k_cap, m.fw, sp, m.plane, m.best, m.nin,
-                              with_all ? m.counts : nullptr, with_all ? m.hyp : nullptr, m.area, m.status,
-                              cfg.groups_per_cu, s);
-    if (st != VM_OK) return st;
-    StageScope t(VM_STAGE_HULL, s);
-    k_multi_scan<<<1, kOneBlockThreads, 0, s>>>(tab, m);
-    k_multi_scatter<<<(int)std::min<uint32_t>(k_cap ? k_cap : 1, 2048), kFBlock, 0, s>>>(tab, m, H, with_all ? 1 : 0);
     VM_HIP(hipGetLastError());
     return VM_OK;
 }

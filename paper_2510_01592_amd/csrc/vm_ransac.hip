@@ -40,13 +40,14 @@ __global__ void __launch_bounds__(kBlock) k_hypotheses(const uint32_t* __restric
                                                        const float* __restrict__ Y, const float* __restrict__ Z,
                                                        uint32_t H, uint64_t seed, uint32_t frame_arg,
                                                        const uint32_t* __restrict__ d_frame,
+                                                       const uint32_t* __restrict__ cframe,
                                                        const uint32_t* __restrict__ tile_off,
                                                        uint32_t* __restrict__ tile_k,
                                                        const uint32_t* __restrict__ tile_off_big,
                                                        uint32_t* __restrict__ tile_k_big, uint32_t wave_max,
                                                        int32_t* __restrict__ counts, float4* __restrict__ hyp)
 {
-    const uint32_t frame = d_frame ? *d_frame : frame_arg;
+    const uint32_t frame_all = d_frame ? *d_frame : frame_arg;
     const uint32_t K = small[0];
     const uint64_t total = (uint64_t)K * H;
     for (uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
@@ -69,6 +70,7 @@ __global__ void __launch_bounds__(kBlock) k_hypotheses(const uint32_t* __restric
         for (uint32_t q = h; q < nt; q += H) tile_k[tile_off[k] + q] = k;
         if (n > wave_max)
             for (uint32_t q = h; q < nt; q += H) tile_k_big[tile_off_big[k] + q] = k;
+        const uint32_t frame = cframe ? cframe[k] : frame_all;   // a merged set's clusters carry their own
         const float4 pl = hyp_plane(X + base, Y + base, Z + base, n, h, tag[k], frame, seed);
         // the tiled kernel adds into the counts; the wave kernel stores every
         // count of its clusters, and clusters of fewer than 3 points have no
@@ -649,7 +651,7 @@ void count_config_set(const vm_count_config& c)
 }
 
 vm_status ransac_planes(const vm_clusters& cl, const vm_ransac_params& p, const vm_planes& out,
-                        const WorkLayout& w, hipStream_t s)
+                        const WorkLayout& w, hipStream_t s, const uint32_t* d_cframe)
 {
     // the workspace is laid out for kc = min(cl.k_cap, out.k_cap) clusters
     const uint32_t kc = cl.k_cap < out.k_cap ? cl.k_cap : out.k_cap;
@@ -671,7 +673,7 @@ vm_status ransac_planes(const vm_clusters& cl, const vm_ransac_params& p, const 
         }
         const uint64_t kh = (uint64_t)kc * H;
         k_hypotheses<<<grid_for(kh, kBlock, 16384), kBlock, 0, s>>>(w.small, cl.d_off, cl.d_tag, cl.d_x, cl.d_y,
-                                                                    cl.d_z, H, p.seed, p.frame, p.d_frame,
+                                                                    cl.d_z, H, p.seed, p.frame, p.d_frame, d_cframe,
                                                                     w.tile_off, w.tile_k, w.tile_off_big, w.tile_k_big,
                                                                     cc.wave_max_points, w.counts, w.hyp);
         VM_HIP(hipGetLastError());

@@ -214,9 +214,9 @@ class GpuBackend(Backend):
     frames of different robots overlap on the device.
     batch=True (continuous batching): the frames admitted together are
     inserted and labelled on their robots' streams (concurrently), then the
-    planes and polygons of all their clusters are computed in one persistent
-    pass (vm_planes_hulls_multi) on a batch stream, each cluster with its own
-    robot's frame number.  A robot's next frame is labelled only after the
+    planes and polygons of all their clusters are computed by one merged
+    sequence of launches (vm_planes_hulls_multi) on a batch stream, each
+    cluster with its own robot's frame number.  A robot's next frame is labelled only after the
     batch that read its map's clusters; its insert may run before.  The
     results are the same in both modes and the same alone or in the mix."""
 
@@ -227,7 +227,7 @@ class GpuBackend(Backend):
         inlier and hull lists) are copied to host memory too, behind the
         frame on its stream, for maps of at most capture_cap occupied voxels
         (for checks; costs large copies).  batch_k_cap / batch_n_cap bound the
-        clusters and points of one persistent pass; a batch whose frames exceed them is split into
+        clusters and points of one merged pass; a batch whose frames exceed them is split into
         several passes (its frames' sizes are read back once their clustering is done)."""
         import torch
 
@@ -249,9 +249,10 @@ class GpuBackend(Backend):
                                      device="cuda")
             self.robot_last = [None] * len(maps)
             self.swork = None    # workspace of single-frame groups, if the batch's is too small
-            self.groups = 0      # persistent passes run (a batch splits where its clusters exceed the caps)
+            self.groups = 0      # merged passes run (a batch splits where its clusters exceed the caps)
         self.host = [dict(plane=torch.empty((k_cap, 4), dtype=torch.float32).pin_memory(),
                           best=torch.empty(k_cap, dtype=torch.int32).pin_memory(),
+                          nin=torch.empty(k_cap, dtype=torch.int32).pin_memory(),
                           area=torch.empty(k_cap, dtype=torch.float64).pin_memory(),
                           v_off=torch.empty(k_cap + 1, dtype=torch.int32).pin_memory(),
                           meta=torch.empty(2, dtype=torch.int32).pin_memory(),
@@ -307,6 +308,7 @@ class GpuBackend(Backend):
             c["v_xyz"].copy_(hb.v_xyz[:self.v_cap], non_blocking=True)
         h["plane"].copy_(pb.plane, non_blocking=True)
         h["best"].copy_(pb.best_h, non_blocking=True)
+        h["nin"].copy_(pb.n_inliers, non_blocking=True)
         h["area"].copy_(hb.area, non_blocking=True)
         h["v_off"].copy_(hb.v_off, non_blocking=True)
         h["meta"].copy_(vm.device_view(cl.d_meta, 2, np.int32), non_blocking=True)
@@ -388,7 +390,8 @@ class GpuBackend(Backend):
             kw = self.kw
             for g in groups:
                 if len(g) == 1:
-                    # a frame alone: the single-set persistent pass with its own frame word
+                    # a frame alone (it may exceed the merged bounds): the two-pass
+                    # kernels with its own frame word
                     i = g[0]
                     need = vm.workspace_bytes(min(views[i].k_cap, pbs[i].k_cap, hbs[i].k_cap), views[i].n_cap,
                                               kw["n_hyp"])
@@ -397,8 +400,9 @@ class GpuBackend(Backend):
                         if self.swork is None or self.swork.numel() < need:
                             self.swork = torch.empty(need, dtype=torch.uint8, device="cuda")
                         work = self.swork
-                    vm.planes_hulls(views[i], vm.ransac_params(kw["n_hyp"], kw["eps"], kw["seed"], frames[i]),
-                                    pbs[i], hbs[i], work, stream=bs)
+                    prm = vm.ransac_params(kw["n_hyp"], kw["eps"], kw["seed"], frames[i])
+                    vm.ransac_planes(views[i], prm, pbs[i], work, stream=bs)
+                    vm.hulls(views[i], pbs[i], hbs[i], work, stream=bs)
                 else:
                     vm.planes_hulls_multi([views[i] for i in g], [frames[i] for i in g],
                                           vm.ransac_params(kw["n_hyp"], kw["eps"], kw["seed"]),
@@ -419,7 +423,8 @@ class GpuBackend(Backend):
     def result(self, handle, slot: int):
         h = self.host[slot]
         K = min(int(h["meta"][0]), self.k_cap)
-        out = dict(K=int(h["meta"][0]), plane=h["plane"][:K].numpy().copy(), best=h["best"][:K].numpy().copy(),
+        out = dict(K=int(h["meta"][0]), N=int(h["meta"][1]), plane=h["plane"][:K].numpy().copy(),
+                   best=h["best"][:K].numpy().copy(), nin=h["nin"][:K].numpy().copy(),
                    area=h["area"][:K].numpy().copy(), v_off=h["v_off"][:K + 1].numpy().copy(),
                    status=h["status"].numpy().copy(), occupied=int(h["stats"][0]))
         if self.capture:

@@ -203,3 +203,36 @@ def test_multi_sets_equal_each_alone():
     assert int(pbs2[2].status.cpu()[0]) & vm.FLAG_CLUSTERS_CAP
     assert int(hbs2[2].status.cpu()[0]) & vm.FLAG_CLUSTERS_CAP
     assert int(pbs2[2].in_off.cpu()[0]) == 0 and int(hbs2[2].v_off.cpu()[0]) == 0
+
+
+def test_multi_sets_with_small_outputs_equal_each_alone():
+    """Merged sets whose own outputs are too small: one set's inlier list
+    holds a third of its inliers (later clusters lose their polygons), one
+    set's vertex list holds 40 vertices, one set has more clusters than its
+    outputs; each gets exactly what it gets alone with the same outputs
+    (flags, offsets, the entries that fit)."""
+    import torch
+    import paper_2510_01592_amd as vm
+    H = 256
+    data = [ragged_clusters(seed=s, n_clusters=n, n_max=m) for s, n, m in ((31, 25, 20_000), (32, 20, 6_000),
+                                                                           (33, 30, 9_000))]
+    views = [_view(vm, *d) for d in data]
+    frames = [3, 11, 7]
+    Ks = [len(d[2]) for d in data]
+    Ns = [len(d[1]) for d in data]
+    k_cap, n_cap = sum(Ks), sum(Ns)
+    caps = [(Ks[0], Ns[0] // 3, Ns[0]), (Ks[1], Ns[1], 40), (Ks[2] - 4, Ns[2], Ns[2])]
+    work = torch.empty(vm.multi_workspace_bytes(k_cap, n_cap, H), dtype=torch.uint8, device="cuda")
+    pbs = [vm.PlaneBuffers.alloc(kc, ic, H) for kc, ic, _ in caps]
+    hbs = [vm.HullBuffers.alloc(kc, vc) for kc, _, vc in caps]
+    note("multi: sets with small outputs")
+    vm.planes_hulls_multi([v for v, _ in views], frames, vm.ransac_params(H, 0.01, SEED, 0), pbs, hbs, k_cap, n_cap,
+                          work)
+    torch.cuda.synchronize()
+    for i, ((cl, _), f) in enumerate(zip(views, frames)):
+        kc, ic, vc = caps[i]
+        alone = _run(vm, cl, H, f, False, k_cap=kc, in_cap=ic, v_cap=vc, with_all=False)
+        _same((planes_np(pbs[i]), hulls_np(hbs[i])), alone, min(kc, Ks[i]))
+    assert int(pbs[0].status.cpu()[0]) & vm.FLAG_INLIERS_CAP
+    assert int(hbs[1].status.cpu()[0]) & vm.FLAG_HULL_CAP
+    assert int(pbs[2].status.cpu()[0]) & vm.FLAG_CLUSTERS_CAP
