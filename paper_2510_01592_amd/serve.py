@@ -249,6 +249,7 @@ class GpuBackend(Backend):
                                      device="cuda")
             self.robot_last = [None] * len(maps)
             self.swork = None    # workspace of single-frame groups, if the batch's is too small
+            self.kn_host = [torch.empty(2, dtype=torch.int32).pin_memory() for _ in range(n_slots)]
             self.groups = 0      # merged passes run (a batch splits where its clusters exceed the caps)
         self.host = [dict(plane=torch.empty((k_cap, 4), dtype=torch.float32).pin_memory(),
                           best=torch.empty(k_cap, dtype=torch.int32).pin_memory(),
@@ -357,6 +358,8 @@ class GpuBackend(Backend):
                 m.stats_async(self.stats_dev[slot], stream=s)
                 self.planes[slot].status.zero_()
                 self.hulls[slot].status.zero_()
+                # the cluster and point counts, to pinned memory behind the labelling
+                self.kn_host[slot].copy_(vm.device_view(cl.d_meta, 2, np.int32), non_blocking=True)
                 ev = torch.cuda.Event()
                 ev.record(s)
                 d.record_stream(s)
@@ -369,10 +372,10 @@ class GpuBackend(Backend):
         # clustering), then groups of consecutive frames within the batch
         # capacities: nothing is truncated by merging
         sizes = []
-        for ev, cl in zip(ready, views):
+        for ev, (req, slot) in zip(ready, items):
             ev.synchronize()
-            meta = vm.device_view(cl.d_meta, 2, np.int32).cpu().numpy()
-            sizes.append((int(meta[0]), int(meta[1])))
+            kn = self.kn_host[slot]
+            sizes.append((int(kn[0]), int(kn[1])))
         groups, cur, ck, cn = [], [], 0, 0
         for i, (k, n) in enumerate(sizes):
             if cur and (ck + k > self.bk or cn + n > self.bn):
