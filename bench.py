@@ -638,7 +638,7 @@ def _served(vm, torch, seconds: float, n_robots: int = 8, rate_hz: float = 30.0,
     # an accumulating map's outliers form thousands of small clusters: room for 65536 per frame
     be = GpuBackend(maps, n_slots=n_slots, n_hyp=512, k_cap=65536)
     be_b = GpuBackend(maps, n_slots=n_slots, n_hyp=512, k_cap=65536, batch=True, batch_k_cap=65536,
-                      batch_n_cap=1 << 24)
+                      batch_n_cap=1 << 26)
 
     def reset():
         with torch.cuda.stream(s):
