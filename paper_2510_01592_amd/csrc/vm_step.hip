@@ -219,8 +219,8 @@ __global__ void __launch_bounds__(kBlock) k_step_classify(StepArgs a, const DevC
         nz /= len;
         // the orientation as one flag and a product with -1 or +1 (exact; +0
         // becomes -0 as under negation): no branches, whose nested short
-        // circuits this build has been seen to resolve for nz >= 0 without the
-        // inner tests
+        // circuits the device compiler has been seen to resolve for nz >= 0
+        // without the inner tests
         const bool flip = (nz < 0.0) | ((nz == 0.0) & ((ny < 0.0) | ((ny == 0.0) & (nx < 0.0))));
         const double sg = flip ? -1.0 : 1.0;
         nx *= sg;
