@@ -746,7 +746,12 @@ __global__ void __launch_bounds__(kBlock) k_group_pairs(const DevCounters* __res
     }
 }
 
-// CSR points: key and Eq. (1) mean of each kept voxel, cluster-major
+constexpr int kGatherU = 4;
+
+// CSR points: key and Eq. (1) mean of each kept voxel, cluster-major.  Each
+// lane gathers kGatherU voxels kGatherU * stride apart, their first probes
+// issued together; a probe loads the whole 32-byte slot, so a hit needs no
+// second load for the sums.
 __global__ void __launch_bounds__(kBlock) k_group_gather(Geom g, Hash h, const DevCounters* __restrict__ ctr,
                                                          const uint32_t* __restrict__ sorted_key0,
                                                          const uint32_t* __restrict__ sorted_key1,
@@ -756,20 +761,47 @@ __global__ void __launch_bounds__(kBlock) k_group_gather(Geom g, Hash h, const D
     const uint32_t* __restrict__ sorted_key = ctr->group_sel ? sorted_key1 : sorted_key0;
     const uint32_t n = ctr->meta[1];
     const uint32_t nx = (uint32_t)g.dims[0], ny = (uint32_t)g.dims[1];
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const uint32_t k = sorted_key[i];
-        const uint32_t s = hash_find(h, k);
-        float mx = 0.0f, my = 0.0f, mz = 0.0f;
-        if (s != kEmpty) {
-            const Slot sl = h.slot[s];
-            mx = voxel_mean_axis(k % nx, sl.sum[0], sl.cnt, g.voxel_size, g.origin[0]);
-            my = voxel_mean_axis((k / nx) % ny, sl.sum[1], sl.cnt, g.voxel_size, g.origin[1]);
-            mz = voxel_mean_axis(k / (nx * ny), sl.sum[2], sl.cnt, g.voxel_size, g.origin[2]);
+    const uint32_t stride = gridDim.x * blockDim.x;
+    const uint32_t nprobe = h.mask < kMaxProbe ? h.mask + 1u : kMaxProbe;
+    for (uint32_t i0 = blockIdx.x * blockDim.x + threadIdx.x; i0 < n; i0 += kGatherU * stride) {
+        uint32_t k[kGatherU], s[kGatherU];
+        Slot sl[kGatherU];
+#pragma unroll
+        for (int u = 0; u < kGatherU; ++u) {
+            const uint32_t i = i0 + (uint32_t)u * stride;
+            k[u] = i < n ? sorted_key[i] : kEmpty;
         }
-        cl_key[i] = k;
-        cl_x[i] = mx;
-        cl_y[i] = my;
-        cl_z[i] = mz;
+#pragma unroll
+        for (int u = 0; u < kGatherU; ++u) {
+            s[u] = hash_slot(k[u], h.log2cap);
+            if (k[u] != kEmpty) {
+                sl[u] = h.slot[s[u]];
+            } else {
+                sl[u].key = kEmpty;
+                sl[u].cnt = 0;
+                sl[u].sum[0] = sl[u].sum[1] = sl[u].sum[2] = 0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kGatherU; ++u) {
+            const uint32_t i = i0 + (uint32_t)u * stride;
+            if (i >= n) continue;
+            // linear probing as in hash_find
+            for (uint32_t p = 1; sl[u].key != k[u] && sl[u].key != kEmpty && p < nprobe; ++p) {
+                s[u] = (s[u] + 1) & h.mask;
+                sl[u] = h.slot[s[u]];
+            }
+            float mx = 0.0f, my = 0.0f, mz = 0.0f;
+            if (sl[u].key == k[u]) {
+                mx = voxel_mean_axis(k[u] % nx, sl[u].sum[0], sl[u].cnt, g.voxel_size, g.origin[0]);
+                my = voxel_mean_axis((k[u] / nx) % ny, sl[u].sum[1], sl[u].cnt, g.voxel_size, g.origin[1]);
+                mz = voxel_mean_axis(k[u] / (nx * ny), sl[u].sum[2], sl[u].cnt, g.voxel_size, g.origin[2]);
+            }
+            cl_key[i] = k[u];
+            cl_x[i] = mx;
+            cl_y[i] = my;
+            cl_z[i] = mz;
+        }
     }
 }
 
@@ -804,7 +836,6 @@ hipError_t launch_ccl(const Geom& g, const uint32_t* bits, SegBuffers& b, uint32
                       hipStream_t s)
 {
     const Dims d = dims_of(g);
-    const int grid = grid_for(cap);
     TileGrid tg;
     tg.ntx = (d.nx + kTX - 1) / kTX;
     tg.nty = (d.ny + kTY - 1) / kTY;
@@ -823,7 +854,7 @@ hipError_t launch_ccl(const Geom& g, const uint32_t* bits, SegBuffers& b, uint32
         StageScope t(VM_STAGE_CCL_LINK, s);
         k_ccl_boundary<<<vgrid, kBlock, 0, s>>>(bits, g.nwords, b.wrank, d, tg, b.parent, b.pairs, b.npair);
         k_ccl_pairs<<<tgrid, kBlock, 0, s>>>((uint32_t)ntiles, b.pairs, b.npair, b.parent);
-        k_ccl_flatten<<<grid, kBlock, 0, s>>>(ctr, b.parent, b.csize);
+        k_ccl_flatten<<<grid_for(cap), kBlock, 0, s>>>(ctr, b.parent, b.csize);
     }
     return hipGetLastError();
 }
@@ -849,7 +880,8 @@ hipError_t launch_group(const Geom& g, const Hash& h, SegBuffers& b, uint32_t ca
     if ((e = radix_sort_pairs_dev(b.sort_k, b.sort_v, &ctr->meta[1], cap, bits_needed, &ctr->kmax, b.hist, b.blk,
                                   &ctr->group_sel, s)) != hipSuccess)
         return e;
-    k_group_gather<<<grid, kBlock, 0, s>>>(g, h, ctr, b.sort_v[0], b.sort_v[1], b.cl_key, b.cl_x, b.cl_y, b.cl_z);
+    k_group_gather<<<grid_for((cap + kGatherU - 1) / kGatherU, kBlock, 2048), kBlock, 0, s>>>(
+        g, h, ctr, b.sort_v[0], b.sort_v[1], b.cl_key, b.cl_x, b.cl_y, b.cl_z);
     if (d_labels) k_labels<<<grid, kBlock, 0, s>>>(ctr, b.parent, b.occ_key, d_labels);
     return hipGetLastError();
 }

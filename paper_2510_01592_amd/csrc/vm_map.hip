@@ -110,6 +110,9 @@ constexpr uint32_t kBucketTable = 1u << kBucketTableLog2;   // LDS table slots: 
                                                              // fit on a CU; a bucket averages kBucketAvg
                                                              // points, so the table is about half full
 static_assert(kBucketTable >= kBucketChunk, "a chunk's distinct keys always fit: every probe ends");
+constexpr uint32_t kRecPerThread = kBucketChunk / kBlock;   // records per thread per fill
+constexpr uint32_t kSlotPerThread = kBucketTable / kBlock;  // table entries per thread
+static_assert(kRecPerThread * kBlock == kBucketChunk && kSlotPerThread * kBlock == kBucketTable, "whole rows per thread");
 
 __device__ __forceinline__ uint32_t bucket_of(uint32_t key, uint32_t lb)
 {
@@ -222,10 +225,19 @@ __global__ void __launch_bounds__(kBlock) k_bucket_insert(const uint4* __restric
                 tsum[0][q] = tsum[1][q] = tsum[2][q] = 0;
             }
             __syncthreads();
-            for (uint32_t i = c0 + threadIdx.x; i < c1; i += kBlock) {
-                const uint4 r = rec[i];
-                const uint32_t k = r.x;
-                const unsigned long long pk = (unsigned long long)r.y | ((unsigned long long)r.z << 32);
+            // a chunk is kRecPerThread records per thread: all loaded before the
+            // table inserts
+            uint4 rr[kRecPerThread];
+#pragma unroll
+            for (uint32_t u = 0; u < kRecPerThread; ++u) {
+                const uint32_t i = c0 + threadIdx.x + u * kBlock;
+                if (i < c1) rr[u] = rec[i];
+            }
+#pragma unroll
+            for (uint32_t u = 0; u < kRecPerThread; ++u) {
+                if (c0 + threadIdx.x + u * kBlock >= c1) continue;
+                const uint32_t k = rr[u].x;
+                const unsigned long long pk = (unsigned long long)rr[u].y | ((unsigned long long)rr[u].z << 32);
                 uint32_t q = table_slot(k);
                 for (;;) {   // at most kBucketChunk keys in a table of kBucketTable slots: ends
                     const uint32_t old = atomicCAS(&tkey[q], kEmpty, k);
@@ -238,28 +250,52 @@ __global__ void __launch_bounds__(kBlock) k_bucket_insert(const uint4* __restric
                 atomicAdd(&tsum[2][q], (uint32_t)((pk >> 40) & 0xFFFFF));
             }
             __syncthreads();
-            for (uint32_t q = threadIdx.x; q < kBucketTable; q += kBlock) {
-                const uint32_t k = tkey[q];
+            // the thread's kSlotPerThread table entries: first probes (whole
+            // 32-byte slots) issued together
+            uint32_t tk[kSlotPerThread], sl[kSlotPerThread];
+            uint4 sa[kSlotPerThread], sb[kSlotPerThread];
+#pragma unroll
+            for (uint32_t u = 0; u < kSlotPerThread; ++u) {
+                tk[u] = tkey[threadIdx.x + u * kBlock];
+                sl[u] = hash_slot(tk[u], h.log2cap);
+                if (tk[u] != kEmpty) {
+                    const uint4* sp = reinterpret_cast<const uint4*>(&h.slot[sl[u]]);
+                    sa[u] = sp[0];
+                    sb[u] = sp[1];
+                }
+            }
+#pragma unroll
+            for (uint32_t u = 0; u < kSlotPerThread; ++u) {
+                const uint32_t q = threadIdx.x + u * kBlock;
+                const uint32_t k = tk[u];
                 if (k == kEmpty) continue;
                 ++n_upd;
-                uint32_t sl = hash_slot(k, h.log2cap);
-                bool ok = false;
-                for (uint32_t p = 0; p < kMaxProbe && p <= h.mask; ++p) {
-                    const uint32_t kk = h.slot[sl].key;
-                    if (kk == k) { ok = true; break; }
-                    if (kk == kEmpty) {
-                        const uint32_t old = atomicCAS(&h.slot[sl].key, kEmpty, k);
-                        if (old == kEmpty || old == k) { ok = true; break; }
+                uint32_t s = sl[u];
+                uint4 a = sa[u], b2 = sb[u];
+                bool ok = a.x == k;
+                if (!ok) {
+                    for (uint32_t p = 0; p < kMaxProbe && p <= h.mask; ++p) {
+                        if (p) a.x = h.slot[s].key;
+                        if (a.x == k) { ok = true; break; }
+                        if (a.x == kEmpty) {
+                            const uint32_t old = atomicCAS(&h.slot[s].key, kEmpty, k);
+                            if (old == kEmpty || old == k) { ok = true; break; }
+                        }
+                        s = (s + 1) & h.mask;
                     }
-                    sl = (sl + 1) & h.mask;
+                    if (ok) {
+                        // claimed or found past the first probe: the slot's
+                        // counts as they stand now
+                        const uint4* sp = reinterpret_cast<const uint4*>(&h.slot[s]);
+                        a = sp[0];
+                        b2 = sp[1];
+                    }
                 }
                 if (!ok) {
                     n_lost += tcnt[q];
                     continue;
                 }
-                // the slot as two 16-byte halves: {key, cnt, sum0}, {sum1, sum2}
-                uint4* sp = reinterpret_cast<uint4*>(&h.slot[sl]);
-                uint4 a = sp[0], b2 = sp[1];
+                uint4* sp = reinterpret_cast<uint4*>(&h.slot[s]);
                 const unsigned long long s0 = ((unsigned long long)a.w << 32 | a.z) + tsum[0][q];
                 const unsigned long long s1 = ((unsigned long long)b2.y << 32 | b2.x) + tsum[1][q];
                 const unsigned long long s2 = ((unsigned long long)b2.w << 32 | b2.z) + tsum[2][q];
