@@ -139,10 +139,10 @@ __device__ __forceinline__ uint32_t validate_clusters(const uint32_t* meta, cons
 
 // Add per-thread counts into global 64-bit counters with one atomic per block
 // and counter (zero totals skipped).  Every thread of the block must call it.
-template <int N>
+template <int N, int T = kBlock>
 __device__ __forceinline__ void block_add_counters(unsigned long long* const (&dst)[N], const uint32_t (&v)[N])
 {
-    __shared__ unsigned long long part[N][kBlock / kWave];
+    __shared__ unsigned long long part[N][T / kWave];
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
 #pragma unroll
     for (int c = 0; c < N; ++c) {

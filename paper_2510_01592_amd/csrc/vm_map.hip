@@ -101,6 +101,7 @@ __global__ void __launch_bounds__(kBlock) k_insert(const float* __restrict__ xyz
 // voxel, a plain read-modify-write since no other workgroup touches those
 // voxels.
 constexpr uint32_t kBucketTile = 4096;    // points per workgroup in the partition passes (at least)
+constexpr int kPartBlock = 1024;          // partition workgroup: 16 waves, four points per thread per tile
 constexpr uint32_t kBucketBlocks = 1024;  // partition workgroups per batch (at most)
 constexpr uint32_t kBucketAvg = 512;      // target points per bucket
 constexpr uint32_t kBucketMaxLog2 = 12;   // at most 4096 buckets (LDS counters)
@@ -109,6 +110,7 @@ constexpr uint32_t kBucketTableLog2 = 10;
 constexpr uint32_t kBucketTable = 1u << kBucketTableLog2;   // LDS table slots: 20 KB, so eight workgroups
                                                              // fit on a CU; a bucket averages kBucketAvg
                                                              // points, so the table is about half full
+static_assert(kBucketTile % kPartBlock == 0, "whole rows of points per partition workgroup");
 static_assert(kBucketTable >= kBucketChunk, "a chunk's distinct keys always fit: every probe ends");
 constexpr uint32_t kRecPerThread = kBucketChunk / kBlock;   // records per thread per fill
 constexpr uint32_t kSlotPerThread = kBucketTable / kBlock;  // table entries per thread
@@ -126,7 +128,7 @@ __device__ __forceinline__ uint32_t table_slot(uint32_t key)
     return (key * 0xCC9E2D51u) >> (32 - kBucketTableLog2);
 }
 
-__global__ void __launch_bounds__(kBlock) k_vox_bucket(const float* __restrict__ xyz, uint32_t n, Pose pose, Geom g,
+__global__ void __launch_bounds__(kPartBlock) k_vox_bucket(const float* __restrict__ xyz, uint32_t n, Pose pose, Geom g,
                                                        uint32_t lb, uint32_t nblk, uint32_t tile, bool first_batch,
                                                        uint32_t* __restrict__ key_out,
                                                        unsigned long long* __restrict__ packed,
@@ -134,7 +136,7 @@ __global__ void __launch_bounds__(kBlock) k_vox_bucket(const float* __restrict__
 {
     __shared__ uint32_t cnt[1u << kBucketMaxLog2];
     const uint32_t B = 1u << lb;
-    for (uint32_t b = threadIdx.x; b < B; b += kBlock) cnt[b] = 0;
+    for (uint32_t b = threadIdx.x; b < B; b += kPartBlock) cnt[b] = 0;
     if (blockIdx.x == 0 && threadIdx.x == 0 && first_batch) ctr->touched = 0;
     __syncthreads();
     uint32_t n_in = 0, n_drop = 0;
@@ -142,8 +144,8 @@ __global__ void __launch_bounds__(kBlock) k_vox_bucket(const float* __restrict__
     const double lim1 = (double)g.dims[1] * 1048576.0;
     const double lim2 = (double)g.dims[2] * 1048576.0;
     const uint64_t base = (uint64_t)blockIdx.x * tile;
-    for (uint32_t j = 0; j < tile / kBlock; ++j) {
-        const uint64_t i = base + (uint64_t)j * kBlock + threadIdx.x;
+    for (uint32_t j = 0; j < tile / kPartBlock; ++j) {
+        const uint64_t i = base + (uint64_t)j * kPartBlock + threadIdx.x;
         if (i >= n) break;
         const double px = (double)xyz[3 * (size_t)i + 0];
         const double py = (double)xyz[3 * (size_t)i + 1];
@@ -172,14 +174,14 @@ __global__ void __launch_bounds__(kBlock) k_vox_bucket(const float* __restrict__
         packed[i] = pk;
     }
     __syncthreads();
-    for (uint32_t b = threadIdx.x; b < B; b += kBlock) hist[(uint64_t)b * nblk + blockIdx.x] = cnt[b];
+    for (uint32_t b = threadIdx.x; b < B; b += kPartBlock) hist[(uint64_t)b * nblk + blockIdx.x] = cnt[b];
     unsigned long long* const dst[2] = {&ctr->points_in, &ctr->points_dropped};
     const uint32_t v[2] = {n_in, n_drop};
-    block_add_counters<2>(dst, v);
+    block_add_counters<2, kPartBlock>(dst, v);
 }
 
 // Points to their buckets (hist holds the exclusive scan, bucket-major).
-__global__ void __launch_bounds__(kBlock) k_bucket_scatter(const uint32_t* __restrict__ key_in,
+__global__ void __launch_bounds__(kPartBlock) k_bucket_scatter(const uint32_t* __restrict__ key_in,
                                                            const unsigned long long* __restrict__ packed, uint32_t n,
                                                            uint32_t lb, uint32_t nblk, uint32_t tile,
                                                            const uint32_t* __restrict__ hist,
@@ -187,11 +189,11 @@ __global__ void __launch_bounds__(kBlock) k_bucket_scatter(const uint32_t* __res
 {
     __shared__ uint32_t pos[1u << kBucketMaxLog2];
     const uint32_t B = 1u << lb;
-    for (uint32_t b = threadIdx.x; b < B; b += kBlock) pos[b] = hist[(uint64_t)b * nblk + blockIdx.x];
+    for (uint32_t b = threadIdx.x; b < B; b += kPartBlock) pos[b] = hist[(uint64_t)b * nblk + blockIdx.x];
     __syncthreads();
     const uint64_t base = (uint64_t)blockIdx.x * tile;
-    for (uint32_t j = 0; j < tile / kBlock; ++j) {
-        const uint64_t i = base + (uint64_t)j * kBlock + threadIdx.x;
+    for (uint32_t j = 0; j < tile / kPartBlock; ++j) {
+        const uint64_t i = base + (uint64_t)j * kPartBlock + threadIdx.x;
         if (i >= n) break;
         const uint32_t k = key_in[i];
         if (k == kEmpty) continue;
@@ -587,11 +589,11 @@ hipError_t launch_insert(const float* xyz, int64_t n, const Pose& pose, const Ge
         const uint32_t lb = bucket_log2(m);
         const uint32_t tile = bucket_tile(m);
         const uint32_t nblk = (m + tile - 1) / tile;
-        k_vox_bucket<<<nblk, kBlock, 0, s>>>(xyz + 3 * done, m, pose, g, lb, nblk, tile, done == 0, sc.key,
+        k_vox_bucket<<<nblk, kPartBlock, 0, s>>>(xyz + 3 * done, m, pose, g, lb, nblk, tile, done == 0, sc.key,
                                             sc.packed, sc.hist, ctr);
         hipError_t e = scan_exclusive_dev(sc.hist, sc.hist, nullptr, (nblk << lb), &ctr->sort_n, sc.blk, s);
         if (e != hipSuccess) return e;
-        k_bucket_scatter<<<nblk, kBlock, 0, s>>>(sc.key, sc.packed, m, lb, nblk, tile, sc.hist, sc.rec);
+        k_bucket_scatter<<<nblk, kPartBlock, 0, s>>>(sc.key, sc.packed, m, lb, nblk, tile, sc.hist, sc.rec);
         k_bucket_insert<<<1u << lb, kBlock, 0, s>>>(sc.rec, lb, nblk, sc.hist, h, bits, ctr);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
