@@ -93,6 +93,7 @@ __global__ void __launch_bounds__(kBlock) k_hull_validate(const uint32_t* __rest
     if (threadIdx.x == 0) {
         small[4] = K;
         small[7] = 0;   // chain list
+        small[9] = 0;   // mid list
     }
 }
 
@@ -136,6 +137,7 @@ __global__ void __launch_bounds__(kOneBlockThreads) k_hull_prepare(
         small[4] = K;
         small[6] = total[0];
         small[7] = 0;   // chain list
+        small[9] = 0;   // mid list
     }
 }
 
@@ -313,14 +315,43 @@ __global__ void __launch_bounds__(kTileThreads) k_hull_filter(
     }
 }
 
+// Filtered clusters whose survivors need a workgroup: up to kMidMax of them
+// go to the mid list (stored from the end of the list buffer, count in
+// small[9]) for k_hull_small, more to the chain list (count in small[7]) for
+// k_hull_chain.  The two never meet: together they hold at most K <= cap
+// entries.
+constexpr uint32_t kMidMax = kChainBlock;
+static_assert(kBlock == kChainBlock, "k_hull_small runs the workgroup chain with its own workgroup");
+
+__global__ void __launch_bounds__(kBlock) k_hull_list(uint32_t* __restrict__ small,
+                                                      const uint32_t* __restrict__ tile_off,
+                                                      const uint32_t* __restrict__ surv_cnt,
+                                                      uint32_t* __restrict__ list, uint32_t cap)
+{
+    const uint32_t K = small[4];
+    const uint32_t T = small[6];
+    for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < K; k += gridDim.x * blockDim.x) {
+        if (tile_off[k] == tiles_end(tile_off, k, K, T)) continue;   // not filtered: the wave path
+        const uint32_t ns = surv_cnt[k];
+        if (ns <= (uint32_t)kWave) continue;
+        if (ns <= kMidMax) list[cap - 1u - atomicAdd(&small[9], 1u)] = k;
+        else list[atomicAdd(&small[7], 1u)] = k;
+    }
+}
+
 // Clusters with at most 64 points to chain -- survivors of the filter, or
 // (clusters the filter skips) all inliers, projected here exactly as the
 // filter projects them -- one wave each, four per workgroup.  The points are
 // sorted across the wave's lanes (bitonic network on shuffles, same order:
 // u, then v, then inlier position), then one lane runs the lower and the
-// upper chain; the result is the same as the workgroup path's.
+// upper chain; the result is the same as the workgroup path's.  Up to half
+// of the workgroups first take the mid list's clusters (65..kMidMax
+// survivors) with the workgroup chain, so that those serial chains run while
+// the other workgroups go through the small clusters instead of in a launch
+// of their own afterwards; the rest split the small clusters among their
+// waves.
 __global__ void __launch_bounds__(kBlock) k_hull_small(
-    uint32_t* __restrict__ small, uint32_t* __restrict__ chain_list, const uint32_t* __restrict__ tile_off,
+    uint32_t* __restrict__ small, const uint32_t* __restrict__ list, uint32_t cap, const uint32_t* __restrict__ tile_off,
     const uint32_t* __restrict__ off,
     const float* __restrict__ X, const float* __restrict__ Y, const float* __restrict__ Z,
     const float4* __restrict__ plane, const int32_t* __restrict__ best, uint32_t in_cap,
@@ -332,12 +363,37 @@ __global__ void __launch_bounds__(kBlock) k_hull_small(
     __shared__ double sv[kBlock / kWave][kWave];
     __shared__ uint32_t si[kBlock / kWave][kWave];
     __shared__ uint8_t st[kBlock / kWave][2 * kWave + 2];
+    __shared__ ChainLds<kMidMax> L;
     const uint32_t K = small[4];
     const uint32_t T = small[6];
+    const uint32_t nmid = small[9];
+    const uint32_t gmid = nmid < gridDim.x / 2 ? nmid : gridDim.x / 2;   // uniform over the grid
+    if (blockIdx.x < gmid) {
+        for (uint32_t c = blockIdx.x; c < nmid; c += gmid) {
+            const uint32_t k = list[cap - 1u - c];
+            const uint32_t ib = in_off[k];
+            const uint32_t ns = surv_cnt[k];   // 65..kMidMax
+            double area = 0.0;
+            const uint32_t hh = block_chain(L, ns,
+                                            [&](uint32_t t, double* u, double* v, uint32_t* id) {
+                                                *u = gu[ib + t];
+                                                *v = gv[ib + t];
+                                                *id = gi[ib + t];
+                                            },
+                                            [&](uint32_t q, uint32_t p) { hull_tmp[ib + k + q] = in_idx[ib + L.si[p]]; },
+                                            &area);
+            if (threadIdx.x == 0) {
+                area_out[k] = area;
+                hull_cnt[k] = hh;
+            }
+            __syncthreads();   // L is reused by the next cluster
+        }
+        return;
+    }
     const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
-    const uint32_t waves = gridDim.x * (kBlock / kWave);
+    const uint32_t waves = (gridDim.x - gmid) * (kBlock / kWave);
     // wave-uniform cluster index: the cluster's own loads become scalar
-    const uint32_t w0 = __builtin_amdgcn_readfirstlane(blockIdx.x * (kBlock / kWave) + wv);
+    const uint32_t w0 = __builtin_amdgcn_readfirstlane((blockIdx.x - gmid) * (kBlock / kWave) + wv);
     for (uint32_t k = w0; k < K; k += waves) {
         const bool tiled = tile_off[k] != tiles_end(tile_off, k, K, T);
         uint32_t ns;
@@ -346,10 +402,7 @@ __global__ void __launch_bounds__(kBlock) k_hull_small(
         const uint32_t ib = in_off[k];
         if (tiled) {
             ns = surv_cnt[k];
-            if (ns > (uint32_t)kWave) {   // the workgroup path takes it from the list
-                if (lane == 0) chain_list[atomicAdd(&small[7], 1u)] = k;
-                continue;
-            }
+            if (ns > (uint32_t)kWave) continue;   // listed for a workgroup chain
             if ((uint32_t)lane < ns) {
                 u = gu[ib + lane];
                 v = gv[ib + lane];
@@ -544,7 +597,8 @@ __global__ void __launch_bounds__(kChainBlock) k_hull_chain(
 {
     __shared__ ChainLds<kLdsCap> L;
     __shared__ RefineLds R;
-    // the clusters with more than one wave of survivors, listed by k_hull_small
+    // the listed clusters: more than kMidMax survivors (k_hull_list), or the
+    // persistent pass's clusters with more than one wave of survivors
     const uint32_t nc = small[7];
     for (uint32_t c = blockIdx.x; c < nc; c += gridDim.x) {
         const uint32_t k = chain_list[c];
@@ -715,7 +769,8 @@ vm_status hulls(const vm_clusters& cl, const vm_planes& planes, const vm_hulls_o
     k_hull_filter<<<tgrid, kTileThreads, 0, s>>>(w.small, w.hull_tile_off, cl.d_off, cl.d_x, cl.d_y, cl.d_z, pl,
                                                  planes.d_in_off, planes.d_in_idx, w.poly, w.surv_cnt, w.hull_u,
                                                  w.hull_v, w.hull_i);
-    k_hull_small<<<kSmallGrid, kBlock, 0, s>>>(w.small, w.chain_list, w.hull_tile_off, cl.d_off, cl.d_x, cl.d_y,
+    k_hull_list<<<grid_for(kc), kBlock, 0, s>>>(w.small, w.hull_tile_off, w.surv_cnt, w.chain_list, kc);
+    k_hull_small<<<kSmallGrid, kBlock, 0, s>>>(w.small, w.chain_list, kc, w.hull_tile_off, cl.d_off, cl.d_x, cl.d_y,
                                               cl.d_z, pl,
                                               planes.d_best_h, planes.in_cap, planes.d_in_off, planes.d_in_idx,
                                               w.surv_cnt, w.hull_u, w.hull_v, w.hull_i, w.hull_cnt, w.hull_tmp,
