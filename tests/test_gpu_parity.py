@@ -390,3 +390,49 @@ def test_hull_paths_by_survivor_count(vm):
         a, b = int(off[k]), int(off[k + 1])
         r = oracle.plane_and_hull(xyz[a:b, 0], xyz[a:b, 1], xyz[a:b, 2], H, 0.01, SEED, int(tag[k]), 1)
         compare_cluster(k, P, Hh, r, check_all_hyp=False)
+
+
+def test_hull_mid_list_beyond_half_the_grid(vm):
+    """More clusters with 65..256 hull survivors (thin rings: nearly every
+    point is on the hull) than half of the small-cluster kernel's workgroups,
+    so that its workgroup chains stride over the list, mixed with discs small
+    enough for the one-wave path; every cluster against the oracle, vertex
+    lists bit for bit."""
+    import os
+    rng = np.random.default_rng(71)
+    nrm = np.array([0.3, 0.1, 1.0]) / np.linalg.norm([0.3, 0.1, 1.0])
+    a = np.cross(nrm, [1.0, 0.0, 0.0])
+    a /= np.linalg.norm(a)
+    b = np.cross(nrm, a)
+    parts = []
+    for q in range(1300):
+        n = int(rng.integers(80, 250))
+        r = 0.2 + 0.1 * rng.random() + rng.normal(0, 1e-5, n)
+        th = rng.random(n) * 2 * np.pi
+        p = (r * np.cos(th))[:, None] * a + (r * np.sin(th))[:, None] * b + rng.random(3)
+        parts.append(p.astype(np.float32))
+        if q % 5 == 0:
+            n = int(rng.integers(8, 60))
+            r = 0.05 * np.sqrt(rng.random(n))
+            th = rng.random(n) * 2 * np.pi
+            p = (r * np.cos(th))[:, None] * a + (r * np.sin(th))[:, None] * b + rng.random(3)
+            parts.append(p.astype(np.float32))
+    off = np.zeros(len(parts) + 1, np.uint32)
+    off[1:] = np.cumsum([len(p) for p in parts])
+    xyz = np.concatenate(parts)
+    K = len(parts)
+    tag = np.arange(K, dtype=np.uint32) * 31 + 9
+    T = cluster_tensors(off, xyz, tag)
+    cl = vm.cluster_view(T["off"], T["x"], T["y"], T["z"], T["tag"], T["meta"])
+    H = 32
+    note(f"hull mid list: {K} clusters, {len(xyz)} points")
+    pb, hb = run_planes_and_hulls(vm, cl, K, len(xyz), H, 0.01, SEED, 3, with_all=False)
+    P, Hh = planes_np(pb), hulls_np(hb)
+    assert P["status"] == 0 and Hh["status"] == 0
+    refs = oracle.planes_and_hulls(off, xyz, tag, H, 0.01, SEED, 3, threads=max(1, min(16, os.cpu_count() or 1)))
+    survivors = 0
+    for k, r in enumerate(refs):
+        compare_cluster(k, P, Hh, r, check_all_hyp=False)
+        survivors += int(Hh["v_off"][k + 1] - Hh["v_off"][k]) > 64
+    # the rings' polygons keep more than a wave of vertices: they took the workgroup chain
+    assert survivors > 1024, survivors
