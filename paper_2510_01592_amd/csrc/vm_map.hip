@@ -331,38 +331,39 @@ __global__ void __launch_bounds__(kBlock) k_bucket_insert(const uint4* __restric
 }
 
 // Occupied keys in rank order; the component-size counters of the ranks are
-// cleared on the way (the labelling accumulates into them).
+// cleared on the way (the labelling accumulates into them).  A workgroup
+// takes kCompactWords consecutive grid words per pass: their keys (at most
+// 32 per word) go to LDS at their ranks' offsets from the pass's first rank,
+// then the workgroup stores them, and the cleared counters, as contiguous
+// rows.
+constexpr uint32_t kCompactWords = kBlock;
+
 __global__ void __launch_bounds__(kBlock) k_compact(const uint32_t* __restrict__ bits, uint32_t nwords,
                                                     const uint32_t* __restrict__ wrank,
                                                     uint32_t* __restrict__ occ_key, uint32_t* __restrict__ csize)
 {
-    for (uint32_t w = blockIdx.x * blockDim.x + threadIdx.x; w < nwords; w += gridDim.x * blockDim.x) {
-        uint32_t b = bits[w];
-        uint32_t r = wrank[w];
-        // the word's keys go to consecutive entries: single stores up to a
-        // 16-byte boundary, then four keys per store, then the rest
-        for (; b && (r & 3u); b &= b - 1, ++r) {
-            csize[r] = 0u;
-            occ_key[r] = (w << 5) | (uint32_t)(__ffs(b) - 1);
+    __shared__ uint32_t keys[kCompactWords * 32];
+    __shared__ uint32_t s_base, s_end;
+    for (uint32_t w0 = blockIdx.x * kCompactWords; w0 < nwords; w0 += gridDim.x * kCompactWords) {
+        const uint32_t w = w0 + threadIdx.x;
+        const uint32_t wl = (nwords - w0 < kCompactWords ? nwords : w0 + kCompactWords) - 1;   // last word
+        uint32_t b = 0, r = 0;
+        if (w < nwords) {
+            b = bits[w];
+            r = wrank[w];
         }
-        while (__popc(b) >= 4) {
-            uint4 k;
-            k.x = (w << 5) | (uint32_t)(__ffs(b) - 1);
-            b &= b - 1;
-            k.y = (w << 5) | (uint32_t)(__ffs(b) - 1);
-            b &= b - 1;
-            k.z = (w << 5) | (uint32_t)(__ffs(b) - 1);
-            b &= b - 1;
-            k.w = (w << 5) | (uint32_t)(__ffs(b) - 1);
-            b &= b - 1;
-            *reinterpret_cast<uint4*>(csize + r) = make_uint4(0u, 0u, 0u, 0u);
-            *reinterpret_cast<uint4*>(occ_key + r) = k;
-            r += 4;
+        if (w == w0) s_base = r;
+        if (w == wl) s_end = r + (uint32_t)__popc(b);
+        __syncthreads();
+        const uint32_t base = s_base;
+        for (uint32_t q = r - base; b; b &= b - 1, ++q) keys[q] = (w << 5) | (uint32_t)(__ffs(b) - 1);
+        __syncthreads();
+        const uint32_t n = s_end - base;   // at most 32 keys per word
+        for (uint32_t i = threadIdx.x; i < n; i += kBlock) {
+            occ_key[base + i] = keys[i];
+            csize[base + i] = 0u;
         }
-        for (; b; b &= b - 1, ++r) {
-            csize[r] = 0u;
-            occ_key[r] = (w << 5) | (uint32_t)(__ffs(b) - 1);
-        }
+        __syncthreads();   // keys, s_base and s_end are reused by the next pass
     }
 }
 
